@@ -1,0 +1,124 @@
+"""Pins of the oracle's ACA (Sec. 2.2, Algorithm 1).
+
+PIN-A1  exactness on synthetic rank-k matrices A = X Y^T (m != n): rank k and
+        ||A - U V^T||_F <= 1e-12 ||A||_F, also with vanishing rows present.
+PIN-A2  interpolation property of the crosses: u_k and v_k are the pivot column
+        and (scaled) pivot row of the remainder, so the final remainder vanishes
+        on every pivot row and every pivot column.
+PIN-A3  on Kelvin far blocks the ACA rank is at least the optimal rank of
+        the truncated SVD (Sec. 2, Eckart-Young) for the accuracy ACA actually
+        reached, and ||B - U V^T||_F <= 10 eps ||B||_F on at least 90% of the
+        blocks checked (the blockwise target is heuristic for partial
+        pivoting; no block may exceed 200 eps).
+Also: the stop rule holds at the returned rank (ratio <= 1), the rank-1
+normalisation v_k(j_k) = 1 of the pivot row, and the first pivot row is 0.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+
+@pytest.mark.parametrize("k", [1, 5, 20])
+@pytest.mark.parametrize("shape", [(60, 45), (37, 90)])
+def test_exact_low_rank(k, shape):
+    rng = np.random.default_rng(k * 100 + shape[0])
+    m, n = shape
+    A = rng.standard_normal((m, k)) @ rng.standard_normal((k, n))
+    r = O.aca_dense(A, 1e-14)
+    R = A - r["U"] @ r["V"].T
+    assert r["U"].shape[1] == k
+    assert np.linalg.norm(R) <= 1e-12 * np.linalg.norm(A)
+
+
+def test_exact_low_rank_with_vanishing_rows():
+    rng = np.random.default_rng(11)
+    m, n, k = 50, 40, 6
+    A = rng.standard_normal((m, k)) @ rng.standard_normal((k, n))
+    A[0] = 0.0  # the first row tried vanishes (k = 0 branch)
+    A[[3, 7, 19]] = 0.0
+    r = O.aca_dense(A, 1e-14)
+    assert r["U"].shape[1] == k
+    assert r["rows"][0] == 1  # lowest row not yet in Z after row 0 vanished
+    assert np.linalg.norm(A - r["U"] @ r["V"].T) <= 1e-12 * np.linalg.norm(A)
+    Z = np.zeros((5, 9))
+    r0 = O.aca_dense(Z, 1e-6)
+    assert r0["U"].shape[1] == 0 and r0["stop"] == 3
+
+
+def test_full_rank_stops_at_min_dim():
+    rng = np.random.default_rng(2)
+    A = rng.standard_normal((12, 7))
+    r = O.aca_dense(A, 1e-15)
+    assert r["U"].shape[1] == 7 and r["stop"] == 2
+    assert np.linalg.norm(A - r["U"] @ r["V"].T) <= 1e-12 * np.linalg.norm(A)
+
+
+def _check_cross(B, r, tol):
+    R = B - r["U"] @ r["V"].T
+    scale = np.abs(B).max()
+    assert np.abs(R[r["rows"], :]).max() <= tol * scale
+    assert np.abs(R[:, r["cols"]]).max() <= tol * scale
+    # v_k is normalised at its pivot entry: v_k(j_k) = 1
+    k = r["U"].shape[1]
+    assert np.allclose(r["V"][r["cols"], np.arange(k)], 1.0, rtol=0, atol=1e-15)
+    assert r["rows"][0] == 0
+
+
+@pytest.fixture(scope="module")
+def c0():
+    V, T = W.icosphere(3)
+    mesh = O.Mesh(V, T, 1.0, 0.3)
+    h = O.HMatrix(mesh, 2.0, 32, eps=1e-4)
+    return V, T, mesh, h
+
+
+def _block_dense(mesh, h, b, order):
+    bl = h.blocks()[b]
+    rt = order[bl[0]:bl[0] + bl[1]]
+    ct = order[bl[2]:bl[2] + bl[3]]
+    rows = (3 * rt[:, None] + np.arange(3)[None, :]).ravel()
+    cols = (3 * ct[:, None] + np.arange(3)[None, :]).ravel()
+    R, Cc = np.meshgrid(rows, cols, indexing="ij")
+    return mesh.entries(R.ravel(), Cc.ravel()).reshape(len(rows), len(cols))
+
+
+def test_kelvin_blocks_cross_and_svd(c0):
+    V, T, mesh, h = c0
+    eps = 1e-4
+    B = h.blocks()
+    order = h.order
+    far = np.nonzero(B[:, 4] == 1)[0]
+    rng = np.random.default_rng(0)
+    pick = list(far[np.argsort(-(B[far, 1] + B[far, 3]))[:6]]) + list(rng.choice(far, 30, replace=False))
+    ratios = h.stop_ratios()
+    errs = []
+    for b in pick:
+        Bd = _block_dense(mesh, h, b, order)
+        U, Vf, pr, pc = h.factors(b)
+        r = dict(U=U, V=Vf, rows=pr, cols=pc)
+        _check_cross(Bd, r, 1e-13)
+        err = np.linalg.norm(Bd - U @ Vf.T) / np.linalg.norm(Bd)
+        errs.append(err / eps)
+        s = np.linalg.svd(Bd, compute_uv=False)
+        tail = np.append(np.sqrt(np.cumsum((s ** 2)[::-1])[::-1]), 0.0)  # tail[k] = ||B - B_k||_F
+        k_svd = int(np.argmax(tail <= err * np.linalg.norm(Bd)))
+        assert U.shape[1] >= k_svd, (b, U.shape[1], k_svd)
+        assert ratios[b] <= 1.0 and B[b, 6] == 1
+    errs = np.array(errs)
+    assert np.mean(errs <= 10) >= 0.9 and errs.max() <= 200, errs
+
+
+def test_dense_aca_matches_blockwise(c0):
+    """The generic dense-matrix ACA and the on-the-fly Kelvin-block ACA follow the same steps."""
+    V, T, mesh, h = c0
+    B = h.blocks()
+    order = h.order
+    far = np.nonzero(B[:, 4] == 1)[0]
+    for b in far[:20]:
+        Bd = _block_dense(mesh, h, b, order)
+        r = O.aca_dense(Bd, 1e-4)
+        U, Vf, pr, pc = h.factors(b)
+        assert np.array_equal(r["rows"], pr) and np.array_equal(r["cols"], pc)
+        assert np.allclose(r["U"], U, rtol=0, atol=1e-13 * np.abs(U).max())

@@ -1,0 +1,277 @@
+"""Seeded synthetic inputs: surface meshes and right-hand sides.
+
+This module only *generates* data (vertex coordinates, triangle indices,
+random vectors). It contains none of the method's arithmetic: no kernel,
+no quadrature, no clustering, no approximation. Both the HIP path and the
+CPU oracle receive exactly the arrays produced here.
+
+Meshes are flat-triangle surface meshes: ``vertices`` is float64 [nv, 3],
+``triangles`` is int32 [nt, 3] (0-based, outward orientation where the
+surface is closed). All generators are deterministic.
+"""
+from __future__ import annotations
+
+import hashlib
+import math
+
+import numpy as np
+
+__all__ = [
+    "icosahedron",
+    "icosphere",
+    "geodesic_sphere",
+    "ellipsoid",
+    "torus",
+    "box_surface",
+    "cube_surface",
+    "random_x",
+    "smooth_rhs",
+    "mesh_hash",
+    "workload_c0",
+    "workload_c1",
+]
+
+
+def _orient_outward(vertices: np.ndarray, tris: np.ndarray, center: np.ndarray) -> np.ndarray:
+    p0 = vertices[tris[:, 0]]
+    p1 = vertices[tris[:, 1]]
+    p2 = vertices[tris[:, 2]]
+    n = np.cross(p1 - p0, p2 - p0)
+    c = (p0 + p1 + p2) / 3.0 - center
+    flip = np.einsum("ij,ij->i", n, c) < 0
+    out = tris.copy()
+    out[flip, 1], out[flip, 2] = tris[flip, 2], tris[flip, 1]
+    return out
+
+
+def icosahedron() -> tuple[np.ndarray, np.ndarray]:
+    """Regular icosahedron inscribed in the unit sphere.
+
+    Vertices are the cyclic permutations of (0, +-1, +-phi), normalised.
+    Faces are the vertex triples that are pairwise at the edge length 2
+    (before normalisation), oriented outward and sorted lexicographically.
+    """
+    phi = (1.0 + math.sqrt(5.0)) / 2.0
+    pts = []
+    for s1 in (-1.0, 1.0):
+        for s2 in (-phi, phi):
+            pts.append((0.0, s1, s2))
+            pts.append((s1, s2, 0.0))
+            pts.append((s2, 0.0, s1))
+    raw = np.array(pts, dtype=np.float64)
+    faces = []
+    n = len(raw)
+    d = np.linalg.norm(raw[:, None, :] - raw[None, :, :], axis=2)
+    adj = np.abs(d - 2.0) < 1e-9
+    for a in range(n):
+        for b in range(a + 1, n):
+            if not adj[a, b]:
+                continue
+            for c in range(b + 1, n):
+                if adj[a, c] and adj[b, c]:
+                    faces.append((a, b, c))
+    assert len(faces) == 20
+    v = raw / np.linalg.norm(raw, axis=1, keepdims=True)
+    t = _orient_outward(v, np.array(faces, dtype=np.int32), np.zeros(3))
+    return v, t.astype(np.int32)
+
+
+def icosphere(level: int) -> tuple[np.ndarray, np.ndarray]:
+    """Icosahedron refined ``level`` times by edge midpoints projected to the unit sphere.
+
+    Each triangle (a, b, c) becomes (a, ab, ca), (b, bc, ab), (c, ca, bc), (ab, bc, ca).
+    New vertices are numbered in order of first appearance. Level L has
+    20*4**L triangles and 10*4**L + 2 vertices.
+    """
+    v, t = icosahedron()
+    verts = [tuple(p) for p in v]
+    tris = [tuple(int(i) for i in f) for f in t]
+    for _ in range(level):
+        cache: dict[tuple[int, int], int] = {}
+
+        def mid(i: int, j: int) -> int:
+            key = (i, j) if i < j else (j, i)
+            k = cache.get(key)
+            if k is None:
+                p = np.array(verts[i]) + np.array(verts[j])
+                p = p / np.linalg.norm(p)
+                verts.append(tuple(p))
+                k = len(verts) - 1
+                cache[key] = k
+            return k
+
+        new = []
+        for a, b, c in tris:
+            ab, bc, ca = mid(a, b), mid(b, c), mid(c, a)
+            new += [(a, ab, ca), (b, bc, ab), (c, ca, bc), (ab, bc, ca)]
+        tris = new
+    return np.array(verts, dtype=np.float64), np.array(tris, dtype=np.int32)
+
+
+def geodesic_sphere(freq: int) -> tuple[np.ndarray, np.ndarray]:
+    """Frequency-``freq`` geodesic sphere: each icosahedron face cut into freq**2 triangles.
+
+    Grid points of each face are projected onto the unit sphere; points on shared
+    edges and corners are merged. 20*freq**2 triangles.
+    """
+    v0, t0 = icosahedron()
+    f = int(freq)
+    assert f >= 1
+    key_to_idx: dict[tuple[int, ...], int] = {}
+    verts: list[np.ndarray] = []
+
+    def vid(face: tuple[int, int, int], i: int, j: int) -> int:
+        # barycentric integer coordinates (f-i-j, i, j) on face (a, b, c)
+        a, b, c = face
+        w = {a: f - i - j, b: i, c: j}
+        key = tuple(sorted((k, wk) for k, wk in w.items() if wk > 0))
+        idx = key_to_idx.get(key)
+        if idx is None:
+            p = (w[a] * v0[a] + w[b] * v0[b] + w[c] * v0[c]) / f
+            p = p / np.linalg.norm(p)
+            verts.append(p)
+            idx = len(verts) - 1
+            key_to_idx[key] = idx
+        return idx
+
+    tris = []
+    for face in t0:
+        fc = (int(face[0]), int(face[1]), int(face[2]))
+        for i in range(f):
+            for j in range(f - i):
+                p = vid(fc, i, j)
+                q = vid(fc, i + 1, j)
+                r = vid(fc, i, j + 1)
+                tris.append((p, q, r))
+                if i + j < f - 1:
+                    s = vid(fc, i + 1, j + 1)
+                    tris.append((q, s, r))
+    V = np.array(verts, dtype=np.float64)
+    T = _orient_outward(V, np.array(tris, dtype=np.int32), np.zeros(3))
+    return V, T.astype(np.int32)
+
+
+def ellipsoid(freq: int, axes) -> tuple[np.ndarray, np.ndarray]:
+    """Geodesic sphere of frequency ``freq`` scaled by semi-axes ``axes``."""
+    V, T = geodesic_sphere(freq)
+    return V * np.asarray(axes, dtype=np.float64)[None, :], T
+
+
+def torus(R: float, r: float, nu: int, nv: int) -> tuple[np.ndarray, np.ndarray]:
+    """Torus with major radius R and minor radius r on an nu x nv grid (2*nu*nv triangles)."""
+    u = 2.0 * np.pi * np.arange(nu) / nu
+    w = 2.0 * np.pi * np.arange(nv) / nv
+    U, W = np.meshgrid(u, w, indexing="ij")
+    X = (R + r * np.cos(W)) * np.cos(U)
+    Y = (R + r * np.cos(W)) * np.sin(U)
+    Z = r * np.sin(W)
+    V = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+    tris = []
+    for i in range(nu):
+        for j in range(nv):
+            a = i * nv + j
+            b = ((i + 1) % nu) * nv + j
+            c = ((i + 1) % nu) * nv + (j + 1) % nv
+            d = i * nv + (j + 1) % nv
+            tris.append((a, b, c))
+            tris.append((a, c, d))
+    T = np.array(tris, dtype=np.int32)
+    # outward w.r.t. the tube centre line
+    p0, p1, p2 = V[T[:, 0]], V[T[:, 1]], V[T[:, 2]]
+    n = np.cross(p1 - p0, p2 - p0)
+    c = (p0 + p1 + p2) / 3.0
+    ang = np.arctan2(c[:, 1], c[:, 0])
+    core = np.stack([R * np.cos(ang), R * np.sin(ang), np.zeros_like(ang)], axis=1)
+    flip = np.einsum("ij,ij->i", n, c - core) < 0
+    T2 = T.copy()
+    T2[flip, 1], T2[flip, 2] = T[flip, 2], T[flip, 1]
+    return V.astype(np.float64), T2.astype(np.int32)
+
+
+def box_surface(lx: float, ly: float, lz: float, nx: int, ny: int, nz: int):
+    """Structured triangulated surface of the box [0,lx]x[0,ly]x[0,lz].
+
+    Face grids have nx, ny, nz cells along x, y, z; each cell is cut into two
+    triangles. Vertices on shared edges are merged. 4*(nx*ny + ny*nz + nx*nz) triangles.
+    """
+    index: dict[tuple[int, int, int], int] = {}
+    verts = []
+
+    def vid(i: int, j: int, k: int) -> int:
+        key = (i, j, k)
+        idx = index.get(key)
+        if idx is None:
+            verts.append((lx * i / nx, ly * j / ny, lz * k / nz))
+            idx = len(verts) - 1
+            index[key] = idx
+        return idx
+
+    tris = []
+
+    def quad(a, b, c, d):
+        tris.append((a, b, c))
+        tris.append((a, c, d))
+
+    for fixed, (n1, n2) in ((0, (ny, nz)), (1, (nx, nz)), (2, (nx, ny))):
+        for side in (0, 1):
+            for i in range(n1):
+                for j in range(n2):
+                    def P(ii, jj):
+                        if fixed == 0:
+                            return vid(side * nx, ii, jj)
+                        if fixed == 1:
+                            return vid(ii, side * ny, jj)
+                        return vid(ii, jj, side * nz)
+                    quad(P(i, j), P(i + 1, j), P(i + 1, j + 1), P(i, j + 1))
+    V = np.array(verts, dtype=np.float64)
+    T = _orient_outward(V, np.array(tris, dtype=np.int32), np.array([lx, ly, lz]) / 2.0)
+    return V, T.astype(np.int32)
+
+
+def cube_surface(n: int):
+    """Surface of [-1,1]^3 with an n x n grid per face: 12 n^2 triangles, 6 n^2 + 2 nodes."""
+    V, T = box_surface(2.0, 2.0, 2.0, n, n, n)
+    return V - 1.0, T
+
+
+def random_x(n_dof: int, nrhs: int = 1, seed: int = 0) -> np.ndarray:
+    """x ~ N(0,1), shape (nrhs, n_dof), from NumPy PCG64 ``default_rng(seed)``."""
+    return np.random.default_rng(seed).standard_normal((nrhs, n_dof))
+
+
+def smooth_rhs(vertices: np.ndarray, triangles: np.ndarray, seed: int = 1) -> np.ndarray:
+    """Random smooth vector field sampled at the triangle centroids (length 3*nt, DOF 3i+a).
+
+    g_a(x) = sum over m = 1..8 and monomials x^alpha with |alpha| <= 2 of
+    c[m, a, alpha] x^alpha, monomials ordered 1, x, y, z, x^2, xy, xz, y^2, yz, z^2,
+    coefficients N(0,1) from ``default_rng(seed)`` drawn with shape (8, 3, 10).
+    """
+    c = np.random.default_rng(seed).standard_normal((8, 3, 10))
+    p = vertices[triangles]
+    x = ((p[:, 0] + p[:, 1]) + p[:, 2]) / 3.0
+    X, Y, Z = x[:, 0], x[:, 1], x[:, 2]
+    mono = np.stack([np.ones_like(X), X, Y, Z, X * X, X * Y, X * Z, Y * Y, Y * Z, Z * Z], axis=1)
+    g = np.einsum("mak,ik->ia", c, mono)
+    return np.ascontiguousarray(g.reshape(-1))
+
+
+def mesh_hash(vertices: np.ndarray, triangles: np.ndarray) -> str:
+    h = hashlib.sha256()
+    h.update(np.ascontiguousarray(vertices, dtype=np.float64).tobytes())
+    h.update(np.ascontiguousarray(triangles, dtype=np.int32).tobytes())
+    return h.hexdigest()[:16]
+
+
+# Named workloads (material and approximation parameters used throughout).
+def workload_c0():
+    """Unit icosphere level 3 (1280 triangles, 3840 DOF), E=1, nu=0.3, eta=2, leaf 32, eps=1e-4."""
+    V, T = icosphere(3)
+    return dict(name="icosphere-L3", vertices=V, triangles=T, E=1.0, nu=0.3, eta=2.0,
+                leaf=32, eps=1e-4, nrhs=1)
+
+
+def workload_c1():
+    """Unit icosphere level 5 (20480 triangles, 61440 DOF), eps=1e-6, 16 right-hand sides."""
+    V, T = icosphere(5)
+    return dict(name="icosphere-L5", vertices=V, triangles=T, E=1.0, nu=0.3, eta=2.0,
+                leaf=32, eps=1e-6, nrhs=16)
