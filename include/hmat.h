@@ -1,0 +1,221 @@
+/*
+ * hmat.h -- C ABI of the MI355X (gfx950) H-matrix library for the Lame
+ * single-layer operator discretised by piecewise-constant collocation.
+ *
+ * Method: Bauer & Bebendorf, "Adaptive H-Matrix Computations in Linear
+ * Elasticity" (arXiv 2205.04752):
+ *   - Kelvin's solution tensor S_K (Sec. 4.1) as the kernel of the
+ *     single-layer potential V~ (Sec. 4.1);
+ *   - collocation (Sec. 2, discretisation examples) with the piecewise
+ *     constant basis of S^0_h (Sec. 4.2), collocation point = centroid,
+ *     coefficient order t = [t_i^(1), t_i^(2), t_i^(3)]_i (Sec. 4.2), i.e.
+ *     DOF 3i+a is component a of triangle i;
+ *   - binary cluster tree, block-cluster tree, admissibility (eq. adm) and
+ *     partition P = P_adm u P_nonadm (Sec. 2.1);
+ *   - ACA with partial pivoting on every admissible block (Sec. 2.2,
+ *     Algorithm 1), dense non-admissible blocks (Sec. 2.2);
+ *   - the H-matrix-vector product (Sec. 2: outer-product representation,
+ *     O(k(M+N)) per block; Sec. 2.2: H(P,k)).
+ *
+ * Conventions for every call:
+ *   - Every function returns hmat_status; HMAT_OK (0) on success.
+ *   - Arguments are validated on the host before any device work; on a
+ *     validation error nothing is launched, outputs are left untouched and
+ *     *out handles are set to NULL.
+ *   - hmat_last_error() returns a thread-local message for the last failure
+ *     of the calling thread (empty string if none). The pointer is valid
+ *     until the next call on that thread.
+ *   - No C++ exception crosses this interface.
+ *   - "HOST" pointers are ordinary CPU memory; "DEVICE" pointers are HIP
+ *     device memory of the current device (e.g. a torch tensor's data_ptr()).
+ *   - hip_stream is a hipStream_t (NULL = the legacy default stream). Device
+ *     work of a call is enqueued on that stream.
+ *   - Thread safety: different handles may be used from different threads;
+ *     calls on one handle must be serialised by the caller.
+ */
+#ifndef HMAT_H
+#define HMAT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hmat* hmat_t; /* opaque; owns every device allocation it makes */
+
+typedef enum {
+  HMAT_OK = 0,
+  HMAT_EINVAL = 1,  /* invalid argument (nothing was done) */
+  HMAT_ENOMEM = 2,  /* device or host allocation failed (budget included) */
+  HMAT_EDEVICE = 3, /* a HIP call failed */
+  HMAT_ENOCONV = 4, /* iteration limit reached; outputs still written */
+  HMAT_ENOTSUP = 5  /* valid but unsupported request */
+} hmat_status;
+
+/* Surface triangulation (Sec. 4.2: admissible triangulation into flat
+ * triangles tau_i). HOST arrays, borrowed for the duration of the call only:
+ *   vertices [n_vertices][3] float64, triangles [n_triangles][3] int32,
+ *   0-based vertex indices. */
+typedef struct {
+  int32_t n_vertices;
+  int32_t n_triangles;
+  const double* vertices;
+  const int32_t* triangles;
+} hmat_mesh;
+
+/* Build statistics (hmat_info). Storage follows Sec. 2: a low-rank block of
+ * rank k stores k(m+n) scalars, a dense block m n. */
+typedef struct {
+  int64_t n_dof;          /* 3 * n_triangles */
+  int32_t n_triangles;
+  int32_t n_clusters;     /* nodes of the cluster tree */
+  int32_t depth;          /* depth of the cluster tree */
+  int32_t n_blocks;       /* |P| */
+  int32_t n_far;          /* |P_adm| */
+  int32_t n_near;         /* |P_nonadm| */
+  int32_t c_sp;           /* sparsity constant (Sec. 2.1) */
+  int32_t rank_min, rank_max;
+  double rank_mean;
+  int64_t far_scalars;    /* sum over admissible blocks of k(m+n) */
+  int64_t near_scalars;   /* sum over dense blocks of m n */
+  double compression;     /* (far + near scalars) / n_dof^2 */
+  int32_t n_rank_full;    /* admissible blocks that stopped at k = min(m,n) */
+  int32_t n_near_threshold; /* blocks whose final |u||v| / (eps ||S||) lies in [1-1e-9, 1] */
+  int32_t aca_passes;     /* 1, or 2 if some blocks outgrew the first-pass rank capacity */
+  int32_t reserved;
+  double t_plan_ms;       /* host: geometry, tree, partition, device lists */
+  double t_near_ms;       /* device: dense blocks (K1) */
+  double t_aca_ms;        /* device: ACA (K2) incl. compaction */
+  double t_build_ms;      /* whole hmat_build */
+  int64_t device_bytes;   /* persistent device memory held by the handle */
+} hmat_stats;
+
+typedef struct {
+  int32_t iterations;     /* Arnoldi steps (= operator applications inside cycles) */
+  int32_t restarts;       /* completed restart cycles */
+  double relres;          /* explicit ||b - A_H x||_2 / ||b||_2 at return */
+  double time_ms;         /* wall time of the solve (host clock, stream synced) */
+} hmat_solve_info;
+
+/*
+ * hmat_build -- assemble the H-matrix approximation A_H of the collocation
+ * matrix A[3i+a, 3j+b] = integral over tau_j of S_K,ab(c_i - y) ds_y
+ * (Sec. 4.1 kernel; Sec. 2 collocation; Sec. 4.2 basis), c_i the centroid.
+ *   mesh    HOST mesh (copied).
+ *   E, nu   Young modulus E > 0 and Poisson ratio 0 < nu < 1/2 (Sec. 1).
+ *   eta     admissibility parameter > 0: a block t x s is low-rank iff
+ *           dist(X_t, X_s) > 0 and min(diam X_t, diam X_s) <= eta dist(X_t, X_s),
+ *           X_t the axis-aligned box of the vertices of t's triangles (eq. adm).
+ *   leaf    clusters of at most `leaf` triangles are not split (>= 1).
+ *   eps     ACA accuracy 0 < eps < 1: ACA stops at ||u_k|| ||v_k|| <= eps ||S_k||_F
+ *           (Algorithm 1 stop test, constant read as 1).
+ *   hip_stream  stream for all device work; synchronised before return.
+ *   out     receives the handle (NULL on failure).
+ * Quadrature: off-diagonal entries use the degree-5 seven-point rule
+ * (Radon); the self entries split tau_i at c_i into three triangles, each
+ * with 16 x 16 Gauss-Legendre points in Duffy coordinates.
+ * Errors: HMAT_EINVAL for E <= 0, nu outside (0, 1/2), eta <= 0, leaf < 1,
+ * eps outside (0, 1), n_triangles < 1, n_vertices < 3, a vertex index out of
+ * range, a non-finite coordinate or a zero-area triangle; HMAT_ENOMEM;
+ * HMAT_EDEVICE.
+ */
+hmat_status hmat_build(const hmat_mesh* mesh, double E, double nu, double eta, int32_t leaf,
+                       double eps, void* hip_stream, hmat_t* out);
+
+/*
+ * hmat_matvec -- y_r = A_H x_r for r = 0..nrhs-1 (Sec. 2, Sec. 2.2):
+ *   y = sum over admissible b of U_b (V_b^T x_s) + sum over dense b of D_b x_s.
+ *   x    DEVICE float64, nrhs vectors of length n_dof, vector r at x + r*ldx,
+ *        DOF order 3i+a in the caller's triangle numbering.
+ *   y    DEVICE float64, same layout with ldy; fully overwritten. Must not
+ *        overlap x.
+ *   ldx, ldy >= n_dof.  1 <= nrhs <= 64.
+ * Stream-ordered, no host synchronisation; the result is deterministic
+ * (bitwise repeatable for the same inputs). Errors: HMAT_EINVAL (NULL
+ * handle/pointers, bad sizes), HMAT_EDEVICE.
+ */
+hmat_status hmat_matvec(hmat_t h, int32_t nrhs, const double* x, int64_t ldx, double* y,
+                        int64_t ldy, void* hip_stream);
+
+/*
+ * hmat_solve -- solve A_H x = b by restarted GMRES (Saad & Schultz) with
+ * classical Gram-Schmidt applied twice, Givens rotations, x0 = 0. Not part of
+ * the paper, whose saddle-point system is solved by Bramble-Pasciak CG.
+ *   b, x     DEVICE float64 vectors of length n_dof (caller's DOF order).
+ *   tol      > 0: converged iff the explicit ||b - A_H x||_2 <= tol ||b||_2.
+ *   restart  Krylov dimension per cycle, 1..1024.
+ *   maxit    maximum number of Arnoldi steps in total (>= 1).
+ *   info     HOST, may be NULL.
+ * Synchronises the stream (the Hessenberg column is read back each step).
+ * Returns HMAT_ENOCONV if maxit is reached first; x and info are written in
+ * that case too.
+ */
+hmat_status hmat_solve(hmat_t h, const double* b, double* x, double tol, int32_t restart,
+                       int32_t maxit, void* hip_stream, hmat_solve_info* info);
+
+/* hmat_info -- copy build statistics into *st (HOST). */
+hmat_status hmat_info(hmat_t h, hmat_stats* st);
+
+/* hmat_free -- release all device and host memory of h (NULL is a no-op).
+ * Synchronises the device work of h first. */
+hmat_status hmat_free(hmat_t h);
+
+/* Thread-local description of the last failure on the calling thread. */
+const char* hmat_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * Inspection entry points (host copies; used by tests and tools).
+ * ------------------------------------------------------------------------ */
+
+/*
+ * hmat_plan -- host-only partition of a mesh, no device work (Sec. 2.1).
+ *   order      HOST int32 [n_triangles] (may be NULL): cluster position p ->
+ *              caller's triangle index.
+ *   n_blocks   HOST: in: capacity of `blocks` (in blocks); out: |P|.
+ *   blocks     HOST int32 [capacity][5] (may be NULL): row_off, row_len,
+ *              col_off, col_len (cluster positions, triangles) and 1 for
+ *              admissible / 0 for dense, sorted by (row_off, col_off).
+ * If the capacity is too small, *n_blocks is set and HMAT_EINVAL returned
+ * without writing `blocks`. Same validation as hmat_build for mesh/eta/leaf.
+ */
+hmat_status hmat_plan(const hmat_mesh* mesh, double eta, int32_t leaf, int32_t* order,
+                      int32_t* n_blocks, int32_t* blocks);
+
+/*
+ * hmat_block -- block b (0 <= b < n_blocks, canonical order of hmat_plan).
+ *   info   HOST int32[8]: row_off, row_len, col_off, col_len (triangles),
+ *          admissible flag, rank k (0 for dense), ACA stop reason
+ *          (1 threshold, 2 k = min(m,n), 3 all rows vanished; 0 for dense),
+ *          reserved.
+ *   A      HOST (may be NULL): dense block D_b (m x n, column-major, m = 3 row_len)
+ *          or the factor U_b (m x k, column-major).
+ *   B      HOST (may be NULL): V_b (n x k, column-major); unused for dense blocks.
+ *   prow, pcol  HOST int32 [k] (may be NULL): ACA pivot rows/columns (local DOF).
+ */
+hmat_status hmat_block(hmat_t h, int32_t b, int32_t* info, double* A, double* B, int32_t* prow,
+                       int32_t* pcol);
+
+/*
+ * hmat_entries -- A[rows[k], cols[k]] for k < n, evaluated on the device by
+ * the same entry code as the dense blocks and ACA (HOST int64 DOF indices in
+ * the caller's numbering, HOST float64 output). Synchronises the stream.
+ */
+hmat_status hmat_entries(hmat_t h, int64_t n, const int64_t* rows, const int64_t* cols,
+                         double* out, void* hip_stream);
+
+/*
+ * hmat_set_factors -- replace every admissible block's factors with the given
+ * ones (HOST): ranks [n_blocks] (entries of dense blocks ignored), and U, V
+ * concatenated over admissible blocks in canonical order, each block's U
+ * (m x k) then nothing else in U, V (n x k) in V, column-major. Lets the
+ * product be checked on factors computed elsewhere. Synchronises the stream.
+ */
+hmat_status hmat_set_factors(hmat_t h, const int32_t* ranks, const double* U, const double* V,
+                             void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HMAT_H */

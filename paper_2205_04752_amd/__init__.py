@@ -1,0 +1,220 @@
+"""Python binding of libhmat.so, the MI355X H-matrix library for the Lame
+single-layer operator (Kelvin kernel, collocation, ACA, H-matrix product).
+
+Argument marshalling only: every step runs in the HIP library through its C
+ABI (``include/hmat.h``). Device vectors are torch tensors on the ROCm device;
+torch supplies device memory and the current stream. There is no CPU fallback:
+if the library has not been built, loading it raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+__all__ = ["lib", "HMatrix", "plan", "HmatError", "LIB_PATH"]
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhmat.so")
+
+HMAT_OK, HMAT_EINVAL, HMAT_ENOMEM, HMAT_EDEVICE, HMAT_ENOCONV, HMAT_ENOTSUP = range(6)
+_STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ENOCONV", 5: "ENOTSUP"}
+
+
+class HmatError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"hmat {_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _Mesh(C.Structure):
+    _fields_ = [("n_vertices", C.c_int32), ("n_triangles", C.c_int32),
+                ("vertices", C.c_void_p), ("triangles", C.c_void_p)]
+
+
+class _Stats(C.Structure):
+    _fields_ = [("n_dof", C.c_int64), ("n_triangles", C.c_int32), ("n_clusters", C.c_int32),
+                ("depth", C.c_int32), ("n_blocks", C.c_int32), ("n_far", C.c_int32),
+                ("n_near", C.c_int32), ("c_sp", C.c_int32), ("rank_min", C.c_int32),
+                ("rank_max", C.c_int32), ("rank_mean", C.c_double), ("far_scalars", C.c_int64),
+                ("near_scalars", C.c_int64), ("compression", C.c_double),
+                ("n_rank_full", C.c_int32), ("n_near_threshold", C.c_int32),
+                ("aca_passes", C.c_int32), ("reserved", C.c_int32), ("t_plan_ms", C.c_double),
+                ("t_near_ms", C.c_double), ("t_aca_ms", C.c_double), ("t_build_ms", C.c_double),
+                ("device_bytes", C.c_int64)]
+
+
+class _SolveInfo(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("restarts", C.c_int32), ("relres", C.c_double),
+                ("time_ms", C.c_double)]
+
+
+EXPORTS = ["hmat_build", "hmat_matvec", "hmat_solve", "hmat_info", "hmat_free",
+           "hmat_last_error", "hmat_plan", "hmat_block", "hmat_entries", "hmat_set_factors"]
+
+_lib = None
+
+
+def lib():
+    """Load libhmat.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                           "or python paper_2205_04752_amd/build.py")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    L.hmat_build.argtypes = [C.POINTER(_Mesh), dbl, dbl, dbl, i32, dbl, vp, C.POINTER(vp)]
+    L.hmat_matvec.argtypes = [vp, i32, vp, i64, vp, i64, vp]
+    L.hmat_solve.argtypes = [vp, vp, vp, dbl, i32, i32, vp, C.POINTER(_SolveInfo)]
+    L.hmat_info.argtypes = [vp, C.POINTER(_Stats)]
+    L.hmat_free.argtypes = [vp]
+    L.hmat_last_error.restype = C.c_char_p
+    L.hmat_plan.argtypes = [C.POINTER(_Mesh), dbl, i32, vp, C.POINTER(i32), vp]
+    L.hmat_block.argtypes = [vp, i32, vp, vp, vp, vp, vp]
+    L.hmat_entries.argtypes = [vp, i64, vp, vp, vp, vp]
+    L.hmat_set_factors.argtypes = [vp, vp, vp, vp, vp]
+    for name in EXPORTS:
+        if name != "hmat_last_error":
+            getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def _check(st: int) -> None:
+    if st != HMAT_OK:
+        raise HmatError(st, lib().hmat_last_error().decode())
+
+
+def _mesh(vertices, triangles):
+    V = np.ascontiguousarray(vertices, dtype=np.float64)
+    T = np.ascontiguousarray(triangles, dtype=np.int32)
+    if V.ndim != 2 or V.shape[1] != 3 or T.ndim != 2 or T.shape[1] != 3:
+        raise ValueError("vertices must be [nv, 3] and triangles [nt, 3]")
+    m = _Mesh(V.shape[0], T.shape[0], V.ctypes.data, T.ctypes.data)
+    return m, (V, T)
+
+
+def _stream(stream):
+    if stream is not None:
+        return C.c_void_p(int(getattr(stream, "cuda_stream", stream)))
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev_ptr(t, n_dof, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64:
+        raise TypeError(f"{name} must be a float64 tensor on the GPU")
+    if t.dim() == 1:
+        t = t.unsqueeze(0)
+    if t.dim() != 2 or t.shape[1] != n_dof or t.stride(1) != 1:
+        raise ValueError(f"{name} must be [nrhs, {n_dof}] with unit column stride")
+    return t, t.data_ptr(), t.stride(0)
+
+
+def plan(vertices, triangles, eta: float = 2.0, leaf: int = 32):
+    """Host-only partition: (order [nt], blocks [nb, 5]: row_off, row_len, col_off, col_len, far)."""
+    m, keep = _mesh(vertices, triangles)
+    nb = C.c_int32(0)
+    order = np.zeros(m.n_triangles, dtype=np.int32)
+    _check(lib().hmat_plan(C.byref(m), float(eta), int(leaf), order.ctypes.data, C.byref(nb), None))
+    blocks = np.zeros((nb.value, 5), dtype=np.int32)
+    _check(lib().hmat_plan(C.byref(m), float(eta), int(leaf), None, C.byref(nb), blocks.ctypes.data))
+    return order, blocks
+
+
+class HMatrix:
+    """Device-resident H-matrix of the Kelvin single-layer collocation matrix."""
+
+    def __init__(self, vertices, triangles, E=1.0, nu=0.3, eta=2.0, leaf=32, eps=1e-4,
+                 stream=None):
+        m, keep = _mesh(vertices, triangles)
+        h = C.c_void_p()
+        _check(lib().hmat_build(C.byref(m), float(E), float(nu), float(eta), int(leaf),
+                                float(eps), _stream(stream), C.byref(h)))
+        self._h = h
+        self.n_triangles = m.n_triangles
+        self.n_dof = 3 * m.n_triangles
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().hmat_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def matvec(self, x, y=None, stream=None):
+        """y = A_H x for x of shape [nrhs, n_dof] (or [n_dof]); float64 on the GPU."""
+        import torch
+        squeeze = x.dim() == 1
+        x2, xp, ldx = _dev_ptr(x, self.n_dof, "x")
+        if y is None:
+            y = torch.empty_like(x2)
+        y2, yp, ldy = _dev_ptr(y, self.n_dof, "y")
+        if y2.shape[0] != x2.shape[0]:
+            raise ValueError("x and y must hold the same number of vectors")
+        _check(lib().hmat_matvec(self._h, x2.shape[0], xp, ldx, yp, ldy, _stream(stream)))
+        return y2[0] if squeeze else y2
+
+    def solve(self, b, x=None, tol=1e-8, restart=50, maxit=10000, stream=None, check=True):
+        """GMRES(restart) for A_H x = b; returns (x, info dict)."""
+        import torch
+        b2, bp, _ = _dev_ptr(b, self.n_dof, "b")
+        if x is None:
+            x = torch.empty_like(b2[0])
+        x2, xp, _ = _dev_ptr(x, self.n_dof, "x")
+        info = _SolveInfo()
+        st = lib().hmat_solve(self._h, bp, xp, float(tol), int(restart), int(maxit),
+                              _stream(stream), C.byref(info))
+        if st not in (HMAT_OK, HMAT_ENOCONV) or (check and st != HMAT_OK):
+            _check(st)
+        return x2[0], dict(status=st, iterations=info.iterations, restarts=info.restarts,
+                           relres=info.relres, time_ms=info.time_ms)
+
+    def info(self) -> dict:
+        s = _Stats()
+        _check(lib().hmat_info(self._h, C.byref(s)))
+        return {k: getattr(s, k) for k, _ in _Stats._fields_}
+
+    def block(self, b: int) -> dict:
+        """Host copy of block b (canonical order): info, dense D or factors U, V, pivots."""
+        info = np.zeros(8, dtype=np.int32)
+        _check(lib().hmat_block(self._h, int(b), info.ctypes.data, None, None, None, None))
+        m, n, k = 3 * int(info[1]), 3 * int(info[3]), int(info[5])
+        out = dict(row_off=int(info[0]), row_len=int(info[1]), col_off=int(info[2]),
+                   col_len=int(info[3]), far=int(info[4]), rank=k, stop=int(info[6]))
+        if info[4]:
+            U = np.zeros(m * k)
+            V = np.zeros(n * k)
+            pr = np.zeros(k, dtype=np.int32)
+            pc = np.zeros(k, dtype=np.int32)
+            _check(lib().hmat_block(self._h, int(b), info.ctypes.data, U.ctypes.data,
+                                    V.ctypes.data, pr.ctypes.data, pc.ctypes.data))
+            out.update(U=U.reshape(k, m).T.copy(), V=V.reshape(k, n).T.copy(), rows=pr, cols=pc)
+        else:
+            D = np.zeros(m * n)
+            _check(lib().hmat_block(self._h, int(b), info.ctypes.data, D.ctypes.data, None,
+                                    None, None))
+            out.update(D=D.reshape(n, m).T.copy())
+        return out
+
+    def entries(self, rows, cols, stream=None) -> np.ndarray:
+        r = np.ascontiguousarray(rows, dtype=np.int64)
+        c = np.ascontiguousarray(cols, dtype=np.int64)
+        out = np.zeros(r.shape[0])
+        _check(lib().hmat_entries(self._h, r.shape[0], r.ctypes.data, c.ctypes.data,
+                                  out.ctypes.data, _stream(stream)))
+        return out
+
+    def set_factors(self, ranks, U_cat, V_cat, stream=None) -> None:
+        rk = np.ascontiguousarray(ranks, dtype=np.int32)
+        U = np.ascontiguousarray(U_cat, dtype=np.float64)
+        V = np.ascontiguousarray(V_cat, dtype=np.float64)
+        _check(lib().hmat_set_factors(self._h, rk.ctypes.data, U.ctypes.data, V.ctypes.data,
+                                      _stream(stream)))

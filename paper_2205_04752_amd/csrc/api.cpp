@@ -1,0 +1,826 @@
+// C ABI of the H-matrix library: validation, handle lifetime, build
+// orchestration (plan -> K1 -> K2 -> compaction -> product plan), the product,
+// GMRES and the inspection entry points.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "hmat_internal.hpp"
+
+namespace hm {
+hipError_t launch_self(const DevGeo&, const SelfTask*, double*, hipStream_t);
+hipError_t launch_near_only(const DevGeo&, const NearTask*, int, double*, hipStream_t);
+hipError_t launch_entries(const DevGeo&, int64_t, const int64_t*, const int64_t*, double*, hipStream_t);
+hipError_t launch_aca(const DevGeo&, const AcaTask*, int, size_t, double, int32_t*, int32_t*, double*, hipStream_t);
+hipError_t launch_compact(const CopyTask*, int, hipStream_t);
+hipError_t launch_gather(int, const double*, int64_t, const int32_t*, int64_t, double*, hipStream_t);
+hipError_t launch_matvec_group(int, const MvA*, int, const MvChunk*, int, const MvSeg*, const int32_t*, int,
+                               const double*, const double*, const double*, int64_t, double*, int64_t,
+                               double*, const int32_t*, int64_t, double*, int64_t, hipStream_t);
+hipError_t launch_dots(const double*, int64_t, int64_t, int, const double*, double*, hipStream_t);
+hipError_t launch_sub_proj(const double*, int64_t, int64_t, int, const double*, double*, double*, hipStream_t);
+hipError_t launch_norm(const double*, int64_t, double*, hipStream_t);
+hipError_t launch_scale(const double*, int64_t, const double*, double*, hipStream_t);
+hipError_t launch_add_comb(const double*, int64_t, int64_t, int, const double*, double*, hipStream_t);
+hipError_t launch_residual(const double*, int64_t, double*, hipStream_t);
+hipError_t launch_fill(double*, int64_t, double, hipStream_t);
+}  // namespace hm
+
+using namespace hm;
+
+namespace {
+
+thread_local std::string g_err;
+
+hmat_status fail(hmat_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+struct HipError {
+  hmat_status st;
+  std::string msg;
+};
+
+void check(hipError_t e, const char* what) {
+  if (e == hipSuccess) return;
+  const bool oom = (e == hipErrorOutOfMemory);
+  (void)hipGetLastError();
+  throw HipError{oom ? HMAT_ENOMEM : HMAT_EDEVICE, std::string(what) + ": " + hipGetErrorString(e)};
+}
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  void alloc(size_t b, const char* what) {
+    release();
+    if (b == 0) return;
+    check(hipMalloc(&p, b), what);
+    bytes = b;
+  }
+  template <class T>
+  T* as() const { return static_cast<T*>(p); }
+};
+
+template <class T>
+void upload(DevBuf& d, const std::vector<T>& h, hipStream_t s, const char* what) {
+  d.alloc(h.size() * sizeof(T), what);
+  if (!h.empty()) check(hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s), what);
+}
+
+constexpr int KCAP_FIRST = 128;  // first-pass panel capacity (columns) of ACA
+constexpr int MV_TILE = 64;      // rows per product tile (one wave)
+constexpr int MV_SEG_COLS = 128; // columns per product segment
+constexpr int64_t MV_CHUNK_BYTES = 96 * 1024;
+constexpr int MV_MAX_NR = 16;    // right-hand sides per pass over the matrix
+
+double ms_since(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace
+
+struct hmat {
+  int device = 0;
+  Plan plan;
+  double E = 0, nu = 0, eta = 0, eps = 0;
+  int32_t leaf = 0;
+  int64_t N = 0;
+  DevBuf d_cen, d_q, d_vtx, d_gl, d_order;
+  DevGeo G{};
+  std::vector<int32_t> inv_order;  // caller's triangle -> cluster position
+  // block bookkeeping (canonical order)
+  std::vector<int32_t> kind_index;  // far index or near index of block b
+  std::vector<int32_t> far_blocks, near_blocks;
+  std::vector<int64_t> near_off;
+  DevBuf near_arena;
+  std::vector<int32_t> rank, stop;
+  std::vector<double> ratio;
+  std::vector<int64_t> far_off;
+  DevBuf far_arena;
+  DevBuf piv1, piv2;
+  std::vector<const int32_t*> piv_ptr;  // per far block: device [2][cap]
+  std::vector<int32_t> piv_cap;
+  int aca_passes = 0;
+  // product plan
+  DevBuf d_mvA, d_seg, d_chunk, d_tile_chunk;
+  int nA = 0, nSeg = 0, nChunk = 0, nTiles = 0;
+  int64_t Ztot = 0;
+  DevBuf d_xp, d_z, d_part;
+  // GMRES workspace
+  DevBuf d_Q, d_w, d_small;
+  int q_cols = 0;
+  hmat_stats st{};
+};
+
+namespace {
+
+int64_t block_m(const hmat* h, int32_t b) { return 3 * (int64_t)h->plan.cl[h->plan.blk[b].t].len; }
+int64_t block_n(const hmat* h, int32_t b) { return 3 * (int64_t)h->plan.cl[h->plan.blk[b].s].len; }
+
+// Product plan: phase-A items per far block and column group, phase-B segments
+// per (block, 64-row tile, column range), grouped into chunks of about
+// MV_CHUNK_BYTES per tile.
+void build_product_plan(hmat* h, hipStream_t s) {
+  const Plan& P = h->plan;
+  std::vector<MvA> items;
+  std::vector<int64_t> zoff(h->far_blocks.size(), 0);
+  int64_t z = 0;
+  for (size_t f = 0; f < h->far_blocks.size(); f++) {
+    const int32_t b = h->far_blocks[f];
+    const int32_t k = h->rank[f];
+    zoff[f] = z;
+    if (k == 0) continue;
+    const int64_t m = block_m(h, b), n = block_n(h, b);
+    for (int32_t l0 = 0; l0 < k; l0 += 8)
+      items.push_back(MvA{h->far_off[f] + m * k, (int32_t)n, l0, std::min(k, l0 + 8),
+                          3 * P.cl[P.blk[b].s].off, (int32_t)(z + l0), 0});
+    z += k;
+  }
+  h->Ztot = std::max<int64_t>(z, 1);
+  struct SegT { int32_t tile; MvSeg seg; };
+  std::vector<SegT> segs;
+  for (size_t b = 0; b < P.blk.size(); b++) {
+    const BlockRec& B = P.blk[b];
+    const int64_t r0 = 3 * (int64_t)P.cl[B.t].off, m = block_m(h, (int32_t)b);
+    int64_t base, ncols, soff;
+    int32_t far;
+    if (B.far) {
+      const int32_t f = h->kind_index[b];
+      if (h->rank[f] == 0) continue;
+      base = h->far_off[f];
+      ncols = h->rank[f];
+      soff = zoff[f];
+      far = 1;
+    } else {
+      const int32_t nidx = h->kind_index[b];
+      base = h->near_off[nidx];
+      ncols = block_n(h, (int32_t)b);
+      soff = 3 * (int64_t)P.cl[B.s].off;
+      far = 0;
+    }
+    for (int64_t T = r0 / MV_TILE; T * MV_TILE < r0 + m; T++) {
+      const int64_t lo = std::max(r0, T * MV_TILE) - T * MV_TILE;
+      const int64_t hi = std::min(r0 + m, (T + 1) * MV_TILE) - T * MV_TILE;
+      for (int64_t c0 = 0; c0 < ncols; c0 += MV_SEG_COLS) {
+        MvSeg sg{};
+        sg.a_off = base + (T * MV_TILE - r0);
+        sg.lda = (int32_t)m;
+        sg.c0 = (int32_t)c0;
+        sg.c1 = (int32_t)std::min<int64_t>(ncols, c0 + MV_SEG_COLS);
+        sg.soff = (int32_t)soff;
+        sg.row_lo = (int16_t)lo;
+        sg.row_hi = (int16_t)hi;
+        sg.far = far;
+        segs.push_back(SegT{(int32_t)T, sg});
+      }
+    }
+  }
+  std::stable_sort(segs.begin(), segs.end(), [](const SegT& a, const SegT& b) { return a.tile < b.tile; });
+  h->nTiles = (int)((h->N + MV_TILE - 1) / MV_TILE);
+  std::vector<MvSeg> flat(segs.size());
+  std::vector<MvChunk> chunks;
+  std::vector<int32_t> tile_chunk(h->nTiles + 1, 0);
+  size_t i = 0;
+  for (int32_t T = 0; T < h->nTiles; T++) {
+    tile_chunk[T] = (int32_t)chunks.size();
+    while (i < segs.size() && segs[i].tile == T) {
+      MvChunk c{T, (int32_t)i, (int32_t)i, 0};
+      int64_t bytes = 0;
+      while (i < segs.size() && segs[i].tile == T && (bytes < MV_CHUNK_BYTES || c.seg_hi == c.seg_lo)) {
+        const MvSeg& sg = segs[i].seg;
+        bytes += (int64_t)(sg.row_hi - sg.row_lo) * (sg.c1 - sg.c0) * 8;
+        flat[i] = sg;
+        i++;
+        c.seg_hi = (int32_t)i;
+      }
+      chunks.push_back(c);
+    }
+  }
+  tile_chunk[h->nTiles] = (int32_t)chunks.size();
+  h->nA = (int)items.size();
+  h->nSeg = (int)flat.size();
+  h->nChunk = (int)chunks.size();
+  upload(h->d_mvA, items, s, "product plan");
+  upload(h->d_seg, flat, s, "product plan");
+  upload(h->d_chunk, chunks, s, "product plan");
+  upload(h->d_tile_chunk, tile_chunk, s, "product plan");
+  h->d_xp.alloc(sizeof(double) * MV_MAX_NR * h->N, "product workspace");
+  h->d_z.alloc(sizeof(double) * MV_MAX_NR * h->Ztot, "product workspace");
+  h->d_part.alloc(sizeof(double) * MV_MAX_NR * MV_TILE * std::max(1, h->nChunk), "product workspace");
+}
+
+void fill_stats(hmat* h) {
+  hmat_stats& st = h->st;
+  const Plan& P = h->plan;
+  st.n_dof = h->N;
+  st.n_triangles = P.nt;
+  st.n_clusters = (int32_t)P.cl.size();
+  st.depth = P.depth;
+  st.n_blocks = (int32_t)P.blk.size();
+  st.n_far = (int32_t)h->far_blocks.size();
+  st.n_near = (int32_t)h->near_blocks.size();
+  st.c_sp = P.csp;
+  st.rank_min = INT32_MAX;
+  st.rank_max = 0;
+  double rs = 0;
+  st.far_scalars = 0;
+  st.near_scalars = 0;
+  st.n_rank_full = 0;
+  st.n_near_threshold = 0;
+  for (size_t f = 0; f < h->far_blocks.size(); f++) {
+    const int32_t b = h->far_blocks[f], k = h->rank[f];
+    st.rank_min = std::min(st.rank_min, k);
+    st.rank_max = std::max(st.rank_max, k);
+    rs += k;
+    st.far_scalars += (int64_t)k * (block_m(h, b) + block_n(h, b));
+    if (h->stop[f] == 2) st.n_rank_full++;
+    if (h->ratio[f] >= 1.0 - 1e-9 && h->ratio[f] <= 1.0) st.n_near_threshold++;
+  }
+  if (h->far_blocks.empty()) st.rank_min = 0;
+  st.rank_mean = h->far_blocks.empty() ? 0.0 : rs / h->far_blocks.size();
+  for (int32_t b : h->near_blocks) st.near_scalars += block_m(h, b) * block_n(h, b);
+  st.compression = (double)(st.far_scalars + st.near_scalars) / ((double)h->N * (double)h->N);
+  st.aca_passes = h->aca_passes;
+  st.device_bytes = (int64_t)(h->d_cen.bytes + h->d_q.bytes + h->d_vtx.bytes + h->d_gl.bytes +
+                              h->d_order.bytes + h->near_arena.bytes + h->far_arena.bytes +
+                              h->piv1.bytes + h->piv2.bytes + h->d_mvA.bytes + h->d_seg.bytes +
+                              h->d_chunk.bytes + h->d_tile_chunk.bytes + h->d_xp.bytes +
+                              h->d_z.bytes + h->d_part.bytes + h->d_Q.bytes + h->d_w.bytes +
+                              h->d_small.bytes);
+}
+
+struct EventPair {
+  hipEvent_t a = nullptr, b = nullptr;
+  EventPair() {
+    check(hipEventCreate(&a), "event");
+    check(hipEventCreate(&b), "event");
+  }
+  ~EventPair() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+  double ms() const {
+    float t = 0.f;
+    (void)hipEventElapsedTime(&t, a, b);
+    return t;
+  }
+};
+
+// One ACA pass over the far blocks listed in `fidx` with per-block capacity
+// cap(f); panels in `panels`, pivots in `piv`.
+template <class CapFn>
+void run_aca_pass(hmat* h, const std::vector<int32_t>& fidx, CapFn cap, DevBuf& panels, DevBuf& piv,
+                  DevBuf& d_rank, DevBuf& d_stop, DevBuf& d_ratio,
+                  std::vector<const double*>& panel_ptr, hipStream_t s) {
+  const Plan& P = h->plan;
+  std::vector<int32_t> ord(fidx);
+  std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) {
+    const BlockRec& A = P.blk[h->far_blocks[a]];
+    const BlockRec& B = P.blk[h->far_blocks[b]];
+    return (int64_t)P.cl[A.t].len + P.cl[A.s].len > (int64_t)P.cl[B.t].len + P.cl[B.s].len;
+  });
+  int64_t panel_total = 0, piv_total = 0;
+  size_t shmem = 0;
+  for (int32_t f : ord) {
+    const int32_t b = h->far_blocks[f];
+    const int64_t m = block_m(h, b), n = block_n(h, b);
+    const int32_t kc = cap(f);
+    panel_total += (m + n) * kc;
+    piv_total += 2 * (int64_t)kc;
+    shmem = std::max(shmem, (size_t)kc * 8 + (size_t)((m + 31) / 32) * 4);
+  }
+  if (shmem > 160 * 1024) throw HipError{HMAT_ENOTSUP, "ACA panel row exceeds LDS capacity"};
+  panels.alloc(sizeof(double) * panel_total, "ACA panels");
+  piv.alloc(sizeof(int32_t) * piv_total, "ACA pivots");
+  std::vector<AcaTask> tasks;
+  tasks.reserve(ord.size());
+  int64_t po = 0, vo = 0;
+  for (int32_t f : ord) {
+    const int32_t b = h->far_blocks[f];
+    const BlockRec& B = P.blk[b];
+    const int64_t m = block_m(h, b), n = block_n(h, b);
+    const int32_t kc = cap(f);
+    AcaTask t{};
+    t.t_off = P.cl[B.t].off;
+    t.t_len = P.cl[B.t].len;
+    t.s_off = P.cl[B.s].off;
+    t.s_len = P.cl[B.s].len;
+    t.panel = panels.as<double>() + po;
+    t.piv = piv.as<int32_t>() + vo;
+    t.kcap = kc;
+    t.blk = f;
+    tasks.push_back(t);
+    h->piv_ptr[f] = t.piv;
+    h->piv_cap[f] = kc;
+    panel_ptr[f] = t.panel;
+    po += (m + n) * kc;
+    vo += 2 * (int64_t)kc;
+  }
+  DevBuf d_tasks;
+  upload(d_tasks, tasks, s, "ACA tasks");
+  check(launch_aca(h->G, d_tasks.as<AcaTask>(), (int)tasks.size(), shmem, h->eps, d_rank.as<int32_t>(),
+                   d_stop.as<int32_t>(), d_ratio.as<double>(), s),
+        "ACA launch");
+  check(hipStreamSynchronize(s), "ACA");
+}
+
+hmat_status build_impl(const hmat_mesh* mesh, double E, double nu, double eta, int32_t leaf,
+                       double eps, hipStream_t s, hmat** out) {
+  auto t0 = std::chrono::steady_clock::now();
+  hmat* h = new (std::nothrow) hmat();
+  if (!h) return fail(HMAT_ENOMEM, "host allocation failed");
+  try {
+    check(hipGetDevice(&h->device), "hipGetDevice");
+    h->E = E;
+    h->nu = nu;
+    h->eta = eta;
+    h->leaf = leaf;
+    h->eps = eps;
+    make_plan(mesh, eta, leaf, h->plan);
+    const Plan& P = h->plan;
+    const int32_t nt = P.nt;
+    h->N = 3 * (int64_t)nt;
+    h->inv_order.assign(nt, 0);
+    for (int32_t p = 0; p < nt; p++) h->inv_order[P.order[p]] = p;
+    HostGeometry hg;
+    make_geometry(mesh, P, hg);
+    upload(h->d_cen, hg.cen, s, "geometry");
+    upload(h->d_q, hg.q, s, "geometry");
+    upload(h->d_vtx, hg.vtx, s, "geometry");
+    upload(h->d_gl, hg.gl, s, "geometry");
+    upload(h->d_order, P.order, s, "geometry");
+    const double cK = (1.0 + nu) / (8.0 * M_PI * E * (1.0 - nu));
+    h->G = DevGeo{h->d_cen.as<double>(), h->d_q.as<double>(), h->d_vtx.as<double>(),
+                  h->d_gl.as<double>(), nt, 0, cK * (3.0 - 4.0 * nu), cK};
+    // classify blocks
+    h->kind_index.assign(P.blk.size(), -1);
+    for (size_t b = 0; b < P.blk.size(); b++) {
+      if (P.blk[b].far) {
+        h->kind_index[b] = (int32_t)h->far_blocks.size();
+        h->far_blocks.push_back((int32_t)b);
+      } else {
+        h->kind_index[b] = (int32_t)h->near_blocks.size();
+        h->near_blocks.push_back((int32_t)b);
+      }
+    }
+    // near arena and tasks
+    std::vector<NearTask> ntasks;
+    std::vector<SelfTask> stasks(nt);
+    int64_t noff = 0;
+    for (int32_t b : h->near_blocks) {
+      const BlockRec& B = P.blk[b];
+      const Cluster& T = P.cl[B.t];
+      const Cluster& S = P.cl[B.s];
+      h->near_off.push_back(noff);
+      ntasks.push_back(NearTask{T.off, T.len, S.off, S.len, noff});
+      if (B.t == B.s)
+        for (int32_t p = 0; p < T.len; p++) stasks[T.off + p] = SelfTask{noff, 3 * T.len, p};
+      noff += 9 * (int64_t)T.len * S.len;
+    }
+    {
+      std::vector<char> seen(nt, 0);
+      for (int32_t b : h->near_blocks)
+        if (P.blk[b].t == P.blk[b].s)
+          for (int32_t p = 0; p < P.cl[P.blk[b].t].len; p++) seen[P.cl[P.blk[b].t].off + p] = 1;
+      for (int32_t p = 0; p < nt; p++)
+        if (!seen[p]) throw HipError{HMAT_EDEVICE, "internal: triangle without diagonal dense block"};
+    }
+    h->st.t_plan_ms = ms_since(t0);
+    h->near_arena.alloc(sizeof(double) * noff, "dense blocks");
+    DevBuf d_ntasks, d_stasks;
+    upload(d_ntasks, ntasks, s, "dense tasks");
+    upload(d_stasks, stasks, s, "self tasks");
+    EventPair evn;
+    check(hipEventRecord(evn.a, s), "event");
+    check(launch_near_only(h->G, d_ntasks.as<NearTask>(), (int)ntasks.size(), h->near_arena.as<double>(), s), "K1 launch");
+    check(launch_self(h->G, d_stasks.as<SelfTask>(), h->near_arena.as<double>(), s), "K1 self launch");
+    check(hipEventRecord(evn.b, s), "event");
+    // ACA
+    const size_t nf = h->far_blocks.size();
+    h->rank.assign(nf, 0);
+    h->stop.assign(nf, 0);
+    h->ratio.assign(nf, 0.0);
+    h->piv_ptr.assign(nf, nullptr);
+    h->piv_cap.assign(nf, 0);
+    DevBuf d_rank, d_stop, d_ratio, panels1, panels2;
+    d_rank.alloc(sizeof(int32_t) * std::max<size_t>(nf, 1), "ACA ranks");
+    d_stop.alloc(sizeof(int32_t) * std::max<size_t>(nf, 1), "ACA ranks");
+    d_ratio.alloc(sizeof(double) * std::max<size_t>(nf, 1), "ACA ranks");
+    EventPair eva;
+    check(hipEventRecord(eva.a, s), "event");
+    std::vector<int32_t> all(nf);
+    std::iota(all.begin(), all.end(), 0);
+    auto cap1 = [&](int32_t f) {
+      const int32_t b = h->far_blocks[f];
+      return (int32_t)std::min<int64_t>(std::min(block_m(h, b), block_n(h, b)), KCAP_FIRST);
+    };
+    std::vector<int32_t> capv(nf, 0);
+    std::vector<const double*> panel_ptr(nf, nullptr);
+    for (size_t f = 0; f < nf; f++) capv[f] = cap1((int32_t)f);
+    h->aca_passes = 0;
+    if (nf > 0) {
+      run_aca_pass(h, all, cap1, panels1, h->piv1, d_rank, d_stop, d_ratio, panel_ptr, s);
+      h->aca_passes = 1;
+      check(hipMemcpy(h->rank.data(), d_rank.p, sizeof(int32_t) * nf, hipMemcpyDeviceToHost), "ranks");
+      check(hipMemcpy(h->stop.data(), d_stop.p, sizeof(int32_t) * nf, hipMemcpyDeviceToHost), "ranks");
+      std::vector<int32_t> again;
+      for (size_t f = 0; f < nf; f++)
+        if (h->stop[f] == 4) again.push_back((int32_t)f);
+      if (!again.empty()) {
+        auto cap2 = [&](int32_t f) {
+          const int32_t b = h->far_blocks[f];
+          return (int32_t)std::min(block_m(h, b), block_n(h, b));
+        };
+        for (int32_t f : again) capv[f] = cap2(f);
+        run_aca_pass(h, again, cap2, panels2, h->piv2, d_rank, d_stop, d_ratio, panel_ptr, s);
+        h->aca_passes = 2;
+        check(hipMemcpy(h->rank.data(), d_rank.p, sizeof(int32_t) * nf, hipMemcpyDeviceToHost), "ranks");
+        check(hipMemcpy(h->stop.data(), d_stop.p, sizeof(int32_t) * nf, hipMemcpyDeviceToHost), "ranks");
+      }
+      check(hipMemcpy(h->ratio.data(), d_ratio.p, sizeof(double) * nf, hipMemcpyDeviceToHost), "ranks");
+      for (size_t f = 0; f < nf; f++)
+        if (h->stop[f] == 5)
+          throw HipError{HMAT_EINVAL, "non-finite matrix entries (overlapping or duplicate triangles?)"};
+      // compaction into the final arena
+      h->far_off.assign(nf, 0);
+      int64_t fo = 0;
+      for (size_t f = 0; f < nf; f++) {
+        const int32_t b = h->far_blocks[f];
+        h->far_off[f] = fo;
+        fo += (int64_t)h->rank[f] * (block_m(h, b) + block_n(h, b));
+      }
+      h->far_arena.alloc(sizeof(double) * std::max<int64_t>(fo, 1), "low-rank arena");
+      const std::vector<const double*>& src = panel_ptr;
+      std::vector<CopyTask> ct;
+      for (size_t f = 0; f < nf; f++) {
+        const int32_t b = h->far_blocks[f];
+        const int32_t m = (int32_t)block_m(h, b), n = (int32_t)block_n(h, b), k = h->rank[f];
+        if (k == 0) continue;
+        ct.push_back(CopyTask{src[f], src[f] + (int64_t)m * capv[f],
+                              h->far_arena.as<double>() + h->far_off[f], m, n, k, 0});
+      }
+      DevBuf d_ct;
+      upload(d_ct, ct, s, "compaction tasks");
+      check(launch_compact(d_ct.as<CopyTask>(), (int)ct.size(), s), "compaction launch");
+      check(hipStreamSynchronize(s), "compaction");
+      panels1.release();
+      panels2.release();
+    } else {
+      h->far_arena.alloc(sizeof(double), "low-rank arena");
+    }
+    check(hipEventRecord(eva.b, s), "event");
+    check(hipStreamSynchronize(s), "build");
+    h->st.t_near_ms = evn.ms();
+    h->st.t_aca_ms = eva.ms();
+    build_product_plan(h, s);
+    check(hipStreamSynchronize(s), "build");
+    fill_stats(h);
+    h->st.t_build_ms = ms_since(t0);
+    *out = h;
+    return HMAT_OK;
+  } catch (const HipError& e) {
+    (void)hipStreamSynchronize(s);
+    delete h;
+    return fail(e.st, e.msg);
+  } catch (const std::bad_alloc&) {
+    (void)hipStreamSynchronize(s);
+    delete h;
+    return fail(HMAT_ENOMEM, "host allocation failed");
+  }
+}
+
+void matvec_impl(hmat* h, int32_t nrhs, const double* x, int64_t ldx, double* y, int64_t ldy,
+                 hipStream_t s) {
+  for (int32_t r0 = 0; r0 < nrhs; r0 += MV_MAX_NR) {
+    const int nr = std::min<int32_t>(MV_MAX_NR, nrhs - r0);
+    check(launch_gather(nr, x + r0 * ldx, ldx, h->d_order.as<int32_t>(), h->N, h->d_xp.as<double>(), s), "gather");
+    check(launch_matvec_group(nr, h->d_mvA.as<MvA>(), h->nA, h->d_chunk.as<MvChunk>(), h->nChunk,
+                              h->d_seg.as<MvSeg>(), h->d_tile_chunk.as<int32_t>(), h->nTiles,
+                              h->far_arena.as<double>(), h->near_arena.as<double>(), h->d_xp.as<double>(),
+                              h->N, h->d_z.as<double>(), h->Ztot, h->d_part.as<double>(),
+                              h->d_order.as<int32_t>(), h->N, y + r0 * ldy, ldy, s),
+          "product");
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* hmat_last_error(void) { return g_err.c_str(); }
+
+hmat_status hmat_build(const hmat_mesh* mesh, double E, double nu, double eta, int32_t leaf,
+                       double eps, void* hip_stream, hmat_t* out) {
+  if (!out) return fail(HMAT_EINVAL, "out is NULL");
+  *out = nullptr;
+  std::string err;
+  hmat_status st = validate_params(E, nu, eta, leaf, eps, err);
+  if (st != HMAT_OK) return fail(st, err);
+  st = validate_mesh(mesh, err);
+  if (st != HMAT_OK) return fail(st, err);
+  g_err.clear();
+  return build_impl(mesh, E, nu, eta, leaf, eps, (hipStream_t)hip_stream, out);
+}
+
+hmat_status hmat_matvec(hmat_t h, int32_t nrhs, const double* x, int64_t ldx, double* y,
+                        int64_t ldy, void* hip_stream) {
+  if (!h) return fail(HMAT_EINVAL, "handle is NULL");
+  if (!x || !y) return fail(HMAT_EINVAL, "x or y is NULL");
+  if (nrhs < 1 || nrhs > 64) return fail(HMAT_EINVAL, "nrhs must lie in [1, 64]");
+  if (ldx < h->N || ldy < h->N) return fail(HMAT_EINVAL, "ldx and ldy must be >= n_dof");
+  const char* xa = (const char*)x;
+  const char* xb = (const char*)(x + (nrhs - 1) * ldx + h->N);
+  const char* ya = (const char*)y;
+  const char* yb = (const char*)(y + (nrhs - 1) * ldy + h->N);
+  if (xa < yb && ya < xb) return fail(HMAT_EINVAL, "x and y overlap");
+  try {
+    matvec_impl(h, nrhs, x, ldx, y, ldy, (hipStream_t)hip_stream);
+  } catch (const HipError& e) {
+    return fail(e.st, e.msg);
+  }
+  return HMAT_OK;
+}
+
+hmat_status hmat_solve(hmat_t h, const double* b, double* x, double tol, int32_t restart,
+                       int32_t maxit, void* hip_stream, hmat_solve_info* info) {
+  if (!h) return fail(HMAT_EINVAL, "handle is NULL");
+  if (!b || !x) return fail(HMAT_EINVAL, "b or x is NULL");
+  if (b == x) return fail(HMAT_EINVAL, "b and x alias");
+  if (!(tol > 0.0)) return fail(HMAT_EINVAL, "tol must be > 0");
+  if (restart < 1 || restart > 1024) return fail(HMAT_EINVAL, "restart must lie in [1, 1024]");
+  if (maxit < 1) return fail(HMAT_EINVAL, "maxit must be >= 1");
+  hipStream_t s = (hipStream_t)hip_stream;
+  auto t0 = std::chrono::steady_clock::now();
+  const int64_t N = h->N;
+  const int m = restart;
+  try {
+    if (h->q_cols < m + 1) {
+      h->d_Q.alloc(sizeof(double) * N * (m + 1), "GMRES basis");
+      h->q_cols = m + 1;
+    }
+    if (!h->d_w.p) h->d_w.alloc(sizeof(double) * N, "GMRES work");
+    if (h->d_small.bytes < sizeof(double) * (3 * 1026 + 8)) h->d_small.alloc(sizeof(double) * (3 * 1026 + 8), "GMRES work");
+    double* Q = h->d_Q.as<double>();
+    double* w = h->d_w.as<double>();
+    double* hdot = h->d_small.as<double>();        // [m+1] projections of one pass
+    double* hacc = hdot + 1026;                      // [m+2] accumulated Hessenberg column
+    double* ycoef = hacc + 1026;                     // [m]
+    double* scal = ycoef + 1026;                     // scalars
+    auto norm_host = [&](const double* v) {
+      check(launch_norm(v, N, scal, s), "norm");
+      double r = 0;
+      check(hipMemcpyAsync(&r, scal, sizeof(double), hipMemcpyDeviceToHost, s), "norm");
+      check(hipStreamSynchronize(s), "norm");
+      return r;
+    };
+    check(launch_fill(x, N, 0.0, s), "fill");
+    const double bn = norm_host(b);
+    int total = 0, restarts = 0;
+    double rel = 0.0;
+    hmat_status status = HMAT_ENOCONV;
+    std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1), yv(m), col(m + 2);
+    if (bn == 0.0) {
+      status = HMAT_OK;
+      rel = 0.0;
+    } else {
+      for (;;) {
+        matvec_impl(h, 1, x, N, w, N, s);
+        check(launch_residual(b, N, w, s), "residual");
+        const double beta = norm_host(w);
+        rel = beta / bn;
+        if (beta <= tol * bn) {
+          status = HMAT_OK;
+          break;
+        }
+        if (total >= maxit) break;
+        check(launch_scale(w, N, scal, Q, s), "scale");  // scal[0] = ||r|| from norm_host
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int j = 0;
+        for (; j < m && total < maxit;) {
+          matvec_impl(h, 1, Q + (size_t)j * N, N, w, N, s);
+          total++;
+          check(launch_fill(hacc, j + 2, 0.0, s), "fill");
+          for (int pass = 0; pass < 2; pass++) {
+            check(launch_dots(Q, N, N, j + 1, w, hdot, s), "dots");
+            check(launch_sub_proj(Q, N, N, j + 1, hdot, w, hacc, s), "project");
+          }
+          check(launch_norm(w, N, hacc + j + 1, s), "norm");
+          check(launch_scale(w, N, hacc + j + 1, Q + (size_t)(j + 1) * N, s), "scale");
+          check(hipMemcpyAsync(col.data(), hacc, sizeof(double) * (j + 2), hipMemcpyDeviceToHost, s), "hessenberg");
+          check(hipStreamSynchronize(s), "hessenberg");
+          for (int i = 0; i <= j + 1; i++) H[(size_t)i * m + j] = col[i];
+          const double hn = col[j + 1];
+          for (int i = 0; i < j; i++) {
+            const double a = H[(size_t)i * m + j], c2 = H[(size_t)(i + 1) * m + j];
+            H[(size_t)i * m + j] = cs[i] * a + sn[i] * c2;
+            H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * c2;
+          }
+          const double a = H[(size_t)j * m + j], c2 = H[(size_t)(j + 1) * m + j];
+          const double den = std::sqrt(a * a + c2 * c2);
+          cs[j] = den == 0.0 ? 1.0 : a / den;
+          sn[j] = den == 0.0 ? 0.0 : c2 / den;
+          H[(size_t)j * m + j] = cs[j] * a + sn[j] * c2;
+          H[(size_t)(j + 1) * m + j] = 0.0;
+          g[j + 1] = -sn[j] * g[j];
+          g[j] = cs[j] * g[j];
+          j++;
+          if (std::fabs(g[j]) <= tol * bn || hn == 0.0) break;
+        }
+        for (int i = j - 1; i >= 0; i--) {
+          double sum = g[i];
+          for (int q = i + 1; q < j; q++) sum -= H[(size_t)i * m + q] * yv[q];
+          yv[i] = sum / H[(size_t)i * m + i];
+        }
+        check(hipMemcpyAsync(ycoef, yv.data(), sizeof(double) * j, hipMemcpyHostToDevice, s), "update");
+        check(launch_add_comb(Q, N, N, j, ycoef, x, s), "update");
+        restarts++;
+      }
+    }
+    check(hipStreamSynchronize(s), "solve");
+    if (info) {
+      info->iterations = total;
+      info->restarts = restarts;
+      info->relres = rel;
+      info->time_ms = ms_since(t0);
+    }
+    if (status != HMAT_OK) return fail(status, "GMRES reached maxit before tol");
+    return HMAT_OK;
+  } catch (const HipError& e) {
+    return fail(e.st, e.msg);
+  }
+}
+
+hmat_status hmat_info(hmat_t h, hmat_stats* st) {
+  if (!h || !st) return fail(HMAT_EINVAL, "handle or stats is NULL");
+  fill_stats(h);
+  *st = h->st;
+  return HMAT_OK;
+}
+
+hmat_status hmat_free(hmat_t h) {
+  if (!h) return HMAT_OK;
+  (void)hipDeviceSynchronize();
+  delete h;
+  return HMAT_OK;
+}
+
+hmat_status hmat_plan(const hmat_mesh* mesh, double eta, int32_t leaf, int32_t* order,
+                      int32_t* n_blocks, int32_t* blocks) {
+  std::string err;
+  hmat_status st = validate_params(1.0, 0.25, eta, leaf, 0.5, err);
+  if (st != HMAT_OK) return fail(st, err);
+  st = validate_mesh(mesh, err);
+  if (st != HMAT_OK) return fail(st, err);
+  if (!n_blocks) return fail(HMAT_EINVAL, "n_blocks is NULL");
+  try {
+    Plan P;
+    make_plan(mesh, eta, leaf, P);
+    if (order) std::memcpy(order, P.order.data(), sizeof(int32_t) * P.nt);
+    const int32_t capacity = *n_blocks;
+    *n_blocks = (int32_t)P.blk.size();
+    if (blocks) {
+      if (capacity < (int32_t)P.blk.size()) return fail(HMAT_EINVAL, "blocks capacity too small");
+      for (size_t b = 0; b < P.blk.size(); b++) {
+        const BlockRec& B = P.blk[b];
+        blocks[5 * b + 0] = P.cl[B.t].off;
+        blocks[5 * b + 1] = P.cl[B.t].len;
+        blocks[5 * b + 2] = P.cl[B.s].off;
+        blocks[5 * b + 3] = P.cl[B.s].len;
+        blocks[5 * b + 4] = B.far;
+      }
+    }
+  } catch (const std::bad_alloc&) {
+    return fail(HMAT_ENOMEM, "host allocation failed");
+  }
+  return HMAT_OK;
+}
+
+hmat_status hmat_block(hmat_t h, int32_t b, int32_t* info, double* A, double* B, int32_t* prow,
+                       int32_t* pcol) {
+  if (!h) return fail(HMAT_EINVAL, "handle is NULL");
+  if (b < 0 || b >= (int32_t)h->plan.blk.size()) return fail(HMAT_EINVAL, "block index out of range");
+  const BlockRec& R = h->plan.blk[b];
+  const int64_t m = block_m(h, b), n = block_n(h, b);
+  const int32_t idx = h->kind_index[b];
+  const int32_t k = R.far ? h->rank[idx] : 0;
+  if (info) {
+    info[0] = h->plan.cl[R.t].off;
+    info[1] = h->plan.cl[R.t].len;
+    info[2] = h->plan.cl[R.s].off;
+    info[3] = h->plan.cl[R.s].len;
+    info[4] = R.far;
+    info[5] = k;
+    info[6] = R.far ? h->stop[idx] : 0;
+    info[7] = 0;
+  }
+  try {
+    if (R.far) {
+      const double* base = h->far_arena.as<double>() + h->far_off[idx];
+      if (A && k) check(hipMemcpy(A, base, sizeof(double) * m * k, hipMemcpyDeviceToHost), "block copy");
+      if (B && k) check(hipMemcpy(B, base + m * k, sizeof(double) * n * k, hipMemcpyDeviceToHost), "block copy");
+      if (h->piv_ptr[idx] && k) {
+        if (prow) check(hipMemcpy(prow, h->piv_ptr[idx], sizeof(int32_t) * k, hipMemcpyDeviceToHost), "pivots");
+        if (pcol)
+          check(hipMemcpy(pcol, h->piv_ptr[idx] + h->piv_cap[idx], sizeof(int32_t) * k, hipMemcpyDeviceToHost), "pivots");
+      }
+    } else if (A) {
+      check(hipMemcpy(A, h->near_arena.as<double>() + h->near_off[idx], sizeof(double) * m * n,
+                      hipMemcpyDeviceToHost),
+            "block copy");
+    }
+  } catch (const HipError& e) {
+    return fail(e.st, e.msg);
+  }
+  return HMAT_OK;
+}
+
+hmat_status hmat_entries(hmat_t h, int64_t n, const int64_t* rows, const int64_t* cols,
+                         double* out, void* hip_stream) {
+  if (!h) return fail(HMAT_EINVAL, "handle is NULL");
+  if (n < 0 || (n > 0 && (!rows || !cols || !out))) return fail(HMAT_EINVAL, "bad arrays");
+  std::vector<int64_t> r(n), c(n);
+  for (int64_t k = 0; k < n; k++) {
+    if (rows[k] < 0 || rows[k] >= h->N || cols[k] < 0 || cols[k] >= h->N)
+      return fail(HMAT_EINVAL, "entry index out of range");
+    r[k] = 3 * (int64_t)h->inv_order[rows[k] / 3] + rows[k] % 3;
+    c[k] = 3 * (int64_t)h->inv_order[cols[k] / 3] + cols[k] % 3;
+  }
+  if (n == 0) return HMAT_OK;
+  hipStream_t s = (hipStream_t)hip_stream;
+  try {
+    DevBuf dr, dc, dout;
+    upload(dr, r, s, "entries");
+    upload(dc, c, s, "entries");
+    dout.alloc(sizeof(double) * n, "entries");
+    check(launch_entries(h->G, n, dr.as<int64_t>(), dc.as<int64_t>(), dout.as<double>(), s), "entries");
+    check(hipMemcpyAsync(out, dout.p, sizeof(double) * n, hipMemcpyDeviceToHost, s), "entries");
+    check(hipStreamSynchronize(s), "entries");
+  } catch (const HipError& e) {
+    return fail(e.st, e.msg);
+  }
+  return HMAT_OK;
+}
+
+hmat_status hmat_set_factors(hmat_t h, const int32_t* ranks, const double* U, const double* V,
+                             void* hip_stream) {
+  if (!h || !ranks) return fail(HMAT_EINVAL, "handle or ranks is NULL");
+  hipStream_t s = (hipStream_t)hip_stream;
+  const size_t nf = h->far_blocks.size();
+  int64_t fo = 0, uo = 0, vo = 0;
+  std::vector<int64_t> off(nf);
+  for (size_t f = 0; f < nf; f++) {
+    const int32_t b = h->far_blocks[f], k = ranks[b];
+    if (k < 0 || k > std::min(block_m(h, b), block_n(h, b))) return fail(HMAT_EINVAL, "rank out of range");
+    off[f] = fo;
+    fo += (int64_t)k * (block_m(h, b) + block_n(h, b));
+  }
+  if (fo > 0 && (!U || !V)) return fail(HMAT_EINVAL, "U or V is NULL");
+  try {
+    std::vector<double> host(std::max<int64_t>(fo, 1));
+    for (size_t f = 0; f < nf; f++) {
+      const int32_t b = h->far_blocks[f], k = ranks[b];
+      const int64_t m = block_m(h, b), n = block_n(h, b);
+      std::memcpy(host.data() + off[f], U + uo, sizeof(double) * m * k);
+      std::memcpy(host.data() + off[f] + m * k, V + vo, sizeof(double) * n * k);
+      uo += m * k;
+      vo += n * k;
+    }
+    check(hipStreamSynchronize(s), "set factors");
+    h->far_arena.alloc(sizeof(double) * host.size(), "low-rank arena");
+    check(hipMemcpy(h->far_arena.p, host.data(), sizeof(double) * host.size(), hipMemcpyHostToDevice), "set factors");
+    for (size_t f = 0; f < nf; f++) {
+      h->rank[f] = ranks[h->far_blocks[f]];
+      h->stop[f] = 0;
+      h->ratio[f] = 0.0;
+      h->piv_ptr[f] = nullptr;
+    }
+    h->far_off = off;
+    build_product_plan(h, s);
+    check(hipStreamSynchronize(s), "set factors");
+  } catch (const HipError& e) {
+    return fail(e.st, e.msg);
+  } catch (const std::bad_alloc&) {
+    return fail(HMAT_ENOMEM, "host allocation failed");
+  }
+  return HMAT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,113 @@
+// Internal declarations shared by the host planner, the kernels and the C ABI.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "hmat.h"
+
+namespace hm {
+
+// Task and descriptor records handed to the kernels (plain data, identical
+// layout on host and device).
+
+// Geometry in cluster order p (see Geometry below); c1 = cK (3 - 4 nu), c2 = cK,
+// cK = (1+nu)/(8 pi E (1-nu)) -- Kelvin tensor S = c1 delta/|r| + c2 r r^T/|r|^3 (Sec. 4.1).
+struct DevGeo {
+  const double* cen;  // [3][nt]
+  const double* q;    // [4][7][nt]: x, y, z, weight*area
+  const double* vtx;  // [9][nt]: p0x p0y p0z p1x ... p2z
+  const double* gl;   // [2][16] Gauss-Legendre nodes and weights on [0,1]
+  int32_t nt;
+  int32_t pad;
+  double c1, c2;
+};
+
+// Dense (non-admissible) block: column-major m x n at d_off in the near arena.
+struct NearTask {
+  int32_t t_off, t_len, s_off, s_len;
+  int64_t d_off;
+};
+
+// Self entry of cluster position p: lives in the diagonal dense block at d_off
+// (leading dimension m), local triangle index ploc.
+struct SelfTask {
+  int64_t d_off;
+  int32_t m, ploc;
+};
+
+// ACA task: panels U (m x kcap) then V (n x kcap), column-major, at `panel`.
+struct AcaTask {
+  int32_t t_off, t_len, s_off, s_len;
+  double* panel;
+  int32_t* piv;   // [2][kcap]: pivot rows, pivot columns
+  int32_t kcap;
+  int32_t blk;    // index into the far-block result arrays
+};
+
+// Compaction: copy the first k columns of U and V into the final arena.
+struct CopyTask {
+  const double* srcU;
+  const double* srcV;
+  double* dst;    // U (m x k) followed by V (n x k)
+  int32_t m, n, k, pad;
+};
+
+// Product, phase A: z[zoff + l] = V[:, l] . xp[xoff : xoff+n] for l in [l0, l1).
+struct MvA {
+  int64_t v_off;  // V of the block in the far arena
+  int32_t n, l0, l1, xoff;
+  int32_t zoff, pad;
+};
+
+// Product, phase B: rows [row_lo, row_hi) of a 64-row tile, columns
+// [c0, c1) of a column-major matrix with leading dimension lda; matrix element
+// of tile row L and column c is base[a_off + L + c*lda]; the vector entry for
+// column c is src[soff + c] with src = z (far) or xp (near).
+struct MvSeg {
+  int64_t a_off;
+  int32_t lda, c0, c1, soff;
+  int16_t row_lo, row_hi;
+  int32_t far;  // 1: matrix in the far arena, vector z; 0: near arena, vector xp
+};
+
+struct MvChunk {
+  int32_t tile, seg_lo, seg_hi, pad;
+};
+
+// ----------------------------------------------------------------------------
+// Host planner (planner.cpp).
+
+struct Cluster {
+  int32_t off, len, son0, son1, level;
+  double lo[3], hi[3];  // box of the vertices of the cluster's triangles
+};
+
+struct BlockRec {
+  int32_t t, s;  // cluster ids
+  int32_t far;
+};
+
+struct Plan {
+  int32_t nt = 0;
+  std::vector<int32_t> order;  // cluster position -> caller's triangle
+  std::vector<Cluster> cl;
+  std::vector<BlockRec> blk;   // canonical order (row_off, col_off)
+  int32_t csp = 0, depth = 0;
+};
+
+struct HostGeometry {  // cluster order, SoA as in DevGeo
+  std::vector<double> cen, q, vtx, gl;
+};
+
+// Returns HMAT_OK or HMAT_EINVAL with a message.
+hmat_status validate_mesh(const hmat_mesh* mesh, std::string& err);
+hmat_status validate_params(double E, double nu, double eta, int32_t leaf, double eps,
+                            std::string& err);
+void make_plan(const hmat_mesh* mesh, double eta, int32_t leaf, Plan& plan);
+void make_geometry(const hmat_mesh* mesh, const Plan& plan, HostGeometry& g);
+void gauss_legendre_unit(int n, double* x, double* w);  // rule on [0,1]
+void radon7(double bary[7][3], double w[7]);
+
+}  // namespace hm

@@ -1,0 +1,748 @@
+// CDNA4 (gfx950) kernels of the H-matrix path.
+//
+//   K1  k_near / k_self   dense (non-admissible) blocks entry by entry (Sec. 2.2)
+//   K2  k_aca             ACA with partial pivoting on every admissible block
+//                         (Sec. 2.2, Algorithm 1), one workgroup per block
+//   --  k_compact         final low-rank arena (first k columns of the panels)
+//   K3  k_gather, k_mvA, k_mvB, k_reduce
+//                         y = sum U_b (V_b^T x_s) + sum D_b x_s (Sec. 2)
+//   --  GMRES helpers     dots, column updates, norms
+//
+// Entries: A[3i+a, 3j+b] = int_{tau_j} S_ab(c_i - y) ds_y with Kelvin's tensor
+// S = c1 delta/|r| + c2 r r^T/|r|^3 (Sec. 4.1), collocation at the centroid c_i
+// (Sec. 2 and Sec. 4.2). Off-diagonal: seven-point rule (geometry supplies the
+// nodes and weights*area in cluster order). Self: tau_i split at c_i into three
+// triangles in Duffy coordinates y = c + s[(p_m - c) + t(p_{m+1} - p_m)]; the
+// product of kernel and Jacobian does not depend on s (|r| = s|d(t)|), so the
+// 16-point rule in s integrates it exactly and only the 16 points in t remain.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+
+#include "hmat_internal.hpp"
+
+namespace hm {
+
+constexpr int WAVE = 64;
+
+// ---------------------------------------------------------------------------
+// Entry generation.
+
+// For collocation point x and triangle q (cluster position): e_b = sum_k w_k S_ab(x - y_k)
+// for the fixed row component a, b = 0..2.
+__device__ __forceinline__ void row3(const DevGeo& g, double x0, double x1, double x2, int a,
+                                     int q, double& e0, double& e1, double& e2) {
+  const int nt = g.nt;
+  e0 = e1 = e2 = 0.0;
+  double diag = 0.0;
+#pragma unroll
+  for (int k = 0; k < 7; k++) {
+    const double r0 = x0 - g.q[(0 * 7 + k) * (size_t)nt + q];
+    const double r1 = x1 - g.q[(1 * 7 + k) * (size_t)nt + q];
+    const double r2 = x2 - g.q[(2 * 7 + k) * (size_t)nt + q];
+    const double w = g.q[(3 * 7 + k) * (size_t)nt + q];
+    const double inv = 1.0 / sqrt(r0 * r0 + r1 * r1 + r2 * r2);
+    const double ra = (a == 0) ? r0 : ((a == 1) ? r1 : r2);
+    const double t = w * inv * inv * inv * ra;
+    e0 += t * r0;
+    e1 += t * r1;
+    e2 += t * r2;
+    diag += w * inv;
+  }
+  e0 *= g.c2;
+  e1 *= g.c2;
+  e2 *= g.c2;
+  const double dd = g.c1 * diag;
+  if (a == 0) e0 += dd; else if (a == 1) e1 += dd; else e2 += dd;
+}
+
+// Full symmetric 3x3 for collocation point x and triangle q (off-diagonal pair):
+// s = {S00, S11, S22, S01, S02, S12}.
+__device__ __forceinline__ void full3(const DevGeo& g, double x0, double x1, double x2, int q,
+                                      double s[6]) {
+  const int nt = g.nt;
+  double d = 0.0, m00 = 0.0, m11 = 0.0, m22 = 0.0, m01 = 0.0, m02 = 0.0, m12 = 0.0;
+#pragma unroll
+  for (int k = 0; k < 7; k++) {
+    const double r0 = x0 - g.q[(0 * 7 + k) * (size_t)nt + q];
+    const double r1 = x1 - g.q[(1 * 7 + k) * (size_t)nt + q];
+    const double r2 = x2 - g.q[(2 * 7 + k) * (size_t)nt + q];
+    const double w = g.q[(3 * 7 + k) * (size_t)nt + q];
+    const double inv = 1.0 / sqrt(r0 * r0 + r1 * r1 + r2 * r2);
+    const double w3 = w * inv * inv * inv;
+    d += w * inv;
+    m00 += w3 * r0 * r0;
+    m11 += w3 * r1 * r1;
+    m22 += w3 * r2 * r2;
+    m01 += w3 * r0 * r1;
+    m02 += w3 * r0 * r2;
+    m12 += w3 * r1 * r2;
+  }
+  s[0] = g.c1 * d + g.c2 * m00;
+  s[1] = g.c1 * d + g.c2 * m11;
+  s[2] = g.c1 * d + g.c2 * m22;
+  s[3] = g.c2 * m01;
+  s[4] = g.c2 * m02;
+  s[5] = g.c2 * m12;
+}
+
+// Self term, one angular point: sub-triangle m (0..2), Gauss node kt (0..15).
+// Adds weight * (c1 delta/|d| + c2 d d^T/|d|^3) with weight = w_t |(p_m - c) x (p_{m+1} - p_m)|.
+__device__ __forceinline__ void self_point(const DevGeo& g, int p, int m, int kt, double s[6]) {
+  const int nt = g.nt;
+  const double c0 = g.cen[p], c1v = g.cen[nt + p], c2v = g.cen[2 * nt + p];
+  const int m1 = (m + 1) % 3;
+  const double a0 = g.vtx[(m * 3 + 0) * (size_t)nt + p] - c0;
+  const double a1 = g.vtx[(m * 3 + 1) * (size_t)nt + p] - c1v;
+  const double a2 = g.vtx[(m * 3 + 2) * (size_t)nt + p] - c2v;
+  const double b0 = g.vtx[(m1 * 3 + 0) * (size_t)nt + p] - g.vtx[(m * 3 + 0) * (size_t)nt + p];
+  const double b1 = g.vtx[(m1 * 3 + 1) * (size_t)nt + p] - g.vtx[(m * 3 + 1) * (size_t)nt + p];
+  const double b2 = g.vtx[(m1 * 3 + 2) * (size_t)nt + p] - g.vtx[(m * 3 + 2) * (size_t)nt + p];
+  const double n0 = a1 * b2 - a2 * b1, n1 = a2 * b0 - a0 * b2, n2 = a0 * b1 - a1 * b0;
+  const double jac = sqrt(n0 * n0 + n1 * n1 + n2 * n2);
+  const double t = g.gl[kt], wt = g.gl[16 + kt] * jac;
+  const double d0 = a0 + t * b0, d1 = a1 + t * b1, d2 = a2 + t * b2;
+  const double inv = 1.0 / sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+  const double w3 = wt * inv * inv * inv * g.c2;
+  const double wd = wt * inv * g.c1;
+  s[0] += wd + w3 * d0 * d0;
+  s[1] += wd + w3 * d1 * d1;
+  s[2] += wd + w3 * d2 * d2;
+  s[3] += w3 * d0 * d1;
+  s[4] += w3 * d0 * d2;
+  s[5] += w3 * d1 * d2;
+}
+
+__device__ __forceinline__ double sym_get(const double s[6], int a, int b) {
+  if (a == b) return s[a];
+  const int lo = a < b ? a : b, hi = a < b ? b : a;
+  return (lo == 0) ? (hi == 1 ? s[3] : s[4]) : s[5];
+}
+
+// K1: dense blocks, one workgroup per block, one thread per triangle pair.
+// D is column-major m x n with m = 3 t_len; consecutive threads take consecutive
+// row triangles so the three rows of a pair land in contiguous memory.
+__global__ __launch_bounds__(256) void k_near(DevGeo g, const NearTask* __restrict__ tasks,
+                                              double* __restrict__ D) {
+  const NearTask T = tasks[blockIdx.x];
+  const int m = 3 * T.t_len;
+  double* __restrict__ Db = D + T.d_off;
+  const int npair = T.t_len * T.s_len;
+  for (int idx = threadIdx.x; idx < npair; idx += blockDim.x) {
+    const int p = idx % T.t_len, q = idx / T.t_len;
+    const int ip = T.t_off + p, jq = T.s_off + q;
+    if (ip == jq) continue;  // self entries: k_self
+    double s[6];
+    full3(g, g.cen[ip], g.cen[g.nt + ip], g.cen[2 * g.nt + ip], jq, s);
+#pragma unroll
+    for (int b = 0; b < 3; b++)
+#pragma unroll
+      for (int a = 0; a < 3; a++) Db[(size_t)(3 * q + b) * m + 3 * p + a] = sym_get(s, a, b);
+  }
+}
+
+// K1 self entries: one wave per triangle, 48 angular points over the lanes.
+__global__ __launch_bounds__(256) void k_self(DevGeo g, const SelfTask* __restrict__ tasks,
+                                              double* __restrict__ D) {
+  const int p = blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+  const int lane = threadIdx.x % WAVE;
+  if (p >= g.nt) return;
+  double s[6] = {0, 0, 0, 0, 0, 0};
+  if (lane < 48) self_point(g, p, lane / 16, lane % 16, s);
+#pragma unroll
+  for (int c = 0; c < 6; c++)
+    for (int o = WAVE / 2; o > 0; o >>= 1) s[c] += __shfl_xor(s[c], o, WAVE);
+  if (lane == 0) {
+    const SelfTask T = tasks[p];
+    double* Db = D + T.d_off;
+    for (int b = 0; b < 3; b++)
+      for (int a = 0; a < 3; a++) Db[(size_t)(3 * T.ploc + b) * T.m + 3 * T.ploc + a] = sym_get(s, a, b);
+  }
+}
+
+// Entries at arbitrary (row, col) DOF pairs in cluster numbering (p*3 + a).
+__global__ void k_entries(DevGeo g, int64_t n, const int64_t* __restrict__ rows,
+                          const int64_t* __restrict__ cols, double* __restrict__ out) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int p = (int)(rows[k] / 3), a = (int)(rows[k] % 3);
+  const int q = (int)(cols[k] / 3), b = (int)(cols[k] % 3);
+  double s[6] = {0, 0, 0, 0, 0, 0};
+  if (p == q) {
+    for (int m = 0; m < 3; m++)
+      for (int kt = 0; kt < 16; kt++) self_point(g, p, m, kt, s);
+  } else {
+    full3(g, g.cen[p], g.cen[g.nt + p], g.cen[2 * g.nt + p], q, s);
+  }
+  out[k] = sym_get(s, a, b);
+}
+
+// ---------------------------------------------------------------------------
+// Block-wide reductions for 256-thread workgroups. Two alternating LDS slot
+// sets: a slot set is rewritten only after every thread has passed the
+// barrier of the following reduction, so one barrier per reduction suffices.
+
+constexpr int ACA_T = 256;
+constexpr int NW = ACA_T / WAVE;
+
+struct Red {
+  double d[2][2][NW];
+  int i[2][NW];
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+  for (int o = WAVE / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, WAVE));
+  return v;
+}
+__device__ __forceinline__ int wave_min(int v) {
+  for (int o = WAVE / 2; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, WAVE));
+  return v;
+}
+
+__device__ __forceinline__ double blk_max(double v, Red& R, int& ph) {
+  v = wave_max(v);
+  if ((threadIdx.x & (WAVE - 1)) == 0) R.d[ph][0][threadIdx.x / WAVE] = v;
+  __syncthreads();
+  double r = R.d[ph][0][0];
+#pragma unroll
+  for (int w = 1; w < NW; w++) r = fmax(r, R.d[ph][0][w]);
+  ph ^= 1;
+  return r;
+}
+__device__ __forceinline__ int blk_min(int v, Red& R, int& ph) {
+  v = wave_min(v);
+  if ((threadIdx.x & (WAVE - 1)) == 0) R.i[ph][threadIdx.x / WAVE] = v;
+  __syncthreads();
+  int r = R.i[ph][0];
+#pragma unroll
+  for (int w = 1; w < NW; w++) r = min(r, R.i[ph][w]);
+  ph ^= 1;
+  return r;
+}
+__device__ __forceinline__ void blk_sum2(double& a, double& b, Red& R, int& ph) {
+  a = wave_sum(a);
+  b = wave_sum(b);
+  if ((threadIdx.x & (WAVE - 1)) == 0) {
+    R.d[ph][0][threadIdx.x / WAVE] = a;
+    R.d[ph][1][threadIdx.x / WAVE] = b;
+  }
+  __syncthreads();
+  a = R.d[ph][0][0];
+  b = R.d[ph][1][0];
+#pragma unroll
+  for (int w = 1; w < NW; w++) {
+    a += R.d[ph][0][w];
+    b += R.d[ph][1][w];
+  }
+  ph ^= 1;
+}
+
+__device__ __forceinline__ bool in_z(const uint32_t* Z, int r) { return (Z[r >> 5] >> (r & 31)) & 1u; }
+
+// Fuzzy argmax over rows not in Z: lowest r with |u_r| >= (1 - 1e-10) max.
+__device__ int argmax_free(const double* __restrict__ u, int m, const uint32_t* Z, Red& R, int& ph) {
+  double mx = -1.0;
+  for (int r = threadIdx.x; r < m; r += ACA_T)
+    if (!in_z(Z, r)) mx = fmax(mx, fabs(u[r]));
+  mx = blk_max(mx, R, ph);
+  const double thr = (1.0 - 1e-10) * mx;
+  int cand = INT_MAX;
+  for (int r = threadIdx.x; r < m; r += ACA_T)
+    if (!in_z(Z, r) && fabs(u[r]) >= thr) {
+      cand = r;
+      break;
+    }
+  return blk_min(cand, R, ph);
+}
+
+// K2: ACA (Algorithm 1) on the DOF block of task blockIdx.x.
+//   rows i_{k+1}: fuzzy argmax over rows not in Z of |u_k| (i_1 = 0);
+//   columns j_k: fuzzy argmax of |v~_k|; v_k = v~_k / v~_k(j_k);
+//   v~ vanishes if max|v~| = 0 (k = 0) or <= 1e-14 ||S_k||_F;
+//   ||S_k||^2 = ||S_{k-1}||^2 + 2 sum_{l<k} (u_l.u_k)(v_l.v_k) + |u_k|^2 |v_k|^2 in FP64;
+//   stop: |u_k||v_k| <= eps ||S_k|| (1), k = min(m,n) (2), Z full (3),
+//   panel capacity reached (4: the host re-runs the block with a larger capacity),
+//   no finite pivot (5: non-finite entries; reported as an error).
+// Panels live in global memory (column-major U m x kcap, V n x kcap); the
+// coefficient row U[i, 0:k] / V[j, 0:k] and the set Z are staged in LDS.
+__global__ __launch_bounds__(ACA_T) void k_aca(DevGeo g, const AcaTask* __restrict__ tasks,
+                                               double eps, int32_t* __restrict__ rank_out,
+                                               int32_t* __restrict__ stop_out,
+                                               double* __restrict__ ratio_out) {
+  extern __shared__ double sh[];
+  __shared__ Red R;
+  const AcaTask T = tasks[blockIdx.x];
+  const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
+  const int m = 3 * T.t_len, n = 3 * T.s_len, kmax = min(m, n), kcap = T.kcap;
+  double* __restrict__ U = T.panel;
+  double* __restrict__ V = T.panel + (size_t)m * kcap;
+  double* coef = sh;
+  uint32_t* Z = reinterpret_cast<uint32_t*>(sh + kcap);
+  const int zw = (m + 31) >> 5;
+  for (int w = tid; w < zw; w += ACA_T) Z[w] = 0u;
+  const int nt = g.nt;
+  int ph = 0, k = 0, nZ = 0, i = 0, stop = 0;
+  double S2 = 0.0, ratio = 0.0;
+  __syncthreads();
+  for (;;) {
+    for (int l = tid; l < k; l += ACA_T) coef[l] = U[i + (size_t)l * m];
+    if (tid == 0) Z[i >> 5] |= (1u << (i & 31));
+    nZ++;
+    __syncthreads();
+    // row i of the remainder into V[:, k]
+    double* __restrict__ vk = V + (size_t)k * n;
+    const int pi = T.t_off + i / 3, ai = i % 3;
+    const double x0 = g.cen[pi], x1 = g.cen[nt + pi], x2 = g.cen[2 * nt + pi];
+    double mx = 0.0;
+    for (int q = tid; q < T.s_len; q += ACA_T) {
+      double e0, e1, e2;
+      row3(g, x0, x1, x2, ai, T.s_off + q, e0, e1, e2);
+      const double* vc = V + 3 * q;
+      for (int l = 0; l < k; l++, vc += n) {
+        const double c = coef[l];
+        e0 -= c * vc[0];
+        e1 -= c * vc[1];
+        e2 -= c * vc[2];
+      }
+      vk[3 * q] = e0;
+      vk[3 * q + 1] = e1;
+      vk[3 * q + 2] = e2;
+      mx = fmax(mx, fmax(fabs(e0), fmax(fabs(e1), fabs(e2))));
+    }
+    mx = blk_max(mx, R, ph);
+    const bool vanished = (k == 0) ? (mx == 0.0) : (mx <= 1e-14 * sqrt(S2));
+    if (vanished) {
+      if (nZ == m) {
+        stop = 3;
+        break;
+      }
+      if (k == 0) {
+        int cand = INT_MAX;
+        for (int r = tid; r < m; r += ACA_T)
+          if (!in_z(Z, r)) {
+            cand = r;
+            break;
+          }
+        i = blk_min(cand, R, ph);
+      } else {
+        i = argmax_free(U + (size_t)(k - 1) * m, m, Z, R, ph);
+      }
+      if (i >= m) {
+        stop = 5;
+        break;
+      }
+      continue;
+    }
+    const double thr = (1.0 - 1e-10) * mx;
+    int cand = INT_MAX;
+    for (int c = tid; c < n; c += ACA_T)
+      if (fabs(vk[c]) >= thr) {
+        cand = c;
+        break;
+      }
+    const int j = blk_min(cand, R, ph);
+    if (j >= n) {  // no finite pivot (non-finite entries)
+      stop = 5;
+      break;
+    }
+    const double piv = vk[j];
+    __syncthreads();  // every thread holds piv before vk is normalised in place
+    double vv = 0.0;
+    for (int c = tid; c < n; c += ACA_T) {
+      const double v = vk[c] / piv;
+      vk[c] = v;
+      vv += v * v;
+    }
+    for (int l = tid; l < k; l += ACA_T) coef[l] = V[j + (size_t)l * n];
+    __syncthreads();
+    // column j of the remainder into U[:, k] (S is symmetric: A[3p+a, 3q+b] = S_ba)
+    double* __restrict__ uk = U + (size_t)k * m;
+    const int qj = T.s_off + j / 3, bj = j % 3;
+    double uu = 0.0;
+    for (int p = tid; p < T.t_len; p += ACA_T) {
+      const int ip = T.t_off + p;
+      double e0, e1, e2;
+      row3(g, g.cen[ip], g.cen[nt + ip], g.cen[2 * nt + ip], bj, qj, e0, e1, e2);
+      const double* uc = U + 3 * p;
+      for (int l = 0; l < k; l++, uc += m) {
+        const double c = coef[l];
+        e0 -= c * uc[0];
+        e1 -= c * uc[1];
+        e2 -= c * uc[2];
+      }
+      uk[3 * p] = e0;
+      uk[3 * p + 1] = e1;
+      uk[3 * p + 2] = e2;
+      uu += e0 * e0 + e1 * e1 + e2 * e2;
+    }
+    blk_sum2(uu, vv, R, ph);
+    // sum_{l<k} (u_l . u_k)(v_l . v_k): wave w takes l = w, w + NW, ...
+    double cr = 0.0;
+    for (int l = wv; l < k; l += NW) {
+      const double* ul = U + (size_t)l * m;
+      const double* vl = V + (size_t)l * n;
+      double a = 0.0, b = 0.0;
+      for (int r = lane; r < m; r += WAVE) a += ul[r] * uk[r];
+      for (int c = lane; c < n; c += WAVE) b += vl[c] * vk[c];
+      cr += wave_sum(a) * wave_sum(b);
+    }
+    double cross = (lane == 0) ? cr : 0.0, dummy = 0.0;
+    blk_sum2(cross, dummy, R, ph);
+    if (tid == 0) {
+      T.piv[k] = i;
+      T.piv[kcap + k] = j;
+    }
+    k++;
+    S2 = S2 + 2.0 * cross + uu * vv;
+    const double lhs = sqrt(uu) * sqrt(vv), rhs = eps * sqrt(S2);
+    ratio = rhs > 0.0 ? lhs / rhs : INFINITY;
+    if (lhs <= rhs) { stop = 1; break; }
+    if (k == kmax) { stop = 2; break; }
+    if (nZ == m) { stop = 3; break; }
+    if (k == kcap) { stop = 4; break; }
+    i = argmax_free(uk, m, Z, R, ph);
+    if (i >= m) {
+      stop = 5;
+      break;
+    }
+  }
+  if (tid == 0) {
+    rank_out[T.blk] = k;
+    stop_out[T.blk] = stop;
+    ratio_out[T.blk] = ratio;
+  }
+}
+
+// Final low-rank arena: U (m x k) then V (n x k) per block, contiguous.
+__global__ __launch_bounds__(256) void k_compact(const CopyTask* __restrict__ tasks) {
+  const CopyTask T = tasks[blockIdx.x];
+  const size_t mu = (size_t)T.m * T.k, nv = (size_t)T.n * T.k;
+  for (size_t e = threadIdx.x; e < mu; e += blockDim.x) T.dst[e] = T.srcU[e];
+  for (size_t e = threadIdx.x; e < nv; e += blockDim.x) T.dst[mu + e] = T.srcV[e];
+}
+
+// ---------------------------------------------------------------------------
+// K3: H-matrix-vector product.
+
+// xp[r][3p+a] = x[r*ldx + 3 order[p] + a]
+__global__ void k_gather(int nr, const double* __restrict__ x, int64_t ldx,
+                         const int32_t* __restrict__ order, int64_t N, double* __restrict__ xp) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= N * nr) return;
+  const int64_t r = e / N, d = e % N;
+  xp[e] = x[r * ldx + 3 * (int64_t)order[d / 3] + d % 3];
+}
+
+// Phase A: z = V_b^T x_s for a group of <= 8 columns; one wave per item, lanes
+// over rows; NR right-hand sides at once, columns in sub-batches of CB.
+template <int NR>
+__global__ __launch_bounds__(WAVE) void k_mvA(const MvA* __restrict__ items,
+                                              const double* __restrict__ far,
+                                              const double* __restrict__ xp, int64_t ldxp, int nr,
+                                              double* __restrict__ z, int64_t ldz) {
+  constexpr int CB = (NR >= 16) ? 2 : ((NR >= 8) ? 4 : 8);
+  const MvA I = items[blockIdx.x];
+  const int lane = threadIdx.x;
+  const double* __restrict__ V = far + I.v_off;
+  for (int l0 = I.l0; l0 < I.l1; l0 += CB) {
+    const int nc = min(CB, I.l1 - l0);
+    double acc[CB][NR];
+#pragma unroll
+    for (int c = 0; c < CB; c++)
+#pragma unroll
+      for (int r = 0; r < NR; r++) acc[c][r] = 0.0;
+    for (int i = lane; i < I.n; i += WAVE) {
+      double xv[NR];
+#pragma unroll
+      for (int r = 0; r < NR; r++) xv[r] = (r < nr) ? xp[r * ldxp + I.xoff + i] : 0.0;
+#pragma unroll
+      for (int c = 0; c < CB; c++) {
+        if (c < nc) {
+          const double v = V[i + (size_t)(l0 + c) * I.n];
+#pragma unroll
+          for (int r = 0; r < NR; r++) acc[c][r] += v * xv[r];
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < CB; c++)
+#pragma unroll
+      for (int r = 0; r < NR; r++) {
+        const double s = wave_sum(acc[c][r]);
+        if (lane == 0 && c < nc && r < nr) z[r * ldz + I.zoff + (l0 - I.l0) + c] = s;
+      }
+  }
+}
+
+// Phase B: one wave per chunk of segments of one 64-row tile; lane = tile row.
+// Writes the chunk's partial sums part[chunk][r][64].
+template <int NR>
+__global__ __launch_bounds__(WAVE) void k_mvB(const MvChunk* __restrict__ chunks,
+                                              const MvSeg* __restrict__ segs,
+                                              const double* __restrict__ far,
+                                              const double* __restrict__ near,
+                                              const double* __restrict__ z, int64_t ldz,
+                                              const double* __restrict__ xp, int64_t ldxp, int nr,
+                                              double* __restrict__ part) {
+  const MvChunk C = chunks[blockIdx.x];
+  const int L = threadIdx.x;
+  double acc[NR];
+#pragma unroll
+  for (int r = 0; r < NR; r++) acc[r] = 0.0;
+  for (int s = C.seg_lo; s < C.seg_hi; s++) {
+    const MvSeg S = segs[s];
+    const bool act = L >= S.row_lo && L < S.row_hi;
+    const double* __restrict__ A = (S.far ? far : near) + S.a_off + L;
+    const double* __restrict__ src = (S.far ? z : xp) + S.soff;
+    const int64_t ld = S.far ? ldz : ldxp;
+    int c = S.c0;
+    for (; c + 8 <= S.c1; c += 8) {
+      double a[8];
+#pragma unroll
+      for (int u = 0; u < 8; u++) a[u] = act ? A[(size_t)(c + u) * S.lda] : 0.0;
+#pragma unroll
+      for (int r = 0; r < NR; r++) {
+        if (r < nr) {
+          const double* sr = src + r * ld + c;
+#pragma unroll
+          for (int u = 0; u < 8; u++) acc[r] += a[u] * sr[u];
+        }
+      }
+    }
+    for (; c < S.c1; c++) {
+      const double a = act ? A[(size_t)c * S.lda] : 0.0;
+#pragma unroll
+      for (int r = 0; r < NR; r++)
+        if (r < nr) acc[r] += a * src[r * ld + c];
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < NR; r++)
+    if (r < nr) part[((size_t)blockIdx.x * NR + r) * WAVE + L] = acc[r];
+}
+
+// Sum the partials of each tile in chunk order and scatter to the caller's order.
+template <int NR>
+__global__ __launch_bounds__(WAVE) void k_reduce(const int32_t* __restrict__ tile_chunk,
+                                                 const double* __restrict__ part, int nr,
+                                                 const int32_t* __restrict__ order, int64_t N,
+                                                 double* __restrict__ y, int64_t ldy) {
+  const int tile = blockIdx.x, L = threadIdx.x;
+  const int64_t row = (int64_t)tile * WAVE + L;
+  if (row >= N) return;
+  const int c0 = tile_chunk[tile], c1 = tile_chunk[tile + 1];
+  const int64_t dst = 3 * (int64_t)order[row / 3] + row % 3;
+  for (int r = 0; r < nr; r++) {
+    double s = 0.0;
+    for (int c = c0; c < c1; c++) s += part[((size_t)c * NR + r) * WAVE + L];
+    y[r * ldy + dst] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// GMRES helpers (FP64).
+
+// out[c] = Q[:, c] . w for c < ncols; one workgroup per column.
+__global__ __launch_bounds__(256) void k_dots(const double* __restrict__ Q, int64_t ldq,
+                                              int64_t n, const double* __restrict__ w,
+                                              double* __restrict__ out) {
+  __shared__ double sh[NW];
+  const double* q = Q + (size_t)blockIdx.x * ldq;
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) s += q[i] * w[i];
+  s = wave_sum(s);
+  if ((threadIdx.x & (WAVE - 1)) == 0) sh[threadIdx.x / WAVE] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int k = 0; k < NW; k++) t += sh[k];
+    out[blockIdx.x] = t;
+  }
+}
+
+// w -= Q[:, 0:ncols] h (h on the device); acc[c] += h[c] if acc != nullptr (by thread 0 of block 0).
+__global__ __launch_bounds__(256) void k_sub_proj(const double* __restrict__ Q, int64_t ldq,
+                                                  int64_t n, int ncols,
+                                                  const double* __restrict__ h,
+                                                  double* __restrict__ w, double* __restrict__ acc) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (acc && blockIdx.x == 0)
+    for (int c = threadIdx.x; c < ncols; c += blockDim.x) acc[c] += h[c];
+  if (i >= n) return;
+  double s = 0.0;
+  for (int c = 0; c < ncols; c++) s += Q[(size_t)c * ldq + i] * h[c];
+  w[i] -= s;
+}
+
+// out[0] = ||w||_2 (single workgroup of 1024 threads).
+__global__ __launch_bounds__(1024) void k_norm(const double* __restrict__ w, int64_t n,
+                                               double* __restrict__ out) {
+  __shared__ double sh[1024 / WAVE];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) s += w[i] * w[i];
+  s = wave_sum(s);
+  if ((threadIdx.x & (WAVE - 1)) == 0) sh[threadIdx.x / WAVE] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int k = 0; k < (int)(blockDim.x / WAVE); k++) t += sh[k];
+    out[0] = sqrt(t);
+  }
+}
+
+// out = w / *den (den on the device; out untouched if *den == 0).
+__global__ void k_scale(const double* __restrict__ w, int64_t n, const double* __restrict__ den,
+                        double* __restrict__ out) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const double d = *den;
+  if (i < n && d != 0.0) out[i] = w[i] / d;
+}
+
+// x += Q[:, 0:ncols] y (y on the device)
+__global__ __launch_bounds__(256) void k_add_comb(const double* __restrict__ Q, int64_t ldq,
+                                                  int64_t n, int ncols,
+                                                  const double* __restrict__ y,
+                                                  double* __restrict__ x) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int c = 0; c < ncols; c++) s += Q[(size_t)c * ldq + i] * y[c];
+  x[i] += s;
+}
+
+// r = b - r
+__global__ void k_residual(const double* __restrict__ b, int64_t n, double* __restrict__ r) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) r[i] = b[i] - r[i];
+}
+
+__global__ void k_fill(double* __restrict__ x, int64_t n, double v) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) x[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// Launchers (host side).
+
+static inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+hipError_t launch_self(const DevGeo& g, const SelfTask* tasks, double* D, hipStream_t s) {
+  hipLaunchKernelGGL(k_self, dim3(blocks_for(g.nt, 4)), dim3(256), 0, s, g, tasks, D);
+  return hipGetLastError();
+}
+
+hipError_t launch_near_only(const DevGeo& g, const NearTask* tasks, int ntasks, double* D,
+                            hipStream_t s) {
+  if (ntasks > 0) hipLaunchKernelGGL(k_near, dim3(ntasks), dim3(256), 0, s, g, tasks, D);
+  return hipGetLastError();
+}
+
+hipError_t launch_entries(const DevGeo& g, int64_t n, const int64_t* rows, const int64_t* cols,
+                          double* out, hipStream_t s) {
+  if (n > 0)
+    hipLaunchKernelGGL(k_entries, dim3(blocks_for(n, 128)), dim3(128), 0, s, g, n, rows, cols, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_aca(const DevGeo& g, const AcaTask* tasks, int ntasks, size_t shmem, double eps,
+                      int32_t* rank, int32_t* stop, double* ratio, hipStream_t s) {
+  if (shmem > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_aca),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    if (e != hipSuccess) return e;
+  }
+  if (ntasks > 0)
+    hipLaunchKernelGGL(k_aca, dim3(ntasks), dim3(ACA_T), shmem, s, g, tasks, eps, rank, stop, ratio);
+  return hipGetLastError();
+}
+
+hipError_t launch_compact(const CopyTask* tasks, int ntasks, hipStream_t s) {
+  if (ntasks > 0) hipLaunchKernelGGL(k_compact, dim3(ntasks), dim3(256), 0, s, tasks);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather(int nr, const double* x, int64_t ldx, const int32_t* order, int64_t N,
+                         double* xp, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather, dim3(blocks_for(N * nr, 256)), dim3(256), 0, s, nr, x, ldx, order,
+                     N, xp);
+  return hipGetLastError();
+}
+
+template <int NR>
+static void mv_group(const MvA* itemsA, int nA, const MvChunk* chunks, int nC, const MvSeg* segs,
+                     const int32_t* tile_chunk, int ntiles, const double* far, const double* near,
+                     const double* xp, int64_t ldxp, int nr, double* z, int64_t ldz, double* part,
+                     const int32_t* order, int64_t N, double* y, int64_t ldy, hipStream_t s) {
+  if (nA > 0)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mvA<NR>), dim3(nA), dim3(WAVE), 0, s, itemsA, far, xp,
+                       ldxp, nr, z, ldz);
+  if (nC > 0)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mvB<NR>), dim3(nC), dim3(WAVE), 0, s, chunks, segs, far,
+                       near, z, ldz, xp, ldxp, nr, part);
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_reduce<NR>), dim3(ntiles), dim3(WAVE), 0, s, tile_chunk,
+                     part, nr, order, N, y, ldy);
+}
+
+// One pass over the matrix for nr <= 16 right-hand sides (xp already gathered).
+hipError_t launch_matvec_group(int nr, const MvA* itemsA, int nA, const MvChunk* chunks, int nC,
+                               const MvSeg* segs, const int32_t* tile_chunk, int ntiles,
+                               const double* far, const double* near, const double* xp,
+                               int64_t ldxp, double* z, int64_t ldz, double* part,
+                               const int32_t* order, int64_t N, double* y, int64_t ldy,
+                               hipStream_t s) {
+  if (nr <= 1)
+    mv_group<1>(itemsA, nA, chunks, nC, segs, tile_chunk, ntiles, far, near, xp, ldxp, nr, z, ldz, part, order, N, y, ldy, s);
+  else if (nr <= 2)
+    mv_group<2>(itemsA, nA, chunks, nC, segs, tile_chunk, ntiles, far, near, xp, ldxp, nr, z, ldz, part, order, N, y, ldy, s);
+  else if (nr <= 4)
+    mv_group<4>(itemsA, nA, chunks, nC, segs, tile_chunk, ntiles, far, near, xp, ldxp, nr, z, ldz, part, order, N, y, ldy, s);
+  else if (nr <= 8)
+    mv_group<8>(itemsA, nA, chunks, nC, segs, tile_chunk, ntiles, far, near, xp, ldxp, nr, z, ldz, part, order, N, y, ldy, s);
+  else
+    mv_group<16>(itemsA, nA, chunks, nC, segs, tile_chunk, ntiles, far, near, xp, ldxp, nr, z, ldz, part, order, N, y, ldy, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_dots(const double* Q, int64_t ldq, int64_t n, int ncols, const double* w,
+                       double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_dots, dim3(ncols), dim3(256), 0, s, Q, ldq, n, w, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_sub_proj(const double* Q, int64_t ldq, int64_t n, int ncols, const double* h,
+                           double* w, double* acc, hipStream_t s) {
+  hipLaunchKernelGGL(k_sub_proj, dim3(blocks_for(n, 256)), dim3(256), 0, s, Q, ldq, n, ncols, h, w, acc);
+  return hipGetLastError();
+}
+
+hipError_t launch_norm(const double* w, int64_t n, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_norm, dim3(1), dim3(1024), 0, s, w, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale(const double* w, int64_t n, const double* den, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale, dim3(blocks_for(n, 256)), dim3(256), 0, s, w, n, den, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_add_comb(const double* Q, int64_t ldq, int64_t n, int ncols, const double* y,
+                           double* x, hipStream_t s) {
+  hipLaunchKernelGGL(k_add_comb, dim3(blocks_for(n, 256)), dim3(256), 0, s, Q, ldq, n, ncols, y, x);
+  return hipGetLastError();
+}
+
+hipError_t launch_residual(const double* b, int64_t n, double* r, hipStream_t s) {
+  hipLaunchKernelGGL(k_residual, dim3(blocks_for(n, 256)), dim3(256), 0, s, b, n, r);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(double* x, int64_t n, double v, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_fill, dim3(blocks_for(n, 256)), dim3(256), 0, s, x, n, v);
+  return hipGetLastError();
+}
+
+}  // namespace hm

@@ -1,0 +1,110 @@
+"""C ABI checks that need no GPU: the library loads, exports every entry point
+that include/hmat.h declares, rejects invalid arguments before any device
+work, and its host planner reproduces the oracle's cluster tree order and
+block partition (Sec. 2.1) exactly."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+import paper_2205_04752_amd as H
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "hmat.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(hmat_[a-z_]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol():
+    names = _declared()
+    assert set(names) == set(H.EXPORTS), names
+    L = H.lib()
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def _mesh_struct(V, T):
+    m, keep = H._mesh(V, T)
+    return m, keep
+
+
+def test_build_validation_before_device_work():
+    V, T = W.icosphere(1)
+    L = H.lib()
+    m, keep = _mesh_struct(V, T)
+    h = C.c_void_p(123)
+    bad = [
+        (0.0, 0.3, 2.0, 32, 1e-4), (-1.0, 0.3, 2.0, 32, 1e-4), (1.0, 0.0, 2.0, 32, 1e-4),
+        (1.0, 0.5, 2.0, 32, 1e-4), (1.0, 0.3, 0.0, 32, 1e-4), (1.0, 0.3, 2.0, 0, 1e-4),
+        (1.0, 0.3, 2.0, 32, 0.0), (1.0, 0.3, 2.0, 32, 1.0), (float("nan"), 0.3, 2.0, 32, 1e-4),
+    ]
+    for args in bad:
+        st = L.hmat_build(C.byref(m), *args, None, C.byref(h))
+        assert st == H.HMAT_EINVAL, args
+        assert h.value is None
+        assert L.hmat_last_error().decode()
+    # mesh errors
+    T2 = T.copy()
+    T2[5, 1] = len(V)
+    m2, keep2 = _mesh_struct(V, T2)
+    assert L.hmat_build(C.byref(m2), 1.0, 0.3, 2.0, 32, 1e-4, None, C.byref(h)) == H.HMAT_EINVAL
+    assert "out of range" in L.hmat_last_error().decode()
+    T3 = T.copy()
+    T3[7] = [T3[7, 0], T3[7, 0], T3[7, 2]]
+    m3, keep3 = _mesh_struct(V, T3)
+    assert L.hmat_build(C.byref(m3), 1.0, 0.3, 2.0, 32, 1e-4, None, C.byref(h)) == H.HMAT_EINVAL
+    assert "zero area" in L.hmat_last_error().decode()
+    V4 = V.copy()
+    V4[3, 2] = np.inf
+    m4, keep4 = _mesh_struct(V4, T)
+    assert L.hmat_build(C.byref(m4), 1.0, 0.3, 2.0, 32, 1e-4, None, C.byref(h)) == H.HMAT_EINVAL
+    assert L.hmat_build(None, 1.0, 0.3, 2.0, 32, 1e-4, None, C.byref(h)) == H.HMAT_EINVAL
+    assert L.hmat_build(C.byref(m), 1.0, 0.3, 2.0, 32, 1e-4, None, None) == H.HMAT_EINVAL
+
+
+def test_other_entry_points_reject_null_handle():
+    L = H.lib()
+    assert L.hmat_matvec(None, 1, None, 3, None, 3, None) == H.HMAT_EINVAL
+    assert L.hmat_solve(None, None, None, 1e-8, 50, 10, None, None) == H.HMAT_EINVAL
+    assert L.hmat_info(None, None) == H.HMAT_EINVAL
+    assert L.hmat_block(None, 0, None, None, None, None, None) == H.HMAT_EINVAL
+    assert L.hmat_entries(None, 0, None, None, None, None) == H.HMAT_EINVAL
+    assert L.hmat_set_factors(None, None, None, None, None) == H.HMAT_EINVAL
+    assert L.hmat_free(None) == H.HMAT_OK
+
+
+MESHES = {
+    "ico3": lambda: W.icosphere(3),
+    "ico5": lambda: W.icosphere(5),
+    "torus": lambda: W.torus(1.0, 0.3, 60, 20),
+    "ellipsoid": lambda: W.ellipsoid(12, [2.0, 1.0, 0.5]),
+    "box": lambda: W.box_surface(10.0, 1.0, 1.0, 40, 4, 4),
+    "cube": lambda: W.cube_surface(9),
+}
+
+
+@pytest.mark.parametrize("name", list(MESHES))
+@pytest.mark.parametrize("eta,leaf", [(2.0, 32), (0.8, 15)])
+def test_plan_equals_oracle(name, eta, leaf):
+    V, T = MESHES[name]()
+    order, blocks = H.plan(V, T, eta, leaf)
+    h = O.HMatrix(O.Mesh(V, T), eta, leaf)
+    assert np.array_equal(order, h.order)
+    ob = h.blocks()
+    assert np.array_equal(blocks[:, :5], ob[:, :5])
+
+
+def test_plan_capacity_error():
+    V, T = W.icosphere(2)
+    m, keep = _mesh_struct(V, T)
+    nb = C.c_int32(1)
+    buf = np.zeros(5, dtype=np.int32)
+    st = H.lib().hmat_plan(C.byref(m), 2.0, 8, None, C.byref(nb), buf.ctypes.data)
+    assert st == H.HMAT_EINVAL and nb.value > 1
