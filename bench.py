@@ -1,0 +1,230 @@
+#!/usr/bin/env python3
+"""Benchmark of the H-matrix hot path on one MI355X.
+
+Workload (default): unit icosphere, level 5 (20480 flat triangles, 61440 DOF),
+E = 1, nu = 0.3, eta = 2, leaf 32, eps = 1e-6, 16 right-hand sides
+x ~ N(0,1) (seed 0) and GMRES(50) right-hand sides g = random smooth vector
+fields (sum of 8 random degree-2 vector polynomials) at the centroids.
+
+One step = the whole hot path on that input:
+  hmat_build (geometry, tree, partition, K1 dense blocks, K2 ACA, compaction),
+  16 single-vector products, one 16-vector product, and 4 GMRES(50) solves
+  to relative residual 1e-8 (seeds 4k+1 .. 4k+4 for step k).
+All inputs are resident on the GPU before the timed region starts.
+
+Reported value: H-matvec GB/s = algorithmic bytes of one product
+  8 (sum_far k(m+n) + sum_near m n) + 16 N
+divided by the mean duration of the 16 single-vector products (HIP events on
+the library's stream). Also reported: GMRES solves/s (1 / mean solve time),
+p50/p99 solve latency over all timed solves, build time, the roofline of the
+dominant product kernel, and the CPU oracle baseline.
+
+Prints ONE JSON line. Run: python bench.py [--steps K] [--warmup W].
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
+METRIC = "H-matvec GB/s (% HBM peak) + GMRES solves/sec, p50/p99 at rel-res 1e-8"
+
+
+def percentile(v, q):
+    s = sorted(v)
+    if not s:
+        return None
+    k = (len(s) - 1) * q
+    lo, hi = int(k), min(int(k) + 1, len(s) - 1)
+    return s[lo] + (s[hi] - s[lo]) * (k - lo)
+
+
+def cpu_baseline(V, T, wl, x0, seconds_hint: float):
+    """The oracle as it stands, on this host's cores: build (untimed) and a few
+    single-vector H-matrix products; GB/s of the same algorithmic bytes."""
+    import numpy as np
+    import oracle as O
+    t0 = time.perf_counter()
+    mesh = O.Mesh(V, T, wl["E"], wl["nu"])
+    h = O.HMatrix(mesh, wl["eta"], wl["leaf"], eps=wl["eps"])
+    t_build = time.perf_counter() - t0
+    N = 3 * len(T)
+    nbytes = 8 * h.stored() + 16 * N
+    times = []
+    budget = time.perf_counter() + seconds_hint
+    while len(times) < 3 or (time.perf_counter() < budget and len(times) < 20):
+        t = time.perf_counter()
+        h.matvec(x0)
+        times.append(time.perf_counter() - t)
+    med = float(np.median(times))
+    return {
+        "value": round(nbytes / med / 1e9, 3),
+        "unit": "GB/s",
+        "cores": O.num_threads(),
+        "kind": "oracle",
+        "sample": (f"oracle FP64 H-matrix of the same workload built once ({t_build:.1f} s, "
+                   f"untimed), then {len(times)} single-vector products timed; median "
+                   f"{med * 1e3:.1f} ms per product"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", choices=["icosphere-L5", "icosphere-L3"], default="icosphere-L5")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=5.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (the H-matrix path here is single-device); "
+              f"--gpus {args.gpus} is not supported", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import workloads as W
+    import paper_2205_04752_amd as H
+
+    wl = W.workload_c1() if args.workload == "icosphere-L5" else W.workload_c0()
+    V, T = wl["vertices"], wl["triangles"]
+    N = 3 * len(T)
+    nrhs = 16
+    solves_per_step = 4
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    X = torch.from_numpy(W.random_x(N, nrhs, seed=0)).to(dev)
+    Y = torch.empty_like(X)
+    Yb = torch.empty_like(X)
+    n_total = args.warmup + args.steps
+    G = torch.from_numpy(np.stack([W.smooth_rhs(V, T, seed=1 + i)
+                                   for i in range(n_total * solves_per_step)])).to(dev)
+    stream = torch.cuda.current_stream()
+
+    rec = {"mv_ms": [], "mv16_ms": [], "solve_ms": [], "iters": [], "relres": [], "build_ms": [],
+           "phase_ms": np.zeros(4), "phase_calls": 0, "aca_ms": [], "near_ms": []}
+    stats = {}
+
+    def step(k: int, record: bool):
+        h = H.HMatrix(V, T, wl["E"], wl["nu"], wl["eta"], wl["leaf"], wl["eps"])
+        st = h.info()
+        h.profile(True)
+        e0, e1, e2, e3 = (torch.cuda.Event(enable_timing=True) for _ in range(4))
+        e0.record(stream)
+        for r in range(nrhs):
+            h.matvec(X[r], Y[r])
+        e1.record(stream)
+        phases, calls = h.profile(False)  # per-phase times of the 16 single products
+        e2.record(stream)
+        h.matvec(X, Yb)
+        e3.record(stream)
+        solves = []
+        for j in range(solves_per_step):
+            _, info = h.solve(G[k * solves_per_step + j], tol=1e-8, restart=50, maxit=5000)
+            solves.append(info)
+        torch.cuda.synchronize()
+        if record:
+            rec["build_ms"].append(st["t_build_ms"])
+            rec["aca_ms"].append(st["t_aca_ms"])
+            rec["near_ms"].append(st["t_near_ms"])
+            rec["mv_ms"].append(e0.elapsed_time(e1) / nrhs)
+            rec["mv16_ms"].append(e2.elapsed_time(e3))
+            rec["phase_ms"] += phases
+            rec["phase_calls"] += calls
+            for info in solves:
+                rec["solve_ms"].append(info["time_ms"])
+                rec["iters"].append(info["iterations"])
+                rec["relres"].append(info["relres"])
+            stats.update(st)
+        h.close()
+
+    for k in range(args.warmup):
+        step(k, False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.warmup, n_total):
+        step(k, True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    far_u, far_v = stats["far_u_scalars"], stats["far_v_scalars"]
+    near = stats["near_scalars"]
+    bytes_mv = 8 * (far_u + far_v + near) + 16 * N
+    mv_ms = float(np.mean(rec["mv_ms"]))
+    gbs = bytes_mv / (mv_ms * 1e-3) / 1e9
+    bytes_mv16 = 8 * (far_u + far_v + near) + 16 * N * nrhs
+    mv16_ms = float(np.mean(rec["mv16_ms"]))
+    solve_ms = rec["solve_ms"]
+    out = {
+        "metric": METRIC,
+        "value": round(gbs, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall * 1e3 / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wl["name"], "n_triangles": len(T), "n_dof": N, "E": wl["E"],
+                   "nu": wl["nu"], "eta": wl["eta"], "leaf": wl["leaf"], "eps": wl["eps"],
+                   "nrhs": nrhs, "gmres": "GMRES(50), tol 1e-8, x0 = 0",
+                   "solves_per_step": solves_per_step},
+        "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+        "matvec_ms": round(mv_ms, 4),
+        "matvec_bytes": bytes_mv,
+        "matvec16_ms": round(mv16_ms, 4),
+        "matvec16_gbs": round(bytes_mv16 / (mv16_ms * 1e-3) / 1e9, 2),
+        "matvec16_vectors_per_s": round(nrhs / (mv16_ms * 1e-3), 1),
+        "gmres_solves_per_s": round(1e3 / float(np.mean(solve_ms)), 3),
+        "gmres_p50_ms": round(percentile(solve_ms, 0.5), 3),
+        "gmres_p99_ms": round(percentile(solve_ms, 0.99), 3),
+        "gmres_iters_mean": round(float(np.mean(rec["iters"])), 2),
+        "gmres_relres_max": float(np.max(rec["relres"])),
+        "gmres_solves": len(solve_ms),
+        "build_ms": round(float(np.mean(rec["build_ms"])), 3),
+        "build_aca_ms": round(float(np.mean(rec["aca_ms"])), 3),
+        "build_near_ms": round(float(np.mean(rec["near_ms"])), 3),
+        "hmatrix": {"n_blocks": stats["n_blocks"], "n_far": stats["n_far"],
+                    "n_near": stats["n_near"], "c_sp": stats["c_sp"],
+                    "rank_min": stats["rank_min"], "rank_max": stats["rank_max"],
+                    "rank_mean": round(stats["rank_mean"], 3),
+                    "stored_scalars": far_u + far_v + near,
+                    "compression": round(stats["compression"], 5)},
+    }
+    # Roofline of the dominant product kernel (U z + D x), from the events the
+    # library records between its kernels on its stream, averaged over the
+    # single-vector products. Algorithmic bytes per launch: the U factors and
+    # the dense blocks, each streamed once.
+    single_phase = None
+    if rec["phase_calls"] > 0:
+        single_phase = rec["phase_ms"] / rec["phase_calls"]
+    out["phase_ms_mean"] = [round(float(v), 4) for v in single_phase] if single_phase is not None else None
+    kern_bytes = 8 * (far_u + near)
+    kern_ms = float(single_phase[2]) if single_phase is not None else None
+    if kern_ms:
+        ach = kern_bytes / (kern_ms * 1e-3) / 1e9
+        out["roofline"] = {"kernel": "k_mvB (U z + D x)", "bound": "hbm", "achieved": round(ach, 2),
+                           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                           "traffic": None, "bytes_per_launch": kern_bytes,
+                           "avg_launch_ms": round(kern_ms, 4)}
+    if not args.no_cpu_baseline:
+        try:
+            out["cpu_baseline"] = cpu_baseline(V, T, wl, W.random_x(N, 1, seed=0), args.cpu_seconds)
+        except Exception as e:  # report, do not hide
+            out["cpu_baseline"] = {"error": repr(e)}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -89,6 +89,8 @@ typedef struct {
   double t_aca_ms;        /* device: ACA (K2) incl. compaction */
   double t_build_ms;      /* whole hmat_build */
   int64_t device_bytes;   /* persistent device memory held by the handle */
+  int64_t far_u_scalars;  /* sum over admissible blocks of m k (the U factors) */
+  int64_t far_v_scalars;  /* sum over admissible blocks of n k (the V factors) */
 } hmat_stats;
 
 typedef struct {
@@ -213,6 +215,18 @@ hmat_status hmat_entries(hmat_t h, int64_t n, const int64_t* rows, const int64_t
  */
 hmat_status hmat_set_factors(hmat_t h, const int32_t* ranks, const double* U, const double* V,
                              void* hip_stream);
+
+/*
+ * hmat_profile -- per-phase timing of hmat_matvec. With enable = 1 (which also
+ * resets the counters) every later hmat_matvec records HIP events on its
+ * stream between its kernels; enable = 0 stops recording. On return
+ * phase_ms (HOST double[4], may be NULL) holds the accumulated milliseconds of
+ * [gather x to cluster order, z = V^T x, U z + D x, reduction and scatter to
+ * the caller's order] over the products recorded so far, and *calls (may be
+ * NULL) their number (one per group of up to 16 right-hand sides). Reading
+ * waits for the recorded events.
+ */
+hmat_status hmat_profile(hmat_t h, int32_t enable, double* phase_ms, int64_t* calls);
 
 #ifdef __cplusplus
 }

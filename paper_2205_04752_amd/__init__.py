@@ -41,7 +41,8 @@ class _Stats(C.Structure):
                 ("n_rank_full", C.c_int32), ("n_near_threshold", C.c_int32),
                 ("aca_passes", C.c_int32), ("reserved", C.c_int32), ("t_plan_ms", C.c_double),
                 ("t_near_ms", C.c_double), ("t_aca_ms", C.c_double), ("t_build_ms", C.c_double),
-                ("device_bytes", C.c_int64)]
+                ("device_bytes", C.c_int64), ("far_u_scalars", C.c_int64),
+                ("far_v_scalars", C.c_int64)]
 
 
 class _SolveInfo(C.Structure):
@@ -50,7 +51,8 @@ class _SolveInfo(C.Structure):
 
 
 EXPORTS = ["hmat_build", "hmat_matvec", "hmat_solve", "hmat_info", "hmat_free",
-           "hmat_last_error", "hmat_plan", "hmat_block", "hmat_entries", "hmat_set_factors"]
+           "hmat_last_error", "hmat_plan", "hmat_block", "hmat_entries", "hmat_set_factors",
+           "hmat_profile"]
 
 _lib = None
 
@@ -75,6 +77,7 @@ def lib():
     L.hmat_block.argtypes = [vp, i32, vp, vp, vp, vp, vp]
     L.hmat_entries.argtypes = [vp, i64, vp, vp, vp, vp]
     L.hmat_set_factors.argtypes = [vp, vp, vp, vp, vp]
+    L.hmat_profile.argtypes = [vp, i32, vp, C.POINTER(i64)]
     for name in EXPORTS:
         if name != "hmat_last_error":
             getattr(L, name).restype = C.c_int
@@ -211,6 +214,14 @@ class HMatrix:
         _check(lib().hmat_entries(self._h, r.shape[0], r.ctypes.data, c.ctypes.data,
                                   out.ctypes.data, _stream(stream)))
         return out
+
+    def profile(self, enable: bool):
+        """Start (True, resets) or stop (False) per-phase product timing; returns the
+        accumulated (phase_ms[4], calls) so far: gather, V^T x, U z + D x, reduce."""
+        ms = np.zeros(4)
+        calls = C.c_int64(0)
+        _check(lib().hmat_profile(self._h, 1 if enable else 0, ms.ctypes.data, C.byref(calls)))
+        return ms, calls.value
 
     def set_factors(self, ranks, U_cat, V_cat, stream=None) -> None:
         rk = np.ascontiguousarray(ranks, dtype=np.int32)

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -23,7 +24,8 @@ hipError_t launch_compact(const CopyTask*, int, hipStream_t);
 hipError_t launch_gather(int, const double*, int64_t, const int32_t*, int64_t, double*, hipStream_t);
 hipError_t launch_matvec_group(int, const MvA*, int, const MvChunk*, int, const MvSeg*, const int32_t*, int,
                                const double*, const double*, const double*, int64_t, double*, int64_t,
-                               double*, const int32_t*, int64_t, double*, int64_t, hipStream_t);
+                               double*, const int32_t*, int64_t, double*, int64_t, hipStream_t,
+                               hipEvent_t*);
 hipError_t launch_dots(const double*, int64_t, int64_t, int, const double*, double*, hipStream_t);
 hipError_t launch_sub_proj(const double*, int64_t, int64_t, int, const double*, double*, double*, hipStream_t);
 hipError_t launch_norm(const double*, int64_t, double*, hipStream_t);
@@ -126,7 +128,16 @@ struct hmat {
   // GMRES workspace
   DevBuf d_Q, d_w, d_small;
   int q_cols = 0;
+  // product profiling: 5 events per recorded group (start, gathered, V^T x, U z + D x, done)
+  bool prof = false;
+  std::vector<std::array<hipEvent_t, 5>> prof_pending;
+  double prof_ms[4] = {0, 0, 0, 0};
+  int64_t prof_calls = 0;
   hmat_stats st{};
+  ~hmat() {
+    for (auto& e : prof_pending)
+      for (hipEvent_t x : e) (void)hipEventDestroy(x);
+  }
 };
 
 namespace {
@@ -242,6 +253,8 @@ void fill_stats(hmat* h) {
   double rs = 0;
   st.far_scalars = 0;
   st.near_scalars = 0;
+  st.far_u_scalars = 0;
+  st.far_v_scalars = 0;
   st.n_rank_full = 0;
   st.n_near_threshold = 0;
   for (size_t f = 0; f < h->far_blocks.size(); f++) {
@@ -250,6 +263,8 @@ void fill_stats(hmat* h) {
     st.rank_max = std::max(st.rank_max, k);
     rs += k;
     st.far_scalars += (int64_t)k * (block_m(h, b) + block_n(h, b));
+    st.far_u_scalars += (int64_t)k * block_m(h, b);
+    st.far_v_scalars += (int64_t)k * block_n(h, b);
     if (h->stop[f] == 2) st.n_rank_full++;
     if (h->ratio[f] >= 1.0 - 1e-9 && h->ratio[f] <= 1.0) st.n_near_threshold++;
   }
@@ -506,16 +521,42 @@ hmat_status build_impl(const hmat_mesh* mesh, double E, double nu, double eta, i
   }
 }
 
+// Accumulate the elapsed times of recorded product groups (waits for them).
+void prof_collect(hmat* h) {
+  for (auto& e : h->prof_pending) {
+    check(hipEventSynchronize(e[4]), "profile");
+    for (int k = 0; k < 4; k++) {
+      float t = 0.f;
+      check(hipEventElapsedTime(&t, e[k], e[k + 1]), "profile");
+      h->prof_ms[k] += t;
+    }
+    h->prof_calls++;
+    for (hipEvent_t x : e) (void)hipEventDestroy(x);
+  }
+  h->prof_pending.clear();
+}
+
 void matvec_impl(hmat* h, int32_t nrhs, const double* x, int64_t ldx, double* y, int64_t ldy,
                  hipStream_t s) {
   for (int32_t r0 = 0; r0 < nrhs; r0 += MV_MAX_NR) {
     const int nr = std::min<int32_t>(MV_MAX_NR, nrhs - r0);
+    hipEvent_t* ev = nullptr;
+    if (h->prof) {
+      if (h->prof_pending.size() >= 4096) prof_collect(h);
+      std::array<hipEvent_t, 5> e{};
+      for (auto& x : e) check(hipEventCreate(&x), "profile");
+      h->prof_pending.push_back(e);
+      ev = h->prof_pending.back().data();
+      check(hipEventRecord(ev[0], s), "profile");
+    }
     check(launch_gather(nr, x + r0 * ldx, ldx, h->d_order.as<int32_t>(), h->N, h->d_xp.as<double>(), s), "gather");
+    if (ev) check(hipEventRecord(ev[1], s), "profile");
     check(launch_matvec_group(nr, h->d_mvA.as<MvA>(), h->nA, h->d_chunk.as<MvChunk>(), h->nChunk,
                               h->d_seg.as<MvSeg>(), h->d_tile_chunk.as<int32_t>(), h->nTiles,
                               h->far_arena.as<double>(), h->near_arena.as<double>(), h->d_xp.as<double>(),
                               h->N, h->d_z.as<double>(), h->Ztot, h->d_part.as<double>(),
-                              h->d_order.as<int32_t>(), h->N, y + r0 * ldy, ldy, s),
+                              h->d_order.as<int32_t>(), h->N, y + r0 * ldy, ldy, s,
+                              ev ? ev + 2 : nullptr),
           "product");
   }
 }
@@ -819,6 +860,24 @@ hmat_status hmat_set_factors(hmat_t h, const int32_t* ranks, const double* U, co
     return fail(e.st, e.msg);
   } catch (const std::bad_alloc&) {
     return fail(HMAT_ENOMEM, "host allocation failed");
+  }
+  return HMAT_OK;
+}
+
+hmat_status hmat_profile(hmat_t h, int32_t enable, double* phase_ms, int64_t* calls) {
+  if (!h) return fail(HMAT_EINVAL, "handle is NULL");
+  try {
+    prof_collect(h);
+    if (phase_ms)
+      for (int k = 0; k < 4; k++) phase_ms[k] = h->prof_ms[k];
+    if (calls) *calls = h->prof_calls;
+    if (enable) {
+      for (double& t : h->prof_ms) t = 0.0;
+      h->prof_calls = 0;
+    }
+    h->prof = enable != 0;
+  } catch (const HipError& e) {
+    return fail(e.st, e.msg);
   }
   return HMAT_OK;
 }

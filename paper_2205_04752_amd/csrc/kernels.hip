@@ -676,15 +676,19 @@ template <int NR>
 static void mv_group(const MvA* itemsA, int nA, const MvChunk* chunks, int nC, const MvSeg* segs,
                      const int32_t* tile_chunk, int ntiles, const double* far, const double* near,
                      const double* xp, int64_t ldxp, int nr, double* z, int64_t ldz, double* part,
-                     const int32_t* order, int64_t N, double* y, int64_t ldy, hipStream_t s) {
+                     const int32_t* order, int64_t N, double* y, int64_t ldy, hipStream_t s,
+                     hipEvent_t* ev) {
   if (nA > 0)
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mvA<NR>), dim3(nA), dim3(WAVE), 0, s, itemsA, far, xp,
                        ldxp, nr, z, ldz);
+  if (ev) (void)hipEventRecord(ev[0], s);
   if (nC > 0)
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mvB<NR>), dim3(nC), dim3(WAVE), 0, s, chunks, segs, far,
                        near, z, ldz, xp, ldxp, nr, part);
+  if (ev) (void)hipEventRecord(ev[1], s);
   hipLaunchKernelGGL(HIP_KERNEL_NAME(k_reduce<NR>), dim3(ntiles), dim3(WAVE), 0, s, tile_chunk,
                      part, nr, order, N, y, ldy);
+  if (ev) (void)hipEventRecord(ev[2], s);
 }
 
 // One pass over the matrix for nr <= 16 right-hand sides (xp already gathered).
@@ -693,17 +697,17 @@ hipError_t launch_matvec_group(int nr, const MvA* itemsA, int nA, const MvChunk*
                                const double* far, const double* near, const double* xp,
                                int64_t ldxp, double* z, int64_t ldz, double* part,
                                const int32_t* order, int64_t N, double* y, int64_t ldy,
-                               hipStream_t s) {
+                               hipStream_t s, hipEvent_t* ev) {
   if (nr <= 1)
-    mv_group<1>(itemsA, nA, chunks, nC, segs, tile_chunk, ntiles, far, near, xp, ldxp, nr, z, ldz, part, order, N, y, ldy, s);
+    mv_group<1>(itemsA, nA, chunks, nC, segs, tile_chunk, ntiles, far, near, xp, ldxp, nr, z, ldz, part, order, N, y, ldy, s, ev);
   else if (nr <= 2)
-    mv_group<2>(itemsA, nA, chunks, nC, segs, tile_chunk, ntiles, far, near, xp, ldxp, nr, z, ldz, part, order, N, y, ldy, s);
+    mv_group<2>(itemsA, nA, chunks, nC, segs, tile_chunk, ntiles, far, near, xp, ldxp, nr, z, ldz, part, order, N, y, ldy, s, ev);
   else if (nr <= 4)
-    mv_group<4>(itemsA, nA, chunks, nC, segs, tile_chunk, ntiles, far, near, xp, ldxp, nr, z, ldz, part, order, N, y, ldy, s);
+    mv_group<4>(itemsA, nA, chunks, nC, segs, tile_chunk, ntiles, far, near, xp, ldxp, nr, z, ldz, part, order, N, y, ldy, s, ev);
   else if (nr <= 8)
-    mv_group<8>(itemsA, nA, chunks, nC, segs, tile_chunk, ntiles, far, near, xp, ldxp, nr, z, ldz, part, order, N, y, ldy, s);
+    mv_group<8>(itemsA, nA, chunks, nC, segs, tile_chunk, ntiles, far, near, xp, ldxp, nr, z, ldz, part, order, N, y, ldy, s, ev);
   else
-    mv_group<16>(itemsA, nA, chunks, nC, segs, tile_chunk, ntiles, far, near, xp, ldxp, nr, z, ldz, part, order, N, y, ldy, s);
+    mv_group<16>(itemsA, nA, chunks, nC, segs, tile_chunk, ntiles, far, near, xp, ldxp, nr, z, ldz, part, order, N, y, ldy, s, ev);
   return hipGetLastError();
 }
 
