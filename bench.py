@@ -83,6 +83,10 @@ def main():
     ap.add_argument("--workload", choices=["icosphere-L5", "icosphere-L3"], default="icosphere-L5")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=5.0)
+    ap.add_argument("--solves", type=int, default=4, help="GMRES solves per step")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one plain 512 MiB device-to-device copy first (a reference "
+                         "for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (the H-matrix path here is single-device); "
@@ -98,7 +102,7 @@ def main():
     V, T = wl["vertices"], wl["triangles"]
     N = 3 * len(T)
     nrhs = 16
-    solves_per_step = 4
+    solves_per_step = args.solves
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     X = torch.from_numpy(W.random_x(N, nrhs, seed=0)).to(dev)
@@ -108,6 +112,12 @@ def main():
     G = torch.from_numpy(np.stack([W.smooth_rhs(V, T, seed=1 + i)
                                    for i in range(n_total * solves_per_step)])).to(dev)
     stream = torch.cuda.current_stream()
+    if args.copy_calibration:
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device=dev)  # 512 MiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     rec = {"mv_ms": [], "mv16_ms": [], "solve_ms": [], "iters": [], "relres": [], "build_ms": [],
            "phase_ms": np.zeros(4), "phase_calls": 0, "aca_ms": [], "near_ms": []}
