@@ -21,12 +21,13 @@ hipError_t launch_near_only(const DevGeo&, const NearTask*, int, double*, hipStr
 hipError_t launch_entries(const DevGeo&, int64_t, const int64_t*, const int64_t*, double*, hipStream_t);
 hipError_t launch_aca(const DevGeo&, const AcaTask*, int, size_t, double, int32_t*, int32_t*, double*, hipStream_t);
 hipError_t launch_compact(const CopyTask*, int, hipStream_t);
-hipError_t launch_gather(int, const double*, int64_t, const int32_t*, int64_t, double*, hipStream_t);
+hipError_t launch_gather(int, const double*, int64_t, const int32_t*, int64_t, double*, int64_t, hipStream_t);
 hipError_t launch_matvec_group(int, const MvA*, int, const MvChunk*, int, const MvSeg*, const int32_t*, int,
                                const double*, const double*, const double*, int64_t, double*, int64_t,
                                double*, const int32_t*, int64_t, double*, int64_t, hipStream_t,
                                hipEvent_t*);
-hipError_t launch_dots(const double*, int64_t, int64_t, int, const double*, double*, hipStream_t);
+hipError_t launch_dots(const double*, int64_t, int64_t, int, const double*, double*, double*, hipStream_t);
+size_t dots_part_size(int64_t, int);
 hipError_t launch_sub_proj(const double*, int64_t, int64_t, int, const double*, double*, double*, hipStream_t);
 hipError_t launch_norm(const double*, int64_t, double*, hipStream_t);
 hipError_t launch_scale(const double*, int64_t, const double*, double*, hipStream_t);
@@ -87,10 +88,21 @@ void upload(DevBuf& d, const std::vector<T>& h, hipStream_t s, const char* what)
 }
 
 constexpr int KCAP_FIRST = 128;  // first-pass panel capacity (columns) of ACA
-constexpr int MV_TILE = 64;      // rows per product tile (one wave)
+constexpr int MV_TILE = 128;     // rows per product tile (one wave, two rows per lane)
 constexpr int MV_SEG_COLS = 128; // columns per product segment
 constexpr int64_t MV_CHUNK_BYTES = 96 * 1024;
 constexpr int MV_MAX_NR = 16;    // right-hand sides per pass over the matrix
+
+inline int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+// Panel layout of a block matrix whose rows are the global DOFs [R0, R0 + M).
+struct PanelShape {
+  int32_t fp, ld;
+};
+inline PanelShape panel_shape(int64_t R0, int64_t M) {
+  const int32_t fp = (int32_t)(R0 % PANEL_ALIGN);
+  return PanelShape{fp, (int32_t)round_up(fp + M, PANEL_ALIGN)};
+}
 
 double ms_since(std::chrono::steady_clock::time_point t0) {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -110,11 +122,13 @@ struct hmat {
   // block bookkeeping (canonical order)
   std::vector<int32_t> kind_index;  // far index or near index of block b
   std::vector<int32_t> far_blocks, near_blocks;
-  std::vector<int64_t> near_off;
+  std::vector<int64_t> near_off;              // per near block: panel base (multiple of 16)
+  std::vector<PanelShape> near_shape;
   DevBuf near_arena;
   std::vector<int32_t> rank, stop;
   std::vector<double> ratio;
-  std::vector<int64_t> far_off;
+  std::vector<int64_t> far_uoff, far_voff;   // per far block: U and V panel bases
+  std::vector<PanelShape> far_ushape, far_vshape;
   DevBuf far_arena;
   DevBuf piv1, piv2;
   std::vector<const int32_t*> piv_ptr;  // per far block: device [2][cap]
@@ -123,8 +137,8 @@ struct hmat {
   // product plan
   DevBuf d_mvA, d_seg, d_chunk, d_tile_chunk;
   int nA = 0, nSeg = 0, nChunk = 0, nTiles = 0;
-  int64_t Ztot = 0;
-  DevBuf d_xp, d_z, d_part;
+  int64_t Ztot = 0, ldxp = 0;
+  DevBuf d_xp, d_z, d_part, d_dotpart;
   // GMRES workspace
   DevBuf d_Q, d_w, d_small;
   int q_cols = 0;
@@ -158,41 +172,46 @@ void build_product_plan(hmat* h, hipStream_t s) {
     const int32_t k = h->rank[f];
     zoff[f] = z;
     if (k == 0) continue;
-    const int64_t m = block_m(h, b), n = block_n(h, b);
+    const int64_t R0 = 3 * (int64_t)P.cl[P.blk[b].s].off;
+    const PanelShape& V = h->far_vshape[f];
     for (int32_t l0 = 0; l0 < k; l0 += 8)
-      items.push_back(MvA{h->far_off[f] + m * k, (int32_t)n, l0, std::min(k, l0 + 8),
-                          3 * P.cl[P.blk[b].s].off, (int32_t)(z + l0), 0});
+      items.push_back(MvA{h->far_voff[f], V.ld, l0, std::min(k, l0 + 8), (int32_t)(R0 - V.fp),
+                          (int32_t)(z + l0), 0});
     z += k;
   }
-  h->Ztot = std::max<int64_t>(z, 1);
+  h->Ztot = std::max<int64_t>(round_up(z, 2), 2);
   struct SegT { int32_t tile; MvSeg seg; };
   std::vector<SegT> segs;
   for (size_t b = 0; b < P.blk.size(); b++) {
     const BlockRec& B = P.blk[b];
-    const int64_t r0 = 3 * (int64_t)P.cl[B.t].off, m = block_m(h, (int32_t)b);
+    const int64_t R0 = 3 * (int64_t)P.cl[B.t].off;
     int64_t base, ncols, soff;
+    PanelShape sh;
     int32_t far;
     if (B.far) {
       const int32_t f = h->kind_index[b];
       if (h->rank[f] == 0) continue;
-      base = h->far_off[f];
+      base = h->far_uoff[f];
+      sh = h->far_ushape[f];
       ncols = h->rank[f];
       soff = zoff[f];
       far = 1;
     } else {
       const int32_t nidx = h->kind_index[b];
       base = h->near_off[nidx];
+      sh = h->near_shape[nidx];
       ncols = block_n(h, (int32_t)b);
       soff = 3 * (int64_t)P.cl[B.s].off;
       far = 0;
     }
-    for (int64_t T = r0 / MV_TILE; T * MV_TILE < r0 + m; T++) {
-      const int64_t lo = std::max(r0, T * MV_TILE) - T * MV_TILE;
-      const int64_t hi = std::min(r0 + m, (T + 1) * MV_TILE) - T * MV_TILE;
+    const int64_t A0 = R0 - sh.fp, A1 = A0 + sh.ld;  // aligned row window of the panel
+    for (int64_t T = A0 / MV_TILE; T * MV_TILE < A1; T++) {
+      const int64_t lo = std::max(A0, T * MV_TILE) - T * MV_TILE;
+      const int64_t hi = std::min(A1, (T + 1) * MV_TILE) - T * MV_TILE;
       for (int64_t c0 = 0; c0 < ncols; c0 += MV_SEG_COLS) {
         MvSeg sg{};
-        sg.a_off = base + (T * MV_TILE - r0);
-        sg.lda = (int32_t)m;
+        sg.a_off = base - A0 + T * MV_TILE;
+        sg.ld = sh.ld;
         sg.c0 = (int32_t)c0;
         sg.c1 = (int32_t)std::min<int64_t>(ncols, c0 + MV_SEG_COLS);
         sg.soff = (int32_t)soff;
@@ -225,6 +244,29 @@ void build_product_plan(hmat* h, hipStream_t s) {
     }
   }
   tile_chunk[h->nTiles] = (int32_t)chunks.size();
+  // Host-side bounds check of every access the product kernels will make.
+  {
+    const int64_t far_n = (int64_t)(h->far_arena.bytes / sizeof(double));
+    const int64_t near_n = (int64_t)(h->near_arena.bytes / sizeof(double));
+    const int64_t ldxp = round_up(h->N, PANEL_ALIGN);
+    auto bad = [](const char* what) { throw HipError{HMAT_EDEVICE, std::string("internal: product plan: ") + what}; };
+    for (const MvA& I : items) {
+      if (I.v_off < 0 || I.v_off % 2 || I.ld % 2 || I.a0 % 2 || I.a0 < 0) bad("phase A alignment");
+      if (I.v_off + (int64_t)I.l1 * I.ld > far_n) bad("phase A matrix range");
+      if ((int64_t)I.a0 + I.ld > ldxp) bad("phase A vector range");
+      if ((int64_t)I.zoff + (I.l1 - I.l0) > h->Ztot) bad("phase A output range");
+    }
+    for (const MvSeg& sg : flat) {
+      const int64_t n = sg.far ? far_n : near_n;
+      if (sg.row_lo < 0 || sg.row_hi > MV_TILE || sg.row_lo >= sg.row_hi || sg.row_lo % 2) bad("phase B rows");
+      if (sg.a_off % 2 || sg.ld % 2) bad("phase B alignment");
+      if (sg.a_off + sg.row_lo + (int64_t)sg.c0 * sg.ld < 0) bad("phase B matrix range");
+      if (sg.a_off + sg.row_hi + (int64_t)(sg.c1 - 1) * sg.ld > n) bad("phase B matrix range");
+      if ((int64_t)sg.soff + sg.c1 > (sg.far ? h->Ztot : h->N)) bad("phase B vector range");
+    }
+    for (const MvChunk& c : chunks)
+      if (c.tile < 0 || c.tile >= h->nTiles || c.seg_lo >= c.seg_hi || c.seg_hi > (int32_t)flat.size()) bad("chunks");
+  }
   h->nA = (int)items.size();
   h->nSeg = (int)flat.size();
   h->nChunk = (int)chunks.size();
@@ -232,9 +274,15 @@ void build_product_plan(hmat* h, hipStream_t s) {
   upload(h->d_seg, flat, s, "product plan");
   upload(h->d_chunk, chunks, s, "product plan");
   upload(h->d_tile_chunk, tile_chunk, s, "product plan");
-  h->d_xp.alloc(sizeof(double) * MV_MAX_NR * h->N, "product workspace");
+  h->ldxp = round_up(h->N, PANEL_ALIGN);
+  if (h->d_xp.bytes < sizeof(double) * MV_MAX_NR * h->ldxp) {
+    h->d_xp.alloc(sizeof(double) * MV_MAX_NR * h->ldxp, "product workspace");
+    // rows [N, ldxp) stay zero: they meet only zero pad rows of V panels
+    check(hipMemsetAsync(h->d_xp.p, 0, h->d_xp.bytes, s), "product workspace");
+  }
   h->d_z.alloc(sizeof(double) * MV_MAX_NR * h->Ztot, "product workspace");
   h->d_part.alloc(sizeof(double) * MV_MAX_NR * MV_TILE * std::max(1, h->nChunk), "product workspace");
+  check(hipStreamSynchronize(s), "product plan");
 }
 
 void fill_stats(hmat* h) {
@@ -297,6 +345,29 @@ struct EventPair {
     return t;
   }
 };
+
+// Panel layout of the low-rank arena for the current ranks: U then V per block.
+// Returns the arena size in doubles.
+int64_t far_layout(hmat* h) {
+  const Plan& P = h->plan;
+  const size_t nf = h->far_blocks.size();
+  h->far_uoff.assign(nf, 0);
+  h->far_voff.assign(nf, 0);
+  h->far_ushape.assign(nf, PanelShape{0, 0});
+  h->far_vshape.assign(nf, PanelShape{0, 0});
+  int64_t fo = 0;
+  for (size_t f = 0; f < nf; f++) {
+    const BlockRec& B = P.blk[h->far_blocks[f]];
+    const int64_t k = h->rank[f];
+    h->far_ushape[f] = panel_shape(3 * (int64_t)P.cl[B.t].off, 3 * (int64_t)P.cl[B.t].len);
+    h->far_vshape[f] = panel_shape(3 * (int64_t)P.cl[B.s].off, 3 * (int64_t)P.cl[B.s].len);
+    h->far_uoff[f] = fo;
+    fo += (int64_t)h->far_ushape[f].ld * k;
+    h->far_voff[f] = fo;
+    fo += (int64_t)h->far_vshape[f].ld * k;
+  }
+  return fo;
+}
 
 // One ACA pass over the far blocks listed in `fidx` with per-block capacity
 // cap(f); panels in `panels`, pivots in `piv`.
@@ -403,11 +474,13 @@ hmat_status build_impl(const hmat_mesh* mesh, double E, double nu, double eta, i
       const BlockRec& B = P.blk[b];
       const Cluster& T = P.cl[B.t];
       const Cluster& S = P.cl[B.s];
+      const PanelShape sh = panel_shape(3 * (int64_t)T.off, 3 * (int64_t)T.len);
       h->near_off.push_back(noff);
-      ntasks.push_back(NearTask{T.off, T.len, S.off, S.len, noff});
+      h->near_shape.push_back(sh);
+      ntasks.push_back(NearTask{T.off, T.len, S.off, S.len, noff, sh.ld, sh.fp});
       if (B.t == B.s)
-        for (int32_t p = 0; p < T.len; p++) stasks[T.off + p] = SelfTask{noff, 3 * T.len, p};
-      noff += 9 * (int64_t)T.len * S.len;
+        for (int32_t p = 0; p < T.len; p++) stasks[T.off + p] = SelfTask{noff, sh.ld, sh.fp, p, 0};
+      noff += (int64_t)sh.ld * 3 * S.len;
     }
     {
       std::vector<char> seen(nt, 0);
@@ -417,8 +490,15 @@ hmat_status build_impl(const hmat_mesh* mesh, double E, double nu, double eta, i
       for (int32_t p = 0; p < nt; p++)
         if (!seen[p]) throw HipError{HMAT_EDEVICE, "internal: triangle without diagonal dense block"};
     }
+    for (const NearTask& t : ntasks)
+      if (t.d_off + t.fp + (int64_t)(3 * t.s_len - 1) * t.ld + 3 * t.t_len > noff)
+        throw HipError{HMAT_EDEVICE, "internal: dense block out of range"};
+    for (const SelfTask& t : stasks)
+      if (t.d_off + t.fp + (int64_t)(3 * t.ploc + 2) * t.ld + 3 * t.ploc + 3 > noff)
+        throw HipError{HMAT_EDEVICE, "internal: self entry out of range"};
     h->st.t_plan_ms = ms_since(t0);
     h->near_arena.alloc(sizeof(double) * noff, "dense blocks");
+    check(hipMemsetAsync(h->near_arena.p, 0, h->near_arena.bytes, s), "dense blocks");
     DevBuf d_ntasks, d_stasks;
     upload(d_ntasks, ntasks, s, "dense tasks");
     upload(d_stasks, stasks, s, "self tasks");
@@ -473,23 +553,25 @@ hmat_status build_impl(const hmat_mesh* mesh, double E, double nu, double eta, i
       for (size_t f = 0; f < nf; f++)
         if (h->stop[f] == 5)
           throw HipError{HMAT_EINVAL, "non-finite matrix entries (overlapping or duplicate triangles?)"};
-      // compaction into the final arena
-      h->far_off.assign(nf, 0);
-      int64_t fo = 0;
+      // compaction into the final arena (panel layout)
+      const int64_t fo = far_layout(h);
+      h->far_arena.alloc(sizeof(double) * std::max<int64_t>(fo, PANEL_ALIGN), "low-rank arena");
+      check(hipMemsetAsync(h->far_arena.p, 0, h->far_arena.bytes, s), "low-rank arena");
       for (size_t f = 0; f < nf; f++) {
-        const int32_t b = h->far_blocks[f];
-        h->far_off[f] = fo;
-        fo += (int64_t)h->rank[f] * (block_m(h, b) + block_n(h, b));
+        const int64_t k = h->rank[f];
+        if (k > capv[f] || h->far_voff[f] + k * h->far_vshape[f].ld > fo)
+          throw HipError{HMAT_EDEVICE, "internal: low-rank arena out of range"};
       }
-      h->far_arena.alloc(sizeof(double) * std::max<int64_t>(fo, 1), "low-rank arena");
       const std::vector<const double*>& src = panel_ptr;
       std::vector<CopyTask> ct;
       for (size_t f = 0; f < nf; f++) {
         const int32_t b = h->far_blocks[f];
         const int32_t m = (int32_t)block_m(h, b), n = (int32_t)block_n(h, b), k = h->rank[f];
         if (k == 0) continue;
-        ct.push_back(CopyTask{src[f], src[f] + (int64_t)m * capv[f],
-                              h->far_arena.as<double>() + h->far_off[f], m, n, k, 0});
+        double* base = h->far_arena.as<double>();
+        ct.push_back(CopyTask{src[f], src[f] + (int64_t)m * capv[f], base + h->far_uoff[f],
+                              base + h->far_voff[f], m, n, k, h->far_ushape[f].ld,
+                              h->far_ushape[f].fp, h->far_vshape[f].ld, h->far_vshape[f].fp, 0});
       }
       DevBuf d_ct;
       upload(d_ct, ct, s, "compaction tasks");
@@ -498,7 +580,8 @@ hmat_status build_impl(const hmat_mesh* mesh, double E, double nu, double eta, i
       panels1.release();
       panels2.release();
     } else {
-      h->far_arena.alloc(sizeof(double), "low-rank arena");
+      far_layout(h);
+      h->far_arena.alloc(sizeof(double) * PANEL_ALIGN, "low-rank arena");
     }
     check(hipEventRecord(eva.b, s), "event");
     check(hipStreamSynchronize(s), "build");
@@ -549,12 +632,14 @@ void matvec_impl(hmat* h, int32_t nrhs, const double* x, int64_t ldx, double* y,
       ev = h->prof_pending.back().data();
       check(hipEventRecord(ev[0], s), "profile");
     }
-    check(launch_gather(nr, x + r0 * ldx, ldx, h->d_order.as<int32_t>(), h->N, h->d_xp.as<double>(), s), "gather");
+    check(launch_gather(nr, x + r0 * ldx, ldx, h->d_order.as<int32_t>(), h->N, h->d_xp.as<double>(),
+                        h->ldxp, s),
+          "gather");
     if (ev) check(hipEventRecord(ev[1], s), "profile");
     check(launch_matvec_group(nr, h->d_mvA.as<MvA>(), h->nA, h->d_chunk.as<MvChunk>(), h->nChunk,
                               h->d_seg.as<MvSeg>(), h->d_tile_chunk.as<int32_t>(), h->nTiles,
                               h->far_arena.as<double>(), h->near_arena.as<double>(), h->d_xp.as<double>(),
-                              h->N, h->d_z.as<double>(), h->Ztot, h->d_part.as<double>(),
+                              h->ldxp, h->d_z.as<double>(), h->Ztot, h->d_part.as<double>(),
                               h->d_order.as<int32_t>(), h->N, y + r0 * ldy, ldy, s,
                               ev ? ev + 2 : nullptr),
           "product");
@@ -617,6 +702,8 @@ hmat_status hmat_solve(hmat_t h, const double* b, double* x, double tol, int32_t
       h->q_cols = m + 1;
     }
     if (!h->d_w.p) h->d_w.alloc(sizeof(double) * N, "GMRES work");
+    if (h->d_dotpart.bytes < sizeof(double) * dots_part_size(N, m + 1))
+      h->d_dotpart.alloc(sizeof(double) * dots_part_size(N, m + 1), "GMRES work");
     if (h->d_small.bytes < sizeof(double) * (3 * 1026 + 8)) h->d_small.alloc(sizeof(double) * (3 * 1026 + 8), "GMRES work");
     double* Q = h->d_Q.as<double>();
     double* w = h->d_w.as<double>();
@@ -660,7 +747,7 @@ hmat_status hmat_solve(hmat_t h, const double* b, double* x, double tol, int32_t
           total++;
           check(launch_fill(hacc, j + 2, 0.0, s), "fill");
           for (int pass = 0; pass < 2; pass++) {
-            check(launch_dots(Q, N, N, j + 1, w, hdot, s), "dots");
+            check(launch_dots(Q, N, N, j + 1, w, hdot, h->d_dotpart.as<double>(), s), "dots");
             check(launch_sub_proj(Q, N, N, j + 1, hdot, w, hacc, s), "project");
           }
           check(launch_norm(w, N, hacc + j + 1, s), "norm");
@@ -754,6 +841,16 @@ hmat_status hmat_plan(const hmat_mesh* mesh, double eta, int32_t leaf, int32_t* 
   return HMAT_OK;
 }
 
+// Copy a panel (rows [fp, fp + M) of `cols` columns with leading dimension ld)
+// from the device into a plain column-major M x cols host array.
+void copy_panel_out(const double* dev, PanelShape sh, int64_t M, int64_t cols, double* out) {
+  if (cols == 0) return;
+  std::vector<double> tmp((size_t)sh.ld * cols);
+  check(hipMemcpy(tmp.data(), dev, sizeof(double) * tmp.size(), hipMemcpyDeviceToHost), "block copy");
+  for (int64_t c = 0; c < cols; c++)
+    std::memcpy(out + c * M, tmp.data() + c * sh.ld + sh.fp, sizeof(double) * M);
+}
+
 hmat_status hmat_block(hmat_t h, int32_t b, int32_t* info, double* A, double* B, int32_t* prow,
                        int32_t* pcol) {
   if (!h) return fail(HMAT_EINVAL, "handle is NULL");
@@ -774,18 +871,16 @@ hmat_status hmat_block(hmat_t h, int32_t b, int32_t* info, double* A, double* B,
   }
   try {
     if (R.far) {
-      const double* base = h->far_arena.as<double>() + h->far_off[idx];
-      if (A && k) check(hipMemcpy(A, base, sizeof(double) * m * k, hipMemcpyDeviceToHost), "block copy");
-      if (B && k) check(hipMemcpy(B, base + m * k, sizeof(double) * n * k, hipMemcpyDeviceToHost), "block copy");
+      const double* base = h->far_arena.as<double>();
+      if (A) copy_panel_out(base + h->far_uoff[idx], h->far_ushape[idx], m, k, A);
+      if (B) copy_panel_out(base + h->far_voff[idx], h->far_vshape[idx], n, k, B);
       if (h->piv_ptr[idx] && k) {
         if (prow) check(hipMemcpy(prow, h->piv_ptr[idx], sizeof(int32_t) * k, hipMemcpyDeviceToHost), "pivots");
         if (pcol)
           check(hipMemcpy(pcol, h->piv_ptr[idx] + h->piv_cap[idx], sizeof(int32_t) * k, hipMemcpyDeviceToHost), "pivots");
       }
     } else if (A) {
-      check(hipMemcpy(A, h->near_arena.as<double>() + h->near_off[idx], sizeof(double) * m * n,
-                      hipMemcpyDeviceToHost),
-            "block copy");
+      copy_panel_out(h->near_arena.as<double>() + h->near_off[idx], h->near_shape[idx], m, n, A);
     }
   } catch (const HipError& e) {
     return fail(e.st, e.msg);
@@ -825,37 +920,38 @@ hmat_status hmat_set_factors(hmat_t h, const int32_t* ranks, const double* U, co
   if (!h || !ranks) return fail(HMAT_EINVAL, "handle or ranks is NULL");
   hipStream_t s = (hipStream_t)hip_stream;
   const size_t nf = h->far_blocks.size();
-  int64_t fo = 0, uo = 0, vo = 0;
-  std::vector<int64_t> off(nf);
+  int64_t total = 0;
   for (size_t f = 0; f < nf; f++) {
     const int32_t b = h->far_blocks[f], k = ranks[b];
     if (k < 0 || k > std::min(block_m(h, b), block_n(h, b))) return fail(HMAT_EINVAL, "rank out of range");
-    off[f] = fo;
-    fo += (int64_t)k * (block_m(h, b) + block_n(h, b));
+    total += k;
   }
-  if (fo > 0 && (!U || !V)) return fail(HMAT_EINVAL, "U or V is NULL");
+  if (total > 0 && (!U || !V)) return fail(HMAT_EINVAL, "U or V is NULL");
   try {
-    std::vector<double> host(std::max<int64_t>(fo, 1));
-    for (size_t f = 0; f < nf; f++) {
-      const int32_t b = h->far_blocks[f], k = ranks[b];
-      const int64_t m = block_m(h, b), n = block_n(h, b);
-      std::memcpy(host.data() + off[f], U + uo, sizeof(double) * m * k);
-      std::memcpy(host.data() + off[f] + m * k, V + vo, sizeof(double) * n * k);
-      uo += m * k;
-      vo += n * k;
-    }
     check(hipStreamSynchronize(s), "set factors");
-    h->far_arena.alloc(sizeof(double) * host.size(), "low-rank arena");
-    check(hipMemcpy(h->far_arena.p, host.data(), sizeof(double) * host.size(), hipMemcpyHostToDevice), "set factors");
     for (size_t f = 0; f < nf; f++) {
       h->rank[f] = ranks[h->far_blocks[f]];
       h->stop[f] = 0;
       h->ratio[f] = 0.0;
       h->piv_ptr[f] = nullptr;
     }
-    h->far_off = off;
+    const int64_t fo = far_layout(h);
+    std::vector<double> host(std::max<int64_t>(fo, PANEL_ALIGN), 0.0);
+    int64_t uo = 0, vo = 0;
+    for (size_t f = 0; f < nf; f++) {
+      const int32_t b = h->far_blocks[f], k = h->rank[f];
+      const int64_t m = block_m(h, b), n = block_n(h, b);
+      const PanelShape su = h->far_ushape[f], sv = h->far_vshape[f];
+      for (int32_t c = 0; c < k; c++) {
+        std::memcpy(host.data() + h->far_uoff[f] + (int64_t)c * su.ld + su.fp, U + uo + c * m, sizeof(double) * m);
+        std::memcpy(host.data() + h->far_voff[f] + (int64_t)c * sv.ld + sv.fp, V + vo + c * n, sizeof(double) * n);
+      }
+      uo += m * k;
+      vo += n * k;
+    }
+    h->far_arena.alloc(sizeof(double) * host.size(), "low-rank arena");
+    check(hipMemcpy(h->far_arena.p, host.data(), sizeof(double) * host.size(), hipMemcpyHostToDevice), "set factors");
     build_product_plan(h, s);
-    check(hipStreamSynchronize(s), "set factors");
   } catch (const HipError& e) {
     return fail(e.st, e.msg);
   } catch (const std::bad_alloc&) {

@@ -24,20 +24,29 @@ struct DevGeo {
   double c1, c2;
 };
 
-// Dense (non-admissible) block: column-major m x n at d_off in the near arena.
+// Panel layout shared by every stored block matrix (U, V and dense D): column
+// major; a panel whose rows are the global DOFs [R0, R0 + M) keeps row i of
+// column c at base + c*ld + fp + i, with fp = R0 mod 16, ld a multiple of 16
+// >= fp + M, and base 128-byte aligned. Global DOF g therefore sits at an
+// address congruent to g modulo 16 doubles: row windows that start at a
+// multiple of 16 map onto whole cache lines. Pad entries are zero.
+constexpr int PANEL_ALIGN = 16;  // doubles (128 bytes)
+
+// Dense (non-admissible) block at d_off in the near arena (m = 3 t_len rows).
 struct NearTask {
   int32_t t_off, t_len, s_off, s_len;
   int64_t d_off;
+  int32_t ld, fp;
 };
 
 // Self entry of cluster position p: lives in the diagonal dense block at d_off
-// (leading dimension m), local triangle index ploc.
+// with leading dimension ld and front pad fp, local triangle index ploc.
 struct SelfTask {
   int64_t d_off;
-  int32_t m, ploc;
+  int32_t ld, fp, ploc, pad;
 };
 
-// ACA task: panels U (m x kcap) then V (n x kcap), column-major, at `panel`.
+// ACA task: scratch panels U (m x kcap) then V (n x kcap), plain column-major, at `panel`.
 struct AcaTask {
   int32_t t_off, t_len, s_off, s_len;
   double* panel;
@@ -46,30 +55,33 @@ struct AcaTask {
   int32_t blk;    // index into the far-block result arrays
 };
 
-// Compaction: copy the first k columns of U and V into the final arena.
+// Compaction: copy the first k columns of the scratch panels into the final
+// arena in the panel layout above.
 struct CopyTask {
-  const double* srcU;
-  const double* srcV;
-  double* dst;    // U (m x k) followed by V (n x k)
-  int32_t m, n, k, pad;
+  const double* srcU;  // m x k, leading dimension m
+  const double* srcV;  // n x k, leading dimension n
+  double* dstU;        // column c, row i at dstU[c*ldu + fpu + i]
+  double* dstV;
+  int32_t m, n, k, ldu, fpu, ldv, fpv, pad;
 };
 
-// Product, phase A: z[zoff + l] = V[:, l] . xp[xoff : xoff+n] for l in [l0, l1).
+// Product, phase A: z[zoff + l - l0] = V[:, l] . xp[window] for l in [l0, l1).
+// The window is the aligned row range [a0, a0 + ld) of V (global DOFs).
 struct MvA {
-  int64_t v_off;  // V of the block in the far arena
-  int32_t n, l0, l1, xoff;
+  int64_t v_off;  // V base (row a0 of column 0) in the far arena
+  int32_t ld, l0, l1, a0;
   int32_t zoff, pad;
 };
 
-// Product, phase B: rows [row_lo, row_hi) of a 64-row tile, columns
-// [c0, c1) of a column-major matrix with leading dimension lda; matrix element
-// of tile row L and column c is base[a_off + L + c*lda]; the vector entry for
-// column c is src[soff + c] with src = z (far) or xp (near).
+// Product, phase B: columns [c0, c1) of a panel restricted to the rows
+// [row_lo, row_hi) of a 128-row tile (multiples of 16). The element of tile
+// row L and column c is base[a_off + L + c*ld]; the vector entry for column c
+// is src[soff + c] with src = z (far) or xp (near).
 struct MvSeg {
   int64_t a_off;
-  int32_t lda, c0, c1, soff;
+  int32_t ld, c0, c1, soff;
   int16_t row_lo, row_hi;
-  int32_t far;  // 1: matrix in the far arena, vector z; 0: near arena, vector xp
+  int32_t far;  // 1: U panel in the far arena, vector z; 0: D in the near arena, vector xp
 };
 
 struct MvChunk {

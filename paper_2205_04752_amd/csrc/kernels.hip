@@ -120,13 +120,14 @@ __device__ __forceinline__ double sym_get(const double s[6], int a, int b) {
 }
 
 // K1: dense blocks, one workgroup per block, one thread per triangle pair.
-// D is column-major m x n with m = 3 t_len; consecutive threads take consecutive
-// row triangles so the three rows of a pair land in contiguous memory.
+// D is stored in the panel layout (column-major, leading dimension ld, front
+// pad fp); consecutive threads take consecutive row triangles so the three
+// rows of a pair land in contiguous memory.
 __global__ __launch_bounds__(256) void k_near(DevGeo g, const NearTask* __restrict__ tasks,
                                               double* __restrict__ D) {
   const NearTask T = tasks[blockIdx.x];
-  const int m = 3 * T.t_len;
-  double* __restrict__ Db = D + T.d_off;
+  const int ld = T.ld;
+  double* __restrict__ Db = D + T.d_off + T.fp;
   const int npair = T.t_len * T.s_len;
   for (int idx = threadIdx.x; idx < npair; idx += blockDim.x) {
     const int p = idx % T.t_len, q = idx / T.t_len;
@@ -137,7 +138,7 @@ __global__ __launch_bounds__(256) void k_near(DevGeo g, const NearTask* __restri
 #pragma unroll
     for (int b = 0; b < 3; b++)
 #pragma unroll
-      for (int a = 0; a < 3; a++) Db[(size_t)(3 * q + b) * m + 3 * p + a] = sym_get(s, a, b);
+      for (int a = 0; a < 3; a++) Db[(size_t)(3 * q + b) * ld + 3 * p + a] = sym_get(s, a, b);
   }
 }
 
@@ -154,9 +155,9 @@ __global__ __launch_bounds__(256) void k_self(DevGeo g, const SelfTask* __restri
     for (int o = WAVE / 2; o > 0; o >>= 1) s[c] += __shfl_xor(s[c], o, WAVE);
   if (lane == 0) {
     const SelfTask T = tasks[p];
-    double* Db = D + T.d_off;
+    double* Db = D + T.d_off + T.fp;
     for (int b = 0; b < 3; b++)
-      for (int a = 0; a < 3; a++) Db[(size_t)(3 * T.ploc + b) * T.m + 3 * T.ploc + a] = sym_get(s, a, b);
+      for (int a = 0; a < 3; a++) Db[(size_t)(3 * T.ploc + b) * T.ld + 3 * T.ploc + a] = sym_get(s, a, b);
   }
 }
 
@@ -417,28 +418,40 @@ __global__ __launch_bounds__(ACA_T) void k_aca(DevGeo g, const AcaTask* __restri
   }
 }
 
-// Final low-rank arena: U (m x k) then V (n x k) per block, contiguous.
+// Final low-rank arena: the first k columns of the scratch panels, copied into
+// the padded panel layout (pads were zeroed with the arena).
 __global__ __launch_bounds__(256) void k_compact(const CopyTask* __restrict__ tasks) {
   const CopyTask T = tasks[blockIdx.x];
-  const size_t mu = (size_t)T.m * T.k, nv = (size_t)T.n * T.k;
-  for (size_t e = threadIdx.x; e < mu; e += blockDim.x) T.dst[e] = T.srcU[e];
-  for (size_t e = threadIdx.x; e < nv; e += blockDim.x) T.dst[mu + e] = T.srcV[e];
+  const int64_t mu = (int64_t)T.m * T.k, nv = (int64_t)T.n * T.k;
+  for (int64_t e = threadIdx.x; e < mu; e += blockDim.x) {
+    const int64_t c = e / T.m, i = e - c * T.m;
+    T.dstU[c * T.ldu + T.fpu + i] = T.srcU[e];
+  }
+  for (int64_t e = threadIdx.x; e < nv; e += blockDim.x) {
+    const int64_t c = e / T.n, i = e - c * T.n;
+    T.dstV[c * T.ldv + T.fpv + i] = T.srcV[e];
+  }
 }
 
 // ---------------------------------------------------------------------------
 // K3: H-matrix-vector product.
 
-// xp[r][3p+a] = x[r*ldx + 3 order[p] + a]
+// xp[r*ldxp + 3p+a] = x[r*ldx + 3 order[p] + a]
 __global__ void k_gather(int nr, const double* __restrict__ x, int64_t ldx,
-                         const int32_t* __restrict__ order, int64_t N, double* __restrict__ xp) {
+                         const int32_t* __restrict__ order, int64_t N, double* __restrict__ xp,
+                         int64_t ldxp) {
   const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (e >= N * nr) return;
-  const int64_t r = e / N, d = e % N;
-  xp[e] = x[r * ldx + 3 * (int64_t)order[d / 3] + d % 3];
+  const int64_t r = e / N, d = e - r * N;
+  xp[r * ldxp + d] = x[r * ldx + 3 * (int64_t)order[d / 3] + d % 3];
 }
 
-// Phase A: z = V_b^T x_s for a group of <= 8 columns; one wave per item, lanes
-// over rows; NR right-hand sides at once, columns in sub-batches of CB.
+constexpr int TILE = 2 * WAVE;  // rows per product tile: two rows per lane
+
+// Phase A: z = V_b^T x_s for a group of <= 8 columns; one wave per item. Lanes
+// cover the aligned row window of V two rows at a time (16-byte loads of V and
+// of the gathered x; pad rows of V are zero); NR right-hand sides at once,
+// columns in sub-batches of CB.
 template <int NR>
 __global__ __launch_bounds__(WAVE) void k_mvA(const MvA* __restrict__ items,
                                               const double* __restrict__ far,
@@ -448,6 +461,7 @@ __global__ __launch_bounds__(WAVE) void k_mvA(const MvA* __restrict__ items,
   const MvA I = items[blockIdx.x];
   const int lane = threadIdx.x;
   const double* __restrict__ V = far + I.v_off;
+  const double* __restrict__ X = xp + I.a0;
   for (int l0 = I.l0; l0 < I.l1; l0 += CB) {
     const int nc = min(CB, I.l1 - l0);
     double acc[CB][NR];
@@ -455,16 +469,17 @@ __global__ __launch_bounds__(WAVE) void k_mvA(const MvA* __restrict__ items,
     for (int c = 0; c < CB; c++)
 #pragma unroll
       for (int r = 0; r < NR; r++) acc[c][r] = 0.0;
-    for (int i = lane; i < I.n; i += WAVE) {
-      double xv[NR];
+    for (int i = 2 * lane; i < I.ld; i += TILE) {
+      double2 xv[NR];
 #pragma unroll
-      for (int r = 0; r < NR; r++) xv[r] = (r < nr) ? xp[r * ldxp + I.xoff + i] : 0.0;
+      for (int r = 0; r < NR; r++)
+        xv[r] = (r < nr) ? *reinterpret_cast<const double2*>(X + r * ldxp + i) : make_double2(0.0, 0.0);
 #pragma unroll
       for (int c = 0; c < CB; c++) {
         if (c < nc) {
-          const double v = V[i + (size_t)(l0 + c) * I.n];
+          const double2 v = *reinterpret_cast<const double2*>(V + (size_t)(l0 + c) * I.ld + i);
 #pragma unroll
-          for (int r = 0; r < NR; r++) acc[c][r] += v * xv[r];
+          for (int r = 0; r < NR; r++) acc[c][r] += v.x * xv[r].x + v.y * xv[r].y;
         }
       }
     }
@@ -472,14 +487,15 @@ __global__ __launch_bounds__(WAVE) void k_mvA(const MvA* __restrict__ items,
     for (int c = 0; c < CB; c++)
 #pragma unroll
       for (int r = 0; r < NR; r++) {
-        const double s = wave_sum(acc[c][r]);
-        if (lane == 0 && c < nc && r < nr) z[r * ldz + I.zoff + (l0 - I.l0) + c] = s;
+        const double sum = wave_sum(acc[c][r]);
+        if (lane == 0 && c < nc && r < nr) z[r * ldz + I.zoff + (l0 - I.l0) + c] = sum;
       }
   }
 }
 
-// Phase B: one wave per chunk of segments of one 64-row tile; lane = tile row.
-// Writes the chunk's partial sums part[chunk][r][64].
+// Phase B: one wave per chunk of segments of one 128-row tile; lane L owns tile
+// rows 2L and 2L+1 and reads them with one 16-byte load per column. Writes the
+// chunk's partial sums part[chunk][r][128].
 template <int NR>
 __global__ __launch_bounds__(WAVE) void k_mvB(const MvChunk* __restrict__ chunks,
                                               const MvSeg* __restrict__ segs,
@@ -489,40 +505,49 @@ __global__ __launch_bounds__(WAVE) void k_mvB(const MvChunk* __restrict__ chunks
                                               const double* __restrict__ xp, int64_t ldxp, int nr,
                                               double* __restrict__ part) {
   const MvChunk C = chunks[blockIdx.x];
-  const int L = threadIdx.x;
-  double acc[NR];
+  const int L2 = 2 * threadIdx.x;
+  double acc0[NR], acc1[NR];
 #pragma unroll
-  for (int r = 0; r < NR; r++) acc[r] = 0.0;
+  for (int r = 0; r < NR; r++) acc0[r] = acc1[r] = 0.0;
   for (int s = C.seg_lo; s < C.seg_hi; s++) {
     const MvSeg S = segs[s];
-    const bool act = L >= S.row_lo && L < S.row_hi;
-    const double* __restrict__ A = (S.far ? far : near) + S.a_off + L;
+    const bool act = L2 >= S.row_lo && L2 < S.row_hi;
+    const double* __restrict__ A = (S.far ? far : near) + S.a_off + L2;
     const double* __restrict__ src = (S.far ? z : xp) + S.soff;
     const int64_t ld = S.far ? ldz : ldxp;
     int c = S.c0;
     for (; c + 8 <= S.c1; c += 8) {
-      double a[8];
+      double2 a[8];
 #pragma unroll
-      for (int u = 0; u < 8; u++) a[u] = act ? A[(size_t)(c + u) * S.lda] : 0.0;
+      for (int u = 0; u < 8; u++)
+        a[u] = act ? *reinterpret_cast<const double2*>(A + (size_t)(c + u) * S.ld) : make_double2(0.0, 0.0);
 #pragma unroll
       for (int r = 0; r < NR; r++) {
         if (r < nr) {
           const double* sr = src + r * ld + c;
 #pragma unroll
-          for (int u = 0; u < 8; u++) acc[r] += a[u] * sr[u];
+          for (int u = 0; u < 8; u++) {
+            acc0[r] += a[u].x * sr[u];
+            acc1[r] += a[u].y * sr[u];
+          }
         }
       }
     }
     for (; c < S.c1; c++) {
-      const double a = act ? A[(size_t)c * S.lda] : 0.0;
+      const double2 a = act ? *reinterpret_cast<const double2*>(A + (size_t)c * S.ld) : make_double2(0.0, 0.0);
 #pragma unroll
       for (int r = 0; r < NR; r++)
-        if (r < nr) acc[r] += a * src[r * ld + c];
+        if (r < nr) {
+          const double v = src[r * ld + c];
+          acc0[r] += a.x * v;
+          acc1[r] += a.y * v;
+        }
     }
   }
 #pragma unroll
   for (int r = 0; r < NR; r++)
-    if (r < nr) part[((size_t)blockIdx.x * NR + r) * WAVE + L] = acc[r];
+    if (r < nr)
+      *reinterpret_cast<double2*>(part + ((size_t)blockIdx.x * NR + r) * TILE + L2) = make_double2(acc0[r], acc1[r]);
 }
 
 // Sum the partials of each tile in chunk order and scatter to the caller's order.
@@ -531,36 +556,60 @@ __global__ __launch_bounds__(WAVE) void k_reduce(const int32_t* __restrict__ til
                                                  const double* __restrict__ part, int nr,
                                                  const int32_t* __restrict__ order, int64_t N,
                                                  double* __restrict__ y, int64_t ldy) {
-  const int tile = blockIdx.x, L = threadIdx.x;
-  const int64_t row = (int64_t)tile * WAVE + L;
+  const int tile = blockIdx.x, L2 = 2 * threadIdx.x;
+  const int64_t row = (int64_t)tile * TILE + L2;
   if (row >= N) return;
   const int c0 = tile_chunk[tile], c1 = tile_chunk[tile + 1];
-  const int64_t dst = 3 * (int64_t)order[row / 3] + row % 3;
+  const int64_t d0 = 3 * (int64_t)order[row / 3] + row % 3;
+  const bool two = row + 1 < N;
+  const int64_t d1 = two ? 3 * (int64_t)order[(row + 1) / 3] + (row + 1) % 3 : 0;
   for (int r = 0; r < nr; r++) {
-    double s = 0.0;
-    for (int c = c0; c < c1; c++) s += part[((size_t)c * NR + r) * WAVE + L];
-    y[r * ldy + dst] = s;
+    double s0 = 0.0, s1 = 0.0;
+    for (int c = c0; c < c1; c++) {
+      const double2 p = *reinterpret_cast<const double2*>(part + ((size_t)c * NR + r) * TILE + L2);
+      s0 += p.x;
+      s1 += p.y;
+    }
+    y[r * ldy + d0] = s0;
+    if (two) y[r * ldy + d1] = s1;
   }
 }
 
 // ---------------------------------------------------------------------------
 // GMRES helpers (FP64).
 
-// out[c] = Q[:, c] . w for c < ncols; one workgroup per column.
-__global__ __launch_bounds__(256) void k_dots(const double* __restrict__ Q, int64_t ldq,
-                                              int64_t n, const double* __restrict__ w,
-                                              double* __restrict__ out) {
-  __shared__ double sh[NW];
-  const double* q = Q + (size_t)blockIdx.x * ldq;
-  double s = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) s += q[i] * w[i];
-  s = wave_sum(s);
-  if ((threadIdx.x & (WAVE - 1)) == 0) sh[threadIdx.x / WAVE] = s;
+// Two-stage Q^T w: workgroup b takes rows [b*DOT_ROWS, (b+1)*DOT_ROWS) and writes
+// part[b*ncols + c] = sum over its rows of Q[i, c] w[i]; k_dots_final sums over b.
+constexpr int DOT_ROWS = 512;
+__global__ __launch_bounds__(256) void k_dots_part(const double* __restrict__ Q, int64_t ldq,
+                                                   int64_t n, int ncols,
+                                                   const double* __restrict__ w,
+                                                   double* __restrict__ part) {
+  extern __shared__ double red[];  // [NW][ncols]
+  const int64_t i0 = (int64_t)blockIdx.x * DOT_ROWS + threadIdx.x;
+  const int64_t i1 = i0 + 256;
+  const double w0 = i0 < n ? w[i0] : 0.0, w1 = i1 < n ? w[i1] : 0.0;
+  const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+  for (int c = 0; c < ncols; c++) {
+    const double* q = Q + (size_t)c * ldq;
+    double s = (i0 < n ? q[i0] * w0 : 0.0) + (i1 < n ? q[i1] * w1 : 0.0);
+    s = wave_sum(s);
+    if (lane == 0) red[wv * ncols + c] = s;
+  }
   __syncthreads();
-  if (threadIdx.x == 0) {
+  for (int c = threadIdx.x; c < ncols; c += blockDim.x) {
     double t = 0.0;
-    for (int k = 0; k < NW; k++) t += sh[k];
-    out[blockIdx.x] = t;
+    for (int k = 0; k < NW; k++) t += red[k * ncols + c];
+    part[(size_t)blockIdx.x * ncols + c] = t;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_dots_final(const double* __restrict__ part, int nblk,
+                                                    int ncols, double* __restrict__ out) {
+  for (int c = threadIdx.x; c < ncols; c += blockDim.x) {
+    double t = 0.0;
+    for (int b = 0; b < nblk; b++) t += part[(size_t)b * ncols + c];
+    out[c] = t;
   }
 }
 
@@ -666,9 +715,9 @@ hipError_t launch_compact(const CopyTask* tasks, int ntasks, hipStream_t s) {
 }
 
 hipError_t launch_gather(int nr, const double* x, int64_t ldx, const int32_t* order, int64_t N,
-                         double* xp, hipStream_t s) {
+                         double* xp, int64_t ldxp, hipStream_t s) {
   hipLaunchKernelGGL(k_gather, dim3(blocks_for(N * nr, 256)), dim3(256), 0, s, nr, x, ldx, order,
-                     N, xp);
+                     N, xp, ldxp);
   return hipGetLastError();
 }
 
@@ -711,9 +760,15 @@ hipError_t launch_matvec_group(int nr, const MvA* itemsA, int nA, const MvChunk*
   return hipGetLastError();
 }
 
+// out[c] = Q[:, c] . w for c < ncols (part: scratch of dots_part_size(n, ncols) doubles).
+size_t dots_part_size(int64_t n, int ncols) { return (size_t)((n + DOT_ROWS - 1) / DOT_ROWS) * ncols; }
+
 hipError_t launch_dots(const double* Q, int64_t ldq, int64_t n, int ncols, const double* w,
-                       double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_dots, dim3(ncols), dim3(256), 0, s, Q, ldq, n, w, out);
+                       double* out, double* part, hipStream_t s) {
+  const int nblk = (int)((n + DOT_ROWS - 1) / DOT_ROWS);
+  hipLaunchKernelGGL(k_dots_part, dim3(nblk), dim3(256), sizeof(double) * NW * ncols, s, Q, ldq, n,
+                     ncols, w, part);
+  hipLaunchKernelGGL(k_dots_final, dim3(1), dim3(256), 0, s, part, nblk, ncols, out);
   return hipGetLastError();
 }
 
