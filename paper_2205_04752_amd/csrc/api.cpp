@@ -7,6 +7,7 @@
 #include <array>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <numeric>
@@ -21,11 +22,13 @@ hipError_t launch_near_only(const DevGeo&, const NearTask*, int, double*, hipStr
 hipError_t launch_entries(const DevGeo&, int64_t, const int64_t*, const int64_t*, double*, hipStream_t);
 hipError_t launch_aca(const DevGeo&, const AcaTask*, int, size_t, double, int32_t*, int32_t*, double*, hipStream_t);
 hipError_t launch_compact(const CopyTask*, int, hipStream_t);
+hipError_t launch_to_stream(const StreamTask*, int, double*, hipStream_t);
+hipError_t launch_from_stream(const StreamTask*, int, const double*, hipStream_t);
 hipError_t launch_gather(int, const double*, int64_t, const int32_t*, int64_t, double*, int64_t, hipStream_t);
 hipError_t launch_matvec_group(int, const MvA*, int, const MvChunk*, int, const MvSeg*, const int32_t*, int,
                                const double*, const double*, const double*, int64_t, double*, int64_t,
                                double*, const int32_t*, int64_t, double*, int64_t, hipStream_t,
-                               hipEvent_t*);
+                               hipEvent_t*, int);
 hipError_t launch_dots(const double*, int64_t, int64_t, int, const double*, double*, double*, hipStream_t);
 size_t dots_part_size(int64_t, int);
 hipError_t launch_sub_proj(const double*, int64_t, int64_t, int, const double*, double*, double*, hipStream_t);
@@ -90,7 +93,7 @@ void upload(DevBuf& d, const std::vector<T>& h, hipStream_t s, const char* what)
 constexpr int KCAP_FIRST = 128;  // first-pass panel capacity (columns) of ACA
 constexpr int MV_TILE = 128;     // rows per product tile (one wave, two rows per lane)
 constexpr int MV_SEG_COLS = 128; // columns per product segment
-constexpr int64_t MV_CHUNK_BYTES = 96 * 1024;
+constexpr int64_t MV_CHUNK_BYTES = 64 * 1024;  // default; HMAT_MV_CHUNK_KB overrides
 constexpr int MV_MAX_NR = 16;    // right-hand sides per pass over the matrix
 
 inline int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
@@ -122,14 +125,12 @@ struct hmat {
   // block bookkeeping (canonical order)
   std::vector<int32_t> kind_index;  // far index or near index of block b
   std::vector<int32_t> far_blocks, near_blocks;
-  std::vector<int64_t> near_off;              // per near block: panel base (multiple of 16)
-  std::vector<PanelShape> near_shape;
-  DevBuf near_arena;
   std::vector<int32_t> rank, stop;
   std::vector<double> ratio;
-  std::vector<int64_t> far_uoff, far_voff;   // per far block: U and V panel bases
-  std::vector<PanelShape> far_ushape, far_vshape;
-  DevBuf far_arena;
+  std::vector<int64_t> far_voff;    // per far block: V panel base in the far arena
+  std::vector<PanelShape> far_vshape;
+  DevBuf far_arena;                 // V factors (panel layout)
+  DevBuf stream;                    // U factors and dense blocks in product order
   DevBuf piv1, piv2;
   std::vector<const int32_t*> piv_ptr;  // per far block: device [2][cap]
   std::vector<int32_t> piv_cap;
@@ -137,7 +138,12 @@ struct hmat {
   // product plan
   DevBuf d_mvA, d_seg, d_chunk, d_tile_chunk;
   int nA = 0, nSeg = 0, nChunk = 0, nTiles = 0;
-  int64_t Ztot = 0, ldxp = 0;
+  int64_t Ztot = 0, ldxp = 0, stream_n = 0;
+  std::vector<MvSeg> segs;                       // host copy, product order
+  std::vector<int32_t> seg_tile;                 // tile of each segment
+  std::vector<std::vector<int32_t>> block_segs;  // canonical block -> its segments
+  int64_t mv_chunk_bytes = MV_CHUNK_BYTES;       // product tuning (HMAT_MV_CHUNK_KB)
+  int mv_unroll = 16;                            // columns per batch in phase B (HMAT_MV_UNROLL)
   DevBuf d_xp, d_z, d_part, d_dotpart;
   // GMRES workspace
   DevBuf d_Q, d_w, d_small;
@@ -159,9 +165,25 @@ namespace {
 int64_t block_m(const hmat* h, int32_t b) { return 3 * (int64_t)h->plan.cl[h->plan.blk[b].t].len; }
 int64_t block_n(const hmat* h, int32_t b) { return 3 * (int64_t)h->plan.cl[h->plan.blk[b].s].len; }
 
-// Product plan: phase-A items per far block and column group, phase-B segments
-// per (block, 64-row tile, column range), grouped into chunks of about
-// MV_CHUNK_BYTES per tile.
+// Panel layout of the V factors for the current ranks. Returns the arena size in doubles.
+int64_t far_layout(hmat* h) {
+  const Plan& P = h->plan;
+  const size_t nf = h->far_blocks.size();
+  h->far_voff.assign(nf, 0);
+  h->far_vshape.assign(nf, PanelShape{0, 0});
+  int64_t fo = 0;
+  for (size_t f = 0; f < nf; f++) {
+    const BlockRec& B = P.blk[h->far_blocks[f]];
+    h->far_vshape[f] = panel_shape(3 * (int64_t)P.cl[B.s].off, 3 * (int64_t)P.cl[B.s].len);
+    h->far_voff[f] = fo;
+    fo += (int64_t)h->far_vshape[f].ld * h->rank[f];
+  }
+  return fo;
+}
+
+// Product plan for the current ranks and V layout: phase-A items (largest
+// first), phase-B segments in product order with their stream offsets, chunks
+// of about MV_CHUNK_BYTES per tile. Sets stream_n; uploads the plan.
 void build_product_plan(hmat* h, hipStream_t s) {
   const Plan& P = h->plan;
   std::vector<MvA> items;
@@ -179,64 +201,71 @@ void build_product_plan(hmat* h, hipStream_t s) {
                           (int32_t)(z + l0), 0});
     z += k;
   }
+  std::stable_sort(items.begin(), items.end(), [](const MvA& a, const MvA& b) {
+    return (int64_t)a.ld * (a.l1 - a.l0) > (int64_t)b.ld * (b.l1 - b.l0);
+  });
   h->Ztot = std::max<int64_t>(round_up(z, 2), 2);
-  struct SegT { int32_t tile; MvSeg seg; };
+  struct SegT {
+    int32_t tile, block;
+    MvSeg seg;
+  };
   std::vector<SegT> segs;
   for (size_t b = 0; b < P.blk.size(); b++) {
     const BlockRec& B = P.blk[b];
-    const int64_t R0 = 3 * (int64_t)P.cl[B.t].off;
-    int64_t base, ncols, soff;
-    PanelShape sh;
+    const int64_t R0 = 3 * (int64_t)P.cl[B.t].off, m = block_m(h, (int32_t)b);
+    int64_t ncols, soff;
     int32_t far;
     if (B.far) {
       const int32_t f = h->kind_index[b];
       if (h->rank[f] == 0) continue;
-      base = h->far_uoff[f];
-      sh = h->far_ushape[f];
       ncols = h->rank[f];
       soff = zoff[f];
       far = 1;
     } else {
-      const int32_t nidx = h->kind_index[b];
-      base = h->near_off[nidx];
-      sh = h->near_shape[nidx];
       ncols = block_n(h, (int32_t)b);
       soff = 3 * (int64_t)P.cl[B.s].off;
       far = 0;
     }
-    const int64_t A0 = R0 - sh.fp, A1 = A0 + sh.ld;  // aligned row window of the panel
+    // rows [R0, R0 + m) widened to whole cache lines (zero rows in the stream)
+    const int64_t A0 = R0 / STREAM_ALIGN * STREAM_ALIGN, A1 = round_up(R0 + m, STREAM_ALIGN);
     for (int64_t T = A0 / MV_TILE; T * MV_TILE < A1; T++) {
       const int64_t lo = std::max(A0, T * MV_TILE) - T * MV_TILE;
       const int64_t hi = std::min(A1, (T + 1) * MV_TILE) - T * MV_TILE;
       for (int64_t c0 = 0; c0 < ncols; c0 += MV_SEG_COLS) {
         MvSeg sg{};
-        sg.a_off = base - A0 + T * MV_TILE;
-        sg.ld = sh.ld;
         sg.c0 = (int32_t)c0;
         sg.c1 = (int32_t)std::min<int64_t>(ncols, c0 + MV_SEG_COLS);
         sg.soff = (int32_t)soff;
         sg.row_lo = (int16_t)lo;
         sg.row_hi = (int16_t)hi;
         sg.far = far;
-        segs.push_back(SegT{(int32_t)T, sg});
+        segs.push_back(SegT{(int32_t)T, (int32_t)b, sg});
       }
     }
   }
   std::stable_sort(segs.begin(), segs.end(), [](const SegT& a, const SegT& b) { return a.tile < b.tile; });
   h->nTiles = (int)((h->N + MV_TILE - 1) / MV_TILE);
-  std::vector<MvSeg> flat(segs.size());
+  h->segs.assign(segs.size(), MvSeg{});
+  h->seg_tile.assign(segs.size(), 0);
+  h->block_segs.assign(P.blk.size(), {});
   std::vector<MvChunk> chunks;
   std::vector<int32_t> tile_chunk(h->nTiles + 1, 0);
+  int64_t so = 0;
   size_t i = 0;
   for (int32_t T = 0; T < h->nTiles; T++) {
     tile_chunk[T] = (int32_t)chunks.size();
     while (i < segs.size() && segs[i].tile == T) {
       MvChunk c{T, (int32_t)i, (int32_t)i, 0};
       int64_t bytes = 0;
-      while (i < segs.size() && segs[i].tile == T && (bytes < MV_CHUNK_BYTES || c.seg_hi == c.seg_lo)) {
-        const MvSeg& sg = segs[i].seg;
-        bytes += (int64_t)(sg.row_hi - sg.row_lo) * (sg.c1 - sg.c0) * 8;
-        flat[i] = sg;
+      while (i < segs.size() && segs[i].tile == T && (bytes < h->mv_chunk_bytes || c.seg_hi == c.seg_lo)) {
+        MvSeg sg = segs[i].seg;
+        const int64_t len = sg.row_hi - sg.row_lo;
+        sg.so = so;
+        so += len * (sg.c1 - sg.c0);
+        bytes += len * (sg.c1 - sg.c0) * 8;
+        h->segs[i] = sg;
+        h->seg_tile[i] = T;
+        h->block_segs[segs[i].block].push_back((int32_t)i);
         i++;
         c.seg_hi = (int32_t)i;
       }
@@ -244,37 +273,37 @@ void build_product_plan(hmat* h, hipStream_t s) {
     }
   }
   tile_chunk[h->nTiles] = (int32_t)chunks.size();
+  h->stream_n = std::max<int64_t>(so, PANEL_ALIGN);
+  h->ldxp = round_up(h->N, PANEL_ALIGN);
   // Host-side bounds check of every access the product kernels will make.
   {
     const int64_t far_n = (int64_t)(h->far_arena.bytes / sizeof(double));
-    const int64_t near_n = (int64_t)(h->near_arena.bytes / sizeof(double));
-    const int64_t ldxp = round_up(h->N, PANEL_ALIGN);
     auto bad = [](const char* what) { throw HipError{HMAT_EDEVICE, std::string("internal: product plan: ") + what}; };
     for (const MvA& I : items) {
       if (I.v_off < 0 || I.v_off % 2 || I.ld % 2 || I.a0 % 2 || I.a0 < 0) bad("phase A alignment");
       if (I.v_off + (int64_t)I.l1 * I.ld > far_n) bad("phase A matrix range");
-      if ((int64_t)I.a0 + I.ld > ldxp) bad("phase A vector range");
+      if ((int64_t)I.a0 + I.ld > h->ldxp) bad("phase A vector range");
       if ((int64_t)I.zoff + (I.l1 - I.l0) > h->Ztot) bad("phase A output range");
     }
-    for (const MvSeg& sg : flat) {
-      const int64_t n = sg.far ? far_n : near_n;
+    for (const MvSeg& sg : h->segs) {
       if (sg.row_lo < 0 || sg.row_hi > MV_TILE || sg.row_lo >= sg.row_hi || sg.row_lo % 2) bad("phase B rows");
-      if (sg.a_off % 2 || sg.ld % 2) bad("phase B alignment");
-      if (sg.a_off + sg.row_lo + (int64_t)sg.c0 * sg.ld < 0) bad("phase B matrix range");
-      if (sg.a_off + sg.row_hi + (int64_t)(sg.c1 - 1) * sg.ld > n) bad("phase B matrix range");
+      if (sg.so % 2 || sg.so < 0) bad("phase B alignment");
+      if (sg.so + (int64_t)(sg.row_hi - sg.row_lo) * (sg.c1 - sg.c0) > h->stream_n) bad("phase B matrix range");
       if ((int64_t)sg.soff + sg.c1 > (sg.far ? h->Ztot : h->N)) bad("phase B vector range");
     }
     for (const MvChunk& c : chunks)
-      if (c.tile < 0 || c.tile >= h->nTiles || c.seg_lo >= c.seg_hi || c.seg_hi > (int32_t)flat.size()) bad("chunks");
+      if (c.tile < 0 || c.tile >= h->nTiles || c.seg_lo >= c.seg_hi || c.seg_hi > (int32_t)h->segs.size()) bad("chunks");
+    for (int32_t T = 0; T < h->nTiles; T++)
+      if (tile_chunk[T + 1] <= tile_chunk[T]) bad("tile without chunks");
   }
   h->nA = (int)items.size();
-  h->nSeg = (int)flat.size();
+  h->nSeg = (int)h->segs.size();
   h->nChunk = (int)chunks.size();
   upload(h->d_mvA, items, s, "product plan");
-  upload(h->d_seg, flat, s, "product plan");
+  upload(h->d_seg, h->segs, s, "product plan");
   upload(h->d_chunk, chunks, s, "product plan");
   upload(h->d_tile_chunk, tile_chunk, s, "product plan");
-  h->ldxp = round_up(h->N, PANEL_ALIGN);
+
   if (h->d_xp.bytes < sizeof(double) * MV_MAX_NR * h->ldxp) {
     h->d_xp.alloc(sizeof(double) * MV_MAX_NR * h->ldxp, "product workspace");
     // rows [N, ldxp) stay zero: they meet only zero pad rows of V panels
@@ -283,6 +312,34 @@ void build_product_plan(hmat* h, hipStream_t s) {
   h->d_z.alloc(sizeof(double) * MV_MAX_NR * h->Ztot, "product workspace");
   h->d_part.alloc(sizeof(double) * MV_MAX_NR * MV_TILE * std::max(1, h->nChunk), "product workspace");
   check(hipStreamSynchronize(s), "product plan");
+}
+
+// Stream tasks for every segment of the blocks selected by `want`, with the
+// plain column-major source/destination of each block given by `mat(b)`.
+template <class Want, class Mat>
+std::vector<StreamTask> stream_tasks(const hmat* h, Want want, Mat mat) {
+  std::vector<StreamTask> t;
+  const Plan& P = h->plan;
+  for (size_t b = 0; b < P.blk.size(); b++) {
+    if (!want((int32_t)b)) continue;
+    const int64_t R0 = 3 * (int64_t)P.cl[P.blk[b].t].off, m = block_m(h, (int32_t)b);
+    double* ptr = mat((int32_t)b);
+    for (int32_t si : h->block_segs[b]) {
+      const MvSeg& sg = h->segs[si];
+      StreamTask st{};
+      st.src = ptr;
+      st.dst = ptr;
+      st.so = sg.so;
+      st.ld = (int32_t)m;
+      st.r0 = (int32_t)((int64_t)h->seg_tile[si] * MV_TILE - R0);
+      st.row_lo = sg.row_lo;
+      st.row_hi = sg.row_hi;
+      st.c0 = sg.c0;
+      st.c1 = sg.c1;
+      t.push_back(st);
+    }
+  }
+  return t;
 }
 
 void fill_stats(hmat* h) {
@@ -322,11 +379,11 @@ void fill_stats(hmat* h) {
   st.compression = (double)(st.far_scalars + st.near_scalars) / ((double)h->N * (double)h->N);
   st.aca_passes = h->aca_passes;
   st.device_bytes = (int64_t)(h->d_cen.bytes + h->d_q.bytes + h->d_vtx.bytes + h->d_gl.bytes +
-                              h->d_order.bytes + h->near_arena.bytes + h->far_arena.bytes +
+                              h->d_order.bytes + h->far_arena.bytes + h->stream.bytes +
                               h->piv1.bytes + h->piv2.bytes + h->d_mvA.bytes + h->d_seg.bytes +
                               h->d_chunk.bytes + h->d_tile_chunk.bytes + h->d_xp.bytes +
-                              h->d_z.bytes + h->d_part.bytes + h->d_Q.bytes + h->d_w.bytes +
-                              h->d_small.bytes);
+                              h->d_z.bytes + h->d_part.bytes + h->d_dotpart.bytes + h->d_Q.bytes +
+                              h->d_w.bytes + h->d_small.bytes);
 }
 
 struct EventPair {
@@ -346,31 +403,8 @@ struct EventPair {
   }
 };
 
-// Panel layout of the low-rank arena for the current ranks: U then V per block.
-// Returns the arena size in doubles.
-int64_t far_layout(hmat* h) {
-  const Plan& P = h->plan;
-  const size_t nf = h->far_blocks.size();
-  h->far_uoff.assign(nf, 0);
-  h->far_voff.assign(nf, 0);
-  h->far_ushape.assign(nf, PanelShape{0, 0});
-  h->far_vshape.assign(nf, PanelShape{0, 0});
-  int64_t fo = 0;
-  for (size_t f = 0; f < nf; f++) {
-    const BlockRec& B = P.blk[h->far_blocks[f]];
-    const int64_t k = h->rank[f];
-    h->far_ushape[f] = panel_shape(3 * (int64_t)P.cl[B.t].off, 3 * (int64_t)P.cl[B.t].len);
-    h->far_vshape[f] = panel_shape(3 * (int64_t)P.cl[B.s].off, 3 * (int64_t)P.cl[B.s].len);
-    h->far_uoff[f] = fo;
-    fo += (int64_t)h->far_ushape[f].ld * k;
-    h->far_voff[f] = fo;
-    fo += (int64_t)h->far_vshape[f].ld * k;
-  }
-  return fo;
-}
-
-// One ACA pass over the far blocks listed in `fidx` with per-block capacity
-// cap(f); panels in `panels`, pivots in `piv`.
+// One ACA pass over the far blocks listed in `fidx` (largest first) with
+// per-block capacity cap(f); panels in `panels`, pivots in `piv`.
 template <class CapFn>
 void run_aca_pass(hmat* h, const std::vector<int32_t>& fidx, CapFn cap, DevBuf& panels, DevBuf& piv,
                   DevBuf& d_rank, DevBuf& d_stop, DevBuf& d_ratio,
@@ -427,6 +461,23 @@ void run_aca_pass(hmat* h, const std::vector<int32_t>& fidx, CapFn cap, DevBuf& 
   check(hipStreamSynchronize(s), "ACA");
 }
 
+// Fill the stream arena from plain column-major sources of the dense blocks
+// (near_src + near_off[i]) and of the U factors (u_ptr[f], leading dimension m).
+void fill_stream(hmat* h, const double* near_src, const std::vector<int64_t>& near_off,
+                 const std::vector<const double*>& u_ptr, hipStream_t s) {
+  h->stream.alloc(sizeof(double) * h->stream_n, "product stream");
+  auto tasks = stream_tasks(
+      h, [&](int32_t b) { return !h->plan.blk[b].far || h->rank[h->kind_index[b]] > 0; },
+      [&](int32_t b) -> double* {
+        const int32_t idx = h->kind_index[b];
+        return const_cast<double*>(h->plan.blk[b].far ? u_ptr[idx] : near_src + near_off[idx]);
+      });
+  DevBuf d_t;
+  upload(d_t, tasks, s, "stream tasks");
+  check(launch_to_stream(d_t.as<StreamTask>(), (int)tasks.size(), h->stream.as<double>(), s), "stream fill");
+  check(hipStreamSynchronize(s), "stream fill");
+}
+
 hmat_status build_impl(const hmat_mesh* mesh, double E, double nu, double eta, int32_t leaf,
                        double eps, hipStream_t s, hmat** out) {
   auto t0 = std::chrono::steady_clock::now();
@@ -434,6 +485,8 @@ hmat_status build_impl(const hmat_mesh* mesh, double E, double nu, double eta, i
   if (!h) return fail(HMAT_ENOMEM, "host allocation failed");
   try {
     check(hipGetDevice(&h->device), "hipGetDevice");
+    if (const char* e = std::getenv("HMAT_MV_CHUNK_KB")) h->mv_chunk_bytes = std::max(1L, std::atol(e)) * 1024;
+    if (const char* e = std::getenv("HMAT_MV_UNROLL")) h->mv_unroll = std::atoi(e);
     h->E = E;
     h->nu = nu;
     h->eta = eta;
@@ -455,7 +508,6 @@ hmat_status build_impl(const hmat_mesh* mesh, double E, double nu, double eta, i
     const double cK = (1.0 + nu) / (8.0 * M_PI * E * (1.0 - nu));
     h->G = DevGeo{h->d_cen.as<double>(), h->d_q.as<double>(), h->d_vtx.as<double>(),
                   h->d_gl.as<double>(), nt, 0, cK * (3.0 - 4.0 * nu), cK};
-    // classify blocks
     h->kind_index.assign(P.blk.size(), -1);
     for (size_t b = 0; b < P.blk.size(); b++) {
       if (P.blk[b].far) {
@@ -466,21 +518,20 @@ hmat_status build_impl(const hmat_mesh* mesh, double E, double nu, double eta, i
         h->near_blocks.push_back((int32_t)b);
       }
     }
-    // near arena and tasks
+    // K1 into a plain column-major staging arena (m x n per dense block)
     std::vector<NearTask> ntasks;
     std::vector<SelfTask> stasks(nt);
+    std::vector<int64_t> near_off;
     int64_t noff = 0;
     for (int32_t b : h->near_blocks) {
       const BlockRec& B = P.blk[b];
       const Cluster& T = P.cl[B.t];
       const Cluster& S = P.cl[B.s];
-      const PanelShape sh = panel_shape(3 * (int64_t)T.off, 3 * (int64_t)T.len);
-      h->near_off.push_back(noff);
-      h->near_shape.push_back(sh);
-      ntasks.push_back(NearTask{T.off, T.len, S.off, S.len, noff, sh.ld, sh.fp});
+      near_off.push_back(noff);
+      ntasks.push_back(NearTask{T.off, T.len, S.off, S.len, noff, 3 * T.len, 0});
       if (B.t == B.s)
-        for (int32_t p = 0; p < T.len; p++) stasks[T.off + p] = SelfTask{noff, sh.ld, sh.fp, p, 0};
-      noff += (int64_t)sh.ld * 3 * S.len;
+        for (int32_t p = 0; p < T.len; p++) stasks[T.off + p] = SelfTask{noff, 3 * T.len, 0, p, 0};
+      noff += 9 * (int64_t)T.len * S.len;
     }
     {
       std::vector<char> seen(nt, 0);
@@ -491,23 +542,19 @@ hmat_status build_impl(const hmat_mesh* mesh, double E, double nu, double eta, i
         if (!seen[p]) throw HipError{HMAT_EDEVICE, "internal: triangle without diagonal dense block"};
     }
     for (const NearTask& t : ntasks)
-      if (t.d_off + t.fp + (int64_t)(3 * t.s_len - 1) * t.ld + 3 * t.t_len > noff)
-        throw HipError{HMAT_EDEVICE, "internal: dense block out of range"};
-    for (const SelfTask& t : stasks)
-      if (t.d_off + t.fp + (int64_t)(3 * t.ploc + 2) * t.ld + 3 * t.ploc + 3 > noff)
-        throw HipError{HMAT_EDEVICE, "internal: self entry out of range"};
+      if (t.d_off + (int64_t)(3 * t.s_len) * t.ld > noff) throw HipError{HMAT_EDEVICE, "internal: dense block out of range"};
     h->st.t_plan_ms = ms_since(t0);
-    h->near_arena.alloc(sizeof(double) * noff, "dense blocks");
-    check(hipMemsetAsync(h->near_arena.p, 0, h->near_arena.bytes, s), "dense blocks");
+    DevBuf near_stage;
+    near_stage.alloc(sizeof(double) * std::max<int64_t>(noff, 1), "dense blocks");
     DevBuf d_ntasks, d_stasks;
     upload(d_ntasks, ntasks, s, "dense tasks");
     upload(d_stasks, stasks, s, "self tasks");
     EventPair evn;
     check(hipEventRecord(evn.a, s), "event");
-    check(launch_near_only(h->G, d_ntasks.as<NearTask>(), (int)ntasks.size(), h->near_arena.as<double>(), s), "K1 launch");
-    check(launch_self(h->G, d_stasks.as<SelfTask>(), h->near_arena.as<double>(), s), "K1 self launch");
+    check(launch_near_only(h->G, d_ntasks.as<NearTask>(), (int)ntasks.size(), near_stage.as<double>(), s), "K1 launch");
+    check(launch_self(h->G, d_stasks.as<SelfTask>(), near_stage.as<double>(), s), "K1 self launch");
     check(hipEventRecord(evn.b, s), "event");
-    // ACA
+    // K2: ACA
     const size_t nf = h->far_blocks.size();
     h->rank.assign(nf, 0);
     h->stop.assign(nf, 0);
@@ -553,42 +600,34 @@ hmat_status build_impl(const hmat_mesh* mesh, double E, double nu, double eta, i
       for (size_t f = 0; f < nf; f++)
         if (h->stop[f] == 5)
           throw HipError{HMAT_EINVAL, "non-finite matrix entries (overlapping or duplicate triangles?)"};
-      // compaction into the final arena (panel layout)
-      const int64_t fo = far_layout(h);
-      h->far_arena.alloc(sizeof(double) * std::max<int64_t>(fo, PANEL_ALIGN), "low-rank arena");
-      check(hipMemsetAsync(h->far_arena.p, 0, h->far_arena.bytes, s), "low-rank arena");
-      for (size_t f = 0; f < nf; f++) {
-        const int64_t k = h->rank[f];
-        if (k > capv[f] || h->far_voff[f] + k * h->far_vshape[f].ld > fo)
-          throw HipError{HMAT_EDEVICE, "internal: low-rank arena out of range"};
-      }
-      const std::vector<const double*>& src = panel_ptr;
-      std::vector<CopyTask> ct;
-      for (size_t f = 0; f < nf; f++) {
-        const int32_t b = h->far_blocks[f];
-        const int32_t m = (int32_t)block_m(h, b), n = (int32_t)block_n(h, b), k = h->rank[f];
-        if (k == 0) continue;
-        double* base = h->far_arena.as<double>();
-        ct.push_back(CopyTask{src[f], src[f] + (int64_t)m * capv[f], base + h->far_uoff[f],
-                              base + h->far_voff[f], m, n, k, h->far_ushape[f].ld,
-                              h->far_ushape[f].fp, h->far_vshape[f].ld, h->far_vshape[f].fp, 0});
-      }
-      DevBuf d_ct;
-      upload(d_ct, ct, s, "compaction tasks");
-      check(launch_compact(d_ct.as<CopyTask>(), (int)ct.size(), s), "compaction launch");
-      check(hipStreamSynchronize(s), "compaction");
-      panels1.release();
-      panels2.release();
-    } else {
-      far_layout(h);
-      h->far_arena.alloc(sizeof(double) * PANEL_ALIGN, "low-rank arena");
     }
+    // V factors into the panel-layout arena
+    const int64_t fo = far_layout(h);
+    for (size_t f = 0; f < nf; f++)
+      if (h->rank[f] > capv[f] || h->far_voff[f] + (int64_t)h->rank[f] * h->far_vshape[f].ld > fo)
+        throw HipError{HMAT_EDEVICE, "internal: low-rank arena out of range"};
+    h->far_arena.alloc(sizeof(double) * std::max<int64_t>(fo, PANEL_ALIGN), "low-rank arena");
+    check(hipMemsetAsync(h->far_arena.p, 0, h->far_arena.bytes, s), "low-rank arena");
+    std::vector<CopyTask> ct;
+    for (size_t f = 0; f < nf; f++) {
+      const int32_t b = h->far_blocks[f];
+      const int32_t m = (int32_t)block_m(h, b), n = (int32_t)block_n(h, b), k = h->rank[f];
+      if (k == 0) continue;
+      ct.push_back(CopyTask{panel_ptr[f] + (int64_t)m * capv[f], h->far_arena.as<double>() + h->far_voff[f],
+                            n, k, h->far_vshape[f].ld, h->far_vshape[f].fp});
+    }
+    DevBuf d_ct;
+    upload(d_ct, ct, s, "compaction tasks");
+    check(launch_compact(d_ct.as<CopyTask>(), (int)ct.size(), s), "compaction launch");
+    // product plan, then U factors and dense blocks into the stream arena
+    build_product_plan(h, s);
+    fill_stream(h, near_stage.as<double>(), near_off, panel_ptr, s);
     check(hipEventRecord(eva.b, s), "event");
     check(hipStreamSynchronize(s), "build");
+    panels1.release();
+    panels2.release();
     h->st.t_near_ms = evn.ms();
     h->st.t_aca_ms = eva.ms();
-    build_product_plan(h, s);
-    check(hipStreamSynchronize(s), "build");
     fill_stats(h);
     h->st.t_build_ms = ms_since(t0);
     *out = h;
@@ -638,12 +677,36 @@ void matvec_impl(hmat* h, int32_t nrhs, const double* x, int64_t ldx, double* y,
     if (ev) check(hipEventRecord(ev[1], s), "profile");
     check(launch_matvec_group(nr, h->d_mvA.as<MvA>(), h->nA, h->d_chunk.as<MvChunk>(), h->nChunk,
                               h->d_seg.as<MvSeg>(), h->d_tile_chunk.as<int32_t>(), h->nTiles,
-                              h->far_arena.as<double>(), h->near_arena.as<double>(), h->d_xp.as<double>(),
+                              h->far_arena.as<double>(), h->stream.as<double>(), h->d_xp.as<double>(),
                               h->ldxp, h->d_z.as<double>(), h->Ztot, h->d_part.as<double>(),
                               h->d_order.as<int32_t>(), h->N, y + r0 * ldy, ldy, s,
-                              ev ? ev + 2 : nullptr),
+                              ev ? ev + 2 : nullptr, h->mv_unroll),
           "product");
   }
+}
+
+// Copy the V panel of far block f into a plain column-major n x k host array.
+void copy_v_out(const hmat* h, int32_t f, int64_t n, int64_t k, double* out) {
+  if (k == 0) return;
+  const PanelShape sh = h->far_vshape[f];
+  std::vector<double> tmp((size_t)sh.ld * k);
+  check(hipMemcpy(tmp.data(), h->far_arena.as<double>() + h->far_voff[f], sizeof(double) * tmp.size(),
+                  hipMemcpyDeviceToHost),
+        "block copy");
+  for (int64_t c = 0; c < k; c++) std::memcpy(out + c * n, tmp.data() + c * sh.ld + sh.fp, sizeof(double) * n);
+}
+
+// Copy block b's U factor or dense matrix (m x cols) out of the stream arena.
+void copy_stream_out(const hmat* h, int32_t b, int64_t m, int64_t cols, double* out, hipStream_t s) {
+  if (cols == 0) return;
+  DevBuf tmp;
+  tmp.alloc(sizeof(double) * m * cols, "block copy");
+  auto tasks = stream_tasks(h, [&](int32_t bb) { return bb == b; }, [&](int32_t) { return tmp.as<double>(); });
+  DevBuf d_t;
+  upload(d_t, tasks, s, "block copy");
+  check(launch_from_stream(d_t.as<StreamTask>(), (int)tasks.size(), h->stream.as<double>(), s), "block copy");
+  check(hipMemcpyAsync(out, tmp.p, sizeof(double) * m * cols, hipMemcpyDeviceToHost, s), "block copy");
+  check(hipStreamSynchronize(s), "block copy");
 }
 
 }  // namespace
@@ -841,16 +904,6 @@ hmat_status hmat_plan(const hmat_mesh* mesh, double eta, int32_t leaf, int32_t* 
   return HMAT_OK;
 }
 
-// Copy a panel (rows [fp, fp + M) of `cols` columns with leading dimension ld)
-// from the device into a plain column-major M x cols host array.
-void copy_panel_out(const double* dev, PanelShape sh, int64_t M, int64_t cols, double* out) {
-  if (cols == 0) return;
-  std::vector<double> tmp((size_t)sh.ld * cols);
-  check(hipMemcpy(tmp.data(), dev, sizeof(double) * tmp.size(), hipMemcpyDeviceToHost), "block copy");
-  for (int64_t c = 0; c < cols; c++)
-    std::memcpy(out + c * M, tmp.data() + c * sh.ld + sh.fp, sizeof(double) * M);
-}
-
 hmat_status hmat_block(hmat_t h, int32_t b, int32_t* info, double* A, double* B, int32_t* prow,
                        int32_t* pcol) {
   if (!h) return fail(HMAT_EINVAL, "handle is NULL");
@@ -871,19 +924,20 @@ hmat_status hmat_block(hmat_t h, int32_t b, int32_t* info, double* A, double* B,
   }
   try {
     if (R.far) {
-      const double* base = h->far_arena.as<double>();
-      if (A) copy_panel_out(base + h->far_uoff[idx], h->far_ushape[idx], m, k, A);
-      if (B) copy_panel_out(base + h->far_voff[idx], h->far_vshape[idx], n, k, B);
+      if (A) copy_stream_out(h, b, m, k, A, nullptr);
+      if (B) copy_v_out(h, idx, n, k, B);
       if (h->piv_ptr[idx] && k) {
         if (prow) check(hipMemcpy(prow, h->piv_ptr[idx], sizeof(int32_t) * k, hipMemcpyDeviceToHost), "pivots");
         if (pcol)
           check(hipMemcpy(pcol, h->piv_ptr[idx] + h->piv_cap[idx], sizeof(int32_t) * k, hipMemcpyDeviceToHost), "pivots");
       }
     } else if (A) {
-      copy_panel_out(h->near_arena.as<double>() + h->near_off[idx], h->near_shape[idx], m, n, A);
+      copy_stream_out(h, b, m, n, A, nullptr);
     }
   } catch (const HipError& e) {
     return fail(e.st, e.msg);
+  } catch (const std::bad_alloc&) {
+    return fail(HMAT_ENOMEM, "host allocation failed");
   }
   return HMAT_OK;
 }
@@ -920,38 +974,61 @@ hmat_status hmat_set_factors(hmat_t h, const int32_t* ranks, const double* U, co
   if (!h || !ranks) return fail(HMAT_EINVAL, "handle or ranks is NULL");
   hipStream_t s = (hipStream_t)hip_stream;
   const size_t nf = h->far_blocks.size();
-  int64_t total = 0;
+  int64_t total = 0, usz = 0;
   for (size_t f = 0; f < nf; f++) {
     const int32_t b = h->far_blocks[f], k = ranks[b];
     if (k < 0 || k > std::min(block_m(h, b), block_n(h, b))) return fail(HMAT_EINVAL, "rank out of range");
     total += k;
+    usz += block_m(h, b) * k;
   }
   if (total > 0 && (!U || !V)) return fail(HMAT_EINVAL, "U or V is NULL");
   try {
     check(hipStreamSynchronize(s), "set factors");
+    // dense blocks back out of the current stream into a plain staging arena
+    std::vector<int64_t> near_off;
+    int64_t noff = 0;
+    for (int32_t b : h->near_blocks) {
+      near_off.push_back(noff);
+      noff += block_m(h, b) * block_n(h, b);
+    }
+    DevBuf near_stage, u_stage;
+    near_stage.alloc(sizeof(double) * std::max<int64_t>(noff, 1), "set factors");
+    {
+      auto tasks = stream_tasks(
+          h, [&](int32_t b) { return !h->plan.blk[b].far; },
+          [&](int32_t b) { return near_stage.as<double>() + near_off[h->kind_index[b]]; });
+      DevBuf d_t;
+      upload(d_t, tasks, s, "set factors");
+      check(launch_from_stream(d_t.as<StreamTask>(), (int)tasks.size(), h->stream.as<double>(), s), "set factors");
+      check(hipStreamSynchronize(s), "set factors");
+    }
     for (size_t f = 0; f < nf; f++) {
       h->rank[f] = ranks[h->far_blocks[f]];
       h->stop[f] = 0;
       h->ratio[f] = 0.0;
       h->piv_ptr[f] = nullptr;
     }
+    // V into the panel layout (host packing), U staged plain column-major
     const int64_t fo = far_layout(h);
     std::vector<double> host(std::max<int64_t>(fo, PANEL_ALIGN), 0.0);
+    u_stage.alloc(sizeof(double) * std::max<int64_t>(usz, 1), "set factors");
+    std::vector<const double*> u_ptr(nf, nullptr);
     int64_t uo = 0, vo = 0;
     for (size_t f = 0; f < nf; f++) {
       const int32_t b = h->far_blocks[f], k = h->rank[f];
       const int64_t m = block_m(h, b), n = block_n(h, b);
-      const PanelShape su = h->far_ushape[f], sv = h->far_vshape[f];
-      for (int32_t c = 0; c < k; c++) {
-        std::memcpy(host.data() + h->far_uoff[f] + (int64_t)c * su.ld + su.fp, U + uo + c * m, sizeof(double) * m);
+      const PanelShape sv = h->far_vshape[f];
+      for (int32_t c = 0; c < k; c++)
         std::memcpy(host.data() + h->far_voff[f] + (int64_t)c * sv.ld + sv.fp, V + vo + c * n, sizeof(double) * n);
-      }
+      u_ptr[f] = u_stage.as<double>() + uo;
       uo += m * k;
       vo += n * k;
     }
+    if (uo > 0) check(hipMemcpy(u_stage.p, U, sizeof(double) * uo, hipMemcpyHostToDevice), "set factors");
     h->far_arena.alloc(sizeof(double) * host.size(), "low-rank arena");
     check(hipMemcpy(h->far_arena.p, host.data(), sizeof(double) * host.size(), hipMemcpyHostToDevice), "set factors");
     build_product_plan(h, s);
+    fill_stream(h, near_stage.as<double>(), near_off, u_ptr, s);
   } catch (const HipError& e) {
     return fail(e.st, e.msg);
   } catch (const std::bad_alloc&) {

@@ -24,13 +24,17 @@ struct DevGeo {
   double c1, c2;
 };
 
-// Panel layout shared by every stored block matrix (U, V and dense D): column
-// major; a panel whose rows are the global DOFs [R0, R0 + M) keeps row i of
-// column c at base + c*ld + fp + i, with fp = R0 mod 16, ld a multiple of 16
-// >= fp + M, and base 128-byte aligned. Global DOF g therefore sits at an
-// address congruent to g modulo 16 doubles: row windows that start at a
-// multiple of 16 map onto whole cache lines. Pad entries are zero.
-constexpr int PANEL_ALIGN = 16;  // doubles (128 bytes)
+// Row alignment of the stored block matrices. A V panel whose rows are the
+// global DOFs [R0, R0 + M) keeps row i of column c at base + c*ld + fp + i,
+// with fp = R0 mod PANEL_ALIGN, ld a multiple of PANEL_ALIGN >= fp + M and base
+// a multiple of PANEL_ALIGN: global DOF g sits at an address congruent to g
+// modulo PANEL_ALIGN doubles, so a lane reads the row pair (2j, 2j+1) with one
+// 16-byte load. The product-order stream widens block row ranges to multiples
+// of STREAM_ALIGN (a 128-byte cache line): each column slice then covers whole
+// lines, which measures faster than the narrower pad despite the extra zero
+// rows. Pad entries are zero.
+constexpr int PANEL_ALIGN = 2;    // doubles (16 bytes)
+constexpr int STREAM_ALIGN = 16;  // doubles (128 bytes)
 
 // Dense (non-admissible) block at d_off in the near arena (m = 3 t_len rows).
 struct NearTask {
@@ -55,14 +59,12 @@ struct AcaTask {
   int32_t blk;    // index into the far-block result arrays
 };
 
-// Compaction: copy the first k columns of the scratch panels into the final
-// arena in the panel layout above.
+// Compaction of the V factors: copy the first k columns of a scratch panel
+// (n x kcap, leading dimension n) into the panel layout above.
 struct CopyTask {
-  const double* srcU;  // m x k, leading dimension m
-  const double* srcV;  // n x k, leading dimension n
-  double* dstU;        // column c, row i at dstU[c*ldu + fpu + i]
-  double* dstV;
-  int32_t m, n, k, ldu, fpu, ldv, fpv, pad;
+  const double* srcV;
+  double* dstV;  // column c, row i at dstV[c*ldv + fpv + i]
+  int32_t n, k, ldv, fpv;
 };
 
 // Product, phase A: z[zoff + l - l0] = V[:, l] . xp[window] for l in [l0, l1).
@@ -73,15 +75,28 @@ struct MvA {
   int32_t zoff, pad;
 };
 
-// Product, phase B: columns [c0, c1) of a panel restricted to the rows
-// [row_lo, row_hi) of a 128-row tile (multiples of 16). The element of tile
-// row L and column c is base[a_off + L + c*ld]; the vector entry for column c
-// is src[soff + c] with src = z (far) or xp (near).
+// Product, phase B. The U factors and the dense blocks are stored in the order
+// phase B reads them ("stream" arena): 128-row tile by tile, and within a tile
+// segment by segment, each segment being one block's rows [row_lo, row_hi) of
+// the tile (multiples of 16) times its columns [c0, c1), column by column. The
+// slice of column c starts at so + (c - c0) * (row_hi - row_lo); the vector
+// entry for column c is src[soff + c] with src = z (far) or xp (near).
 struct MvSeg {
-  int64_t a_off;
-  int32_t ld, c0, c1, soff;
+  int64_t so;
+  int32_t c0, c1, soff;
   int16_t row_lo, row_hi;
-  int32_t far;  // 1: U panel in the far arena, vector z; 0: D in the near arena, vector xp
+  int32_t far;  // 1: low-rank block (vector z); 0: dense block (vector xp)
+  int32_t pad;
+};
+
+// Copy between a plain column-major block matrix (leading dimension ld = its
+// row count m) and one stream segment. Tile row r is block row r0 + r; rows
+// outside [0, m) are zero in the stream.
+struct StreamTask {
+  const double* src;
+  double* dst;
+  int64_t so;
+  int32_t ld, r0, row_lo, row_hi, c0, c1;
 };
 
 struct MvChunk {

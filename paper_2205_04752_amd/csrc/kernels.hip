@@ -418,15 +418,11 @@ __global__ __launch_bounds__(ACA_T) void k_aca(DevGeo g, const AcaTask* __restri
   }
 }
 
-// Final low-rank arena: the first k columns of the scratch panels, copied into
-// the padded panel layout (pads were zeroed with the arena).
+// V factors: the first k columns of the scratch panel, copied into the padded
+// panel layout (pads were zeroed with the arena).
 __global__ __launch_bounds__(256) void k_compact(const CopyTask* __restrict__ tasks) {
   const CopyTask T = tasks[blockIdx.x];
-  const int64_t mu = (int64_t)T.m * T.k, nv = (int64_t)T.n * T.k;
-  for (int64_t e = threadIdx.x; e < mu; e += blockDim.x) {
-    const int64_t c = e / T.m, i = e - c * T.m;
-    T.dstU[c * T.ldu + T.fpu + i] = T.srcU[e];
-  }
+  const int64_t nv = (int64_t)T.n * T.k;
   for (int64_t e = threadIdx.x; e < nv; e += blockDim.x) {
     const int64_t c = e / T.n, i = e - c * T.n;
     T.dstV[c * T.ldv + T.fpv + i] = T.srcV[e];
@@ -470,16 +466,18 @@ __global__ __launch_bounds__(WAVE) void k_mvA(const MvA* __restrict__ items,
 #pragma unroll
       for (int r = 0; r < NR; r++) acc[c][r] = 0.0;
     for (int i = 2 * lane; i < I.ld; i += TILE) {
-      double2 xv[NR];
+      double2 xv[NR], v[CB];
+#pragma unroll
+      for (int c = 0; c < CB; c++)  // columns past l1 re-read the last one (not accumulated)
+        v[c] = *reinterpret_cast<const double2*>(V + (size_t)(l0 + min(c, nc - 1)) * I.ld + i);
 #pragma unroll
       for (int r = 0; r < NR; r++)
         xv[r] = (r < nr) ? *reinterpret_cast<const double2*>(X + r * ldxp + i) : make_double2(0.0, 0.0);
 #pragma unroll
       for (int c = 0; c < CB; c++) {
         if (c < nc) {
-          const double2 v = *reinterpret_cast<const double2*>(V + (size_t)(l0 + c) * I.ld + i);
 #pragma unroll
-          for (int r = 0; r < NR; r++) acc[c][r] += v.x * xv[r].x + v.y * xv[r].y;
+          for (int r = 0; r < NR; r++) acc[c][r] += v[c].x * xv[r].x + v[c].y * xv[r].y;
         }
       }
     }
@@ -494,13 +492,16 @@ __global__ __launch_bounds__(WAVE) void k_mvA(const MvA* __restrict__ items,
 }
 
 // Phase B: one wave per chunk of segments of one 128-row tile; lane L owns tile
-// rows 2L and 2L+1 and reads them with one 16-byte load per column. Writes the
-// chunk's partial sums part[chunk][r][128].
-template <int NR>
+// rows 2L and 2L+1 and reads them with one 16-byte load per column. A chunk's
+// matrix data is one contiguous range of the stream arena. Lanes outside a
+// segment's rows load a clamped in-segment address and discard the value, so
+// the UNR loads of a batch issue back to back. Writes the chunk's partial sums
+// part[chunk][r][128] (summed per tile by k_reduce: a device-wide fence per
+// chunk to let the last chunk reduce in place costs far more than a launch).
+template <int NR, int UNR>
 __global__ __launch_bounds__(WAVE) void k_mvB(const MvChunk* __restrict__ chunks,
                                               const MvSeg* __restrict__ segs,
-                                              const double* __restrict__ far,
-                                              const double* __restrict__ near,
+                                              const double* __restrict__ stream,
                                               const double* __restrict__ z, int64_t ldz,
                                               const double* __restrict__ xp, int64_t ldxp, int nr,
                                               double* __restrict__ part) {
@@ -512,36 +513,54 @@ __global__ __launch_bounds__(WAVE) void k_mvB(const MvChunk* __restrict__ chunks
   for (int s = C.seg_lo; s < C.seg_hi; s++) {
     const MvSeg S = segs[s];
     const bool act = L2 >= S.row_lo && L2 < S.row_hi;
-    const double* __restrict__ A = (S.far ? far : near) + S.a_off + L2;
+    const int Lc = min(max(L2, (int)S.row_lo), (int)S.row_hi - 2);
+    const int len = S.row_hi - S.row_lo;
+    const double* __restrict__ A = stream + S.so + (Lc - S.row_lo) - (int64_t)S.c0 * len;
     const double* __restrict__ src = (S.far ? z : xp) + S.soff;
     const int64_t ld = S.far ? ldz : ldxp;
-    int c = S.c0;
-    for (; c + 8 <= S.c1; c += 8) {
-      double2 a[8];
+    // Full batches of UNR columns, then one masked batch for the remaining
+    // columns (their loads use the last valid column and are not accumulated),
+    // so every batch issues its UNR loads back to back.
+    for (int c = S.c0; c < S.c1; c += UNR) {
+      const int nc = min(UNR, S.c1 - c);
+      double2 a[UNR];
 #pragma unroll
-      for (int u = 0; u < 8; u++)
-        a[u] = act ? *reinterpret_cast<const double2*>(A + (size_t)(c + u) * S.ld) : make_double2(0.0, 0.0);
+      for (int u = 0; u < UNR; u++) {
+        const int cu = (u < nc) ? c + u : S.c1 - 1;
+        a[u] = *reinterpret_cast<const double2*>(A + (int64_t)cu * len);
+      }
 #pragma unroll
-      for (int r = 0; r < NR; r++) {
-        if (r < nr) {
-          const double* sr = src + r * ld + c;
+      for (int u = 0; u < UNR; u++) {
+        a[u].x = act ? a[u].x : 0.0;
+        a[u].y = act ? a[u].y : 0.0;
+      }
+      if (nc == UNR) {
 #pragma unroll
-          for (int u = 0; u < 8; u++) {
-            acc0[r] += a[u].x * sr[u];
-            acc1[r] += a[u].y * sr[u];
+        for (int r = 0; r < NR; r++) {
+          if (r < nr) {
+            const double* sr = src + r * ld + c;
+#pragma unroll
+            for (int u = 0; u < UNR; u++) {
+              acc0[r] += a[u].x * sr[u];
+              acc1[r] += a[u].y * sr[u];
+            }
+          }
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+          if (r < nr) {
+            const double* sr = src + r * ld + c;
+#pragma unroll
+            for (int u = 0; u < UNR; u++) {
+              if (u < nc) {
+                acc0[r] += a[u].x * sr[u];
+                acc1[r] += a[u].y * sr[u];
+              }
+            }
           }
         }
       }
-    }
-    for (; c < S.c1; c++) {
-      const double2 a = act ? *reinterpret_cast<const double2*>(A + (size_t)c * S.ld) : make_double2(0.0, 0.0);
-#pragma unroll
-      for (int r = 0; r < NR; r++)
-        if (r < nr) {
-          const double v = src[r * ld + c];
-          acc0[r] += a.x * v;
-          acc1[r] += a.y * v;
-        }
     }
   }
 #pragma unroll
@@ -572,6 +591,32 @@ __global__ __launch_bounds__(WAVE) void k_reduce(const int32_t* __restrict__ til
     }
     y[r * ldy + d0] = s0;
     if (two) y[r * ldy + d1] = s1;
+  }
+}
+
+// Plain column-major block matrix -> stream segment (one workgroup per segment).
+__global__ __launch_bounds__(256) void k_to_stream(const StreamTask* __restrict__ tasks,
+                                                   double* __restrict__ stream) {
+  const StreamTask T = tasks[blockIdx.x];
+  const int len = T.row_hi - T.row_lo;
+  const int64_t total = (int64_t)len * (T.c1 - T.c0);
+  for (int64_t e = threadIdx.x; e < total; e += blockDim.x) {
+    const int64_t c = T.c0 + e / len;
+    const int i = T.r0 + T.row_lo + (int)(e % len);
+    stream[T.so + e] = (i >= 0 && i < T.ld) ? T.src[c * T.ld + i] : 0.0;
+  }
+}
+
+// Stream segment -> plain column-major block matrix (rows outside [0, m) skipped).
+__global__ __launch_bounds__(256) void k_from_stream(const StreamTask* __restrict__ tasks,
+                                                     const double* __restrict__ stream) {
+  const StreamTask T = tasks[blockIdx.x];
+  const int len = T.row_hi - T.row_lo;
+  const int64_t total = (int64_t)len * (T.c1 - T.c0);
+  for (int64_t e = threadIdx.x; e < total; e += blockDim.x) {
+    const int64_t c = T.c0 + e / len;
+    const int i = T.r0 + T.row_lo + (int)(e % len);
+    if (i >= 0 && i < T.ld) T.dst[c * T.ld + i] = stream[T.so + e];
   }
 }
 
@@ -723,17 +768,26 @@ hipError_t launch_gather(int nr, const double* x, int64_t ldx, const int32_t* or
 
 template <int NR>
 static void mv_group(const MvA* itemsA, int nA, const MvChunk* chunks, int nC, const MvSeg* segs,
-                     const int32_t* tile_chunk, int ntiles, const double* far, const double* near,
-                     const double* xp, int64_t ldxp, int nr, double* z, int64_t ldz, double* part,
-                     const int32_t* order, int64_t N, double* y, int64_t ldy, hipStream_t s,
-                     hipEvent_t* ev) {
+                     const int32_t* tile_chunk, int ntiles, const double* far,
+                     const double* stream, const double* xp, int64_t ldxp, int nr, double* z,
+                     int64_t ldz, double* part, const int32_t* order, int64_t N, double* y,
+                     int64_t ldy, hipStream_t s, hipEvent_t* ev, int unroll) {
   if (nA > 0)
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mvA<NR>), dim3(nA), dim3(WAVE), 0, s, itemsA, far, xp,
                        ldxp, nr, z, ldz);
   if (ev) (void)hipEventRecord(ev[0], s);
-  if (nC > 0)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mvB<NR>), dim3(nC), dim3(WAVE), 0, s, chunks, segs, far,
-                       near, z, ldz, xp, ldxp, nr, part);
+  if (nC > 0) {
+#define HM_MVB(U)                                                                                 \
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mvB<NR, U>), dim3(nC), dim3(WAVE), 0, s, chunks, segs,     \
+                     stream, z, ldz, xp, ldxp, nr, part)
+    if (unroll >= 16)
+      HM_MVB(16);
+    else if (unroll >= 8)
+      HM_MVB(8);
+    else
+      HM_MVB(4);
+#undef HM_MVB
+  }
   if (ev) (void)hipEventRecord(ev[1], s);
   hipLaunchKernelGGL(HIP_KERNEL_NAME(k_reduce<NR>), dim3(ntiles), dim3(WAVE), 0, s, tile_chunk,
                      part, nr, order, N, y, ldy);
@@ -743,25 +797,35 @@ static void mv_group(const MvA* itemsA, int nA, const MvChunk* chunks, int nC, c
 // One pass over the matrix for nr <= 16 right-hand sides (xp already gathered).
 hipError_t launch_matvec_group(int nr, const MvA* itemsA, int nA, const MvChunk* chunks, int nC,
                                const MvSeg* segs, const int32_t* tile_chunk, int ntiles,
-                               const double* far, const double* near, const double* xp,
+                               const double* far, const double* stream, const double* xp,
                                int64_t ldxp, double* z, int64_t ldz, double* part,
                                const int32_t* order, int64_t N, double* y, int64_t ldy,
-                               hipStream_t s, hipEvent_t* ev) {
+                               hipStream_t s, hipEvent_t* ev, int unroll) {
   if (nr <= 1)
-    mv_group<1>(itemsA, nA, chunks, nC, segs, tile_chunk, ntiles, far, near, xp, ldxp, nr, z, ldz, part, order, N, y, ldy, s, ev);
+    mv_group<1>(itemsA, nA, chunks, nC, segs, tile_chunk, ntiles, far, stream, xp, ldxp, nr, z, ldz, part, order, N, y, ldy, s, ev, unroll);
   else if (nr <= 2)
-    mv_group<2>(itemsA, nA, chunks, nC, segs, tile_chunk, ntiles, far, near, xp, ldxp, nr, z, ldz, part, order, N, y, ldy, s, ev);
+    mv_group<2>(itemsA, nA, chunks, nC, segs, tile_chunk, ntiles, far, stream, xp, ldxp, nr, z, ldz, part, order, N, y, ldy, s, ev, unroll);
   else if (nr <= 4)
-    mv_group<4>(itemsA, nA, chunks, nC, segs, tile_chunk, ntiles, far, near, xp, ldxp, nr, z, ldz, part, order, N, y, ldy, s, ev);
+    mv_group<4>(itemsA, nA, chunks, nC, segs, tile_chunk, ntiles, far, stream, xp, ldxp, nr, z, ldz, part, order, N, y, ldy, s, ev, unroll);
   else if (nr <= 8)
-    mv_group<8>(itemsA, nA, chunks, nC, segs, tile_chunk, ntiles, far, near, xp, ldxp, nr, z, ldz, part, order, N, y, ldy, s, ev);
+    mv_group<8>(itemsA, nA, chunks, nC, segs, tile_chunk, ntiles, far, stream, xp, ldxp, nr, z, ldz, part, order, N, y, ldy, s, ev, unroll);
   else
-    mv_group<16>(itemsA, nA, chunks, nC, segs, tile_chunk, ntiles, far, near, xp, ldxp, nr, z, ldz, part, order, N, y, ldy, s, ev);
+    mv_group<16>(itemsA, nA, chunks, nC, segs, tile_chunk, ntiles, far, stream, xp, ldxp, nr, z, ldz, part, order, N, y, ldy, s, ev, unroll);
   return hipGetLastError();
 }
 
 // out[c] = Q[:, c] . w for c < ncols (part: scratch of dots_part_size(n, ncols) doubles).
 size_t dots_part_size(int64_t n, int ncols) { return (size_t)((n + DOT_ROWS - 1) / DOT_ROWS) * ncols; }
+
+hipError_t launch_to_stream(const StreamTask* tasks, int ntasks, double* stream, hipStream_t s) {
+  if (ntasks > 0) hipLaunchKernelGGL(k_to_stream, dim3(ntasks), dim3(256), 0, s, tasks, stream);
+  return hipGetLastError();
+}
+
+hipError_t launch_from_stream(const StreamTask* tasks, int ntasks, const double* stream, hipStream_t s) {
+  if (ntasks > 0) hipLaunchKernelGGL(k_from_stream, dim3(ntasks), dim3(256), 0, s, tasks, stream);
+  return hipGetLastError();
+}
 
 hipError_t launch_dots(const double* Q, int64_t ldq, int64_t n, int ncols, const double* w,
                        double* out, double* part, hipStream_t s) {
