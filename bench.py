@@ -75,6 +75,24 @@ def cpu_baseline(V, T, wl, x0, seconds_hint: float):
     }
 
 
+def measured_traffic(kernel_tag: str):
+    """HBM bytes per launch of `kernel_tag` from the committed rocprofv3 summary,
+    or None if the kernel source changed since the counters were taken."""
+    import hashlib
+    src = os.path.join(ROOT, "paper_2205_04752_amd", "csrc", "kernels.hip")
+    prof = os.path.join(ROOT, "profiles", "hmatvec_icosphere-L5.md")
+    try:
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        for line in open(prof):
+            if line.startswith(f"traffic {kernel_tag} "):
+                f = dict(kv.split("=") for kv in line.split()[3:])
+                if f.get("kernels_sha") == sha:
+                    return int(f["fetch"]) + int(f["write"])
+    except OSError:
+        pass
+    return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -224,9 +242,10 @@ def main():
     kern_ms = float(single_phase[2]) if single_phase is not None else None
     if kern_ms:
         ach = kern_bytes / (kern_ms * 1e-3) / 1e9
+        traffic = measured_traffic("k_mvB<1,16>") if args.workload == "icosphere-L5" else None
         out["roofline"] = {"kernel": "k_mvB (U z + D x)", "bound": "hbm", "achieved": round(ach, 2),
                            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-                           "traffic": None, "bytes_per_launch": kern_bytes,
+                           "traffic": traffic, "bytes_per_launch": kern_bytes,
                            "avg_launch_ms": round(kern_ms, 4)}
     if not args.no_cpu_baseline:
         try:
