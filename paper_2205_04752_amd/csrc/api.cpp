@@ -25,10 +25,8 @@ hipError_t launch_compact(const CopyTask*, int, hipStream_t);
 hipError_t launch_to_stream(const StreamTask*, int, double*, hipStream_t);
 hipError_t launch_from_stream(const StreamTask*, int, const double*, hipStream_t);
 hipError_t launch_gather(int, const double*, int64_t, const int32_t*, int64_t, double*, int64_t, hipStream_t);
-hipError_t launch_matvec_group(int, const MvA*, int, const MvChunk*, int, const MvSeg*, const int32_t*, int,
-                               const double*, const double*, const double*, int64_t, double*, int64_t,
-                               double*, const int32_t*, int64_t, double*, int64_t, hipStream_t,
-                               hipEvent_t*, int);
+hipError_t launch_matvec_group(const ProductPlanDev&, int, const double*, int64_t, double*, int64_t,
+                               double*, double*, int64_t, hipStream_t, hipEvent_t*, int);
 hipError_t launch_dots(const double*, int64_t, int64_t, int, const double*, double*, double*, hipStream_t);
 size_t dots_part_size(int64_t, int);
 hipError_t launch_sub_proj(const double*, int64_t, int64_t, int, const double*, double*, double*, hipStream_t);
@@ -93,7 +91,7 @@ void upload(DevBuf& d, const std::vector<T>& h, hipStream_t s, const char* what)
 constexpr int KCAP_FIRST = 128;  // first-pass panel capacity (columns) of ACA
 constexpr int MV_TILE = 128;     // rows per product tile (one wave, two rows per lane)
 constexpr int MV_SEG_COLS = 128; // columns per product segment
-constexpr int64_t MV_CHUNK_BYTES = 64 * 1024;  // default; HMAT_MV_CHUNK_KB overrides
+constexpr int64_t MV_CHUNK_BYTES = 32 * 1024;  // default; HMAT_MV_CHUNK_KB overrides
 constexpr int MV_MAX_NR = 16;    // right-hand sides per pass over the matrix
 
 inline int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
@@ -136,12 +134,18 @@ struct hmat {
   std::vector<int32_t> piv_cap;
   int aca_passes = 0;
   // product plan
-  DevBuf d_mvA, d_seg, d_chunk, d_tile_chunk;
-  int nA = 0, nSeg = 0, nChunk = 0, nTiles = 0;
+  DevBuf d_mvA, d_seg, d_chunk, d_tile_near, d_tile_far;
+  int nA = 0, nSeg = 0, nChunk = 0, nNearChunk = 0, nTiles = 0;
   int64_t Ztot = 0, ldxp = 0, stream_n = 0;
   std::vector<MvSeg> segs;                       // host copy, product order
   std::vector<int32_t> seg_tile;                 // tile of each segment
-  std::vector<std::vector<int32_t>> block_segs;  // canonical block -> its segments
+  // Where each block's matrix lives in the stream: pieces (block columns
+  // [bc0, bc1) inside segment `seg`, starting at stream offset so).
+  struct Piece {
+    int32_t seg, bc0, bc1;
+    int64_t so;
+  };
+  std::vector<std::vector<Piece>> block_pieces;  // canonical block -> its pieces
   int64_t mv_chunk_bytes = MV_CHUNK_BYTES;       // product tuning (HMAT_MV_CHUNK_KB)
   int mv_unroll = 16;                            // columns per batch in phase B (HMAT_MV_UNROLL)
   DevBuf d_xp, d_z, d_part, d_dotpart;
@@ -205,74 +209,112 @@ void build_product_plan(hmat* h, hipStream_t s) {
     return (int64_t)a.ld * (a.l1 - a.l0) > (int64_t)b.ld * (b.l1 - b.l0);
   });
   h->Ztot = std::max<int64_t>(round_up(z, 2), 2);
-  struct SegT {
-    int32_t tile, block;
-    MvSeg seg;
-  };
-  std::vector<SegT> segs;
-  for (size_t b = 0; b < P.blk.size(); b++) {
-    const BlockRec& B = P.blk[b];
-    const int64_t R0 = 3 * (int64_t)P.cl[B.t].off, m = block_m(h, (int32_t)b);
+  // Column groups: the low-rank blocks of one row cluster (consecutive in
+  // canonical order, so their z entries are contiguous) form one group whose
+  // columns are the concatenation of their ranks; each dense block is a group
+  // of its own. A group's rows are its row cluster's.
+  struct Group {
+    std::vector<int32_t> members;  // canonical blocks, all far or all near, same row cluster
     int64_t ncols, soff;
     int32_t far;
+  };
+  std::vector<Group> groups;
+  std::vector<int64_t> gcol(P.blk.size(), 0);  // block's first column inside its group
+  int32_t last_far_group = -1;
+  for (size_t b = 0; b < P.blk.size(); b++) {
+    const BlockRec& B = P.blk[b];
     if (B.far) {
       const int32_t f = h->kind_index[b];
       if (h->rank[f] == 0) continue;
-      ncols = h->rank[f];
-      soff = zoff[f];
-      far = 1;
+      Group* g = last_far_group >= 0 ? &groups[last_far_group] : nullptr;
+      if (g && P.blk[g->members[0]].t == B.t && g->soff + g->ncols == zoff[f]) {
+        gcol[b] = g->ncols;
+        g->ncols += h->rank[f];
+        g->members.push_back((int32_t)b);
+      } else {
+        groups.push_back(Group{{(int32_t)b}, h->rank[f], zoff[f], 1});
+        last_far_group = (int32_t)groups.size() - 1;
+      }
     } else {
-      ncols = block_n(h, (int32_t)b);
-      soff = 3 * (int64_t)P.cl[B.s].off;
-      far = 0;
+      groups.push_back(Group{{(int32_t)b}, block_n(h, (int32_t)b), 3 * (int64_t)P.cl[B.s].off, 0});
     }
+  }
+  struct SegT {
+    int32_t tile, group;
+    MvSeg seg;
+  };
+  std::vector<SegT> segs;
+  for (size_t gi = 0; gi < groups.size(); gi++) {
+    const Group& g = groups[gi];
+    const BlockRec& B = P.blk[g.members[0]];
+    const int64_t R0 = 3 * (int64_t)P.cl[B.t].off, m = block_m(h, g.members[0]);
     // rows [R0, R0 + m) widened to whole cache lines (zero rows in the stream)
     const int64_t A0 = R0 / STREAM_ALIGN * STREAM_ALIGN, A1 = round_up(R0 + m, STREAM_ALIGN);
     for (int64_t T = A0 / MV_TILE; T * MV_TILE < A1; T++) {
       const int64_t lo = std::max(A0, T * MV_TILE) - T * MV_TILE;
       const int64_t hi = std::min(A1, (T + 1) * MV_TILE) - T * MV_TILE;
-      for (int64_t c0 = 0; c0 < ncols; c0 += MV_SEG_COLS) {
+      for (int64_t c0 = 0; c0 < g.ncols; c0 += MV_SEG_COLS) {
         MvSeg sg{};
         sg.c0 = (int32_t)c0;
-        sg.c1 = (int32_t)std::min<int64_t>(ncols, c0 + MV_SEG_COLS);
-        sg.soff = (int32_t)soff;
+        sg.c1 = (int32_t)std::min<int64_t>(g.ncols, c0 + MV_SEG_COLS);
+        sg.soff = (int32_t)g.soff;
         sg.row_lo = (int16_t)lo;
         sg.row_hi = (int16_t)hi;
-        sg.far = far;
-        segs.push_back(SegT{(int32_t)T, (int32_t)b, sg});
+        sg.far = g.far;
+        segs.push_back(SegT{(int32_t)T, (int32_t)gi, sg});
       }
     }
   }
-  std::stable_sort(segs.begin(), segs.end(), [](const SegT& a, const SegT& b) { return a.tile < b.tile; });
+  // dense-block segments first (launch 1 reads them with the phase-A items),
+  // then low-rank segments; tile order within each group
+  std::stable_sort(segs.begin(), segs.end(), [](const SegT& a, const SegT& b) {
+    if (a.seg.far != b.seg.far) return a.seg.far < b.seg.far;
+    return a.tile < b.tile;
+  });
   h->nTiles = (int)((h->N + MV_TILE - 1) / MV_TILE);
   h->segs.assign(segs.size(), MvSeg{});
   h->seg_tile.assign(segs.size(), 0);
-  h->block_segs.assign(P.blk.size(), {});
+  h->block_pieces.assign(P.blk.size(), {});
   std::vector<MvChunk> chunks;
-  std::vector<int32_t> tile_chunk(h->nTiles + 1, 0);
+  std::vector<int32_t> tile_near(h->nTiles + 1, 0), tile_far(h->nTiles + 1, 0);
   int64_t so = 0;
   size_t i = 0;
-  for (int32_t T = 0; T < h->nTiles; T++) {
-    tile_chunk[T] = (int32_t)chunks.size();
-    while (i < segs.size() && segs[i].tile == T) {
-      MvChunk c{T, (int32_t)i, (int32_t)i, 0};
-      int64_t bytes = 0;
-      while (i < segs.size() && segs[i].tile == T && (bytes < h->mv_chunk_bytes || c.seg_hi == c.seg_lo)) {
-        MvSeg sg = segs[i].seg;
-        const int64_t len = sg.row_hi - sg.row_lo;
-        sg.so = so;
-        so += len * (sg.c1 - sg.c0);
-        bytes += len * (sg.c1 - sg.c0) * 8;
-        h->segs[i] = sg;
-        h->seg_tile[i] = T;
-        h->block_segs[segs[i].block].push_back((int32_t)i);
-        i++;
-        c.seg_hi = (int32_t)i;
+  for (int32_t group = 0; group < 2; group++) {
+    std::vector<int32_t>& tc = group == 0 ? tile_near : tile_far;
+    for (int32_t T = 0; T < h->nTiles; T++) {
+      tc[T] = (int32_t)chunks.size();
+      while (i < segs.size() && segs[i].seg.far == group && segs[i].tile == T) {
+        MvChunk c{T, (int32_t)i, (int32_t)i, 0};
+        int64_t bytes = 0;
+        while (i < segs.size() && segs[i].seg.far == group && segs[i].tile == T &&
+               (bytes < h->mv_chunk_bytes || c.seg_hi == c.seg_lo)) {
+          MvSeg sg = segs[i].seg;
+          const int64_t len = sg.row_hi - sg.row_lo;
+          sg.so = so;
+          so += len * (sg.c1 - sg.c0);
+          bytes += len * (sg.c1 - sg.c0) * 8;
+          h->segs[i] = sg;
+          h->seg_tile[i] = T;
+          const Group& g = groups[segs[i].group];
+          for (int32_t b : g.members) {
+            const int64_t nb = P.blk[b].far ? h->rank[h->kind_index[b]] : block_n(h, b);
+            const int64_t lo_c = std::max<int64_t>(sg.c0, gcol[b]);
+            const int64_t hi_c = std::min<int64_t>(sg.c1, gcol[b] + nb);
+            if (lo_c >= hi_c) continue;
+            h->block_pieces[b].push_back(hmat::Piece{(int32_t)i, (int32_t)(lo_c - gcol[b]),
+                                                     (int32_t)(hi_c - gcol[b]),
+                                                     sg.so + (lo_c - sg.c0) * len});
+          }
+          i++;
+          c.seg_hi = (int32_t)i;
+        }
+        chunks.push_back(c);
       }
-      chunks.push_back(c);
     }
+    tc[h->nTiles] = (int32_t)chunks.size();
+    if (group == 0) h->nNearChunk = (int32_t)chunks.size();
   }
-  tile_chunk[h->nTiles] = (int32_t)chunks.size();
+  if (i != segs.size()) throw HipError{HMAT_EDEVICE, "internal: product plan: segments left over"};
   h->stream_n = std::max<int64_t>(so, PANEL_ALIGN);
   h->ldxp = round_up(h->N, PANEL_ALIGN);
   // Host-side bounds check of every access the product kernels will make.
@@ -294,7 +336,7 @@ void build_product_plan(hmat* h, hipStream_t s) {
     for (const MvChunk& c : chunks)
       if (c.tile < 0 || c.tile >= h->nTiles || c.seg_lo >= c.seg_hi || c.seg_hi > (int32_t)h->segs.size()) bad("chunks");
     for (int32_t T = 0; T < h->nTiles; T++)
-      if (tile_chunk[T + 1] <= tile_chunk[T]) bad("tile without chunks");
+      if (tile_near[T + 1] <= tile_near[T] || tile_far[T + 1] < tile_far[T]) bad("tile chunk ranges");
   }
   h->nA = (int)items.size();
   h->nSeg = (int)h->segs.size();
@@ -302,7 +344,8 @@ void build_product_plan(hmat* h, hipStream_t s) {
   upload(h->d_mvA, items, s, "product plan");
   upload(h->d_seg, h->segs, s, "product plan");
   upload(h->d_chunk, chunks, s, "product plan");
-  upload(h->d_tile_chunk, tile_chunk, s, "product plan");
+  upload(h->d_tile_near, tile_near, s, "product plan");
+  upload(h->d_tile_far, tile_far, s, "product plan");
 
   if (h->d_xp.bytes < sizeof(double) * MV_MAX_NR * h->ldxp) {
     h->d_xp.alloc(sizeof(double) * MV_MAX_NR * h->ldxp, "product workspace");
@@ -314,7 +357,7 @@ void build_product_plan(hmat* h, hipStream_t s) {
   check(hipStreamSynchronize(s), "product plan");
 }
 
-// Stream tasks for every segment of the blocks selected by `want`, with the
+// Stream tasks for every piece of the blocks selected by `want`, with the
 // plain column-major source/destination of each block given by `mat(b)`.
 template <class Want, class Mat>
 std::vector<StreamTask> stream_tasks(const hmat* h, Want want, Mat mat) {
@@ -324,18 +367,18 @@ std::vector<StreamTask> stream_tasks(const hmat* h, Want want, Mat mat) {
     if (!want((int32_t)b)) continue;
     const int64_t R0 = 3 * (int64_t)P.cl[P.blk[b].t].off, m = block_m(h, (int32_t)b);
     double* ptr = mat((int32_t)b);
-    for (int32_t si : h->block_segs[b]) {
-      const MvSeg& sg = h->segs[si];
+    for (const hmat::Piece& pc : h->block_pieces[b]) {
+      const MvSeg& sg = h->segs[pc.seg];
       StreamTask st{};
       st.src = ptr;
       st.dst = ptr;
-      st.so = sg.so;
+      st.so = pc.so;
       st.ld = (int32_t)m;
-      st.r0 = (int32_t)((int64_t)h->seg_tile[si] * MV_TILE - R0);
+      st.r0 = (int32_t)((int64_t)h->seg_tile[pc.seg] * MV_TILE - R0);
       st.row_lo = sg.row_lo;
       st.row_hi = sg.row_hi;
-      st.c0 = sg.c0;
-      st.c1 = sg.c1;
+      st.c0 = pc.bc0;
+      st.c1 = pc.bc1;
       t.push_back(st);
     }
   }
@@ -381,7 +424,7 @@ void fill_stats(hmat* h) {
   st.device_bytes = (int64_t)(h->d_cen.bytes + h->d_q.bytes + h->d_vtx.bytes + h->d_gl.bytes +
                               h->d_order.bytes + h->far_arena.bytes + h->stream.bytes +
                               h->piv1.bytes + h->piv2.bytes + h->d_mvA.bytes + h->d_seg.bytes +
-                              h->d_chunk.bytes + h->d_tile_chunk.bytes + h->d_xp.bytes +
+                              h->d_chunk.bytes + h->d_tile_near.bytes + h->d_tile_far.bytes + h->d_xp.bytes +
                               h->d_z.bytes + h->d_part.bytes + h->d_dotpart.bytes + h->d_Q.bytes +
                               h->d_w.bytes + h->d_small.bytes);
 }
@@ -675,12 +718,23 @@ void matvec_impl(hmat* h, int32_t nrhs, const double* x, int64_t ldx, double* y,
                         h->ldxp, s),
           "gather");
     if (ev) check(hipEventRecord(ev[1], s), "profile");
-    check(launch_matvec_group(nr, h->d_mvA.as<MvA>(), h->nA, h->d_chunk.as<MvChunk>(), h->nChunk,
-                              h->d_seg.as<MvSeg>(), h->d_tile_chunk.as<int32_t>(), h->nTiles,
-                              h->far_arena.as<double>(), h->stream.as<double>(), h->d_xp.as<double>(),
-                              h->ldxp, h->d_z.as<double>(), h->Ztot, h->d_part.as<double>(),
-                              h->d_order.as<int32_t>(), h->N, y + r0 * ldy, ldy, s,
-                              ev ? ev + 2 : nullptr, h->mv_unroll),
+    ProductPlanDev P{};
+    P.items = h->d_mvA.as<MvA>();
+    P.chunks = h->d_chunk.as<MvChunk>();
+    P.segs = h->d_seg.as<MvSeg>();
+    P.tile_near = h->d_tile_near.as<int32_t>();
+    P.tile_far = h->d_tile_far.as<int32_t>();
+    P.order = h->d_order.as<int32_t>();
+    P.far = h->far_arena.as<double>();
+    P.stream = h->stream.as<double>();
+    P.nA = h->nA;
+    P.n_near_chunks = h->nNearChunk;
+    P.n_far_chunks = h->nChunk - h->nNearChunk;
+    P.ntiles = h->nTiles;
+    P.N = h->N;
+    check(launch_matvec_group(P, nr, h->d_xp.as<double>(), h->ldxp, h->d_z.as<double>(), h->Ztot,
+                              h->d_part.as<double>(), y + r0 * ldy, ldy, s, ev ? ev + 2 : nullptr,
+                              h->mv_unroll),
           "product");
   }
 }

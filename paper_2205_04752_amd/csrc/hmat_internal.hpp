@@ -103,6 +103,21 @@ struct MvChunk {
   int32_t tile, seg_lo, seg_hi, pad;
 };
 
+// Device pointers and sizes of a product plan (passed to the launchers).
+// Chunks: dense-block chunks [0, n_near_chunks), then low-rank chunks.
+struct ProductPlanDev {
+  const MvA* items;
+  const MvChunk* chunks;
+  const MvSeg* segs;
+  const int32_t* tile_near;  // [ntiles + 1] chunk ranges per tile
+  const int32_t* tile_far;   // [ntiles + 1]
+  const int32_t* order;
+  const double* far;         // V panels
+  const double* stream;      // U factors and dense blocks in product order
+  int32_t nA, n_near_chunks, n_far_chunks, ntiles;
+  int64_t N;
+};
+
 // ----------------------------------------------------------------------------
 // Host planner (planner.cpp).
 

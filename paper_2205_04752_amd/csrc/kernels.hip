@@ -4,7 +4,7 @@
 //   K2  k_aca             ACA with partial pivoting on every admissible block
 //                         (Sec. 2.2, Algorithm 1), one workgroup per block
 //   --  k_compact         final low-rank arena (first k columns of the panels)
-//   K3  k_gather, k_mvA, k_mvB, k_reduce
+//   K3  k_gather, k_mv1 (V^T x and dense blocks), k_mv2 (U z), k_reduce
 //                         y = sum U_b (V_b^T x_s) + sum D_b x_s (Sec. 2)
 //   --  GMRES helpers     dots, column updates, norms
 //
@@ -444,18 +444,16 @@ __global__ void k_gather(int nr, const double* __restrict__ x, int64_t ldx,
 
 constexpr int TILE = 2 * WAVE;  // rows per product tile: two rows per lane
 
-// Phase A: z = V_b^T x_s for a group of <= 8 columns; one wave per item. Lanes
+// Phase A item: z = V_b^T x_s for a group of <= 8 columns; one wave. Lanes
 // cover the aligned row window of V two rows at a time (16-byte loads of V and
 // of the gathered x; pad rows of V are zero); NR right-hand sides at once,
 // columns in sub-batches of CB.
 template <int NR>
-__global__ __launch_bounds__(WAVE) void k_mvA(const MvA* __restrict__ items,
-                                              const double* __restrict__ far,
-                                              const double* __restrict__ xp, int64_t ldxp, int nr,
-                                              double* __restrict__ z, int64_t ldz) {
+__device__ __forceinline__ void mv_a_item(const MvA& I, const double* __restrict__ far,
+                                          const double* __restrict__ xp, int64_t ldxp, int nr,
+                                          double* __restrict__ z, int64_t ldz) {
   constexpr int CB = (NR >= 16) ? 2 : ((NR >= 8) ? 4 : 8);
-  const MvA I = items[blockIdx.x];
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & (WAVE - 1);
   const double* __restrict__ V = far + I.v_off;
   const double* __restrict__ X = xp + I.a0;
   for (int l0 = I.l0; l0 < I.l1; l0 += CB) {
@@ -491,22 +489,20 @@ __global__ __launch_bounds__(WAVE) void k_mvA(const MvA* __restrict__ items,
   }
 }
 
-// Phase B: one wave per chunk of segments of one 128-row tile; lane L owns tile
-// rows 2L and 2L+1 and reads them with one 16-byte load per column. A chunk's
-// matrix data is one contiguous range of the stream arena. Lanes outside a
-// segment's rows load a clamped in-segment address and discard the value, so
-// the UNR loads of a batch issue back to back. Writes the chunk's partial sums
-// part[chunk][r][128] (summed per tile by k_reduce: a device-wide fence per
-// chunk to let the last chunk reduce in place costs far more than a launch).
+// Phase B chunk: segments of one 128-row tile; lane L owns tile rows 2L and
+// 2L+1 and reads them with one 16-byte load per column. A chunk's matrix data
+// is one contiguous range of the stream arena. Lanes outside a segment's rows
+// load a clamped in-segment address and discard the value; a segment's last
+// partial batch re-reads its last column without accumulating it -- so every
+// batch issues its UNR loads back to back. Writes part[chunk][r][128].
 template <int NR, int UNR>
-__global__ __launch_bounds__(WAVE) void k_mvB(const MvChunk* __restrict__ chunks,
-                                              const MvSeg* __restrict__ segs,
-                                              const double* __restrict__ stream,
-                                              const double* __restrict__ z, int64_t ldz,
-                                              const double* __restrict__ xp, int64_t ldxp, int nr,
-                                              double* __restrict__ part) {
-  const MvChunk C = chunks[blockIdx.x];
-  const int L2 = 2 * threadIdx.x;
+__device__ __forceinline__ void mv_b_chunk(const MvChunk& C, int chunk,
+                                           const MvSeg* __restrict__ segs,
+                                           const double* __restrict__ stream,
+                                           const double* __restrict__ z, int64_t ldz,
+                                           const double* __restrict__ xp, int64_t ldxp, int nr,
+                                           double* __restrict__ part) {
+  const int L2 = 2 * (threadIdx.x & (WAVE - 1));
   double acc0[NR], acc1[NR];
 #pragma unroll
   for (int r = 0; r < NR; r++) acc0[r] = acc1[r] = 0.0;
@@ -518,9 +514,6 @@ __global__ __launch_bounds__(WAVE) void k_mvB(const MvChunk* __restrict__ chunks
     const double* __restrict__ A = stream + S.so + (Lc - S.row_lo) - (int64_t)S.c0 * len;
     const double* __restrict__ src = (S.far ? z : xp) + S.soff;
     const int64_t ld = S.far ? ldz : ldxp;
-    // Full batches of UNR columns, then one masked batch for the remaining
-    // columns (their loads use the last valid column and are not accumulated),
-    // so every batch issues its UNR loads back to back.
     for (int c = S.c0; c < S.c1; c += UNR) {
       const int nc = min(UNR, S.c1 - c);
       double2 a[UNR];
@@ -566,32 +559,49 @@ __global__ __launch_bounds__(WAVE) void k_mvB(const MvChunk* __restrict__ chunks
 #pragma unroll
   for (int r = 0; r < NR; r++)
     if (r < nr)
-      *reinterpret_cast<double2*>(part + ((size_t)blockIdx.x * NR + r) * TILE + L2) = make_double2(acc0[r], acc1[r]);
+      *reinterpret_cast<double2*>(part + ((size_t)chunk * NR + r) * TILE + L2) = make_double2(acc0[r], acc1[r]);
 }
 
-// Sum the partials of each tile in chunk order and scatter to the caller's order.
-template <int NR>
-__global__ __launch_bounds__(WAVE) void k_reduce(const int32_t* __restrict__ tile_chunk,
-                                                 const double* __restrict__ part, int nr,
-                                                 const int32_t* __restrict__ order, int64_t N,
-                                                 double* __restrict__ y, int64_t ldy) {
-  const int tile = blockIdx.x, L2 = 2 * threadIdx.x;
-  const int64_t row = (int64_t)tile * TILE + L2;
-  if (row >= N) return;
-  const int c0 = tile_chunk[tile], c1 = tile_chunk[tile + 1];
-  const int64_t d0 = 3 * (int64_t)order[row / 3] + row % 3;
-  const bool two = row + 1 < N;
-  const int64_t d1 = two ? 3 * (int64_t)order[(row + 1) / 3] + (row + 1) % 3 : 0;
-  for (int r = 0; r < nr; r++) {
-    double s0 = 0.0, s1 = 0.0;
-    for (int c = c0; c < c1; c++) {
-      const double2 p = *reinterpret_cast<const double2*>(part + ((size_t)c * NR + r) * TILE + L2);
-      s0 += p.x;
-      s1 += p.y;
-    }
-    y[r * ldy + d0] = s0;
-    if (two) y[r * ldy + d1] = s1;
+// Work units (phase-A items, chunks) go one per wave; MV_WPB independent waves
+// share a workgroup (no LDS, no barriers) so more waves fit on a CU.
+constexpr int MV_WPB = 1;
+
+// Product launch 1: the phase-A items (largest first) and the dense-block
+// chunks, which do not depend on z, in one grid so that neither leaves the
+// other's tail idle.
+template <int NR, int UNR>
+__global__ __launch_bounds__(WAVE* MV_WPB) void k_mv1(const MvA* __restrict__ items, int nA,
+                                                      int n_near_chunks,
+                                                      const MvChunk* __restrict__ chunks,
+                                                      const MvSeg* __restrict__ segs,
+                                                      const double* __restrict__ far,
+                                                      const double* __restrict__ stream,
+                                                      const double* __restrict__ xp, int64_t ldxp,
+                                                      int nr, double* __restrict__ z, int64_t ldz,
+                                                      double* __restrict__ part) {
+  // wave-uniform unit index: keeps descriptors and vector entries in scalar loads
+  const int u = __builtin_amdgcn_readfirstlane(blockIdx.x * MV_WPB + threadIdx.x / WAVE);
+  if (u < nA) {
+    mv_a_item<NR>(items[u], far, xp, ldxp, nr, z, ldz);
+  } else if (u < nA + n_near_chunks) {
+    const int c = u - nA;
+    mv_b_chunk<NR, UNR>(chunks[c], c, segs, stream, z, ldz, xp, ldxp, nr, part);
   }
+}
+
+// Product launch 2: the low-rank chunks (U z), chunk ids c_first + unit.
+template <int NR, int UNR>
+__global__ __launch_bounds__(WAVE* MV_WPB) void k_mv2(int c_first, int n,
+                                                      const MvChunk* __restrict__ chunks,
+                                                      const MvSeg* __restrict__ segs,
+                                                      const double* __restrict__ stream,
+                                                      const double* __restrict__ z, int64_t ldz,
+                                                      const double* __restrict__ xp, int64_t ldxp,
+                                                      int nr, double* __restrict__ part) {
+  const int u = __builtin_amdgcn_readfirstlane(blockIdx.x * MV_WPB + threadIdx.x / WAVE);
+  if (u >= n) return;
+  const int c = c_first + u;
+  mv_b_chunk<NR, UNR>(chunks[c], c, segs, stream, z, ldz, xp, ldxp, nr, part);
 }
 
 // Plain column-major block matrix -> stream segment (one workgroup per segment).
@@ -617,6 +627,39 @@ __global__ __launch_bounds__(256) void k_from_stream(const StreamTask* __restric
     const int64_t c = T.c0 + e / len;
     const int i = T.r0 + T.row_lo + (int)(e % len);
     if (i >= 0 && i < T.ld) T.dst[c * T.ld + i] = stream[T.so + e];
+  }
+}
+
+// Sum the partials of each tile -- its dense-block chunks, then its low-rank
+// chunks, each in chunk order -- and scatter to the caller's order.
+template <int NR>
+__global__ __launch_bounds__(WAVE) void k_reduce(const int32_t* __restrict__ tile_near,
+                                                 const int32_t* __restrict__ tile_far,
+                                                 const double* __restrict__ part, int nr,
+                                                 const int32_t* __restrict__ order, int64_t N,
+                                                 double* __restrict__ y, int64_t ldy) {
+  const int tile = blockIdx.x, L2 = 2 * threadIdx.x;
+  const int64_t row = (int64_t)tile * TILE + L2;
+  if (row >= N) return;
+  const int n0 = tile_near[tile], n1 = tile_near[tile + 1];
+  const int f0 = tile_far[tile], f1 = tile_far[tile + 1];
+  const int64_t d0 = 3 * (int64_t)order[row / 3] + row % 3;
+  const bool two = row + 1 < N;
+  const int64_t d1 = two ? 3 * (int64_t)order[(row + 1) / 3] + (row + 1) % 3 : 0;
+  for (int r = 0; r < nr; r++) {
+    double s0 = 0.0, s1 = 0.0;
+    for (int c = n0; c < n1; c++) {
+      const double2 p = *reinterpret_cast<const double2*>(part + ((size_t)c * NR + r) * TILE + L2);
+      s0 += p.x;
+      s1 += p.y;
+    }
+    for (int c = f0; c < f1; c++) {
+      const double2 p = *reinterpret_cast<const double2*>(part + ((size_t)c * NR + r) * TILE + L2);
+      s0 += p.x;
+      s1 += p.y;
+    }
+    y[r * ldy + d0] = s0;
+    if (two) y[r * ldy + d1] = s1;
   }
 }
 
@@ -766,56 +809,50 @@ hipError_t launch_gather(int nr, const double* x, int64_t ldx, const int32_t* or
   return hipGetLastError();
 }
 
-template <int NR>
-static void mv_group(const MvA* itemsA, int nA, const MvChunk* chunks, int nC, const MvSeg* segs,
-                     const int32_t* tile_chunk, int ntiles, const double* far,
-                     const double* stream, const double* xp, int64_t ldxp, int nr, double* z,
-                     int64_t ldz, double* part, const int32_t* order, int64_t N, double* y,
-                     int64_t ldy, hipStream_t s, hipEvent_t* ev, int unroll) {
-  if (nA > 0)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mvA<NR>), dim3(nA), dim3(WAVE), 0, s, itemsA, far, xp,
-                       ldxp, nr, z, ldz);
+template <int NR, int UNR>
+static void mv_group(const ProductPlanDev& P, const double* xp, int64_t ldxp, int nr, double* z,
+                     int64_t ldz, double* part, double* y, int64_t ldy, hipStream_t s,
+                     hipEvent_t* ev) {
+  const int n1 = P.nA + P.n_near_chunks;
+  if (n1 > 0)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mv1<NR, UNR>), dim3((n1 + MV_WPB - 1) / MV_WPB),
+                       dim3(WAVE * MV_WPB), 0, s, P.items, P.nA, P.n_near_chunks, P.chunks, P.segs,
+                       P.far, P.stream, xp, ldxp, nr, z, ldz, part);
   if (ev) (void)hipEventRecord(ev[0], s);
-  if (nC > 0) {
-#define HM_MVB(U)                                                                                 \
-  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mvB<NR, U>), dim3(nC), dim3(WAVE), 0, s, chunks, segs,     \
-                     stream, z, ldz, xp, ldxp, nr, part)
-    if (unroll >= 16)
-      HM_MVB(16);
-    else if (unroll >= 8)
-      HM_MVB(8);
-    else
-      HM_MVB(4);
-#undef HM_MVB
-  }
+  if (P.n_far_chunks > 0)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mv2<NR, UNR>), dim3((P.n_far_chunks + MV_WPB - 1) / MV_WPB),
+                       dim3(WAVE * MV_WPB), 0, s, P.n_near_chunks, P.n_far_chunks, P.chunks, P.segs,
+                       P.stream, z, ldz, xp, ldxp, nr, part);
   if (ev) (void)hipEventRecord(ev[1], s);
-  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_reduce<NR>), dim3(ntiles), dim3(WAVE), 0, s, tile_chunk,
-                     part, nr, order, N, y, ldy);
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_reduce<NR>), dim3(P.ntiles), dim3(WAVE), 0, s, P.tile_near,
+                     P.tile_far, part, nr, P.order, P.N, y, ldy);
   if (ev) (void)hipEventRecord(ev[2], s);
 }
 
 // One pass over the matrix for nr <= 16 right-hand sides (xp already gathered).
-hipError_t launch_matvec_group(int nr, const MvA* itemsA, int nA, const MvChunk* chunks, int nC,
-                               const MvSeg* segs, const int32_t* tile_chunk, int ntiles,
-                               const double* far, const double* stream, const double* xp,
-                               int64_t ldxp, double* z, int64_t ldz, double* part,
-                               const int32_t* order, int64_t N, double* y, int64_t ldy,
+hipError_t launch_matvec_group(const ProductPlanDev& P, int nr, const double* xp, int64_t ldxp,
+                               double* z, int64_t ldz, double* part, double* y, int64_t ldy,
                                hipStream_t s, hipEvent_t* ev, int unroll) {
+#define HM_GROUP(R)                                                            \
+  do {                                                                         \
+    if (unroll >= 16)                                                          \
+      mv_group<R, 16>(P, xp, ldxp, nr, z, ldz, part, y, ldy, s, ev);           \
+    else                                                                       \
+      mv_group<R, 8>(P, xp, ldxp, nr, z, ldz, part, y, ldy, s, ev);            \
+  } while (0)
   if (nr <= 1)
-    mv_group<1>(itemsA, nA, chunks, nC, segs, tile_chunk, ntiles, far, stream, xp, ldxp, nr, z, ldz, part, order, N, y, ldy, s, ev, unroll);
+    HM_GROUP(1);
   else if (nr <= 2)
-    mv_group<2>(itemsA, nA, chunks, nC, segs, tile_chunk, ntiles, far, stream, xp, ldxp, nr, z, ldz, part, order, N, y, ldy, s, ev, unroll);
+    HM_GROUP(2);
   else if (nr <= 4)
-    mv_group<4>(itemsA, nA, chunks, nC, segs, tile_chunk, ntiles, far, stream, xp, ldxp, nr, z, ldz, part, order, N, y, ldy, s, ev, unroll);
+    HM_GROUP(4);
   else if (nr <= 8)
-    mv_group<8>(itemsA, nA, chunks, nC, segs, tile_chunk, ntiles, far, stream, xp, ldxp, nr, z, ldz, part, order, N, y, ldy, s, ev, unroll);
+    HM_GROUP(8);
   else
-    mv_group<16>(itemsA, nA, chunks, nC, segs, tile_chunk, ntiles, far, stream, xp, ldxp, nr, z, ldz, part, order, N, y, ldy, s, ev, unroll);
+    HM_GROUP(16);
+#undef HM_GROUP
   return hipGetLastError();
 }
-
-// out[c] = Q[:, c] . w for c < ncols (part: scratch of dots_part_size(n, ncols) doubles).
-size_t dots_part_size(int64_t n, int ncols) { return (size_t)((n + DOT_ROWS - 1) / DOT_ROWS) * ncols; }
 
 hipError_t launch_to_stream(const StreamTask* tasks, int ntasks, double* stream, hipStream_t s) {
   if (ntasks > 0) hipLaunchKernelGGL(k_to_stream, dim3(ntasks), dim3(256), 0, s, tasks, stream);
@@ -826,6 +863,9 @@ hipError_t launch_from_stream(const StreamTask* tasks, int ntasks, const double*
   if (ntasks > 0) hipLaunchKernelGGL(k_from_stream, dim3(ntasks), dim3(256), 0, s, tasks, stream);
   return hipGetLastError();
 }
+
+// out[c] = Q[:, c] . w for c < ncols (part: scratch of dots_part_size(n, ncols) doubles).
+size_t dots_part_size(int64_t n, int ncols) { return (size_t)((n + DOT_ROWS - 1) / DOT_ROWS) * ncols; }
 
 hipError_t launch_dots(const double* Q, int64_t ldq, int64_t n, int ncols, const double* w,
                        double* out, double* part, hipStream_t s) {
