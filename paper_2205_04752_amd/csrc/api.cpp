@@ -27,10 +27,12 @@ hipError_t launch_from_stream(const StreamTask*, int, const double*, hipStream_t
 hipError_t launch_gather(int, const double*, int64_t, const int32_t*, int64_t, double*, int64_t, hipStream_t);
 hipError_t launch_matvec_group(const ProductPlanDev&, int, const double*, int64_t, double*, int64_t,
                                double*, double*, int64_t, hipStream_t, hipEvent_t*, int);
-hipError_t launch_dots(const double*, int64_t, int64_t, int, const double*, double*, double*, hipStream_t);
+int launch_dots_part(const double*, int64_t, int64_t, int, const double*, double*, hipStream_t);
 size_t dots_part_size(int64_t, int);
-hipError_t launch_sub_proj(const double*, int64_t, int64_t, int, const double*, double*, double*, hipStream_t);
-hipError_t launch_norm(const double*, int64_t, double*, hipStream_t);
+size_t norm_part_size(int64_t);
+hipError_t launch_proj(const double*, int64_t, int64_t, int, const double*, int, double*, double*, int, double*, hipStream_t);
+hipError_t launch_norm(const double*, int64_t, double*, double*, hipStream_t);
+hipError_t launch_norm_final(const double*, int64_t, double*, hipStream_t);
 hipError_t launch_scale(const double*, int64_t, const double*, double*, hipStream_t);
 hipError_t launch_add_comb(const double*, int64_t, int64_t, int, const double*, double*, hipStream_t);
 hipError_t launch_residual(const double*, int64_t, double*, hipStream_t);
@@ -152,6 +154,8 @@ struct hmat {
   // GMRES workspace
   DevBuf d_Q, d_w, d_small;
   int q_cols = 0;
+  double* h_pinned = nullptr;  // [2][1026] Hessenberg columns read back; [1026..] Givens solution
+  hipEvent_t col_ev[2] = {nullptr, nullptr};
   // product profiling: 5 events per recorded group (start, gathered, V^T x, U z + D x, done)
   bool prof = false;
   std::vector<std::array<hipEvent_t, 5>> prof_pending;
@@ -161,6 +165,9 @@ struct hmat {
   ~hmat() {
     for (auto& e : prof_pending)
       for (hipEvent_t x : e) (void)hipEventDestroy(x);
+    for (hipEvent_t e : col_ev)
+      if (e) (void)hipEventDestroy(e);
+    if (h_pinned) (void)hipHostFree(h_pinned);
   }
 };
 
@@ -813,34 +820,58 @@ hmat_status hmat_solve(hmat_t h, const double* b, double* x, double tol, int32_t
   auto t0 = std::chrono::steady_clock::now();
   const int64_t N = h->N;
   const int m = restart;
+  constexpr int COL = 1026;  // stride of a Hessenberg column buffer (restart <= 1024)
   try {
     if (h->q_cols < m + 1) {
       h->d_Q.alloc(sizeof(double) * N * (m + 1), "GMRES basis");
       h->q_cols = m + 1;
     }
     if (!h->d_w.p) h->d_w.alloc(sizeof(double) * N, "GMRES work");
-    if (h->d_dotpart.bytes < sizeof(double) * dots_part_size(N, m + 1))
-      h->d_dotpart.alloc(sizeof(double) * dots_part_size(N, m + 1), "GMRES work");
-    if (h->d_small.bytes < sizeof(double) * (3 * 1026 + 8)) h->d_small.alloc(sizeof(double) * (3 * 1026 + 8), "GMRES work");
+    const size_t dp = dots_part_size(N, m + 1), np = norm_part_size(N);
+    if (h->d_dotpart.bytes < sizeof(double) * (dp + np)) h->d_dotpart.alloc(sizeof(double) * (dp + np), "GMRES work");
+    double* dotpart = h->d_dotpart.as<double>();
+    double* normpart = dotpart + dp;
+    if (h->d_small.bytes < sizeof(double) * (4 * COL + 8)) h->d_small.alloc(sizeof(double) * (4 * COL + 8), "GMRES work");
+    if (!h->h_pinned) check(hipHostMalloc((void**)&h->h_pinned, sizeof(double) * 3 * COL), "GMRES host buffer");
+    for (hipEvent_t& e : h->col_ev)
+      if (!e) check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "GMRES event");
     double* Q = h->d_Q.as<double>();
     double* w = h->d_w.as<double>();
-    double* hdot = h->d_small.as<double>();        // [m+1] projections of one pass
-    double* hacc = hdot + 1026;                      // [m+2] accumulated Hessenberg column
-    double* ycoef = hacc + 1026;                     // [m]
-    double* scal = ycoef + 1026;                     // scalars
+    double* base = h->d_small.as<double>();
+    double* hacc[2] = {base + COL, base + 2 * COL};  // Hessenberg columns, double-buffered
+    double* ycoef = base + 3 * COL;                  // [m]
+    double* scal = ycoef + COL;                      // scalars
+    double* hcol_host[2] = {h->h_pinned, h->h_pinned + COL};
+    double* y_host = h->h_pinned + 2 * COL;
     auto norm_host = [&](const double* v) {
-      check(launch_norm(v, N, scal, s), "norm");
-      double r = 0;
-      check(hipMemcpyAsync(&r, scal, sizeof(double), hipMemcpyDeviceToHost, s), "norm");
+      check(launch_norm(v, N, normpart, scal, s), "norm");
+      check(hipMemcpyAsync(y_host, scal, sizeof(double), hipMemcpyDeviceToHost, s), "norm");
       check(hipStreamSynchronize(s), "norm");
-      return r;
+      return y_host[0];
+    };
+    // One Arnoldi step j: w = A q_j, two classical Gram-Schmidt passes against
+    // q_0..q_j (Hessenberg column in hacc[j % 2]), q_{j+1} = w / ||w||, and an
+    // asynchronous copy of the column to pinned host memory (event col_ev[j % 2]).
+    auto enqueue_step = [&](int j) {
+      double* col = hacc[j % 2];
+      matvec_impl(h, 1, Q + (size_t)j * N, N, w, N, s);
+      for (int pass = 0; pass < 2; pass++) {
+        const int nblk = launch_dots_part(Q, N, N, j + 1, w, dotpart, s);
+        check(launch_proj(Q, N, N, j + 1, dotpart, nblk, w, col, pass == 0, pass == 1 ? normpart : nullptr, s),
+              "project");
+      }
+      check(launch_norm_final(normpart, N, col + j + 1, s), "norm");
+      check(launch_scale(w, N, col + j + 1, Q + (size_t)(j + 1) * N, s), "scale");
+      check(hipMemcpyAsync(hcol_host[j % 2], col, sizeof(double) * (j + 2), hipMemcpyDeviceToHost, s),
+            "hessenberg");
+      check(hipEventRecord(h->col_ev[j % 2], s), "hessenberg");
     };
     check(launch_fill(x, N, 0.0, s), "fill");
     const double bn = norm_host(b);
-    int total = 0, restarts = 0;
+    int used = 0, launched = 0, restarts = 0;
     double rel = 0.0;
     hmat_status status = HMAT_ENOCONV;
-    std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1), yv(m), col(m + 2);
+    std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1), yv(m);
     if (bn == 0.0) {
       status = HMAT_OK;
       rel = 0.0;
@@ -854,23 +885,25 @@ hmat_status hmat_solve(hmat_t h, const double* b, double* x, double tol, int32_t
           status = HMAT_OK;
           break;
         }
-        if (total >= maxit) break;
+        if (launched >= maxit) break;
         check(launch_scale(w, N, scal, Q, s), "scale");  // scal[0] = ||r|| from norm_host
         std::fill(g.begin(), g.end(), 0.0);
         g[0] = beta;
+        // Pipelined Arnoldi: step j+1 is enqueued before the host waits for
+        // column j (it needs only device data), so the host's Givens update
+        // overlaps the device's next product. A step enqueued past convergence
+        // is discarded.
+        enqueue_step(0);
+        launched++;
         int j = 0;
-        for (; j < m && total < maxit;) {
-          matvec_impl(h, 1, Q + (size_t)j * N, N, w, N, s);
-          total++;
-          check(launch_fill(hacc, j + 2, 0.0, s), "fill");
-          for (int pass = 0; pass < 2; pass++) {
-            check(launch_dots(Q, N, N, j + 1, w, hdot, h->d_dotpart.as<double>(), s), "dots");
-            check(launch_sub_proj(Q, N, N, j + 1, hdot, w, hacc, s), "project");
+        for (;;) {
+          const bool more = (j + 1 < m) && (launched < maxit);
+          if (more) {
+            enqueue_step(j + 1);
+            launched++;
           }
-          check(launch_norm(w, N, hacc + j + 1, s), "norm");
-          check(launch_scale(w, N, hacc + j + 1, Q + (size_t)(j + 1) * N, s), "scale");
-          check(hipMemcpyAsync(col.data(), hacc, sizeof(double) * (j + 2), hipMemcpyDeviceToHost, s), "hessenberg");
-          check(hipStreamSynchronize(s), "hessenberg");
+          check(hipEventSynchronize(h->col_ev[j % 2]), "hessenberg");
+          const double* col = hcol_host[j % 2];
           for (int i = 0; i <= j + 1; i++) H[(size_t)i * m + j] = col[i];
           const double hn = col[j + 1];
           for (int i = 0; i < j; i++) {
@@ -887,21 +920,25 @@ hmat_status hmat_solve(hmat_t h, const double* b, double* x, double tol, int32_t
           g[j + 1] = -sn[j] * g[j];
           g[j] = cs[j] * g[j];
           j++;
-          if (std::fabs(g[j]) <= tol * bn || hn == 0.0) break;
+          used++;
+          if (std::fabs(g[j]) <= tol * bn || hn == 0.0 || !more) break;
         }
         for (int i = j - 1; i >= 0; i--) {
           double sum = g[i];
           for (int q = i + 1; q < j; q++) sum -= H[(size_t)i * m + q] * yv[q];
           yv[i] = sum / H[(size_t)i * m + i];
         }
-        check(hipMemcpyAsync(ycoef, yv.data(), sizeof(double) * j, hipMemcpyHostToDevice, s), "update");
+        // the pinned buffer is free again once the stream passes this copy
+        check(hipStreamSynchronize(s), "update");
+        std::memcpy(y_host, yv.data(), sizeof(double) * j);
+        check(hipMemcpyAsync(ycoef, y_host, sizeof(double) * j, hipMemcpyHostToDevice, s), "update");
         check(launch_add_comb(Q, N, N, j, ycoef, x, s), "update");
         restarts++;
       }
     }
     check(hipStreamSynchronize(s), "solve");
     if (info) {
-      info->iterations = total;
+      info->iterations = used;
       info->restarts = restarts;
       info->relres = rel;
       info->time_ms = ms_since(t0);
@@ -909,6 +946,7 @@ hmat_status hmat_solve(hmat_t h, const double* b, double* x, double tol, int32_t
     if (status != HMAT_OK) return fail(status, "GMRES reached maxit before tol");
     return HMAT_OK;
   } catch (const HipError& e) {
+    (void)hipStreamSynchronize(s);
     return fail(e.st, e.msg);
   }
 }

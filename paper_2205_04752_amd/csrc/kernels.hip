@@ -667,7 +667,7 @@ __global__ __launch_bounds__(WAVE) void k_reduce(const int32_t* __restrict__ til
 // GMRES helpers (FP64).
 
 // Two-stage Q^T w: workgroup b takes rows [b*DOT_ROWS, (b+1)*DOT_ROWS) and writes
-// part[b*ncols + c] = sum over its rows of Q[i, c] w[i]; k_dots_final sums over b.
+// part[b*ncols + c] = sum over its rows of Q[i, c] w[i]; k_proj sums over b.
 constexpr int DOT_ROWS = 512;
 __global__ __launch_bounds__(256) void k_dots_part(const double* __restrict__ Q, int64_t ldq,
                                                    int64_t n, int ncols,
@@ -692,42 +692,75 @@ __global__ __launch_bounds__(256) void k_dots_part(const double* __restrict__ Q,
   }
 }
 
-__global__ __launch_bounds__(256) void k_dots_final(const double* __restrict__ part, int nblk,
-                                                    int ncols, double* __restrict__ out) {
+// w -= Q[:, 0:ncols] h, where h[c] = sum_b part[b*ncols + c] (the partial dot
+// products of k_dots_part, summed here by every workgroup into LDS). Block 0
+// also folds h into the Hessenberg column acc (acc = h if assign, else
+// acc += h). If normpart != nullptr, each workgroup writes the partial sum of
+// squares of its updated rows to normpart[blockIdx.x].
+constexpr int PROJ_MAX_COLS = 1025;
+__global__ __launch_bounds__(256) void k_proj(const double* __restrict__ Q, int64_t ldq, int64_t n,
+                                              int ncols, const double* __restrict__ part, int nblk,
+                                              double* __restrict__ w, double* __restrict__ acc,
+                                              int assign, double* __restrict__ normpart) {
+  __shared__ double hs[PROJ_MAX_COLS];
+  __shared__ double red[256 / WAVE];
   for (int c = threadIdx.x; c < ncols; c += blockDim.x) {
     double t = 0.0;
     for (int b = 0; b < nblk; b++) t += part[(size_t)b * ncols + c];
-    out[c] = t;
+    hs[c] = t;
+    if (acc && blockIdx.x == 0) acc[c] = assign ? t : acc[c] + t;
+  }
+  __syncthreads();
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  double sq = 0.0;
+  if (i < n) {
+    double s = 0.0;
+    for (int c = 0; c < ncols; c++) s += Q[(size_t)c * ldq + i] * hs[c];
+    const double v = w[i] - s;
+    w[i] = v;
+    sq = v * v;
+  }
+  if (normpart) {
+    sq = wave_sum(sq);
+    if ((threadIdx.x & (WAVE - 1)) == 0) red[threadIdx.x / WAVE] = sq;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int k = 0; k < 256 / WAVE; k++) t += red[k];
+      normpart[blockIdx.x] = t;
+    }
   }
 }
 
-// w -= Q[:, 0:ncols] h (h on the device); acc[c] += h[c] if acc != nullptr (by thread 0 of block 0).
-__global__ __launch_bounds__(256) void k_sub_proj(const double* __restrict__ Q, int64_t ldq,
-                                                  int64_t n, int ncols,
-                                                  const double* __restrict__ h,
-                                                  double* __restrict__ w, double* __restrict__ acc) {
+// Partial sums of squares: part[b] = sum over the rows of block b of w[i]^2.
+__global__ __launch_bounds__(256) void k_sqnorm_part(const double* __restrict__ w, int64_t n,
+                                                     double* __restrict__ part) {
+  __shared__ double red[256 / WAVE];
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (acc && blockIdx.x == 0)
-    for (int c = threadIdx.x; c < ncols; c += blockDim.x) acc[c] += h[c];
-  if (i >= n) return;
-  double s = 0.0;
-  for (int c = 0; c < ncols; c++) s += Q[(size_t)c * ldq + i] * h[c];
-  w[i] -= s;
-}
-
-// out[0] = ||w||_2 (single workgroup of 1024 threads).
-__global__ __launch_bounds__(1024) void k_norm(const double* __restrict__ w, int64_t n,
-                                               double* __restrict__ out) {
-  __shared__ double sh[1024 / WAVE];
-  double s = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) s += w[i] * w[i];
-  s = wave_sum(s);
-  if ((threadIdx.x & (WAVE - 1)) == 0) sh[threadIdx.x / WAVE] = s;
+  double sq = i < n ? w[i] * w[i] : 0.0;
+  sq = wave_sum(sq);
+  if ((threadIdx.x & (WAVE - 1)) == 0) red[threadIdx.x / WAVE] = sq;
   __syncthreads();
   if (threadIdx.x == 0) {
     double t = 0.0;
-    for (int k = 0; k < (int)(blockDim.x / WAVE); k++) t += sh[k];
-    out[0] = sqrt(t);
+    for (int k = 0; k < 256 / WAVE; k++) t += red[k];
+    part[blockIdx.x] = t;
+  }
+}
+
+// out[0] = sqrt(sum of part[0:nblk]) (one workgroup).
+__global__ __launch_bounds__(256) void k_norm_final(const double* __restrict__ part, int nblk,
+                                                    double* __restrict__ out) {
+  __shared__ double red[256 / WAVE];
+  double t = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x) t += part[b];
+  t = wave_sum(t);
+  if ((threadIdx.x & (WAVE - 1)) == 0) red[threadIdx.x / WAVE] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double u = 0.0;
+    for (int k = 0; k < 256 / WAVE; k++) u += red[k];
+    out[0] = sqrt(u);
   }
 }
 
@@ -864,26 +897,38 @@ hipError_t launch_from_stream(const StreamTask* tasks, int ntasks, const double*
   return hipGetLastError();
 }
 
-// out[c] = Q[:, c] . w for c < ncols (part: scratch of dots_part_size(n, ncols) doubles).
+// Scratch (doubles) for the partial dot products of launch_dots_part.
 size_t dots_part_size(int64_t n, int ncols) { return (size_t)((n + DOT_ROWS - 1) / DOT_ROWS) * ncols; }
 
-hipError_t launch_dots(const double* Q, int64_t ldq, int64_t n, int ncols, const double* w,
-                       double* out, double* part, hipStream_t s) {
+// part[b][c] = partial Q[:, c] . w over row block b (c < ncols); returns the block count.
+int launch_dots_part(const double* Q, int64_t ldq, int64_t n, int ncols, const double* w,
+                     double* part, hipStream_t s) {
   const int nblk = (int)((n + DOT_ROWS - 1) / DOT_ROWS);
   hipLaunchKernelGGL(k_dots_part, dim3(nblk), dim3(256), sizeof(double) * NW * ncols, s, Q, ldq, n,
                      ncols, w, part);
-  hipLaunchKernelGGL(k_dots_final, dim3(1), dim3(256), 0, s, part, nblk, ncols, out);
+  return nblk;
+}
+
+// Partial-norm scratch (doubles) for n rows.
+size_t norm_part_size(int64_t n) { return (size_t)((n + 255) / 256); }
+
+hipError_t launch_proj(const double* Q, int64_t ldq, int64_t n, int ncols, const double* part,
+                       int nblk, double* w, double* acc, int assign, double* normpart, hipStream_t s) {
+  hipLaunchKernelGGL(k_proj, dim3(blocks_for(n, 256)), dim3(256), 0, s, Q, ldq, n, ncols, part, nblk,
+                     w, acc, assign, normpart);
   return hipGetLastError();
 }
 
-hipError_t launch_sub_proj(const double* Q, int64_t ldq, int64_t n, int ncols, const double* h,
-                           double* w, double* acc, hipStream_t s) {
-  hipLaunchKernelGGL(k_sub_proj, dim3(blocks_for(n, 256)), dim3(256), 0, s, Q, ldq, n, ncols, h, w, acc);
+// out[0] = ||w||_2 in two stages (normpart: norm_part_size(n) doubles).
+hipError_t launch_norm(const double* w, int64_t n, double* normpart, double* out, hipStream_t s) {
+  const int nblk = (int)blocks_for(n, 256);
+  hipLaunchKernelGGL(k_sqnorm_part, dim3(nblk), dim3(256), 0, s, w, n, normpart);
+  hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(256), 0, s, normpart, nblk, out);
   return hipGetLastError();
 }
 
-hipError_t launch_norm(const double* w, int64_t n, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_norm, dim3(1), dim3(1024), 0, s, w, n, out);
+hipError_t launch_norm_final(const double* normpart, int64_t n, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(256), 0, s, normpart, (int)blocks_for(n, 256), out);
   return hipGetLastError();
 }
 
