@@ -93,7 +93,8 @@ void upload(DevBuf& d, const std::vector<T>& h, hipStream_t s, const char* what)
 constexpr int KCAP_FIRST = 128;  // first-pass panel capacity (columns) of ACA
 constexpr int MV_TILE = 128;     // rows per product tile (one wave, two rows per lane)
 constexpr int MV_SEG_COLS = 128; // columns per product segment
-constexpr int64_t MV_CHUNK_BYTES = 32 * 1024;  // default; HMAT_MV_CHUNK_KB overrides
+constexpr int64_t MV_CHUNK_BYTES = 16 * 1024;         // nrhs = 1; HMAT_MV_CHUNK_KB overrides
+constexpr int64_t MV_CHUNK_BYTES_MULTI = 128 * 1024;  // nrhs > 1
 constexpr int MV_MAX_NR = 16;    // right-hand sides per pass over the matrix
 
 inline int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
@@ -136,8 +137,15 @@ struct hmat {
   std::vector<int32_t> piv_cap;
   int aca_passes = 0;
   // product plan
-  DevBuf d_mvA, d_seg, d_chunk, d_tile_near, d_tile_far;
-  int nA = 0, nSeg = 0, nChunk = 0, nNearChunk = 0, nTiles = 0;
+  DevBuf d_mvA, d_seg;
+  // Phase-B chunk lists cut from the same segment order: [0] for single
+  // right-hand sides (small chunks, short tail), [1] for several (larger
+  // chunks: the partial sums grow with the number of vectors).
+  struct ChunkList {
+    DevBuf d_chunk, d_tile_near, d_tile_far;
+    int n = 0, n_near = 0;
+  } cl[2];
+  int nA = 0, nSeg = 0, nTiles = 0;
   int64_t Ztot = 0, ldxp = 0, stream_n = 0;
   std::vector<MvSeg> segs;                       // host copy, product order
   std::vector<int32_t> seg_tile;                 // tile of each segment
@@ -149,6 +157,7 @@ struct hmat {
   };
   std::vector<std::vector<Piece>> block_pieces;  // canonical block -> its pieces
   int64_t mv_chunk_bytes = MV_CHUNK_BYTES;       // product tuning (HMAT_MV_CHUNK_KB)
+  int64_t mv_chunk_bytes_multi = MV_CHUNK_BYTES_MULTI;
   int mv_unroll = 16;                            // columns per batch in phase B (HMAT_MV_UNROLL)
   DevBuf d_xp, d_z, d_part, d_dotpart;
   // GMRES workspace
@@ -255,7 +264,7 @@ void build_product_plan(hmat* h, hipStream_t s) {
     const Group& g = groups[gi];
     const BlockRec& B = P.blk[g.members[0]];
     const int64_t R0 = 3 * (int64_t)P.cl[B.t].off, m = block_m(h, g.members[0]);
-    // rows [R0, R0 + m) widened to whole cache lines (zero rows in the stream)
+    // rows [R0, R0 + m) widened to even rows (zero rows in the stream)
     const int64_t A0 = R0 / STREAM_ALIGN * STREAM_ALIGN, A1 = round_up(R0 + m, STREAM_ALIGN);
     for (int64_t T = A0 / MV_TILE; T * MV_TILE < A1; T++) {
       const int64_t lo = std::max(A0, T * MV_TILE) - T * MV_TILE;
@@ -282,46 +291,60 @@ void build_product_plan(hmat* h, hipStream_t s) {
   h->segs.assign(segs.size(), MvSeg{});
   h->seg_tile.assign(segs.size(), 0);
   h->block_pieces.assign(P.blk.size(), {});
-  std::vector<MvChunk> chunks;
-  std::vector<int32_t> tile_near(h->nTiles + 1, 0), tile_far(h->nTiles + 1, 0);
+  // stream offsets in segment order; every segment starts on a 128-byte line
   int64_t so = 0;
-  size_t i = 0;
-  for (int32_t group = 0; group < 2; group++) {
-    std::vector<int32_t>& tc = group == 0 ? tile_near : tile_far;
-    for (int32_t T = 0; T < h->nTiles; T++) {
-      tc[T] = (int32_t)chunks.size();
-      while (i < segs.size() && segs[i].seg.far == group && segs[i].tile == T) {
-        MvChunk c{T, (int32_t)i, (int32_t)i, 0};
-        int64_t bytes = 0;
-        while (i < segs.size() && segs[i].seg.far == group && segs[i].tile == T &&
-               (bytes < h->mv_chunk_bytes || c.seg_hi == c.seg_lo)) {
-          MvSeg sg = segs[i].seg;
-          const int64_t len = sg.row_hi - sg.row_lo;
-          sg.so = so;
-          so += len * (sg.c1 - sg.c0);
-          bytes += len * (sg.c1 - sg.c0) * 8;
-          h->segs[i] = sg;
-          h->seg_tile[i] = T;
-          const Group& g = groups[segs[i].group];
-          for (int32_t b : g.members) {
-            const int64_t nb = P.blk[b].far ? h->rank[h->kind_index[b]] : block_n(h, b);
-            const int64_t lo_c = std::max<int64_t>(sg.c0, gcol[b]);
-            const int64_t hi_c = std::min<int64_t>(sg.c1, gcol[b] + nb);
-            if (lo_c >= hi_c) continue;
-            h->block_pieces[b].push_back(hmat::Piece{(int32_t)i, (int32_t)(lo_c - gcol[b]),
-                                                     (int32_t)(hi_c - gcol[b]),
-                                                     sg.so + (lo_c - sg.c0) * len});
-          }
-          i++;
-          c.seg_hi = (int32_t)i;
-        }
-        chunks.push_back(c);
-      }
+  for (size_t i = 0; i < segs.size(); i++) {
+    MvSeg sg = segs[i].seg;
+    const int64_t len = sg.row_hi - sg.row_lo;
+    so = round_up(so, SEG_START_ALIGN);
+    sg.so = so;
+    so += len * (sg.c1 - sg.c0);
+    h->segs[i] = sg;
+    h->seg_tile[i] = segs[i].tile;
+    const Group& g = groups[segs[i].group];
+    for (int32_t b : g.members) {
+      const int64_t nb = P.blk[b].far ? h->rank[h->kind_index[b]] : block_n(h, b);
+      const int64_t lo_c = std::max<int64_t>(sg.c0, gcol[b]);
+      const int64_t hi_c = std::min<int64_t>(sg.c1, gcol[b] + nb);
+      if (lo_c >= hi_c) continue;
+      h->block_pieces[b].push_back(hmat::Piece{(int32_t)i, (int32_t)(lo_c - gcol[b]),
+                                               (int32_t)(hi_c - gcol[b]), sg.so + (lo_c - sg.c0) * len});
     }
-    tc[h->nTiles] = (int32_t)chunks.size();
-    if (group == 0) h->nNearChunk = (int32_t)chunks.size();
   }
-  if (i != segs.size()) throw HipError{HMAT_EDEVICE, "internal: product plan: segments left over"};
+  // Chunks: runs of consecutive segments of one tile and kind (dense first,
+  // then low-rank) holding about `target` bytes.
+  auto cut = [&](int64_t target, std::vector<MvChunk>& chunks, std::vector<int32_t>& tile_near,
+                 std::vector<int32_t>& tile_far, int& n_near) {
+    tile_near.assign(h->nTiles + 1, 0);
+    tile_far.assign(h->nTiles + 1, 0);
+    size_t i = 0;
+    for (int32_t group = 0; group < 2; group++) {
+      std::vector<int32_t>& tc = group == 0 ? tile_near : tile_far;
+      for (int32_t T = 0; T < h->nTiles; T++) {
+        tc[T] = (int32_t)chunks.size();
+        while (i < segs.size() && segs[i].seg.far == group && segs[i].tile == T) {
+          MvChunk c{T, (int32_t)i, (int32_t)i, 0};
+          int64_t bytes = 0;
+          while (i < segs.size() && segs[i].seg.far == group && segs[i].tile == T &&
+                 (bytes < target || c.seg_hi == c.seg_lo)) {
+            bytes += 8 * (int64_t)(h->segs[i].row_hi - h->segs[i].row_lo) * (h->segs[i].c1 - h->segs[i].c0);
+            i++;
+            c.seg_hi = (int32_t)i;
+          }
+          chunks.push_back(c);
+        }
+      }
+      tc[h->nTiles] = (int32_t)chunks.size();
+      if (group == 0) n_near = (int32_t)chunks.size();
+    }
+    if (i != segs.size()) throw HipError{HMAT_EDEVICE, "internal: product plan: segments left over"};
+  };
+  std::vector<MvChunk> chunk_l[2];
+  std::vector<int32_t> tn_l[2], tf_l[2];
+  int n_near_l[2] = {0, 0};
+  cut(h->mv_chunk_bytes, chunk_l[0], tn_l[0], tf_l[0], n_near_l[0]);
+  cut(h->mv_chunk_bytes_multi, chunk_l[1], tn_l[1], tf_l[1], n_near_l[1]);
+
   h->stream_n = std::max<int64_t>(so, PANEL_ALIGN);
   h->ldxp = round_up(h->N, PANEL_ALIGN);
   // Host-side bounds check of every access the product kernels will make.
@@ -340,19 +363,24 @@ void build_product_plan(hmat* h, hipStream_t s) {
       if (sg.so + (int64_t)(sg.row_hi - sg.row_lo) * (sg.c1 - sg.c0) > h->stream_n) bad("phase B matrix range");
       if ((int64_t)sg.soff + sg.c1 > (sg.far ? h->Ztot : h->N)) bad("phase B vector range");
     }
-    for (const MvChunk& c : chunks)
-      if (c.tile < 0 || c.tile >= h->nTiles || c.seg_lo >= c.seg_hi || c.seg_hi > (int32_t)h->segs.size()) bad("chunks");
-    for (int32_t T = 0; T < h->nTiles; T++)
-      if (tile_near[T + 1] <= tile_near[T] || tile_far[T + 1] < tile_far[T]) bad("tile chunk ranges");
+    for (int l = 0; l < 2; l++) {
+      for (const MvChunk& c : chunk_l[l])
+        if (c.tile < 0 || c.tile >= h->nTiles || c.seg_lo >= c.seg_hi || c.seg_hi > (int32_t)h->segs.size()) bad("chunks");
+      for (int32_t T = 0; T < h->nTiles; T++)
+        if (tn_l[l][T + 1] <= tn_l[l][T] || tf_l[l][T + 1] < tf_l[l][T]) bad("tile chunk ranges");
+    }
   }
   h->nA = (int)items.size();
   h->nSeg = (int)h->segs.size();
-  h->nChunk = (int)chunks.size();
   upload(h->d_mvA, items, s, "product plan");
   upload(h->d_seg, h->segs, s, "product plan");
-  upload(h->d_chunk, chunks, s, "product plan");
-  upload(h->d_tile_near, tile_near, s, "product plan");
-  upload(h->d_tile_far, tile_far, s, "product plan");
+  for (int l = 0; l < 2; l++) {
+    upload(h->cl[l].d_chunk, chunk_l[l], s, "product plan");
+    upload(h->cl[l].d_tile_near, tn_l[l], s, "product plan");
+    upload(h->cl[l].d_tile_far, tf_l[l], s, "product plan");
+    h->cl[l].n = (int)chunk_l[l].size();
+    h->cl[l].n_near = n_near_l[l];
+  }
 
   if (h->d_xp.bytes < sizeof(double) * MV_MAX_NR * h->ldxp) {
     h->d_xp.alloc(sizeof(double) * MV_MAX_NR * h->ldxp, "product workspace");
@@ -360,7 +388,10 @@ void build_product_plan(hmat* h, hipStream_t s) {
     check(hipMemsetAsync(h->d_xp.p, 0, h->d_xp.bytes, s), "product workspace");
   }
   h->d_z.alloc(sizeof(double) * MV_MAX_NR * h->Ztot, "product workspace");
-  h->d_part.alloc(sizeof(double) * MV_MAX_NR * MV_TILE * std::max(1, h->nChunk), "product workspace");
+  // partial sums: [chunk][NR][128] with NR = 1 (list 0) or the multi-vector bucket (<= 16, list 1)
+  h->d_part.alloc(sizeof(double) * MV_TILE *
+                      std::max<int64_t>(std::max(1, h->cl[0].n), (int64_t)MV_MAX_NR * std::max(1, h->cl[1].n)),
+                  "product workspace");
   check(hipStreamSynchronize(s), "product plan");
 }
 
@@ -431,7 +462,8 @@ void fill_stats(hmat* h) {
   st.device_bytes = (int64_t)(h->d_cen.bytes + h->d_q.bytes + h->d_vtx.bytes + h->d_gl.bytes +
                               h->d_order.bytes + h->far_arena.bytes + h->stream.bytes +
                               h->piv1.bytes + h->piv2.bytes + h->d_mvA.bytes + h->d_seg.bytes +
-                              h->d_chunk.bytes + h->d_tile_near.bytes + h->d_tile_far.bytes + h->d_xp.bytes +
+                              h->cl[0].d_chunk.bytes + h->cl[0].d_tile_near.bytes + h->cl[0].d_tile_far.bytes +
+                              h->cl[1].d_chunk.bytes + h->cl[1].d_tile_near.bytes + h->cl[1].d_tile_far.bytes + h->d_xp.bytes +
                               h->d_z.bytes + h->d_part.bytes + h->d_dotpart.bytes + h->d_Q.bytes +
                               h->d_w.bytes + h->d_small.bytes);
 }
@@ -516,6 +548,8 @@ void run_aca_pass(hmat* h, const std::vector<int32_t>& fidx, CapFn cap, DevBuf& 
 void fill_stream(hmat* h, const double* near_src, const std::vector<int64_t>& near_off,
                  const std::vector<const double*>& u_ptr, hipStream_t s) {
   h->stream.alloc(sizeof(double) * h->stream_n, "product stream");
+  // the gaps that align segment starts are never read; keep them zero anyway
+  check(hipMemsetAsync(h->stream.p, 0, h->stream.bytes, s), "product stream");
   auto tasks = stream_tasks(
       h, [&](int32_t b) { return !h->plan.blk[b].far || h->rank[h->kind_index[b]] > 0; },
       [&](int32_t b) -> double* {
@@ -727,16 +761,17 @@ void matvec_impl(hmat* h, int32_t nrhs, const double* x, int64_t ldx, double* y,
     if (ev) check(hipEventRecord(ev[1], s), "profile");
     ProductPlanDev P{};
     P.items = h->d_mvA.as<MvA>();
-    P.chunks = h->d_chunk.as<MvChunk>();
+    const hmat::ChunkList& CL = h->cl[nr > 1 ? 1 : 0];
+    P.chunks = CL.d_chunk.as<MvChunk>();
     P.segs = h->d_seg.as<MvSeg>();
-    P.tile_near = h->d_tile_near.as<int32_t>();
-    P.tile_far = h->d_tile_far.as<int32_t>();
+    P.tile_near = CL.d_tile_near.as<int32_t>();
+    P.tile_far = CL.d_tile_far.as<int32_t>();
     P.order = h->d_order.as<int32_t>();
     P.far = h->far_arena.as<double>();
     P.stream = h->stream.as<double>();
     P.nA = h->nA;
-    P.n_near_chunks = h->nNearChunk;
-    P.n_far_chunks = h->nChunk - h->nNearChunk;
+    P.n_near_chunks = CL.n_near;
+    P.n_far_chunks = CL.n - CL.n_near;
     P.ntiles = h->nTiles;
     P.N = h->N;
     check(launch_matvec_group(P, nr, h->d_xp.as<double>(), h->ldxp, h->d_z.as<double>(), h->Ztot,

@@ -29,12 +29,12 @@ struct DevGeo {
 // with fp = R0 mod PANEL_ALIGN, ld a multiple of PANEL_ALIGN >= fp + M and base
 // a multiple of PANEL_ALIGN: global DOF g sits at an address congruent to g
 // modulo PANEL_ALIGN doubles, so a lane reads the row pair (2j, 2j+1) with one
-// 16-byte load. The product-order stream widens block row ranges to multiples
-// of STREAM_ALIGN (a 128-byte cache line): each column slice then covers whole
-// lines, which measures faster than the narrower pad despite the extra zero
-// rows. Pad entries are zero.
-constexpr int PANEL_ALIGN = 2;    // doubles (16 bytes)
-constexpr int STREAM_ALIGN = 16;  // doubles (128 bytes)
+// 16-byte load. The product-order stream widens block row ranges to even rows
+// the same way (STREAM_ALIGN) and starts every segment on a 128-byte line
+// (SEG_START_ALIGN), so no line is shared by two segments. Pad entries are zero.
+constexpr int PANEL_ALIGN = 2;       // doubles (16 bytes)
+constexpr int STREAM_ALIGN = 2;      // doubles (16 bytes)
+constexpr int SEG_START_ALIGN = 16;  // doubles (128 bytes)
 
 // Dense (non-admissible) block at d_off in the near arena (m = 3 t_len rows).
 struct NearTask {

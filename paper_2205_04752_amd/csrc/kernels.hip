@@ -489,12 +489,72 @@ __device__ __forceinline__ void mv_a_item(const MvA& I, const double* __restrict
   }
 }
 
-// Phase B chunk: segments of one 128-row tile; lane L owns tile rows 2L and
-// 2L+1 and reads them with one 16-byte load per column. A chunk's matrix data
-// is one contiguous range of the stream arena. Lanes outside a segment's rows
-// load a clamped in-segment address and discard the value; a segment's last
-// partial batch re-reads its last column without accumulating it -- so every
-// batch issues its UNR loads back to back. Writes part[chunk][r][128].
+// Phase B chunk: segments of one 128-row tile, each a column-major array of
+// its rows [row_lo, row_hi) (even bounds) times its columns, stored back to
+// back; lane L owns tile rows 2L and 2L+1 (acc0, acc1). A segment taller than
+// half a wave is read with lane L on its own rows (16-byte loads; lanes
+// outside the segment load a clamped in-segment address and discard it). A
+// shorter one (single right-hand side) puts p = 64 / (len/2) columns side by
+// side, so each load instruction covers p*len consecutive doubles; the p
+// column groups are then summed with a lane tree and moved to the owning
+// lanes. A segment's last partial batch re-reads in-segment data without
+// accumulating it, so every batch issues its UNR loads back to back. Writes
+// part[chunk][r][128].
+// One short segment (len <= 64 rows, single right-hand side) of a phase-B
+// chunk: g = len/2 lanes per column, p = 64/g >= 2 columns per load. Lane l
+// reads column c0 + t p + l/g, rows 2(l mod g) and +1, at stream offset
+// so + t p len + 2l -- consecutive lanes, consecutive addresses. Adds the
+// segment's row sums to the owning lanes' acc0/acc1 (fixed summation order).
+template <int UNR>
+__device__ __forceinline__ void mv_b_grouped(const MvSeg& S, const double* __restrict__ stream,
+                                             const double* __restrict__ src, double& acc0,
+                                             double& acc1) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int len = S.row_hi - S.row_lo, g = len >> 1, p = WAVE / g;
+  const int q = lane / g;
+  const bool lact = q < p;
+  const int ncol = S.c1 - S.c0;
+  const int nsteps = (ncol + p - 1) / p;
+  const int64_t step = (int64_t)p * len;
+  const double* __restrict__ A = stream + S.so;
+  const double* __restrict__ xs = src + S.soff + S.c0;
+  double s0 = 0.0, s1 = 0.0;
+  for (int t = 0; t < nsteps; t += UNR) {
+    double2 a[UNR];
+    double xv[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; u++) {
+      const int col = (t + u) * p + q;
+      const bool ok = lact && col < ncol;
+      a[u] = *reinterpret_cast<const double2*>(A + (ok ? (int64_t)(t + u) * step + 2 * lane : 0));
+      xv[u] = xs[ok ? col : 0];
+      xv[u] = ok ? xv[u] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < UNR; u++) {
+      s0 += a[u].x * xv[u];
+      s1 += a[u].y * xv[u];
+    }
+  }
+  // sum the p column groups: group q takes group q + off at level off
+  for (int off = 1; off < p; off <<= 1) {
+    const double o0 = __shfl(s0, (lane + off * g) & (WAVE - 1), WAVE);
+    const double o1 = __shfl(s1, (lane + off * g) & (WAVE - 1), WAVE);
+    if (q % (2 * off) == 0 && q + off < p) {
+      s0 += o0;
+      s1 += o1;
+    }
+  }
+  // lanes [0, g) hold rows row_lo + 2l, +1: move them to lanes row_lo/2 + l
+  const int from = lane - (S.row_lo >> 1);
+  const double m0 = __shfl(s0, from & (WAVE - 1), WAVE);
+  const double m1 = __shfl(s1, from & (WAVE - 1), WAVE);
+  if (from >= 0 && from < g) {
+    acc0 += m0;
+    acc1 += m1;
+  }
+}
+
 template <int NR, int UNR>
 __device__ __forceinline__ void mv_b_chunk(const MvChunk& C, int chunk,
                                            const MvSeg* __restrict__ segs,
@@ -508,9 +568,13 @@ __device__ __forceinline__ void mv_b_chunk(const MvChunk& C, int chunk,
   for (int r = 0; r < NR; r++) acc0[r] = acc1[r] = 0.0;
   for (int s = C.seg_lo; s < C.seg_hi; s++) {
     const MvSeg S = segs[s];
+    const int len = S.row_hi - S.row_lo;
+    if (NR == 1 && len <= WAVE) {
+      mv_b_grouped<UNR>(S, stream, S.far ? z : xp, acc0[0], acc1[0]);
+      continue;
+    }
     const bool act = L2 >= S.row_lo && L2 < S.row_hi;
     const int Lc = min(max(L2, (int)S.row_lo), (int)S.row_hi - 2);
-    const int len = S.row_hi - S.row_lo;
     const double* __restrict__ A = stream + S.so + (Lc - S.row_lo) - (int64_t)S.c0 * len;
     const double* __restrict__ src = (S.far ? z : xp) + S.soff;
     const int64_t ld = S.far ? ldz : ldxp;
@@ -630,36 +694,55 @@ __global__ __launch_bounds__(256) void k_from_stream(const StreamTask* __restric
   }
 }
 
-// Sum the partials of each tile -- its dense-block chunks, then its low-rank
-// chunks, each in chunk order -- and scatter to the caller's order.
+// Sum the partials of each tile and scatter to the caller's order. The tile's
+// chunks (dense-block chunks, then low-rank chunks) are dealt round-robin to
+// RED_WAVES waves, which sum theirs in chunk order; wave 0 adds the waves'
+// sums in wave order (a fixed order: results do not vary between calls).
+constexpr int RED_WAVES = 4;
 template <int NR>
-__global__ __launch_bounds__(WAVE) void k_reduce(const int32_t* __restrict__ tile_near,
-                                                 const int32_t* __restrict__ tile_far,
-                                                 const double* __restrict__ part, int nr,
-                                                 const int32_t* __restrict__ order, int64_t N,
-                                                 double* __restrict__ y, int64_t ldy) {
-  const int tile = blockIdx.x, L2 = 2 * threadIdx.x;
+__global__ __launch_bounds__(WAVE* RED_WAVES) void k_reduce(const int32_t* __restrict__ tile_near,
+                                                            const int32_t* __restrict__ tile_far,
+                                                            const double* __restrict__ part, int nr,
+                                                            const int32_t* __restrict__ order,
+                                                            int64_t N, double* __restrict__ y,
+                                                            int64_t ldy) {
+  __shared__ double2 red[RED_WAVES][WAVE];
+  const int tile = blockIdx.x, w = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
+  const int L2 = 2 * lane;
   const int64_t row = (int64_t)tile * TILE + L2;
-  if (row >= N) return;
-  const int n0 = tile_near[tile], n1 = tile_near[tile + 1];
-  const int f0 = tile_far[tile], f1 = tile_far[tile + 1];
-  const int64_t d0 = 3 * (int64_t)order[row / 3] + row % 3;
-  const bool two = row + 1 < N;
-  const int64_t d1 = two ? 3 * (int64_t)order[(row + 1) / 3] + (row + 1) % 3 : 0;
+  const int n0 = tile_near[tile], nn = tile_near[tile + 1] - n0;
+  const int f0 = tile_far[tile], n = nn + tile_far[tile + 1] - f0;
+  constexpr int DEPTH = 4;  // loads in flight per lane
   for (int r = 0; r < nr; r++) {
     double s0 = 0.0, s1 = 0.0;
-    for (int c = n0; c < n1; c++) {
-      const double2 p = *reinterpret_cast<const double2*>(part + ((size_t)c * NR + r) * TILE + L2);
-      s0 += p.x;
-      s1 += p.y;
+    for (int k = w; k < n; k += RED_WAVES * DEPTH) {
+      double2 p[DEPTH];
+#pragma unroll
+      for (int j = 0; j < DEPTH; j++) {
+        const int kk = k + j * RED_WAVES;
+        const int c = kk < nn ? n0 + kk : f0 + (kk - nn);
+        p[j] = kk < n ? *reinterpret_cast<const double2*>(part + ((size_t)c * NR + r) * TILE + L2)
+                      : make_double2(0.0, 0.0);
+      }
+#pragma unroll
+      for (int j = 0; j < DEPTH; j++) {
+        s0 += p[j].x;
+        s1 += p[j].y;
+      }
     }
-    for (int c = f0; c < f1; c++) {
-      const double2 p = *reinterpret_cast<const double2*>(part + ((size_t)c * NR + r) * TILE + L2);
-      s0 += p.x;
-      s1 += p.y;
+    red[w][lane] = make_double2(s0, s1);
+    __syncthreads();
+    if (w == 0 && row < N) {
+      double t0 = 0.0, t1 = 0.0;
+#pragma unroll
+      for (int v = 0; v < RED_WAVES; v++) {
+        t0 += red[v][lane].x;
+        t1 += red[v][lane].y;
+      }
+      y[r * ldy + 3 * (int64_t)order[row / 3] + row % 3] = t0;
+      if (row + 1 < N) y[r * ldy + 3 * (int64_t)order[(row + 1) / 3] + (row + 1) % 3] = t1;
     }
-    y[r * ldy + d0] = s0;
-    if (two) y[r * ldy + d1] = s1;
+    __syncthreads();
   }
 }
 
@@ -857,7 +940,7 @@ static void mv_group(const ProductPlanDev& P, const double* xp, int64_t ldxp, in
                        dim3(WAVE * MV_WPB), 0, s, P.n_near_chunks, P.n_far_chunks, P.chunks, P.segs,
                        P.stream, z, ldz, xp, ldxp, nr, part);
   if (ev) (void)hipEventRecord(ev[1], s);
-  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_reduce<NR>), dim3(P.ntiles), dim3(WAVE), 0, s, P.tile_near,
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_reduce<NR>), dim3(P.ntiles), dim3(WAVE * RED_WAVES), 0, s, P.tile_near,
                      P.tile_far, part, nr, P.order, P.N, y, ldy);
   if (ev) (void)hipEventRecord(ev[2], s);
 }
