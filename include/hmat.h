@@ -126,6 +126,31 @@ hmat_status hmat_build(const hmat_mesh* mesh, double E, double nu, double eta, i
                        double eps, void* hip_stream, hmat_t* out);
 
 /*
+ * hmat_build_batch -- hmat_build for n_bodies independent bodies in one
+ * handle (the block-diagonal operator diag(A_H^(0), ..., A_H^(n-1))): every
+ * body gets its own cluster tree, partition and ACA (Sec. 2, Algorithm 1)
+ * with its own E[b], nu[b] and eps[b]; eta and leaf are shared. The dense
+ * blocks of all bodies are generated in one launch, ACA runs over the
+ * admissible blocks of all bodies together, and hmat_matvec multiplies all
+ * bodies in one pass.
+ *   meshes, E, nu, eps   HOST arrays of n_bodies entries (copied).
+ * DOF layout of x and y in hmat_matvec / hmat_solve: the bodies' DOF vectors
+ * concatenated in body order (body b starts at DOF 3 * sum_{c<b} n_triangles_c;
+ * hmat_bodies returns the offsets). hmat_block numbers blocks body by body.
+ * hmat_solve runs GMRES on the whole block-diagonal system.
+ * Errors: as hmat_build for each body (the message names the body);
+ * HMAT_EINVAL for n_bodies < 1 or more than 2^31/3 triangles in total.
+ */
+hmat_status hmat_build_batch(int32_t n_bodies, const hmat_mesh* meshes, const double* E,
+                             const double* nu, const double* eps, double eta, int32_t leaf,
+                             void* hip_stream, hmat_t* out);
+
+/* hmat_bodies -- number of bodies of h (1 for hmat_build) and, if dof_off is
+ * not NULL, their DOF offsets: dof_off[b] is the first DOF of body b and
+ * dof_off[n_bodies] = n_dof (HOST array of n_bodies + 1 entries). */
+hmat_status hmat_bodies(hmat_t h, int32_t* n_bodies, int64_t* dof_off);
+
+/*
  * hmat_matvec -- y_r = A_H x_r for r = 0..nrhs-1 (Sec. 2, Sec. 2.2):
  *   y = sum over admissible b of U_b (V_b^T x_s) + sum over dense b of D_b x_s.
  *   x    DEVICE float64, nrhs vectors of length n_dof, vector r at x + r*ldx,

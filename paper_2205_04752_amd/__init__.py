@@ -50,9 +50,9 @@ class _SolveInfo(C.Structure):
                 ("time_ms", C.c_double)]
 
 
-EXPORTS = ["hmat_build", "hmat_matvec", "hmat_solve", "hmat_info", "hmat_free",
-           "hmat_last_error", "hmat_plan", "hmat_block", "hmat_entries", "hmat_set_factors",
-           "hmat_profile"]
+EXPORTS = ["hmat_build", "hmat_build_batch", "hmat_bodies", "hmat_matvec", "hmat_solve",
+           "hmat_info", "hmat_free", "hmat_last_error", "hmat_plan", "hmat_block", "hmat_entries",
+           "hmat_set_factors", "hmat_profile"]
 
 _lib = None
 
@@ -68,6 +68,8 @@ def lib():
     L = C.CDLL(LIB_PATH)
     vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
     L.hmat_build.argtypes = [C.POINTER(_Mesh), dbl, dbl, dbl, i32, dbl, vp, C.POINTER(vp)]
+    L.hmat_build_batch.argtypes = [i32, vp, vp, vp, vp, dbl, i32, vp, C.POINTER(vp)]
+    L.hmat_bodies.argtypes = [vp, C.POINTER(i32), vp]
     L.hmat_matvec.argtypes = [vp, i32, vp, i64, vp, i64, vp]
     L.hmat_solve.argtypes = [vp, vp, vp, dbl, i32, i32, vp, C.POINTER(_SolveInfo)]
     L.hmat_info.argtypes = [vp, C.POINTER(_Stats)]
@@ -140,6 +142,39 @@ class HMatrix:
         self._h = h
         self.n_triangles = m.n_triangles
         self.n_dof = 3 * m.n_triangles
+
+    @classmethod
+    def batch(cls, bodies, eta=2.0, leaf=32, stream=None):
+        """One handle for several independent bodies (block-diagonal operator).
+        bodies: sequence of dicts with vertices, triangles, E, nu, eps. Vectors
+        are the bodies' DOF vectors concatenated (offsets: bodies())."""
+        nb = len(bodies)
+        arr = (_Mesh * nb)()
+        keep = []
+        for i, b in enumerate(bodies):
+            m, k = _mesh(b["vertices"], b["triangles"])
+            arr[i] = m
+            keep.append(k)
+        E = np.ascontiguousarray([float(b["E"]) for b in bodies])
+        nu = np.ascontiguousarray([float(b["nu"]) for b in bodies])
+        eps = np.ascontiguousarray([float(b["eps"]) for b in bodies])
+        h = C.c_void_p()
+        _check(lib().hmat_build_batch(nb, C.cast(arr, C.c_void_p), E.ctypes.data, nu.ctypes.data,
+                                      eps.ctypes.data, float(eta), int(leaf), _stream(stream),
+                                      C.byref(h)))
+        self = cls.__new__(cls)
+        self._h = h
+        self.n_triangles = int(sum(int(np.asarray(b["triangles"]).shape[0]) for b in bodies))
+        self.n_dof = 3 * self.n_triangles
+        return self
+
+    def bodies(self) -> np.ndarray:
+        """DOF offsets of the bodies: [n_bodies + 1], last entry n_dof."""
+        n = C.c_int32(0)
+        _check(lib().hmat_bodies(self._h, C.byref(n), None))
+        off = np.zeros(n.value + 1, dtype=np.int64)
+        _check(lib().hmat_bodies(self._h, C.byref(n), off.ctypes.data))
+        return off
 
     def close(self):
         if getattr(self, "_h", None):

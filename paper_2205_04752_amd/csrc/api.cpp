@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <deque>
 #include <new>
 #include <numeric>
 #include <string>
@@ -20,7 +21,7 @@ namespace hm {
 hipError_t launch_self(const DevGeo&, const SelfTask*, double*, hipStream_t);
 hipError_t launch_near_only(const DevGeo&, const NearTask*, int, double*, hipStream_t);
 hipError_t launch_entries(const DevGeo&, int64_t, const int64_t*, const int64_t*, double*, hipStream_t);
-hipError_t launch_aca(const DevGeo&, const AcaTask*, int, size_t, double, int32_t*, int32_t*, double*, hipStream_t);
+hipError_t launch_aca(const DevGeo&, const AcaTask*, int, size_t, int32_t*, int32_t*, double*, hipStream_t);
 hipError_t launch_compact(const CopyTask*, int, hipStream_t);
 hipError_t launch_to_stream(const StreamTask*, int, double*, hipStream_t);
 hipError_t launch_from_stream(const StreamTask*, int, const double*, hipStream_t);
@@ -117,10 +118,19 @@ double ms_since(std::chrono::steady_clock::time_point t0) {
 struct hmat {
   int device = 0;
   Plan plan;
-  double E = 0, nu = 0, eta = 0, eps = 0;
+  double eta = 0;
   int32_t leaf = 0;
   int64_t N = 0;
-  DevBuf d_cen, d_q, d_vtx, d_gl, d_order;
+  // Bodies: one H-matrix per body, laid out block-diagonally in one handle.
+  // Body b owns triangles [tri_off, tri_off + nt) and DOFs [3 tri_off, ...)
+  // both in the caller's numbering and in cluster order.
+  struct Body {
+    int32_t tri_off, nt;
+    double E, nu, eps;
+  };
+  std::vector<Body> bodies;
+  std::vector<int32_t> pos_body;  // cluster position -> body
+  DevBuf d_cen, d_q, d_vtx, d_gl, d_order, d_kc;
   DevGeo G{};
   std::vector<int32_t> inv_order;  // caller's triangle -> cluster position
   // block bookkeeping (canonical order)
@@ -132,7 +142,7 @@ struct hmat {
   std::vector<PanelShape> far_vshape;
   DevBuf far_arena;                 // V factors (panel layout)
   DevBuf stream;                    // U factors and dense blocks in product order
-  DevBuf piv1, piv2;
+  std::deque<DevBuf> piv_bufs;          // ACA pivots, one buffer per pass and group
   std::vector<const int32_t*> piv_ptr;  // per far block: device [2][cap]
   std::vector<int32_t> piv_cap;
   int aca_passes = 0;
@@ -457,11 +467,15 @@ void fill_stats(hmat* h) {
   if (h->far_blocks.empty()) st.rank_min = 0;
   st.rank_mean = h->far_blocks.empty() ? 0.0 : rs / h->far_blocks.size();
   for (int32_t b : h->near_blocks) st.near_scalars += block_m(h, b) * block_n(h, b);
-  st.compression = (double)(st.far_scalars + st.near_scalars) / ((double)h->N * (double)h->N);
+  double dense = 0.0;  // sum over bodies of n_dof^2
+  for (const hmat::Body& B : h->bodies) dense += 9.0 * (double)B.nt * (double)B.nt;
+  st.compression = (double)(st.far_scalars + st.near_scalars) / dense;
   st.aca_passes = h->aca_passes;
+  size_t piv_bytes = 0;
+  for (const DevBuf& d : h->piv_bufs) piv_bytes += d.bytes;
   st.device_bytes = (int64_t)(h->d_cen.bytes + h->d_q.bytes + h->d_vtx.bytes + h->d_gl.bytes +
                               h->d_order.bytes + h->far_arena.bytes + h->stream.bytes +
-                              h->piv1.bytes + h->piv2.bytes + h->d_mvA.bytes + h->d_seg.bytes +
+                              piv_bytes + h->d_kc.bytes + h->d_mvA.bytes + h->d_seg.bytes +
                               h->cl[0].d_chunk.bytes + h->cl[0].d_tile_near.bytes + h->cl[0].d_tile_far.bytes +
                               h->cl[1].d_chunk.bytes + h->cl[1].d_tile_near.bytes + h->cl[1].d_tile_far.bytes + h->d_xp.bytes +
                               h->d_z.bytes + h->d_part.bytes + h->d_dotpart.bytes + h->d_Q.bytes +
@@ -528,6 +542,7 @@ void run_aca_pass(hmat* h, const std::vector<int32_t>& fidx, CapFn cap, DevBuf& 
     t.piv = piv.as<int32_t>() + vo;
     t.kcap = kc;
     t.blk = f;
+    t.eps = h->bodies[h->pos_body[t.t_off]].eps;
     tasks.push_back(t);
     h->piv_ptr[f] = t.piv;
     h->piv_cap[f] = kc;
@@ -537,7 +552,7 @@ void run_aca_pass(hmat* h, const std::vector<int32_t>& fidx, CapFn cap, DevBuf& 
   }
   DevBuf d_tasks;
   upload(d_tasks, tasks, s, "ACA tasks");
-  check(launch_aca(h->G, d_tasks.as<AcaTask>(), (int)tasks.size(), shmem, h->eps, d_rank.as<int32_t>(),
+  check(launch_aca(h->G, d_tasks.as<AcaTask>(), (int)tasks.size(), shmem, d_rank.as<int32_t>(),
                    d_stop.as<int32_t>(), d_ratio.as<double>(), s),
         "ACA launch");
   check(hipStreamSynchronize(s), "ACA");
@@ -562,8 +577,66 @@ void fill_stream(hmat* h, const double* near_src, const std::vector<int64_t>& ne
   check(hipStreamSynchronize(s), "stream fill");
 }
 
-hmat_status build_impl(const hmat_mesh* mesh, double E, double nu, double eta, int32_t leaf,
-                       double eps, hipStream_t s, hmat** out) {
+// One body of a build: mesh (HOST, borrowed) and its material and accuracy.
+struct BodyIn {
+  const hmat_mesh* mesh;
+  double E, nu, eps;
+};
+
+// Plans of all bodies merged into one: triangles, clusters and blocks of body
+// b follow those of bodies 0..b-1, offsets shifted; the block list stays in
+// canonical (row_off, col_off) order. The meshes are concatenated likewise.
+void merge_bodies(hmat* h, const std::vector<BodyIn>& in, double eta, int32_t leaf,
+                  std::vector<double>& allV, std::vector<int32_t>& allT) {
+  Plan& P = h->plan;
+  P = Plan{};
+  int32_t vtx_off = 0;
+  for (const BodyIn& B : in) {
+    Plan pb;
+    make_plan(B.mesh, eta, leaf, pb);
+    const int32_t tri_off = P.nt, cl_off = (int32_t)P.cl.size();
+    for (int32_t o : pb.order) P.order.push_back(o + tri_off);
+    for (Cluster c : pb.cl) {
+      c.off += tri_off;
+      if (c.son0 >= 0) {
+        c.son0 += cl_off;
+        c.son1 += cl_off;
+      }
+      P.cl.push_back(c);
+    }
+    for (BlockRec r : pb.blk) {
+      r.t += cl_off;
+      r.s += cl_off;
+      P.blk.push_back(r);
+    }
+    P.csp = std::max(P.csp, pb.csp);
+    P.depth = std::max(P.depth, pb.depth);
+    P.nt += pb.nt;
+    allV.insert(allV.end(), B.mesh->vertices, B.mesh->vertices + 3 * (size_t)B.mesh->n_vertices);
+    for (int64_t e = 0; e < 3 * (int64_t)B.mesh->n_triangles; e++) allT.push_back(B.mesh->triangles[e] + vtx_off);
+    vtx_off += B.mesh->n_vertices;
+    h->bodies.push_back(hmat::Body{tri_off, pb.nt, B.E, B.nu, B.eps});
+  }
+  h->pos_body.assign(P.nt, 0);
+  for (size_t b = 0; b < h->bodies.size(); b++)
+    std::fill(h->pos_body.begin() + h->bodies[b].tri_off,
+              h->pos_body.begin() + h->bodies[b].tri_off + h->bodies[b].nt, (int32_t)b);
+}
+
+// Bytes of first-pass ACA panels that one group may hold at once
+// (HMAT_ACA_BUDGET_MB overrides): a quarter of the free device memory, >= 1 GiB.
+int64_t aca_budget() {
+  if (const char* e = std::getenv("HMAT_ACA_BUDGET_MB")) return std::max(1L, std::atol(e)) << 20;
+  size_t fr = 0, tot = 0;
+  if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+    (void)hipGetLastError();
+    return (int64_t)1 << 30;
+  }
+  return std::max<int64_t>((int64_t)1 << 30, (int64_t)(fr / 4));
+}
+
+hmat_status build_impl(const std::vector<BodyIn>& in, double eta, int32_t leaf, hipStream_t s,
+                       hmat** out) {
   auto t0 = std::chrono::steady_clock::now();
   hmat* h = new (std::nothrow) hmat();
   if (!h) return fail(HMAT_ENOMEM, "host allocation failed");
@@ -571,27 +644,34 @@ hmat_status build_impl(const hmat_mesh* mesh, double E, double nu, double eta, i
     check(hipGetDevice(&h->device), "hipGetDevice");
     if (const char* e = std::getenv("HMAT_MV_CHUNK_KB")) h->mv_chunk_bytes = std::max(1L, std::atol(e)) * 1024;
     if (const char* e = std::getenv("HMAT_MV_UNROLL")) h->mv_unroll = std::atoi(e);
-    h->E = E;
-    h->nu = nu;
     h->eta = eta;
     h->leaf = leaf;
-    h->eps = eps;
-    make_plan(mesh, eta, leaf, h->plan);
+    std::vector<double> allV;
+    std::vector<int32_t> allT;
+    merge_bodies(h, in, eta, leaf, allV, allT);
     const Plan& P = h->plan;
     const int32_t nt = P.nt;
     h->N = 3 * (int64_t)nt;
     h->inv_order.assign(nt, 0);
     for (int32_t p = 0; p < nt; p++) h->inv_order[P.order[p]] = p;
     HostGeometry hg;
-    make_geometry(mesh, P, hg);
+    const hmat_mesh all{(int32_t)(allV.size() / 3), nt, allV.data(), allT.data()};
+    make_geometry(&all, P, hg);
     upload(h->d_cen, hg.cen, s, "geometry");
     upload(h->d_q, hg.q, s, "geometry");
     upload(h->d_vtx, hg.vtx, s, "geometry");
     upload(h->d_gl, hg.gl, s, "geometry");
     upload(h->d_order, P.order, s, "geometry");
-    const double cK = (1.0 + nu) / (8.0 * M_PI * E * (1.0 - nu));
+    std::vector<double> kc(2 * (size_t)nt);
+    for (int32_t p = 0; p < nt; p++) {
+      const hmat::Body& B = h->bodies[h->pos_body[p]];
+      const double cK = (1.0 + B.nu) / (8.0 * M_PI * B.E * (1.0 - B.nu));
+      kc[p] = cK * (3.0 - 4.0 * B.nu);
+      kc[nt + p] = cK;
+    }
+    upload(h->d_kc, kc, s, "geometry");
     h->G = DevGeo{h->d_cen.as<double>(), h->d_q.as<double>(), h->d_vtx.as<double>(),
-                  h->d_gl.as<double>(), nt, 0, cK * (3.0 - 4.0 * nu), cK};
+                  h->d_gl.as<double>(), h->d_kc.as<double>(), nt, 0, 0.0, 0.0};
     h->kind_index.assign(P.blk.size(), -1);
     for (size_t b = 0; b < P.blk.size(); b++) {
       if (P.blk[b].far) {
@@ -638,48 +718,97 @@ hmat_status build_impl(const hmat_mesh* mesh, double E, double nu, double eta, i
     check(launch_near_only(h->G, d_ntasks.as<NearTask>(), (int)ntasks.size(), near_stage.as<double>(), s), "K1 launch");
     check(launch_self(h->G, d_stasks.as<SelfTask>(), near_stage.as<double>(), s), "K1 self launch");
     check(hipEventRecord(evn.b, s), "event");
-    // K2: ACA
+    // K2: ACA in groups of far blocks (canonical order) whose first-pass
+    // panels fit the budget; each group's factors are compacted into a plain
+    // column-major staging buffer (U m x k, then V n x k) and its panels freed.
     const size_t nf = h->far_blocks.size();
     h->rank.assign(nf, 0);
     h->stop.assign(nf, 0);
     h->ratio.assign(nf, 0.0);
     h->piv_ptr.assign(nf, nullptr);
     h->piv_cap.assign(nf, 0);
-    DevBuf d_rank, d_stop, d_ratio, panels1, panels2;
+    DevBuf d_rank, d_stop, d_ratio;
     d_rank.alloc(sizeof(int32_t) * std::max<size_t>(nf, 1), "ACA ranks");
     d_stop.alloc(sizeof(int32_t) * std::max<size_t>(nf, 1), "ACA ranks");
     d_ratio.alloc(sizeof(double) * std::max<size_t>(nf, 1), "ACA ranks");
     EventPair eva;
     check(hipEventRecord(eva.a, s), "event");
-    std::vector<int32_t> all(nf);
-    std::iota(all.begin(), all.end(), 0);
     auto cap1 = [&](int32_t f) {
       const int32_t b = h->far_blocks[f];
       return (int32_t)std::min<int64_t>(std::min(block_m(h, b), block_n(h, b)), KCAP_FIRST);
     };
+    auto cap2 = [&](int32_t f) {
+      const int32_t b = h->far_blocks[f];
+      return (int32_t)std::min(block_m(h, b), block_n(h, b));
+    };
     std::vector<int32_t> capv(nf, 0);
-    std::vector<const double*> panel_ptr(nf, nullptr);
-    for (size_t f = 0; f < nf; f++) capv[f] = cap1((int32_t)f);
+    std::vector<const double*> panel_ptr(nf, nullptr), u_ptr(nf, nullptr), v_ptr(nf, nullptr);
+    std::deque<DevBuf> fstage;
+    const int64_t budget = aca_budget();
     h->aca_passes = 0;
-    if (nf > 0) {
-      run_aca_pass(h, all, cap1, panels1, h->piv1, d_rank, d_stop, d_ratio, panel_ptr, s);
-      h->aca_passes = 1;
-      check(hipMemcpy(h->rank.data(), d_rank.p, sizeof(int32_t) * nf, hipMemcpyDeviceToHost), "ranks");
-      check(hipMemcpy(h->stop.data(), d_stop.p, sizeof(int32_t) * nf, hipMemcpyDeviceToHost), "ranks");
-      std::vector<int32_t> again;
-      for (size_t f = 0; f < nf; f++)
-        if (h->stop[f] == 4) again.push_back((int32_t)f);
-      if (!again.empty()) {
-        auto cap2 = [&](int32_t f) {
-          const int32_t b = h->far_blocks[f];
-          return (int32_t)std::min(block_m(h, b), block_n(h, b));
-        };
-        for (int32_t f : again) capv[f] = cap2(f);
-        run_aca_pass(h, again, cap2, panels2, h->piv2, d_rank, d_stop, d_ratio, panel_ptr, s);
-        h->aca_passes = 2;
-        check(hipMemcpy(h->rank.data(), d_rank.p, sizeof(int32_t) * nf, hipMemcpyDeviceToHost), "ranks");
-        check(hipMemcpy(h->stop.data(), d_stop.p, sizeof(int32_t) * nf, hipMemcpyDeviceToHost), "ranks");
+    for (size_t f0 = 0; f0 < nf;) {
+      size_t f1 = f0;
+      int64_t bytes = 0;
+      while (f1 < nf) {
+        const int32_t b = h->far_blocks[f1];
+        const int64_t bb = 8 * (block_m(h, b) + block_n(h, b)) * cap1((int32_t)f1);
+        if (f1 > f0 && bytes + bb > budget) break;
+        bytes += bb;
+        f1++;
       }
+      std::vector<int32_t> grp(f1 - f0);
+      std::iota(grp.begin(), grp.end(), (int32_t)f0);
+      for (int32_t f : grp) capv[f] = cap1(f);
+      DevBuf panels1, panels2;
+      h->piv_bufs.emplace_back();
+      run_aca_pass(h, grp, cap1, panels1, h->piv_bufs.back(), d_rank, d_stop, d_ratio, panel_ptr, s);
+      h->aca_passes = std::max(h->aca_passes, 1);
+      auto fetch = [&]() {
+        check(hipMemcpy(h->rank.data() + f0, d_rank.as<int32_t>() + f0, sizeof(int32_t) * (f1 - f0),
+                        hipMemcpyDeviceToHost), "ranks");
+        check(hipMemcpy(h->stop.data() + f0, d_stop.as<int32_t>() + f0, sizeof(int32_t) * (f1 - f0),
+                        hipMemcpyDeviceToHost), "ranks");
+      };
+      fetch();
+      std::vector<int32_t> again;
+      for (int32_t f : grp)
+        if (h->stop[f] == 4) again.push_back(f);
+      if (!again.empty()) {
+        for (int32_t f : again) capv[f] = cap2(f);
+        h->piv_bufs.emplace_back();
+        run_aca_pass(h, again, cap2, panels2, h->piv_bufs.back(), d_rank, d_stop, d_ratio, panel_ptr, s);
+        h->aca_passes = 2;
+        fetch();
+      }
+      int64_t tot = 0;
+      for (int32_t f : grp) {
+        const int32_t b = h->far_blocks[f];
+        if (h->rank[f] > capv[f]) throw HipError{HMAT_EDEVICE, "internal: ACA rank beyond capacity"};
+        tot += (block_m(h, b) + block_n(h, b)) * h->rank[f];
+      }
+      fstage.emplace_back();
+      DevBuf& fs = fstage.back();
+      fs.alloc(sizeof(double) * std::max<int64_t>(tot, 1), "low-rank factors");
+      std::vector<CopyTask> ct;
+      int64_t o = 0;
+      for (int32_t f : grp) {
+        const int32_t b = h->far_blocks[f];
+        const int32_t m = (int32_t)block_m(h, b), n = (int32_t)block_n(h, b), k = h->rank[f];
+        u_ptr[f] = fs.as<double>() + o;
+        v_ptr[f] = fs.as<double>() + o + (int64_t)m * k;
+        if (k > 0) {
+          ct.push_back(CopyTask{panel_ptr[f], fs.as<double>() + o, m, k, m, 0});
+          ct.push_back(CopyTask{panel_ptr[f] + (int64_t)m * capv[f], fs.as<double>() + o + (int64_t)m * k, n, k, n, 0});
+        }
+        o += (int64_t)(m + n) * k;
+      }
+      DevBuf d_ct;
+      upload(d_ct, ct, s, "compaction tasks");
+      check(launch_compact(d_ct.as<CopyTask>(), (int)ct.size(), s), "compaction launch");
+      check(hipStreamSynchronize(s), "compaction");
+      f0 = f1;
+    }
+    if (nf > 0) {
       check(hipMemcpy(h->ratio.data(), d_ratio.p, sizeof(double) * nf, hipMemcpyDeviceToHost), "ranks");
       for (size_t f = 0; f < nf; f++)
         if (h->stop[f] == 5)
@@ -688,28 +817,27 @@ hmat_status build_impl(const hmat_mesh* mesh, double E, double nu, double eta, i
     // V factors into the panel-layout arena
     const int64_t fo = far_layout(h);
     for (size_t f = 0; f < nf; f++)
-      if (h->rank[f] > capv[f] || h->far_voff[f] + (int64_t)h->rank[f] * h->far_vshape[f].ld > fo)
+      if (h->far_voff[f] + (int64_t)h->rank[f] * h->far_vshape[f].ld > fo)
         throw HipError{HMAT_EDEVICE, "internal: low-rank arena out of range"};
     h->far_arena.alloc(sizeof(double) * std::max<int64_t>(fo, PANEL_ALIGN), "low-rank arena");
     check(hipMemsetAsync(h->far_arena.p, 0, h->far_arena.bytes, s), "low-rank arena");
     std::vector<CopyTask> ct;
     for (size_t f = 0; f < nf; f++) {
       const int32_t b = h->far_blocks[f];
-      const int32_t m = (int32_t)block_m(h, b), n = (int32_t)block_n(h, b), k = h->rank[f];
+      const int32_t n = (int32_t)block_n(h, b), k = h->rank[f];
       if (k == 0) continue;
-      ct.push_back(CopyTask{panel_ptr[f] + (int64_t)m * capv[f], h->far_arena.as<double>() + h->far_voff[f],
-                            n, k, h->far_vshape[f].ld, h->far_vshape[f].fp});
+      ct.push_back(CopyTask{v_ptr[f], h->far_arena.as<double>() + h->far_voff[f], n, k,
+                            h->far_vshape[f].ld, h->far_vshape[f].fp});
     }
     DevBuf d_ct;
     upload(d_ct, ct, s, "compaction tasks");
     check(launch_compact(d_ct.as<CopyTask>(), (int)ct.size(), s), "compaction launch");
     // product plan, then U factors and dense blocks into the stream arena
     build_product_plan(h, s);
-    fill_stream(h, near_stage.as<double>(), near_off, panel_ptr, s);
+    fill_stream(h, near_stage.as<double>(), near_off, u_ptr, s);
     check(hipEventRecord(eva.b, s), "event");
     check(hipStreamSynchronize(s), "build");
-    panels1.release();
-    panels2.release();
+    fstage.clear();
     h->st.t_near_ms = evn.ms();
     h->st.t_aca_ms = eva.ms();
     fill_stats(h);
@@ -821,7 +949,40 @@ hmat_status hmat_build(const hmat_mesh* mesh, double E, double nu, double eta, i
   st = validate_mesh(mesh, err);
   if (st != HMAT_OK) return fail(st, err);
   g_err.clear();
-  return build_impl(mesh, E, nu, eta, leaf, eps, (hipStream_t)hip_stream, out);
+  return build_impl({BodyIn{mesh, E, nu, eps}}, eta, leaf, (hipStream_t)hip_stream, out);
+}
+
+hmat_status hmat_build_batch(int32_t n_bodies, const hmat_mesh* meshes, const double* E,
+                             const double* nu, const double* eps, double eta, int32_t leaf,
+                             void* hip_stream, hmat_t* out) {
+  if (!out) return fail(HMAT_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (n_bodies < 1) return fail(HMAT_EINVAL, "n_bodies must be >= 1");
+  if (!meshes || !E || !nu || !eps) return fail(HMAT_EINVAL, "meshes, E, nu or eps is NULL");
+  std::vector<BodyIn> in;
+  int64_t nt = 0, nv = 0;
+  for (int32_t b = 0; b < n_bodies; b++) {
+    std::string err;
+    hmat_status st = validate_params(E[b], nu[b], eta, leaf, eps[b], err);
+    if (st == HMAT_OK) st = validate_mesh(&meshes[b], err);
+    if (st != HMAT_OK) return fail(st, "body " + std::to_string(b) + ": " + err);
+    nt += meshes[b].n_triangles;
+    nv += meshes[b].n_vertices;
+    in.push_back(BodyIn{&meshes[b], E[b], nu[b], eps[b]});
+  }
+  if (nt > INT32_MAX / 3 || nv > INT32_MAX) return fail(HMAT_EINVAL, "batch too large (triangles or vertices beyond 32-bit indexing)");
+  g_err.clear();
+  return build_impl(in, eta, leaf, (hipStream_t)hip_stream, out);
+}
+
+hmat_status hmat_bodies(hmat_t h, int32_t* n_bodies, int64_t* dof_off) {
+  if (!h) return fail(HMAT_EINVAL, "handle is NULL");
+  if (n_bodies) *n_bodies = (int32_t)h->bodies.size();
+  if (dof_off) {
+    for (size_t b = 0; b < h->bodies.size(); b++) dof_off[b] = 3 * (int64_t)h->bodies[b].tri_off;
+    dof_off[h->bodies.size()] = h->N;
+  }
+  return HMAT_OK;
 }
 
 hmat_status hmat_matvec(hmat_t h, int32_t nrhs, const double* x, int64_t ldx, double* y,

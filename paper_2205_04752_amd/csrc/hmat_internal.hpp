@@ -12,13 +12,18 @@ namespace hm {
 // Task and descriptor records handed to the kernels (plain data, identical
 // layout on host and device).
 
-// Geometry in cluster order p (see Geometry below); c1 = cK (3 - 4 nu), c2 = cK,
-// cK = (1+nu)/(8 pi E (1-nu)) -- Kelvin tensor S = c1 delta/|r| + c2 r r^T/|r|^3 (Sec. 4.1).
+// Geometry in cluster order p (see Geometry below). Kelvin tensor
+// S = c1 delta/|r| + c2 r r^T/|r|^3 with c1 = cK (3 - 4 nu), c2 = cK,
+// cK = (1+nu)/(8 pi E (1-nu)) (Sec. 4.1). kc holds c1 and c2 per triangle
+// (several bodies with their own E, nu may share one geometry); a kernel
+// copies the constants of the body it works on into c1, c2, which the entry
+// functions read.
 struct DevGeo {
   const double* cen;  // [3][nt]
   const double* q;    // [4][7][nt]: x, y, z, weight*area
   const double* vtx;  // [9][nt]: p0x p0y p0z p1x ... p2z
   const double* gl;   // [2][16] Gauss-Legendre nodes and weights on [0,1]
+  const double* kc;   // [2][nt]: c1, c2 of the triangle's body
   int32_t nt;
   int32_t pad;
   double c1, c2;
@@ -57,6 +62,7 @@ struct AcaTask {
   int32_t* piv;   // [2][kcap]: pivot rows, pivot columns
   int32_t kcap;
   int32_t blk;    // index into the far-block result arrays
+  double eps;     // ACA accuracy of the block's body
 };
 
 // Compaction of the V factors: copy the first k columns of a scratch panel

@@ -119,13 +119,22 @@ __device__ __forceinline__ double sym_get(const double s[6], int a, int b) {
   return (lo == 0) ? (hi == 1 ? s[3] : s[4]) : s[5];
 }
 
+// The geometry with the Kelvin constants of the body of triangle p.
+__device__ __forceinline__ DevGeo body_geo(const DevGeo& g, int p) {
+  DevGeo b = g;
+  b.c1 = g.kc[p];
+  b.c2 = g.kc[g.nt + p];
+  return b;
+}
+
 // K1: dense blocks, one workgroup per block, one thread per triangle pair.
 // D is stored in the panel layout (column-major, leading dimension ld, front
 // pad fp); consecutive threads take consecutive row triangles so the three
 // rows of a pair land in contiguous memory.
-__global__ __launch_bounds__(256) void k_near(DevGeo g, const NearTask* __restrict__ tasks,
+__global__ __launch_bounds__(256) void k_near(DevGeo g0, const NearTask* __restrict__ tasks,
                                               double* __restrict__ D) {
   const NearTask T = tasks[blockIdx.x];
+  const DevGeo g = body_geo(g0, T.t_off);
   const int ld = T.ld;
   double* __restrict__ Db = D + T.d_off + T.fp;
   const int npair = T.t_len * T.s_len;
@@ -143,11 +152,12 @@ __global__ __launch_bounds__(256) void k_near(DevGeo g, const NearTask* __restri
 }
 
 // K1 self entries: one wave per triangle, 48 angular points over the lanes.
-__global__ __launch_bounds__(256) void k_self(DevGeo g, const SelfTask* __restrict__ tasks,
+__global__ __launch_bounds__(256) void k_self(DevGeo g0, const SelfTask* __restrict__ tasks,
                                               double* __restrict__ D) {
   const int p = blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
   const int lane = threadIdx.x % WAVE;
-  if (p >= g.nt) return;
+  if (p >= g0.nt) return;
+  const DevGeo g = body_geo(g0, p);
   double s[6] = {0, 0, 0, 0, 0, 0};
   if (lane < 48) self_point(g, p, lane / 16, lane % 16, s);
 #pragma unroll
@@ -162,11 +172,12 @@ __global__ __launch_bounds__(256) void k_self(DevGeo g, const SelfTask* __restri
 }
 
 // Entries at arbitrary (row, col) DOF pairs in cluster numbering (p*3 + a).
-__global__ void k_entries(DevGeo g, int64_t n, const int64_t* __restrict__ rows,
+__global__ void k_entries(DevGeo g0, int64_t n, const int64_t* __restrict__ rows,
                           const int64_t* __restrict__ cols, double* __restrict__ out) {
   const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (k >= n) return;
   const int p = (int)(rows[k] / 3), a = (int)(rows[k] % 3);
+  const DevGeo g = body_geo(g0, p);
   const int q = (int)(cols[k] / 3), b = (int)(cols[k] % 3);
   double s[6] = {0, 0, 0, 0, 0, 0};
   if (p == q) {
@@ -270,13 +281,15 @@ __device__ int argmax_free(const double* __restrict__ u, int m, const uint32_t* 
 //   no finite pivot (5: non-finite entries; reported as an error).
 // Panels live in global memory (column-major U m x kcap, V n x kcap); the
 // coefficient row U[i, 0:k] / V[j, 0:k] and the set Z are staged in LDS.
-__global__ __launch_bounds__(ACA_T) void k_aca(DevGeo g, const AcaTask* __restrict__ tasks,
-                                               double eps, int32_t* __restrict__ rank_out,
+__global__ __launch_bounds__(ACA_T) void k_aca(DevGeo g0, const AcaTask* __restrict__ tasks,
+                                               int32_t* __restrict__ rank_out,
                                                int32_t* __restrict__ stop_out,
                                                double* __restrict__ ratio_out) {
   extern __shared__ double sh[];
   __shared__ Red R;
   const AcaTask T = tasks[blockIdx.x];
+  const DevGeo g = body_geo(g0, T.t_off);
+  const double eps = T.eps;
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
   const int m = 3 * T.t_len, n = 3 * T.s_len, kmax = min(m, n), kcap = T.kcap;
   double* __restrict__ U = T.panel;
@@ -901,7 +914,7 @@ hipError_t launch_entries(const DevGeo& g, int64_t n, const int64_t* rows, const
   return hipGetLastError();
 }
 
-hipError_t launch_aca(const DevGeo& g, const AcaTask* tasks, int ntasks, size_t shmem, double eps,
+hipError_t launch_aca(const DevGeo& g, const AcaTask* tasks, int ntasks, size_t shmem,
                       int32_t* rank, int32_t* stop, double* ratio, hipStream_t s) {
   if (shmem > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_aca),
@@ -909,7 +922,7 @@ hipError_t launch_aca(const DevGeo& g, const AcaTask* tasks, int ntasks, size_t 
     if (e != hipSuccess) return e;
   }
   if (ntasks > 0)
-    hipLaunchKernelGGL(k_aca, dim3(ntasks), dim3(ACA_T), shmem, s, g, tasks, eps, rank, stop, ratio);
+    hipLaunchKernelGGL(k_aca, dim3(ntasks), dim3(ACA_T), shmem, s, g, tasks, rank, stop, ratio);
   return hipGetLastError();
 }
 

@@ -69,6 +69,42 @@ def test_build_validation_before_device_work():
     assert L.hmat_build(C.byref(m), 1.0, 0.3, 2.0, 32, 1e-4, None, None) == H.HMAT_EINVAL
 
 
+def test_batch_validation_before_device_work():
+    L = H.lib()
+    V, T = W.icosphere(1)
+    V2, T2 = W.torus(1.0, 0.3, 12, 6)
+    arr = (H._Mesh * 2)()
+    keep = []
+    for i, (v, t) in enumerate([(V, T), (V2, T2)]):
+        m, k = _mesh_struct(v, t)
+        arr[i] = m
+        keep.append(k)
+    h = C.c_void_p(123)
+
+    def call(n, E, nu, eps, eta=2.0, leaf=32, meshes=arr):
+        E = np.ascontiguousarray(E, dtype=np.float64)
+        nu = np.ascontiguousarray(nu, dtype=np.float64)
+        eps = np.ascontiguousarray(eps, dtype=np.float64)
+        return L.hmat_build_batch(n, C.cast(meshes, C.c_void_p) if meshes is not None else None,
+                                  E.ctypes.data, nu.ctypes.data, eps.ctypes.data, eta, leaf, None,
+                                  C.byref(h))
+
+    assert call(0, [1.0], [0.3], [1e-4]) == H.HMAT_EINVAL and h.value is None
+    assert call(2, [1.0, 1.0], [0.3, 0.6], [1e-4, 1e-4]) == H.HMAT_EINVAL
+    assert "body 1" in L.hmat_last_error().decode()
+    assert call(2, [1.0, -2.0], [0.3, 0.3], [1e-4, 1e-4]) == H.HMAT_EINVAL
+    assert call(2, [1.0, 1.0], [0.3, 0.3], [1e-4, 1.5]) == H.HMAT_EINVAL
+    assert call(2, [1.0, 1.0], [0.3, 0.3], [1e-4, 1e-4], eta=0.0) == H.HMAT_EINVAL
+    assert call(2, [1.0, 1.0], [0.3, 0.3], [1e-4, 1e-4], meshes=None) == H.HMAT_EINVAL
+    T3 = T2.copy()
+    T3[0, 0] = len(V2) + 4
+    m3, k3 = _mesh_struct(V2, T3)
+    arr[1] = m3
+    assert call(2, [1.0, 1.0], [0.3, 0.3], [1e-4, 1e-4]) == H.HMAT_EINVAL
+    assert "body 1" in L.hmat_last_error().decode()
+    assert L.hmat_bodies(None, None, None) == H.HMAT_EINVAL
+
+
 def test_other_entry_points_reject_null_handle():
     L = H.lib()
     assert L.hmat_matvec(None, 1, None, 3, None, 3, None) == H.HMAT_EINVAL

@@ -275,3 +275,43 @@ def workload_c1():
     V, T = icosphere(5)
     return dict(name="icosphere-L5", vertices=V, triangles=T, E=1.0, nu=0.3, eta=2.0,
                 leaf=32, eps=1e-6, nrhs=16)
+
+
+def batch_bodies(n_bodies: int = 96, n_lo: int = 2000, n_hi: int = 40000, seed: int = 2,
+                 eps: float = 1e-5):
+    """Independent bodies for one batched build: ellipsoids and tori.
+
+    Per body, from NumPy PCG64 ``default_rng(seed)`` in this order: the kind
+    (ellipsoid if a uniform draw is < 1/2, else torus), a target triangle count
+    n log-uniform in [n_lo, n_hi], then the shape -- ellipsoid: semi-axes
+    uniform in [0.5, 2] (three draws), a geodesic sphere of frequency
+    round(sqrt(n/20)); torus: R = 1, r uniform in [0.2, 0.5], an n_u x n_v grid
+    with n_v = round(sqrt(n r / 2)), n_u = round(n / (2 n_v)) -- and Poisson's
+    ratio uniform in [0.2, 0.45]. E = 1 and the given eps for every body.
+    """
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n_bodies):
+        is_ell = rng.random() < 0.5
+        n = float(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi))))
+        if is_ell:
+            axes = rng.uniform(0.5, 2.0, 3)
+            f = max(1, int(round(np.sqrt(n / 20.0))))
+            V, T = ellipsoid(f, axes)
+            kind = "ellipsoid"
+        else:
+            r = float(rng.uniform(0.2, 0.5))
+            nv = max(3, int(round(np.sqrt(n * r / 2.0))))
+            nu_ = max(3, int(round(n / (2.0 * nv))))
+            V, T = torus(1.0, r, nu_, nv)
+            kind = "torus"
+        pr = float(rng.uniform(0.2, 0.45))
+        out.append(dict(kind=kind, vertices=V, triangles=T, E=1.0, nu=pr, eps=eps))
+    return out
+
+
+def workload_c2():
+    """96 bodies (ellipsoids and tori, 2k-40k triangles, log-uniform), eps 1e-5,
+    8 right-hand sides per body; eta 2, leaf 32."""
+    return dict(name="batch96", bodies=batch_bodies(96, 2000, 40000, seed=2, eps=1e-5), eta=2.0,
+                leaf=32, nrhs=8)
