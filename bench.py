@@ -93,12 +93,105 @@ def measured_traffic(kernel_tag: str):
     return None
 
 
+def bench_batch(args):
+    """Batched workload: 96 independent bodies (ellipsoids and tori, 2k-40k
+    triangles), eps 1e-5, one handle. Step = batched build + 8-vector products
+    (8 right-hand sides per body) + single-vector products. Value: algorithmic
+    bytes of one 8-vector product 8 (sum_far k(m+n) + sum_near m n) + 16 N 8
+    over its mean time."""
+    import numpy as np
+    import torch
+    import workloads as W
+    import paper_2205_04752_amd as H
+
+    wl = W.workload_c2()
+    bodies = wl["bodies"]
+    nrhs = wl["nrhs"]
+    N = 3 * sum(len(b["triangles"]) for b in bodies)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    X = torch.from_numpy(W.random_x(N, nrhs, seed=2)).to(dev)
+    Y = torch.empty_like(X)
+    stream = torch.cuda.current_stream()
+    reps = 10
+    rec = {"build_ms": [], "aca_ms": [], "near_ms": [], "mv8_ms": [], "mv1_ms": [], "phase": np.zeros(4),
+           "calls": 0, "aca_kernel_ms": [], "layout_ms": [], "plan_ms": []}
+    stats = {}
+    for k in range(args.warmup + args.steps):
+        print(f"batch96 step {k}: build", file=sys.stderr, flush=True)
+        h = H.HMatrix.batch(bodies, eta=wl["eta"], leaf=wl["leaf"])
+        st = h.info()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        ev[0].record(stream)
+        for _ in range(reps):
+            h.matvec(X, Y)
+        ev[1].record(stream)
+        h.profile(True)
+        ev[2].record(stream)
+        for r in range(reps):
+            h.matvec(X[r % nrhs], Y[r % nrhs])
+        ev[3].record(stream)
+        phases, calls = h.profile(False)
+        torch.cuda.synchronize()
+        if k >= args.warmup:
+            rec["build_ms"].append(st["t_build_ms"])
+            rec["aca_ms"].append(st["t_aca_ms"])
+            rec["near_ms"].append(st["t_near_ms"])
+            rec["aca_kernel_ms"].append(st["t_aca_kernel_ms"])
+            rec["layout_ms"].append(st["t_layout_ms"])
+            rec["plan_ms"].append(st["t_plan_ms"])
+            rec["mv8_ms"].append(ev[0].elapsed_time(ev[1]) / reps)
+            rec["mv1_ms"].append(ev[2].elapsed_time(ev[3]) / reps)
+            rec["phase"] += phases
+            rec["calls"] += calls
+            stats.update(st)
+        h.close()
+    stored = stats["far_u_scalars"] + stats["far_v_scalars"] + stats["near_scalars"]
+    b8 = 8 * stored + 16 * N * nrhs
+    b1 = 8 * stored + 16 * N
+    mv8 = float(np.mean(rec["mv8_ms"]))
+    mv1 = float(np.mean(rec["mv1_ms"]))
+    ph = rec["phase"] / max(rec["calls"], 1)
+    out = {
+        "metric": "batched H-matvec GB/s, 8 right-hand sides per body",
+        "value": round(b8 / (mv8 * 1e-3) / 1e9, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "higher_is_better": True,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wl["name"], "n_bodies": len(bodies), "n_dof": N,
+                   "n_triangles": N // 3, "eps": 1e-5, "eta": wl["eta"], "leaf": wl["leaf"],
+                   "nrhs": nrhs},
+        "matvec8_ms": round(mv8, 4),
+        "matvec8_vectors_per_s": round(nrhs / (mv8 * 1e-3), 1),
+        "matvec1_ms": round(mv1, 4),
+        "matvec1_gbs": round(b1 / (mv1 * 1e-3) / 1e9, 2),
+        "phase_ms_single": [round(float(v), 4) for v in ph],
+        "build_ms": round(float(np.mean(rec["build_ms"])), 1),
+        "build_aca_ms": round(float(np.mean(rec["aca_ms"])), 1),
+        "build_near_ms": round(float(np.mean(rec["near_ms"])), 1),
+        "build_aca_kernel_ms": round(float(np.mean(rec["aca_kernel_ms"])), 1),
+        "build_layout_ms": round(float(np.mean(rec["layout_ms"])), 1),
+        "build_plan_ms": round(float(np.mean(rec["plan_ms"])), 1),
+        "aca_groups": stats["aca_groups"],
+        "hmatrix": {"n_blocks": stats["n_blocks"], "n_far": stats["n_far"],
+                    "rank_mean": round(stats["rank_mean"], 2), "rank_max": stats["rank_max"],
+                    "stored_scalars": stored, "device_bytes": stats["device_bytes"],
+                    "compression": round(stats["compression"], 5)},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["icosphere-L5", "icosphere-L3"], default="icosphere-L5")
+    ap.add_argument("--workload", choices=["icosphere-L5", "icosphere-L3", "batch96"],
+                    default="icosphere-L5")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=5.0)
     ap.add_argument("--solves", type=int, default=4, help="GMRES solves per step")
@@ -116,6 +209,9 @@ def main():
     import workloads as W
     import paper_2205_04752_amd as H
 
+    if args.workload == "batch96":
+        bench_batch(args)
+        return
     wl = W.workload_c1() if args.workload == "icosphere-L5" else W.workload_c0()
     V, T = wl["vertices"], wl["triangles"]
     N = 3 * len(T)

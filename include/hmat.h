@@ -91,6 +91,10 @@ typedef struct {
   int64_t device_bytes;   /* persistent device memory held by the handle */
   int64_t far_u_scalars;  /* sum over admissible blocks of m k (the U factors) */
   int64_t far_v_scalars;  /* sum over admissible blocks of n k (the V factors) */
+  double t_aca_kernel_ms; /* device: the ACA kernels alone (all groups and passes) */
+  double t_layout_ms;     /* host + device: compaction, product plan, stream fill */
+  int32_t aca_groups;     /* groups of admissible blocks ACA ran in (memory budget) */
+  int32_t n_bodies;       /* bodies in the handle (hmat_build_batch) */
 } hmat_stats;
 
 typedef struct {

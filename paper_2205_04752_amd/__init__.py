@@ -42,7 +42,8 @@ class _Stats(C.Structure):
                 ("aca_passes", C.c_int32), ("reserved", C.c_int32), ("t_plan_ms", C.c_double),
                 ("t_near_ms", C.c_double), ("t_aca_ms", C.c_double), ("t_build_ms", C.c_double),
                 ("device_bytes", C.c_int64), ("far_u_scalars", C.c_int64),
-                ("far_v_scalars", C.c_int64)]
+                ("far_v_scalars", C.c_int64), ("t_aca_kernel_ms", C.c_double),
+                ("t_layout_ms", C.c_double), ("aca_groups", C.c_int32), ("n_bodies", C.c_int32)]
 
 
 class _SolveInfo(C.Structure):

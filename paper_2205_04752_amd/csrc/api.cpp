@@ -8,6 +8,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdlib>
+#include <cstdio>
 #include <cstring>
 #include <deque>
 #include <new>
@@ -471,6 +472,7 @@ void fill_stats(hmat* h) {
   for (const hmat::Body& B : h->bodies) dense += 9.0 * (double)B.nt * (double)B.nt;
   st.compression = (double)(st.far_scalars + st.near_scalars) / dense;
   st.aca_passes = h->aca_passes;
+  st.n_bodies = (int32_t)h->bodies.size();
   size_t piv_bytes = 0;
   for (const DevBuf& d : h->piv_bufs) piv_bytes += d.bytes;
   st.device_bytes = (int64_t)(h->d_cen.bytes + h->d_q.bytes + h->d_vtx.bytes + h->d_gl.bytes +
@@ -499,6 +501,19 @@ struct EventPair {
   }
 };
 
+// Build phase timing on stderr when HMAT_TRACE_BUILD is set (synchronises
+// the stream at every mark, so device work is charged to its phase).
+struct BuildTrace {
+  bool on = std::getenv("HMAT_TRACE_BUILD") != nullptr;
+  std::chrono::steady_clock::time_point last = std::chrono::steady_clock::now();
+  void mark(const char* what, hipStream_t s) {
+    if (!on) return;
+    (void)hipStreamSynchronize(s);
+    std::fprintf(stderr, "hmat build: %-28s %9.1f ms\n", what, ms_since(last));
+    last = std::chrono::steady_clock::now();
+  }
+};
+
 // One ACA pass over the far blocks listed in `fidx` (largest first) with
 // per-block capacity cap(f); panels in `panels`, pivots in `piv`.
 template <class CapFn>
@@ -523,7 +538,7 @@ void run_aca_pass(hmat* h, const std::vector<int32_t>& fidx, CapFn cap, DevBuf& 
     shmem = std::max(shmem, (size_t)kc * 8 + (size_t)((m + 31) / 32) * 4);
   }
   if (shmem > 160 * 1024) throw HipError{HMAT_ENOTSUP, "ACA panel row exceeds LDS capacity"};
-  panels.alloc(sizeof(double) * panel_total, "ACA panels");
+  if (panels.bytes < sizeof(double) * panel_total) panels.alloc(sizeof(double) * panel_total, "ACA panels");
   piv.alloc(sizeof(int32_t) * piv_total, "ACA pivots");
   std::vector<AcaTask> tasks;
   tasks.reserve(ord.size());
@@ -552,10 +567,14 @@ void run_aca_pass(hmat* h, const std::vector<int32_t>& fidx, CapFn cap, DevBuf& 
   }
   DevBuf d_tasks;
   upload(d_tasks, tasks, s, "ACA tasks");
+  EventPair ev;
+  check(hipEventRecord(ev.a, s), "event");
   check(launch_aca(h->G, d_tasks.as<AcaTask>(), (int)tasks.size(), shmem, d_rank.as<int32_t>(),
                    d_stop.as<int32_t>(), d_ratio.as<double>(), s),
         "ACA launch");
+  check(hipEventRecord(ev.b, s), "event");
   check(hipStreamSynchronize(s), "ACA");
+  h->st.t_aca_kernel_ms += ev.ms();
 }
 
 // Fill the stream arena from plain column-major sources of the dense blocks
@@ -746,6 +765,9 @@ hmat_status build_impl(const std::vector<BodyIn>& in, double eta, int32_t leaf, 
     std::deque<DevBuf> fstage;
     const int64_t budget = aca_budget();
     h->aca_passes = 0;
+    DevBuf panels1;  // first-pass panels, reused by every group
+    BuildTrace tr;
+    tr.mark("plan, geometry, K1", s);
     for (size_t f0 = 0; f0 < nf;) {
       size_t f1 = f0;
       int64_t bytes = 0;
@@ -759,7 +781,7 @@ hmat_status build_impl(const std::vector<BodyIn>& in, double eta, int32_t leaf, 
       std::vector<int32_t> grp(f1 - f0);
       std::iota(grp.begin(), grp.end(), (int32_t)f0);
       for (int32_t f : grp) capv[f] = cap1(f);
-      DevBuf panels1, panels2;
+      DevBuf panels2;
       h->piv_bufs.emplace_back();
       run_aca_pass(h, grp, cap1, panels1, h->piv_bufs.back(), d_rank, d_stop, d_ratio, panel_ptr, s);
       h->aca_passes = std::max(h->aca_passes, 1);
@@ -806,8 +828,12 @@ hmat_status build_impl(const std::vector<BodyIn>& in, double eta, int32_t leaf, 
       upload(d_ct, ct, s, "compaction tasks");
       check(launch_compact(d_ct.as<CopyTask>(), (int)ct.size(), s), "compaction launch");
       check(hipStreamSynchronize(s), "compaction");
+      h->st.aca_groups++;
       f0 = f1;
+      tr.mark("ACA group", s);
     }
+    panels1.release();
+    const auto t_layout = std::chrono::steady_clock::now();
     if (nf > 0) {
       check(hipMemcpy(h->ratio.data(), d_ratio.p, sizeof(double) * nf, hipMemcpyDeviceToHost), "ranks");
       for (size_t f = 0; f < nf; f++)
@@ -832,11 +858,15 @@ hmat_status build_impl(const std::vector<BodyIn>& in, double eta, int32_t leaf, 
     DevBuf d_ct;
     upload(d_ct, ct, s, "compaction tasks");
     check(launch_compact(d_ct.as<CopyTask>(), (int)ct.size(), s), "compaction launch");
+    tr.mark("V arena", s);
     // product plan, then U factors and dense blocks into the stream arena
     build_product_plan(h, s);
+    tr.mark("product plan", s);
     fill_stream(h, near_stage.as<double>(), near_off, u_ptr, s);
+    tr.mark("stream fill", s);
     check(hipEventRecord(eva.b, s), "event");
     check(hipStreamSynchronize(s), "build");
+    h->st.t_layout_ms = ms_since(t_layout);
     fstage.clear();
     h->st.t_near_ms = evn.ms();
     h->st.t_aca_ms = eva.ms();
