@@ -148,15 +148,16 @@ struct hmat {
   std::vector<int32_t> piv_cap;
   int aca_passes = 0;
   // product plan
-  DevBuf d_mvA, d_seg;
-  // Phase-B chunk lists cut from the same segment order: [0] for single
-  // right-hand sides (small chunks, short tail), [1] for several (larger
-  // chunks: the partial sums grow with the number of vectors).
+  DevBuf d_seg;
+  // Work lists: [0] for single right-hand sides (8-column phase-A items,
+  // small chunks, short tail), [1] for several (64-column items for the
+  // matrix cores; larger chunks, as the partial sums grow with the number of
+  // vectors). Both chunk lists are cut from the same segment order.
   struct ChunkList {
-    DevBuf d_chunk, d_tile_near, d_tile_far;
-    int n = 0, n_near = 0;
+    DevBuf d_items, d_chunk, d_tile_near, d_tile_far;
+    int nA = 0, n = 0, n_near = 0;
   } cl[2];
-  int nA = 0, nSeg = 0, nTiles = 0;
+  int nSeg = 0, nTiles = 0;
   int64_t Ztot = 0, ldxp = 0, stream_n = 0;
   std::vector<MvSeg> segs;                       // host copy, product order
   std::vector<int32_t> seg_tile;                 // tile of each segment
@@ -217,7 +218,10 @@ int64_t far_layout(hmat* h) {
 // of about MV_CHUNK_BYTES per tile. Sets stream_n; uploads the plan.
 void build_product_plan(hmat* h, hipStream_t s) {
   const Plan& P = h->plan;
-  std::vector<MvA> items;
+  // Phase-A items: groups of <= 8 columns of one V panel for one vector, of
+  // <= 64 (four matrix-core tiles, sharing each load of the vectors) for
+  // several; largest first.
+  std::vector<MvA> items_l[2];
   std::vector<int64_t> zoff(h->far_blocks.size(), 0);
   int64_t z = 0;
   for (size_t f = 0; f < h->far_blocks.size(); f++) {
@@ -227,14 +231,18 @@ void build_product_plan(hmat* h, hipStream_t s) {
     if (k == 0) continue;
     const int64_t R0 = 3 * (int64_t)P.cl[P.blk[b].s].off;
     const PanelShape& V = h->far_vshape[f];
-    for (int32_t l0 = 0; l0 < k; l0 += 8)
-      items.push_back(MvA{h->far_voff[f], V.ld, l0, std::min(k, l0 + 8), (int32_t)(R0 - V.fp),
-                          (int32_t)(z + l0), 0});
+    for (int l = 0; l < 2; l++) {
+      const int32_t w = l == 0 ? 8 : 64;
+      for (int32_t l0 = 0; l0 < k; l0 += w)
+        items_l[l].push_back(MvA{h->far_voff[f], V.ld, l0, std::min(k, l0 + w), (int32_t)(R0 - V.fp),
+                                 (int32_t)(z + l0), 0});
+    }
     z += k;
   }
-  std::stable_sort(items.begin(), items.end(), [](const MvA& a, const MvA& b) {
-    return (int64_t)a.ld * (a.l1 - a.l0) > (int64_t)b.ld * (b.l1 - b.l0);
-  });
+  for (auto& items : items_l)
+    std::stable_sort(items.begin(), items.end(), [](const MvA& a, const MvA& b) {
+      return (int64_t)a.ld * (a.l1 - a.l0) > (int64_t)b.ld * (b.l1 - b.l0);
+    });
   h->Ztot = std::max<int64_t>(round_up(z, 2), 2);
   // Column groups: the low-rank blocks of one row cluster (consecutive in
   // canonical order, so their z entries are contiguous) form one group whose
@@ -362,12 +370,14 @@ void build_product_plan(hmat* h, hipStream_t s) {
   {
     const int64_t far_n = (int64_t)(h->far_arena.bytes / sizeof(double));
     auto bad = [](const char* what) { throw HipError{HMAT_EDEVICE, std::string("internal: product plan: ") + what}; };
-    for (const MvA& I : items) {
-      if (I.v_off < 0 || I.v_off % 2 || I.ld % 2 || I.a0 % 2 || I.a0 < 0) bad("phase A alignment");
-      if (I.v_off + (int64_t)I.l1 * I.ld > far_n) bad("phase A matrix range");
-      if ((int64_t)I.a0 + I.ld > h->ldxp) bad("phase A vector range");
-      if ((int64_t)I.zoff + (I.l1 - I.l0) > h->Ztot) bad("phase A output range");
-    }
+    for (const auto& items : items_l)
+      for (const MvA& I : items) {
+        if (I.v_off < 0 || I.v_off % 2 || I.ld % 2 || I.a0 % 2 || I.a0 < 0) bad("phase A alignment");
+        if (I.l0 < 0 || I.l1 <= I.l0 || I.l1 - I.l0 > 64) bad("phase A columns");
+        if (I.v_off + (int64_t)I.l1 * I.ld > far_n) bad("phase A matrix range");
+        if ((int64_t)I.a0 + I.ld > h->ldxp) bad("phase A vector range");
+        if ((int64_t)I.zoff + (I.l1 - I.l0) > h->Ztot) bad("phase A output range");
+      }
     for (const MvSeg& sg : h->segs) {
       if (sg.row_lo < 0 || sg.row_hi > MV_TILE || sg.row_lo >= sg.row_hi || sg.row_lo % 2) bad("phase B rows");
       if (sg.so % 2 || sg.so < 0) bad("phase B alignment");
@@ -381,11 +391,11 @@ void build_product_plan(hmat* h, hipStream_t s) {
         if (tn_l[l][T + 1] <= tn_l[l][T] || tf_l[l][T + 1] < tf_l[l][T]) bad("tile chunk ranges");
     }
   }
-  h->nA = (int)items.size();
   h->nSeg = (int)h->segs.size();
-  upload(h->d_mvA, items, s, "product plan");
   upload(h->d_seg, h->segs, s, "product plan");
   for (int l = 0; l < 2; l++) {
+    upload(h->cl[l].d_items, items_l[l], s, "product plan");
+    h->cl[l].nA = (int)items_l[l].size();
     upload(h->cl[l].d_chunk, chunk_l[l], s, "product plan");
     upload(h->cl[l].d_tile_near, tn_l[l], s, "product plan");
     upload(h->cl[l].d_tile_far, tf_l[l], s, "product plan");
@@ -477,7 +487,7 @@ void fill_stats(hmat* h) {
   for (const DevBuf& d : h->piv_bufs) piv_bytes += d.bytes;
   st.device_bytes = (int64_t)(h->d_cen.bytes + h->d_q.bytes + h->d_vtx.bytes + h->d_gl.bytes +
                               h->d_order.bytes + h->far_arena.bytes + h->stream.bytes +
-                              piv_bytes + h->d_kc.bytes + h->d_mvA.bytes + h->d_seg.bytes +
+                              piv_bytes + h->d_kc.bytes + h->cl[0].d_items.bytes + h->cl[1].d_items.bytes + h->d_seg.bytes +
                               h->cl[0].d_chunk.bytes + h->cl[0].d_tile_near.bytes + h->cl[0].d_tile_far.bytes +
                               h->cl[1].d_chunk.bytes + h->cl[1].d_tile_near.bytes + h->cl[1].d_tile_far.bytes + h->d_xp.bytes +
                               h->d_z.bytes + h->d_part.bytes + h->d_dotpart.bytes + h->d_Q.bytes +
@@ -918,8 +928,9 @@ void matvec_impl(hmat* h, int32_t nrhs, const double* x, int64_t ldx, double* y,
           "gather");
     if (ev) check(hipEventRecord(ev[1], s), "profile");
     ProductPlanDev P{};
-    P.items = h->d_mvA.as<MvA>();
+
     const hmat::ChunkList& CL = h->cl[nr > 1 ? 1 : 0];
+    P.items = CL.d_items.as<MvA>();
     P.chunks = CL.d_chunk.as<MvChunk>();
     P.segs = h->d_seg.as<MvSeg>();
     P.tile_near = CL.d_tile_near.as<int32_t>();
@@ -927,7 +938,7 @@ void matvec_impl(hmat* h, int32_t nrhs, const double* x, int64_t ldx, double* y,
     P.order = h->d_order.as<int32_t>();
     P.far = h->far_arena.as<double>();
     P.stream = h->stream.as<double>();
-    P.nA = h->nA;
+    P.nA = CL.nA;
     P.n_near_chunks = CL.n_near;
     P.n_far_chunks = CL.n - CL.n_near;
     P.ntiles = h->nTiles;

@@ -681,6 +681,198 @@ __global__ __launch_bounds__(WAVE* MV_WPB) void k_mv2(int c_first, int n,
   mv_b_chunk<NR, UNR>(chunks[c], c, segs, stream, z, ldz, xp, ldxp, nr, part);
 }
 
+// ---------------------------------------------------------------------------
+// Several right-hand sides (2..16): the two contractions V^T X and U Z (and
+// D X) on the FP64 matrix cores. v_mfma_f64_16x16x4f64 computes
+// D += A B with A 16x4, B 4x16; lane l holds A[l%16][l/16], B[l/16][l%16]
+// and D[4v + l/16][l%16] in item v (v = 0..3). The right-hand sides are the
+// 16 columns of B (lanes with l%16 >= nr carry zeros). To let every lane load
+// four consecutive matrix rows with two 16-byte loads, the four products of a
+// group take rows 4m + t (t = 0..3) in place of row m: a permutation of the
+// summation (phase A) or of the output rows (phase B), undone when storing.
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ v4d mfma4(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Phase A, several vectors: z[:, zoff + c] = V[:, l0 + c]^T X for c < l1 - l0
+// (<= 64 columns: four 16-column tiles). Per 16-row step lane l reads rows
+// 4(l/16) .. +3 of column l%16 of each tile and the same rows of vector l%16.
+__device__ __forceinline__ void mv_a_mfma(const MvA& I, const double* __restrict__ far,
+                                          const double* __restrict__ xp, int64_t ldxp, int nr,
+                                          double* __restrict__ z, int64_t ldz) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int kq = lane >> 4, cl = lane & 15;
+  const int ncols = I.l1 - I.l0;
+  const int ntile = (ncols + 15) >> 4;
+  const bool rv = cl < nr;
+  const double* __restrict__ X = xp + (int64_t)min(cl, nr - 1) * ldxp + I.a0;
+  const double* Vc[4];
+  bool cv[4];
+#pragma unroll
+  for (int q = 0; q < 4; q++) {
+    const int col = q * 16 + cl;
+    cv[q] = col < ncols;
+    Vc[q] = far + I.v_off + (int64_t)(I.l0 + min(col, ncols - 1)) * I.ld;
+  }
+  v4d acc[4];
+#pragma unroll
+  for (int q = 0; q < 4; q++) acc[q] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int i0 = 0; i0 < I.ld; i0 += 16) {
+    const int r0 = i0 + 4 * kq;
+    const bool p0 = r0 < I.ld, p1 = r0 + 2 < I.ld;  // ld and r0 even: pairs are whole
+    double2 x0 = *reinterpret_cast<const double2*>(X + (p0 ? r0 : 0));
+    double2 x1 = *reinterpret_cast<const double2*>(X + (p1 ? r0 + 2 : 0));
+    const bool b0 = rv && p0, b1 = rv && p1;
+    x0.x = b0 ? x0.x : 0.0;
+    x0.y = b0 ? x0.y : 0.0;
+    x1.x = b1 ? x1.x : 0.0;
+    x1.y = b1 ? x1.y : 0.0;
+    double2 a0[4], a1[4];
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      if (q < ntile) {
+        a0[q] = *reinterpret_cast<const double2*>(Vc[q] + (p0 ? r0 : 0));
+        a1[q] = *reinterpret_cast<const double2*>(Vc[q] + (p1 ? r0 + 2 : 0));
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      if (q < ntile) {
+        const bool ok = cv[q];
+        acc[q] = mfma4(ok ? a0[q].x : 0.0, x0.x, acc[q]);
+        acc[q] = mfma4(ok ? a0[q].y : 0.0, x0.y, acc[q]);
+        acc[q] = mfma4(ok ? a1[q].x : 0.0, x1.x, acc[q]);
+        acc[q] = mfma4(ok ? a1[q].y : 0.0, x1.y, acc[q]);
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; q++) {
+    if (q < ntile) {
+#pragma unroll
+      for (int v = 0; v < 4; v++) {
+        const int col = q * 16 + 4 * v + kq;
+        if (col < ncols && rv) z[(int64_t)cl * ldz + I.zoff + col] = acc[q][v];
+      }
+    }
+  }
+}
+
+// Phase B, several vectors: one chunk (segments of one 128-row tile). Per
+// group of four columns c..c+3, lane l reads rows 4(l%16) .. +3 of column
+// c + l/16 in each 64-row half the segment touches, and entry c + l/16 of
+// vector l%16. Product t of a half accumulates tile rows 64h + 4m + t.
+// Writes part[chunk][16][128].
+__device__ __forceinline__ void mv_b_mfma(const MvChunk& C, int chunk,
+                                          const MvSeg* __restrict__ segs,
+                                          const double* __restrict__ stream,
+                                          const double* __restrict__ z, int64_t ldz,
+                                          const double* __restrict__ xp, int64_t ldxp, int nr,
+                                          double* __restrict__ part) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int kq = lane >> 4, m16 = lane & 15;
+  const bool rv = m16 < nr;
+  v4d acc[2][4];
+#pragma unroll
+  for (int h = 0; h < 2; h++)
+#pragma unroll
+    for (int t = 0; t < 4; t++) acc[h][t] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int s = C.seg_lo; s < C.seg_hi; s++) {
+    const MvSeg S = segs[s];
+    const int len = S.row_hi - S.row_lo;
+    const double* __restrict__ Bp =
+        (S.far ? z + (int64_t)min(m16, nr - 1) * ldz : xp + (int64_t)min(m16, nr - 1) * ldxp) + S.soff;
+    const bool h0 = S.row_lo < 64, h1 = S.row_hi > 64;  // halves the segment touches
+    // this lane's rows in each half, relative to the segment (pairs are whole: bounds are even)
+    const int R0 = 4 * m16 - S.row_lo, R1 = 64 + 4 * m16 - S.row_lo;
+    const bool q00 = R0 >= 0 && R0 < len, q01 = R0 + 2 >= 0 && R0 + 2 < len;
+    const bool q10 = R1 >= 0 && R1 < len, q11 = R1 + 2 >= 0 && R1 + 2 < len;
+    // batches of 16 columns (four groups of four): all loads first
+    for (int c = S.c0; c < S.c1; c += 16) {
+      double bv[4];
+      double2 av[4][2][2];
+#pragma unroll
+      for (int g = 0; g < 4; g++) {
+        const int cc = c + 4 * g + kq;
+        const bool cok = cc < S.c1;
+        const int ccl = cok ? cc : S.c1 - 1;
+        const double* __restrict__ col = stream + S.so + (int64_t)(ccl - S.c0) * len;
+        bv[g] = Bp[ccl];
+        bv[g] = (cok && rv) ? bv[g] : 0.0;
+        if (h0) {
+          av[g][0][0] = *reinterpret_cast<const double2*>(col + (q00 ? R0 : 0));
+          av[g][0][1] = *reinterpret_cast<const double2*>(col + (q01 ? R0 + 2 : 0));
+        }
+        if (h1) {
+          av[g][1][0] = *reinterpret_cast<const double2*>(col + (q10 ? R1 : 0));
+          av[g][1][1] = *reinterpret_cast<const double2*>(col + (q11 ? R1 + 2 : 0));
+        }
+      }
+#pragma unroll
+      for (int g = 0; g < 4; g++) {
+        if (h0) {
+          acc[0][0] = mfma4(q00 ? av[g][0][0].x : 0.0, bv[g], acc[0][0]);
+          acc[0][1] = mfma4(q00 ? av[g][0][0].y : 0.0, bv[g], acc[0][1]);
+          acc[0][2] = mfma4(q01 ? av[g][0][1].x : 0.0, bv[g], acc[0][2]);
+          acc[0][3] = mfma4(q01 ? av[g][0][1].y : 0.0, bv[g], acc[0][3]);
+        }
+        if (h1) {
+          acc[1][0] = mfma4(q10 ? av[g][1][0].x : 0.0, bv[g], acc[1][0]);
+          acc[1][1] = mfma4(q10 ? av[g][1][0].y : 0.0, bv[g], acc[1][1]);
+          acc[1][2] = mfma4(q11 ? av[g][1][1].x : 0.0, bv[g], acc[1][2]);
+          acc[1][3] = mfma4(q11 ? av[g][1][1].y : 0.0, bv[g], acc[1][3]);
+        }
+      }
+    }
+  }
+  // lane holds vector m16, tile rows 64h + 16v + 4kq + t in acc[h][t][v]
+  if (rv) {
+    double* __restrict__ out = part + ((size_t)chunk * 16 + m16) * TILE;
+#pragma unroll
+    for (int h = 0; h < 2; h++)
+#pragma unroll
+      for (int v = 0; v < 4; v++) {
+        const int row = 64 * h + 16 * v + 4 * kq;
+        *reinterpret_cast<double2*>(out + row) = make_double2(acc[h][0][v], acc[h][1][v]);
+        *reinterpret_cast<double2*>(out + row + 2) = make_double2(acc[h][2][v], acc[h][3][v]);
+      }
+  }
+}
+
+__global__ __launch_bounds__(WAVE) void k_mv1_mfma(const MvA* __restrict__ items, int nA,
+                                                   int n_near_chunks,
+                                                   const MvChunk* __restrict__ chunks,
+                                                   const MvSeg* __restrict__ segs,
+                                                   const double* __restrict__ far,
+                                                   const double* __restrict__ stream,
+                                                   const double* __restrict__ xp, int64_t ldxp,
+                                                   int nr, double* __restrict__ z, int64_t ldz,
+                                                   double* __restrict__ part) {
+  const int u = __builtin_amdgcn_readfirstlane(blockIdx.x);
+  if (u < nA) {
+    mv_a_mfma(items[u], far, xp, ldxp, nr, z, ldz);
+  } else if (u < nA + n_near_chunks) {
+    const int c = u - nA;
+    mv_b_mfma(chunks[c], c, segs, stream, z, ldz, xp, ldxp, nr, part);
+  }
+}
+
+__global__ __launch_bounds__(WAVE) void k_mv2_mfma(int c_first, int n,
+                                                   const MvChunk* __restrict__ chunks,
+                                                   const MvSeg* __restrict__ segs,
+                                                   const double* __restrict__ stream,
+                                                   const double* __restrict__ z, int64_t ldz,
+                                                   const double* __restrict__ xp, int64_t ldxp,
+                                                   int nr, double* __restrict__ part) {
+  const int u = __builtin_amdgcn_readfirstlane(blockIdx.x);
+  if (u >= n) return;
+  const int c = c_first + u;
+  mv_b_mfma(chunks[c], c, segs, stream, z, ldz, xp, ldxp, nr, part);
+}
+
 // Plain column-major block matrix -> stream segment (one workgroup per segment).
 __global__ __launch_bounds__(256) void k_to_stream(const StreamTask* __restrict__ tasks,
                                                    double* __restrict__ stream) {
@@ -958,7 +1150,25 @@ static void mv_group(const ProductPlanDev& P, const double* xp, int64_t ldxp, in
   if (ev) (void)hipEventRecord(ev[2], s);
 }
 
+static void mv_group_mfma(const ProductPlanDev& P, const double* xp, int64_t ldxp, int nr,
+                          double* z, int64_t ldz, double* part, double* y, int64_t ldy,
+                          hipStream_t s, hipEvent_t* ev) {
+  const int n1 = P.nA + P.n_near_chunks;
+  if (n1 > 0)
+    hipLaunchKernelGGL(k_mv1_mfma, dim3(n1), dim3(WAVE), 0, s, P.items, P.nA, P.n_near_chunks,
+                       P.chunks, P.segs, P.far, P.stream, xp, ldxp, nr, z, ldz, part);
+  if (ev) (void)hipEventRecord(ev[0], s);
+  if (P.n_far_chunks > 0)
+    hipLaunchKernelGGL(k_mv2_mfma, dim3(P.n_far_chunks), dim3(WAVE), 0, s, P.n_near_chunks,
+                       P.n_far_chunks, P.chunks, P.segs, P.stream, z, ldz, xp, ldxp, nr, part);
+  if (ev) (void)hipEventRecord(ev[1], s);
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_reduce<16>), dim3(P.ntiles), dim3(WAVE * RED_WAVES), 0, s,
+                     P.tile_near, P.tile_far, part, nr, P.order, P.N, y, ldy);
+  if (ev) (void)hipEventRecord(ev[2], s);
+}
+
 // One pass over the matrix for nr <= 16 right-hand sides (xp already gathered).
+// One vector: the vector-ALU kernels; two to sixteen: matrix cores.
 hipError_t launch_matvec_group(const ProductPlanDev& P, int nr, const double* xp, int64_t ldxp,
                                double* z, int64_t ldz, double* part, double* y, int64_t ldy,
                                hipStream_t s, hipEvent_t* ev, int unroll) {
@@ -971,14 +1181,8 @@ hipError_t launch_matvec_group(const ProductPlanDev& P, int nr, const double* xp
   } while (0)
   if (nr <= 1)
     HM_GROUP(1);
-  else if (nr <= 2)
-    HM_GROUP(2);
-  else if (nr <= 4)
-    HM_GROUP(4);
-  else if (nr <= 8)
-    HM_GROUP(8);
   else
-    HM_GROUP(16);
+    mv_group_mfma(P, xp, ldxp, nr, z, ldz, part, y, ldy, s, ev);
 #undef HM_GROUP
   return hipGetLastError();
 }

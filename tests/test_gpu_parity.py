@@ -103,7 +103,7 @@ def test_k2_pivots_ranks_factors(c0):
     assert worst <= 1e-10, worst
 
 
-@pytest.mark.parametrize("nrhs", [1, 3, 16, 17])
+@pytest.mark.parametrize("nrhs", [1, 2, 3, 8, 16, 17])
 def test_k3_on_oracle_factors(c0, nrhs):
     H = _H()
     V, T = c0.V, c0.T
