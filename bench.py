@@ -9,7 +9,10 @@ fields (sum of 8 random degree-2 vector polynomials) at the centroids.
 One step = the whole hot path on that input:
   hmat_build (geometry, tree, partition, K1 dense blocks, K2 ACA, compaction),
   16 single-vector products, one 16-vector product, and 4 GMRES(50) solves
-  to relative residual 1e-8 (seeds 4k+1 .. 4k+4 for step k).
+  to relative residual 1e-8 (seeds 4k+1 .. 4k+4 for step k); then the
+  mixed-precision form: FP32 copies of the entries, 16 FP32-storage products
+  and the same 4 systems by iterative refinement (FP64 residuals, inner
+  GMRES(50) on the FP32 entries) to the same FP64 relative residual 1e-8.
 All inputs are resident on the GPU before the timed region starts.
 
 Reported value: H-matvec GB/s = algorithmic bytes of one product
@@ -234,7 +237,8 @@ def main():
         del src, dst
 
     rec = {"mv_ms": [], "mv16_ms": [], "solve_ms": [], "iters": [], "relres": [], "build_ms": [],
-           "phase_ms": np.zeros(4), "phase_calls": 0, "aca_ms": [], "near_ms": []}
+           "phase_ms": np.zeros(4), "phase_calls": 0, "aca_ms": [], "near_ms": [], "mv32_ms": [],
+           "ir_ms": [], "ir_iters": [], "ir_outer": [], "ir_relres": []}
     stats = {}
 
     def step(k: int, record: bool):
@@ -254,6 +258,19 @@ def main():
         for j in range(solves_per_step):
             _, info = h.solve(G[k * solves_per_step + j], tol=1e-8, restart=50, maxit=5000)
             solves.append(info)
+        # mixed precision: FP32 copies of the entries, single products and
+        # iterative-refinement solves (FP64 residuals) of the same systems
+        h.set_precision(1)
+        f0, f1 = (torch.cuda.Event(enable_timing=True) for _ in range(2))
+        f0.record(stream)
+        for r in range(nrhs):
+            h.matvec(X[r], Y[r], precision=1)
+        f1.record(stream)
+        solves_ir = []
+        for j in range(solves_per_step):
+            _, info = h.solve_ir(G[k * solves_per_step + j], tol=1e-8, restart=50, maxit=5000,
+                                 inner_precision=1, inner_tol=1e-6)
+            solves_ir.append(info)
         torch.cuda.synchronize()
         if record:
             rec["build_ms"].append(st["t_build_ms"])
@@ -267,6 +284,12 @@ def main():
                 rec["solve_ms"].append(info["time_ms"])
                 rec["iters"].append(info["iterations"])
                 rec["relres"].append(info["relres"])
+            rec["mv32_ms"].append(f0.elapsed_time(f1) / nrhs)
+            for info in solves_ir:
+                rec["ir_ms"].append(info["time_ms"])
+                rec["ir_iters"].append(info["iterations"])
+                rec["ir_outer"].append(info["refinements"])
+                rec["ir_relres"].append(info["relres"])
             stats.update(st)
         h.close()
 
@@ -316,6 +339,15 @@ def main():
         "gmres_iters_mean": round(float(np.mean(rec["iters"])), 2),
         "gmres_relres_max": float(np.max(rec["relres"])),
         "gmres_solves": len(solve_ms),
+        "matvec_f32_ms": round(float(np.mean(rec["mv32_ms"])), 4),
+        "matvec_f32_gbs": round((4 * (far_u + far_v + near) + 16 * N)
+                                / (float(np.mean(rec["mv32_ms"])) * 1e-3) / 1e9, 2),
+        "gmres_ir_solves_per_s": round(1e3 / float(np.mean(rec["ir_ms"])), 3),
+        "gmres_ir_p50_ms": round(percentile(rec["ir_ms"], 0.5), 3),
+        "gmres_ir_p99_ms": round(percentile(rec["ir_ms"], 0.99), 3),
+        "gmres_ir_inner_iters_mean": round(float(np.mean(rec["ir_iters"])), 2),
+        "gmres_ir_refinements_mean": round(float(np.mean(rec["ir_outer"])), 2),
+        "gmres_ir_relres_max": float(np.max(rec["ir_relres"])),
         "build_ms": round(float(np.mean(rec["build_ms"])), 3),
         "build_aca_ms": round(float(np.mean(rec["aca_ms"])), 3),
         "build_near_ms": round(float(np.mean(rec["near_ms"])), 3),

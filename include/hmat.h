@@ -102,6 +102,8 @@ typedef struct {
   int32_t restarts;       /* completed restart cycles */
   double relres;          /* explicit ||b - A_H x||_2 / ||b||_2 at return */
   double time_ms;         /* wall time of the solve (host clock, stream synced) */
+  int32_t refinements;    /* hmat_solve_ir: outer refinement steps (0 for hmat_solve) */
+  int32_t reserved;
 } hmat_solve_info;
 
 /*
@@ -184,6 +186,39 @@ hmat_status hmat_matvec(hmat_t h, int32_t nrhs, const double* x, int64_t ldx, do
  */
 hmat_status hmat_solve(hmat_t h, const double* b, double* x, double tol, int32_t restart,
                        int32_t maxit, void* hip_stream, hmat_solve_info* info);
+
+/*
+ * hmat_set_precision -- reduced-precision storage of the H-matrix entries.
+ * precision 1 makes FP32 copies of the stored low-rank factors and dense
+ * blocks (same layout; FP64 values rounded to nearest) next to the FP64
+ * ones, which stay: hmat_matvec_ex(h, 1, ...) reads the copies and computes
+ * in FP64, so its result differs from the FP64 product by the rounding of
+ * the stored entries (relative 2-norm error about 1e-7). precision 0 frees
+ * the copies. Synchronises the stream. Errors: HMAT_EINVAL, HMAT_ENOMEM.
+ */
+hmat_status hmat_set_precision(hmat_t h, int32_t precision, void* hip_stream);
+
+/* hmat_matvec_ex -- hmat_matvec reading the entries stored in `precision`
+ * (0: FP64, 1: the FP32 copies of hmat_set_precision; HMAT_EINVAL if absent). */
+hmat_status hmat_matvec_ex(hmat_t h, int32_t precision, int32_t nrhs, const double* x, int64_t ldx,
+                           double* y, int64_t ldy, void* hip_stream);
+
+/*
+ * hmat_solve_ir -- A_H x = b by iterative refinement: x_0 = 0, and while
+ * ||b - A_H x_k||_2 > tol ||b||_2 (residual with the FP64 entries),
+ * x_{k+1} = x_k + d_k where GMRES(restart) solves A_p d_k = r_k with the
+ * entries stored in inner_precision p (1: FP32 copies) to the relative
+ * residual max(inner_tol, tol ||b|| / (2 ||r_k||)). The accuracy reached is
+ * that of hmat_solve at the same tol; the inner products read half the bytes.
+ * b, x: DEVICE, n_dof entries. maxit bounds the inner iterations in total.
+ * info->iterations counts inner GMRES steps, info->refinements outer steps,
+ * info->relres is the final FP64 relative residual. Errors: as hmat_solve;
+ * HMAT_EINVAL if inner_precision is 1 without FP32 copies or inner_tol is
+ * outside (0, 1); HMAT_ENOCONV (x and info written) when maxit is reached.
+ */
+hmat_status hmat_solve_ir(hmat_t h, const double* b, double* x, double tol, int32_t restart,
+                          int32_t maxit, int32_t inner_precision, double inner_tol,
+                          void* hip_stream, hmat_solve_info* info);
 
 /* hmat_info -- copy build statistics into *st (HOST). */
 hmat_status hmat_info(hmat_t h, hmat_stats* st);

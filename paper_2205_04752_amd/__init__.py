@@ -48,12 +48,13 @@ class _Stats(C.Structure):
 
 class _SolveInfo(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("restarts", C.c_int32), ("relres", C.c_double),
-                ("time_ms", C.c_double)]
+                ("time_ms", C.c_double), ("refinements", C.c_int32), ("reserved", C.c_int32)]
 
 
-EXPORTS = ["hmat_build", "hmat_build_batch", "hmat_bodies", "hmat_matvec", "hmat_solve",
-           "hmat_info", "hmat_free", "hmat_last_error", "hmat_plan", "hmat_block", "hmat_entries",
-           "hmat_set_factors", "hmat_profile"]
+EXPORTS = ["hmat_build", "hmat_build_batch", "hmat_bodies", "hmat_matvec", "hmat_matvec_ex",
+           "hmat_solve", "hmat_solve_ir", "hmat_set_precision", "hmat_info", "hmat_free",
+           "hmat_last_error", "hmat_plan", "hmat_block", "hmat_entries", "hmat_set_factors",
+           "hmat_profile"]
 
 _lib = None
 
@@ -73,6 +74,9 @@ def lib():
     L.hmat_bodies.argtypes = [vp, C.POINTER(i32), vp]
     L.hmat_matvec.argtypes = [vp, i32, vp, i64, vp, i64, vp]
     L.hmat_solve.argtypes = [vp, vp, vp, dbl, i32, i32, vp, C.POINTER(_SolveInfo)]
+    L.hmat_solve_ir.argtypes = [vp, vp, vp, dbl, i32, i32, i32, dbl, vp, C.POINTER(_SolveInfo)]
+    L.hmat_set_precision.argtypes = [vp, i32, vp]
+    L.hmat_matvec_ex.argtypes = [vp, i32, i32, vp, i64, vp, i64, vp]
     L.hmat_info.argtypes = [vp, C.POINTER(_Stats)]
     L.hmat_free.argtypes = [vp]
     L.hmat_last_error.restype = C.c_char_p
@@ -188,8 +192,9 @@ class HMatrix:
         except Exception:
             pass
 
-    def matvec(self, x, y=None, stream=None):
-        """y = A_H x for x of shape [nrhs, n_dof] (or [n_dof]); float64 on the GPU."""
+    def matvec(self, x, y=None, stream=None, precision: int = 0):
+        """y = A_H x for x of shape [nrhs, n_dof] (or [n_dof]); float64 on the GPU.
+        precision 1 reads the FP32 copies of the entries (set_precision(1))."""
         import torch
         squeeze = x.dim() == 1
         x2, xp, ldx = _dev_ptr(x, self.n_dof, "x")
@@ -198,8 +203,35 @@ class HMatrix:
         y2, yp, ldy = _dev_ptr(y, self.n_dof, "y")
         if y2.shape[0] != x2.shape[0]:
             raise ValueError("x and y must hold the same number of vectors")
-        _check(lib().hmat_matvec(self._h, x2.shape[0], xp, ldx, yp, ldy, _stream(stream)))
+        if precision == 0:
+            _check(lib().hmat_matvec(self._h, x2.shape[0], xp, ldx, yp, ldy, _stream(stream)))
+        else:
+            _check(lib().hmat_matvec_ex(self._h, int(precision), x2.shape[0], xp, ldx, yp, ldy,
+                                        _stream(stream)))
         return y2[0] if squeeze else y2
+
+    def set_precision(self, precision: int, stream=None) -> None:
+        """1: make FP32 copies of the stored entries; 0: free them."""
+        _check(lib().hmat_set_precision(self._h, int(precision), _stream(stream)))
+
+    def solve_ir(self, b, x=None, tol=1e-8, restart=50, maxit=10000, inner_precision=1,
+                 inner_tol=1e-6, stream=None, check=True):
+        """Iterative refinement: FP64 residuals, inner GMRES on the entries stored
+        in inner_precision; returns (x, info dict)."""
+        import torch
+        b2, bp, _ = _dev_ptr(b, self.n_dof, "b")
+        if x is None:
+            x = torch.empty_like(b2[0])
+        x2, xp, _ = _dev_ptr(x, self.n_dof, "x")
+        info = _SolveInfo()
+        st = lib().hmat_solve_ir(self._h, bp, xp, float(tol), int(restart), int(maxit),
+                                 int(inner_precision), float(inner_tol), _stream(stream),
+                                 C.byref(info))
+        if st not in (HMAT_OK, HMAT_ENOCONV) or (check and st != HMAT_OK):
+            _check(st)
+        return x2[0], dict(status=st, iterations=info.iterations, restarts=info.restarts,
+                           relres=info.relres, time_ms=info.time_ms,
+                           refinements=info.refinements)
 
     def solve(self, b, x=None, tol=1e-8, restart=50, maxit=10000, stream=None, check=True):
         """GMRES(restart) for A_H x = b; returns (x, info dict)."""

@@ -27,8 +27,9 @@ hipError_t launch_compact(const CopyTask*, int, hipStream_t);
 hipError_t launch_to_stream(const StreamTask*, int, double*, hipStream_t);
 hipError_t launch_from_stream(const StreamTask*, int, const double*, hipStream_t);
 hipError_t launch_gather(int, const double*, int64_t, const int32_t*, int64_t, double*, int64_t, hipStream_t);
-hipError_t launch_matvec_group(const ProductPlanDev&, int, const double*, int64_t, double*, int64_t,
+hipError_t launch_matvec_group(const ProductPlanDev&, int, int, const double*, int64_t, double*, int64_t,
                                double*, double*, int64_t, hipStream_t, hipEvent_t*, int);
+hipError_t launch_to_f32(const double*, float*, int64_t, hipStream_t);
 int launch_dots_part(const double*, int64_t, int64_t, int, const double*, double*, hipStream_t);
 size_t dots_part_size(int64_t, int);
 size_t norm_part_size(int64_t);
@@ -39,6 +40,7 @@ hipError_t launch_scale(const double*, int64_t, const double*, double*, hipStrea
 hipError_t launch_add_comb(const double*, int64_t, int64_t, int, const double*, double*, hipStream_t);
 hipError_t launch_residual(const double*, int64_t, double*, hipStream_t);
 hipError_t launch_fill(double*, int64_t, double, hipStream_t);
+hipError_t launch_axpy(double, const double*, int64_t, double*, hipStream_t);
 }  // namespace hm
 
 using namespace hm;
@@ -143,6 +145,7 @@ struct hmat {
   std::vector<PanelShape> far_vshape;
   DevBuf far_arena;                 // V factors (panel layout)
   DevBuf stream;                    // U factors and dense blocks in product order
+  DevBuf far32, stream32;           // FP32 copies of both (hmat_set_precision), same layout
   std::deque<DevBuf> piv_bufs;          // ACA pivots, one buffer per pass and group
   std::vector<const int32_t*> piv_ptr;  // per far block: device [2][cap]
   std::vector<int32_t> piv_cap;
@@ -172,6 +175,7 @@ struct hmat {
   int64_t mv_chunk_bytes_multi = MV_CHUNK_BYTES_MULTI;
   int mv_unroll = 16;                            // columns per batch in phase B (HMAT_MV_UNROLL)
   DevBuf d_xp, d_z, d_part, d_dotpart;
+  DevBuf d_ir;  // iterative refinement: residual and correction
   // GMRES workspace
   DevBuf d_Q, d_w, d_small;
   int q_cols = 0;
@@ -491,7 +495,8 @@ void fill_stats(hmat* h) {
                               h->cl[0].d_chunk.bytes + h->cl[0].d_tile_near.bytes + h->cl[0].d_tile_far.bytes +
                               h->cl[1].d_chunk.bytes + h->cl[1].d_tile_near.bytes + h->cl[1].d_tile_far.bytes + h->d_xp.bytes +
                               h->d_z.bytes + h->d_part.bytes + h->d_dotpart.bytes + h->d_Q.bytes +
-                              h->d_w.bytes + h->d_small.bytes);
+                              h->d_w.bytes + h->d_small.bytes + h->far32.bytes + h->stream32.bytes +
+                              h->d_ir.bytes);
 }
 
 struct EventPair {
@@ -910,8 +915,8 @@ void prof_collect(hmat* h) {
   h->prof_pending.clear();
 }
 
-void matvec_impl(hmat* h, int32_t nrhs, const double* x, int64_t ldx, double* y, int64_t ldy,
-                 hipStream_t s) {
+void matvec_impl(hmat* h, int prec, int32_t nrhs, const double* x, int64_t ldx, double* y,
+                 int64_t ldy, hipStream_t s) {
   for (int32_t r0 = 0; r0 < nrhs; r0 += MV_MAX_NR) {
     const int nr = std::min<int32_t>(MV_MAX_NR, nrhs - r0);
     hipEvent_t* ev = nullptr;
@@ -938,12 +943,14 @@ void matvec_impl(hmat* h, int32_t nrhs, const double* x, int64_t ldx, double* y,
     P.order = h->d_order.as<int32_t>();
     P.far = h->far_arena.as<double>();
     P.stream = h->stream.as<double>();
+    P.far32 = h->far32.as<float>();
+    P.stream32 = h->stream32.as<float>();
     P.nA = CL.nA;
     P.n_near_chunks = CL.n_near;
     P.n_far_chunks = CL.n - CL.n_near;
     P.ntiles = h->nTiles;
     P.N = h->N;
-    check(launch_matvec_group(P, nr, h->d_xp.as<double>(), h->ldxp, h->d_z.as<double>(), h->Ztot,
+    check(launch_matvec_group(P, prec, nr, h->d_xp.as<double>(), h->ldxp, h->d_z.as<double>(), h->Ztot,
                               h->d_part.as<double>(), y + r0 * ldy, ldy, s, ev ? ev + 2 : nullptr,
                               h->mv_unroll),
           "product");
@@ -972,6 +979,158 @@ void copy_stream_out(const hmat* h, int32_t b, int64_t m, int64_t cols, double* 
   check(launch_from_stream(d_t.as<StreamTask>(), (int)tasks.size(), h->stream.as<double>(), s), "block copy");
   check(hipMemcpyAsync(out, tmp.p, sizeof(double) * m * cols, hipMemcpyDeviceToHost, s), "block copy");
   check(hipStreamSynchronize(s), "block copy");
+}
+
+// GMRES(m) for A_p x = b with x0 = 0, A_p the H-matrix with its entries
+// stored in precision p (0: FP64, 1: FP32; FP64 arithmetic either way).
+// Convergence on the explicit residual ||b - A_p x|| <= tol ||b||. Returns
+// HMAT_OK or HMAT_ENOCONV; throws HipError on device errors.
+constexpr int GM_COL = 1026;  // stride of a Hessenberg column buffer (restart <= 1024)
+
+// GMRES(m) workspace of the handle (grown, never shrunk). Allocation happens
+// here, before any solve enqueues work, so no buffer is freed under a
+// running kernel.
+void ensure_gmres_ws(hmat* h, int m) {
+  const int64_t N = h->N;
+  if (h->q_cols < m + 1) {
+    h->d_Q.alloc(sizeof(double) * N * (m + 1), "GMRES basis");
+    h->q_cols = m + 1;
+  }
+  if (!h->d_w.p) h->d_w.alloc(sizeof(double) * N, "GMRES work");
+  const size_t dp = dots_part_size(N, m + 1), np = norm_part_size(N);
+  if (h->d_dotpart.bytes < sizeof(double) * (dp + np)) h->d_dotpart.alloc(sizeof(double) * (dp + np), "GMRES work");
+  if (h->d_small.bytes < sizeof(double) * (4 * GM_COL + 8)) h->d_small.alloc(sizeof(double) * (4 * GM_COL + 8), "GMRES work");
+  if (!h->h_pinned) check(hipHostMalloc((void**)&h->h_pinned, sizeof(double) * 3 * GM_COL), "GMRES host buffer");
+  for (hipEvent_t& e : h->col_ev)
+    if (!e) check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "GMRES event");
+}
+
+hmat_status gmres_impl(hmat* h, int prec, const double* b, double* x, double tol, int m,
+                       int maxit, hipStream_t s, int* used_out, int* restarts_out,
+                       double* rel_out) {
+  const int64_t N = h->N;
+  constexpr int COL = GM_COL;
+    ensure_gmres_ws(h, m);
+    const size_t dp = dots_part_size(N, m + 1);
+    double* dotpart = h->d_dotpart.as<double>();
+    double* normpart = dotpart + dp;
+    double* Q = h->d_Q.as<double>();
+    double* w = h->d_w.as<double>();
+    double* base = h->d_small.as<double>();
+    double* hacc[2] = {base + COL, base + 2 * COL};  // Hessenberg columns, double-buffered
+    double* ycoef = base + 3 * COL;                  // [m]
+    double* scal = ycoef + COL;                      // scalars
+    double* hcol_host[2] = {h->h_pinned, h->h_pinned + COL};
+    double* y_host = h->h_pinned + 2 * COL;
+    auto norm_host = [&](const double* v) {
+      check(launch_norm(v, N, normpart, scal, s), "norm");
+      check(hipMemcpyAsync(y_host, scal, sizeof(double), hipMemcpyDeviceToHost, s), "norm");
+      check(hipStreamSynchronize(s), "norm");
+      return y_host[0];
+    };
+    // One Arnoldi step j: w = A q_j, two classical Gram-Schmidt passes against
+    // q_0..q_j (Hessenberg column in hacc[j % 2]), q_{j+1} = w / ||w||, and an
+    // asynchronous copy of the column to pinned host memory (event col_ev[j % 2]).
+    auto enqueue_step = [&](int j) {
+      double* col = hacc[j % 2];
+      matvec_impl(h, prec, 1, Q + (size_t)j * N, N, w, N, s);
+      for (int pass = 0; pass < 2; pass++) {
+        const int nblk = launch_dots_part(Q, N, N, j + 1, w, dotpart, s);
+        check(launch_proj(Q, N, N, j + 1, dotpart, nblk, w, col, pass == 0, pass == 1 ? normpart : nullptr, s),
+              "project");
+      }
+      check(launch_norm_final(normpart, N, col + j + 1, s), "norm");
+      check(launch_scale(w, N, col + j + 1, Q + (size_t)(j + 1) * N, s), "scale");
+      check(hipMemcpyAsync(hcol_host[j % 2], col, sizeof(double) * (j + 2), hipMemcpyDeviceToHost, s),
+            "hessenberg");
+      check(hipEventRecord(h->col_ev[j % 2], s), "hessenberg");
+    };
+    check(launch_fill(x, N, 0.0, s), "fill");
+    const double bn = norm_host(b);
+    int used = 0, launched = 0, restarts = 0;
+    double rel = 0.0;
+    hmat_status status = HMAT_ENOCONV;
+    std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1), yv(m);
+    if (bn == 0.0) {
+      status = HMAT_OK;
+      rel = 0.0;
+    } else {
+      for (;;) {
+        matvec_impl(h, prec, 1, x, N, w, N, s);
+        check(launch_residual(b, N, w, s), "residual");
+        const double beta = norm_host(w);
+        rel = beta / bn;
+        if (beta <= tol * bn) {
+          status = HMAT_OK;
+          break;
+        }
+        if (launched >= maxit) break;
+        check(launch_scale(w, N, scal, Q, s), "scale");  // scal[0] = ||r|| from norm_host
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        // Pipelined Arnoldi: step j+1 is enqueued before the host waits for
+        // column j (it needs only device data), so the host's Givens update
+        // overlaps the device's next product. A step enqueued past convergence
+        // is discarded.
+        enqueue_step(0);
+        launched++;
+        int j = 0;
+        for (;;) {
+          const bool more = (j + 1 < m) && (launched < maxit);
+          if (more) {
+            enqueue_step(j + 1);
+            launched++;
+          }
+          check(hipEventSynchronize(h->col_ev[j % 2]), "hessenberg");
+          const double* col = hcol_host[j % 2];
+          for (int i = 0; i <= j + 1; i++) H[(size_t)i * m + j] = col[i];
+          const double hn = col[j + 1];
+          for (int i = 0; i < j; i++) {
+            const double a = H[(size_t)i * m + j], c2 = H[(size_t)(i + 1) * m + j];
+            H[(size_t)i * m + j] = cs[i] * a + sn[i] * c2;
+            H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * c2;
+          }
+          const double a = H[(size_t)j * m + j], c2 = H[(size_t)(j + 1) * m + j];
+          const double den = std::sqrt(a * a + c2 * c2);
+          cs[j] = den == 0.0 ? 1.0 : a / den;
+          sn[j] = den == 0.0 ? 0.0 : c2 / den;
+          H[(size_t)j * m + j] = cs[j] * a + sn[j] * c2;
+          H[(size_t)(j + 1) * m + j] = 0.0;
+          g[j + 1] = -sn[j] * g[j];
+          g[j] = cs[j] * g[j];
+          j++;
+          used++;
+          if (std::fabs(g[j]) <= tol * bn || hn == 0.0 || !more) break;
+        }
+        for (int i = j - 1; i >= 0; i--) {
+          double sum = g[i];
+          for (int q = i + 1; q < j; q++) sum -= H[(size_t)i * m + q] * yv[q];
+          yv[i] = sum / H[(size_t)i * m + i];
+        }
+        // the pinned buffer is free again once the stream passes this copy
+        check(hipStreamSynchronize(s), "update");
+        std::memcpy(y_host, yv.data(), sizeof(double) * j);
+        check(hipMemcpyAsync(ycoef, y_host, sizeof(double) * j, hipMemcpyHostToDevice, s), "update");
+        check(launch_add_comb(Q, N, N, j, ycoef, x, s), "update");
+        restarts++;
+      }
+    }
+  check(hipStreamSynchronize(s), "solve");
+  *used_out = used;
+  *restarts_out = restarts;
+  *rel_out = rel;
+  return status;
+}
+
+hmat_status check_solve_args(hmat_t h, const double* b, const double* x, double tol,
+                             int32_t restart, int32_t maxit) {
+  if (!h) return fail(HMAT_EINVAL, "handle is NULL");
+  if (!b || !x) return fail(HMAT_EINVAL, "b or x is NULL");
+  if (b == x) return fail(HMAT_EINVAL, "b and x alias");
+  if (!(tol > 0.0)) return fail(HMAT_EINVAL, "tol must be > 0");
+  if (restart < 1 || restart > 1024) return fail(HMAT_EINVAL, "restart must lie in [1, 1024]");
+  if (maxit < 1) return fail(HMAT_EINVAL, "maxit must be >= 1");
+  return HMAT_OK;
 }
 
 }  // namespace
@@ -1038,7 +1197,7 @@ hmat_status hmat_matvec(hmat_t h, int32_t nrhs, const double* x, int64_t ldx, do
   const char* yb = (const char*)(y + (nrhs - 1) * ldy + h->N);
   if (xa < yb && ya < xb) return fail(HMAT_EINVAL, "x and y overlap");
   try {
-    matvec_impl(h, nrhs, x, ldx, y, ldy, (hipStream_t)hip_stream);
+    matvec_impl(h, 0, nrhs, x, ldx, y, ldy, (hipStream_t)hip_stream);
   } catch (const HipError& e) {
     return fail(e.st, e.msg);
   }
@@ -1047,130 +1206,82 @@ hmat_status hmat_matvec(hmat_t h, int32_t nrhs, const double* x, int64_t ldx, do
 
 hmat_status hmat_solve(hmat_t h, const double* b, double* x, double tol, int32_t restart,
                        int32_t maxit, void* hip_stream, hmat_solve_info* info) {
-  if (!h) return fail(HMAT_EINVAL, "handle is NULL");
-  if (!b || !x) return fail(HMAT_EINVAL, "b or x is NULL");
-  if (b == x) return fail(HMAT_EINVAL, "b and x alias");
-  if (!(tol > 0.0)) return fail(HMAT_EINVAL, "tol must be > 0");
-  if (restart < 1 || restart > 1024) return fail(HMAT_EINVAL, "restart must lie in [1, 1024]");
-  if (maxit < 1) return fail(HMAT_EINVAL, "maxit must be >= 1");
+  hmat_status st = check_solve_args(h, b, x, tol, restart, maxit);
+  if (st != HMAT_OK) return st;
+  hipStream_t s = (hipStream_t)hip_stream;
+  auto t0 = std::chrono::steady_clock::now();
+  try {
+    int used = 0, restarts = 0;
+    double rel = 0.0;
+    st = gmres_impl(h, 0, b, x, tol, restart, maxit, s, &used, &restarts, &rel);
+    if (info) {
+      info->iterations = used;
+      info->restarts = restarts;
+      info->relres = rel;
+      info->time_ms = ms_since(t0);
+      info->refinements = 0;
+    }
+    if (st != HMAT_OK) return fail(st, "GMRES reached maxit before tol");
+    return HMAT_OK;
+  } catch (const HipError& e) {
+    (void)hipStreamSynchronize(s);
+    return fail(e.st, e.msg);
+  }
+}
+
+hmat_status hmat_solve_ir(hmat_t h, const double* b, double* x, double tol, int32_t restart,
+                          int32_t maxit, int32_t inner_precision, double inner_tol,
+                          void* hip_stream, hmat_solve_info* info) {
+  hmat_status st = check_solve_args(h, b, x, tol, restart, maxit);
+  if (st != HMAT_OK) return st;
+  if (inner_precision != 0 && inner_precision != 1) return fail(HMAT_EINVAL, "inner_precision must be 0 or 1");
+  if (inner_precision == 1 && !h->far32.p && !h->stream32.p)
+    return fail(HMAT_EINVAL, "no FP32 copy: call hmat_set_precision(h, 1, ...) first");
+  if (!(inner_tol > 0.0 && inner_tol < 1.0)) return fail(HMAT_EINVAL, "inner_tol must lie in (0, 1)");
   hipStream_t s = (hipStream_t)hip_stream;
   auto t0 = std::chrono::steady_clock::now();
   const int64_t N = h->N;
-  const int m = restart;
-  constexpr int COL = 1026;  // stride of a Hessenberg column buffer (restart <= 1024)
   try {
-    if (h->q_cols < m + 1) {
-      h->d_Q.alloc(sizeof(double) * N * (m + 1), "GMRES basis");
-      h->q_cols = m + 1;
-    }
-    if (!h->d_w.p) h->d_w.alloc(sizeof(double) * N, "GMRES work");
-    const size_t dp = dots_part_size(N, m + 1), np = norm_part_size(N);
-    if (h->d_dotpart.bytes < sizeof(double) * (dp + np)) h->d_dotpart.alloc(sizeof(double) * (dp + np), "GMRES work");
-    double* dotpart = h->d_dotpart.as<double>();
-    double* normpart = dotpart + dp;
-    if (h->d_small.bytes < sizeof(double) * (4 * COL + 8)) h->d_small.alloc(sizeof(double) * (4 * COL + 8), "GMRES work");
-    if (!h->h_pinned) check(hipHostMalloc((void**)&h->h_pinned, sizeof(double) * 3 * COL), "GMRES host buffer");
-    for (hipEvent_t& e : h->col_ev)
-      if (!e) check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "GMRES event");
-    double* Q = h->d_Q.as<double>();
-    double* w = h->d_w.as<double>();
-    double* base = h->d_small.as<double>();
-    double* hacc[2] = {base + COL, base + 2 * COL};  // Hessenberg columns, double-buffered
-    double* ycoef = base + 3 * COL;                  // [m]
-    double* scal = ycoef + COL;                      // scalars
-    double* hcol_host[2] = {h->h_pinned, h->h_pinned + COL};
-    double* y_host = h->h_pinned + 2 * COL;
+    check(hipStreamSynchronize(s), "solve");
+    if (h->d_ir.bytes < sizeof(double) * 2 * N) h->d_ir.alloc(sizeof(double) * 2 * N, "refinement work");
+    double* r = h->d_ir.as<double>();
+    double* d = r + N;
+    ensure_gmres_ws(h, restart);
     auto norm_host = [&](const double* v) {
-      check(launch_norm(v, N, normpart, scal, s), "norm");
-      check(hipMemcpyAsync(y_host, scal, sizeof(double), hipMemcpyDeviceToHost, s), "norm");
+      check(launch_norm(v, N, h->d_dotpart.as<double>(), h->d_small.as<double>(), s), "norm");
+      check(hipMemcpyAsync(h->h_pinned, h->d_small.p, sizeof(double), hipMemcpyDeviceToHost, s), "norm");
       check(hipStreamSynchronize(s), "norm");
-      return y_host[0];
-    };
-    // One Arnoldi step j: w = A q_j, two classical Gram-Schmidt passes against
-    // q_0..q_j (Hessenberg column in hacc[j % 2]), q_{j+1} = w / ||w||, and an
-    // asynchronous copy of the column to pinned host memory (event col_ev[j % 2]).
-    auto enqueue_step = [&](int j) {
-      double* col = hacc[j % 2];
-      matvec_impl(h, 1, Q + (size_t)j * N, N, w, N, s);
-      for (int pass = 0; pass < 2; pass++) {
-        const int nblk = launch_dots_part(Q, N, N, j + 1, w, dotpart, s);
-        check(launch_proj(Q, N, N, j + 1, dotpart, nblk, w, col, pass == 0, pass == 1 ? normpart : nullptr, s),
-              "project");
-      }
-      check(launch_norm_final(normpart, N, col + j + 1, s), "norm");
-      check(launch_scale(w, N, col + j + 1, Q + (size_t)(j + 1) * N, s), "scale");
-      check(hipMemcpyAsync(hcol_host[j % 2], col, sizeof(double) * (j + 2), hipMemcpyDeviceToHost, s),
-            "hessenberg");
-      check(hipEventRecord(h->col_ev[j % 2], s), "hessenberg");
+      return h->h_pinned[0];
     };
     check(launch_fill(x, N, 0.0, s), "fill");
     const double bn = norm_host(b);
-    int used = 0, launched = 0, restarts = 0;
+    int used = 0, restarts = 0, outer = 0;
     double rel = 0.0;
-    hmat_status status = HMAT_ENOCONV;
-    std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1), yv(m);
+    st = HMAT_ENOCONV;
     if (bn == 0.0) {
-      status = HMAT_OK;
-      rel = 0.0;
+      st = HMAT_OK;
     } else {
+      // x_{k+1} = x_k + d_k with A_p d_k = b - A x_k solved by GMRES to a
+      // relative residual max(inner_tol, tol ||b|| / (2 ||r_k||)); the
+      // residual r_k = b - A x_k uses the FP64 matrix.
       for (;;) {
-        matvec_impl(h, 1, x, N, w, N, s);
-        check(launch_residual(b, N, w, s), "residual");
-        const double beta = norm_host(w);
-        rel = beta / bn;
-        if (beta <= tol * bn) {
-          status = HMAT_OK;
+        matvec_impl(h, 0, 1, x, N, r, N, s);
+        check(launch_residual(b, N, r, s), "residual");
+        const double rn = norm_host(r);
+        rel = rn / bn;
+        if (rn <= tol * bn) {
+          st = HMAT_OK;
           break;
         }
-        if (launched >= maxit) break;
-        check(launch_scale(w, N, scal, Q, s), "scale");  // scal[0] = ||r|| from norm_host
-        std::fill(g.begin(), g.end(), 0.0);
-        g[0] = beta;
-        // Pipelined Arnoldi: step j+1 is enqueued before the host waits for
-        // column j (it needs only device data), so the host's Givens update
-        // overlaps the device's next product. A step enqueued past convergence
-        // is discarded.
-        enqueue_step(0);
-        launched++;
-        int j = 0;
-        for (;;) {
-          const bool more = (j + 1 < m) && (launched < maxit);
-          if (more) {
-            enqueue_step(j + 1);
-            launched++;
-          }
-          check(hipEventSynchronize(h->col_ev[j % 2]), "hessenberg");
-          const double* col = hcol_host[j % 2];
-          for (int i = 0; i <= j + 1; i++) H[(size_t)i * m + j] = col[i];
-          const double hn = col[j + 1];
-          for (int i = 0; i < j; i++) {
-            const double a = H[(size_t)i * m + j], c2 = H[(size_t)(i + 1) * m + j];
-            H[(size_t)i * m + j] = cs[i] * a + sn[i] * c2;
-            H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * c2;
-          }
-          const double a = H[(size_t)j * m + j], c2 = H[(size_t)(j + 1) * m + j];
-          const double den = std::sqrt(a * a + c2 * c2);
-          cs[j] = den == 0.0 ? 1.0 : a / den;
-          sn[j] = den == 0.0 ? 0.0 : c2 / den;
-          H[(size_t)j * m + j] = cs[j] * a + sn[j] * c2;
-          H[(size_t)(j + 1) * m + j] = 0.0;
-          g[j + 1] = -sn[j] * g[j];
-          g[j] = cs[j] * g[j];
-          j++;
-          used++;
-          if (std::fabs(g[j]) <= tol * bn || hn == 0.0 || !more) break;
-        }
-        for (int i = j - 1; i >= 0; i--) {
-          double sum = g[i];
-          for (int q = i + 1; q < j; q++) sum -= H[(size_t)i * m + q] * yv[q];
-          yv[i] = sum / H[(size_t)i * m + i];
-        }
-        // the pinned buffer is free again once the stream passes this copy
-        check(hipStreamSynchronize(s), "update");
-        std::memcpy(y_host, yv.data(), sizeof(double) * j);
-        check(hipMemcpyAsync(ycoef, y_host, sizeof(double) * j, hipMemcpyHostToDevice, s), "update");
-        check(launch_add_comb(Q, N, N, j, ycoef, x, s), "update");
-        restarts++;
+        if (used >= maxit || outer >= 64) break;
+        const double itol = std::max(inner_tol, 0.5 * tol * bn / rn);
+        int u = 0, rs = 0;
+        double irel = 0.0;
+        (void)gmres_impl(h, inner_precision, r, d, itol, restart, maxit - used, s, &u, &rs, &irel);
+        used += u;
+        restarts += rs;
+        outer++;
+        check(launch_axpy(1.0, d, N, x, s), "update");
       }
     }
     check(hipStreamSynchronize(s), "solve");
@@ -1179,13 +1290,61 @@ hmat_status hmat_solve(hmat_t h, const double* b, double* x, double tol, int32_t
       info->restarts = restarts;
       info->relres = rel;
       info->time_ms = ms_since(t0);
+      info->refinements = outer;
     }
-    if (status != HMAT_OK) return fail(status, "GMRES reached maxit before tol");
+    if (st != HMAT_OK) return fail(st, "refinement reached maxit before tol");
     return HMAT_OK;
   } catch (const HipError& e) {
     (void)hipStreamSynchronize(s);
     return fail(e.st, e.msg);
   }
+}
+
+hmat_status hmat_set_precision(hmat_t h, int32_t precision, void* hip_stream) {
+  if (!h) return fail(HMAT_EINVAL, "handle is NULL");
+  if (precision != 0 && precision != 1) return fail(HMAT_EINVAL, "precision must be 0 (FP64) or 1 (FP32)");
+  hipStream_t s = (hipStream_t)hip_stream;
+  try {
+    check(hipStreamSynchronize(s), "set precision");
+    h->far32.release();
+    h->stream32.release();
+    if (precision == 1) {
+      const int64_t nf = (int64_t)(h->far_arena.bytes / sizeof(double));
+      const int64_t ns = (int64_t)(h->stream.bytes / sizeof(double));
+      h->far32.alloc(sizeof(float) * std::max<int64_t>(nf, 2), "FP32 copy");
+      h->stream32.alloc(sizeof(float) * std::max<int64_t>(ns, 2), "FP32 copy");
+      check(launch_to_f32(h->far_arena.as<double>(), h->far32.as<float>(), nf, s), "FP32 copy");
+      check(launch_to_f32(h->stream.as<double>(), h->stream32.as<float>(), ns, s), "FP32 copy");
+      check(hipStreamSynchronize(s), "FP32 copy");
+    }
+    fill_stats(h);
+  } catch (const HipError& e) {
+    (void)hipStreamSynchronize(s);
+    return fail(e.st, e.msg);
+  }
+  return HMAT_OK;
+}
+
+hmat_status hmat_matvec_ex(hmat_t h, int32_t precision, int32_t nrhs, const double* x, int64_t ldx,
+                           double* y, int64_t ldy, void* hip_stream) {
+  if (!h) return fail(HMAT_EINVAL, "handle is NULL");
+  if (precision != 0 && precision != 1) return fail(HMAT_EINVAL, "precision must be 0 (FP64) or 1 (FP32)");
+  if (precision == 1 && !h->far32.p && !h->stream32.p)
+    return fail(HMAT_EINVAL, "no FP32 copy: call hmat_set_precision(h, 1, ...) first");
+  if (!x || !y) return fail(HMAT_EINVAL, "x or y is NULL");
+  if (nrhs < 1 || nrhs > 64) return fail(HMAT_EINVAL, "nrhs must lie in [1, 64]");
+  if (ldx < h->N || ldy < h->N) return fail(HMAT_EINVAL, "ldx and ldy must be >= n_dof");
+  const char* xa = (const char*)x;
+  const char* xb = (const char*)(x + (nrhs - 1) * ldx + h->N);
+  const char* ya = (const char*)y;
+  const char* yb = (const char*)(y + (nrhs - 1) * ldy + h->N);
+  if (xa < yb && ya < xb) return fail(HMAT_EINVAL, "x and y overlap");
+  try {
+    matvec_impl(h, precision, nrhs, x, ldx, y, ldy, (hipStream_t)hip_stream);
+  } catch (const HipError& e) {
+    return fail(e.st, e.msg);
+  }
+  return HMAT_OK;
 }
 
 hmat_status hmat_info(hmat_t h, hmat_stats* st) {

@@ -120,6 +120,8 @@ struct ProductPlanDev {
   const int32_t* order;
   const double* far;         // V panels
   const double* stream;      // U factors and dense blocks in product order
+  const float* far32;        // FP32 copies of the two (reduced-precision storage), or null
+  const float* stream32;
   int32_t nA, n_near_chunks, n_far_chunks, ntiles;
   int64_t N;
 };

@@ -457,17 +457,39 @@ __global__ void k_gather(int nr, const double* __restrict__ x, int64_t ldx,
 
 constexpr int TILE = 2 * WAVE;  // rows per product tile: two rows per lane
 
+// Stored matrix entries are FP64 or FP32 (T); the product computes in FP64.
+// Pair<T> is the two-entry vector a lane loads (16 or 8 bytes); ld2 widens it.
+template <typename T>
+struct Pair;
+template <>
+struct Pair<double> {
+  using type = double2;
+};
+template <>
+struct Pair<float> {
+  using type = float2;
+};
+template <typename T>
+__device__ __forceinline__ typename Pair<T>::type ldp(const T* p) {
+  return *reinterpret_cast<const typename Pair<T>::type*>(p);
+}
+template <typename T>
+__device__ __forceinline__ double2 ld2(const T* p) {
+  const typename Pair<T>::type v = ldp(p);
+  return make_double2((double)v.x, (double)v.y);
+}
+
 // Phase A item: z = V_b^T x_s for a group of <= 8 columns; one wave. Lanes
 // cover the aligned row window of V two rows at a time (16-byte loads of V and
 // of the gathered x; pad rows of V are zero); NR right-hand sides at once,
 // columns in sub-batches of CB.
-template <int NR>
-__device__ __forceinline__ void mv_a_item(const MvA& I, const double* __restrict__ far,
+template <int NR, typename T>
+__device__ __forceinline__ void mv_a_item(const MvA& I, const T* __restrict__ far,
                                           const double* __restrict__ xp, int64_t ldxp, int nr,
                                           double* __restrict__ z, int64_t ldz) {
   constexpr int CB = (NR >= 16) ? 2 : ((NR >= 8) ? 4 : 8);
   const int lane = threadIdx.x & (WAVE - 1);
-  const double* __restrict__ V = far + I.v_off;
+  const T* __restrict__ V = far + I.v_off;
   const double* __restrict__ X = xp + I.a0;
   for (int l0 = I.l0; l0 < I.l1; l0 += CB) {
     const int nc = min(CB, I.l1 - l0);
@@ -480,7 +502,7 @@ __device__ __forceinline__ void mv_a_item(const MvA& I, const double* __restrict
       double2 xv[NR], v[CB];
 #pragma unroll
       for (int c = 0; c < CB; c++)  // columns past l1 re-read the last one (not accumulated)
-        v[c] = *reinterpret_cast<const double2*>(V + (size_t)(l0 + min(c, nc - 1)) * I.ld + i);
+        v[c] = ld2(V + (size_t)(l0 + min(c, nc - 1)) * I.ld + i);
 #pragma unroll
       for (int r = 0; r < NR; r++)
         xv[r] = (r < nr) ? *reinterpret_cast<const double2*>(X + r * ldxp + i) : make_double2(0.0, 0.0);
@@ -518,8 +540,8 @@ __device__ __forceinline__ void mv_a_item(const MvA& I, const double* __restrict
 // reads column c0 + t p + l/g, rows 2(l mod g) and +1, at stream offset
 // so + t p len + 2l -- consecutive lanes, consecutive addresses. Adds the
 // segment's row sums to the owning lanes' acc0/acc1 (fixed summation order).
-template <int UNR>
-__device__ __forceinline__ void mv_b_grouped(const MvSeg& S, const double* __restrict__ stream,
+template <int UNR, typename T>
+__device__ __forceinline__ void mv_b_grouped(const MvSeg& S, const T* __restrict__ stream,
                                              const double* __restrict__ src, double& acc0,
                                              double& acc1) {
   const int lane = threadIdx.x & (WAVE - 1);
@@ -529,24 +551,24 @@ __device__ __forceinline__ void mv_b_grouped(const MvSeg& S, const double* __res
   const int ncol = S.c1 - S.c0;
   const int nsteps = (ncol + p - 1) / p;
   const int64_t step = (int64_t)p * len;
-  const double* __restrict__ A = stream + S.so;
+  const T* __restrict__ A = stream + S.so;
   const double* __restrict__ xs = src + S.soff + S.c0;
   double s0 = 0.0, s1 = 0.0;
   for (int t = 0; t < nsteps; t += UNR) {
-    double2 a[UNR];
+    typename Pair<T>::type a[UNR];
     double xv[UNR];
 #pragma unroll
     for (int u = 0; u < UNR; u++) {
       const int col = (t + u) * p + q;
       const bool ok = lact && col < ncol;
-      a[u] = *reinterpret_cast<const double2*>(A + (ok ? (int64_t)(t + u) * step + 2 * lane : 0));
+      a[u] = ldp(A + (ok ? (int64_t)(t + u) * step + 2 * lane : 0));
       xv[u] = xs[ok ? col : 0];
       xv[u] = ok ? xv[u] : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < UNR; u++) {
-      s0 += a[u].x * xv[u];
-      s1 += a[u].y * xv[u];
+      s0 += (double)a[u].x * xv[u];
+      s1 += (double)a[u].y * xv[u];
     }
   }
   // sum the p column groups: group q takes group q + off at level off
@@ -568,10 +590,10 @@ __device__ __forceinline__ void mv_b_grouped(const MvSeg& S, const double* __res
   }
 }
 
-template <int NR, int UNR>
+template <int NR, int UNR, typename T>
 __device__ __forceinline__ void mv_b_chunk(const MvChunk& C, int chunk,
                                            const MvSeg* __restrict__ segs,
-                                           const double* __restrict__ stream,
+                                           const T* __restrict__ stream,
                                            const double* __restrict__ z, int64_t ldz,
                                            const double* __restrict__ xp, int64_t ldxp, int nr,
                                            double* __restrict__ part) {
@@ -583,26 +605,26 @@ __device__ __forceinline__ void mv_b_chunk(const MvChunk& C, int chunk,
     const MvSeg S = segs[s];
     const int len = S.row_hi - S.row_lo;
     if (NR == 1 && len <= WAVE) {
-      mv_b_grouped<UNR>(S, stream, S.far ? z : xp, acc0[0], acc1[0]);
+      mv_b_grouped<UNR, T>(S, stream, S.far ? z : xp, acc0[0], acc1[0]);
       continue;
     }
     const bool act = L2 >= S.row_lo && L2 < S.row_hi;
     const int Lc = min(max(L2, (int)S.row_lo), (int)S.row_hi - 2);
-    const double* __restrict__ A = stream + S.so + (Lc - S.row_lo) - (int64_t)S.c0 * len;
+    const T* __restrict__ A = stream + S.so + (Lc - S.row_lo) - (int64_t)S.c0 * len;
     const double* __restrict__ src = (S.far ? z : xp) + S.soff;
     const int64_t ld = S.far ? ldz : ldxp;
     for (int c = S.c0; c < S.c1; c += UNR) {
       const int nc = min(UNR, S.c1 - c);
-      double2 a[UNR];
+      typename Pair<T>::type a[UNR];
 #pragma unroll
       for (int u = 0; u < UNR; u++) {
         const int cu = (u < nc) ? c + u : S.c1 - 1;
-        a[u] = *reinterpret_cast<const double2*>(A + (int64_t)cu * len);
+        a[u] = ldp(A + (int64_t)cu * len);
       }
 #pragma unroll
       for (int u = 0; u < UNR; u++) {
-        a[u].x = act ? a[u].x : 0.0;
-        a[u].y = act ? a[u].y : 0.0;
+        a[u].x = act ? a[u].x : (T)0;
+        a[u].y = act ? a[u].y : (T)0;
       }
       if (nc == UNR) {
 #pragma unroll
@@ -611,8 +633,8 @@ __device__ __forceinline__ void mv_b_chunk(const MvChunk& C, int chunk,
             const double* sr = src + r * ld + c;
 #pragma unroll
             for (int u = 0; u < UNR; u++) {
-              acc0[r] += a[u].x * sr[u];
-              acc1[r] += a[u].y * sr[u];
+              acc0[r] += (double)a[u].x * sr[u];
+              acc1[r] += (double)a[u].y * sr[u];
             }
           }
         }
@@ -624,8 +646,8 @@ __device__ __forceinline__ void mv_b_chunk(const MvChunk& C, int chunk,
 #pragma unroll
             for (int u = 0; u < UNR; u++) {
               if (u < nc) {
-                acc0[r] += a[u].x * sr[u];
-                acc1[r] += a[u].y * sr[u];
+                acc0[r] += (double)a[u].x * sr[u];
+                acc1[r] += (double)a[u].y * sr[u];
               }
             }
           }
@@ -646,39 +668,39 @@ constexpr int MV_WPB = 1;
 // Product launch 1: the phase-A items (largest first) and the dense-block
 // chunks, which do not depend on z, in one grid so that neither leaves the
 // other's tail idle.
-template <int NR, int UNR>
+template <int NR, int UNR, typename T>
 __global__ __launch_bounds__(WAVE* MV_WPB) void k_mv1(const MvA* __restrict__ items, int nA,
                                                       int n_near_chunks,
                                                       const MvChunk* __restrict__ chunks,
                                                       const MvSeg* __restrict__ segs,
-                                                      const double* __restrict__ far,
-                                                      const double* __restrict__ stream,
+                                                      const T* __restrict__ far,
+                                                      const T* __restrict__ stream,
                                                       const double* __restrict__ xp, int64_t ldxp,
                                                       int nr, double* __restrict__ z, int64_t ldz,
                                                       double* __restrict__ part) {
   // wave-uniform unit index: keeps descriptors and vector entries in scalar loads
   const int u = __builtin_amdgcn_readfirstlane(blockIdx.x * MV_WPB + threadIdx.x / WAVE);
   if (u < nA) {
-    mv_a_item<NR>(items[u], far, xp, ldxp, nr, z, ldz);
+    mv_a_item<NR, T>(items[u], far, xp, ldxp, nr, z, ldz);
   } else if (u < nA + n_near_chunks) {
     const int c = u - nA;
-    mv_b_chunk<NR, UNR>(chunks[c], c, segs, stream, z, ldz, xp, ldxp, nr, part);
+    mv_b_chunk<NR, UNR, T>(chunks[c], c, segs, stream, z, ldz, xp, ldxp, nr, part);
   }
 }
 
 // Product launch 2: the low-rank chunks (U z), chunk ids c_first + unit.
-template <int NR, int UNR>
+template <int NR, int UNR, typename T>
 __global__ __launch_bounds__(WAVE* MV_WPB) void k_mv2(int c_first, int n,
                                                       const MvChunk* __restrict__ chunks,
                                                       const MvSeg* __restrict__ segs,
-                                                      const double* __restrict__ stream,
+                                                      const T* __restrict__ stream,
                                                       const double* __restrict__ z, int64_t ldz,
                                                       const double* __restrict__ xp, int64_t ldxp,
                                                       int nr, double* __restrict__ part) {
   const int u = __builtin_amdgcn_readfirstlane(blockIdx.x * MV_WPB + threadIdx.x / WAVE);
   if (u >= n) return;
   const int c = c_first + u;
-  mv_b_chunk<NR, UNR>(chunks[c], c, segs, stream, z, ldz, xp, ldxp, nr, part);
+  mv_b_chunk<NR, UNR, T>(chunks[c], c, segs, stream, z, ldz, xp, ldxp, nr, part);
 }
 
 // ---------------------------------------------------------------------------
@@ -700,7 +722,8 @@ __device__ __forceinline__ v4d mfma4(double a, double b, v4d c) {
 // Phase A, several vectors: z[:, zoff + c] = V[:, l0 + c]^T X for c < l1 - l0
 // (<= 64 columns: four 16-column tiles). Per 16-row step lane l reads rows
 // 4(l/16) .. +3 of column l%16 of each tile and the same rows of vector l%16.
-__device__ __forceinline__ void mv_a_mfma(const MvA& I, const double* __restrict__ far,
+template <typename T>
+__device__ __forceinline__ void mv_a_mfma(const MvA& I, const T* __restrict__ far,
                                           const double* __restrict__ xp, int64_t ldxp, int nr,
                                           double* __restrict__ z, int64_t ldz) {
   const int lane = threadIdx.x & (WAVE - 1);
@@ -709,7 +732,7 @@ __device__ __forceinline__ void mv_a_mfma(const MvA& I, const double* __restrict
   const int ntile = (ncols + 15) >> 4;
   const bool rv = cl < nr;
   const double* __restrict__ X = xp + (int64_t)min(cl, nr - 1) * ldxp + I.a0;
-  const double* Vc[4];
+  const T* Vc[4];
   bool cv[4];
 #pragma unroll
   for (int q = 0; q < 4; q++) {
@@ -734,8 +757,8 @@ __device__ __forceinline__ void mv_a_mfma(const MvA& I, const double* __restrict
 #pragma unroll
     for (int q = 0; q < 4; q++) {
       if (q < ntile) {
-        a0[q] = *reinterpret_cast<const double2*>(Vc[q] + (p0 ? r0 : 0));
-        a1[q] = *reinterpret_cast<const double2*>(Vc[q] + (p1 ? r0 + 2 : 0));
+        a0[q] = ld2(Vc[q] + (p0 ? r0 : 0));
+        a1[q] = ld2(Vc[q] + (p1 ? r0 + 2 : 0));
       }
     }
 #pragma unroll
@@ -766,9 +789,10 @@ __device__ __forceinline__ void mv_a_mfma(const MvA& I, const double* __restrict
 // c + l/16 in each 64-row half the segment touches, and entry c + l/16 of
 // vector l%16. Product t of a half accumulates tile rows 64h + 4m + t.
 // Writes part[chunk][16][128].
+template <typename T>
 __device__ __forceinline__ void mv_b_mfma(const MvChunk& C, int chunk,
                                           const MvSeg* __restrict__ segs,
-                                          const double* __restrict__ stream,
+                                          const T* __restrict__ stream,
                                           const double* __restrict__ z, int64_t ldz,
                                           const double* __restrict__ xp, int64_t ldxp, int nr,
                                           double* __restrict__ part) {
@@ -799,16 +823,16 @@ __device__ __forceinline__ void mv_b_mfma(const MvChunk& C, int chunk,
         const int cc = c + 4 * g + kq;
         const bool cok = cc < S.c1;
         const int ccl = cok ? cc : S.c1 - 1;
-        const double* __restrict__ col = stream + S.so + (int64_t)(ccl - S.c0) * len;
+        const T* __restrict__ col = stream + S.so + (int64_t)(ccl - S.c0) * len;
         bv[g] = Bp[ccl];
         bv[g] = (cok && rv) ? bv[g] : 0.0;
         if (h0) {
-          av[g][0][0] = *reinterpret_cast<const double2*>(col + (q00 ? R0 : 0));
-          av[g][0][1] = *reinterpret_cast<const double2*>(col + (q01 ? R0 + 2 : 0));
+          av[g][0][0] = ld2(col + (q00 ? R0 : 0));
+          av[g][0][1] = ld2(col + (q01 ? R0 + 2 : 0));
         }
         if (h1) {
-          av[g][1][0] = *reinterpret_cast<const double2*>(col + (q10 ? R1 : 0));
-          av[g][1][1] = *reinterpret_cast<const double2*>(col + (q11 ? R1 + 2 : 0));
+          av[g][1][0] = ld2(col + (q10 ? R1 : 0));
+          av[g][1][1] = ld2(col + (q11 ? R1 + 2 : 0));
         }
       }
 #pragma unroll
@@ -842,12 +866,13 @@ __device__ __forceinline__ void mv_b_mfma(const MvChunk& C, int chunk,
   }
 }
 
+template <typename T>
 __global__ __launch_bounds__(WAVE) void k_mv1_mfma(const MvA* __restrict__ items, int nA,
                                                    int n_near_chunks,
                                                    const MvChunk* __restrict__ chunks,
                                                    const MvSeg* __restrict__ segs,
-                                                   const double* __restrict__ far,
-                                                   const double* __restrict__ stream,
+                                                   const T* __restrict__ far,
+                                                   const T* __restrict__ stream,
                                                    const double* __restrict__ xp, int64_t ldxp,
                                                    int nr, double* __restrict__ z, int64_t ldz,
                                                    double* __restrict__ part) {
@@ -860,10 +885,11 @@ __global__ __launch_bounds__(WAVE) void k_mv1_mfma(const MvA* __restrict__ items
   }
 }
 
+template <typename T>
 __global__ __launch_bounds__(WAVE) void k_mv2_mfma(int c_first, int n,
                                                    const MvChunk* __restrict__ chunks,
                                                    const MvSeg* __restrict__ segs,
-                                                   const double* __restrict__ stream,
+                                                   const T* __restrict__ stream,
                                                    const double* __restrict__ z, int64_t ldz,
                                                    const double* __restrict__ xp, int64_t ldxp,
                                                    int nr, double* __restrict__ part) {
@@ -871,6 +897,13 @@ __global__ __launch_bounds__(WAVE) void k_mv2_mfma(int c_first, int n,
   if (u >= n) return;
   const int c = c_first + u;
   mv_b_mfma(chunks[c], c, segs, stream, z, ldz, xp, ldxp, nr, part);
+}
+
+// FP32 copy of an FP64 array (reduced-precision storage of the arenas).
+__global__ void k_to_f32(const double* __restrict__ src, float* __restrict__ dst, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = (float)src[i];
 }
 
 // Plain column-major block matrix -> stream segment (one workgroup per segment).
@@ -1078,6 +1111,12 @@ __global__ void k_residual(const double* __restrict__ b, int64_t n, double* __re
   if (i < n) r[i] = b[i] - r[i];
 }
 
+// y += a x.
+__global__ void k_axpy(double a, const double* __restrict__ x, int64_t n, double* __restrict__ y) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) y[i] += a * x[i];
+}
+
 __global__ void k_fill(double* __restrict__ x, int64_t n, double v) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i < n) x[i] = v;
@@ -1118,6 +1157,11 @@ hipError_t launch_aca(const DevGeo& g, const AcaTask* tasks, int ntasks, size_t 
   return hipGetLastError();
 }
 
+hipError_t launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_to_f32, dim3(4096), dim3(256), 0, s, src, dst, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_compact(const CopyTask* tasks, int ntasks, hipStream_t s) {
   if (ntasks > 0) hipLaunchKernelGGL(k_compact, dim3(ntasks), dim3(256), 0, s, tasks);
   return hipGetLastError();
@@ -1130,60 +1174,70 @@ hipError_t launch_gather(int nr, const double* x, int64_t ldx, const int32_t* or
   return hipGetLastError();
 }
 
-template <int NR, int UNR>
-static void mv_group(const ProductPlanDev& P, const double* xp, int64_t ldxp, int nr, double* z,
-                     int64_t ldz, double* part, double* y, int64_t ldy, hipStream_t s,
-                     hipEvent_t* ev) {
+template <int NR, int UNR, typename T>
+static void mv_group(const ProductPlanDev& P, const T* far, const T* stream, const double* xp,
+                     int64_t ldxp, int nr, double* z, int64_t ldz, double* part, double* y,
+                     int64_t ldy, hipStream_t s, hipEvent_t* ev) {
   const int n1 = P.nA + P.n_near_chunks;
   if (n1 > 0)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mv1<NR, UNR>), dim3((n1 + MV_WPB - 1) / MV_WPB),
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mv1<NR, UNR, T>), dim3((n1 + MV_WPB - 1) / MV_WPB),
                        dim3(WAVE * MV_WPB), 0, s, P.items, P.nA, P.n_near_chunks, P.chunks, P.segs,
-                       P.far, P.stream, xp, ldxp, nr, z, ldz, part);
+                       far, stream, xp, ldxp, nr, z, ldz, part);
   if (ev) (void)hipEventRecord(ev[0], s);
   if (P.n_far_chunks > 0)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mv2<NR, UNR>), dim3((P.n_far_chunks + MV_WPB - 1) / MV_WPB),
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mv2<NR, UNR, T>), dim3((P.n_far_chunks + MV_WPB - 1) / MV_WPB),
                        dim3(WAVE * MV_WPB), 0, s, P.n_near_chunks, P.n_far_chunks, P.chunks, P.segs,
-                       P.stream, z, ldz, xp, ldxp, nr, part);
+                       stream, z, ldz, xp, ldxp, nr, part);
   if (ev) (void)hipEventRecord(ev[1], s);
   hipLaunchKernelGGL(HIP_KERNEL_NAME(k_reduce<NR>), dim3(P.ntiles), dim3(WAVE * RED_WAVES), 0, s, P.tile_near,
                      P.tile_far, part, nr, P.order, P.N, y, ldy);
   if (ev) (void)hipEventRecord(ev[2], s);
 }
 
-static void mv_group_mfma(const ProductPlanDev& P, const double* xp, int64_t ldxp, int nr,
-                          double* z, int64_t ldz, double* part, double* y, int64_t ldy,
-                          hipStream_t s, hipEvent_t* ev) {
+template <typename T>
+static void mv_group_mfma(const ProductPlanDev& P, const T* far, const T* stream, const double* xp,
+                          int64_t ldxp, int nr, double* z, int64_t ldz, double* part, double* y,
+                          int64_t ldy, hipStream_t s, hipEvent_t* ev) {
   const int n1 = P.nA + P.n_near_chunks;
   if (n1 > 0)
-    hipLaunchKernelGGL(k_mv1_mfma, dim3(n1), dim3(WAVE), 0, s, P.items, P.nA, P.n_near_chunks,
-                       P.chunks, P.segs, P.far, P.stream, xp, ldxp, nr, z, ldz, part);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mv1_mfma<T>), dim3(n1), dim3(WAVE), 0, s, P.items, P.nA,
+                       P.n_near_chunks, P.chunks, P.segs, far, stream, xp, ldxp, nr, z, ldz, part);
   if (ev) (void)hipEventRecord(ev[0], s);
   if (P.n_far_chunks > 0)
-    hipLaunchKernelGGL(k_mv2_mfma, dim3(P.n_far_chunks), dim3(WAVE), 0, s, P.n_near_chunks,
-                       P.n_far_chunks, P.chunks, P.segs, P.stream, z, ldz, xp, ldxp, nr, part);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mv2_mfma<T>), dim3(P.n_far_chunks), dim3(WAVE), 0, s,
+                       P.n_near_chunks, P.n_far_chunks, P.chunks, P.segs, stream, z, ldz, xp, ldxp,
+                       nr, part);
   if (ev) (void)hipEventRecord(ev[1], s);
   hipLaunchKernelGGL(HIP_KERNEL_NAME(k_reduce<16>), dim3(P.ntiles), dim3(WAVE * RED_WAVES), 0, s,
                      P.tile_near, P.tile_far, part, nr, P.order, P.N, y, ldy);
   if (ev) (void)hipEventRecord(ev[2], s);
 }
 
-// One pass over the matrix for nr <= 16 right-hand sides (xp already gathered).
+// One pass over the matrix for nr <= 16 right-hand sides (xp already gathered),
+// reading the FP64 arenas (prec 0) or their FP32 copies (prec 1).
 // One vector: the vector-ALU kernels; two to sixteen: matrix cores.
-hipError_t launch_matvec_group(const ProductPlanDev& P, int nr, const double* xp, int64_t ldxp,
-                               double* z, int64_t ldz, double* part, double* y, int64_t ldy,
-                               hipStream_t s, hipEvent_t* ev, int unroll) {
-#define HM_GROUP(R)                                                            \
-  do {                                                                         \
-    if (unroll >= 16)                                                          \
-      mv_group<R, 16>(P, xp, ldxp, nr, z, ldz, part, y, ldy, s, ev);           \
-    else                                                                       \
-      mv_group<R, 8>(P, xp, ldxp, nr, z, ldz, part, y, ldy, s, ev);            \
-  } while (0)
-  if (nr <= 1)
-    HM_GROUP(1);
-  else
-    mv_group_mfma(P, xp, ldxp, nr, z, ldz, part, y, ldy, s, ev);
-#undef HM_GROUP
+hipError_t launch_matvec_group(const ProductPlanDev& P, int prec, int nr, const double* xp,
+                               int64_t ldxp, double* z, int64_t ldz, double* part, double* y,
+                               int64_t ldy, hipStream_t s, hipEvent_t* ev, int unroll) {
+  if (prec == 1) {
+    if (nr <= 1) {
+      if (unroll >= 16)
+        mv_group<1, 16, float>(P, P.far32, P.stream32, xp, ldxp, nr, z, ldz, part, y, ldy, s, ev);
+      else
+        mv_group<1, 8, float>(P, P.far32, P.stream32, xp, ldxp, nr, z, ldz, part, y, ldy, s, ev);
+    } else {
+      mv_group_mfma<float>(P, P.far32, P.stream32, xp, ldxp, nr, z, ldz, part, y, ldy, s, ev);
+    }
+  } else {
+    if (nr <= 1) {
+      if (unroll >= 16)
+        mv_group<1, 16, double>(P, P.far, P.stream, xp, ldxp, nr, z, ldz, part, y, ldy, s, ev);
+      else
+        mv_group<1, 8, double>(P, P.far, P.stream, xp, ldxp, nr, z, ldz, part, y, ldy, s, ev);
+    } else {
+      mv_group_mfma<double>(P, P.far, P.stream, xp, ldxp, nr, z, ldz, part, y, ldy, s, ev);
+    }
+  }
   return hipGetLastError();
 }
 
@@ -1245,6 +1299,11 @@ hipError_t launch_add_comb(const double* Q, int64_t ldq, int64_t n, int ncols, c
 
 hipError_t launch_residual(const double* b, int64_t n, double* r, hipStream_t s) {
   hipLaunchKernelGGL(k_residual, dim3(blocks_for(n, 256)), dim3(256), 0, s, b, n, r);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpy(double a, const double* x, int64_t n, double* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpy, dim3(blocks_for(n, 256)), dim3(256), 0, s, a, x, n, y);
   return hipGetLastError();
 }
 

@@ -113,6 +113,9 @@ def test_other_entry_points_reject_null_handle():
     assert L.hmat_block(None, 0, None, None, None, None, None) == H.HMAT_EINVAL
     assert L.hmat_entries(None, 0, None, None, None, None) == H.HMAT_EINVAL
     assert L.hmat_set_factors(None, None, None, None, None) == H.HMAT_EINVAL
+    assert L.hmat_set_precision(None, 1, None) == H.HMAT_EINVAL
+    assert L.hmat_matvec_ex(None, 1, 1, None, 3, None, 3, None) == H.HMAT_EINVAL
+    assert L.hmat_solve_ir(None, None, None, 1e-8, 50, 10, 1, 1e-6, None, None) == H.HMAT_EINVAL
     assert L.hmat_free(None) == H.HMAT_OK
 
 
