@@ -292,6 +292,74 @@ hmat_status hmat_set_factors(hmat_t h, const int32_t* ranks, const double* U, co
  */
 hmat_status hmat_profile(hmat_t h, int32_t enable, double* phase_ms, int64_t* calls);
 
+/* ------------------------------------------------------------------------
+ * Request server: continuous admission of independent requests (one mesh
+ * each: build, then products or a solve) under a device-memory budget.
+ * `slots` worker threads, each with its own HIP stream, run admitted requests
+ * concurrently on the device; the oldest pending request is admitted as soon
+ * as a worker is free and its memory estimate fits beside the running ones
+ * (always when nothing runs). Each request's H-matrix stays on the device
+ * for all of its vectors and is freed when the request completes. A result
+ * does not depend on the other requests: the same request alone and in a mix
+ * gives the same values.
+ */
+typedef struct hmat_server* hmat_server_t;
+
+enum { HMAT_REQ_MATVEC = 0, HMAT_REQ_SOLVE = 1 };
+
+typedef struct {
+  int32_t kind;       /* HMAT_REQ_MATVEC: nvec products; HMAT_REQ_SOLVE: one solve */
+  int32_t nvec;       /* products: 1..64 vectors (ignored for a solve) */
+  int32_t precision;  /* 0: FP64 throughout; 1: FP32 copies of the entries (products
+                         read them; solves refine FP32 inner GMRES with FP64 residuals,
+                         hmat_solve_ir with inner_tol 1e-6) */
+  int32_t restart;    /* solve: GMRES restart length (1..1024) */
+  double E, nu, eps;  /* material (Sec. 1) and ACA accuracy, as for hmat_build */
+  double tol;         /* solve: FP64 relative residual to reach */
+} hmat_request;
+
+typedef struct {
+  int32_t status;       /* hmat_status of the request */
+  int32_t iterations;   /* solve: GMRES steps (inner steps for precision 1) */
+  int32_t refinements;  /* solve, precision 1: outer refinement steps */
+  int32_t reserved;
+  double relres;        /* solve: final FP64 relative residual */
+  double t_submit_ms;   /* server clock (ms since hmat_server_create) */
+  double t_admit_ms;
+  double t_done_ms;
+  double build_ms;      /* hmat_build of the request's H-matrix */
+  int64_t device_bytes; /* device memory its handle held */
+} hmat_result;
+
+/* hmat_server_create -- start `slots` (1..64) workers on the current device.
+ * hbm_budget: bytes the running requests may hold together (0: 80% of the
+ * free device memory). eta, leaf: as for hmat_build, shared by all requests.
+ * Errors: HMAT_EINVAL, HMAT_ENOMEM, HMAT_EDEVICE (no device). */
+hmat_status hmat_server_create(int32_t slots, int64_t hbm_budget, double eta, int32_t leaf,
+                               hmat_server_t* out);
+
+/* hmat_server_submit -- queue a request; mesh, req and in are HOST data,
+ * copied before return. in: nvec x n_dof vectors (products, vector-major)
+ * or n_dof (the right-hand side of a solve), DOF 3i+a in mesh order.
+ * *id receives the request id. Errors: HMAT_EINVAL (mesh or parameters,
+ * as hmat_build; kind, precision, nvec, tol, restart), HMAT_ENOMEM. */
+hmat_status hmat_server_submit(hmat_server_t s, const hmat_mesh* mesh, const hmat_request* req,
+                               const double* in, int64_t* id);
+
+/* hmat_server_wait -- block until request `id` completes; out (HOST,
+ * nvec x n_dof or n_dof; may be NULL) receives A_H x or the solution, res
+ * (may be NULL) its timings and counts. A request is collected once.
+ * Returns the request's status (its error message via
+ * hmat_server_last_error); HMAT_EINVAL for an unknown id. */
+hmat_status hmat_server_wait(hmat_server_t s, int64_t id, double* out, hmat_result* res);
+
+/* hmat_server_destroy -- finish every queued request, stop the workers and
+ * free the server (NULL is a no-op). */
+hmat_status hmat_server_destroy(hmat_server_t s);
+
+/* Message of the last failed server call on this thread. */
+const char* hmat_server_last_error(void);
+
 #ifdef __cplusplus
 }
 #endif

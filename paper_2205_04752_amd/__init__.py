@@ -13,7 +13,7 @@ import os
 
 import numpy as np
 
-__all__ = ["lib", "HMatrix", "plan", "HmatError", "LIB_PATH"]
+__all__ = ["lib", "HMatrix", "Server", "plan", "HmatError", "LIB_PATH"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhmat.so")
 
@@ -51,10 +51,24 @@ class _SolveInfo(C.Structure):
                 ("time_ms", C.c_double), ("refinements", C.c_int32), ("reserved", C.c_int32)]
 
 
+class _Request(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("nvec", C.c_int32), ("precision", C.c_int32),
+                ("restart", C.c_int32), ("E", C.c_double), ("nu", C.c_double), ("eps", C.c_double),
+                ("tol", C.c_double)]
+
+
+class _Result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iterations", C.c_int32), ("refinements", C.c_int32),
+                ("reserved", C.c_int32), ("relres", C.c_double), ("t_submit_ms", C.c_double),
+                ("t_admit_ms", C.c_double), ("t_done_ms", C.c_double), ("build_ms", C.c_double),
+                ("device_bytes", C.c_int64)]
+
+
 EXPORTS = ["hmat_build", "hmat_build_batch", "hmat_bodies", "hmat_matvec", "hmat_matvec_ex",
            "hmat_solve", "hmat_solve_ir", "hmat_set_precision", "hmat_info", "hmat_free",
            "hmat_last_error", "hmat_plan", "hmat_block", "hmat_entries", "hmat_set_factors",
-           "hmat_profile"]
+           "hmat_profile", "hmat_server_create", "hmat_server_submit", "hmat_server_wait",
+           "hmat_server_destroy", "hmat_server_last_error"]
 
 _lib = None
 
@@ -85,8 +99,13 @@ def lib():
     L.hmat_entries.argtypes = [vp, i64, vp, vp, vp, vp]
     L.hmat_set_factors.argtypes = [vp, vp, vp, vp, vp]
     L.hmat_profile.argtypes = [vp, i32, vp, C.POINTER(i64)]
+    L.hmat_server_create.argtypes = [i32, i64, dbl, i32, C.POINTER(vp)]
+    L.hmat_server_submit.argtypes = [vp, C.POINTER(_Mesh), C.POINTER(_Request), vp, C.POINTER(i64)]
+    L.hmat_server_wait.argtypes = [vp, i64, vp, C.POINTER(_Result)]
+    L.hmat_server_destroy.argtypes = [vp]
+    L.hmat_server_last_error.restype = C.c_char_p
     for name in EXPORTS:
-        if name != "hmat_last_error":
+        if name not in ("hmat_last_error", "hmat_server_last_error"):
             getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -297,3 +316,63 @@ class HMatrix:
         V = np.ascontiguousarray(V_cat, dtype=np.float64)
         _check(lib().hmat_set_factors(self._h, rk.ctypes.data, U.ctypes.data, V.ctypes.data,
                                       _stream(stream)))
+
+
+REQ_MATVEC, REQ_SOLVE = 0, 1
+
+
+class Server:
+    """Request server (hmat_server_*): `slots` workers with their own streams
+    admit queued requests under a device-memory budget; inputs and outputs are
+    host arrays (NumPy)."""
+
+    def __init__(self, slots: int = 4, hbm_budget: int = 0, eta: float = 2.0, leaf: int = 32):
+        h = C.c_void_p()
+        st = lib().hmat_server_create(int(slots), int(hbm_budget), float(eta), int(leaf), C.byref(h))
+        if st != HMAT_OK:
+            raise HmatError(st, lib().hmat_server_last_error().decode())
+        self._s = h
+        self._n = {}
+
+    def submit(self, vertices, triangles, x, kind: int = REQ_MATVEC, E: float = 1.0,
+               nu: float = 0.3, eps: float = 1e-5, precision: int = 0, tol: float = 1e-8,
+               restart: int = 50) -> int:
+        """x: [nvec, n_dof] vectors (products) or [n_dof] right-hand side (solve)."""
+        m, keep = _mesh(vertices, triangles)
+        X = np.ascontiguousarray(x, dtype=np.float64)
+        N = 3 * m.n_triangles
+        nvec = 1 if (kind == REQ_SOLVE or X.ndim == 1) else X.shape[0]
+        if X.size != nvec * N:
+            raise ValueError("x must hold nvec x n_dof values")
+        q = _Request(int(kind), int(nvec), int(precision), int(restart), float(E), float(nu),
+                     float(eps), float(tol))
+        rid = C.c_int64(0)
+        st = lib().hmat_server_submit(self._s, C.byref(m), C.byref(q), X.ctypes.data, C.byref(rid))
+        if st != HMAT_OK:
+            raise HmatError(st, lib().hmat_server_last_error().decode())
+        self._n[rid.value] = (nvec, N, kind)
+        return rid.value
+
+    def wait(self, rid: int, check: bool = True):
+        """(output array, result dict) of request rid; output None on failure."""
+        nvec, N, kind = self._n.pop(rid)
+        out = np.zeros(N if kind == REQ_SOLVE else (nvec, N))
+        res = _Result()
+        st = lib().hmat_server_wait(self._s, int(rid), out.ctypes.data, C.byref(res))
+        info = {k: getattr(res, k) for k, _ in _Result._fields_}
+        if st != HMAT_OK:
+            if check:
+                raise HmatError(st, lib().hmat_server_last_error().decode())
+            return None, info
+        return out, info
+
+    def close(self):
+        if getattr(self, "_s", None):
+            lib().hmat_server_destroy(self._s)
+            self._s = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -657,9 +657,13 @@ void merge_bodies(hmat* h, const std::vector<BodyIn>& in, double eta, int32_t le
               h->pos_body.begin() + h->bodies[b].tri_off + h->bodies[b].nt, (int32_t)b);
 }
 
-// Bytes of first-pass ACA panels that one group may hold at once
-// (HMAT_ACA_BUDGET_MB overrides): a quarter of the free device memory, >= 1 GiB.
+thread_local int64_t g_aca_budget = 0;  // per-thread override (hm::set_thread_aca_budget)
+
+// Bytes of first-pass ACA panels that one group may hold at once: the
+// calling thread's override if set, else HMAT_ACA_BUDGET_MB, else a quarter
+// of the free device memory (>= 1 GiB).
 int64_t aca_budget() {
+  if (g_aca_budget > 0) return g_aca_budget;
   if (const char* e = std::getenv("HMAT_ACA_BUDGET_MB")) return std::max(1L, std::atol(e)) << 20;
   size_t fr = 0, tot = 0;
   if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
@@ -1134,6 +1138,8 @@ hmat_status check_solve_args(hmat_t h, const double* b, const double* x, double 
 }
 
 }  // namespace
+
+void hm::set_thread_aca_budget(int64_t bytes) { g_aca_budget = bytes > 0 ? bytes : 0; }
 
 extern "C" {
 

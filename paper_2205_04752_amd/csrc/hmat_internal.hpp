@@ -158,6 +158,11 @@ hmat_status validate_params(double E, double nu, double eta, int32_t leaf, doubl
 void make_plan(const hmat_mesh* mesh, double eta, int32_t leaf, Plan& plan);
 void make_geometry(const hmat_mesh* mesh, const Plan& plan, HostGeometry& g);
 void gauss_legendre_unit(int n, double* x, double* w);  // rule on [0,1]
+
+// Cap on the ACA panel memory of builds made by the calling thread (0: the
+// default, a quarter of the free device memory). Used by the request server,
+// whose workers build concurrently.
+void set_thread_aca_budget(int64_t bytes);
 void radon7(double bary[7][3], double w[7]);
 
 }  // namespace hm

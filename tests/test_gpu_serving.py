@@ -1,0 +1,133 @@
+"""Request server: results alone and in a mix are the same; parity of served
+results with the oracle; admission under a memory budget.
+
+  * a mix of product and solve requests (FP64 and FP32 storage, several
+    meshes and materials) run one at a time on a one-slot server and
+    together on a four-slot server: every output agrees to 1e-12 (the work
+    of one request does not depend on the others, so the values are the same);
+  * FP64 product requests equal the oracle's H-matrix product within 1e-10,
+    FP32-storage ones within the request's eps; solves reach their FP64
+    relative residual (checked with a separate FP64 handle);
+  * with a budget below any request, requests run one after another.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _H():
+    import paper_2205_04752_amd as H
+    return H
+
+
+def _requests():
+    H = _H()
+    meshes = [W.icosphere(2), W.torus(1.0, 0.3, 28, 10), W.ellipsoid(5, (1.2, 0.8, 0.5)),
+              W.icosphere(3), W.torus(1.0, 0.45, 20, 12)]
+    reqs = []
+    rng = np.random.default_rng(9)
+    specs = [(0, H.REQ_MATVEC, 3, 0, 1e-6, 0.3), (1, H.REQ_SOLVE, 1, 1, 1e-5, 0.25),
+             (2, H.REQ_MATVEC, 1, 1, 1e-5, 0.42), (3, H.REQ_SOLVE, 1, 0, 1e-7, 0.3),
+             (4, H.REQ_MATVEC, 5, 0, 1e-3, 0.2), (0, H.REQ_SOLVE, 1, 1, 1e-6, 0.35),
+             (1, H.REQ_MATVEC, 2, 1, 1e-7, 0.3), (3, H.REQ_MATVEC, 8, 0, 1e-5, 0.3)]
+    for mi, kind, nvec, prec, eps, nu in specs:
+        V, T = meshes[mi]
+        N = 3 * len(T)
+        if kind == H.REQ_SOLVE:
+            x = W.smooth_rhs(V, T, seed=int(rng.integers(1, 1000)))
+        else:
+            x = W.random_x(N, nvec, seed=int(rng.integers(1, 1000)))
+        reqs.append(dict(V=V, T=T, x=x, kind=kind, prec=prec, eps=eps, nu=nu))
+    return reqs
+
+
+def _submit(srv, r):
+    return srv.submit(r["V"], r["T"], r["x"], kind=r["kind"], E=1.0, nu=r["nu"], eps=r["eps"],
+                      precision=r["prec"], tol=1e-8, restart=50)
+
+
+@pytest.fixture(scope="module")
+def served():
+    H = _H()
+    reqs = _requests()
+    print("case serving: 8 requests alone (1 slot) and mixed (4 slots)", flush=True)
+    s1 = H.Server(slots=1)
+    alone = []
+    for r in reqs:  # one at a time: each runs alone on the device
+        alone.append(s1.wait(_submit(s1, r)))
+    s1.close()
+    s4 = H.Server(slots=4)
+    ids = [_submit(s4, r) for r in reqs]
+    mixed = [s4.wait(i) for i in ids]
+    s4.close()
+    return dict(reqs=reqs, alone=alone, mixed=mixed)
+
+
+def test_alone_equals_mixed(served):
+    worst = 0.0
+    for (ya, ia), (ym, im) in zip(served["alone"], served["mixed"]):
+        assert ia["status"] == 0 and im["status"] == 0
+        worst = max(worst, float(np.abs(ya - ym).max() / np.abs(ya).max()))
+        assert ia["iterations"] == im["iterations"]
+    assert worst <= 1e-12, worst
+    # the mix overlapped: some request was admitted before another finished
+    ts = sorted((i["t_admit_ms"], i["t_done_ms"]) for _, i in served["mixed"])
+    assert any(ts[k + 1][0] < ts[k][1] for k in range(len(ts) - 1))
+
+
+def test_served_products_match_oracle(served):
+    H = _H()
+    for r, (y, info) in zip(served["reqs"], served["mixed"]):
+        if r["kind"] != H.REQ_MATVEC:
+            continue
+        mesh = O.Mesh(r["V"], r["T"], 1.0, r["nu"])
+        o = O.HMatrix(mesh, 2.0, 32, eps=r["eps"])
+        yo = o.matvec(np.atleast_2d(r["x"]))
+        y = np.atleast_2d(y)
+        rel = np.linalg.norm(y - yo, axis=1) / np.linalg.norm(yo, axis=1)
+        bound = 1e-10 if r["prec"] == 0 else r["eps"]
+        assert rel.max() <= bound, (r["prec"], r["eps"], rel)
+
+
+def test_served_solves_reach_tolerance(served):
+    H = _H()
+    for r, (x, info) in zip(served["reqs"], served["mixed"]):
+        if r["kind"] != H.REQ_SOLVE:
+            continue
+        g = H.HMatrix(r["V"], r["T"], 1.0, r["nu"], 2.0, 32, r["eps"])
+        b = torch.from_numpy(r["x"]).cuda()
+        rel = float(torch.linalg.norm(b - g.matvec(torch.from_numpy(x).cuda())) / torch.linalg.norm(b))
+        assert rel <= 1e-8 * (1 + 1e-6) and info["relres"] <= 1e-8, (rel, info)
+        if r["prec"] == 1:
+            assert info["refinements"] >= 1
+        g.close()
+
+
+def test_budget_serialises():
+    H = _H()
+    reqs = _requests()[:4]
+    srv = H.Server(slots=4, hbm_budget=1)
+    ids = [_submit(srv, r) for r in reqs]
+    infos = [srv.wait(i)[1] for i in ids]
+    srv.close()
+    ts = sorted((i["t_admit_ms"], i["t_done_ms"]) for i in infos)
+    for k in range(len(ts) - 1):
+        assert ts[k + 1][0] >= ts[k][1] - 1e-6
+
+
+def test_submit_errors():
+    H = _H()
+    srv = H.Server(slots=1)
+    V, T = W.icosphere(1)
+    with pytest.raises(H.HmatError):
+        srv.submit(V, T, np.zeros(3 * len(T)), nu=0.7)
+    with pytest.raises(H.HmatError):
+        srv.submit(V, T, np.zeros(3 * len(T)), eps=2.0)
+    with pytest.raises(H.HmatError):
+        srv.submit(V, T, np.zeros(3 * len(T)), kind=H.REQ_SOLVE, tol=0.0)
+    srv.close()
