@@ -188,13 +188,111 @@ def bench_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_serve(args):
+    """Serving workload: a stream of independent requests (sphere, ellipsoid or
+    torus meshes of 1k-80k DOF, eps in {1e-3, 1e-5, 1e-7}, half of them one
+    GMRES(50) solve to FP64 relative residual 1e-8, half 1-32 products; seed 4).
+    Compared: the plain form -- one request at a time, FP64 -- and the serving
+    form -- `slots` requests in flight, FP32 storage with FP64 refinement for
+    solves. Each is run with every request arriving at once (capacity) and
+    with Poisson arrivals at 0.5x and 1.0x the plain form's capacity (latency)."""
+    import threading
+
+    import numpy as np
+    import torch  # noqa: F401  (device initialisation before the server threads)
+    import workloads as W
+    import paper_2205_04752_amd as H
+
+    reqs = W.serving_requests(args.requests, seed=4)
+    print(f"serve: generating {len(reqs)} meshes", file=sys.stderr, flush=True)
+    data = []
+    for r in reqs:
+        V, T = W.mesh_of(r)
+        N = 3 * len(T)
+        x = W.smooth_rhs(V, T, seed=r["vseed"]) if r["solve"] else W.random_x(N, r["m"], seed=r["vseed"])
+        data.append((V, T, x))
+    n_solves = sum(r["solve"] for r in reqs)
+    dof = [3 * len(d[1]) for d in data]
+
+    def run(slots, prec, rate, label):
+        print(f"serve: {label}", file=sys.stderr, flush=True)
+        srv = H.Server(slots=slots)
+        Vw, Tw = W.icosphere(2)  # warm-up request (not counted)
+        srv.wait(srv.submit(Vw, Tw, W.random_x(3 * len(Tw), 1, 0), precision=prec))
+        if rate:
+            gaps = np.random.default_rng(5).exponential(1.0 / rate, len(reqs))
+            arrive = np.cumsum(gaps) - gaps[0]
+        else:
+            arrive = np.zeros(len(reqs))
+        ids = [None] * len(reqs)
+        t0 = time.perf_counter()
+
+        def feeder():
+            for k, (r, (V, T, x)) in enumerate(zip(reqs, data)):
+                dt = arrive[k] - (time.perf_counter() - t0)
+                if dt > 0:
+                    time.sleep(dt)
+                ids[k] = srv.submit(V, T, x, kind=H.REQ_SOLVE if r["solve"] else H.REQ_MATVEC,
+                                    E=r["E"], nu=r["nu"], eps=r["eps"], precision=prec, tol=1e-8,
+                                    restart=50)
+
+        th = threading.Thread(target=feeder)
+        th.start()
+        infos = []
+        for k in range(len(reqs)):
+            while ids[k] is None:
+                time.sleep(0.0005)
+            infos.append(srv.wait(ids[k])[1])
+        th.join()
+        srv.close()
+        lat = np.array([i["t_done_ms"] - i["t_submit_ms"] for i in infos])
+        lat_s = np.array([i["t_done_ms"] - i["t_submit_ms"] for i, r in zip(infos, reqs) if r["solve"]])
+        span = (max(i["t_done_ms"] for i in infos) - min(i["t_submit_ms"] for i in infos)) * 1e-3
+        relres = max((i["relres"] for i, r in zip(infos, reqs) if r["solve"]), default=0.0)
+        return {"slots": slots, "precision": "fp64" if prec == 0 else "fp32+fp64-refinement",
+                "arrival_rate_per_s": round(rate, 3) if rate else None,
+                "makespan_s": round(span, 3), "requests_per_s": round(len(reqs) / span, 3),
+                "solves_per_s": round(n_solves / span, 3),
+                "latency_p50_ms": round(percentile(lat, 0.5), 2),
+                "latency_p99_ms": round(percentile(lat, 0.99), 2),
+                "solve_latency_p50_ms": round(percentile(lat_s, 0.5), 2),
+                "solve_latency_p99_ms": round(percentile(lat_s, 0.99), 2),
+                "solve_relres_max": relres}
+
+    plain_cap = run(1, 0, None, "plain FP64, one at a time, all arrive at once")
+    serve_cap = run(args.slots, 1, None, f"serving, {args.slots} slots, mixed precision, all at once")
+    cap = plain_cap["requests_per_s"]
+    loads = {}
+    for f in (0.5, 1.0):
+        loads[f"{f}x"] = {"plain": run(1, 0, f * cap, f"plain FP64 at {f}x capacity"),
+                          "serving": run(args.slots, 1, f * cap, f"serving at {f}x capacity")}
+    out = {
+        "metric": "serving: solves/s and p50/p99 latency (Poisson arrivals), vs one-at-a-time FP64",
+        "value": serve_cap["solves_per_s"],
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "dtype": "f32 storage, f64 refinement",
+        "data": "synthetic",
+        "config": {"workload": "serve", "requests": len(reqs), "solves": n_solves,
+                   "dof_min": min(dof), "dof_max": max(dof), "dof_total": sum(dof),
+                   "slots": args.slots, "eta": 2.0, "leaf": 32, "tol": 1e-8},
+        "vs_plain_fp64": round(serve_cap["solves_per_s"] / plain_cap["solves_per_s"], 3),
+        "capacity": {"plain": plain_cap, "serving": serve_cap},
+        "poisson": loads,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["icosphere-L5", "icosphere-L3", "batch96"],
+    ap.add_argument("--workload", choices=["icosphere-L5", "icosphere-L3", "batch96", "serve"],
                     default="icosphere-L5")
+    ap.add_argument("--requests", type=int, default=120, help="serve: requests per run")
+    ap.add_argument("--slots", type=int, default=4, help="serve: concurrent requests")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=5.0)
     ap.add_argument("--solves", type=int, default=4, help="GMRES solves per step")
@@ -214,6 +312,9 @@ def main():
 
     if args.workload == "batch96":
         bench_batch(args)
+        return
+    if args.workload == "serve":
+        bench_serve(args)
         return
     wl = W.workload_c1() if args.workload == "icosphere-L5" else W.workload_c0()
     V, T = wl["vertices"], wl["triangles"]

@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <deque>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <string>
@@ -66,6 +67,35 @@ void check(hipError_t e, const char* what) {
   throw HipError{oom ? HMAT_ENOMEM : HMAT_EDEVICE, std::string(what) + ": " + hipGetErrorString(e)};
 }
 
+// Device memory is stream-ordered (hipMallocAsync / hipFreeAsync) on the
+// stream of the entry point being served, so allocating or freeing never
+// waits for work of other streams -- concurrent requests on their own
+// streams do not serialise on each other's allocations. Every entry point
+// sets the stream with a StreamScope; a buffer is used only on that stream
+// (calls on one handle are serialised by the caller).
+thread_local hipStream_t g_alloc_stream = nullptr;
+
+struct StreamScope {
+  hipStream_t prev;
+  explicit StreamScope(hipStream_t s) : prev(g_alloc_stream) { g_alloc_stream = s; }
+  ~StreamScope() { g_alloc_stream = prev; }
+};
+
+// Small freed blocks stay cached in the device's default pool (up to 4 GiB);
+// larger releases go back to the device at the next synchronisation.
+void init_pool() {
+  static std::once_flag once;
+  std::call_once(once, [] {
+    int dev = 0;
+    hipMemPool_t pool = nullptr;
+    if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+      uint64_t thr = (uint64_t)4 << 30;
+      (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    }
+    (void)hipGetLastError();
+  });
+}
+
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
@@ -74,14 +104,14 @@ struct DevBuf {
   DevBuf& operator=(const DevBuf&) = delete;
   ~DevBuf() { release(); }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) (void)hipFreeAsync(p, g_alloc_stream);
     p = nullptr;
     bytes = 0;
   }
   void alloc(size_t b, const char* what) {
     release();
     if (b == 0) return;
-    check(hipMalloc(&p, b), what);
+    check(hipMallocAsync(&p, b, g_alloc_stream), what);
     bytes = b;
   }
   template <class T>
@@ -118,8 +148,37 @@ double ms_since(std::chrono::steady_clock::time_point t0) {
 
 }  // namespace
 
+namespace {
+// Pinned host buffers for GMRES's Hessenberg columns (3 x 1026 doubles),
+// recycled across handles: allocating pinned memory synchronises the device.
+std::mutex g_pin_mu;
+std::vector<double*> g_pin_free;
+constexpr size_t PIN_DOUBLES = 3 * 1026;
+double* pinned_acquire() {
+  {
+    std::lock_guard<std::mutex> lk(g_pin_mu);
+    if (!g_pin_free.empty()) {
+      double* p = g_pin_free.back();
+      g_pin_free.pop_back();
+      return p;
+    }
+  }
+  double* p = nullptr;
+  if (hipHostMalloc((void**)&p, sizeof(double) * PIN_DOUBLES) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return p;
+}
+void pinned_release(double* p) {
+  std::lock_guard<std::mutex> lk(g_pin_mu);
+  g_pin_free.push_back(p);
+}
+}  // namespace
+
 struct hmat {
   int device = 0;
+  hipStream_t last_stream = nullptr;  // stream of the latest call (hmat_free syncs it)
   Plan plan;
   double eta = 0;
   int32_t leaf = 0;
@@ -192,7 +251,7 @@ struct hmat {
       for (hipEvent_t x : e) (void)hipEventDestroy(x);
     for (hipEvent_t e : col_ev)
       if (e) (void)hipEventDestroy(e);
-    if (h_pinned) (void)hipHostFree(h_pinned);
+    if (h_pinned) pinned_release(h_pinned);
   }
 };
 
@@ -220,8 +279,22 @@ int64_t far_layout(hmat* h) {
 // Product plan for the current ranks and V layout: phase-A items (largest
 // first), phase-B segments in product order with their stream offsets, chunks
 // of about MV_CHUNK_BYTES per tile. Sets stream_n; uploads the plan.
+// Build phase timing on stderr when HMAT_TRACE_BUILD is set (synchronises
+// the stream at every mark, so device work is charged to its phase).
+struct BuildTrace {
+  bool on = std::getenv("HMAT_TRACE_BUILD") != nullptr;
+  std::chrono::steady_clock::time_point last = std::chrono::steady_clock::now();
+  void mark(const char* what, hipStream_t s) {
+    if (!on) return;
+    (void)hipStreamSynchronize(s);
+    std::fprintf(stderr, "hmat build: %-28s %9.1f ms\n", what, ms_since(last));
+    last = std::chrono::steady_clock::now();
+  }
+};
+
 void build_product_plan(hmat* h, hipStream_t s) {
   const Plan& P = h->plan;
+  BuildTrace tr;
   // Phase-A items: groups of <= 8 columns of one V panel for one vector, of
   // <= 64 (four matrix-core tiles, sharing each load of the vectors) for
   // several; largest first.
@@ -243,10 +316,17 @@ void build_product_plan(hmat* h, hipStream_t s) {
     }
     z += k;
   }
-  for (auto& items : items_l)
-    std::stable_sort(items.begin(), items.end(), [](const MvA& a, const MvA& b) {
-      return (int64_t)a.ld * (a.l1 - a.l0) > (int64_t)b.ld * (b.l1 - b.l0);
-    });
+  for (auto& items : items_l) {
+    // largest first; equal sizes keep their canonical order
+    std::vector<std::pair<int64_t, int32_t>> key(items.size());
+    for (size_t t = 0; t < items.size(); t++)
+      key[t] = {-(int64_t)items[t].ld * (items[t].l1 - items[t].l0), (int32_t)t};
+    std::sort(key.begin(), key.end());
+    std::vector<MvA> sorted(items.size());
+    for (size_t t = 0; t < items.size(); t++) sorted[t] = items[key[t].second];
+    items.swap(sorted);
+  }
+  tr.mark("  plan: phase-A items", s);
   h->Ztot = std::max<int64_t>(round_up(z, 2), 2);
   // Column groups: the low-rank blocks of one row cluster (consecutive in
   // canonical order, so their z entries are contiguous) form one group whose
@@ -306,10 +386,17 @@ void build_product_plan(hmat* h, hipStream_t s) {
   }
   // dense-block segments first (launch 1 reads them with the phase-A items),
   // then low-rank segments; tile order within each group
-  std::stable_sort(segs.begin(), segs.end(), [](const SegT& a, const SegT& b) {
-    if (a.seg.far != b.seg.far) return a.seg.far < b.seg.far;
-    return a.tile < b.tile;
-  });
+  {
+    // stable counting sort by (far, tile)
+    const int64_t nT = (h->N + MV_TILE - 1) / MV_TILE;
+    std::vector<int64_t> cnt(2 * nT + 1, 0);
+    for (const SegT& t : segs) cnt[t.seg.far * nT + t.tile + 1]++;
+    for (size_t b = 1; b < cnt.size(); b++) cnt[b] += cnt[b - 1];
+    std::vector<SegT> sorted(segs.size());
+    for (const SegT& t : segs) sorted[cnt[t.seg.far * nT + t.tile]++] = t;
+    segs.swap(sorted);
+  }
+  tr.mark("  plan: groups, segments", s);
   h->nTiles = (int)((h->N + MV_TILE - 1) / MV_TILE);
   h->segs.assign(segs.size(), MvSeg{});
   h->seg_tile.assign(segs.size(), 0);
@@ -362,6 +449,7 @@ void build_product_plan(hmat* h, hipStream_t s) {
     }
     if (i != segs.size()) throw HipError{HMAT_EDEVICE, "internal: product plan: segments left over"};
   };
+  tr.mark("  plan: offsets, pieces", s);
   std::vector<MvChunk> chunk_l[2];
   std::vector<int32_t> tn_l[2], tf_l[2];
   int n_near_l[2] = {0, 0};
@@ -396,6 +484,7 @@ void build_product_plan(hmat* h, hipStream_t s) {
     }
   }
   h->nSeg = (int)h->segs.size();
+  tr.mark("  plan: chunks, checks", s);
   upload(h->d_seg, h->segs, s, "product plan");
   for (int l = 0; l < 2; l++) {
     upload(h->cl[l].d_items, items_l[l], s, "product plan");
@@ -513,19 +602,6 @@ struct EventPair {
     float t = 0.f;
     (void)hipEventElapsedTime(&t, a, b);
     return t;
-  }
-};
-
-// Build phase timing on stderr when HMAT_TRACE_BUILD is set (synchronises
-// the stream at every mark, so device work is charged to its phase).
-struct BuildTrace {
-  bool on = std::getenv("HMAT_TRACE_BUILD") != nullptr;
-  std::chrono::steady_clock::time_point last = std::chrono::steady_clock::now();
-  void mark(const char* what, hipStream_t s) {
-    if (!on) return;
-    (void)hipStreamSynchronize(s);
-    std::fprintf(stderr, "hmat build: %-28s %9.1f ms\n", what, ms_since(last));
-    last = std::chrono::steady_clock::now();
   }
 };
 
@@ -658,6 +734,7 @@ void merge_bodies(hmat* h, const std::vector<BodyIn>& in, double eta, int32_t le
 }
 
 thread_local int64_t g_aca_budget = 0;  // per-thread override (hm::set_thread_aca_budget)
+thread_local std::mutex* g_aca_gate = nullptr;  // held around the ACA phase (hm::set_thread_aca_gate)
 
 // Bytes of first-pass ACA panels that one group may hold at once: the
 // calling thread's override if set, else HMAT_ACA_BUDGET_MB, else a quarter
@@ -676,8 +753,11 @@ int64_t aca_budget() {
 hmat_status build_impl(const std::vector<BodyIn>& in, double eta, int32_t leaf, hipStream_t s,
                        hmat** out) {
   auto t0 = std::chrono::steady_clock::now();
+  StreamScope scope(s);
+  init_pool();
   hmat* h = new (std::nothrow) hmat();
   if (!h) return fail(HMAT_ENOMEM, "host allocation failed");
+  h->last_stream = s;
   try {
     check(hipGetDevice(&h->device), "hipGetDevice");
     if (const char* e = std::getenv("HMAT_MV_CHUNK_KB")) h->mv_chunk_bytes = std::max(1L, std::atol(e)) * 1024;
@@ -787,6 +867,10 @@ hmat_status build_impl(const std::vector<BodyIn>& in, double eta, int32_t leaf, 
     DevBuf panels1;  // first-pass panels, reused by every group
     BuildTrace tr;
     tr.mark("plan, geometry, K1", s);
+    // concurrent builds of a request server take the ACA phase one at a time
+    // (their host phases still overlap); the gate is released after it
+    std::unique_lock<std::mutex> gate;
+    if (g_aca_gate) gate = std::unique_lock<std::mutex>(*g_aca_gate);
     for (size_t f0 = 0; f0 < nf;) {
       size_t f1 = f0;
       int64_t bytes = 0;
@@ -805,10 +889,11 @@ hmat_status build_impl(const std::vector<BodyIn>& in, double eta, int32_t leaf, 
       run_aca_pass(h, grp, cap1, panels1, h->piv_bufs.back(), d_rank, d_stop, d_ratio, panel_ptr, s);
       h->aca_passes = std::max(h->aca_passes, 1);
       auto fetch = [&]() {
-        check(hipMemcpy(h->rank.data() + f0, d_rank.as<int32_t>() + f0, sizeof(int32_t) * (f1 - f0),
-                        hipMemcpyDeviceToHost), "ranks");
-        check(hipMemcpy(h->stop.data() + f0, d_stop.as<int32_t>() + f0, sizeof(int32_t) * (f1 - f0),
-                        hipMemcpyDeviceToHost), "ranks");
+        check(hipMemcpyAsync(h->rank.data() + f0, d_rank.as<int32_t>() + f0, sizeof(int32_t) * (f1 - f0),
+                             hipMemcpyDeviceToHost, s), "ranks");
+        check(hipMemcpyAsync(h->stop.data() + f0, d_stop.as<int32_t>() + f0, sizeof(int32_t) * (f1 - f0),
+                             hipMemcpyDeviceToHost, s), "ranks");
+        check(hipStreamSynchronize(s), "ranks");
       };
       fetch();
       std::vector<int32_t> again;
@@ -852,9 +937,14 @@ hmat_status build_impl(const std::vector<BodyIn>& in, double eta, int32_t leaf, 
       tr.mark("ACA group", s);
     }
     panels1.release();
+    if (gate.owns_lock()) {
+      check(hipStreamSynchronize(s), "ACA");
+      gate.unlock();
+    }
     const auto t_layout = std::chrono::steady_clock::now();
     if (nf > 0) {
-      check(hipMemcpy(h->ratio.data(), d_ratio.p, sizeof(double) * nf, hipMemcpyDeviceToHost), "ranks");
+      check(hipMemcpyAsync(h->ratio.data(), d_ratio.p, sizeof(double) * nf, hipMemcpyDeviceToHost, s), "ranks");
+      check(hipStreamSynchronize(s), "ranks");
       for (size_t f = 0; f < nf; f++)
         if (h->stop[f] == 5)
           throw HipError{HMAT_EINVAL, "non-finite matrix entries (overlapping or duplicate triangles?)"};
@@ -1004,7 +1094,10 @@ void ensure_gmres_ws(hmat* h, int m) {
   const size_t dp = dots_part_size(N, m + 1), np = norm_part_size(N);
   if (h->d_dotpart.bytes < sizeof(double) * (dp + np)) h->d_dotpart.alloc(sizeof(double) * (dp + np), "GMRES work");
   if (h->d_small.bytes < sizeof(double) * (4 * GM_COL + 8)) h->d_small.alloc(sizeof(double) * (4 * GM_COL + 8), "GMRES work");
-  if (!h->h_pinned) check(hipHostMalloc((void**)&h->h_pinned, sizeof(double) * 3 * GM_COL), "GMRES host buffer");
+  if (!h->h_pinned) {
+    h->h_pinned = pinned_acquire();
+    if (!h->h_pinned) throw HipError{HMAT_ENOMEM, "GMRES host buffer"};
+  }
   for (hipEvent_t& e : h->col_ev)
     if (!e) check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "GMRES event");
 }
@@ -1140,6 +1233,7 @@ hmat_status check_solve_args(hmat_t h, const double* b, const double* x, double 
 }  // namespace
 
 void hm::set_thread_aca_budget(int64_t bytes) { g_aca_budget = bytes > 0 ? bytes : 0; }
+void hm::set_thread_aca_gate(std::mutex* gate) { g_aca_gate = gate; }
 
 extern "C" {
 
@@ -1202,6 +1296,8 @@ hmat_status hmat_matvec(hmat_t h, int32_t nrhs, const double* x, int64_t ldx, do
   const char* ya = (const char*)y;
   const char* yb = (const char*)(y + (nrhs - 1) * ldy + h->N);
   if (xa < yb && ya < xb) return fail(HMAT_EINVAL, "x and y overlap");
+  StreamScope scope((hipStream_t)hip_stream);
+  h->last_stream = (hipStream_t)hip_stream;
   try {
     matvec_impl(h, 0, nrhs, x, ldx, y, ldy, (hipStream_t)hip_stream);
   } catch (const HipError& e) {
@@ -1215,6 +1311,8 @@ hmat_status hmat_solve(hmat_t h, const double* b, double* x, double tol, int32_t
   hmat_status st = check_solve_args(h, b, x, tol, restart, maxit);
   if (st != HMAT_OK) return st;
   hipStream_t s = (hipStream_t)hip_stream;
+  StreamScope scope(s);
+  h->last_stream = s;
   auto t0 = std::chrono::steady_clock::now();
   try {
     int used = 0, restarts = 0;
@@ -1245,6 +1343,8 @@ hmat_status hmat_solve_ir(hmat_t h, const double* b, double* x, double tol, int3
     return fail(HMAT_EINVAL, "no FP32 copy: call hmat_set_precision(h, 1, ...) first");
   if (!(inner_tol > 0.0 && inner_tol < 1.0)) return fail(HMAT_EINVAL, "inner_tol must lie in (0, 1)");
   hipStream_t s = (hipStream_t)hip_stream;
+  StreamScope scope(s);
+  h->last_stream = s;
   auto t0 = std::chrono::steady_clock::now();
   const int64_t N = h->N;
   try {
@@ -1310,6 +1410,8 @@ hmat_status hmat_set_precision(hmat_t h, int32_t precision, void* hip_stream) {
   if (!h) return fail(HMAT_EINVAL, "handle is NULL");
   if (precision != 0 && precision != 1) return fail(HMAT_EINVAL, "precision must be 0 (FP64) or 1 (FP32)");
   hipStream_t s = (hipStream_t)hip_stream;
+  StreamScope scope(s);
+  h->last_stream = s;
   try {
     check(hipStreamSynchronize(s), "set precision");
     h->far32.release();
@@ -1345,6 +1447,8 @@ hmat_status hmat_matvec_ex(hmat_t h, int32_t precision, int32_t nrhs, const doub
   const char* ya = (const char*)y;
   const char* yb = (const char*)(y + (nrhs - 1) * ldy + h->N);
   if (xa < yb && ya < xb) return fail(HMAT_EINVAL, "x and y overlap");
+  StreamScope scope((hipStream_t)hip_stream);
+  h->last_stream = (hipStream_t)hip_stream;
   try {
     matvec_impl(h, precision, nrhs, x, ldx, y, ldy, (hipStream_t)hip_stream);
   } catch (const HipError& e) {
@@ -1362,8 +1466,11 @@ hmat_status hmat_info(hmat_t h, hmat_stats* st) {
 
 hmat_status hmat_free(hmat_t h) {
   if (!h) return HMAT_OK;
-  (void)hipDeviceSynchronize();
+  const hipStream_t s = h->last_stream;
+  StreamScope scope(s);
+  (void)hipStreamSynchronize(s);
   delete h;
+  (void)hipStreamSynchronize(s);
   return HMAT_OK;
 }
 
@@ -1416,9 +1523,10 @@ hmat_status hmat_block(hmat_t h, int32_t b, int32_t* info, double* A, double* B,
     info[6] = R.far ? h->stop[idx] : 0;
     info[7] = 0;
   }
+  StreamScope scope(h->last_stream);
   try {
     if (R.far) {
-      if (A) copy_stream_out(h, b, m, k, A, nullptr);
+      if (A) copy_stream_out(h, b, m, k, A, h->last_stream);
       if (B) copy_v_out(h, idx, n, k, B);
       if (h->piv_ptr[idx] && k) {
         if (prow) check(hipMemcpy(prow, h->piv_ptr[idx], sizeof(int32_t) * k, hipMemcpyDeviceToHost), "pivots");
@@ -1426,7 +1534,7 @@ hmat_status hmat_block(hmat_t h, int32_t b, int32_t* info, double* A, double* B,
           check(hipMemcpy(pcol, h->piv_ptr[idx] + h->piv_cap[idx], sizeof(int32_t) * k, hipMemcpyDeviceToHost), "pivots");
       }
     } else if (A) {
-      copy_stream_out(h, b, m, n, A, nullptr);
+      copy_stream_out(h, b, m, n, A, h->last_stream);
     }
   } catch (const HipError& e) {
     return fail(e.st, e.msg);
@@ -1449,6 +1557,8 @@ hmat_status hmat_entries(hmat_t h, int64_t n, const int64_t* rows, const int64_t
   }
   if (n == 0) return HMAT_OK;
   hipStream_t s = (hipStream_t)hip_stream;
+  StreamScope scope(s);
+  h->last_stream = s;
   try {
     DevBuf dr, dc, dout;
     upload(dr, r, s, "entries");
@@ -1467,6 +1577,8 @@ hmat_status hmat_set_factors(hmat_t h, const int32_t* ranks, const double* U, co
                              void* hip_stream) {
   if (!h || !ranks) return fail(HMAT_EINVAL, "handle or ranks is NULL");
   hipStream_t s = (hipStream_t)hip_stream;
+  StreamScope scope(s);
+  h->last_stream = s;
   const size_t nf = h->far_blocks.size();
   int64_t total = 0, usz = 0;
   for (size_t f = 0; f < nf; f++) {
@@ -1518,9 +1630,10 @@ hmat_status hmat_set_factors(hmat_t h, const int32_t* ranks, const double* U, co
       uo += m * k;
       vo += n * k;
     }
-    if (uo > 0) check(hipMemcpy(u_stage.p, U, sizeof(double) * uo, hipMemcpyHostToDevice), "set factors");
+    if (uo > 0) check(hipMemcpyAsync(u_stage.p, U, sizeof(double) * uo, hipMemcpyHostToDevice, s), "set factors");
     h->far_arena.alloc(sizeof(double) * host.size(), "low-rank arena");
-    check(hipMemcpy(h->far_arena.p, host.data(), sizeof(double) * host.size(), hipMemcpyHostToDevice), "set factors");
+    check(hipMemcpyAsync(h->far_arena.p, host.data(), sizeof(double) * host.size(), hipMemcpyHostToDevice, s), "set factors");
+    check(hipStreamSynchronize(s), "set factors");
     build_product_plan(h, s);
     fill_stream(h, near_stage.as<double>(), near_off, u_ptr, s);
   } catch (const HipError& e) {

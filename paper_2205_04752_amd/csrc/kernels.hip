@@ -194,12 +194,13 @@ __global__ void k_entries(DevGeo g0, int64_t n, const int64_t* __restrict__ rows
 // sets: a slot set is rewritten only after every thread has passed the
 // barrier of the following reduction, so one barrier per reduction suffices.
 
-constexpr int ACA_T = 256;
-constexpr int NW = ACA_T / WAVE;
+constexpr int ACA_T = 256;      // workgroup of the ACA kernel
+constexpr int NW = 256 / WAVE;  // waves of a 256-thread workgroup
 
-struct Red {
-  double d[2][2][NW];
-  int i[2][NW];
+template <int NWV>
+struct RedT {
+  double d[2][2][NWV];
+  int i[2][NWV];
 };
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -215,27 +216,30 @@ __device__ __forceinline__ int wave_min(int v) {
   return v;
 }
 
-__device__ __forceinline__ double blk_max(double v, Red& R, int& ph) {
+template <int NWV>
+__device__ __forceinline__ double blk_max(double v, RedT<NWV>& R, int& ph) {
   v = wave_max(v);
   if ((threadIdx.x & (WAVE - 1)) == 0) R.d[ph][0][threadIdx.x / WAVE] = v;
   __syncthreads();
   double r = R.d[ph][0][0];
 #pragma unroll
-  for (int w = 1; w < NW; w++) r = fmax(r, R.d[ph][0][w]);
+  for (int w = 1; w < NWV; w++) r = fmax(r, R.d[ph][0][w]);
   ph ^= 1;
   return r;
 }
-__device__ __forceinline__ int blk_min(int v, Red& R, int& ph) {
+template <int NWV>
+__device__ __forceinline__ int blk_min(int v, RedT<NWV>& R, int& ph) {
   v = wave_min(v);
   if ((threadIdx.x & (WAVE - 1)) == 0) R.i[ph][threadIdx.x / WAVE] = v;
   __syncthreads();
   int r = R.i[ph][0];
 #pragma unroll
-  for (int w = 1; w < NW; w++) r = min(r, R.i[ph][w]);
+  for (int w = 1; w < NWV; w++) r = min(r, R.i[ph][w]);
   ph ^= 1;
   return r;
 }
-__device__ __forceinline__ void blk_sum2(double& a, double& b, Red& R, int& ph) {
+template <int NWV>
+__device__ __forceinline__ void blk_sum2(double& a, double& b, RedT<NWV>& R, int& ph) {
   a = wave_sum(a);
   b = wave_sum(b);
   if ((threadIdx.x & (WAVE - 1)) == 0) {
@@ -246,7 +250,7 @@ __device__ __forceinline__ void blk_sum2(double& a, double& b, Red& R, int& ph) 
   a = R.d[ph][0][0];
   b = R.d[ph][1][0];
 #pragma unroll
-  for (int w = 1; w < NW; w++) {
+  for (int w = 1; w < NWV; w++) {
     a += R.d[ph][0][w];
     b += R.d[ph][1][w];
   }
@@ -256,19 +260,74 @@ __device__ __forceinline__ void blk_sum2(double& a, double& b, Red& R, int& ph) 
 __device__ __forceinline__ bool in_z(const uint32_t* Z, int r) { return (Z[r >> 5] >> (r & 31)) & 1u; }
 
 // Fuzzy argmax over rows not in Z: lowest r with |u_r| >= (1 - 1e-10) max.
-__device__ int argmax_free(const double* __restrict__ u, int m, const uint32_t* Z, Red& R, int& ph) {
+template <int TPB>
+__device__ int argmax_free(const double* __restrict__ u, int m, const uint32_t* Z,
+                           RedT<TPB / WAVE>& R, int& ph) {
   double mx = -1.0;
-  for (int r = threadIdx.x; r < m; r += ACA_T)
+  for (int r = threadIdx.x; r < m; r += TPB)
     if (!in_z(Z, r)) mx = fmax(mx, fabs(u[r]));
   mx = blk_max(mx, R, ph);
   const double thr = (1.0 - 1e-10) * mx;
   int cand = INT_MAX;
-  for (int r = threadIdx.x; r < m; r += ACA_T)
+  for (int r = threadIdx.x; r < m; r += TPB)
     if (!in_z(Z, r) && fabs(u[r]) >= thr) {
       cand = r;
       break;
     }
   return blk_min(cand, R, ph);
+}
+
+// e_b -= sum_{l<k} coef[l] * P[l*ld + b] for b = 0..2 (one triangle's three
+// rows or columns of a panel); four columns per step with separate sums, so
+// twelve loads are in flight.
+__device__ __forceinline__ void sub_panel3(const double* __restrict__ coef, const double* P,
+                                           int k, int ld, double& e0, double& e1, double& e2) {
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, b0 = 0.0, b1 = 0.0, b2 = 0.0;
+  double c0 = 0.0, c1 = 0.0, c2 = 0.0, d0 = 0.0, d1 = 0.0, d2 = 0.0;
+  int l = 0;
+  for (; l + 3 < k; l += 4) {
+    const double* p0 = P + (size_t)l * ld;
+    const double* p1 = p0 + ld;
+    const double* p2 = p1 + ld;
+    const double* p3 = p2 + ld;
+    const double w0 = coef[l], w1 = coef[l + 1], w2 = coef[l + 2], w3 = coef[l + 3];
+    a0 += w0 * p0[0];
+    a1 += w0 * p0[1];
+    a2 += w0 * p0[2];
+    b0 += w1 * p1[0];
+    b1 += w1 * p1[1];
+    b2 += w1 * p1[2];
+    c0 += w2 * p2[0];
+    c1 += w2 * p2[1];
+    c2 += w2 * p2[2];
+    d0 += w3 * p3[0];
+    d1 += w3 * p3[1];
+    d2 += w3 * p3[2];
+  }
+  for (; l < k; l++) {
+    const double* p0 = P + (size_t)l * ld;
+    const double w0 = coef[l];
+    a0 += w0 * p0[0];
+    a1 += w0 * p0[1];
+    a2 += w0 * p0[2];
+  }
+  e0 -= (a0 + b0) + (c0 + d0);
+  e1 -= (a1 + b1) + (c1 + d1);
+  e2 -= (a2 + b2) + (c2 + d2);
+}
+
+// sum_r x[r] y[r] over r = lane, lane + 64, ... < n; four partial sums.
+__device__ __forceinline__ double lane_dot(const double* x, const double* y, int n, int lane) {
+  double a = 0.0, b = 0.0, c = 0.0, d = 0.0;
+  int r = lane;
+  for (; r + 3 * WAVE < n; r += 4 * WAVE) {
+    a += x[r] * y[r];
+    b += x[r + WAVE] * y[r + WAVE];
+    c += x[r + 2 * WAVE] * y[r + 2 * WAVE];
+    d += x[r + 3 * WAVE] * y[r + 3 * WAVE];
+  }
+  for (; r < n; r += WAVE) a += x[r] * y[r];
+  return (a + b) + (c + d);
 }
 
 // K2: ACA (Algorithm 1) on the DOF block of task blockIdx.x.
@@ -281,12 +340,14 @@ __device__ int argmax_free(const double* __restrict__ u, int m, const uint32_t* 
 //   no finite pivot (5: non-finite entries; reported as an error).
 // Panels live in global memory (column-major U m x kcap, V n x kcap); the
 // coefficient row U[i, 0:k] / V[j, 0:k] and the set Z are staged in LDS.
-__global__ __launch_bounds__(ACA_T) void k_aca(DevGeo g0, const AcaTask* __restrict__ tasks,
+template <int TPB>
+__global__ __launch_bounds__(TPB) void k_aca(DevGeo g0, const AcaTask* __restrict__ tasks,
                                                int32_t* __restrict__ rank_out,
                                                int32_t* __restrict__ stop_out,
                                                double* __restrict__ ratio_out) {
   extern __shared__ double sh[];
-  __shared__ Red R;
+  constexpr int NWV = TPB / WAVE;
+  __shared__ RedT<NWV> R;
   const AcaTask T = tasks[blockIdx.x];
   const DevGeo g = body_geo(g0, T.t_off);
   const double eps = T.eps;
@@ -297,13 +358,13 @@ __global__ __launch_bounds__(ACA_T) void k_aca(DevGeo g0, const AcaTask* __restr
   double* coef = sh;
   uint32_t* Z = reinterpret_cast<uint32_t*>(sh + kcap);
   const int zw = (m + 31) >> 5;
-  for (int w = tid; w < zw; w += ACA_T) Z[w] = 0u;
+  for (int w = tid; w < zw; w += TPB) Z[w] = 0u;
   const int nt = g.nt;
   int ph = 0, k = 0, nZ = 0, i = 0, stop = 0;
   double S2 = 0.0, ratio = 0.0;
   __syncthreads();
   for (;;) {
-    for (int l = tid; l < k; l += ACA_T) coef[l] = U[i + (size_t)l * m];
+    for (int l = tid; l < k; l += TPB) coef[l] = U[i + (size_t)l * m];
     if (tid == 0) Z[i >> 5] |= (1u << (i & 31));
     nZ++;
     __syncthreads();
@@ -312,16 +373,10 @@ __global__ __launch_bounds__(ACA_T) void k_aca(DevGeo g0, const AcaTask* __restr
     const int pi = T.t_off + i / 3, ai = i % 3;
     const double x0 = g.cen[pi], x1 = g.cen[nt + pi], x2 = g.cen[2 * nt + pi];
     double mx = 0.0;
-    for (int q = tid; q < T.s_len; q += ACA_T) {
+    for (int q = tid; q < T.s_len; q += TPB) {
       double e0, e1, e2;
       row3(g, x0, x1, x2, ai, T.s_off + q, e0, e1, e2);
-      const double* vc = V + 3 * q;
-      for (int l = 0; l < k; l++, vc += n) {
-        const double c = coef[l];
-        e0 -= c * vc[0];
-        e1 -= c * vc[1];
-        e2 -= c * vc[2];
-      }
+      sub_panel3(coef, V + 3 * q, k, n, e0, e1, e2);
       vk[3 * q] = e0;
       vk[3 * q + 1] = e1;
       vk[3 * q + 2] = e2;
@@ -336,14 +391,14 @@ __global__ __launch_bounds__(ACA_T) void k_aca(DevGeo g0, const AcaTask* __restr
       }
       if (k == 0) {
         int cand = INT_MAX;
-        for (int r = tid; r < m; r += ACA_T)
+        for (int r = tid; r < m; r += TPB)
           if (!in_z(Z, r)) {
             cand = r;
             break;
           }
         i = blk_min(cand, R, ph);
       } else {
-        i = argmax_free(U + (size_t)(k - 1) * m, m, Z, R, ph);
+        i = argmax_free<TPB>(U + (size_t)(k - 1) * m, m, Z, R, ph);
       }
       if (i >= m) {
         stop = 5;
@@ -353,7 +408,7 @@ __global__ __launch_bounds__(ACA_T) void k_aca(DevGeo g0, const AcaTask* __restr
     }
     const double thr = (1.0 - 1e-10) * mx;
     int cand = INT_MAX;
-    for (int c = tid; c < n; c += ACA_T)
+    for (int c = tid; c < n; c += TPB)
       if (fabs(vk[c]) >= thr) {
         cand = c;
         break;
@@ -366,42 +421,34 @@ __global__ __launch_bounds__(ACA_T) void k_aca(DevGeo g0, const AcaTask* __restr
     const double piv = vk[j];
     __syncthreads();  // every thread holds piv before vk is normalised in place
     double vv = 0.0;
-    for (int c = tid; c < n; c += ACA_T) {
+    for (int c = tid; c < n; c += TPB) {
       const double v = vk[c] / piv;
       vk[c] = v;
       vv += v * v;
     }
-    for (int l = tid; l < k; l += ACA_T) coef[l] = V[j + (size_t)l * n];
+    for (int l = tid; l < k; l += TPB) coef[l] = V[j + (size_t)l * n];
     __syncthreads();
     // column j of the remainder into U[:, k] (S is symmetric: A[3p+a, 3q+b] = S_ba)
     double* __restrict__ uk = U + (size_t)k * m;
     const int qj = T.s_off + j / 3, bj = j % 3;
     double uu = 0.0;
-    for (int p = tid; p < T.t_len; p += ACA_T) {
+    for (int p = tid; p < T.t_len; p += TPB) {
       const int ip = T.t_off + p;
       double e0, e1, e2;
       row3(g, g.cen[ip], g.cen[nt + ip], g.cen[2 * nt + ip], bj, qj, e0, e1, e2);
-      const double* uc = U + 3 * p;
-      for (int l = 0; l < k; l++, uc += m) {
-        const double c = coef[l];
-        e0 -= c * uc[0];
-        e1 -= c * uc[1];
-        e2 -= c * uc[2];
-      }
+      sub_panel3(coef, U + 3 * p, k, m, e0, e1, e2);
       uk[3 * p] = e0;
       uk[3 * p + 1] = e1;
       uk[3 * p + 2] = e2;
       uu += e0 * e0 + e1 * e1 + e2 * e2;
     }
     blk_sum2(uu, vv, R, ph);
-    // sum_{l<k} (u_l . u_k)(v_l . v_k): wave w takes l = w, w + NW, ...
+    // sum_{l<k} (u_l . u_k)(v_l . v_k): wave w takes l = w, w + NWV, ...
     double cr = 0.0;
-    for (int l = wv; l < k; l += NW) {
+    for (int l = wv; l < k; l += NWV) {
       const double* ul = U + (size_t)l * m;
       const double* vl = V + (size_t)l * n;
-      double a = 0.0, b = 0.0;
-      for (int r = lane; r < m; r += WAVE) a += ul[r] * uk[r];
-      for (int c = lane; c < n; c += WAVE) b += vl[c] * vk[c];
+      const double a = lane_dot(ul, uk, m, lane), b = lane_dot(vl, vk, n, lane);
       cr += wave_sum(a) * wave_sum(b);
     }
     double cross = (lane == 0) ? cr : 0.0, dummy = 0.0;
@@ -418,7 +465,7 @@ __global__ __launch_bounds__(ACA_T) void k_aca(DevGeo g0, const AcaTask* __restr
     if (k == kmax) { stop = 2; break; }
     if (nZ == m) { stop = 3; break; }
     if (k == kcap) { stop = 4; break; }
-    i = argmax_free(uk, m, Z, R, ph);
+    i = argmax_free<TPB>(uk, m, Z, R, ph);
     if (i >= m) {
       stop = 5;
       break;
@@ -1148,12 +1195,13 @@ hipError_t launch_entries(const DevGeo& g, int64_t n, const int64_t* rows, const
 hipError_t launch_aca(const DevGeo& g, const AcaTask* tasks, int ntasks, size_t shmem,
                       int32_t* rank, int32_t* stop, double* ratio, hipStream_t s) {
   if (shmem > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_aca),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_aca<ACA_T>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
     if (e != hipSuccess) return e;
   }
   if (ntasks > 0)
-    hipLaunchKernelGGL(k_aca, dim3(ntasks), dim3(ACA_T), shmem, s, g, tasks, rank, stop, ratio);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_aca<ACA_T>), dim3(ntasks), dim3(ACA_T), shmem, s, g, tasks,
+                       rank, stop, ratio);
   return hipGetLastError();
 }
 

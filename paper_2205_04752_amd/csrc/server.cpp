@@ -69,6 +69,7 @@ struct hmat_server {
   int32_t leaf = 32;
   Clock::time_point t0 = Clock::now();
   std::mutex mu;
+  std::mutex aca_gate;  // one build's ACA phase at a time
   std::condition_variable cv_work, cv_done;
   std::deque<std::shared_ptr<Request>> pending;
   std::map<int64_t, std::shared_ptr<Request>> all;
@@ -93,10 +94,17 @@ hmat_status srv_fail(hmat_status st, const std::string& m) {
   return st;
 }
 
+// Request vectors, stream-ordered on the worker's stream (no device-wide
+// synchronisation on allocation or release).
 struct DevVec {
   double* p = nullptr;
+  hipStream_t s = nullptr;
+  bool alloc(size_t bytes, hipStream_t st) {
+    s = st;
+    return hipMallocAsync((void**)&p, bytes, st) == hipSuccess;
+  }
   ~DevVec() {
-    if (p) (void)hipFree(p);
+    if (p) (void)hipFreeAsync(p, s);
   }
 };
 
@@ -133,8 +141,7 @@ void hmat_server::execute(Request& r, hipStream_t s) {
   cv_work.notify_all();
   const int nv = r.q.kind == HMAT_REQ_SOLVE ? 1 : r.q.nvec;
   DevVec dx, dy;
-  if (hipMalloc(&dx.p, sizeof(double) * N * nv) != hipSuccess ||
-      hipMalloc(&dy.p, sizeof(double) * N * nv) != hipSuccess) {
+  if (!dx.alloc(sizeof(double) * N * nv, s) || !dy.alloc(sizeof(double) * N * nv, s)) {
     (void)hipGetLastError();
     g_srv_err = "request vectors: out of device memory";
     r.res.status = HMAT_ENOMEM;
@@ -179,6 +186,7 @@ void hmat_server::execute(Request& r, hipStream_t s) {
 void hmat_server::run_worker() {
   (void)hipSetDevice(device);
   hm::set_thread_aca_budget(aca_cap);
+  hm::set_thread_aca_gate(&aca_gate);
   hipStream_t s = nullptr;
   if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
     (void)hipGetLastError();

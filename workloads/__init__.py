@@ -315,3 +315,52 @@ def workload_c2():
     8 right-hand sides per body; eta 2, leaf 32."""
     return dict(name="batch96", bodies=batch_bodies(96, 2000, 40000, seed=2, eps=1e-5), eta=2.0,
                 leaf=32, nrhs=8)
+
+
+def serving_requests(n_requests: int = 2000, seed: int = 4, dof_lo: int = 1000,
+                     dof_hi: int = 80000):
+    """Requests of the serving workload, from NumPy PCG64 ``default_rng(seed)``.
+
+    Per request, in this order: the mesh type, uniform over sphere, ellipsoid,
+    torus; the DOF count log-uniform in [dof_lo, dof_hi] (triangles = DOF/3);
+    for an ellipsoid three semi-axes uniform in [0.5, 2], for a torus r uniform
+    in [0.2, 0.5] (R = 1); Poisson's ratio uniform in [0.2, 0.45]; eps uniform
+    over {1e-3, 1e-5, 1e-7}; a solve (probability 1/2) or m products with m
+    uniform in 1..32; then the seed of the request's vectors. Spheres and
+    ellipsoids are geodesic spheres of frequency round(sqrt(n/20)); tori use the
+    grid rule of ``batch_bodies``. Meshes are generated lazily by ``mesh_of``.
+    """
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n_requests):
+        kind = ("sphere", "ellipsoid", "torus")[int(rng.integers(0, 3))]
+        dof = float(np.exp(rng.uniform(np.log(dof_lo), np.log(dof_hi))))
+        n = dof / 3.0
+        shape = {}
+        if kind == "ellipsoid":
+            shape["axes"] = tuple(float(a) for a in rng.uniform(0.5, 2.0, 3))
+        elif kind == "torus":
+            shape["r"] = float(rng.uniform(0.2, 0.5))
+        nu = float(rng.uniform(0.2, 0.45))
+        eps = (1e-3, 1e-5, 1e-7)[int(rng.integers(0, 3))]
+        solve = bool(rng.random() < 0.5)
+        m = 1 if solve else int(rng.integers(1, 33))
+        vseed = int(rng.integers(0, 2**31 - 1))
+        out.append(dict(kind=kind, n=n, shape=shape, nu=nu, E=1.0, eps=eps, solve=solve, m=m,
+                        vseed=vseed))
+    return out
+
+
+def mesh_of(req: dict):
+    """Mesh of a serving request (see ``serving_requests``)."""
+    n = req["n"]
+    if req["kind"] == "torus":
+        r = req["shape"]["r"]
+        nv = max(3, int(round(np.sqrt(n * r / 2.0))))
+        nu_ = max(3, int(round(n / (2.0 * nv))))
+        return torus(1.0, r, nu_, nv)
+    f = max(1, int(round(np.sqrt(n / 20.0))))
+    V, T = geodesic_sphere(f)
+    if req["kind"] == "ellipsoid":
+        V = V * np.asarray(req["shape"]["axes"])[None, :]
+    return V, T
