@@ -50,6 +50,8 @@ def lib():
     L.or_h_plan.argtypes = [vp, C.c_double, C.c_int]
     L.or_h_fill.restype = C.c_int
     L.or_h_fill.argtypes = [vp, C.c_double]
+    L.or_h_fill_steps.restype = C.c_int
+    L.or_h_fill_steps.argtypes = [vp, C.c_int]
     L.or_h_free.argtypes = [vp]
     L.or_h_nclusters.restype = C.c_int
     L.or_h_nclusters.argtypes = [vp]
@@ -200,6 +202,12 @@ class HMatrix:
     def fill(self, eps: float) -> None:
         if lib().or_h_fill(self._h, float(eps)) != 0:
             raise ValueError("oracle: invalid eps")
+
+    def fill_steps(self, kcap: int) -> None:
+        """Dense blocks, and ACA on every admissible block for kcap steps
+        without the accuracy test (crosses for the adaptive multiplication)."""
+        if lib().or_h_fill_steps(self._h, int(kcap)) != 0:
+            raise ValueError("oracle: invalid step count")
 
     @property
     def order(self) -> np.ndarray:

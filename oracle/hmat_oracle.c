@@ -376,7 +376,8 @@ static int fuzzy_argmax(const double* v, int n, const unsigned char* skip) {
 }
 
 static int aca_core(int m, int n, or_rowfn rowf, or_colfn colf, void* user, double eps,
-                    double** pU, double** pV, int* prow, int* pcol, int* stop, double* ratio) {
+                    int kcap, double** pU, double** pV, int* prow, int* pcol, int* stop,
+                    double* ratio) {
   int kmax = m < n ? m : n;
   int cap = 8 < kmax ? 8 : kmax;
   double* U = (double*)malloc(sizeof(double) * (size_t)m * cap);
@@ -443,6 +444,7 @@ static int aca_core(int m, int n, or_rowfn rowf, or_colfn colf, void* user, doub
     if (lhs <= rhs) { *stop = 1; break; }
     if (k == kmax) { *stop = 2; break; }
     if (nZ == m) { *stop = 3; break; }
+    if (kcap > 0 && k == kcap) { *stop = 4; break; }
     i = fuzzy_argmax(u, m, Z);
   }
   free(Z); free(vt); free(ut);
@@ -466,7 +468,7 @@ int or_aca_dense(int m, int n, const double* A, double eps, double* U, double* V
                  int* pcol, int* stop, double* ratio) {
   dense_src s = {m, n, A};
   double *Ui, *Vi;
-  int k = aca_core(m, n, dense_row, dense_col, &s, eps, &Ui, &Vi, prow, pcol, stop, ratio);
+  int k = aca_core(m, n, dense_row, dense_col, &s, eps, 0, &Ui, &Vi, prow, pcol, stop, ratio);
   memcpy(U, Ui, sizeof(double) * (size_t)m * k);
   memcpy(V, Vi, sizeof(double) * (size_t)n * k);
   free(Ui); free(Vi);
@@ -729,9 +731,25 @@ static int cmp_cost(const void* a, const void* b) {
   return x < y ? -1 : (x > y ? 1 : 0);
 }
 
+static int h_fill(or_hmat* h, double eps, int kcap);
+
 /* Dense blocks entry by entry (Sec. 2.2) and ACA on every admissible block. */
 int or_h_fill(or_hmat* h, double eps) {
   if (!(eps > 0.0 && eps < 1.0)) return 1;
+  return h_fill(h, eps, 0);
+}
+
+/* The same with ACA run for a fixed number of steps: no accuracy test
+ * (eps = 0), stopping at k = kcap (stop code 4) unless a block is exhausted
+ * first (k = min(m,n), or every row used). ACA is sequential, so the first
+ * r crosses of such a run are those of any run that takes r steps: the
+ * adaptive multiplication (Algorithm 2) uses prefixes of these crosses. */
+int or_h_fill_steps(or_hmat* h, int kcap) {
+  if (kcap < 1) return 1;
+  return h_fill(h, 0.0, kcap);
+}
+
+static int h_fill(or_hmat* h, double eps, int kcap) {
   h->eps = eps;
   int nb = h->nb;
   h->rank = (int*)calloc(nb, sizeof(int));
@@ -777,7 +795,7 @@ int or_h_fill(or_hmat* h, double eps) {
     blk_src src = {h, B->t, B->s};
     h->prow[b] = (int*)malloc(sizeof(int) * kmax);
     h->pcol[b] = (int*)malloc(sizeof(int) * kmax);
-    h->rank[b] = aca_core(m, n, blk_row, blk_col, &src, eps, &h->U[b], &h->Vf[b], h->prow[b],
+    h->rank[b] = aca_core(m, n, blk_row, blk_col, &src, eps, kcap, &h->U[b], &h->Vf[b], h->prow[b],
                           h->pcol[b], &h->stop[b], &h->ratio[b]);
   }
   free(idx);

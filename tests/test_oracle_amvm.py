@@ -1,0 +1,160 @@
+"""Pins of the oracle's adaptive matrix-vector multiplication (Algorithm 2).
+
+Checked against quantities recomputed here from the oracle's ACA crosses as
+dense block matrices (no code shared with oracle/amvm.py's row bookkeeping):
+  * ACA run for a fixed number of steps gives, for every block, the same
+    crosses as the accuracy-controlled run (ACA is sequential), so prefixes
+    are resumed ACA;
+  * gamma_k = ||b_k - b^_k|| with A_k, A^_k assembled densely from the ranks
+    recorded at every round;
+  * the marked set meets the Doerfler condition gamma_k(P_k) <= (1-theta)
+    gamma_k (the Remark after Algorithm 2), every marked block has a row
+    entry above the threshold, and only marked blocks grow, by two steps;
+  * x = 0 needs no ACA step; blocks whose columns meet no nonzero of x are
+    never refined;
+  * the result converges to the exact collocation product, and the
+    estimator stays within a factor 2 of the true error (the paper's
+    efficiency/reliability figure) once the saturation regime is reached.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from oracle.amvm import amvm
+
+pytestmark = pytest.mark.filterwarnings("ignore")
+
+
+def _point_force_x(V, T, p=(5.0, 5.0, 5.0)):
+    """Smooth data: x_i = S(c_i - p) e_3 at the centroids (the paper's example)."""
+    c = V[T].mean(axis=1)
+    return np.concatenate([O.kelvin(ci - np.asarray(p))[:, 2] for ci in c])
+
+
+@pytest.fixture(scope="module")
+def small():
+    V, T = W.icosphere(2)
+    mesh = O.Mesh(V, T, 1.0, 0.3)
+    return V, T, mesh
+
+
+def _dense_blocks(hm):
+    ob = hm.blocks()
+    far = {}
+    for b in np.nonzero(ob[:, 4] == 1)[0]:
+        U, Vv, _, _ = hm.factors(int(b))
+        far[int(b)] = (U, Vv)
+    return ob, far
+
+
+def _assemble(hm, ob, far, ranks, extra=0):
+    """Dense cluster-order matrix with admissible block b at rank ranks[b] + extra."""
+    order = hm.order
+    N = 3 * len(order)
+    A = np.zeros((N, N))
+    for b in range(len(ob)):
+        rs = slice(3 * ob[b, 0], 3 * (ob[b, 0] + ob[b, 1]))
+        cs = slice(3 * ob[b, 2], 3 * (ob[b, 2] + ob[b, 3]))
+        if ob[b, 4]:
+            U, Vv = far[b]
+            r = min(int(ranks[b]) + extra, U.shape[1])
+            A[rs, cs] = U[:, :r] @ Vv[:, :r].T
+        else:
+            A[rs, cs] = hm.dense_block(b)
+    perm = (3 * order[:, None] + np.arange(3)).ravel()
+    return A, perm
+
+
+def test_step_limited_aca_prefixes(small):
+    V, T, mesh = small
+    a = O.HMatrix(mesh, 2.0, 16)
+    a.fill_steps(96)
+    e = O.HMatrix(mesh, 2.0, 16, eps=1e-6)
+    ob = e.blocks()
+    for b in np.nonzero(ob[:, 4] == 1)[0]:
+        Ue, Ve, pre, pce = e.factors(int(b))
+        Ua, Va, pra, pca = a.factors(int(b))
+        k = min(Ue.shape[1], Ua.shape[1])
+        assert np.array_equal(pre[:k], pra[:k]) and np.array_equal(pce[:k], pca[:k])
+        assert np.array_equal(Ue[:, :k], Ua[:, :k]) and np.array_equal(Ve[:, :k], Va[:, :k])
+
+
+def test_rounds_against_dense_recomputation(small):
+    V, T, mesh = small
+    x = _point_force_x(V, T)
+    theta = 0.5
+    y, hist, hm = amvm(mesh, x, theta=theta, tol=1e-7, leaf=16, kcap=96)
+    ob, far = _dense_blocks(hm)
+    assert len(hist) > 3
+    for k, rec in enumerate(hist):
+        Ak, perm = _assemble(hm, ob, far, rec["ranks"])
+        Ah, _ = _assemble(hm, ob, far, rec["ranks"], extra=2)
+        xp = x[perm]
+        gk = np.linalg.norm((Ak - Ah) @ xp)
+        assert abs(gk - rec["gamma"]) <= 1e-12 * max(gk, 1e-300), (k, gk, rec["gamma"])
+        if not rec["marked"]:
+            continue
+        # Doerfler condition, recomputed from the dense difference
+        D = Ah - Ak
+        keep = np.ones(len(ob), dtype=bool)
+        keep[rec["marked"]] = False
+        rest = np.zeros(D.shape[0])
+        for b in np.nonzero((ob[:, 4] == 1) & keep)[0]:
+            rs = slice(3 * ob[b, 0], 3 * (ob[b, 0] + ob[b, 1]))
+            cs = slice(3 * ob[b, 2], 3 * (ob[b, 2] + ob[b, 3]))
+            rest[rs] += D[rs, cs] @ xp[cs]
+        assert np.linalg.norm(rest) <= (1 - theta) * gk * (1 + 1e-10)
+        # the threshold of step 3 b (iii), and every marked block reaches it
+        N = D.shape[0]
+        assert abs(rec["tau"] - (1 - theta) * gk / np.sqrt(hm.csp() * N * N)) <= 1e-12 * rec["tau"]
+        for b in rec["marked"]:
+            rs = slice(3 * ob[b, 0], 3 * (ob[b, 0] + ob[b, 1]))
+            cs = slice(3 * ob[b, 2], 3 * (ob[b, 2] + ob[b, 3]))
+            assert np.abs(D[rs, cs] @ xp[cs]).max() >= rec["tau"] * (1 - 1e-12)
+        # only marked blocks grow, by two steps (or to their last cross)
+        if k + 1 < len(hist):
+            nxt = hist[k + 1]["ranks"]
+            for b in np.nonzero(ob[:, 4] == 1)[0]:
+                if b in rec["marked"]:
+                    assert nxt[b] == min(rec["ranks"][b] + 2, far[b][0].shape[1])
+                else:
+                    assert nxt[b] == rec["ranks"][b]
+
+
+def test_zero_and_sparse_data(small):
+    V, T, mesh = small
+    y, hist, hm = amvm(mesh, np.zeros(3 * len(T)), leaf=16)
+    assert np.all(y == 0.0) and len(hist) == 1 and hist[0]["gamma"] == 0.0
+    # x nonzero on the triangles of one leaf cluster only
+    cl = [c for c in hm.clusters() if c["son0"] < 0][3]
+    tri = hm.order[cl["off"]:cl["off"] + cl["len"]]
+    x = np.zeros(3 * len(T))
+    x[(3 * tri[:, None] + np.arange(3)).ravel()] = 1.0
+    y, hist, hm = amvm(mesh, x, tol=1e-8, leaf=16, hm=hm)
+    ob = hm.blocks()
+    final = hist[-1]["ranks"]
+    for b in np.nonzero(ob[:, 4] == 1)[0]:
+        c0, c1 = ob[b, 2], ob[b, 2] + ob[b, 3]
+        if c1 <= cl["off"] or c0 >= cl["off"] + cl["len"]:
+            assert final[b] == 0, b
+
+
+def test_convergence_and_estimator_quality(small):
+    V, T, mesh = small
+    x = _point_force_x(V, T)
+    A = mesh.dense()
+    bt = A @ x
+    y, hist, hm = amvm(mesh, x, theta=0.5, tol=1e-8, leaf=16, kcap=96)
+    assert np.linalg.norm(y - bt) <= 1e-6 * np.linalg.norm(bt)
+    ob, far = _dense_blocks(hm)
+    ratios = []
+    for rec in hist:
+        Ak, perm = _assemble(hm, ob, far, rec["ranks"])
+        bk = np.zeros_like(x)
+        bk[perm] = Ak @ x[perm]
+        err = np.linalg.norm(bk - bt)
+        if err > 1e-13 * np.linalg.norm(bt):
+            ratios.append(rec["gamma"] / err)
+    ratios = np.array(ratios[2:])  # after the first rounds (saturation regime)
+    assert np.mean((ratios >= 0.5) & (ratios <= 2.0)) >= 0.8, ratios
