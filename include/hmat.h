@@ -292,6 +292,44 @@ hmat_status hmat_set_factors(hmat_t h, const int32_t* ranks, const double* U, co
  */
 hmat_status hmat_profile(hmat_t h, int32_t enable, double* phase_ms, int64_t* calls);
 
+/*
+ * hmat_amvm -- adaptive matrix-vector multiplication (Algorithm 2, Sec. 3):
+ * y ~= A x without building the H-matrix to a fixed accuracy first. The
+ * sequence A_k shares the tree and partition of hmat_build (eta, leaf); its
+ * dense blocks are exact, and every admissible block starts at rank 0. The
+ * look-ahead A^_k takes two more ACA steps on every admissible block; ACA is
+ * resumed from saved state, with no accuracy test of its own. Each round:
+ *   - d_b = (A^_k - A_k)_b x_s for every admissible block;
+ *   - gamma_k = ||b_k - b^_k||_2 = ||sum_b d_b||;
+ *   - rows are visited in decreasing |(b^_k - b_k)_i|, and a block containing
+ *     row i is marked when |(d_b)_i| >= (1 - theta)(c_sp M N)^(-1/2) gamma_k;
+ *   - marking stops once ||sum_{b unmarked} d_b|| <= (1 - theta) gamma_k;
+ *   - marked blocks take their look-ahead (A_{k+1} = A^_k there).
+ * Stops when gamma_k <= tol ||b^_k||_2 (tolerance read as relative) or after
+ * max_rounds rounds; y = b_k.
+ *   mesh, E, nu, eta, leaf   as for hmat_build (HOST mesh, copied).
+ *   x, y     DEVICE vectors of n_dof entries, DOF 3i+a in mesh order.
+ *   theta    Doerfler parameter in (0, 1); tol > 0.
+ *   kmax     cap on the ACA steps per block (2..4096); a block that reaches
+ *            it, or full rank, is exhausted and contributes no further.
+ *   ranks    HOST, n_blocks entries or NULL: final rank of each admissible
+ *            block in canonical block order (-1 for dense blocks).
+ * Synchronises the stream. Errors: as hmat_build; HMAT_EINVAL for theta,
+ * tol, kmax, max_rounds or NULL/aliased vectors.
+ */
+typedef struct {
+  int32_t rounds;          /* rounds of Algorithm 2 that marked blocks */
+  int32_t exhausted;       /* admissible blocks out of ACA steps (rank min(m,n), rows used, or kmax) */
+  int64_t aca_steps;       /* sum over admissible blocks of the ACA steps taken (incl. look-ahead) */
+  int64_t marked_total;    /* sum over rounds of |P_k| */
+  double gamma;            /* final estimator gamma_k */
+  double time_ms;
+} hmat_amvm_info;
+
+hmat_status hmat_amvm(const hmat_mesh* mesh, double E, double nu, double eta, int32_t leaf,
+                      const double* x, double* y, double theta, double tol, int32_t max_rounds,
+                      int32_t kmax, void* hip_stream, int32_t* ranks, hmat_amvm_info* info);
+
 /* ------------------------------------------------------------------------
  * Request server: continuous admission of independent requests (one mesh
  * each: build, then products or a solve) under a device-memory budget.

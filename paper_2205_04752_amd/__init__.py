@@ -13,7 +13,7 @@ import os
 
 import numpy as np
 
-__all__ = ["lib", "HMatrix", "Server", "plan", "HmatError", "LIB_PATH"]
+__all__ = ["lib", "HMatrix", "Server", "plan", "amvm", "HmatError", "LIB_PATH"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhmat.so")
 
@@ -51,6 +51,11 @@ class _SolveInfo(C.Structure):
                 ("time_ms", C.c_double), ("refinements", C.c_int32), ("reserved", C.c_int32)]
 
 
+class _AmvmInfo(C.Structure):
+    _fields_ = [("rounds", C.c_int32), ("exhausted", C.c_int32), ("aca_steps", C.c_int64),
+                ("marked_total", C.c_int64), ("gamma", C.c_double), ("time_ms", C.c_double)]
+
+
 class _Request(C.Structure):
     _fields_ = [("kind", C.c_int32), ("nvec", C.c_int32), ("precision", C.c_int32),
                 ("restart", C.c_int32), ("E", C.c_double), ("nu", C.c_double), ("eps", C.c_double),
@@ -67,7 +72,7 @@ class _Result(C.Structure):
 EXPORTS = ["hmat_build", "hmat_build_batch", "hmat_bodies", "hmat_matvec", "hmat_matvec_ex",
            "hmat_solve", "hmat_solve_ir", "hmat_set_precision", "hmat_info", "hmat_free",
            "hmat_last_error", "hmat_plan", "hmat_block", "hmat_entries", "hmat_set_factors",
-           "hmat_profile", "hmat_server_create", "hmat_server_submit", "hmat_server_wait",
+           "hmat_profile", "hmat_amvm", "hmat_server_create", "hmat_server_submit", "hmat_server_wait",
            "hmat_server_destroy", "hmat_server_last_error"]
 
 _lib = None
@@ -99,6 +104,8 @@ def lib():
     L.hmat_entries.argtypes = [vp, i64, vp, vp, vp, vp]
     L.hmat_set_factors.argtypes = [vp, vp, vp, vp, vp]
     L.hmat_profile.argtypes = [vp, i32, vp, C.POINTER(i64)]
+    L.hmat_amvm.argtypes = [C.POINTER(_Mesh), dbl, dbl, dbl, i32, vp, vp, dbl, dbl, i32, i32, vp,
+                            vp, C.POINTER(_AmvmInfo)]
     L.hmat_server_create.argtypes = [i32, i64, dbl, i32, C.POINTER(vp)]
     L.hmat_server_submit.argtypes = [vp, C.POINTER(_Mesh), C.POINTER(_Request), vp, C.POINTER(i64)]
     L.hmat_server_wait.argtypes = [vp, i64, vp, C.POINTER(_Result)]
@@ -152,6 +159,25 @@ def plan(vertices, triangles, eta: float = 2.0, leaf: int = 32):
     blocks = np.zeros((nb.value, 5), dtype=np.int32)
     _check(lib().hmat_plan(C.byref(m), float(eta), int(leaf), None, C.byref(nb), blocks.ctypes.data))
     return order, blocks
+
+
+def amvm(vertices, triangles, x, E=1.0, nu=0.3, eta=2.0, leaf=32, theta=0.5, tol=1e-6,
+         max_rounds=1000, kmax=128, stream=None):
+    """Adaptive matrix-vector multiplication (hmat_amvm): returns (y, info, ranks)
+    with y on the device, ranks per block in canonical order (-1: dense)."""
+    import torch
+    m, keep = _mesh(vertices, triangles)
+    N = 3 * m.n_triangles
+    x2, xp, _ = _dev_ptr(x, N, "x")
+    y = torch.empty_like(x2[0])
+    info = _AmvmInfo()
+    nb = C.c_int32(0)
+    lib().hmat_plan(C.byref(m), float(eta), int(leaf), None, C.byref(nb), None)
+    ranks = np.zeros(max(nb.value, 1), dtype=np.int32)
+    _check(lib().hmat_amvm(C.byref(m), float(E), float(nu), float(eta), int(leaf), xp, y.data_ptr(),
+                           float(theta), float(tol), int(max_rounds), int(kmax), _stream(stream),
+                           ranks.ctypes.data, C.byref(info)))
+    return y, {k: getattr(info, k) for k, _ in _AmvmInfo._fields_}, ranks[:nb.value]
 
 
 class HMatrix:

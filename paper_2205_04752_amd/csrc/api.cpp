@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <deque>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <numeric>
@@ -42,6 +43,8 @@ hipError_t launch_add_comb(const double*, int64_t, int64_t, int, const double*, 
 hipError_t launch_residual(const double*, int64_t, double*, hipStream_t);
 hipError_t launch_fill(double*, int64_t, double, hipStream_t);
 hipError_t launch_axpy(double, const double*, int64_t, double*, hipStream_t);
+hipError_t launch_dense_mv(const DenseMvTask*, int, const double*, const double*, double*, hipStream_t);
+hipError_t launch_lowrank_delta(const DeltaTask*, int, const double*, double*, hipStream_t);
 }  // namespace hm
 
 using namespace hm;
@@ -750,6 +753,85 @@ int64_t aca_budget() {
   return std::max<int64_t>((int64_t)1 << 30, (int64_t)(fr / 4));
 }
 
+// Plan (tree, partition; several bodies merged), geometry upload and the
+// dense blocks (K1) into a plain column-major staging arena: dense block i
+// at near_off[i], m x n. Shared by the build and the adaptive multiplication.
+void setup_dense(hmat* h, const std::vector<BodyIn>& in, double eta, int32_t leaf, hipStream_t s,
+                 std::chrono::steady_clock::time_point t0, DevBuf& near_stage,
+                 std::vector<int64_t>& near_off, EventPair& evn) {
+  h->eta = eta;
+  h->leaf = leaf;
+  std::vector<double> allV;
+  std::vector<int32_t> allT;
+  merge_bodies(h, in, eta, leaf, allV, allT);
+  const Plan& P = h->plan;
+  const int32_t nt = P.nt;
+  h->N = 3 * (int64_t)nt;
+  h->inv_order.assign(nt, 0);
+  for (int32_t p = 0; p < nt; p++) h->inv_order[P.order[p]] = p;
+  HostGeometry hg;
+  const hmat_mesh all{(int32_t)(allV.size() / 3), nt, allV.data(), allT.data()};
+  make_geometry(&all, P, hg);
+  upload(h->d_cen, hg.cen, s, "geometry");
+  upload(h->d_q, hg.q, s, "geometry");
+  upload(h->d_vtx, hg.vtx, s, "geometry");
+  upload(h->d_gl, hg.gl, s, "geometry");
+  upload(h->d_order, P.order, s, "geometry");
+  std::vector<double> kc(2 * (size_t)nt);
+  for (int32_t p = 0; p < nt; p++) {
+    const hmat::Body& B = h->bodies[h->pos_body[p]];
+    const double cK = (1.0 + B.nu) / (8.0 * M_PI * B.E * (1.0 - B.nu));
+    kc[p] = cK * (3.0 - 4.0 * B.nu);
+    kc[nt + p] = cK;
+  }
+  upload(h->d_kc, kc, s, "geometry");
+  h->G = DevGeo{h->d_cen.as<double>(), h->d_q.as<double>(), h->d_vtx.as<double>(),
+                h->d_gl.as<double>(), h->d_kc.as<double>(), nt, 0, 0.0, 0.0};
+  h->kind_index.assign(P.blk.size(), -1);
+  for (size_t b = 0; b < P.blk.size(); b++) {
+    if (P.blk[b].far) {
+      h->kind_index[b] = (int32_t)h->far_blocks.size();
+      h->far_blocks.push_back((int32_t)b);
+    } else {
+      h->kind_index[b] = (int32_t)h->near_blocks.size();
+      h->near_blocks.push_back((int32_t)b);
+    }
+  }
+  // K1 into a plain column-major staging arena (m x n per dense block)
+  std::vector<NearTask> ntasks;
+  std::vector<SelfTask> stasks(nt);
+  int64_t noff = 0;
+  for (int32_t b : h->near_blocks) {
+    const BlockRec& B = P.blk[b];
+    const Cluster& T = P.cl[B.t];
+    const Cluster& S = P.cl[B.s];
+    near_off.push_back(noff);
+    ntasks.push_back(NearTask{T.off, T.len, S.off, S.len, noff, 3 * T.len, 0});
+    if (B.t == B.s)
+      for (int32_t p = 0; p < T.len; p++) stasks[T.off + p] = SelfTask{noff, 3 * T.len, 0, p, 0};
+    noff += 9 * (int64_t)T.len * S.len;
+  }
+  {
+    std::vector<char> seen(nt, 0);
+    for (int32_t b : h->near_blocks)
+      if (P.blk[b].t == P.blk[b].s)
+        for (int32_t p = 0; p < P.cl[P.blk[b].t].len; p++) seen[P.cl[P.blk[b].t].off + p] = 1;
+    for (int32_t p = 0; p < nt; p++)
+      if (!seen[p]) throw HipError{HMAT_EDEVICE, "internal: triangle without diagonal dense block"};
+  }
+  for (const NearTask& t : ntasks)
+    if (t.d_off + (int64_t)(3 * t.s_len) * t.ld > noff) throw HipError{HMAT_EDEVICE, "internal: dense block out of range"};
+  h->st.t_plan_ms = ms_since(t0);
+  near_stage.alloc(sizeof(double) * std::max<int64_t>(noff, 1), "dense blocks");
+  DevBuf d_ntasks, d_stasks;
+  upload(d_ntasks, ntasks, s, "dense tasks");
+  upload(d_stasks, stasks, s, "self tasks");
+  check(hipEventRecord(evn.a, s), "event");
+  check(launch_near_only(h->G, d_ntasks.as<NearTask>(), (int)ntasks.size(), near_stage.as<double>(), s), "K1 launch");
+  check(launch_self(h->G, d_stasks.as<SelfTask>(), near_stage.as<double>(), s), "K1 self launch");
+  check(hipEventRecord(evn.b, s), "event");
+}
+
 hmat_status build_impl(const std::vector<BodyIn>& in, double eta, int32_t leaf, hipStream_t s,
                        hmat** out) {
   auto t0 = std::chrono::steady_clock::now();
@@ -764,78 +846,12 @@ hmat_status build_impl(const std::vector<BodyIn>& in, double eta, int32_t leaf, 
     if (const char* e = std::getenv("HMAT_MV_UNROLL")) h->mv_unroll = std::atoi(e);
     h->eta = eta;
     h->leaf = leaf;
-    std::vector<double> allV;
-    std::vector<int32_t> allT;
-    merge_bodies(h, in, eta, leaf, allV, allT);
+    DevBuf near_stage;
+    std::vector<int64_t> near_off;
+    EventPair evn;
+    setup_dense(h, in, eta, leaf, s, t0, near_stage, near_off, evn);
     const Plan& P = h->plan;
     const int32_t nt = P.nt;
-    h->N = 3 * (int64_t)nt;
-    h->inv_order.assign(nt, 0);
-    for (int32_t p = 0; p < nt; p++) h->inv_order[P.order[p]] = p;
-    HostGeometry hg;
-    const hmat_mesh all{(int32_t)(allV.size() / 3), nt, allV.data(), allT.data()};
-    make_geometry(&all, P, hg);
-    upload(h->d_cen, hg.cen, s, "geometry");
-    upload(h->d_q, hg.q, s, "geometry");
-    upload(h->d_vtx, hg.vtx, s, "geometry");
-    upload(h->d_gl, hg.gl, s, "geometry");
-    upload(h->d_order, P.order, s, "geometry");
-    std::vector<double> kc(2 * (size_t)nt);
-    for (int32_t p = 0; p < nt; p++) {
-      const hmat::Body& B = h->bodies[h->pos_body[p]];
-      const double cK = (1.0 + B.nu) / (8.0 * M_PI * B.E * (1.0 - B.nu));
-      kc[p] = cK * (3.0 - 4.0 * B.nu);
-      kc[nt + p] = cK;
-    }
-    upload(h->d_kc, kc, s, "geometry");
-    h->G = DevGeo{h->d_cen.as<double>(), h->d_q.as<double>(), h->d_vtx.as<double>(),
-                  h->d_gl.as<double>(), h->d_kc.as<double>(), nt, 0, 0.0, 0.0};
-    h->kind_index.assign(P.blk.size(), -1);
-    for (size_t b = 0; b < P.blk.size(); b++) {
-      if (P.blk[b].far) {
-        h->kind_index[b] = (int32_t)h->far_blocks.size();
-        h->far_blocks.push_back((int32_t)b);
-      } else {
-        h->kind_index[b] = (int32_t)h->near_blocks.size();
-        h->near_blocks.push_back((int32_t)b);
-      }
-    }
-    // K1 into a plain column-major staging arena (m x n per dense block)
-    std::vector<NearTask> ntasks;
-    std::vector<SelfTask> stasks(nt);
-    std::vector<int64_t> near_off;
-    int64_t noff = 0;
-    for (int32_t b : h->near_blocks) {
-      const BlockRec& B = P.blk[b];
-      const Cluster& T = P.cl[B.t];
-      const Cluster& S = P.cl[B.s];
-      near_off.push_back(noff);
-      ntasks.push_back(NearTask{T.off, T.len, S.off, S.len, noff, 3 * T.len, 0});
-      if (B.t == B.s)
-        for (int32_t p = 0; p < T.len; p++) stasks[T.off + p] = SelfTask{noff, 3 * T.len, 0, p, 0};
-      noff += 9 * (int64_t)T.len * S.len;
-    }
-    {
-      std::vector<char> seen(nt, 0);
-      for (int32_t b : h->near_blocks)
-        if (P.blk[b].t == P.blk[b].s)
-          for (int32_t p = 0; p < P.cl[P.blk[b].t].len; p++) seen[P.cl[P.blk[b].t].off + p] = 1;
-      for (int32_t p = 0; p < nt; p++)
-        if (!seen[p]) throw HipError{HMAT_EDEVICE, "internal: triangle without diagonal dense block"};
-    }
-    for (const NearTask& t : ntasks)
-      if (t.d_off + (int64_t)(3 * t.s_len) * t.ld > noff) throw HipError{HMAT_EDEVICE, "internal: dense block out of range"};
-    h->st.t_plan_ms = ms_since(t0);
-    DevBuf near_stage;
-    near_stage.alloc(sizeof(double) * std::max<int64_t>(noff, 1), "dense blocks");
-    DevBuf d_ntasks, d_stasks;
-    upload(d_ntasks, ntasks, s, "dense tasks");
-    upload(d_stasks, stasks, s, "self tasks");
-    EventPair evn;
-    check(hipEventRecord(evn.a, s), "event");
-    check(launch_near_only(h->G, d_ntasks.as<NearTask>(), (int)ntasks.size(), near_stage.as<double>(), s), "K1 launch");
-    check(launch_self(h->G, d_stasks.as<SelfTask>(), near_stage.as<double>(), s), "K1 self launch");
-    check(hipEventRecord(evn.b, s), "event");
     // K2: ACA in groups of far blocks (canonical order) whose first-pass
     // panels fit the budget; each group's factors are compacted into a plain
     // column-major staging buffer (U m x k, then V n x k) and its panels freed.
@@ -1230,6 +1246,273 @@ hmat_status check_solve_args(hmat_t h, const double* b, const double* x, double 
   return HMAT_OK;
 }
 
+// Adaptive matrix-vector multiplication (Algorithm 2, Sec. 3) on the device:
+// resumable ACA (k_aca with saved state, paused at a step count), the
+// rank-two look-ahead contributions d_b = (A^_k - A_k)_b x_s per admissible
+// block, and the marking on the host. A_0: dense blocks exact, admissible
+// blocks of rank 0; the look-ahead adds two ACA steps per block; rows are
+// visited in decreasing |(b^_k - b_k)_i| (ties: lower row first), blocks of a
+// row in canonical order; a block joins P_k when its entry in that row
+// reaches (1 - theta)(c_sp M N)^(-1/2) gamma_k; marking stops after the
+// first row at which ||sum_{b not in P_k} d_b|| <= (1 - theta) gamma_k. Stop
+// when gamma_k <= tol ||b^_k|| (relative tolerance) or after max_rounds.
+hmat_status amvm_impl(const hmat_mesh* mesh, double E, double nu, double eta, int32_t leaf,
+                      const double* x, double* y, double theta, double tol, int32_t max_rounds,
+                      int32_t kmax, hipStream_t s, int32_t* ranks_out, hmat_amvm_info* info) {
+  auto t0 = std::chrono::steady_clock::now();
+  StreamScope scope(s);
+  init_pool();
+  std::unique_ptr<hmat> hp(new (std::nothrow) hmat());
+  if (!hp) return fail(HMAT_ENOMEM, "host allocation failed");
+  hmat* h = hp.get();
+  h->last_stream = s;
+  constexpr int LOOK = 2;  // look-ahead ACA steps
+  try {
+    check(hipGetDevice(&h->device), "hipGetDevice");
+    DevBuf near_stage;
+    std::vector<int64_t> near_off;
+    EventPair evn;
+    setup_dense(h, {BodyIn{mesh, E, nu, 0.5}}, eta, leaf, s, t0, near_stage, near_off, evn);
+    const Plan& P = h->plan;
+    const int64_t N = h->N;
+    const size_t nf = h->far_blocks.size();
+    // x in cluster order
+    DevBuf xp;
+    xp.alloc(sizeof(double) * std::max<int64_t>(N, 1), "amvm vectors");
+    check(launch_gather(1, x, N, h->d_order.as<int32_t>(), N, xp.as<double>(), N, s), "gather");
+    // b_0: dense blocks
+    std::vector<double> b(N, 0.0);
+    {
+      std::vector<DenseMvTask> dt;
+      int64_t o = 0;
+      for (size_t q = 0; q < h->near_blocks.size(); q++) {
+        const int32_t bb = h->near_blocks[q];
+        const int32_t m = (int32_t)block_m(h, bb), n = (int32_t)block_n(h, bb);
+        dt.push_back(DenseMvTask{near_off[q], o, m, n, 3 * P.cl[P.blk[bb].s].off, 0});
+        o += m;
+      }
+      DevBuf d_t, d_out;
+      upload(d_t, dt, s, "amvm dense");
+      d_out.alloc(sizeof(double) * std::max<int64_t>(o, 1), "amvm dense");
+      check(launch_dense_mv(d_t.as<DenseMvTask>(), (int)dt.size(), near_stage.as<double>(), xp.as<double>(),
+                            d_out.as<double>(), s), "amvm dense");
+      std::vector<double> out(std::max<int64_t>(o, 1));
+      check(hipMemcpyAsync(out.data(), d_out.p, sizeof(double) * o, hipMemcpyDeviceToHost, s), "amvm dense");
+      check(hipStreamSynchronize(s), "amvm dense");
+      for (size_t q = 0; q < h->near_blocks.size(); q++) {
+        const int32_t bb = h->near_blocks[q];
+        const int64_t R0 = 3 * (int64_t)P.cl[P.blk[bb].t].off, m = block_m(h, bb);
+        for (int64_t r = 0; r < m; r++) b[R0 + r] += out[dt[q].out + r];
+      }
+    }
+    // resumable ACA state of every admissible block
+    std::vector<int32_t> kcap(nf), r_use(nf, 0), k_avail(nf, 0), done(nf, 0);
+    std::vector<int64_t> poff(nf), zoff(nf), doff(nf), R0(nf), M(nf), Nn(nf);
+    int64_t ptot = 0, ztot = 0, vtot = 0, dtot = 0;
+    for (size_t f = 0; f < nf; f++) {
+      const int32_t bb = h->far_blocks[f];
+      M[f] = block_m(h, bb);
+      Nn[f] = block_n(h, bb);
+      R0[f] = 3 * (int64_t)P.cl[P.blk[bb].t].off;
+      kcap[f] = (int32_t)std::min<int64_t>(std::min(M[f], Nn[f]), kmax);
+      poff[f] = ptot;
+      ptot += (M[f] + Nn[f]) * kcap[f];
+      zoff[f] = ztot;
+      ztot += (M[f] + 31) / 32;
+      vtot += 2 * (int64_t)kcap[f];
+      doff[f] = dtot;
+      dtot += M[f];
+    }
+    DevBuf panels, pivs, states, zbits, d_rank, d_stop, d_ratio, d_d;
+    panels.alloc(sizeof(double) * std::max<int64_t>(ptot, 1), "amvm panels");
+    pivs.alloc(sizeof(int32_t) * std::max<int64_t>(vtot, 1), "amvm panels");
+    states.alloc(sizeof(AcaState) * std::max<size_t>(nf, 1), "amvm state");
+    zbits.alloc(sizeof(uint32_t) * std::max<int64_t>(ztot, 1), "amvm state");
+    check(hipMemsetAsync(states.p, 0, states.bytes, s), "amvm state");
+    check(hipMemsetAsync(zbits.p, 0, zbits.bytes, s), "amvm state");
+    d_rank.alloc(sizeof(int32_t) * std::max<size_t>(nf, 1), "amvm state");
+    d_stop.alloc(sizeof(int32_t) * std::max<size_t>(nf, 1), "amvm state");
+    d_ratio.alloc(sizeof(double) * std::max<size_t>(nf, 1), "amvm state");
+    d_d.alloc(sizeof(double) * std::max<int64_t>(dtot, 1), "amvm deltas");
+    std::vector<AcaTask> base(nf);
+    {
+      int64_t vo = 0;
+      for (size_t f = 0; f < nf; f++) {
+        const BlockRec& B = P.blk[h->far_blocks[f]];
+        AcaTask& t = base[f];
+        t = AcaTask{};
+        t.t_off = P.cl[B.t].off;
+        t.t_len = P.cl[B.t].len;
+        t.s_off = P.cl[B.s].off;
+        t.s_len = P.cl[B.s].len;
+        t.panel = panels.as<double>() + poff[f];
+        t.piv = pivs.as<int32_t>() + vo;
+        vo += 2 * (int64_t)kcap[f];
+        t.kcap = kcap[f];
+        t.blk = (int32_t)f;
+        t.eps = 0.0;  // no accuracy test: steps are steered by the estimator
+        t.st = states.as<AcaState>() + f;
+        t.zbits = zbits.as<uint32_t>() + zoff[f];
+      }
+    }
+    size_t shmem = 0;
+    for (size_t f = 0; f < nf; f++)
+      shmem = std::max(shmem, (size_t)kcap[f] * 8 + (size_t)((M[f] + 31) / 32) * 4);
+    if (shmem > 160 * 1024) throw HipError{HMAT_ENOTSUP, "ACA panel row exceeds LDS capacity"};
+    // rows -> admissible blocks containing them (canonical order)
+    std::vector<int64_t> rptr(N + 1, 0);
+    for (size_t f = 0; f < nf; f++)
+      for (int64_t r = 0; r < M[f]; r++) rptr[R0[f] + r + 1]++;
+    for (int64_t i = 0; i < N; i++) rptr[i + 1] += rptr[i];
+    std::vector<int32_t> rblk(rptr[N]);
+    {
+      std::vector<int64_t> fill(rptr.begin(), rptr.end() - 1);
+      for (size_t f = 0; f < nf; f++)
+        for (int64_t r = 0; r < M[f]; r++) rblk[fill[R0[f] + r]++] = (int32_t)f;
+    }
+    std::vector<char> adv(nf, 1);  // blocks whose look-ahead must be computed
+    std::vector<double> d(std::max<int64_t>(dtot, 1)), e(N), rest(N);
+    std::vector<int64_t> rows(N);
+    std::vector<char> marked(nf, 0), has_d(nf, 0);
+    int rounds = 0;
+    int64_t marked_total = 0;
+    double gamma = 0.0;
+    for (;;) {
+      // (a) resume ACA up to r_use + LOOK on the blocks that need it
+      std::vector<AcaTask> tasks;
+      for (size_t f = 0; f < nf; f++) {
+        if (!adv[f] || done[f]) continue;
+        const int32_t target = std::min(r_use[f] + LOOK, kcap[f]);
+        if (k_avail[f] >= target) continue;
+        AcaTask t = base[f];
+        t.k_stop = target;
+        tasks.push_back(t);
+      }
+      if (!tasks.empty()) {
+        DevBuf d_tasks;
+        upload(d_tasks, tasks, s, "amvm ACA");
+        check(launch_aca(h->G, d_tasks.as<AcaTask>(), (int)tasks.size(), shmem, d_rank.as<int32_t>(),
+                         d_stop.as<int32_t>(), d_ratio.as<double>(), s), "amvm ACA");
+        std::vector<int32_t> rk(nf), sp(nf);
+        check(hipMemcpyAsync(rk.data(), d_rank.p, sizeof(int32_t) * nf, hipMemcpyDeviceToHost, s), "amvm ACA");
+        check(hipMemcpyAsync(sp.data(), d_stop.p, sizeof(int32_t) * nf, hipMemcpyDeviceToHost, s), "amvm ACA");
+        check(hipStreamSynchronize(s), "amvm ACA");
+        for (const AcaTask& t : tasks) {
+          const int32_t f = t.blk;
+          if (sp[f] == 5) throw HipError{HMAT_EINVAL, "non-finite matrix entries (overlapping or duplicate triangles?)"};
+          k_avail[f] = rk[f];
+          done[f] = sp[f] != 6;
+        }
+      }
+      std::fill(adv.begin(), adv.end(), 0);
+      // (b) look-ahead contributions d_b of every block with a window
+      std::vector<DeltaTask> dts;
+      std::fill(has_d.begin(), has_d.end(), 0);
+      for (size_t f = 0; f < nf; f++) {
+        const int32_t r1 = std::min(r_use[f] + LOOK, k_avail[f]);
+        if (r1 <= r_use[f]) continue;
+        has_d[f] = 1;
+        const double* pan = panels.as<double>() + poff[f];
+        dts.push_back(DeltaTask{pan, pan + M[f] * kcap[f], doff[f], (int32_t)M[f], (int32_t)Nn[f], r_use[f], r1,
+                                3 * P.cl[P.blk[h->far_blocks[f]].s].off, 0});
+      }
+      if (!dts.empty()) {
+        DevBuf d_t;
+        upload(d_t, dts, s, "amvm deltas");
+        check(launch_lowrank_delta(d_t.as<DeltaTask>(), (int)dts.size(), xp.as<double>(), d_d.as<double>(), s),
+              "amvm deltas");
+        check(hipMemcpyAsync(d.data(), d_d.p, sizeof(double) * dtot, hipMemcpyDeviceToHost, s), "amvm deltas");
+        check(hipStreamSynchronize(s), "amvm deltas");
+      }
+      // (c) the estimator
+      std::fill(e.begin(), e.end(), 0.0);
+      for (size_t f = 0; f < nf; f++)
+        if (has_d[f])
+          for (int64_t r = 0; r < M[f]; r++) e[R0[f] + r] += d[doff[f] + r];
+      double g2 = 0.0, bh2 = 0.0;
+      for (int64_t i = 0; i < N; i++) {
+        g2 += e[i] * e[i];
+        bh2 += (b[i] + e[i]) * (b[i] + e[i]);
+      }
+      gamma = std::sqrt(g2);
+      if (dts.empty() || gamma <= tol * std::sqrt(bh2) || rounds >= max_rounds) break;
+      // (d) marking along rows of decreasing error
+      const double tau = (1.0 - theta) * gamma / std::sqrt((double)P.csp * (double)N * (double)N);
+      std::iota(rows.begin(), rows.end(), (int64_t)0);
+      std::stable_sort(rows.begin(), rows.end(), [&](int64_t a, int64_t c) { return std::fabs(e[a]) > std::fabs(e[c]); });
+      rest = e;
+      double rn2 = g2;
+      std::fill(marked.begin(), marked.end(), 0);
+      std::vector<int32_t> Pk;
+      const double goal = (1.0 - theta) * gamma;
+      for (int64_t i : rows) {
+        bool added = false;
+        for (int64_t q = rptr[i]; q < rptr[i + 1]; q++) {
+          const int32_t f = rblk[q];
+          if (marked[f] || !has_d[f]) continue;
+          if (std::fabs(d[doff[f] + (i - R0[f])]) < tau) continue;
+          marked[f] = 1;
+          Pk.push_back(f);
+          for (int64_t r = 0; r < M[f]; r++) {
+            double& v = rest[R0[f] + r];
+            rn2 -= v * v;
+            v -= d[doff[f] + r];
+            rn2 += v * v;
+          }
+          added = true;
+        }
+        if (added && rn2 <= goal * goal * (1.0 + 1e-6)) {
+          double ex = 0.0;  // confirm with the exact norm
+          for (int64_t j = 0; j < N; j++) ex += rest[j] * rest[j];
+          rn2 = ex;
+          if (std::sqrt(ex) <= goal) break;
+        }
+      }
+      if (Pk.empty()) break;
+      // (e) A_{k+1} = A^_k on the marked blocks
+      for (int32_t f : Pk) {
+        for (int64_t r = 0; r < M[f]; r++) b[R0[f] + r] += d[doff[f] + r];
+        r_use[f] = std::min(r_use[f] + LOOK, k_avail[f]);
+        adv[f] = 1;
+      }
+      marked_total += (int64_t)Pk.size();
+      rounds++;
+    }
+    // result in the caller's order
+    std::vector<double> yh(N);
+    for (int32_t p = 0; p < P.nt; p++)
+      for (int a = 0; a < 3; a++) yh[3 * (int64_t)P.order[p] + a] = b[3 * (int64_t)p + a];
+    check(hipMemcpyAsync(y, yh.data(), sizeof(double) * N, hipMemcpyHostToDevice, s), "amvm result");
+    check(hipStreamSynchronize(s), "amvm result");
+    if (ranks_out) {
+      for (size_t q = 0; q < P.blk.size(); q++) ranks_out[q] = -1;
+      for (size_t f = 0; f < nf; f++) ranks_out[h->far_blocks[f]] = r_use[f];
+    }
+    if (info) {
+      int64_t steps = 0;
+      int32_t exhausted = 0;
+      for (size_t f = 0; f < nf; f++) {
+        steps += k_avail[f];
+        exhausted += done[f] ? 1 : 0;
+      }
+      info->rounds = rounds;
+      info->aca_steps = steps;
+      info->marked_total = marked_total;
+      info->exhausted = exhausted;
+      info->gamma = gamma;
+      info->time_ms = ms_since(t0);
+    }
+    check(hipStreamSynchronize(s), "amvm");
+    return HMAT_OK;
+  } catch (const HipError& e) {
+    (void)hipStreamSynchronize(s);
+    return fail(e.st, e.msg);
+  } catch (const std::bad_alloc&) {
+    (void)hipStreamSynchronize(s);
+    return fail(HMAT_ENOMEM, "host allocation failed");
+  }
+}
+
 }  // namespace
 
 void hm::set_thread_aca_budget(int64_t bytes) { g_aca_budget = bytes > 0 ? bytes : 0; }
@@ -1273,6 +1556,24 @@ hmat_status hmat_build_batch(int32_t n_bodies, const hmat_mesh* meshes, const do
   if (nt > INT32_MAX / 3 || nv > INT32_MAX) return fail(HMAT_EINVAL, "batch too large (triangles or vertices beyond 32-bit indexing)");
   g_err.clear();
   return build_impl(in, eta, leaf, (hipStream_t)hip_stream, out);
+}
+
+hmat_status hmat_amvm(const hmat_mesh* mesh, double E, double nu, double eta, int32_t leaf,
+                      const double* x, double* y, double theta, double tol, int32_t max_rounds,
+                      int32_t kmax, void* hip_stream, int32_t* ranks, hmat_amvm_info* info) {
+  std::string err;
+  hmat_status st = validate_params(E, nu, eta, leaf, 0.5, err);
+  if (st == HMAT_OK) st = validate_mesh(mesh, err);
+  if (st != HMAT_OK) return fail(st, err);
+  if (!x || !y) return fail(HMAT_EINVAL, "x or y is NULL");
+  if (!(theta > 0.0 && theta < 1.0)) return fail(HMAT_EINVAL, "theta must lie in (0, 1)");
+  if (!(tol > 0.0)) return fail(HMAT_EINVAL, "tol must be > 0");
+  if (max_rounds < 0) return fail(HMAT_EINVAL, "max_rounds must be >= 0");
+  if (kmax < 2 || kmax > 4096) return fail(HMAT_EINVAL, "kmax must lie in [2, 4096]");
+  if (x == y) return fail(HMAT_EINVAL, "x and y alias");
+  g_err.clear();
+  return amvm_impl(mesh, E, nu, eta, leaf, x, y, theta, tol, max_rounds, kmax,
+                   (hipStream_t)hip_stream, ranks, info);
 }
 
 hmat_status hmat_bodies(hmat_t h, int32_t* n_bodies, int64_t* dof_off) {

@@ -57,6 +57,13 @@ struct SelfTask {
 };
 
 // ACA task: scratch panels U (m x kcap) then V (n x kcap), plain column-major, at `panel`.
+// Resumable ACA state of one block (adaptive multiplication): steps taken,
+// next pivot row, rows used, ||S_k||_F^2, last stop code (6: paused).
+struct AcaState {
+  int32_t k, i, nZ, stop;
+  double S2, ratio;
+};
+
 struct AcaTask {
   int32_t t_off, t_len, s_off, s_len;
   double* panel;
@@ -64,6 +71,27 @@ struct AcaTask {
   int32_t kcap;
   int32_t blk;    // index into the far-block result arrays
   double eps;     // ACA accuracy of the block's body
+  AcaState* st;   // null: start from scratch; else resume from and save to *st
+  uint32_t* zbits;  // with st: the block's set Z of used rows, (m + 31) / 32 words
+  int32_t k_stop;   // > 0: pause (stop code 6) once k reaches k_stop
+  int32_t pad;
+};
+
+// Adaptive multiplication: out[out + r] = (D x)_r for a dense block (D plain
+// column-major m x n at d_off of the dense staging arena, x entries from
+// xp[col0 ...]).
+struct DenseMvTask {
+  int64_t d_off, out;
+  int32_t m, n, col0, pad;
+};
+
+// Adaptive multiplication: out[out + r] = sum_{l in [r0, r1)} U[r, l] (V[:, l] . x)
+// for one admissible block's ACA panels (U m x ldk, V n x ldk, column-major).
+struct DeltaTask {
+  const double* U;
+  const double* V;
+  int64_t out;
+  int32_t m, n, r0, r1, col0, pad;
 };
 
 // Compaction of the V factors: copy the first k columns of a scratch panel

@@ -358,10 +358,20 @@ __global__ __launch_bounds__(TPB) void k_aca(DevGeo g0, const AcaTask* __restric
   double* coef = sh;
   uint32_t* Z = reinterpret_cast<uint32_t*>(sh + kcap);
   const int zw = (m + 31) >> 5;
-  for (int w = tid; w < zw; w += TPB) Z[w] = 0u;
   const int nt = g.nt;
   int ph = 0, k = 0, nZ = 0, i = 0, stop = 0;
   double S2 = 0.0, ratio = 0.0;
+  if (T.st) {  // resume
+    const AcaState s0 = *T.st;
+    k = s0.k;
+    i = s0.i;
+    nZ = s0.nZ;
+    S2 = s0.S2;
+    ratio = s0.ratio;
+    for (int w = tid; w < zw; w += TPB) Z[w] = T.zbits[w];
+  } else {
+    for (int w = tid; w < zw; w += TPB) Z[w] = 0u;
+  }
   __syncthreads();
   for (;;) {
     for (int l = tid; l < k; l += TPB) coef[l] = U[i + (size_t)l * m];
@@ -470,11 +480,20 @@ __global__ __launch_bounds__(TPB) void k_aca(DevGeo g0, const AcaTask* __restric
       stop = 5;
       break;
     }
+    if (T.k_stop > 0 && k >= T.k_stop) {  // paused: the next step starts at row i
+      stop = 6;
+      break;
+    }
   }
   if (tid == 0) {
     rank_out[T.blk] = k;
     stop_out[T.blk] = stop;
     ratio_out[T.blk] = ratio;
+  }
+  if (T.st) {
+    __syncthreads();
+    for (int w = tid; w < zw; w += TPB) T.zbits[w] = Z[w];
+    if (tid == 0) *T.st = AcaState{k, i, nZ, stop, S2, ratio};
   }
 }
 
@@ -944,6 +963,62 @@ __global__ __launch_bounds__(WAVE) void k_mv2_mfma(int c_first, int n,
   if (u >= n) return;
   const int c = c_first + u;
   mv_b_mfma(chunks[c], c, segs, stream, z, ldz, xp, ldxp, nr, part);
+}
+
+// Adaptive multiplication (Algorithm 2): dense-block products and the
+// rank-two look-ahead contributions (A^_k - A_k)_b x_s, one workgroup per block.
+__global__ __launch_bounds__(256) void k_dense_mv(const DenseMvTask* __restrict__ tasks,
+                                                  const double* __restrict__ D,
+                                                  const double* __restrict__ xp,
+                                                  double* __restrict__ out) {
+  const DenseMvTask T = tasks[blockIdx.x];
+  const double* __restrict__ Db = D + T.d_off;
+  const double* __restrict__ xs = xp + T.col0;
+  for (int r = threadIdx.x; r < T.m; r += blockDim.x) {
+    double acc = 0.0;
+    for (int c = 0; c < T.n; c++) acc += Db[(size_t)c * T.m + r] * xs[c];
+    out[T.out + r] = acc;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_lowrank_delta(const DeltaTask* __restrict__ tasks,
+                                                       const double* __restrict__ xp,
+                                                       double* __restrict__ out) {
+  __shared__ double red[2][256 / WAVE];
+  const DeltaTask T = tasks[blockIdx.x];
+  const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
+  const int nl = T.r1 - T.r0;  // 1 or 2
+  double w[2] = {0.0, 0.0};
+  for (int l = 0; l < nl; l++) {
+    const double* __restrict__ v = T.V + (size_t)(T.r0 + l) * T.n;
+    double a = 0.0;
+    for (int c = tid; c < T.n; c += blockDim.x) a += v[c] * xp[T.col0 + c];
+    a = wave_sum(a);
+    if (lane == 0) red[l][wv] = a;
+  }
+  __syncthreads();
+  for (int l = 0; l < nl; l++) {
+    double t = 0.0;
+    for (int q = 0; q < 256 / WAVE; q++) t += red[l][q];
+    w[l] = t;
+  }
+  for (int r = tid; r < T.m; r += blockDim.x) {
+    double acc = 0.0;
+    for (int l = 0; l < nl; l++) acc += T.U[(size_t)(T.r0 + l) * T.m + r] * w[l];
+    out[T.out + r] = acc;
+  }
+}
+
+hipError_t launch_dense_mv(const DenseMvTask* tasks, int n, const double* D, const double* xp,
+                           double* out, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_dense_mv, dim3(n), dim3(256), 0, s, tasks, D, xp, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_lowrank_delta(const DeltaTask* tasks, int n, const double* xp, double* out,
+                                hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_lowrank_delta, dim3(n), dim3(256), 0, s, tasks, xp, out);
+  return hipGetLastError();
 }
 
 // FP32 copy of an FP64 array (reduced-precision storage of the arenas).

@@ -105,6 +105,27 @@ def test_batch_validation_before_device_work():
     assert L.hmat_bodies(None, None, None) == H.HMAT_EINVAL
 
 
+def test_amvm_validation_before_device_work():
+    L = H.lib()
+    V, T = W.icosphere(1)
+    m, keep = _mesh_struct(V, T)
+    buf = np.zeros(3 * len(T))
+    x = buf.ctypes.data
+    y = np.zeros(3 * len(T)).ctypes.data
+    ok = dict(E=1.0, nu=0.3, eta=2.0, leaf=32, theta=0.5, tol=1e-6, rounds=10, kmax=64)
+
+    def call(**kw):
+        a = dict(ok, **kw)
+        return L.hmat_amvm(C.byref(m), a["E"], a["nu"], a["eta"], a["leaf"], a.get("x", x),
+                           a.get("y", y), a["theta"], a["tol"], a["rounds"], a["kmax"], None, None,
+                           None)
+
+    for bad in (dict(theta=0.0), dict(theta=1.0), dict(tol=0.0), dict(kmax=1), dict(rounds=-1),
+                dict(nu=0.5), dict(E=-1.0), dict(eta=0.0), dict(x=None), dict(y=x)):
+        assert call(**bad) == H.HMAT_EINVAL, bad
+        assert L.hmat_last_error().decode()
+
+
 def test_other_entry_points_reject_null_handle():
     L = H.lib()
     assert L.hmat_matvec(None, 1, None, 3, None, 3, None) == H.HMAT_EINVAL
