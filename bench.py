@@ -80,9 +80,9 @@ def cpu_baseline(V, T, wl, x0, seconds_hint: float):
 
 def measured_traffic(kernel_tag: str):
     """HBM bytes per launch of `kernel_tag` from the committed rocprofv3 summary,
-    or None if the kernel source changed since the counters were taken."""
+    or None if the product kernels' source changed since the counters were taken."""
     import hashlib
-    src = os.path.join(ROOT, "paper_2205_04752_amd", "csrc", "kernels.hip")
+    src = os.path.join(ROOT, "paper_2205_04752_amd", "csrc", "product.hip")
     prof = os.path.join(ROOT, "profiles", "hmatvec_icosphere-L5.md")
     try:
         sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]

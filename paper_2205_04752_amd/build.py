@@ -25,6 +25,7 @@ NO_PK = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 SOURCES = [
     # (file, extra flags)
     ("kernels.hip", ["-x", "hip", f"--offload-arch={ARCH}", *NO_PK, "-munsafe-fp-atomics"]),
+    ("product.hip", ["-x", "hip", f"--offload-arch={ARCH}", *NO_PK]),
     # the planner's geometry and admissibility tests must not be contracted
     ("planner.cpp", ["-ffp-contract=off"]),
     ("api.cpp", []),

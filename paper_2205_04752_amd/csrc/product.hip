@@ -1,0 +1,648 @@
+// K3, the H-matrix-vector product y = sum_far U_b (V_b^T x_s) + sum_near D_b x_s
+// (Sec. 2): gather into cluster order, phase A (V^T x items and dense-block
+// chunks, k_mv1), phase B (U z chunks, k_mv2), the tile reduction (k_reduce);
+// vector-ALU kernels for one right-hand side, matrix-core kernels for 2..16.
+// Stored entries are FP64 or their FP32 copies; arithmetic is FP64. Also the
+// layout kernels of the product-order stream and the FP32 conversion.
+#include <hip/hip_runtime.h>
+
+#include "device_common.hpp"
+#include "hmat_internal.hpp"
+
+namespace hm {
+
+// ---------------------------------------------------------------------------
+// K3: H-matrix-vector product.
+
+// xp[r*ldxp + 3p+a] = x[r*ldx + 3 order[p] + a]
+__global__ void k_gather(int nr, const double* __restrict__ x, int64_t ldx,
+                         const int32_t* __restrict__ order, int64_t N, double* __restrict__ xp,
+                         int64_t ldxp) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= N * nr) return;
+  const int64_t r = e / N, d = e - r * N;
+  xp[r * ldxp + d] = x[r * ldx + 3 * (int64_t)order[d / 3] + d % 3];
+}
+
+constexpr int TILE = 2 * WAVE;  // rows per product tile: two rows per lane
+
+// Stored matrix entries are FP64 or FP32 (T); the product computes in FP64.
+// Pair<T> is the two-entry vector a lane loads (16 or 8 bytes); ld2 widens it.
+template <typename T>
+struct Pair;
+template <>
+struct Pair<double> {
+  using type = double2;
+};
+template <>
+struct Pair<float> {
+  using type = float2;
+};
+template <typename T>
+__device__ __forceinline__ typename Pair<T>::type ldp(const T* p) {
+  return *reinterpret_cast<const typename Pair<T>::type*>(p);
+}
+template <typename T>
+__device__ __forceinline__ double2 ld2(const T* p) {
+  const typename Pair<T>::type v = ldp(p);
+  return make_double2((double)v.x, (double)v.y);
+}
+
+// Phase A item: z = V_b^T x_s for a group of <= 8 columns; one wave. Lanes
+// cover the aligned row window of V two rows at a time (16-byte loads of V and
+// of the gathered x; pad rows of V are zero); NR right-hand sides at once,
+// columns in sub-batches of CB.
+template <int NR, typename T>
+__device__ __forceinline__ void mv_a_item(const MvA& I, const T* __restrict__ far,
+                                          const double* __restrict__ xp, int64_t ldxp, int nr,
+                                          double* __restrict__ z, int64_t ldz) {
+  constexpr int CB = (NR >= 16) ? 2 : ((NR >= 8) ? 4 : 8);
+  const int lane = threadIdx.x & (WAVE - 1);
+  const T* __restrict__ V = far + I.v_off;
+  const double* __restrict__ X = xp + I.a0;
+  for (int l0 = I.l0; l0 < I.l1; l0 += CB) {
+    const int nc = min(CB, I.l1 - l0);
+    double acc[CB][NR];
+#pragma unroll
+    for (int c = 0; c < CB; c++)
+#pragma unroll
+      for (int r = 0; r < NR; r++) acc[c][r] = 0.0;
+    for (int i = 2 * lane; i < I.ld; i += TILE) {
+      double2 xv[NR], v[CB];
+#pragma unroll
+      for (int c = 0; c < CB; c++)  // columns past l1 re-read the last one (not accumulated)
+        v[c] = ld2(V + (size_t)(l0 + min(c, nc - 1)) * I.ld + i);
+#pragma unroll
+      for (int r = 0; r < NR; r++)
+        xv[r] = (r < nr) ? *reinterpret_cast<const double2*>(X + r * ldxp + i) : make_double2(0.0, 0.0);
+#pragma unroll
+      for (int c = 0; c < CB; c++) {
+        if (c < nc) {
+#pragma unroll
+          for (int r = 0; r < NR; r++) acc[c][r] += v[c].x * xv[r].x + v[c].y * xv[r].y;
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < CB; c++)
+#pragma unroll
+      for (int r = 0; r < NR; r++) {
+        const double sum = wave_sum(acc[c][r]);
+        if (lane == 0 && c < nc && r < nr) z[r * ldz + I.zoff + (l0 - I.l0) + c] = sum;
+      }
+  }
+}
+
+// Phase B chunk: segments of one 128-row tile, each a column-major array of
+// its rows [row_lo, row_hi) (even bounds) times its columns, stored back to
+// back; lane L owns tile rows 2L and 2L+1 (acc0, acc1). A segment taller than
+// half a wave is read with lane L on its own rows (16-byte loads; lanes
+// outside the segment load a clamped in-segment address and discard it). A
+// shorter one (single right-hand side) puts p = 64 / (len/2) columns side by
+// side, so each load instruction covers p*len consecutive doubles; the p
+// column groups are then summed with a lane tree and moved to the owning
+// lanes. A segment's last partial batch re-reads in-segment data without
+// accumulating it, so every batch issues its UNR loads back to back. Writes
+// part[chunk][r][128].
+// One short segment (len <= 64 rows, single right-hand side) of a phase-B
+// chunk: g = len/2 lanes per column, p = 64/g >= 2 columns per load. Lane l
+// reads column c0 + t p + l/g, rows 2(l mod g) and +1, at stream offset
+// so + t p len + 2l -- consecutive lanes, consecutive addresses. Adds the
+// segment's row sums to the owning lanes' acc0/acc1 (fixed summation order).
+template <int UNR, typename T>
+__device__ __forceinline__ void mv_b_grouped(const MvSeg& S, const T* __restrict__ stream,
+                                             const double* __restrict__ src, double& acc0,
+                                             double& acc1) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int len = S.row_hi - S.row_lo, g = len >> 1, p = WAVE / g;
+  const int q = lane / g;
+  const bool lact = q < p;
+  const int ncol = S.c1 - S.c0;
+  const int nsteps = (ncol + p - 1) / p;
+  const int64_t step = (int64_t)p * len;
+  const T* __restrict__ A = stream + S.so;
+  const double* __restrict__ xs = src + S.soff + S.c0;
+  double s0 = 0.0, s1 = 0.0;
+  for (int t = 0; t < nsteps; t += UNR) {
+    typename Pair<T>::type a[UNR];
+    double xv[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; u++) {
+      const int col = (t + u) * p + q;
+      const bool ok = lact && col < ncol;
+      a[u] = ldp(A + (ok ? (int64_t)(t + u) * step + 2 * lane : 0));
+      xv[u] = xs[ok ? col : 0];
+      xv[u] = ok ? xv[u] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < UNR; u++) {
+      s0 += (double)a[u].x * xv[u];
+      s1 += (double)a[u].y * xv[u];
+    }
+  }
+  // sum the p column groups: group q takes group q + off at level off
+  for (int off = 1; off < p; off <<= 1) {
+    const double o0 = __shfl(s0, (lane + off * g) & (WAVE - 1), WAVE);
+    const double o1 = __shfl(s1, (lane + off * g) & (WAVE - 1), WAVE);
+    if (q % (2 * off) == 0 && q + off < p) {
+      s0 += o0;
+      s1 += o1;
+    }
+  }
+  // lanes [0, g) hold rows row_lo + 2l, +1: move them to lanes row_lo/2 + l
+  const int from = lane - (S.row_lo >> 1);
+  const double m0 = __shfl(s0, from & (WAVE - 1), WAVE);
+  const double m1 = __shfl(s1, from & (WAVE - 1), WAVE);
+  if (from >= 0 && from < g) {
+    acc0 += m0;
+    acc1 += m1;
+  }
+}
+
+template <int NR, int UNR, typename T>
+__device__ __forceinline__ void mv_b_chunk(const MvChunk& C, int chunk,
+                                           const MvSeg* __restrict__ segs,
+                                           const T* __restrict__ stream,
+                                           const double* __restrict__ z, int64_t ldz,
+                                           const double* __restrict__ xp, int64_t ldxp, int nr,
+                                           double* __restrict__ part) {
+  const int L2 = 2 * (threadIdx.x & (WAVE - 1));
+  double acc0[NR], acc1[NR];
+#pragma unroll
+  for (int r = 0; r < NR; r++) acc0[r] = acc1[r] = 0.0;
+  for (int s = C.seg_lo; s < C.seg_hi; s++) {
+    const MvSeg S = segs[s];
+    const int len = S.row_hi - S.row_lo;
+    if (NR == 1 && len <= WAVE) {
+      mv_b_grouped<UNR, T>(S, stream, S.far ? z : xp, acc0[0], acc1[0]);
+      continue;
+    }
+    const bool act = L2 >= S.row_lo && L2 < S.row_hi;
+    const int Lc = min(max(L2, (int)S.row_lo), (int)S.row_hi - 2);
+    const T* __restrict__ A = stream + S.so + (Lc - S.row_lo) - (int64_t)S.c0 * len;
+    const double* __restrict__ src = (S.far ? z : xp) + S.soff;
+    const int64_t ld = S.far ? ldz : ldxp;
+    for (int c = S.c0; c < S.c1; c += UNR) {
+      const int nc = min(UNR, S.c1 - c);
+      typename Pair<T>::type a[UNR];
+#pragma unroll
+      for (int u = 0; u < UNR; u++) {
+        const int cu = (u < nc) ? c + u : S.c1 - 1;
+        a[u] = ldp(A + (int64_t)cu * len);
+      }
+#pragma unroll
+      for (int u = 0; u < UNR; u++) {
+        a[u].x = act ? a[u].x : (T)0;
+        a[u].y = act ? a[u].y : (T)0;
+      }
+      if (nc == UNR) {
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+          if (r < nr) {
+            const double* sr = src + r * ld + c;
+#pragma unroll
+            for (int u = 0; u < UNR; u++) {
+              acc0[r] += (double)a[u].x * sr[u];
+              acc1[r] += (double)a[u].y * sr[u];
+            }
+          }
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+          if (r < nr) {
+            const double* sr = src + r * ld + c;
+#pragma unroll
+            for (int u = 0; u < UNR; u++) {
+              if (u < nc) {
+                acc0[r] += (double)a[u].x * sr[u];
+                acc1[r] += (double)a[u].y * sr[u];
+              }
+            }
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < NR; r++)
+    if (r < nr)
+      *reinterpret_cast<double2*>(part + ((size_t)chunk * NR + r) * TILE + L2) = make_double2(acc0[r], acc1[r]);
+}
+
+// Work units (phase-A items, chunks) go one per wave; MV_WPB independent waves
+// share a workgroup (no LDS, no barriers) so more waves fit on a CU.
+constexpr int MV_WPB = 1;
+
+// Product launch 1: the phase-A items (largest first) and the dense-block
+// chunks, which do not depend on z, in one grid so that neither leaves the
+// other's tail idle.
+template <int NR, int UNR, typename T>
+__global__ __launch_bounds__(WAVE* MV_WPB) void k_mv1(const MvA* __restrict__ items, int nA,
+                                                      int n_near_chunks,
+                                                      const MvChunk* __restrict__ chunks,
+                                                      const MvSeg* __restrict__ segs,
+                                                      const T* __restrict__ far,
+                                                      const T* __restrict__ stream,
+                                                      const double* __restrict__ xp, int64_t ldxp,
+                                                      int nr, double* __restrict__ z, int64_t ldz,
+                                                      double* __restrict__ part) {
+  // wave-uniform unit index: keeps descriptors and vector entries in scalar loads
+  const int u = __builtin_amdgcn_readfirstlane(blockIdx.x * MV_WPB + threadIdx.x / WAVE);
+  if (u < nA) {
+    mv_a_item<NR, T>(items[u], far, xp, ldxp, nr, z, ldz);
+  } else if (u < nA + n_near_chunks) {
+    const int c = u - nA;
+    mv_b_chunk<NR, UNR, T>(chunks[c], c, segs, stream, z, ldz, xp, ldxp, nr, part);
+  }
+}
+
+// Product launch 2: the low-rank chunks (U z), chunk ids c_first + unit.
+template <int NR, int UNR, typename T>
+__global__ __launch_bounds__(WAVE* MV_WPB) void k_mv2(int c_first, int n,
+                                                      const MvChunk* __restrict__ chunks,
+                                                      const MvSeg* __restrict__ segs,
+                                                      const T* __restrict__ stream,
+                                                      const double* __restrict__ z, int64_t ldz,
+                                                      const double* __restrict__ xp, int64_t ldxp,
+                                                      int nr, double* __restrict__ part) {
+  const int u = __builtin_amdgcn_readfirstlane(blockIdx.x * MV_WPB + threadIdx.x / WAVE);
+  if (u >= n) return;
+  const int c = c_first + u;
+  mv_b_chunk<NR, UNR, T>(chunks[c], c, segs, stream, z, ldz, xp, ldxp, nr, part);
+}
+
+// ---------------------------------------------------------------------------
+// Several right-hand sides (2..16): the two contractions V^T X and U Z (and
+// D X) on the FP64 matrix cores. v_mfma_f64_16x16x4f64 computes
+// D += A B with A 16x4, B 4x16; lane l holds A[l%16][l/16], B[l/16][l%16]
+// and D[4v + l/16][l%16] in item v (v = 0..3). The right-hand sides are the
+// 16 columns of B (lanes with l%16 >= nr carry zeros). To let every lane load
+// four consecutive matrix rows with two 16-byte loads, the four products of a
+// group take rows 4m + t (t = 0..3) in place of row m: a permutation of the
+// summation (phase A) or of the output rows (phase B), undone when storing.
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ v4d mfma4(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Phase A, several vectors: z[:, zoff + c] = V[:, l0 + c]^T X for c < l1 - l0
+// (<= 64 columns: four 16-column tiles). Per 16-row step lane l reads rows
+// 4(l/16) .. +3 of column l%16 of each tile and the same rows of vector l%16.
+template <typename T>
+__device__ __forceinline__ void mv_a_mfma(const MvA& I, const T* __restrict__ far,
+                                          const double* __restrict__ xp, int64_t ldxp, int nr,
+                                          double* __restrict__ z, int64_t ldz) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int kq = lane >> 4, cl = lane & 15;
+  const int ncols = I.l1 - I.l0;
+  const int ntile = (ncols + 15) >> 4;
+  const bool rv = cl < nr;
+  const double* __restrict__ X = xp + (int64_t)min(cl, nr - 1) * ldxp + I.a0;
+  const T* Vc[4];
+  bool cv[4];
+#pragma unroll
+  for (int q = 0; q < 4; q++) {
+    const int col = q * 16 + cl;
+    cv[q] = col < ncols;
+    Vc[q] = far + I.v_off + (int64_t)(I.l0 + min(col, ncols - 1)) * I.ld;
+  }
+  v4d acc[4];
+#pragma unroll
+  for (int q = 0; q < 4; q++) acc[q] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int i0 = 0; i0 < I.ld; i0 += 16) {
+    const int r0 = i0 + 4 * kq;
+    const bool p0 = r0 < I.ld, p1 = r0 + 2 < I.ld;  // ld and r0 even: pairs are whole
+    double2 x0 = *reinterpret_cast<const double2*>(X + (p0 ? r0 : 0));
+    double2 x1 = *reinterpret_cast<const double2*>(X + (p1 ? r0 + 2 : 0));
+    const bool b0 = rv && p0, b1 = rv && p1;
+    x0.x = b0 ? x0.x : 0.0;
+    x0.y = b0 ? x0.y : 0.0;
+    x1.x = b1 ? x1.x : 0.0;
+    x1.y = b1 ? x1.y : 0.0;
+    double2 a0[4], a1[4];
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      if (q < ntile) {
+        a0[q] = ld2(Vc[q] + (p0 ? r0 : 0));
+        a1[q] = ld2(Vc[q] + (p1 ? r0 + 2 : 0));
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      if (q < ntile) {
+        const bool ok = cv[q];
+        acc[q] = mfma4(ok ? a0[q].x : 0.0, x0.x, acc[q]);
+        acc[q] = mfma4(ok ? a0[q].y : 0.0, x0.y, acc[q]);
+        acc[q] = mfma4(ok ? a1[q].x : 0.0, x1.x, acc[q]);
+        acc[q] = mfma4(ok ? a1[q].y : 0.0, x1.y, acc[q]);
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; q++) {
+    if (q < ntile) {
+#pragma unroll
+      for (int v = 0; v < 4; v++) {
+        const int col = q * 16 + 4 * v + kq;
+        if (col < ncols && rv) z[(int64_t)cl * ldz + I.zoff + col] = acc[q][v];
+      }
+    }
+  }
+}
+
+// Phase B, several vectors: one chunk (segments of one 128-row tile). Per
+// group of four columns c..c+3, lane l reads rows 4(l%16) .. +3 of column
+// c + l/16 in each 64-row half the segment touches, and entry c + l/16 of
+// vector l%16. Product t of a half accumulates tile rows 64h + 4m + t.
+// Writes part[chunk][16][128].
+template <typename T>
+__device__ __forceinline__ void mv_b_mfma(const MvChunk& C, int chunk,
+                                          const MvSeg* __restrict__ segs,
+                                          const T* __restrict__ stream,
+                                          const double* __restrict__ z, int64_t ldz,
+                                          const double* __restrict__ xp, int64_t ldxp, int nr,
+                                          double* __restrict__ part) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int kq = lane >> 4, m16 = lane & 15;
+  const bool rv = m16 < nr;
+  v4d acc[2][4];
+#pragma unroll
+  for (int h = 0; h < 2; h++)
+#pragma unroll
+    for (int t = 0; t < 4; t++) acc[h][t] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int s = C.seg_lo; s < C.seg_hi; s++) {
+    const MvSeg S = segs[s];
+    const int len = S.row_hi - S.row_lo;
+    const double* __restrict__ Bp =
+        (S.far ? z + (int64_t)min(m16, nr - 1) * ldz : xp + (int64_t)min(m16, nr - 1) * ldxp) + S.soff;
+    const bool h0 = S.row_lo < 64, h1 = S.row_hi > 64;  // halves the segment touches
+    // this lane's rows in each half, relative to the segment (pairs are whole: bounds are even)
+    const int R0 = 4 * m16 - S.row_lo, R1 = 64 + 4 * m16 - S.row_lo;
+    const bool q00 = R0 >= 0 && R0 < len, q01 = R0 + 2 >= 0 && R0 + 2 < len;
+    const bool q10 = R1 >= 0 && R1 < len, q11 = R1 + 2 >= 0 && R1 + 2 < len;
+    // batches of 16 columns (four groups of four): all loads first
+    for (int c = S.c0; c < S.c1; c += 16) {
+      double bv[4];
+      double2 av[4][2][2];
+#pragma unroll
+      for (int g = 0; g < 4; g++) {
+        const int cc = c + 4 * g + kq;
+        const bool cok = cc < S.c1;
+        const int ccl = cok ? cc : S.c1 - 1;
+        const T* __restrict__ col = stream + S.so + (int64_t)(ccl - S.c0) * len;
+        bv[g] = Bp[ccl];
+        bv[g] = (cok && rv) ? bv[g] : 0.0;
+        if (h0) {
+          av[g][0][0] = ld2(col + (q00 ? R0 : 0));
+          av[g][0][1] = ld2(col + (q01 ? R0 + 2 : 0));
+        }
+        if (h1) {
+          av[g][1][0] = ld2(col + (q10 ? R1 : 0));
+          av[g][1][1] = ld2(col + (q11 ? R1 + 2 : 0));
+        }
+      }
+#pragma unroll
+      for (int g = 0; g < 4; g++) {
+        if (h0) {
+          acc[0][0] = mfma4(q00 ? av[g][0][0].x : 0.0, bv[g], acc[0][0]);
+          acc[0][1] = mfma4(q00 ? av[g][0][0].y : 0.0, bv[g], acc[0][1]);
+          acc[0][2] = mfma4(q01 ? av[g][0][1].x : 0.0, bv[g], acc[0][2]);
+          acc[0][3] = mfma4(q01 ? av[g][0][1].y : 0.0, bv[g], acc[0][3]);
+        }
+        if (h1) {
+          acc[1][0] = mfma4(q10 ? av[g][1][0].x : 0.0, bv[g], acc[1][0]);
+          acc[1][1] = mfma4(q10 ? av[g][1][0].y : 0.0, bv[g], acc[1][1]);
+          acc[1][2] = mfma4(q11 ? av[g][1][1].x : 0.0, bv[g], acc[1][2]);
+          acc[1][3] = mfma4(q11 ? av[g][1][1].y : 0.0, bv[g], acc[1][3]);
+        }
+      }
+    }
+  }
+  // lane holds vector m16, tile rows 64h + 16v + 4kq + t in acc[h][t][v]
+  if (rv) {
+    double* __restrict__ out = part + ((size_t)chunk * 16 + m16) * TILE;
+#pragma unroll
+    for (int h = 0; h < 2; h++)
+#pragma unroll
+      for (int v = 0; v < 4; v++) {
+        const int row = 64 * h + 16 * v + 4 * kq;
+        *reinterpret_cast<double2*>(out + row) = make_double2(acc[h][0][v], acc[h][1][v]);
+        *reinterpret_cast<double2*>(out + row + 2) = make_double2(acc[h][2][v], acc[h][3][v]);
+      }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(WAVE) void k_mv1_mfma(const MvA* __restrict__ items, int nA,
+                                                   int n_near_chunks,
+                                                   const MvChunk* __restrict__ chunks,
+                                                   const MvSeg* __restrict__ segs,
+                                                   const T* __restrict__ far,
+                                                   const T* __restrict__ stream,
+                                                   const double* __restrict__ xp, int64_t ldxp,
+                                                   int nr, double* __restrict__ z, int64_t ldz,
+                                                   double* __restrict__ part) {
+  const int u = __builtin_amdgcn_readfirstlane(blockIdx.x);
+  if (u < nA) {
+    mv_a_mfma(items[u], far, xp, ldxp, nr, z, ldz);
+  } else if (u < nA + n_near_chunks) {
+    const int c = u - nA;
+    mv_b_mfma(chunks[c], c, segs, stream, z, ldz, xp, ldxp, nr, part);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(WAVE) void k_mv2_mfma(int c_first, int n,
+                                                   const MvChunk* __restrict__ chunks,
+                                                   const MvSeg* __restrict__ segs,
+                                                   const T* __restrict__ stream,
+                                                   const double* __restrict__ z, int64_t ldz,
+                                                   const double* __restrict__ xp, int64_t ldxp,
+                                                   int nr, double* __restrict__ part) {
+  const int u = __builtin_amdgcn_readfirstlane(blockIdx.x);
+  if (u >= n) return;
+  const int c = c_first + u;
+  mv_b_mfma(chunks[c], c, segs, stream, z, ldz, xp, ldxp, nr, part);
+}
+
+// FP32 copy of an FP64 array (reduced-precision storage of the arenas).
+__global__ void k_to_f32(const double* __restrict__ src, float* __restrict__ dst, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = (float)src[i];
+}
+
+// Plain column-major block matrix -> stream segment (one workgroup per segment).
+__global__ __launch_bounds__(256) void k_to_stream(const StreamTask* __restrict__ tasks,
+                                                   double* __restrict__ stream) {
+  const StreamTask T = tasks[blockIdx.x];
+  const int len = T.row_hi - T.row_lo;
+  const int64_t total = (int64_t)len * (T.c1 - T.c0);
+  for (int64_t e = threadIdx.x; e < total; e += blockDim.x) {
+    const int64_t c = T.c0 + e / len;
+    const int i = T.r0 + T.row_lo + (int)(e % len);
+    stream[T.so + e] = (i >= 0 && i < T.ld) ? T.src[c * T.ld + i] : 0.0;
+  }
+}
+
+// Stream segment -> plain column-major block matrix (rows outside [0, m) skipped).
+__global__ __launch_bounds__(256) void k_from_stream(const StreamTask* __restrict__ tasks,
+                                                     const double* __restrict__ stream) {
+  const StreamTask T = tasks[blockIdx.x];
+  const int len = T.row_hi - T.row_lo;
+  const int64_t total = (int64_t)len * (T.c1 - T.c0);
+  for (int64_t e = threadIdx.x; e < total; e += blockDim.x) {
+    const int64_t c = T.c0 + e / len;
+    const int i = T.r0 + T.row_lo + (int)(e % len);
+    if (i >= 0 && i < T.ld) T.dst[c * T.ld + i] = stream[T.so + e];
+  }
+}
+
+// Sum the partials of each tile and scatter to the caller's order. The tile's
+// chunks (dense-block chunks, then low-rank chunks) are dealt round-robin to
+// RED_WAVES waves, which sum theirs in chunk order; wave 0 adds the waves'
+// sums in wave order (a fixed order: results do not vary between calls).
+constexpr int RED_WAVES = 4;
+template <int NR>
+__global__ __launch_bounds__(WAVE* RED_WAVES) void k_reduce(const int32_t* __restrict__ tile_near,
+                                                            const int32_t* __restrict__ tile_far,
+                                                            const double* __restrict__ part, int nr,
+                                                            const int32_t* __restrict__ order,
+                                                            int64_t N, double* __restrict__ y,
+                                                            int64_t ldy) {
+  __shared__ double2 red[RED_WAVES][WAVE];
+  const int tile = blockIdx.x, w = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
+  const int L2 = 2 * lane;
+  const int64_t row = (int64_t)tile * TILE + L2;
+  const int n0 = tile_near[tile], nn = tile_near[tile + 1] - n0;
+  const int f0 = tile_far[tile], n = nn + tile_far[tile + 1] - f0;
+  constexpr int DEPTH = 4;  // loads in flight per lane
+  for (int r = 0; r < nr; r++) {
+    double s0 = 0.0, s1 = 0.0;
+    for (int k = w; k < n; k += RED_WAVES * DEPTH) {
+      double2 p[DEPTH];
+#pragma unroll
+      for (int j = 0; j < DEPTH; j++) {
+        const int kk = k + j * RED_WAVES;
+        const int c = kk < nn ? n0 + kk : f0 + (kk - nn);
+        p[j] = kk < n ? *reinterpret_cast<const double2*>(part + ((size_t)c * NR + r) * TILE + L2)
+                      : make_double2(0.0, 0.0);
+      }
+#pragma unroll
+      for (int j = 0; j < DEPTH; j++) {
+        s0 += p[j].x;
+        s1 += p[j].y;
+      }
+    }
+    red[w][lane] = make_double2(s0, s1);
+    __syncthreads();
+    if (w == 0 && row < N) {
+      double t0 = 0.0, t1 = 0.0;
+#pragma unroll
+      for (int v = 0; v < RED_WAVES; v++) {
+        t0 += red[v][lane].x;
+        t1 += red[v][lane].y;
+      }
+      y[r * ldy + 3 * (int64_t)order[row / 3] + row % 3] = t0;
+      if (row + 1 < N) y[r * ldy + 3 * (int64_t)order[(row + 1) / 3] + (row + 1) % 3] = t1;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers.
+
+hipError_t launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_to_f32, dim3(4096), dim3(256), 0, s, src, dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather(int nr, const double* x, int64_t ldx, const int32_t* order, int64_t N,
+                         double* xp, int64_t ldxp, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather, dim3(blocks_for(N * nr, 256)), dim3(256), 0, s, nr, x, ldx, order,
+                     N, xp, ldxp);
+  return hipGetLastError();
+}
+
+template <int NR, int UNR, typename T>
+static void mv_group(const ProductPlanDev& P, const T* far, const T* stream, const double* xp,
+                     int64_t ldxp, int nr, double* z, int64_t ldz, double* part, double* y,
+                     int64_t ldy, hipStream_t s, hipEvent_t* ev) {
+  const int n1 = P.nA + P.n_near_chunks;
+  if (n1 > 0)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mv1<NR, UNR, T>), dim3((n1 + MV_WPB - 1) / MV_WPB),
+                       dim3(WAVE * MV_WPB), 0, s, P.items, P.nA, P.n_near_chunks, P.chunks, P.segs,
+                       far, stream, xp, ldxp, nr, z, ldz, part);
+  if (ev) (void)hipEventRecord(ev[0], s);
+  if (P.n_far_chunks > 0)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mv2<NR, UNR, T>), dim3((P.n_far_chunks + MV_WPB - 1) / MV_WPB),
+                       dim3(WAVE * MV_WPB), 0, s, P.n_near_chunks, P.n_far_chunks, P.chunks, P.segs,
+                       stream, z, ldz, xp, ldxp, nr, part);
+  if (ev) (void)hipEventRecord(ev[1], s);
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_reduce<NR>), dim3(P.ntiles), dim3(WAVE * RED_WAVES), 0, s, P.tile_near,
+                     P.tile_far, part, nr, P.order, P.N, y, ldy);
+  if (ev) (void)hipEventRecord(ev[2], s);
+}
+
+template <typename T>
+static void mv_group_mfma(const ProductPlanDev& P, const T* far, const T* stream, const double* xp,
+                          int64_t ldxp, int nr, double* z, int64_t ldz, double* part, double* y,
+                          int64_t ldy, hipStream_t s, hipEvent_t* ev) {
+  const int n1 = P.nA + P.n_near_chunks;
+  if (n1 > 0)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mv1_mfma<T>), dim3(n1), dim3(WAVE), 0, s, P.items, P.nA,
+                       P.n_near_chunks, P.chunks, P.segs, far, stream, xp, ldxp, nr, z, ldz, part);
+  if (ev) (void)hipEventRecord(ev[0], s);
+  if (P.n_far_chunks > 0)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mv2_mfma<T>), dim3(P.n_far_chunks), dim3(WAVE), 0, s,
+                       P.n_near_chunks, P.n_far_chunks, P.chunks, P.segs, stream, z, ldz, xp, ldxp,
+                       nr, part);
+  if (ev) (void)hipEventRecord(ev[1], s);
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_reduce<16>), dim3(P.ntiles), dim3(WAVE * RED_WAVES), 0, s,
+                     P.tile_near, P.tile_far, part, nr, P.order, P.N, y, ldy);
+  if (ev) (void)hipEventRecord(ev[2], s);
+}
+
+// One pass over the matrix for nr <= 16 right-hand sides (xp already gathered),
+// reading the FP64 arenas (prec 0) or their FP32 copies (prec 1).
+// One vector: the vector-ALU kernels; two to sixteen: matrix cores.
+hipError_t launch_matvec_group(const ProductPlanDev& P, int prec, int nr, const double* xp,
+                               int64_t ldxp, double* z, int64_t ldz, double* part, double* y,
+                               int64_t ldy, hipStream_t s, hipEvent_t* ev, int unroll) {
+  if (prec == 1) {
+    if (nr <= 1) {
+      if (unroll >= 16)
+        mv_group<1, 16, float>(P, P.far32, P.stream32, xp, ldxp, nr, z, ldz, part, y, ldy, s, ev);
+      else
+        mv_group<1, 8, float>(P, P.far32, P.stream32, xp, ldxp, nr, z, ldz, part, y, ldy, s, ev);
+    } else {
+      mv_group_mfma<float>(P, P.far32, P.stream32, xp, ldxp, nr, z, ldz, part, y, ldy, s, ev);
+    }
+  } else {
+    if (nr <= 1) {
+      if (unroll >= 16)
+        mv_group<1, 16, double>(P, P.far, P.stream, xp, ldxp, nr, z, ldz, part, y, ldy, s, ev);
+      else
+        mv_group<1, 8, double>(P, P.far, P.stream, xp, ldxp, nr, z, ldz, part, y, ldy, s, ev);
+    } else {
+      mv_group_mfma<double>(P, P.far, P.stream, xp, ldxp, nr, z, ldz, part, y, ldy, s, ev);
+    }
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_to_stream(const StreamTask* tasks, int ntasks, double* stream, hipStream_t s) {
+  if (ntasks > 0) hipLaunchKernelGGL(k_to_stream, dim3(ntasks), dim3(256), 0, s, tasks, stream);
+  return hipGetLastError();
+}
+
+hipError_t launch_from_stream(const StreamTask* tasks, int ntasks, const double* stream, hipStream_t s) {
+  if (ntasks > 0) hipLaunchKernelGGL(k_from_stream, dim3(ntasks), dim3(256), 0, s, tasks, stream);
+  return hipGetLastError();
+}
+
+}  // namespace hm
