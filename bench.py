@@ -540,7 +540,7 @@ def main():
                    ("k_mv2 (U z)", 8 * far_u, float(single_phase[2]))]
         name, kern_bytes, kern_ms = max(kernels, key=lambda t: t[2])
         ach = kern_bytes / (kern_ms * 1e-3) / 1e9
-        tag = "k_mv1<1,16>" if name.startswith("k_mv1") else "k_mv2<1,16>"
+        tag = "k_mv1<1,16,double>" if name.startswith("k_mv1") else "k_mv2<1,16,double>"
         traffic = measured_traffic(tag) if args.workload == "icosphere-L5" else None
         out["roofline"] = {"kernel": name, "bound": "hbm", "achieved": round(ach, 2),
                            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
