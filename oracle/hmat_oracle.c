@@ -357,7 +357,15 @@ void or_brute_matvec_rows(const or_ctx* c, int nrows, const int* tri_rows, int n
  *   - v~ vanishes if max|v~| == 0 (k = 0) or max|v~| <= 1e-14 ||S_k||_F;
  *   - ||S_k||_F^2 = ||S_{k-1}||_F^2 + 2 sum_{l<k} (u_l.u_k)(v_l.v_k) + |u_k|^2 |v_k|^2;
  *   - stop when |u_k| |v_k| <= eps ||S_k||_F (cross kept), when k = min(m,n),
- *     or when Z holds every row.
+ *     or when Z holds every row;
+ *   - rows fall into ncls classes (row i in class i mod ncls: the three
+ *     displacement components of a tensor block; 1 for a plain matrix). The
+ *     accuracy test only stops ACA once every class has had a row in Z.
+ *     Otherwise the next row is the lowest unused row of the lowest class
+ *     not yet visited; if that row's remainder vanishes, the test counts as
+ *     passed. (On coplanar clusters the Kelvin tensor decouples into
+ *     in-plane and normal parts, and pivoting that never visits one class
+ *     would miss its part of the block.)
  * U is m x k and V is n x k, both column-major, returned through *pU / *pV
  * (malloc'd, grown as needed). Pivots are recorded in prow/pcol (capacity
  * min(m,n)). stop: 1 = threshold, 2 = rank = min(m,n), 3 = Z full. */
@@ -375,10 +383,22 @@ static int fuzzy_argmax(const double* v, int n, const unsigned char* skip) {
   return -1;
 }
 
+/* Lowest unused row of the lowest row class not in `visited`; -1 if none. */
+static int class_probe(const unsigned char* Z, int m, int ncls, int visited) {
+  for (int c = 0; c < ncls; c++) {
+    if (visited & (1 << c)) continue;
+    for (int r = c; r < m; r += ncls)
+      if (!Z[r]) return r;
+  }
+  return -1;
+}
+
 static int aca_core(int m, int n, or_rowfn rowf, or_colfn colf, void* user, double eps,
-                    int kcap, double** pU, double** pV, int* prow, int* pcol, int* stop,
-                    double* ratio) {
+                    int kcap, int ncls, double** pU, double** pV, int* prow, int* pcol,
+                    int* stop, double* ratio) {
   int kmax = m < n ? m : n;
+  const int allcls = (1 << ncls) - 1;
+  int visited = 0, pending = 0;
   int cap = 8 < kmax ? 8 : kmax;
   double* U = (double*)malloc(sizeof(double) * (size_t)m * cap);
   double* V = (double*)malloc(sizeof(double) * (size_t)n * cap);
@@ -396,13 +416,18 @@ static int aca_core(int m, int n, or_rowfn rowf, or_colfn colf, void* user, doub
       for (int c = 0; c < n; c++) vt[c] -= uil * V[(size_t)l * n + c];
     }
     if (!Z[i]) { Z[i] = 1; nZ++; }
+    visited |= 1 << (i % ncls);
     double mx = 0.0;
     for (int c = 0; c < n; c++)
       if (fabs(vt[c]) > mx) mx = fabs(vt[c]);
     int vanished = (k == 0) ? (mx == 0.0) : (mx <= 1e-14 * sqrt(S2));
     if (vanished) {
       if (nZ == m) { *stop = 3; break; }
-      if (k == 0) {
+      if (pending && visited == allcls) { *stop = 1; break; }
+      if (pending) {
+        i = class_probe(Z, m, ncls, visited);
+        if (i < 0) { *stop = 1; break; }
+      } else if (k == 0) {
         i = 0;
         while (Z[i]) i++;
       } else {
@@ -441,11 +466,20 @@ static int aca_core(int m, int n, or_rowfn rowf, or_colfn colf, void* user, doub
     S2 = S2 + 2.0 * cross + uu * vv;
     double lhs = sqrt(uu) * sqrt(vv), rhs = eps * sqrt(S2);
     *ratio = rhs > 0.0 ? lhs / rhs : INFINITY;
-    if (lhs <= rhs) { *stop = 1; break; }
+    pending = 0;
+    if (lhs <= rhs) {
+      if (visited == allcls) { *stop = 1; break; }
+      pending = 1;
+    }
     if (k == kmax) { *stop = 2; break; }
     if (nZ == m) { *stop = 3; break; }
     if (kcap > 0 && k == kcap) { *stop = 4; break; }
-    i = fuzzy_argmax(u, m, Z);
+    if (pending) {
+      i = class_probe(Z, m, ncls, visited);
+      if (i < 0) { *stop = 1; break; }
+    } else {
+      i = fuzzy_argmax(u, m, Z);
+    }
   }
   free(Z); free(vt); free(ut);
   *pU = U;
@@ -468,7 +502,7 @@ int or_aca_dense(int m, int n, const double* A, double eps, double* U, double* V
                  int* pcol, int* stop, double* ratio) {
   dense_src s = {m, n, A};
   double *Ui, *Vi;
-  int k = aca_core(m, n, dense_row, dense_col, &s, eps, 0, &Ui, &Vi, prow, pcol, stop, ratio);
+  int k = aca_core(m, n, dense_row, dense_col, &s, eps, 0, 1, &Ui, &Vi, prow, pcol, stop, ratio);
   memcpy(U, Ui, sizeof(double) * (size_t)m * k);
   memcpy(V, Vi, sizeof(double) * (size_t)n * k);
   free(Ui); free(Vi);
@@ -795,7 +829,7 @@ static int h_fill(or_hmat* h, double eps, int kcap) {
     blk_src src = {h, B->t, B->s};
     h->prow[b] = (int*)malloc(sizeof(int) * kmax);
     h->pcol[b] = (int*)malloc(sizeof(int) * kmax);
-    h->rank[b] = aca_core(m, n, blk_row, blk_col, &src, eps, kcap, &h->U[b], &h->Vf[b], h->prow[b],
+    h->rank[b] = aca_core(m, n, blk_row, blk_col, &src, eps, kcap, 3, &h->U[b], &h->Vf[b], h->prow[b],
                           h->pcol[b], &h->stop[b], &h->ratio[b]);
   }
   free(idx);

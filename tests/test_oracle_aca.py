@@ -122,3 +122,23 @@ def test_dense_aca_matches_blockwise(c0):
         U, Vf, pr, pc = h.factors(b)
         assert np.array_equal(r["rows"], pr) and np.array_equal(r["cols"], pc)
         assert np.allclose(r["U"], U, rtol=0, atol=1e-13 * np.abs(U).max())
+
+
+@pytest.mark.parametrize("eps", [1e-4, 1e-6])
+def test_flat_geometry_all_components(eps):
+    """On a flat plate every cluster is coplanar and the Kelvin tensor splits
+    into an in-plane part (components x, y) and a normal part (z) with no
+    coupling: S_xz = S_yz = 0. A block's rows of one class can then never
+    become pivots through |u_k|, so the accuracy test may only stop ACA once
+    every component has had a row (reading of the row rule for tensor
+    blocks). Pinned against the dense product: without the class rule the
+    error here is of order one."""
+    V, T = W.plate(24)
+    mesh = O.Mesh(V, T, 1.0, 0.3)
+    A = mesh.dense()
+    x = np.random.default_rng(3).standard_normal(A.shape[0])
+    h = O.HMatrix(mesh, 2.0, 32, eps=eps)
+    y = h.matvec(x[None, :])[0]
+    assert np.linalg.norm(y - A @ x) <= 10 * eps * np.linalg.norm(A @ x)
+    ob = h.blocks()
+    assert int(ob[:, 4].sum()) > 50  # many admissible (coplanar) blocks

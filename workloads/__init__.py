@@ -234,6 +234,23 @@ def cube_surface(n: int):
     return V - 1.0, T
 
 
+def plate(n: int, size: float = 1.0):
+    """Flat square [0,size]^2 in the plane z = 0, n x n grid, 2 n^2 triangles
+    (every cluster coplanar: the Kelvin tensor decouples into in-plane and
+    normal parts)."""
+    g = np.linspace(0.0, size, n + 1)
+    X, Y = np.meshgrid(g, g, indexing="ij")
+    V = np.stack([X.ravel(), Y.ravel(), np.zeros(X.size)], axis=1)
+    tris = []
+    for i in range(n):
+        for j in range(n):
+            a = i * (n + 1) + j
+            b = (i + 1) * (n + 1) + j
+            tris.append((a, b, b + 1))
+            tris.append((a, b + 1, a + 1))
+    return V.astype(np.float64), np.array(tris, dtype=np.int32)
+
+
 def random_x(n_dof: int, nrhs: int = 1, seed: int = 0) -> np.ndarray:
     """x ~ N(0,1), shape (nrhs, n_dof), from NumPy PCG64 ``default_rng(seed)``."""
     return np.random.default_rng(seed).standard_normal((nrhs, n_dof))
