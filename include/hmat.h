@@ -117,7 +117,9 @@ typedef struct {
  *           X_t the axis-aligned box of the vertices of t's triangles (eq. adm).
  *   leaf    clusters of at most `leaf` triangles are not split (>= 1).
  *   eps     ACA accuracy 0 < eps < 1: ACA stops at ||u_k|| ||v_k|| <= eps ||S_k||_F
- *           (Algorithm 1 stop test, constant read as 1).
+ *           (Algorithm 1 stop test, constant read as 1) once rows of all three
+ *           displacement components have been used (coplanar clusters
+ *           decouple them).
  *   hip_stream  stream for all device work; synchronised before return.
  *   out     receives the handle (NULL on failure).
  * Quadrature: off-diagonal entries use the degree-5 seven-point rule

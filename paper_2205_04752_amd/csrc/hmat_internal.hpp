@@ -58,9 +58,11 @@ struct SelfTask {
 
 // ACA task: scratch panels U (m x kcap) then V (n x kcap), plain column-major, at `panel`.
 // Resumable ACA state of one block (adaptive multiplication): steps taken,
-// next pivot row, rows used, ||S_k||_F^2, last stop code (6: paused).
+// next pivot row, rows used, last stop code (6: paused), row classes visited
+// (bit c: a row of component c was used), accuracy test passed while a class
+// was unvisited, ||S_k||_F^2, last stop ratio.
 struct AcaState {
-  int32_t k, i, nZ, stop;
+  int32_t k, i, nZ, stop, visited, pending;
   double S2, ratio;
 };
 

@@ -264,6 +264,24 @@ __device__ int argmax_free(const double* __restrict__ u, int m, const uint32_t* 
   return blk_min(cand, R, ph);
 }
 
+// Lowest unused row (not in Z) of the lowest of the three row classes
+// (r mod 3: displacement component) not in `visited`; -1 if none.
+template <int TPB>
+__device__ int class_probe(const uint32_t* Z, int m, int visited, RedT<TPB / WAVE>& R, int& ph) {
+  for (int c = 0; c < 3; c++) {
+    if (visited & (1 << c)) continue;
+    int cand = INT_MAX;
+    for (int r = c + 3 * (int)threadIdx.x; r < m; r += 3 * TPB)
+      if (!in_z(Z, r)) {
+        cand = r;
+        break;
+      }
+    const int best = blk_min(cand, R, ph);
+    if (best < m) return best;
+  }
+  return -1;
+}
+
 // e_b -= sum_{l<k} coef[l] * P[l*ld + b] for b = 0..2 (one triangle's three
 // rows or columns of a panel); four columns per step with separate sums, so
 // twelve loads are in flight.
@@ -322,6 +340,9 @@ __device__ __forceinline__ double lane_dot(const double* x, const double* y, int
 //   columns j_k: fuzzy argmax of |v~_k|; v_k = v~_k / v~_k(j_k);
 //   v~ vanishes if max|v~| = 0 (k = 0) or <= 1e-14 ||S_k||_F;
 //   ||S_k||^2 = ||S_{k-1}||^2 + 2 sum_{l<k} (u_l.u_k)(v_l.v_k) + |u_k|^2 |v_k|^2 in FP64;
+//   the accuracy test stops ACA only once rows of all three components
+//   (row mod 3) are in Z; before that, the next row is the lowest unused row
+//   of the first unvisited component, and a vanishing remainder there passes;
 //   stop: |u_k||v_k| <= eps ||S_k|| (1), k = min(m,n) (2), Z full (3),
 //   panel capacity reached (4: the host re-runs the block with a larger capacity),
 //   no finite pivot (5: non-finite entries; reported as an error).
@@ -346,13 +367,15 @@ __global__ __launch_bounds__(TPB) void k_aca(DevGeo g0, const AcaTask* __restric
   uint32_t* Z = reinterpret_cast<uint32_t*>(sh + kcap);
   const int zw = (m + 31) >> 5;
   const int nt = g.nt;
-  int ph = 0, k = 0, nZ = 0, i = 0, stop = 0;
+  int ph = 0, k = 0, nZ = 0, i = 0, stop = 0, visited = 0, pending = 0;
   double S2 = 0.0, ratio = 0.0;
   if (T.st) {  // resume
     const AcaState s0 = *T.st;
     k = s0.k;
     i = s0.i;
     nZ = s0.nZ;
+    visited = s0.visited;
+    pending = s0.pending;
     S2 = s0.S2;
     ratio = s0.ratio;
     for (int w = tid; w < zw; w += TPB) Z[w] = T.zbits[w];
@@ -364,6 +387,7 @@ __global__ __launch_bounds__(TPB) void k_aca(DevGeo g0, const AcaTask* __restric
     for (int l = tid; l < k; l += TPB) coef[l] = U[i + (size_t)l * m];
     if (tid == 0) Z[i >> 5] |= (1u << (i & 31));
     nZ++;
+    visited |= 1 << (i % 3);
     __syncthreads();
     // row i of the remainder into V[:, k]
     double* __restrict__ vk = V + (size_t)k * n;
@@ -386,7 +410,17 @@ __global__ __launch_bounds__(TPB) void k_aca(DevGeo g0, const AcaTask* __restric
         stop = 3;
         break;
       }
-      if (k == 0) {
+      if (pending && visited == 7) {  // the probe row of the last class is captured
+        stop = 1;
+        break;
+      }
+      if (pending) {
+        i = class_probe<TPB>(Z, m, visited, R, ph);
+        if (i < 0) {
+          stop = 1;
+          break;
+        }
+      } else if (k == 0) {
         int cand = INT_MAX;
         for (int r = tid; r < m; r += TPB)
           if (!in_z(Z, r)) {
@@ -458,14 +492,25 @@ __global__ __launch_bounds__(TPB) void k_aca(DevGeo g0, const AcaTask* __restric
     S2 = S2 + 2.0 * cross + uu * vv;
     const double lhs = sqrt(uu) * sqrt(vv), rhs = eps * sqrt(S2);
     ratio = rhs > 0.0 ? lhs / rhs : INFINITY;
-    if (lhs <= rhs) { stop = 1; break; }
+    // the accuracy test stops ACA only once every row class (component) has
+    // had a row in Z; otherwise the next row probes the first unvisited class
+    pending = 0;
+    if (lhs <= rhs) {
+      if (visited == 7) { stop = 1; break; }
+      pending = 1;
+    }
     if (k == kmax) { stop = 2; break; }
     if (nZ == m) { stop = 3; break; }
     if (k == kcap) { stop = 4; break; }
-    i = argmax_free<TPB>(uk, m, Z, R, ph);
-    if (i >= m) {
-      stop = 5;
-      break;
+    if (pending) {
+      i = class_probe<TPB>(Z, m, visited, R, ph);
+      if (i < 0) { stop = 1; break; }
+    } else {
+      i = argmax_free<TPB>(uk, m, Z, R, ph);
+      if (i >= m) {
+        stop = 5;
+        break;
+      }
     }
     if (T.k_stop > 0 && k >= T.k_stop) {  // paused: the next step starts at row i
       stop = 6;
@@ -480,7 +525,7 @@ __global__ __launch_bounds__(TPB) void k_aca(DevGeo g0, const AcaTask* __restric
   if (T.st) {
     __syncthreads();
     for (int w = tid; w < zw; w += TPB) T.zbits[w] = Z[w];
-    if (tid == 0) *T.st = AcaState{k, i, nZ, stop, S2, ratio};
+    if (tid == 0) *T.st = AcaState{k, i, nZ, stop, visited, pending, S2, ratio};
   }
 }
 
