@@ -290,9 +290,10 @@ def bench_amvm(args):
     with the paper's smooth data x_i = S(c_i - p) e_3, p = (5, 5, 5).
     Compared with building the H-matrix to eps and multiplying once, at
     matched accuracy; the reference product comes from an eps = 1e-10 build.
-    (The paper's cube is not used: on coplanar faces the 3x3 Kelvin block
-    decouples into in-plane and normal parts, and ACA with partial pivoting
-    on the tensor block misses one of them -- in the oracle as on the GPU.)"""
+    (The paper's own cube is not used: on its coplanar faces the look-ahead
+    ACA steps, which have no accuracy test and hence no component probe,
+    sample only the in-plane part of a block, so the estimator cannot see the
+    normal part it misses.)"""
     import numpy as np
     import torch
     import workloads as W
