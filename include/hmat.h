@@ -295,6 +295,27 @@ hmat_status hmat_set_factors(hmat_t h, const int32_t* ranks, const double* U, co
 hmat_status hmat_profile(hmat_t h, int32_t enable, double* phase_ms, int64_t* calls);
 
 /*
+ * hmat_tune -- autotuner of the product schedule for nrhs vectors per pass.
+ * Times `reps` products (after one warm-up) for each candidate: chunk sizes
+ * 8, 16, 32, 64 KB and 8 or 16 columns per batch for one vector; chunk sizes
+ * 64, 128, 256, 512 KB for several (the matrix-core path). Keeps the fastest
+ * for later products of h. The values of a product change with the schedule
+ * only by rounding (the partial sums are grouped differently); each schedule
+ * is deterministic. x, y are internal (all-ones input). Synchronises the stream.
+ */
+typedef struct {
+  int32_t nrhs, n_candidates;
+  int32_t chunk_kb[8];  /* candidates tried */
+  int32_t unroll[8];
+  double ms[8];         /* their mean product time */
+  int32_t best;         /* index of the chosen candidate */
+  int32_t reserved;
+  double best_ms;
+} hmat_tune_info;
+
+hmat_status hmat_tune(hmat_t h, int32_t nrhs, int32_t reps, void* hip_stream, hmat_tune_info* info);
+
+/*
  * hmat_amvm -- adaptive matrix-vector multiplication (Algorithm 2, Sec. 3):
  * y ~= A x without building the H-matrix to a fixed accuracy first. The
  * sequence A_k shares the tree and partition of hmat_build (eta, leaf); its

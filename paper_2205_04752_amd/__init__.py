@@ -51,6 +51,12 @@ class _SolveInfo(C.Structure):
                 ("time_ms", C.c_double), ("refinements", C.c_int32), ("reserved", C.c_int32)]
 
 
+class _TuneInfo(C.Structure):
+    _fields_ = [("nrhs", C.c_int32), ("n_candidates", C.c_int32), ("chunk_kb", C.c_int32 * 8),
+                ("unroll", C.c_int32 * 8), ("ms", C.c_double * 8), ("best", C.c_int32),
+                ("reserved", C.c_int32), ("best_ms", C.c_double)]
+
+
 class _AmvmInfo(C.Structure):
     _fields_ = [("rounds", C.c_int32), ("exhausted", C.c_int32), ("aca_steps", C.c_int64),
                 ("marked_total", C.c_int64), ("gamma", C.c_double), ("time_ms", C.c_double)]
@@ -72,7 +78,7 @@ class _Result(C.Structure):
 EXPORTS = ["hmat_build", "hmat_build_batch", "hmat_bodies", "hmat_matvec", "hmat_matvec_ex",
            "hmat_solve", "hmat_solve_ir", "hmat_set_precision", "hmat_info", "hmat_free",
            "hmat_last_error", "hmat_plan", "hmat_block", "hmat_entries", "hmat_set_factors",
-           "hmat_profile", "hmat_amvm", "hmat_server_create", "hmat_server_submit", "hmat_server_wait",
+           "hmat_profile", "hmat_tune", "hmat_amvm", "hmat_server_create", "hmat_server_submit", "hmat_server_wait",
            "hmat_server_destroy", "hmat_server_last_error"]
 
 _lib = None
@@ -104,6 +110,7 @@ def lib():
     L.hmat_entries.argtypes = [vp, i64, vp, vp, vp, vp]
     L.hmat_set_factors.argtypes = [vp, vp, vp, vp, vp]
     L.hmat_profile.argtypes = [vp, i32, vp, C.POINTER(i64)]
+    L.hmat_tune.argtypes = [vp, i32, i32, vp, C.POINTER(_TuneInfo)]
     L.hmat_amvm.argtypes = [C.POINTER(_Mesh), dbl, dbl, dbl, i32, vp, vp, dbl, dbl, i32, i32, vp,
                             vp, C.POINTER(_AmvmInfo)]
     L.hmat_server_create.argtypes = [i32, i64, dbl, i32, C.POINTER(vp)]
@@ -254,6 +261,14 @@ class HMatrix:
             _check(lib().hmat_matvec_ex(self._h, int(precision), x2.shape[0], xp, ldx, yp, ldy,
                                         _stream(stream)))
         return y2[0] if squeeze else y2
+
+    def tune(self, nrhs: int = 1, reps: int = 5, stream=None) -> dict:
+        """Autotune the product schedule for nrhs vectors (hmat_tune)."""
+        t = _TuneInfo()
+        _check(lib().hmat_tune(self._h, int(nrhs), int(reps), _stream(stream), C.byref(t)))
+        n = t.n_candidates
+        return dict(nrhs=t.nrhs, candidates=[(t.chunk_kb[c], t.unroll[c], t.ms[c]) for c in range(n)],
+                    best=t.best, best_ms=t.best_ms, chunk_kb=t.chunk_kb[t.best], unroll=t.unroll[t.best])
 
     def set_precision(self, precision: int, stream=None) -> None:
         """1: make FP32 copies of the stored entries; 0: free them."""

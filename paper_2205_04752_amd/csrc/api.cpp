@@ -221,6 +221,7 @@ struct hmat {
   struct ChunkList {
     DevBuf d_items, d_chunk, d_tile_near, d_tile_far;
     int nA = 0, n = 0, n_near = 0;
+    int64_t target = 0;  // chunk size in bytes the list was cut for
   } cl[2];
   int nSeg = 0, nTiles = 0;
   int64_t Ztot = 0, ldxp = 0, stream_n = 0;
@@ -294,6 +295,53 @@ struct BuildTrace {
     last = std::chrono::steady_clock::now();
   }
 };
+
+// Phase-B chunk list l: runs of consecutive segments of one tile and kind
+// (dense first, then low-rank) holding about `target` bytes, checked and
+// uploaded; the partial-sum workspace grows to fit ([chunk][NR][128], NR = 1
+// for list 0, up to 16 for list 1).
+void set_chunk_list(hmat* h, int l, int64_t target, hipStream_t s) {
+  std::vector<MvChunk> chunks;
+  std::vector<int32_t> tile_near(h->nTiles + 1, 0), tile_far(h->nTiles + 1, 0);
+  int n_near = 0;
+  const size_t ns = h->segs.size();
+  size_t i = 0;
+  for (int32_t group = 0; group < 2; group++) {
+    std::vector<int32_t>& tc = group == 0 ? tile_near : tile_far;
+    for (int32_t T = 0; T < h->nTiles; T++) {
+      tc[T] = (int32_t)chunks.size();
+      while (i < ns && h->segs[i].far == group && h->seg_tile[i] == T) {
+        MvChunk c{T, (int32_t)i, (int32_t)i, 0};
+        int64_t bytes = 0;
+        while (i < ns && h->segs[i].far == group && h->seg_tile[i] == T &&
+               (bytes < target || c.seg_hi == c.seg_lo)) {
+          bytes += 8 * (int64_t)(h->segs[i].row_hi - h->segs[i].row_lo) * (h->segs[i].c1 - h->segs[i].c0);
+          i++;
+          c.seg_hi = (int32_t)i;
+        }
+        chunks.push_back(c);
+      }
+    }
+    tc[h->nTiles] = (int32_t)chunks.size();
+    if (group == 0) n_near = (int32_t)chunks.size();
+  }
+  auto bad = [](const char* what) { throw HipError{HMAT_EDEVICE, std::string("internal: product plan: ") + what}; };
+  if (i != ns) bad("segments left over");
+  for (const MvChunk& c : chunks)
+    if (c.tile < 0 || c.tile >= h->nTiles || c.seg_lo >= c.seg_hi || c.seg_hi > (int32_t)ns) bad("chunks");
+  for (int32_t T = 0; T < h->nTiles; T++)
+    if (tile_near[T + 1] <= tile_near[T] || tile_far[T + 1] < tile_far[T]) bad("tile chunk ranges");
+  hmat::ChunkList& CL = h->cl[l];
+  upload(CL.d_chunk, chunks, s, "product plan");
+  upload(CL.d_tile_near, tile_near, s, "product plan");
+  upload(CL.d_tile_far, tile_far, s, "product plan");
+  CL.n = (int)chunks.size();
+  CL.n_near = n_near;
+  CL.target = target;
+  const size_t need = sizeof(double) * MV_TILE *
+                      std::max<int64_t>(std::max(1, h->cl[0].n), (int64_t)MV_MAX_NR * std::max(1, h->cl[1].n));
+  if (h->d_part.bytes < need) h->d_part.alloc(need, "product workspace");
+}
 
 void build_product_plan(hmat* h, hipStream_t s) {
   const Plan& P = h->plan;
@@ -424,40 +472,7 @@ void build_product_plan(hmat* h, hipStream_t s) {
                                                (int32_t)(hi_c - gcol[b]), sg.so + (lo_c - sg.c0) * len});
     }
   }
-  // Chunks: runs of consecutive segments of one tile and kind (dense first,
-  // then low-rank) holding about `target` bytes.
-  auto cut = [&](int64_t target, std::vector<MvChunk>& chunks, std::vector<int32_t>& tile_near,
-                 std::vector<int32_t>& tile_far, int& n_near) {
-    tile_near.assign(h->nTiles + 1, 0);
-    tile_far.assign(h->nTiles + 1, 0);
-    size_t i = 0;
-    for (int32_t group = 0; group < 2; group++) {
-      std::vector<int32_t>& tc = group == 0 ? tile_near : tile_far;
-      for (int32_t T = 0; T < h->nTiles; T++) {
-        tc[T] = (int32_t)chunks.size();
-        while (i < segs.size() && segs[i].seg.far == group && segs[i].tile == T) {
-          MvChunk c{T, (int32_t)i, (int32_t)i, 0};
-          int64_t bytes = 0;
-          while (i < segs.size() && segs[i].seg.far == group && segs[i].tile == T &&
-                 (bytes < target || c.seg_hi == c.seg_lo)) {
-            bytes += 8 * (int64_t)(h->segs[i].row_hi - h->segs[i].row_lo) * (h->segs[i].c1 - h->segs[i].c0);
-            i++;
-            c.seg_hi = (int32_t)i;
-          }
-          chunks.push_back(c);
-        }
-      }
-      tc[h->nTiles] = (int32_t)chunks.size();
-      if (group == 0) n_near = (int32_t)chunks.size();
-    }
-    if (i != segs.size()) throw HipError{HMAT_EDEVICE, "internal: product plan: segments left over"};
-  };
   tr.mark("  plan: offsets, pieces", s);
-  std::vector<MvChunk> chunk_l[2];
-  std::vector<int32_t> tn_l[2], tf_l[2];
-  int n_near_l[2] = {0, 0};
-  cut(h->mv_chunk_bytes, chunk_l[0], tn_l[0], tf_l[0], n_near_l[0]);
-  cut(h->mv_chunk_bytes_multi, chunk_l[1], tn_l[1], tf_l[1], n_near_l[1]);
 
   h->stream_n = std::max<int64_t>(so, PANEL_ALIGN);
   h->ldxp = round_up(h->N, PANEL_ALIGN);
@@ -479,12 +494,6 @@ void build_product_plan(hmat* h, hipStream_t s) {
       if (sg.so + (int64_t)(sg.row_hi - sg.row_lo) * (sg.c1 - sg.c0) > h->stream_n) bad("phase B matrix range");
       if ((int64_t)sg.soff + sg.c1 > (sg.far ? h->Ztot : h->N)) bad("phase B vector range");
     }
-    for (int l = 0; l < 2; l++) {
-      for (const MvChunk& c : chunk_l[l])
-        if (c.tile < 0 || c.tile >= h->nTiles || c.seg_lo >= c.seg_hi || c.seg_hi > (int32_t)h->segs.size()) bad("chunks");
-      for (int32_t T = 0; T < h->nTiles; T++)
-        if (tn_l[l][T + 1] <= tn_l[l][T] || tf_l[l][T + 1] < tf_l[l][T]) bad("tile chunk ranges");
-    }
   }
   h->nSeg = (int)h->segs.size();
   tr.mark("  plan: chunks, checks", s);
@@ -492,11 +501,7 @@ void build_product_plan(hmat* h, hipStream_t s) {
   for (int l = 0; l < 2; l++) {
     upload(h->cl[l].d_items, items_l[l], s, "product plan");
     h->cl[l].nA = (int)items_l[l].size();
-    upload(h->cl[l].d_chunk, chunk_l[l], s, "product plan");
-    upload(h->cl[l].d_tile_near, tn_l[l], s, "product plan");
-    upload(h->cl[l].d_tile_far, tf_l[l], s, "product plan");
-    h->cl[l].n = (int)chunk_l[l].size();
-    h->cl[l].n_near = n_near_l[l];
+    set_chunk_list(h, l, l == 0 ? h->mv_chunk_bytes : h->mv_chunk_bytes_multi, s);
   }
 
   if (h->d_xp.bytes < sizeof(double) * MV_MAX_NR * h->ldxp) {
@@ -505,10 +510,6 @@ void build_product_plan(hmat* h, hipStream_t s) {
     check(hipMemsetAsync(h->d_xp.p, 0, h->d_xp.bytes, s), "product workspace");
   }
   h->d_z.alloc(sizeof(double) * MV_MAX_NR * h->Ztot, "product workspace");
-  // partial sums: [chunk][NR][128] with NR = 1 (list 0) or the multi-vector bucket (<= 16, list 1)
-  h->d_part.alloc(sizeof(double) * MV_TILE *
-                      std::max<int64_t>(std::max(1, h->cl[0].n), (int64_t)MV_MAX_NR * std::max(1, h->cl[1].n)),
-                  "product workspace");
   check(hipStreamSynchronize(s), "product plan");
 }
 
@@ -877,7 +878,7 @@ hmat_status build_impl(const std::vector<BodyIn>& in, double eta, int32_t leaf, 
     };
     std::vector<int32_t> capv(nf, 0);
     std::vector<const double*> panel_ptr(nf, nullptr), u_ptr(nf, nullptr), v_ptr(nf, nullptr);
-    std::deque<DevBuf> fstage;
+    std::deque<DevBuf> ustage, vstage;
     const int64_t budget = aca_budget();
     h->aca_passes = 0;
     DevBuf panels1;  // first-pass panels, reused by every group
@@ -922,27 +923,34 @@ hmat_status build_impl(const std::vector<BodyIn>& in, double eta, int32_t leaf, 
         h->aca_passes = 2;
         fetch();
       }
-      int64_t tot = 0;
+      // U and V staged in separate buffers: the V staging is freed as soon as
+      // the V arena is filled, before the stream arena is allocated
+      int64_t totu = 0, totv = 0;
       for (int32_t f : grp) {
         const int32_t b = h->far_blocks[f];
         if (h->rank[f] > capv[f]) throw HipError{HMAT_EDEVICE, "internal: ACA rank beyond capacity"};
-        tot += (block_m(h, b) + block_n(h, b)) * h->rank[f];
+        totu += block_m(h, b) * h->rank[f];
+        totv += block_n(h, b) * h->rank[f];
       }
-      fstage.emplace_back();
-      DevBuf& fs = fstage.back();
-      fs.alloc(sizeof(double) * std::max<int64_t>(tot, 1), "low-rank factors");
+      ustage.emplace_back();
+      vstage.emplace_back();
+      DevBuf& us = ustage.back();
+      DevBuf& vs = vstage.back();
+      us.alloc(sizeof(double) * std::max<int64_t>(totu, 1), "low-rank factors");
+      vs.alloc(sizeof(double) * std::max<int64_t>(totv, 1), "low-rank factors");
       std::vector<CopyTask> ct;
-      int64_t o = 0;
+      int64_t ou = 0, ov = 0;
       for (int32_t f : grp) {
         const int32_t b = h->far_blocks[f];
         const int32_t m = (int32_t)block_m(h, b), n = (int32_t)block_n(h, b), k = h->rank[f];
-        u_ptr[f] = fs.as<double>() + o;
-        v_ptr[f] = fs.as<double>() + o + (int64_t)m * k;
+        u_ptr[f] = us.as<double>() + ou;
+        v_ptr[f] = vs.as<double>() + ov;
         if (k > 0) {
-          ct.push_back(CopyTask{panel_ptr[f], fs.as<double>() + o, m, k, m, 0});
-          ct.push_back(CopyTask{panel_ptr[f] + (int64_t)m * capv[f], fs.as<double>() + o + (int64_t)m * k, n, k, n, 0});
+          ct.push_back(CopyTask{panel_ptr[f], us.as<double>() + ou, m, k, m, 0});
+          ct.push_back(CopyTask{panel_ptr[f] + (int64_t)m * capv[f], vs.as<double>() + ov, n, k, n, 0});
         }
-        o += (int64_t)(m + n) * k;
+        ou += (int64_t)m * k;
+        ov += (int64_t)n * k;
       }
       DevBuf d_ct;
       upload(d_ct, ct, s, "compaction tasks");
@@ -983,6 +991,7 @@ hmat_status build_impl(const std::vector<BodyIn>& in, double eta, int32_t leaf, 
     DevBuf d_ct;
     upload(d_ct, ct, s, "compaction tasks");
     check(launch_compact(d_ct.as<CopyTask>(), (int)ct.size(), s), "compaction launch");
+    vstage.clear();  // stream-ordered: released after the compaction
     tr.mark("V arena", s);
     // product plan, then U factors and dense blocks into the stream arena
     build_product_plan(h, s);
@@ -992,7 +1001,7 @@ hmat_status build_impl(const std::vector<BodyIn>& in, double eta, int32_t leaf, 
     check(hipEventRecord(eva.b, s), "event");
     check(hipStreamSynchronize(s), "build");
     h->st.t_layout_ms = ms_since(t_layout);
-    fstage.clear();
+    ustage.clear();
     h->st.t_near_ms = evn.ms();
     h->st.t_aca_ms = eva.ms();
     fill_stats(h);
@@ -1574,6 +1583,70 @@ hmat_status hmat_amvm(const hmat_mesh* mesh, double E, double nu, double eta, in
   g_err.clear();
   return amvm_impl(mesh, E, nu, eta, leaf, x, y, theta, tol, max_rounds, kmax,
                    (hipStream_t)hip_stream, ranks, info);
+}
+
+hmat_status hmat_tune(hmat_t h, int32_t nrhs, int32_t reps, void* hip_stream, hmat_tune_info* info) {
+  if (!h) return fail(HMAT_EINVAL, "handle is NULL");
+  if (nrhs < 1 || nrhs > MV_MAX_NR) return fail(HMAT_EINVAL, "nrhs must lie in [1, 16]");
+  if (reps < 1 || reps > 1000) return fail(HMAT_EINVAL, "reps must lie in [1, 1000]");
+  hipStream_t s = (hipStream_t)hip_stream;
+  StreamScope scope(s);
+  h->last_stream = s;
+  // candidates: (chunk KB, columns per batch of the single-vector kernels)
+  std::vector<std::pair<int, int>> cand;
+  if (nrhs == 1) {
+    for (int kb : {8, 16, 32, 64})
+      for (int u : {8, 16}) cand.push_back({kb, u});
+  } else {
+    for (int kb : {64, 128, 256, 512}) cand.push_back({kb, h->mv_unroll});
+  }
+  const int l = nrhs > 1 ? 1 : 0;
+  try {
+    DevBuf dx, dy;
+    dx.alloc(sizeof(double) * h->N * nrhs, "tune vectors");
+    dy.alloc(sizeof(double) * h->N * nrhs, "tune vectors");
+    check(launch_fill(dx.as<double>(), h->N * nrhs, 1.0, s), "tune vectors");
+    EventPair ev;
+    std::vector<double> ms(cand.size(), 0.0);
+    size_t best = 0;
+    for (size_t c = 0; c < cand.size(); c++) {
+      set_chunk_list(h, l, (int64_t)cand[c].first * 1024, s);
+      h->mv_unroll = cand[c].second;
+      matvec_impl(h, 0, nrhs, dx.as<double>(), h->N, dy.as<double>(), h->N, s);  // warm-up
+      check(hipEventRecord(ev.a, s), "tune");
+      for (int r = 0; r < reps; r++)
+        matvec_impl(h, 0, nrhs, dx.as<double>(), h->N, dy.as<double>(), h->N, s);
+      check(hipEventRecord(ev.b, s), "tune");
+      check(hipEventSynchronize(ev.b), "tune");
+      ms[c] = ev.ms() / reps;
+      if (ms[c] < ms[best]) best = c;
+    }
+    if (l == 0) {
+      h->mv_chunk_bytes = (int64_t)cand[best].first * 1024;
+      h->mv_unroll = cand[best].second;
+    } else {
+      h->mv_chunk_bytes_multi = (int64_t)cand[best].first * 1024;
+    }
+    set_chunk_list(h, l, (int64_t)cand[best].first * 1024, s);
+    check(hipStreamSynchronize(s), "tune");
+    if (info) {
+      *info = hmat_tune_info{};
+      info->nrhs = nrhs;
+      info->n_candidates = (int32_t)std::min<size_t>(cand.size(), 8);
+      for (size_t c = 0; c < cand.size() && c < 8; c++) {
+        info->chunk_kb[c] = cand[c].first;
+        info->unroll[c] = cand[c].second;
+        info->ms[c] = ms[c];
+      }
+      info->best = (int32_t)best;
+      info->best_ms = ms[best];
+    }
+    fill_stats(h);
+  } catch (const HipError& e) {
+    (void)hipStreamSynchronize(s);
+    return fail(e.st, e.msg);
+  }
+  return HMAT_OK;
 }
 
 hmat_status hmat_bodies(hmat_t h, int32_t* n_bodies, int64_t* dof_off) {

@@ -19,7 +19,11 @@ torch = pytest.importorskip("torch")
 
 
 def test_batch96_sampled_bodies():
+    import gc
+
     import paper_2205_04752_amd as H
+    gc.collect()  # handles of earlier tests release their device memory
+    torch.cuda.empty_cache()
     wl = W.workload_c2()
     bodies = wl["bodies"]
     print("case batch96: building 96 bodies", flush=True)

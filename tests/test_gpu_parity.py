@@ -240,3 +240,24 @@ def test_flat_plate(leaf):
     else:
         assert diff <= 0.01 * len(far), (diff, len(far))
     c.g.close()
+
+
+def test_autotune_keeps_results(c0):
+    """The autotuner times every schedule candidate and keeps the fastest; the
+    product stays within the FP64 parity bound of the oracle (only the grouping
+    of partial sums changes) and is deterministic under the chosen schedule."""
+    H = _H()
+    g = H.HMatrix(c0.V, c0.T, 1.0, 0.3, 2.0, 32, c0.eps)
+    x = W.random_x(c0.N, 8, seed=12)
+    yo = c0.o.matvec(x)
+    for nrhs in (1, 8):
+        t = g.tune(nrhs=nrhs, reps=3)
+        ms = [c[2] for c in t["candidates"]]
+        assert t["best_ms"] == min(ms) and len(ms) == (8 if nrhs == 1 else 4)
+        xs = _dev(x[:nrhs] if nrhs > 1 else x[0])
+        y = np.atleast_2d(g.matvec(xs).cpu().numpy())
+        for r in range(nrhs):
+            assert np.linalg.norm(y[r] - yo[r]) <= 1e-10 * np.linalg.norm(yo[r])
+        y2 = np.atleast_2d(g.matvec(xs).cpu().numpy())
+        assert np.array_equal(y, y2)
+    g.close()
