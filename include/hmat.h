@@ -295,6 +295,22 @@ hmat_status hmat_set_factors(hmat_t h, const int32_t* ranks, const double* U, co
 hmat_status hmat_profile(hmat_t h, int32_t enable, double* phase_ms, int64_t* calls);
 
 /*
+ * hmat_matvec_graph -- hmat_matvec_ex replayed from a captured HIP graph. The
+ * first call for a given (precision, nrhs, x, ldx, y, ldy) captures the
+ * product's kernel launches into a graph (no allocation or memset is
+ * recorded); later calls with the same arguments replay it, one launch in
+ * place of four per pass. Capture runs on an internal stream; replays are
+ * enqueued on `hip_stream`. Up to 256 argument sets are kept per handle
+ * (oldest dropped). Results are those of hmat_matvec_ex, bit for bit.
+ * Calls that change the product schedule or the stored entries
+ * (hmat_tune, hmat_set_factors, hmat_set_precision) wait for the latest
+ * replay and drop the graphs, so the next call captures again.
+ * Errors: as hmat_matvec_ex.
+ */
+hmat_status hmat_matvec_graph(hmat_t h, int32_t precision, int32_t nrhs, const double* x,
+                              int64_t ldx, double* y, int64_t ldy, void* hip_stream);
+
+/*
  * hmat_tune -- autotuner of the product schedule for nrhs vectors per pass.
  * Times `reps` products (after one warm-up) for each candidate: chunk sizes
  * 8, 16, 32, 64 KB and 8 or 16 columns per batch for one vector; chunk sizes

@@ -78,7 +78,7 @@ class _Result(C.Structure):
 EXPORTS = ["hmat_build", "hmat_build_batch", "hmat_bodies", "hmat_matvec", "hmat_matvec_ex",
            "hmat_solve", "hmat_solve_ir", "hmat_set_precision", "hmat_info", "hmat_free",
            "hmat_last_error", "hmat_plan", "hmat_block", "hmat_entries", "hmat_set_factors",
-           "hmat_profile", "hmat_tune", "hmat_amvm", "hmat_server_create", "hmat_server_submit", "hmat_server_wait",
+           "hmat_profile", "hmat_tune", "hmat_matvec_graph", "hmat_amvm", "hmat_server_create", "hmat_server_submit", "hmat_server_wait",
            "hmat_server_destroy", "hmat_server_last_error"]
 
 _lib = None
@@ -111,6 +111,7 @@ def lib():
     L.hmat_set_factors.argtypes = [vp, vp, vp, vp, vp]
     L.hmat_profile.argtypes = [vp, i32, vp, C.POINTER(i64)]
     L.hmat_tune.argtypes = [vp, i32, i32, vp, C.POINTER(_TuneInfo)]
+    L.hmat_matvec_graph.argtypes = [vp, i32, i32, vp, i64, vp, i64, vp]
     L.hmat_amvm.argtypes = [C.POINTER(_Mesh), dbl, dbl, dbl, i32, vp, vp, dbl, dbl, i32, i32, vp,
                             vp, C.POINTER(_AmvmInfo)]
     L.hmat_server_create.argtypes = [i32, i64, dbl, i32, C.POINTER(vp)]
@@ -244,9 +245,10 @@ class HMatrix:
         except Exception:
             pass
 
-    def matvec(self, x, y=None, stream=None, precision: int = 0):
+    def matvec(self, x, y=None, stream=None, precision: int = 0, graph: bool = False):
         """y = A_H x for x of shape [nrhs, n_dof] (or [n_dof]); float64 on the GPU.
-        precision 1 reads the FP32 copies of the entries (set_precision(1))."""
+        precision 1 reads the FP32 copies of the entries (set_precision(1));
+        graph replays a captured HIP graph for this (x, y) pair."""
         import torch
         squeeze = x.dim() == 1
         x2, xp, ldx = _dev_ptr(x, self.n_dof, "x")
@@ -255,7 +257,10 @@ class HMatrix:
         y2, yp, ldy = _dev_ptr(y, self.n_dof, "y")
         if y2.shape[0] != x2.shape[0]:
             raise ValueError("x and y must hold the same number of vectors")
-        if precision == 0:
+        if graph:
+            _check(lib().hmat_matvec_graph(self._h, int(precision), x2.shape[0], xp, ldx, yp, ldy,
+                                           _stream(stream)))
+        elif precision == 0:
             _check(lib().hmat_matvec(self._h, x2.shape[0], xp, ldx, yp, ldy, _stream(stream)))
         else:
             _check(lib().hmat_matvec_ex(self._h, int(precision), x2.shape[0], xp, ldx, yp, ldy,

@@ -182,6 +182,22 @@ void pinned_release(double* p) {
 struct hmat {
   int device = 0;
   hipStream_t last_stream = nullptr;  // stream of the latest call (hmat_free syncs it)
+  // Captured products (hmat_matvec_graph): one executable graph per argument
+  // set, replayed on an internal stream ordered after and before the caller's.
+  struct GraphKey {
+    int prec, nrhs;
+    const double* x;
+    int64_t ldx;
+    double* y;
+    int64_t ldy;
+    bool operator==(const GraphKey& o) const {
+      return prec == o.prec && nrhs == o.nrhs && x == o.x && ldx == o.ldx && y == o.y && ldy == o.ldy;
+    }
+  };
+  std::vector<std::pair<GraphKey, hipGraphExec_t>> graphs;
+  hipStream_t graph_stream = nullptr;
+  hipEvent_t graph_done = nullptr;  // recorded after every replay
+  bool graph_live = false;          // graph_done marks a replay
   Plan plan;
   double eta = 0;
   int32_t leaf = 0;
@@ -255,6 +271,13 @@ struct hmat {
       for (hipEvent_t x : e) (void)hipEventDestroy(x);
     for (hipEvent_t e : col_ev)
       if (e) (void)hipEventDestroy(e);
+    if (graph_live) (void)hipEventSynchronize(graph_done);
+    for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
+    if (graph_done) (void)hipEventDestroy(graph_done);
+    if (graph_stream) {
+      (void)hipStreamSynchronize(graph_stream);
+      (void)hipStreamDestroy(graph_stream);
+    }
     if (h_pinned) pinned_release(h_pinned);
   }
 };
@@ -296,11 +319,22 @@ struct BuildTrace {
   }
 };
 
+// Captured product graphs hold the plan's and arenas' device pointers:
+// drop them whenever those change (after the graphs' last replay finished).
+void drop_graphs(hmat* h) {
+  if (h->graphs.empty()) return;
+  if (h->graph_live) (void)hipEventSynchronize(h->graph_done);
+  h->graph_live = false;
+  for (auto& g : h->graphs) (void)hipGraphExecDestroy(g.second);
+  h->graphs.clear();
+}
+
 // Phase-B chunk list l: runs of consecutive segments of one tile and kind
 // (dense first, then low-rank) holding about `target` bytes, checked and
 // uploaded; the partial-sum workspace grows to fit ([chunk][NR][128], NR = 1
 // for list 0, up to 16 for list 1).
 void set_chunk_list(hmat* h, int l, int64_t target, hipStream_t s) {
+  drop_graphs(h);
   std::vector<MvChunk> chunks;
   std::vector<int32_t> tile_near(h->nTiles + 1, 0), tile_far(h->nTiles + 1, 0);
   int n_near = 0;
@@ -1585,6 +1619,69 @@ hmat_status hmat_amvm(const hmat_mesh* mesh, double E, double nu, double eta, in
                    (hipStream_t)hip_stream, ranks, info);
 }
 
+hmat_status hmat_matvec_graph(hmat_t h, int32_t precision, int32_t nrhs, const double* x,
+                              int64_t ldx, double* y, int64_t ldy, void* hip_stream) {
+  if (!h) return fail(HMAT_EINVAL, "handle is NULL");
+  if (precision != 0 && precision != 1) return fail(HMAT_EINVAL, "precision must be 0 (FP64) or 1 (FP32)");
+  if (precision == 1 && !h->far32.p && !h->stream32.p)
+    return fail(HMAT_EINVAL, "no FP32 copy: call hmat_set_precision(h, 1, ...) first");
+  if (!x || !y) return fail(HMAT_EINVAL, "x or y is NULL");
+  if (nrhs < 1 || nrhs > 64) return fail(HMAT_EINVAL, "nrhs must lie in [1, 64]");
+  if (ldx < h->N || ldy < h->N) return fail(HMAT_EINVAL, "ldx and ldy must be >= n_dof");
+  const char* xa = (const char*)x;
+  const char* xb = (const char*)(x + (nrhs - 1) * ldx + h->N);
+  const char* ya = (const char*)y;
+  const char* yb = (const char*)(y + (nrhs - 1) * ldy + h->N);
+  if (xa < yb && ya < xb) return fail(HMAT_EINVAL, "x and y overlap");
+  hipStream_t s = (hipStream_t)hip_stream;
+  StreamScope scope(s);
+  h->last_stream = s;
+  try {
+    if (!h->graph_stream) {
+      check(hipStreamCreateWithFlags(&h->graph_stream, hipStreamNonBlocking), "graph stream");
+      check(hipEventCreateWithFlags(&h->graph_done, hipEventDisableTiming), "graph stream");
+    }
+    const hmat::GraphKey key{precision, nrhs, x, ldx, y, ldy};
+    hipGraphExec_t exec = nullptr;
+    for (auto& g : h->graphs)
+      if (g.first == key) exec = g.second;
+    if (!exec) {
+      // capture the product's launches (no allocation, no memset inside)
+      const bool prof = h->prof;
+      h->prof = false;
+      hipGraph_t graph = nullptr;
+      check(hipStreamBeginCapture(h->graph_stream, hipStreamCaptureModeThreadLocal), "graph capture");
+      try {
+        matvec_impl(h, precision, nrhs, x, ldx, y, ldy, h->graph_stream);
+      } catch (...) {
+        (void)hipStreamEndCapture(h->graph_stream, &graph);
+        if (graph) (void)hipGraphDestroy(graph);
+        h->prof = prof;
+        throw;
+      }
+      h->prof = prof;
+      check(hipStreamEndCapture(h->graph_stream, &graph), "graph capture");
+      const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      check(e, "graph instantiate");
+      if (h->graphs.size() >= 256) {  // bounded cache: drop the oldest
+        if (h->graph_live) (void)hipEventSynchronize(h->graph_done);
+        (void)hipGraphExecDestroy(h->graphs.front().second);
+        h->graphs.erase(h->graphs.begin());
+      }
+      h->graphs.push_back({key, exec});
+    }
+    // replayed on the caller's stream; the event marks the latest replay so
+    // that dropping the graphs can wait for it
+    check(hipGraphLaunch(exec, s), "graph launch");
+    check(hipEventRecord(h->graph_done, s), "graph launch");
+    h->graph_live = true;
+  } catch (const HipError& e) {
+    return fail(e.st, e.msg);
+  }
+  return HMAT_OK;
+}
+
 hmat_status hmat_tune(hmat_t h, int32_t nrhs, int32_t reps, void* hip_stream, hmat_tune_info* info) {
   if (!h) return fail(HMAT_EINVAL, "handle is NULL");
   if (nrhs < 1 || nrhs > MV_MAX_NR) return fail(HMAT_EINVAL, "nrhs must lie in [1, 16]");
@@ -1788,6 +1885,7 @@ hmat_status hmat_set_precision(hmat_t h, int32_t precision, void* hip_stream) {
   h->last_stream = s;
   try {
     check(hipStreamSynchronize(s), "set precision");
+    drop_graphs(h);
     h->far32.release();
     h->stream32.release();
     if (precision == 1) {

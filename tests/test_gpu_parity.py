@@ -261,3 +261,29 @@ def test_autotune_keeps_results(c0):
         y2 = np.atleast_2d(g.matvec(xs).cpu().numpy())
         assert np.array_equal(y, y2)
     g.close()
+
+
+@pytest.mark.parametrize("nrhs,prec", [(1, 0), (3, 0), (1, 1)])
+def test_graph_replays(c0, nrhs, prec):
+    """A captured product replayed several times, with eager products, in-place
+    changes of x and synchronisations between replays: every replay equals the
+    eager product of the same x bit for bit."""
+    H = _H()
+    g = H.HMatrix(c0.V, c0.T, 1.0, 0.3, 2.0, 32, c0.eps)
+    if prec:
+        g.set_precision(1)
+    X = _dev(W.random_x(c0.N, nrhs, seed=20))
+    Y = torch.empty_like(X)
+    other = _dev(W.random_x(c0.N, 2, seed=21))
+    for rep in range(5):
+        X.mul_(1.0 + 0.1 * rep)  # new contents, same pointer
+        g.matvec(X, Y, precision=prec, graph=True)
+        eager = g.matvec(X, precision=prec)
+        g.matvec(other, precision=prec)  # eager work between replays
+        torch.cuda.synchronize()
+        assert torch.equal(Y, eager), rep
+    # a schedule change drops the captured graphs; replays stay correct
+    g.tune(nrhs=nrhs, reps=1)
+    g.matvec(X, Y, precision=prec, graph=True)
+    assert torch.equal(Y, g.matvec(X, precision=prec))
+    g.close()
