@@ -174,7 +174,9 @@ __device__ __forceinline__ void mv_b_chunk(const MvChunk& C, int chunk,
     const MvSeg S = segs[s];
     const int len = S.row_hi - S.row_lo;
     if (NR == 1 && len <= WAVE) {
-      mv_b_grouped<UNR, T>(S, stream, S.far ? z : xp, acc0[0], acc1[0]);
+      // at most 8 loads per batch here: the x values are per lane too, and a
+      // deeper batch raises the kernel's register count past 4 waves per SIMD
+      mv_b_grouped<(UNR > 8 ? 8 : UNR), T>(S, stream, S.far ? z : xp, acc0[0], acc1[0]);
       continue;
     }
     const bool act = L2 >= S.row_lo && L2 < S.row_hi;
