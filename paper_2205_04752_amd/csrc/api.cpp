@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <deque>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <new>
@@ -32,12 +33,11 @@ hipError_t launch_gather(int, const double*, int64_t, const int32_t*, int64_t, d
 hipError_t launch_matvec_group(const ProductPlanDev&, int, int, const double*, int64_t, double*, int64_t,
                                double*, double*, int64_t, hipStream_t, hipEvent_t*, int);
 hipError_t launch_to_f32(const double*, float*, int64_t, hipStream_t);
-int launch_dots_part(const double*, int64_t, int64_t, int, const double*, double*, hipStream_t);
 size_t dots_part_size(int64_t, int);
 size_t norm_part_size(int64_t);
-hipError_t launch_proj(const double*, int64_t, int64_t, int, const double*, int, double*, double*, int, double*, hipStream_t);
+hipError_t launch_cgs_pass(const double*, int64_t, int64_t, int, double*, double*, double*, double*, int, double*, hipStream_t);
 hipError_t launch_norm(const double*, int64_t, double*, double*, hipStream_t);
-hipError_t launch_norm_final(const double*, int64_t, double*, hipStream_t);
+hipError_t launch_scale_norm(const double*, int64_t, const double*, double*, double*, hipStream_t);
 hipError_t launch_scale(const double*, int64_t, const double*, double*, hipStream_t);
 hipError_t launch_add_comb(const double*, int64_t, int64_t, int, const double*, double*, hipStream_t);
 hipError_t launch_residual(const double*, int64_t, double*, hipStream_t);
@@ -70,12 +70,12 @@ void check(hipError_t e, const char* what) {
   throw HipError{oom ? HMAT_ENOMEM : HMAT_EDEVICE, std::string(what) + ": " + hipGetErrorString(e)};
 }
 
-// Device memory is stream-ordered (hipMallocAsync / hipFreeAsync) on the
-// stream of the entry point being served, so allocating or freeing never
-// waits for work of other streams -- concurrent requests on their own
-// streams do not serialise on each other's allocations. Every entry point
-// sets the stream with a StreamScope; a buffer is used only on that stream
-// (calls on one handle are serialised by the caller).
+// Device memory is stream-ordered on the stream of the entry point being
+// served, so allocating or freeing never waits for work of other streams --
+// concurrent requests on their own streams do not serialise on each other's
+// allocations. Every entry point sets the stream with a StreamScope; a buffer
+// is used only on that stream (calls on one handle are serialised by the
+// caller).
 thread_local hipStream_t g_alloc_stream = nullptr;
 
 struct StreamScope {
@@ -99,22 +99,179 @@ void init_pool() {
   });
 }
 
+// Device memory cache. A stream-ordered hipMallocAsync / hipFreeAsync pair
+// costs about 0.3 ms on an idle device and far more when several threads
+// allocate at once, and a build makes dozens of allocations; so blocks the
+// library releases are kept per device and handed to later allocations. Sizes
+// are rounded up to classes of an eighth of a power of two (at least 256 B);
+// an allocation takes the smallest cached block of at least its class and at
+// most 1.5 times it. A released block carries an event recorded on the
+// releasing stream (the stream of its last use), and the allocating stream
+// waits for it, so reuse on any stream is ordered after the last use. The
+// cache holds at most a sixteenth of the device memory (the largest blocks go
+// first beyond that) and is emptied when an allocation runs out of memory.
+constexpr int MAX_DEVICES = 64;
+struct CachedBlock {
+  void* p;
+  size_t bytes;
+  hipEvent_t ev;
+};
+struct MemCache {
+  std::mutex mu;
+  std::multimap<size_t, CachedBlock> blocks;  // by size
+  size_t cached = 0, limit = 0;
+  std::vector<hipEvent_t> spare;  // events of reused blocks
+};
+MemCache g_mem[MAX_DEVICES];
+
+size_t size_class(size_t b) {
+  if (b <= 256) return 256;
+  const int lg = 63 - __builtin_clzll((unsigned long long)(b - 1));  // 2^lg <= b-1 < 2^(lg+1)
+  const size_t step = (size_t)1 << (lg - 3);
+  return (b + step - 1) / step * step;
+}
+
+int current_device() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return -1;
+  }
+  return dev < MAX_DEVICES ? dev : -1;
+}
+
+// Frees every cached block of device dev, ordered on stream s.
+void mem_trim(int dev, hipStream_t s) {
+  if (dev < 0) return;
+  MemCache& c = g_mem[dev];
+  std::vector<CachedBlock> all;
+  {
+    std::lock_guard<std::mutex> lk(c.mu);
+    for (auto& kv : c.blocks) all.push_back(kv.second);
+    c.blocks.clear();
+    c.cached = 0;
+  }
+  for (const CachedBlock& b : all) {
+    (void)hipStreamWaitEvent(s, b.ev, 0);
+    (void)hipFreeAsync(b.p, s);
+    (void)hipEventDestroy(b.ev);
+  }
+  (void)hipStreamSynchronize(s);
+  (void)hipGetLastError();
+}
+
+// At least b bytes for use on stream s; *cls and *dev receive what mem_free needs.
+void* mem_alloc(size_t b, hipStream_t s, size_t* cls, int* dev, const char* what) {
+  const size_t cl = size_class(b);
+  const int d = current_device();
+  *dev = d;
+  if (d >= 0) {
+    MemCache& c = g_mem[d];
+    CachedBlock blk{nullptr, 0, nullptr};
+    {
+      std::lock_guard<std::mutex> lk(c.mu);
+      auto it = c.blocks.lower_bound(cl);
+      if (it != c.blocks.end() && it->first <= cl + cl / 2) {
+        blk = it->second;
+        c.cached -= blk.bytes;
+        c.blocks.erase(it);
+      }
+    }
+    if (blk.p) {
+      const hipError_t e = hipStreamWaitEvent(s, blk.ev, 0);
+      {
+        std::lock_guard<std::mutex> lk(c.mu);
+        c.spare.push_back(blk.ev);
+      }
+      if (e != hipSuccess) {  // cannot order the reuse: give the block back to the pool
+        (void)hipGetLastError();
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(blk.p);
+      } else {
+        *cls = blk.bytes;
+        return blk.p;
+      }
+    }
+  }
+  void* p = nullptr;
+  hipError_t e = hipMallocAsync(&p, cl, s);
+  if (e == hipErrorOutOfMemory) {
+    (void)hipGetLastError();
+    mem_trim(d, s);
+    e = hipMallocAsync(&p, cl, s);
+  }
+  check(e, what);
+  *cls = cl;
+  return p;
+}
+
+// Releases a block of class cls (from mem_alloc on device dev) whose last use
+// is on stream s.
+void mem_free(void* p, size_t cls, int dev, hipStream_t s) {
+  if (dev < 0 || dev != current_device()) {
+    (void)hipFreeAsync(p, s);
+    return;
+  }
+  MemCache& c = g_mem[dev];
+  hipEvent_t ev = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(c.mu);
+    if (c.limit == 0) {
+      size_t fr = 0, tot = 0;
+      c.limit = hipMemGetInfo(&fr, &tot) == hipSuccess ? tot / 16 : (size_t)1 << 30;
+      (void)hipGetLastError();
+    }
+    if (!c.spare.empty()) {
+      ev = c.spare.back();
+      c.spare.pop_back();
+    }
+  }
+  if ((!ev && hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) ||
+      hipEventRecord(ev, s) != hipSuccess) {
+    (void)hipGetLastError();
+    if (ev) (void)hipEventDestroy(ev);
+    (void)hipFreeAsync(p, s);
+    return;
+  }
+  std::vector<CachedBlock> evict;
+  {
+    std::lock_guard<std::mutex> lk(c.mu);
+    c.blocks.emplace(cls, CachedBlock{p, cls, ev});
+    c.cached += cls;
+    while (c.cached > c.limit && !c.blocks.empty()) {
+      auto it = std::prev(c.blocks.end());
+      evict.push_back(it->second);
+      c.cached -= it->first;
+      c.blocks.erase(it);
+    }
+  }
+  for (const CachedBlock& b : evict) {
+    (void)hipStreamWaitEvent(s, b.ev, 0);
+    (void)hipFreeAsync(b.p, s);
+    std::lock_guard<std::mutex> lk(c.mu);
+    c.spare.push_back(b.ev);
+  }
+}
+
 struct DevBuf {
   void* p = nullptr;
-  size_t bytes = 0;
+  size_t bytes = 0;  // requested
+  size_t cls = 0;    // held (size class)
+  int dev = -1;
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
   ~DevBuf() { release(); }
   void release() {
-    if (p) (void)hipFreeAsync(p, g_alloc_stream);
+    if (p) mem_free(p, cls, dev, g_alloc_stream);
     p = nullptr;
     bytes = 0;
+    cls = 0;
   }
   void alloc(size_t b, const char* what) {
     release();
     if (b == 0) return;
-    check(hipMallocAsync(&p, b, g_alloc_stream), what);
+    p = mem_alloc(b, g_alloc_stream, &cls, &dev, what);
     bytes = b;
   }
   template <class T>
@@ -127,7 +284,106 @@ void upload(DevBuf& d, const std::vector<T>& h, hipStream_t s, const char* what)
   if (!h.empty()) check(hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s), what);
 }
 
-constexpr int KCAP_FIRST = 128;  // first-pass panel capacity (columns) of ACA
+constexpr int KCAP_FIRST = 128;  // largest first-pass panel capacity (columns) of ACA
+
+// First-pass capacity for accuracy eps: about twice the largest rank that
+// ACA reaches at that accuracy on the surface meshes here (ranks grow by
+// about six per decade of eps), in multiples of 16, at most KCAP_FIRST. A
+// block that reaches it is run again with capacity min(m, n), so the factors
+// do not depend on this choice; only the panel memory and the reruns do.
+int32_t kcap_first(double eps) {
+  const double d = -std::log10(eps);
+  const int32_t c = 16 * (int32_t)std::ceil((24.0 + 12.0 * d) / 16.0);
+  return std::min<int32_t>(KCAP_FIRST, std::max<int32_t>(32, c));
+}
+
+// First-pass ACA panels (several GB for a mesh of 10^5 DOF) are not
+// allocated per build: each device keeps one buffer, grown to the largest
+// request up to a sixteenth of the device memory and never shrunk, which is
+// lent to one build at a time. A build that finds it lent, or needs more,
+// uses a buffer of its own, released after its ACA phase. Allocating and
+// releasing buffers of that size on every build stalled builds for up to
+// seconds. The buffer is held until the process ends.
+struct PanelCache {
+  std::mutex mu;
+  void* p = nullptr;
+  size_t bytes = 0;
+  size_t keep_max = 0;  // largest buffer kept (0: not known yet)
+  bool lent = false;
+};
+PanelCache g_panel_cache[MAX_DEVICES];
+
+class PanelLease {
+ public:
+  PanelLease(int dev, hipStream_t s) : s_(s) {
+    if (dev < 0 || dev >= MAX_DEVICES) return;
+    PanelCache& c = g_panel_cache[dev];
+    std::lock_guard<std::mutex> lk(c.mu);
+    if (c.lent) return;
+    if (c.keep_max == 0) {
+      size_t fr = 0, tot = 0;
+      if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+        (void)hipGetLastError();
+        return;
+      }
+      c.keep_max = tot / 16;
+    }
+    c.lent = true;
+    cache_ = &c;
+    p_ = c.p;
+    bytes_ = c.bytes;
+    keep_max_ = c.keep_max;
+  }
+  PanelLease(const PanelLease&) = delete;
+  PanelLease& operator=(const PanelLease&) = delete;
+  // At least `need` bytes, on the lease's stream.
+  double* get(size_t need) {
+    if (!cache_ || need > keep_max_) {
+      if (cache_ && p_) {  // a large build: the kept buffer's memory goes back too
+        (void)hipFreeAsync(p_, s_);
+        p_ = nullptr;
+        bytes_ = 0;
+      }
+      if (own_.bytes < need) own_.alloc(need, "ACA panels");
+      return own_.as<double>();
+    }
+    if (bytes_ < need) {
+      if (p_) (void)hipFreeAsync(p_, s_);
+      p_ = nullptr;
+      bytes_ = 0;
+      hipError_t e = hipMallocAsync(&p_, need, s_);
+      if (e == hipErrorOutOfMemory) {
+        (void)hipGetLastError();
+        mem_trim(current_device(), s_);
+        e = hipMallocAsync(&p_, need, s_);
+      }
+      check(e, "ACA panels");
+      bytes_ = need;
+    }
+    return static_cast<double*>(p_);
+  }
+  // Returned (at the latest by the destructor) once the stream has finished
+  // every kernel that used it.
+  void give_back() {
+    own_.release();
+    if (!cache_) return;
+    (void)hipStreamSynchronize(s_);
+    std::lock_guard<std::mutex> lk(cache_->mu);
+    cache_->p = p_;
+    cache_->bytes = bytes_;
+    cache_->lent = false;
+    cache_ = nullptr;
+  }
+  ~PanelLease() { give_back(); }
+
+ private:
+  hipStream_t s_;
+  PanelCache* cache_ = nullptr;
+  void* p_ = nullptr;
+  size_t bytes_ = 0;
+  size_t keep_max_ = 0;
+  DevBuf own_;
+};
 constexpr int MV_TILE = 128;     // rows per product tile (one wave, two rows per lane)
 constexpr int MV_SEG_COLS = 128; // columns per product segment
 constexpr int64_t MV_CHUNK_BYTES = 16 * 1024;         // nrhs = 1; HMAT_MV_CHUNK_KB overrides
@@ -645,8 +901,8 @@ struct EventPair {
 
 // One ACA pass over the far blocks listed in `fidx` (largest first) with
 // per-block capacity cap(f); panels in `panels`, pivots in `piv`.
-template <class CapFn>
-void run_aca_pass(hmat* h, const std::vector<int32_t>& fidx, CapFn cap, DevBuf& panels, DevBuf& piv,
+template <class CapFn, class PanelFn>
+void run_aca_pass(hmat* h, const std::vector<int32_t>& fidx, CapFn cap, PanelFn get_panels, DevBuf& piv,
                   DevBuf& d_rank, DevBuf& d_stop, DevBuf& d_ratio,
                   std::vector<const double*>& panel_ptr, hipStream_t s) {
   const Plan& P = h->plan;
@@ -667,7 +923,7 @@ void run_aca_pass(hmat* h, const std::vector<int32_t>& fidx, CapFn cap, DevBuf& 
     shmem = std::max(shmem, (size_t)kc * 8 + (size_t)((m + 31) / 32) * 4);
   }
   if (shmem > 160 * 1024) throw HipError{HMAT_ENOTSUP, "ACA panel row exceeds LDS capacity"};
-  if (panels.bytes < sizeof(double) * panel_total) panels.alloc(sizeof(double) * panel_total, "ACA panels");
+  double* const panels = get_panels(sizeof(double) * std::max<int64_t>(panel_total, 1));
   piv.alloc(sizeof(int32_t) * piv_total, "ACA pivots");
   std::vector<AcaTask> tasks;
   tasks.reserve(ord.size());
@@ -682,7 +938,7 @@ void run_aca_pass(hmat* h, const std::vector<int32_t>& fidx, CapFn cap, DevBuf& 
     t.t_len = P.cl[B.t].len;
     t.s_off = P.cl[B.s].off;
     t.s_len = P.cl[B.s].len;
-    t.panel = panels.as<double>() + po;
+    t.panel = panels + po;
     t.piv = piv.as<int32_t>() + vo;
     t.kcap = kc;
     t.blk = f;
@@ -904,7 +1160,8 @@ hmat_status build_impl(const std::vector<BodyIn>& in, double eta, int32_t leaf, 
     check(hipEventRecord(eva.a, s), "event");
     auto cap1 = [&](int32_t f) {
       const int32_t b = h->far_blocks[f];
-      return (int32_t)std::min<int64_t>(std::min(block_m(h, b), block_n(h, b)), KCAP_FIRST);
+      const double e = h->bodies[h->pos_body[h->plan.cl[h->plan.blk[b].t].off]].eps;
+      return (int32_t)std::min<int64_t>(std::min(block_m(h, b), block_n(h, b)), kcap_first(e));
     };
     auto cap2 = [&](int32_t f) {
       const int32_t b = h->far_blocks[f];
@@ -915,7 +1172,7 @@ hmat_status build_impl(const std::vector<BodyIn>& in, double eta, int32_t leaf, 
     std::deque<DevBuf> ustage, vstage;
     const int64_t budget = aca_budget();
     h->aca_passes = 0;
-    DevBuf panels1;  // first-pass panels, reused by every group
+    PanelLease panels1(h->device, s);  // first-pass panels, reused by every group
     BuildTrace tr;
     tr.mark("plan, geometry, K1", s);
     // concurrent builds of a request server take the ACA phase one at a time
@@ -937,7 +1194,8 @@ hmat_status build_impl(const std::vector<BodyIn>& in, double eta, int32_t leaf, 
       for (int32_t f : grp) capv[f] = cap1(f);
       DevBuf panels2;
       h->piv_bufs.emplace_back();
-      run_aca_pass(h, grp, cap1, panels1, h->piv_bufs.back(), d_rank, d_stop, d_ratio, panel_ptr, s);
+      run_aca_pass(h, grp, cap1, [&](size_t b) { return panels1.get(b); }, h->piv_bufs.back(), d_rank,
+                   d_stop, d_ratio, panel_ptr, s);
       h->aca_passes = std::max(h->aca_passes, 1);
       auto fetch = [&]() {
         check(hipMemcpyAsync(h->rank.data() + f0, d_rank.as<int32_t>() + f0, sizeof(int32_t) * (f1 - f0),
@@ -953,7 +1211,12 @@ hmat_status build_impl(const std::vector<BodyIn>& in, double eta, int32_t leaf, 
       if (!again.empty()) {
         for (int32_t f : again) capv[f] = cap2(f);
         h->piv_bufs.emplace_back();
-        run_aca_pass(h, again, cap2, panels2, h->piv_bufs.back(), d_rank, d_stop, d_ratio, panel_ptr, s);
+        run_aca_pass(h, again, cap2,
+                     [&](size_t b) {
+                       if (panels2.bytes < b) panels2.alloc(b, "ACA panels");
+                       return panels2.as<double>();
+                     },
+                     h->piv_bufs.back(), d_rank, d_stop, d_ratio, panel_ptr, s);
         h->aca_passes = 2;
         fetch();
       }
@@ -994,7 +1257,7 @@ hmat_status build_impl(const std::vector<BodyIn>& in, double eta, int32_t leaf, 
       f0 = f1;
       tr.mark("ACA group", s);
     }
-    panels1.release();
+    panels1.give_back();
     if (gate.owns_lock()) {
       check(hipStreamSynchronize(s), "ACA");
       gate.unlock();
@@ -1173,6 +1436,7 @@ hmat_status gmres_impl(hmat* h, int prec, const double* b, double* x, double tol
     double* Q = h->d_Q.as<double>();
     double* w = h->d_w.as<double>();
     double* base = h->d_small.as<double>();
+    double* hvec = base;                             // coefficients of one Gram-Schmidt pass
     double* hacc[2] = {base + COL, base + 2 * COL};  // Hessenberg columns, double-buffered
     double* ycoef = base + 3 * COL;                  // [m]
     double* scal = ycoef + COL;                      // scalars
@@ -1190,13 +1454,11 @@ hmat_status gmres_impl(hmat* h, int prec, const double* b, double* x, double tol
     auto enqueue_step = [&](int j) {
       double* col = hacc[j % 2];
       matvec_impl(h, prec, 1, Q + (size_t)j * N, N, w, N, s);
-      for (int pass = 0; pass < 2; pass++) {
-        const int nblk = launch_dots_part(Q, N, N, j + 1, w, dotpart, s);
-        check(launch_proj(Q, N, N, j + 1, dotpart, nblk, w, col, pass == 0, pass == 1 ? normpart : nullptr, s),
+      for (int pass = 0; pass < 2; pass++)
+        check(launch_cgs_pass(Q, N, N, j + 1, w, dotpart, hvec, col, pass == 0,
+                              pass == 1 ? normpart : nullptr, s),
               "project");
-      }
-      check(launch_norm_final(normpart, N, col + j + 1, s), "norm");
-      check(launch_scale(w, N, col + j + 1, Q + (size_t)(j + 1) * N, s), "scale");
+      check(launch_scale_norm(w, N, normpart, col + j + 1, Q + (size_t)(j + 1) * N, s), "scale");
       check(hipMemcpyAsync(hcol_host[j % 2], col, sizeof(double) * (j + 2), hipMemcpyDeviceToHost, s),
             "hessenberg");
       check(hipEventRecord(h->col_ev[j % 2], s), "hessenberg");

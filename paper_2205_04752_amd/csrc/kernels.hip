@@ -599,56 +599,75 @@ hipError_t launch_lowrank_delta(const DeltaTask* tasks, int n, const double* xp,
 // ---------------------------------------------------------------------------
 // GMRES helpers (FP64).
 
-// Two-stage Q^T w: workgroup b takes rows [b*DOT_ROWS, (b+1)*DOT_ROWS) and writes
-// part[b*ncols + c] = sum over its rows of Q[i, c] w[i]; k_proj sums over b.
+// Classical Gram-Schmidt pass h = Q^T w, w -= Q h in three launches:
+// k_dots_part (partial dot products per block of rows and group of columns),
+// k_dots_final (one wave per column sums the partials in a fixed order) and
+// k_proj (the update, reading h).
+//
+// Workgroup (b, g) takes rows [b*DOT_ROWS, (b+1)*DOT_ROWS) (two per thread)
+// and columns [g*DOT_COLS, (g+1)*DOT_COLS), and writes
+// part[b*ncols + c] = sum over its rows of Q[i, c] w[i]. The column group's
+// loads are independent, so each thread has 2*DOT_COLS of them in flight.
 constexpr int DOT_ROWS = 512;
+constexpr int DOT_COLS = 8;
 __global__ __launch_bounds__(256) void k_dots_part(const double* __restrict__ Q, int64_t ldq,
                                                    int64_t n, int ncols,
                                                    const double* __restrict__ w,
                                                    double* __restrict__ part) {
-  extern __shared__ double red[];  // [NW][ncols]
+  __shared__ double red[NW][DOT_COLS];
+  const int c0 = blockIdx.y * DOT_COLS;
+  const int nc = min(DOT_COLS, ncols - c0);
   const int64_t i0 = (int64_t)blockIdx.x * DOT_ROWS + threadIdx.x;
   const int64_t i1 = i0 + 256;
   const double w0 = i0 < n ? w[i0] : 0.0, w1 = i1 < n ? w[i1] : 0.0;
   const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
-  for (int c = 0; c < ncols; c++) {
-    const double* q = Q + (size_t)c * ldq;
-    double s = (i0 < n ? q[i0] * w0 : 0.0) + (i1 < n ? q[i1] * w1 : 0.0);
-    s = wave_sum(s);
-    if (lane == 0) red[wv * ncols + c] = s;
+  double acc[DOT_COLS];
+#pragma unroll
+  for (int c = 0; c < DOT_COLS; c++) {
+    // columns past the group's last re-read it (not stored)
+    const double* q = Q + (size_t)(c0 + min(c, nc - 1)) * ldq;
+    acc[c] = (i0 < n ? q[i0] * w0 : 0.0) + (i1 < n ? q[i1] * w1 : 0.0);
+  }
+#pragma unroll
+  for (int c = 0; c < DOT_COLS; c++) {
+    const double t = wave_sum(acc[c]);
+    if (lane == 0) red[wv][c] = t;
   }
   __syncthreads();
-  for (int c = threadIdx.x; c < ncols; c += blockDim.x) {
+  if (threadIdx.x < nc) {
     double t = 0.0;
-    for (int k = 0; k < NW; k++) t += red[k * ncols + c];
-    part[(size_t)blockIdx.x * ncols + c] = t;
+    for (int k = 0; k < NW; k++) t += red[k][threadIdx.x];
+    part[(size_t)blockIdx.x * ncols + c0 + threadIdx.x] = t;
   }
 }
 
-// w -= Q[:, 0:ncols] h, where h[c] = sum_b part[b*ncols + c] (the partial dot
-// products of k_dots_part, summed here by every workgroup into LDS). Block 0
-// also folds h into the Hessenberg column acc (acc = h if assign, else
-// acc += h). If normpart != nullptr, each workgroup writes the partial sum of
-// squares of its updated rows to normpart[blockIdx.x].
-constexpr int PROJ_MAX_COLS = 1025;
-__global__ __launch_bounds__(256) void k_proj(const double* __restrict__ Q, int64_t ldq, int64_t n,
-                                              int ncols, const double* __restrict__ part, int nblk,
-                                              double* __restrict__ w, double* __restrict__ acc,
-                                              int assign, double* __restrict__ normpart) {
-  __shared__ double hs[PROJ_MAX_COLS];
-  __shared__ double red[256 / WAVE];
-  for (int c = threadIdx.x; c < ncols; c += blockDim.x) {
-    double t = 0.0;
-    for (int b = 0; b < nblk; b++) t += part[(size_t)b * ncols + c];
-    hs[c] = t;
-    if (acc && blockIdx.x == 0) acc[c] = assign ? t : acc[c] + t;
+// hv[c] = sum_b part[b*ncols + c] (one wave per column: lanes stride over b,
+// then a wave sum); the Hessenberg column acc takes hv (assign) or adds it.
+__global__ __launch_bounds__(WAVE) void k_dots_final(const double* __restrict__ part, int nblk,
+                                                     int ncols, double* __restrict__ hv,
+                                                     double* __restrict__ acc, int assign) {
+  const int c = blockIdx.x;
+  double t = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += WAVE) t += part[(size_t)b * ncols + c];
+  t = wave_sum(t);
+  if (threadIdx.x == 0) {
+    hv[c] = t;
+    acc[c] = assign ? t : acc[c] + t;
   }
-  __syncthreads();
+}
+
+// w -= Q[:, 0:ncols] hv. If normpart != nullptr, each workgroup writes the
+// partial sum of squares of its updated rows to normpart[blockIdx.x].
+__global__ __launch_bounds__(256) void k_proj(const double* __restrict__ Q, int64_t ldq, int64_t n,
+                                              int ncols, const double* __restrict__ hv,
+                                              double* __restrict__ w, double* __restrict__ normpart) {
+  __shared__ double red[NW];
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   double sq = 0.0;
   if (i < n) {
     double s = 0.0;
-    for (int c = 0; c < ncols; c++) s += Q[(size_t)c * ldq + i] * hs[c];
+#pragma unroll 8
+    for (int c = 0; c < ncols; c++) s += Q[(size_t)c * ldq + i] * hv[c];
     const double v = w[i] - s;
     w[i] = v;
     sq = v * v;
@@ -659,10 +678,36 @@ __global__ __launch_bounds__(256) void k_proj(const double* __restrict__ Q, int6
     __syncthreads();
     if (threadIdx.x == 0) {
       double t = 0.0;
-      for (int k = 0; k < 256 / WAVE; k++) t += red[k];
+      for (int k = 0; k < NW; k++) t += red[k];
       normpart[blockIdx.x] = t;
     }
   }
+}
+
+// out = w / ||w|| with ||w|| = sqrt(sum of normpart[0:nblk]), summed by every
+// workgroup in the same order (so all use the same value); workgroup 0 also
+// stores the norm in *nrm. out is untouched when the norm is 0.
+__global__ __launch_bounds__(256) void k_scale_norm(const double* __restrict__ w, int64_t n,
+                                                    const double* __restrict__ normpart, int nblk,
+                                                    double* __restrict__ nrm,
+                                                    double* __restrict__ out) {
+  __shared__ double red[NW];
+  __shared__ double dsh;
+  double t = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x) t += normpart[b];
+  t = wave_sum(t);
+  if ((threadIdx.x & (WAVE - 1)) == 0) red[threadIdx.x / WAVE] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double u = 0.0;
+    for (int k = 0; k < NW; k++) u += red[k];
+    dsh = sqrt(u);
+    if (blockIdx.x == 0) *nrm = dsh;
+  }
+  __syncthreads();
+  const double d = dsh;
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n && d != 0.0) out[i] = w[i] / d;
 }
 
 // Partial sums of squares: part[b] = sum over the rows of block b of w[i]^2.
@@ -774,25 +819,33 @@ hipError_t launch_compact(const CopyTask* tasks, int ntasks, hipStream_t s) {
   return hipGetLastError();
 }
 
-// Scratch (doubles) for the partial dot products of launch_dots_part.
+// Scratch (doubles) for the partial dot products of launch_cgs_pass.
 size_t dots_part_size(int64_t n, int ncols) { return (size_t)((n + DOT_ROWS - 1) / DOT_ROWS) * ncols; }
 
-// part[b][c] = partial Q[:, c] . w over row block b (c < ncols); returns the block count.
-int launch_dots_part(const double* Q, int64_t ldq, int64_t n, int ncols, const double* w,
-                     double* part, hipStream_t s) {
+// One Gram-Schmidt pass: hv = Q[:, 0:ncols]^T w, acc = hv (assign) or
+// acc += hv, w -= Q hv; with normpart, also the partial sums of squares of
+// the new w (norm_part_size(n) doubles). part: dots_part_size(n, ncols).
+hipError_t launch_cgs_pass(const double* Q, int64_t ldq, int64_t n, int ncols, double* w,
+                           double* part, double* hv, double* acc, int assign, double* normpart,
+                           hipStream_t s) {
   const int nblk = (int)((n + DOT_ROWS - 1) / DOT_ROWS);
-  hipLaunchKernelGGL(k_dots_part, dim3(nblk), dim3(256), sizeof(double) * NW * ncols, s, Q, ldq, n,
-                     ncols, w, part);
-  return nblk;
+  hipLaunchKernelGGL(k_dots_part, dim3(nblk, (ncols + DOT_COLS - 1) / DOT_COLS), dim3(256), 0, s, Q, ldq,
+                     n, ncols, w, part);
+  hipLaunchKernelGGL(k_dots_final, dim3(ncols), dim3(WAVE), 0, s, part, nblk, ncols, hv, acc, assign);
+  hipLaunchKernelGGL(k_proj, dim3(blocks_for(n, 256)), dim3(256), 0, s, Q, ldq, n, ncols, hv, w,
+                     normpart);
+  return hipGetLastError();
 }
 
 // Partial-norm scratch (doubles) for n rows.
 size_t norm_part_size(int64_t n) { return (size_t)((n + 255) / 256); }
 
-hipError_t launch_proj(const double* Q, int64_t ldq, int64_t n, int ncols, const double* part,
-                       int nblk, double* w, double* acc, int assign, double* normpart, hipStream_t s) {
-  hipLaunchKernelGGL(k_proj, dim3(blocks_for(n, 256)), dim3(256), 0, s, Q, ldq, n, ncols, part, nblk,
-                     w, acc, assign, normpart);
+// out = w / ||w|| from the partial sums of squares written by the last pass;
+// *nrm = ||w||.
+hipError_t launch_scale_norm(const double* w, int64_t n, const double* normpart, double* nrm,
+                             double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_norm, dim3(blocks_for(n, 256)), dim3(256), 0, s, w, n, normpart,
+                     (int)blocks_for(n, 256), nrm, out);
   return hipGetLastError();
 }
 
@@ -801,11 +854,6 @@ hipError_t launch_norm(const double* w, int64_t n, double* normpart, double* out
   const int nblk = (int)blocks_for(n, 256);
   hipLaunchKernelGGL(k_sqnorm_part, dim3(nblk), dim3(256), 0, s, w, n, normpart);
   hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(256), 0, s, normpart, nblk, out);
-  return hipGetLastError();
-}
-
-hipError_t launch_norm_final(const double* normpart, int64_t n, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(256), 0, s, normpart, (int)blocks_for(n, 256), out);
   return hipGetLastError();
 }
 
