@@ -103,9 +103,9 @@ void init_pool() {
 // costs about 0.3 ms on an idle device and far more when several threads
 // allocate at once, and a build makes dozens of allocations; so blocks the
 // library releases are kept per device and handed to later allocations. Sizes
-// are rounded up to classes of an eighth of a power of two (at least 256 B);
-// an allocation takes the smallest cached block of at least its class and at
-// most 1.5 times it. A released block carries an event recorded on the
+// are rounded up to classes of an eighth of a power of two (at least 256 B)
+// up to 64 MiB and to multiples of 2 MiB above; an allocation takes the
+// smallest cached block of at least its class and at most 1.25 times it. A released block carries an event recorded on the
 // releasing stream (the stream of its last use), and the allocating stream
 // waits for it, so reuse on any stream is ordered after the last use. The
 // cache holds at most a sixteenth of the device memory (the largest blocks go
@@ -126,6 +126,7 @@ MemCache g_mem[MAX_DEVICES];
 
 size_t size_class(size_t b) {
   if (b <= 256) return 256;
+  if (b > ((size_t)64 << 20)) return (b + ((size_t)2 << 20) - 1) / ((size_t)2 << 20) * ((size_t)2 << 20);
   const int lg = 63 - __builtin_clzll((unsigned long long)(b - 1));  // 2^lg <= b-1 < 2^(lg+1)
   const size_t step = (size_t)1 << (lg - 3);
   return (b + step - 1) / step * step;
@@ -171,7 +172,7 @@ void* mem_alloc(size_t b, hipStream_t s, size_t* cls, int* dev, const char* what
     {
       std::lock_guard<std::mutex> lk(c.mu);
       auto it = c.blocks.lower_bound(cl);
-      if (it != c.blocks.end() && it->first <= cl + cl / 2) {
+      if (it != c.blocks.end() && it->first <= cl + cl / 4) {
         blk = it->second;
         c.cached -= blk.bytes;
         c.blocks.erase(it);
