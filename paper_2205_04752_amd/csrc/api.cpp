@@ -25,7 +25,7 @@ namespace hm {
 hipError_t launch_self(const DevGeo&, const SelfTask*, double*, hipStream_t);
 hipError_t launch_near_only(const DevGeo&, const NearTask*, int, double*, hipStream_t);
 hipError_t launch_entries(const DevGeo&, int64_t, const int64_t*, const int64_t*, double*, hipStream_t);
-hipError_t launch_aca(const DevGeo&, const AcaTask*, int, size_t, int32_t*, int32_t*, double*, hipStream_t);
+hipError_t launch_aca(const DevGeo&, const AcaTask*, int, int, size_t, int32_t*, int32_t*, double*, hipStream_t);
 hipError_t launch_compact(const CopyTask*, int, hipStream_t);
 hipError_t launch_to_stream(const StreamTask*, int, double*, hipStream_t);
 hipError_t launch_from_stream(const StreamTask*, int, const double*, hipStream_t);
@@ -913,6 +913,12 @@ void run_aca_pass(hmat* h, const std::vector<int32_t>& fidx, CapFn cap, PanelFn 
     const BlockRec& B = P.blk[h->far_blocks[b]];
     return (int64_t)P.cl[A.t].len + P.cl[A.s].len > (int64_t)P.cl[B.t].len + P.cl[B.s].len;
   });
+  // blocks for the 256-thread kernel first, then the one-wave ones
+  auto big = [&](int32_t f) {
+    const BlockRec& B = P.blk[h->far_blocks[f]];
+    return std::max(P.cl[B.t].len, P.cl[B.s].len) > ACA_SMALL_TRI;
+  };
+  const int n_big = (int)(std::stable_partition(ord.begin(), ord.end(), big) - ord.begin());
   int64_t panel_total = 0, piv_total = 0;
   size_t shmem = 0;
   for (int32_t f : ord) {
@@ -955,7 +961,7 @@ void run_aca_pass(hmat* h, const std::vector<int32_t>& fidx, CapFn cap, PanelFn 
   upload(d_tasks, tasks, s, "ACA tasks");
   EventPair ev;
   check(hipEventRecord(ev.a, s), "event");
-  check(launch_aca(h->G, d_tasks.as<AcaTask>(), (int)tasks.size(), shmem, d_rank.as<int32_t>(),
+  check(launch_aca(h->G, d_tasks.as<AcaTask>(), (int)tasks.size(), n_big, shmem, d_rank.as<int32_t>(),
                    d_stop.as<int32_t>(), d_ratio.as<double>(), s),
         "ACA launch");
   check(hipEventRecord(ev.b, s), "event");
@@ -1695,9 +1701,12 @@ hmat_status amvm_impl(const hmat_mesh* mesh, double E, double nu, double eta, in
         tasks.push_back(t);
       }
       if (!tasks.empty()) {
+        const int n_big = (int)(std::stable_partition(tasks.begin(), tasks.end(), [](const AcaTask& t) {
+                                  return std::max(t.t_len, t.s_len) > ACA_SMALL_TRI;
+                                }) - tasks.begin());
         DevBuf d_tasks;
         upload(d_tasks, tasks, s, "amvm ACA");
-        check(launch_aca(h->G, d_tasks.as<AcaTask>(), (int)tasks.size(), shmem, d_rank.as<int32_t>(),
+        check(launch_aca(h->G, d_tasks.as<AcaTask>(), (int)tasks.size(), n_big, shmem, d_rank.as<int32_t>(),
                          d_stop.as<int32_t>(), d_ratio.as<double>(), s), "amvm ACA");
         std::vector<int32_t> rk(nf), sp(nf);
         check(hipMemcpyAsync(rk.data(), d_rank.p, sizeof(int32_t) * nf, hipMemcpyDeviceToHost, s), "amvm ACA");

@@ -41,6 +41,10 @@ struct DevGeo {
 constexpr int PANEL_ALIGN = 2;       // doubles (16 bytes)
 constexpr int STREAM_ALIGN = 2;      // doubles (16 bytes)
 constexpr int SEG_START_ALIGN = 16;  // doubles (128 bytes)
+// ACA runs one 256-thread workgroup per block, or one wave per block for
+// blocks with at most ACA_SMALL_TRI triangles on either side (the launch
+// takes the large blocks first, then the small ones).
+constexpr int ACA_SMALL_TRI = 64;
 
 // Dense (non-admissible) block at d_off in the near arena (m = 3 t_len rows).
 struct NearTask {

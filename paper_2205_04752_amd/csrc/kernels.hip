@@ -193,7 +193,8 @@ __global__ void k_entries(DevGeo g0, int64_t n, const int64_t* __restrict__ rows
 // sets: a slot set is rewritten only after every thread has passed the
 // barrier of the following reduction, so one barrier per reduction suffices.
 
-constexpr int ACA_T = 256;      // workgroup of the ACA kernel
+constexpr int ACA_T = 256;      // workgroup of the ACA kernel (large blocks)
+constexpr int ACA_SMALL_T = WAVE;  // one wave per small block
 constexpr int NW = 256 / WAVE;  // waves of a 256-thread workgroup
 
 template <int NWV>
@@ -801,16 +802,25 @@ hipError_t launch_entries(const DevGeo& g, int64_t n, const int64_t* rows, const
   return hipGetLastError();
 }
 
-hipError_t launch_aca(const DevGeo& g, const AcaTask* tasks, int ntasks, size_t shmem,
+// tasks[0, n_big): 256-thread workgroups; tasks[n_big, ntasks): blocks with
+// at most ACA_SMALL_TRI triangles per side, one wave each. A one-wave block
+// has no cross-wave barriers, and four times as many blocks fit on a CU.
+hipError_t launch_aca(const DevGeo& g, const AcaTask* tasks, int ntasks, int n_big, size_t shmem,
                       int32_t* rank, int32_t* stop, double* ratio, hipStream_t s) {
   if (shmem > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_aca<ACA_T>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_aca<ACA_SMALL_T>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
     if (e != hipSuccess) return e;
   }
-  if (ntasks > 0)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_aca<ACA_T>), dim3(ntasks), dim3(ACA_T), shmem, s, g, tasks,
+  if (n_big > 0)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_aca<ACA_T>), dim3(n_big), dim3(ACA_T), shmem, s, g, tasks,
                        rank, stop, ratio);
+  if (ntasks > n_big)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_aca<ACA_SMALL_T>), dim3(ntasks - n_big), dim3(ACA_SMALL_T),
+                       shmem, s, g, tasks + n_big, rank, stop, ratio);
   return hipGetLastError();
 }
 
