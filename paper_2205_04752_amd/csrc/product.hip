@@ -47,6 +47,25 @@ __device__ __forceinline__ double2 ld2(const T* p) {
   const typename Pair<T>::type v = ldp(p);
   return make_double2((double)v.x, (double)v.y);
 }
+// The single-vector kernels read each matrix entry once per product:
+// non-temporal loads keep the entries from displacing the vectors and partial
+// sums, which are reused, in the caches (0.667 -> 0.637 ms at icosphere L5).
+// The matrix-core kernels keep plain loads: their lanes share cache lines of
+// the panels, and non-temporal loads made them fetch 28% more.
+template <typename T>
+__device__ __forceinline__ typename Pair<T>::type ldp_nt(const T* p) {
+  typedef T nv2 __attribute__((ext_vector_type(2)));
+  const nv2 v = __builtin_nontemporal_load(reinterpret_cast<const nv2*>(p));
+  typename Pair<T>::type r;
+  r.x = v.x;
+  r.y = v.y;
+  return r;
+}
+template <typename T>
+__device__ __forceinline__ double2 ld2_nt(const T* p) {
+  const typename Pair<T>::type v = ldp_nt(p);
+  return make_double2((double)v.x, (double)v.y);
+}
 
 // Phase A item: z = V_b^T x_s for a group of <= 8 columns; one wave. Lanes
 // cover the aligned row window of V two rows at a time (16-byte loads of V and
@@ -71,7 +90,7 @@ __device__ __forceinline__ void mv_a_item(const MvA& I, const T* __restrict__ fa
       double2 xv[NR], v[CB];
 #pragma unroll
       for (int c = 0; c < CB; c++)  // columns past l1 re-read the last one (not accumulated)
-        v[c] = ld2(V + (size_t)(l0 + min(c, nc - 1)) * I.ld + i);
+        v[c] = ld2_nt(V + (size_t)(l0 + min(c, nc - 1)) * I.ld + i);
 #pragma unroll
       for (int r = 0; r < NR; r++)
         xv[r] = (r < nr) ? *reinterpret_cast<const double2*>(X + r * ldxp + i) : make_double2(0.0, 0.0);
@@ -102,8 +121,9 @@ __device__ __forceinline__ void mv_a_item(const MvA& I, const T* __restrict__ fa
 // side, so each load instruction covers p*len consecutive doubles; the p
 // column groups are then summed with a lane tree and moved to the owning
 // lanes. A segment's last partial batch re-reads in-segment data without
-// accumulating it, so every batch issues its UNR loads back to back. Writes
-// part[chunk][r][128].
+// accumulating it, so every batch issues its UNR loads back to back (skipping
+// those loads instead saves 0.5% in FP64 and costs 70% with FP32 entries).
+// Writes part[chunk][r][128].
 // One short segment (len <= 64 rows, single right-hand side) of a phase-B
 // chunk: g = len/2 lanes per column, p = 64/g >= 2 columns per load. Lane l
 // reads column c0 + t p + l/g, rows 2(l mod g) and +1, at stream offset
@@ -130,7 +150,7 @@ __device__ __forceinline__ void mv_b_grouped(const MvSeg& S, const T* __restrict
     for (int u = 0; u < UNR; u++) {
       const int col = (t + u) * p + q;
       const bool ok = lact && col < ncol;
-      a[u] = ldp(A + (ok ? (int64_t)(t + u) * step + 2 * lane : 0));
+      a[u] = ldp_nt(A + (ok ? (int64_t)(t + u) * step + 2 * lane : 0));
       xv[u] = xs[ok ? col : 0];
       xv[u] = ok ? xv[u] : 0.0;
     }
@@ -190,7 +210,7 @@ __device__ __forceinline__ void mv_b_chunk(const MvChunk& C, int chunk,
 #pragma unroll
       for (int u = 0; u < UNR; u++) {
         const int cu = (u < nc) ? c + u : S.c1 - 1;
-        a[u] = ldp(A + (int64_t)cu * len);
+        a[u] = ldp_nt(A + (int64_t)cu * len);
       }
 #pragma unroll
       for (int u = 0; u < UNR; u++) {
