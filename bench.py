@@ -67,15 +67,77 @@ def cpu_baseline(V, T, wl, x0, seconds_hint: float):
         h.matvec(x0)
         times.append(time.perf_counter() - t)
     med = float(np.median(times))
+    cores = O.num_threads()
+    # the same products on one thread (the paper's timings are serial)
+    O.set_threads(1)
+    times1 = []
+    try:
+        for _ in range(2):
+            t = time.perf_counter()
+            h.matvec(x0)
+            times1.append(time.perf_counter() - t)
+    finally:
+        O.set_threads(cores)
+    med1 = float(np.median(times1))
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {
         "value": round(nbytes / med / 1e9, 3),
         "unit": "GB/s",
-        "cores": O.num_threads(),
+        "cores": cores,
         "kind": "oracle",
+        "cpu_model": model,
+        "value_1_thread": round(nbytes / med1 / 1e9, 3),
         "sample": (f"oracle FP64 H-matrix of the same workload built once ({t_build:.1f} s, "
-                   f"untimed), then {len(times)} single-vector products timed; median "
-                   f"{med * 1e3:.1f} ms per product"),
+                   f"untimed), then {len(times)} single-vector products timed on {cores} "
+                   f"threads (median {med * 1e3:.1f} ms per product) and {len(times1)} on one "
+                   f"thread (median {med1 * 1e3:.1f} ms)"),
     }
+
+
+FP64_VALU_PEAK_TFLOPS = 78.6  # MI355X FP64 vector
+
+
+def build_flops(H, V, T, wl, stats, rec):
+    """Algorithmic FP64 operations of the build's kernels (sqrt and division
+    count as one each) over their event-timed durations, against the FP64
+    vector-ALU peak:
+      K1 near entries: 35 per quadrature point, 7 points per off-diagonal
+        near triangle pair, 48 per self triangle (3 x 16 angular points);
+      ACA: 24 per point x 7 points x k (|t| + |s|) for the entries of the k
+        rows and columns of each admissible block, plus 6 k^2 (|t| + |s|) for
+        the residual updates and the norm recursion.
+    Block ranks come from one more build of the same H-matrix (outside the
+    timed steps; the partition and ranks are the same in every step)."""
+    import ctypes as C
+    import numpy as np
+    g = H.HMatrix(V, T, wl["E"], wl["nu"], wl["eta"], wl["leaf"], wl["eps"])
+    info = np.zeros(8, dtype=np.int32)
+    s1 = s2 = 0.0
+    for b in range(g.info()["n_blocks"]):
+        H.lib().hmat_block(g._h, b, info.ctypes.data, None, None, None, None)
+        if info[4]:
+            k, ts = float(info[5]), float(info[1] + info[3])
+            s1 += k * ts
+            s2 += k * k * ts
+    g.close()
+    nt = len(T)
+    p_off = stats["near_scalars"] / 9 - nt
+    f_near = 35.0 * (7 * p_off + 48 * nt)
+    f_aca = 24.0 * 7 * s1 + 6.0 * s2
+    near_ms = float(np.mean(rec["near_ms"]))
+    aca_ms = float(np.mean(rec["aca_kernel_ms"]))
+    def entry(f, ms):
+        tf = f / (ms * 1e-3) / 1e12
+        return {"gflop": round(f / 1e9, 3), "ms": round(ms, 3), "tflops": round(tf, 3),
+                "peak_tflops": FP64_VALU_PEAK_TFLOPS, "frac": round(tf / FP64_VALU_PEAK_TFLOPS, 4)}
+    return {"k1_near_entries": entry(f_near, near_ms), "aca": entry(f_aca, aca_ms)}
 
 
 def measured_traffic(kernel_tag: str):
@@ -408,16 +470,22 @@ def main():
 
     rec = {"mv_ms": [], "mv16_ms": [], "solve_ms": [], "iters": [], "relres": [], "build_ms": [],
            "phase_ms": np.zeros(4), "phase_calls": 0, "aca_ms": [], "near_ms": [], "mv32_ms": [],
-           "ir_ms": [], "ir_iters": [], "ir_outer": [], "ir_relres": []}
+           "ir_ms": [], "ir_iters": [], "ir_outer": [], "ir_relres": [], "aca_kernel_ms": []}
     stats = {}
 
     def step(k: int, record: bool):
         h = H.HMatrix(V, T, wl["E"], wl["nu"], wl["eta"], wl["leaf"], wl["eps"])
         st = h.info()
         e0, e1, e2, e3 = (torch.cuda.Event(enable_timing=True) for _ in range(4))
+        # each product between events of its own (their latency distribution);
+        # the mean over them is the reported throughput
+        ev_mv = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                 for _ in range(nrhs)]
         e0.record(stream)
         for r in range(nrhs):
+            ev_mv[r][0].record(stream)
             h.matvec(X[r], Y[r])
+            ev_mv[r][1].record(stream)
         e1.record(stream)
         # the same 16 products again with the library's per-phase events (the
         # roofline's kernel durations); the events cost a few us per product,
@@ -451,7 +519,8 @@ def main():
             rec["build_ms"].append(st["t_build_ms"])
             rec["aca_ms"].append(st["t_aca_ms"])
             rec["near_ms"].append(st["t_near_ms"])
-            rec["mv_ms"].append(e0.elapsed_time(e1) / nrhs)
+            rec["aca_kernel_ms"].append(st["t_aca_kernel_ms"])
+            rec["mv_ms"].extend(a.elapsed_time(b) for a, b in ev_mv)
             rec["mv16_ms"].append(e2.elapsed_time(e3))
             rec["phase_ms"] += phases
             rec["phase_calls"] += calls
@@ -504,6 +573,9 @@ def main():
                    "solves_per_step": solves_per_step},
         "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
         "matvec_ms": round(mv_ms, 4),
+        "matvec_p50_ms": round(percentile(rec["mv_ms"], 0.5), 4),
+        "matvec_p99_ms": round(percentile(rec["mv_ms"], 0.99), 4),
+        "matvec_samples": len(rec["mv_ms"]),
         "matvec_bytes": bytes_mv,
         "matvec16_ms": round(mv16_ms, 4),
         "matvec16_gbs": round(bytes_mv16 / (mv16_ms * 1e-3) / 1e9, 2),
@@ -557,6 +629,7 @@ def main():
                            "other_kernels": {n: {"bytes": bb, "ms": round(t, 4),
                                                  "gbs": round(bb / (t * 1e-3) / 1e9, 2)}
                                              for n, bb, t in kernels if n != name}}
+    out["build_flops"] = build_flops(H, V, T, wl, stats, rec)
     if not args.no_cpu_baseline:
         try:
             out["cpu_baseline"] = cpu_baseline(V, T, wl, W.random_x(N, 1, seed=0), args.cpu_seconds)
