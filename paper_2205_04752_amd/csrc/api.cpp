@@ -84,18 +84,34 @@ struct StreamScope {
   ~StreamScope() { g_alloc_stream = prev; }
 };
 
-// Small freed blocks stay cached in the device's default pool (up to 4 GiB);
-// larger releases go back to the device at the next synchronisation.
+// Release threshold of the device's default pool (freed memory beyond it
+// goes back to the device at the next synchronisation): 4 GiB, and 64 GiB
+// (at most a quarter of the device memory) while a request server runs.
+// Handing memory back while other streams run stalled concurrent builds
+// (measured with four to eight at once); a single large build, on the other
+// hand, needs its freed staging back for its arenas. An allocation that runs
+// out of memory empties the pool and the library's caches and tries again
+// (mem_trim).
+std::mutex g_pool_mu;
+int g_pool_servers = 0;  // request servers alive
+
+void apply_pool_threshold() {  // with g_pool_mu held
+  int dev = 0;
+  hipMemPool_t pool = nullptr;
+  size_t fr = 0, tot = 0;
+  if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess &&
+      hipMemGetInfo(&fr, &tot) == hipSuccess) {
+    uint64_t thr = g_pool_servers > 0 ? std::min<uint64_t>((uint64_t)64 << 30, tot / 4) : (uint64_t)4 << 30;
+    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+  }
+  (void)hipGetLastError();
+}
+
 void init_pool() {
   static std::once_flag once;
   std::call_once(once, [] {
-    int dev = 0;
-    hipMemPool_t pool = nullptr;
-    if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
-      uint64_t thr = (uint64_t)4 << 30;
-      (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
-    }
-    (void)hipGetLastError();
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    apply_pool_threshold();
   });
 }
 
@@ -141,7 +157,8 @@ int current_device() {
   return dev < MAX_DEVICES ? dev : -1;
 }
 
-// Frees every cached block of device dev, ordered on stream s.
+// Frees every cached block of device dev, ordered on stream s, and hands the
+// default pool's unused memory back to the device.
 void mem_trim(int dev, hipStream_t s) {
   if (dev < 0) return;
   MemCache& c = g_mem[dev];
@@ -158,6 +175,26 @@ void mem_trim(int dev, hipStream_t s) {
     (void)hipEventDestroy(b.ev);
   }
   (void)hipStreamSynchronize(s);
+  hipMemPool_t pool = nullptr;
+  if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) (void)hipMemPoolTrimTo(pool, 0);
+  (void)hipGetLastError();
+}
+
+// A build whose staging buffers are a large share of the device memory hands
+// them back to the device once freed (after the stream has passed their last
+// use): kept in the pool, they would crowd out the build's next, differently
+// sized arenas. Builds of serving size stay below the bar and trim nothing.
+void trim_pool_after(int64_t freed_bytes, hipStream_t s) {
+  size_t fr = 0, tot = 0;
+  if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+    (void)hipGetLastError();
+    return;
+  }
+  const int dev = current_device();
+  if (dev < 0 || (size_t)freed_bytes <= tot / 16) return;
+  (void)hipStreamSynchronize(s);
+  hipMemPool_t pool = nullptr;
+  if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) (void)hipMemPoolTrimTo(pool, (size_t)4 << 30);
   (void)hipGetLastError();
 }
 
@@ -299,18 +336,18 @@ int32_t kcap_first(double eps) {
 }
 
 // First-pass ACA panels (several GB for a mesh of 10^5 DOF) are not
-// allocated per build: each device keeps one buffer, grown to the largest
-// request up to a sixteenth of the device memory and never shrunk, which is
-// lent to one build at a time. A build that finds it lent, or needs more,
-// uses a buffer of its own, released after its ACA phase. Allocating and
-// releasing buffers of that size on every build stalled builds for up to
-// seconds. The buffer is held until the process ends.
+// allocated per build: each device keeps the panel buffers of finished ACA
+// passes (each up to a sixteenth of the device memory, together up to an
+// eighth; the smallest go first beyond that). A pass borrows the smallest
+// idle buffer that is large enough and allocates a new one only if none is;
+// a pass that needs more than a sixteenth uses a buffer of its own, released
+// after its build's ACA phase. Allocating and releasing buffers of that size
+// on every build stalled builds for up to seconds, the more so with several
+// builds at once. Kept buffers are held until the process ends.
 struct PanelCache {
   std::mutex mu;
-  void* p = nullptr;
-  size_t bytes = 0;
-  size_t keep_max = 0;  // largest buffer kept (0: not known yet)
-  bool lent = false;
+  std::vector<std::pair<void*, size_t>> idle;  // buffers not lent
+  size_t keep_max = 0;                         // largest buffer kept (0: not known yet)
 };
 PanelCache g_panel_cache[MAX_DEVICES];
 
@@ -320,7 +357,6 @@ class PanelLease {
     if (dev < 0 || dev >= MAX_DEVICES) return;
     PanelCache& c = g_panel_cache[dev];
     std::lock_guard<std::mutex> lk(c.mu);
-    if (c.lent) return;
     if (c.keep_max == 0) {
       size_t fr = 0, tot = 0;
       if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
@@ -329,35 +365,45 @@ class PanelLease {
       }
       c.keep_max = tot / 16;
     }
-    c.lent = true;
     cache_ = &c;
-    p_ = c.p;
-    bytes_ = c.bytes;
     keep_max_ = c.keep_max;
   }
   PanelLease(const PanelLease&) = delete;
   PanelLease& operator=(const PanelLease&) = delete;
-  // At least `need` bytes, on the lease's stream.
+  // At least `need` bytes, on the lease's stream. Every kernel that used the
+  // previous buffer of this lease has finished (the build synchronises its
+  // stream after each ACA pass).
   double* get(size_t need) {
+    if (p_ && bytes_ >= need) return static_cast<double*>(p_);
     if (!cache_ || need > keep_max_) {
-      if (cache_ && p_) {  // a large build: the kept buffer's memory goes back too
-        (void)hipFreeAsync(p_, s_);
-        p_ = nullptr;
-        bytes_ = 0;
-      }
       if (own_.bytes < need) own_.alloc(need, "ACA panels");
       return own_.as<double>();
     }
-    if (bytes_ < need) {
-      if (p_) (void)hipFreeAsync(p_, s_);
-      p_ = nullptr;
-      bytes_ = 0;
+    void* had = p_;
+    const size_t had_bytes = bytes_;
+    p_ = nullptr;
+    bytes_ = 0;
+    {
+      std::lock_guard<std::mutex> lk(cache_->mu);
+      if (had) cache_->idle.emplace_back(had, had_bytes);
+      auto best = cache_->idle.end();
+      for (auto it = cache_->idle.begin(); it != cache_->idle.end(); ++it)
+        if (it->second >= need && (best == cache_->idle.end() || it->second < best->second)) best = it;
+      if (best != cache_->idle.end()) {
+        p_ = best->first;
+        bytes_ = best->second;
+        cache_->idle.erase(best);
+      }
+    }
+    if (!p_) {
       hipError_t e = hipMallocAsync(&p_, need, s_);
       if (e == hipErrorOutOfMemory) {
         (void)hipGetLastError();
+        drop_idle(0);
         mem_trim(current_device(), s_);
         e = hipMallocAsync(&p_, need, s_);
       }
+      if (e != hipSuccess) p_ = nullptr;
       check(e, "ACA panels");
       bytes_ = need;
     }
@@ -368,16 +414,39 @@ class PanelLease {
   void give_back() {
     own_.release();
     if (!cache_) return;
-    (void)hipStreamSynchronize(s_);
-    std::lock_guard<std::mutex> lk(cache_->mu);
-    cache_->p = p_;
-    cache_->bytes = bytes_;
-    cache_->lent = false;
+    if (p_) {
+      (void)hipStreamSynchronize(s_);
+      std::lock_guard<std::mutex> lk(cache_->mu);
+      cache_->idle.emplace_back(p_, bytes_);
+    }
+    p_ = nullptr;
+    bytes_ = 0;
+    drop_idle(2 * keep_max_);
     cache_ = nullptr;
   }
   ~PanelLease() { give_back(); }
 
  private:
+  // Frees idle buffers, smallest first, until at most `keep` bytes are idle.
+  void drop_idle(size_t keep) {
+    std::vector<void*> drop;
+    {
+      std::lock_guard<std::mutex> lk(cache_->mu);
+      size_t total = 0;
+      for (const auto& q : cache_->idle) total += q.second;
+      while (total > keep && !cache_->idle.empty()) {
+        auto it = std::min_element(cache_->idle.begin(), cache_->idle.end(),
+                                   [](const std::pair<void*, size_t>& x, const std::pair<void*, size_t>& y) {
+                                     return x.second < y.second;
+                                   });
+        total -= it->second;
+        drop.push_back(it->first);
+        cache_->idle.erase(it);
+      }
+    }
+    for (void* q : drop) (void)hipFreeAsync(q, s_);
+  }
+
   hipStream_t s_;
   PanelCache* cache_ = nullptr;
   void* p_ = nullptr;
@@ -1035,7 +1104,6 @@ void merge_bodies(hmat* h, const std::vector<BodyIn>& in, double eta, int32_t le
 }
 
 thread_local int64_t g_aca_budget = 0;  // per-thread override (hm::set_thread_aca_budget)
-thread_local std::mutex* g_aca_gate = nullptr;  // held around the ACA phase (hm::set_thread_aca_gate)
 
 // Bytes of first-pass ACA panels that one group may hold at once: the
 // calling thread's override if set, else HMAT_ACA_BUDGET_MB, else a quarter
@@ -1177,15 +1245,12 @@ hmat_status build_impl(const std::vector<BodyIn>& in, double eta, int32_t leaf, 
     std::vector<int32_t> capv(nf, 0);
     std::vector<const double*> panel_ptr(nf, nullptr), u_ptr(nf, nullptr), v_ptr(nf, nullptr);
     std::deque<DevBuf> ustage, vstage;
+    int64_t staged_u = 0, staged_v = 0;  // bytes
     const int64_t budget = aca_budget();
     h->aca_passes = 0;
     PanelLease panels1(h->device, s);  // first-pass panels, reused by every group
     BuildTrace tr;
     tr.mark("plan, geometry, K1", s);
-    // concurrent builds of a request server take the ACA phase one at a time
-    // (their host phases still overlap); the gate is released after it
-    std::unique_lock<std::mutex> gate;
-    if (g_aca_gate) gate = std::unique_lock<std::mutex>(*g_aca_gate);
     for (size_t f0 = 0; f0 < nf;) {
       size_t f1 = f0;
       int64_t bytes = 0;
@@ -1242,6 +1307,8 @@ hmat_status build_impl(const std::vector<BodyIn>& in, double eta, int32_t leaf, 
       DevBuf& vs = vstage.back();
       us.alloc(sizeof(double) * std::max<int64_t>(totu, 1), "low-rank factors");
       vs.alloc(sizeof(double) * std::max<int64_t>(totv, 1), "low-rank factors");
+      staged_u += (int64_t)us.bytes;
+      staged_v += (int64_t)vs.bytes;
       std::vector<CopyTask> ct;
       int64_t ou = 0, ov = 0;
       for (int32_t f : grp) {
@@ -1265,10 +1332,6 @@ hmat_status build_impl(const std::vector<BodyIn>& in, double eta, int32_t leaf, 
       tr.mark("ACA group", s);
     }
     panels1.give_back();
-    if (gate.owns_lock()) {
-      check(hipStreamSynchronize(s), "ACA");
-      gate.unlock();
-    }
     const auto t_layout = std::chrono::steady_clock::now();
     if (nf > 0) {
       check(hipMemcpyAsync(h->ratio.data(), d_ratio.p, sizeof(double) * nf, hipMemcpyDeviceToHost, s), "ranks");
@@ -1296,6 +1359,7 @@ hmat_status build_impl(const std::vector<BodyIn>& in, double eta, int32_t leaf, 
     upload(d_ct, ct, s, "compaction tasks");
     check(launch_compact(d_ct.as<CopyTask>(), (int)ct.size(), s), "compaction launch");
     vstage.clear();  // stream-ordered: released after the compaction
+    trim_pool_after(staged_v, s);
     tr.mark("V arena", s);
     // product plan, then U factors and dense blocks into the stream arena
     build_product_plan(h, s);
@@ -1306,6 +1370,7 @@ hmat_status build_impl(const std::vector<BodyIn>& in, double eta, int32_t leaf, 
     check(hipStreamSynchronize(s), "build");
     h->st.t_layout_ms = ms_since(t_layout);
     ustage.clear();
+    trim_pool_after(staged_u, s);
     h->st.t_near_ms = evn.ms();
     h->st.t_aca_ms = eva.ms();
     fill_stats(h);
@@ -1831,7 +1896,12 @@ hmat_status amvm_impl(const hmat_mesh* mesh, double E, double nu, double eta, in
 }  // namespace
 
 void hm::set_thread_aca_budget(int64_t bytes) { g_aca_budget = bytes > 0 ? bytes : 0; }
-void hm::set_thread_aca_gate(std::mutex* gate) { g_aca_gate = gate; }
+
+void hm::serving_pool(bool begin) {
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  g_pool_servers += begin ? 1 : -1;
+  apply_pool_threshold();
+}
 
 extern "C" {
 

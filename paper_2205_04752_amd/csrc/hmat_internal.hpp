@@ -2,7 +2,6 @@
 #pragma once
 
 #include <cstdint>
-#include <mutex>
 #include <string>
 #include <vector>
 
@@ -198,12 +197,10 @@ void gauss_legendre_unit(int n, double* x, double* w);  // rule on [0,1]
 // default, a quarter of the free device memory). Used by the request server,
 // whose workers build concurrently.
 void set_thread_aca_budget(int64_t bytes);
-// Mutex that builds made by the calling thread hold during their ACA phase
-// (null: none). The request server gives all its workers one gate, so ACA
-// kernels, which fill the device and contend for its caches, run one build
-// at a time while the host phases of other builds and other requests'
-// products and solves overlap with them.
-void set_thread_aca_gate(std::mutex* gate);
+// A request server starts (true) or ends (false): while any runs, freed
+// device memory is kept in the pool up to 64 GiB instead of 4 GiB (see
+// init_pool in api.cpp).
+void serving_pool(bool begin);
 void radon7(double bary[7][3], double w[7]);
 
 }  // namespace hm

@@ -69,7 +69,6 @@ struct hmat_server {
   int32_t leaf = 32;
   Clock::time_point t0 = Clock::now();
   std::mutex mu;
-  std::mutex aca_gate;  // one build's ACA phase at a time
   std::condition_variable cv_work, cv_done;
   std::deque<std::shared_ptr<Request>> pending;
   std::map<int64_t, std::shared_ptr<Request>> all;
@@ -186,7 +185,6 @@ void hmat_server::execute(Request& r, hipStream_t s) {
 void hmat_server::run_worker() {
   (void)hipSetDevice(device);
   hm::set_thread_aca_budget(aca_cap);
-  hm::set_thread_aca_gate(&aca_gate);
   hipStream_t s = nullptr;
   if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
     (void)hipGetLastError();
@@ -256,6 +254,7 @@ hmat_status hmat_server_create(int32_t slots, int64_t hbm_budget, double eta, in
   S->aca_cap = std::max<int64_t>((int64_t)256 << 20, std::min<int64_t>((int64_t)2 << 30, S->budget / (4 * slots)));
   S->eta = eta;
   S->leaf = leaf;
+  hm::serving_pool(true);
   try {
     for (int i = 0; i < slots; i++) S->workers.emplace_back([S] { S->run_worker(); });
   } catch (...) {
@@ -266,6 +265,7 @@ hmat_status hmat_server_create(int32_t slots, int64_t hbm_budget, double eta, in
     S->cv_work.notify_all();
     for (auto& t : S->workers) t.join();
     delete S;
+    hm::serving_pool(false);
     return srv_fail(HMAT_ENOMEM, "cannot start worker threads");
   }
   *out = S;
@@ -335,6 +335,7 @@ hmat_status hmat_server_destroy(hmat_server_t S) {
   S->cv_work.notify_all();
   for (auto& t : S->workers) t.join();
   delete S;
+  hm::serving_pool(false);
   return HMAT_OK;
 }
 
