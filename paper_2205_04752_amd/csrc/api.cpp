@@ -703,6 +703,28 @@ void set_chunk_list(hmat* h, int l, int64_t target, hipStream_t s) {
   if (h->d_part.bytes < need) h->d_part.alloc(need, "product workspace");
 }
 
+// Indices of `key` in decreasing key order, equal keys in increasing index
+// order: least-significant-digit radix sort, 16 bits per pass, as many
+// passes as the largest key needs (a comparison sort of the ~10^5 product
+// items took several ms of every build).
+std::vector<int32_t> order_desc_stable(const std::vector<uint64_t>& key) {
+  const size_t n = key.size();
+  std::vector<int32_t> idx(n), tmp(n);
+  for (size_t t = 0; t < n; t++) idx[t] = (int32_t)t;
+  uint64_t kmax = 0;
+  for (uint64_t k : key) kmax = std::max(kmax, k);
+  std::vector<size_t> cnt(65537);
+  for (int sh = 0; sh < 64 && (sh == 0 || (kmax >> sh) != 0); sh += 16) {
+    std::fill(cnt.begin(), cnt.end(), 0);
+    // digit d goes to bucket 65535 - d: larger digits first
+    for (size_t t = 0; t < n; t++) cnt[65535 - ((key[idx[t]] >> sh) & 0xFFFF) + 1]++;
+    for (size_t b = 0; b < 65536; b++) cnt[b + 1] += cnt[b];
+    for (size_t t = 0; t < n; t++) tmp[cnt[65535 - ((key[idx[t]] >> sh) & 0xFFFF)]++] = idx[t];
+    idx.swap(tmp);
+  }
+  return idx;
+}
+
 void build_product_plan(hmat* h, hipStream_t s) {
   const Plan& P = h->plan;
   BuildTrace tr;
@@ -729,12 +751,11 @@ void build_product_plan(hmat* h, hipStream_t s) {
   }
   for (auto& items : items_l) {
     // largest first; equal sizes keep their canonical order
-    std::vector<std::pair<int64_t, int32_t>> key(items.size());
-    for (size_t t = 0; t < items.size(); t++)
-      key[t] = {-(int64_t)items[t].ld * (items[t].l1 - items[t].l0), (int32_t)t};
-    std::sort(key.begin(), key.end());
+    std::vector<uint64_t> key(items.size());
+    for (size_t t = 0; t < items.size(); t++) key[t] = (uint64_t)items[t].ld * (uint64_t)(items[t].l1 - items[t].l0);
+    const std::vector<int32_t> ord = order_desc_stable(key);
     std::vector<MvA> sorted(items.size());
-    for (size_t t = 0; t < items.size(); t++) sorted[t] = items[key[t].second];
+    for (size_t t = 0; t < items.size(); t++) sorted[t] = items[ord[t]];
     items.swap(sorted);
   }
   tr.mark("  plan: phase-A items", s);
@@ -976,12 +997,15 @@ void run_aca_pass(hmat* h, const std::vector<int32_t>& fidx, CapFn cap, PanelFn 
                   DevBuf& d_rank, DevBuf& d_stop, DevBuf& d_ratio,
                   std::vector<const double*>& panel_ptr, hipStream_t s) {
   const Plan& P = h->plan;
-  std::vector<int32_t> ord(fidx);
-  std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) {
-    const BlockRec& A = P.blk[h->far_blocks[a]];
-    const BlockRec& B = P.blk[h->far_blocks[b]];
-    return (int64_t)P.cl[A.t].len + P.cl[A.s].len > (int64_t)P.cl[B.t].len + P.cl[B.s].len;
-  });
+  // largest blocks first (|t| + |s|), equal sizes in the given order
+  std::vector<uint64_t> size(fidx.size());
+  for (size_t q = 0; q < fidx.size(); q++) {
+    const BlockRec& B = P.blk[h->far_blocks[fidx[q]]];
+    size[q] = (uint64_t)P.cl[B.t].len + (uint64_t)P.cl[B.s].len;
+  }
+  const std::vector<int32_t> by_size = order_desc_stable(size);
+  std::vector<int32_t> ord(fidx.size());
+  for (size_t q = 0; q < fidx.size(); q++) ord[q] = fidx[by_size[q]];
   // blocks for the 256-thread kernel first, then the one-wave ones
   auto big = [&](int32_t f) {
     const BlockRec& B = P.blk[h->far_blocks[f]];
