@@ -1772,7 +1772,16 @@ hmat_status amvm_impl(const hmat_mesh* mesh, double E, double nu, double eta, in
         for (int64_t r = 0; r < M[f]; r++) rblk[fill[R0[f] + r]++] = (int32_t)f;
     }
     std::vector<char> adv(nf, 1);  // blocks whose look-ahead must be computed
-    std::vector<double> d(std::max<int64_t>(dtot, 1)), e(N), rest(N);
+    // the look-ahead contributions come back every round: pinned host memory
+    struct Pinned {
+      double* p = nullptr;
+      ~Pinned() {
+        if (p) (void)hipHostFree(p);
+      }
+    } d_host;
+    check(hipHostMalloc((void**)&d_host.p, sizeof(double) * std::max<int64_t>(dtot, 1)), "amvm host buffer");
+    double* const d = d_host.p;
+    std::vector<double> e(N), rest(N);
     std::vector<int64_t> rows(N);
     std::vector<char> marked(nf, 0), has_d(nf, 0);
     int rounds = 0;
@@ -1825,7 +1834,7 @@ hmat_status amvm_impl(const hmat_mesh* mesh, double E, double nu, double eta, in
         upload(d_t, dts, s, "amvm deltas");
         check(launch_lowrank_delta(d_t.as<DeltaTask>(), (int)dts.size(), xp.as<double>(), d_d.as<double>(), s),
               "amvm deltas");
-        check(hipMemcpyAsync(d.data(), d_d.p, sizeof(double) * dtot, hipMemcpyDeviceToHost, s), "amvm deltas");
+        check(hipMemcpyAsync(d, d_d.p, sizeof(double) * dtot, hipMemcpyDeviceToHost, s), "amvm deltas");
         check(hipStreamSynchronize(s), "amvm deltas");
       }
       // (c) the estimator
@@ -1842,14 +1851,25 @@ hmat_status amvm_impl(const hmat_mesh* mesh, double E, double nu, double eta, in
       if (dts.empty() || gamma <= tol * std::sqrt(bh2) || rounds >= max_rounds) break;
       // (d) marking along rows of decreasing error
       const double tau = (1.0 - theta) * gamma / std::sqrt((double)P.csp * (double)N * (double)N);
+      // rows come off a max-heap keyed by (|e_i| descending, i ascending): the
+      // order of a stable sort by |e_i|, but marking usually stops after a
+      // small share of the rows, so only those are ordered
+      const auto lower = [&](int64_t a, int64_t c) {
+        const double fa = std::fabs(e[a]), fc = std::fabs(e[c]);
+        return fa < fc || (fa == fc && a > c);
+      };
       std::iota(rows.begin(), rows.end(), (int64_t)0);
-      std::stable_sort(rows.begin(), rows.end(), [&](int64_t a, int64_t c) { return std::fabs(e[a]) > std::fabs(e[c]); });
+      std::make_heap(rows.begin(), rows.end(), lower);
+      auto heap_end = rows.end();
       rest = e;
       double rn2 = g2;
       std::fill(marked.begin(), marked.end(), 0);
       std::vector<int32_t> Pk;
       const double goal = (1.0 - theta) * gamma;
-      for (int64_t i : rows) {
+      while (heap_end != rows.begin()) {
+        std::pop_heap(rows.begin(), heap_end, lower);
+        --heap_end;
+        const int64_t i = *heap_end;
         bool added = false;
         for (int64_t q = rptr[i]; q < rptr[i + 1]; q++) {
           const int32_t f = rblk[q];
