@@ -703,28 +703,6 @@ void set_chunk_list(hmat* h, int l, int64_t target, hipStream_t s) {
   if (h->d_part.bytes < need) h->d_part.alloc(need, "product workspace");
 }
 
-// Indices of `key` in decreasing key order, equal keys in increasing index
-// order: least-significant-digit radix sort, 16 bits per pass, as many
-// passes as the largest key needs (a comparison sort of the ~10^5 product
-// items took several ms of every build).
-std::vector<int32_t> order_desc_stable(const std::vector<uint64_t>& key) {
-  const size_t n = key.size();
-  std::vector<int32_t> idx(n), tmp(n);
-  for (size_t t = 0; t < n; t++) idx[t] = (int32_t)t;
-  uint64_t kmax = 0;
-  for (uint64_t k : key) kmax = std::max(kmax, k);
-  std::vector<size_t> cnt(65537);
-  for (int sh = 0; sh < 64 && (sh == 0 || (kmax >> sh) != 0); sh += 16) {
-    std::fill(cnt.begin(), cnt.end(), 0);
-    // digit d goes to bucket 65535 - d: larger digits first
-    for (size_t t = 0; t < n; t++) cnt[65535 - ((key[idx[t]] >> sh) & 0xFFFF) + 1]++;
-    for (size_t b = 0; b < 65536; b++) cnt[b + 1] += cnt[b];
-    for (size_t t = 0; t < n; t++) tmp[cnt[65535 - ((key[idx[t]] >> sh) & 0xFFFF)]++] = idx[t];
-    idx.swap(tmp);
-  }
-  return idx;
-}
-
 void build_product_plan(hmat* h, hipStream_t s) {
   const Plan& P = h->plan;
   BuildTrace tr;

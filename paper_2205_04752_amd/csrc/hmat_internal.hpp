@@ -202,5 +202,8 @@ void set_thread_aca_budget(int64_t bytes);
 // init_pool in api.cpp).
 void serving_pool(bool begin);
 void radon7(double bary[7][3], double w[7]);
+// Indices of `key` in decreasing key order, equal keys in increasing index
+// order (stable radix sort; planner.cpp).
+std::vector<int32_t> order_desc_stable(const std::vector<uint64_t>& key);
 
 }  // namespace hm

@@ -102,6 +102,28 @@ double dist(const Cluster& a, const Cluster& b) {
 
 }  // namespace
 
+// Indices of `key` in decreasing key order, equal keys in increasing index
+// order: least-significant-digit radix sort, 16 bits per pass, as many
+// passes as the largest key needs (a comparison sort of the ~10^5 product
+// items took several ms of every build).
+std::vector<int32_t> order_desc_stable(const std::vector<uint64_t>& key) {
+  const size_t n = key.size();
+  std::vector<int32_t> idx(n), tmp(n);
+  for (size_t t = 0; t < n; t++) idx[t] = (int32_t)t;
+  uint64_t kmax = 0;
+  for (uint64_t k : key) kmax = std::max(kmax, k);
+  std::vector<size_t> cnt(65537);
+  for (int sh = 0; sh < 64 && (sh == 0 || (kmax >> sh) != 0); sh += 16) {
+    std::fill(cnt.begin(), cnt.end(), 0);
+    // digit d goes to bucket 65535 - d: larger digits first
+    for (size_t t = 0; t < n; t++) cnt[65535 - ((key[idx[t]] >> sh) & 0xFFFF) + 1]++;
+    for (size_t b = 0; b < 65536; b++) cnt[b + 1] += cnt[b];
+    for (size_t t = 0; t < n; t++) tmp[cnt[65535 - ((key[idx[t]] >> sh) & 0xFFFF)]++] = idx[t];
+    idx.swap(tmp);
+  }
+  return idx;
+}
+
 void make_plan(const hmat_mesh* m, double eta, int32_t leaf, Plan& plan) {
   const int32_t nt = m->n_triangles;
   plan.nt = nt;
@@ -184,11 +206,16 @@ void make_plan(const hmat_mesh* m, double eta, int32_t leaf, Plan& plan) {
       todo.push_back({T.son1, S.son1});
     }
   }
-  std::sort(plan.blk.begin(), plan.blk.end(), [&](const BlockRec& a, const BlockRec& b) {
-    const int32_t ar = plan.cl[a.t].off, br = plan.cl[b.t].off;
-    if (ar != br) return ar < br;
-    return plan.cl[a.s].off < plan.cl[b.s].off;
-  });
+  // canonical order: by row offset, then column offset (the pairs are unique)
+  {
+    std::vector<uint64_t> key(plan.blk.size());
+    for (size_t q = 0; q < plan.blk.size(); q++)
+      key[q] = ~(((uint64_t)(uint32_t)plan.cl[plan.blk[q].t].off << 32) | (uint32_t)plan.cl[plan.blk[q].s].off);
+    const std::vector<int32_t> ord = order_desc_stable(key);  // descending complement = ascending
+    std::vector<BlockRec> sorted(plan.blk.size());
+    for (size_t q = 0; q < plan.blk.size(); q++) sorted[q] = plan.blk[ord[q]];
+    plan.blk.swap(sorted);
+  }
   std::vector<int32_t> nr(plan.cl.size(), 0), nc(plan.cl.size(), 0);
   for (const BlockRec& b : plan.blk) {
     nr[b.t]++;
