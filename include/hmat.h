@@ -32,6 +32,13 @@
  *     work of a call is enqueued on that stream.
  *   - Thread safety: different handles may be used from different threads;
  *     calls on one handle must be serialised by the caller.
+ *   - Device memory: buffers the library releases (hmat_free, the staging of
+ *     a build) are kept for later builds and calls rather than handed back:
+ *     a cache of released buffers (up to 1/16 of the device memory), idle
+ *     ACA panel buffers (up to 1/8) and the stream-ordered pool's retained
+ *     memory (4 GiB; 64 GiB while a request server runs). Allocating and
+ *     releasing buffers of that size per build stalled builds, the more so
+ *     with several at once. hmat_release_memory hands all of it back.
  */
 #ifndef HMAT_H
 #define HMAT_H
@@ -226,8 +233,18 @@ hmat_status hmat_solve_ir(hmat_t h, const double* b, double* x, double tol, int3
 hmat_status hmat_info(hmat_t h, hmat_stats* st);
 
 /* hmat_free -- release all device and host memory of h (NULL is a no-op).
- * Synchronises the device work of h first. */
+ * Synchronises the device work of h first. The device memory goes to the
+ * library's caches (see the conventions above), not back to the device. */
 hmat_status hmat_free(hmat_t h);
+
+/* hmat_release_memory -- hand the device memory the library keeps for reuse
+ * back to the device: the cache of released buffers, the idle ACA panel
+ * buffers and the unused memory of the current device's stream-ordered pool.
+ * The frees are ordered on hip_stream, which is synchronised before return.
+ * Memory of live handles is untouched. Must not run while another thread
+ * builds on the same device (its panel buffers are not idle then and stay
+ * kept). Errors: none beyond device errors (HMAT_EDEVICE). */
+hmat_status hmat_release_memory(void* hip_stream);
 
 /* Thread-local description of the last failure on the calling thread. */
 const char* hmat_last_error(void);

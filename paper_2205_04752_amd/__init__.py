@@ -13,7 +13,7 @@ import os
 
 import numpy as np
 
-__all__ = ["lib", "HMatrix", "Server", "plan", "amvm", "HmatError", "LIB_PATH"]
+__all__ = ["lib", "HMatrix", "Server", "plan", "amvm", "release_memory", "HmatError", "LIB_PATH"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhmat.so")
 
@@ -79,7 +79,7 @@ EXPORTS = ["hmat_build", "hmat_build_batch", "hmat_bodies", "hmat_matvec", "hmat
            "hmat_solve", "hmat_solve_ir", "hmat_set_precision", "hmat_info", "hmat_free",
            "hmat_last_error", "hmat_plan", "hmat_block", "hmat_entries", "hmat_set_factors",
            "hmat_profile", "hmat_tune", "hmat_matvec_graph", "hmat_amvm", "hmat_server_create", "hmat_server_submit", "hmat_server_wait",
-           "hmat_server_destroy", "hmat_server_last_error"]
+           "hmat_server_destroy", "hmat_server_last_error", "hmat_release_memory"]
 
 _lib = None
 
@@ -104,6 +104,7 @@ def lib():
     L.hmat_matvec_ex.argtypes = [vp, i32, i32, vp, i64, vp, i64, vp]
     L.hmat_info.argtypes = [vp, C.POINTER(_Stats)]
     L.hmat_free.argtypes = [vp]
+    L.hmat_release_memory.argtypes = [vp]
     L.hmat_last_error.restype = C.c_char_p
     L.hmat_plan.argtypes = [C.POINTER(_Mesh), dbl, i32, vp, C.POINTER(i32), vp]
     L.hmat_block.argtypes = [vp, i32, vp, vp, vp, vp, vp]
@@ -156,6 +157,12 @@ def _dev_ptr(t, n_dof, name):
     if t.dim() != 2 or t.shape[1] != n_dof or t.stride(1) != 1:
         raise ValueError(f"{name} must be [nrhs, {n_dof}] with unit column stride")
     return t, t.data_ptr(), t.stride(0)
+
+
+def release_memory(stream=None) -> None:
+    """Hand the device memory the library keeps for reuse back to the device
+    (hmat_release_memory); live handles keep theirs."""
+    _check(lib().hmat_release_memory(_stream(stream)))
 
 
 def plan(vertices, triangles, eta: float = 2.0, leaf: int = 32):

@@ -2300,6 +2300,27 @@ hmat_status hmat_info(hmat_t h, hmat_stats* st) {
   return HMAT_OK;
 }
 
+hmat_status hmat_release_memory(void* hip_stream) {
+  const hipStream_t s = (hipStream_t)hip_stream;
+  StreamScope scope(s);
+  const int dev = current_device();
+  if (dev < 0) return fail(HMAT_EDEVICE, "no HIP device");
+  std::vector<void*> idle;
+  {
+    std::lock_guard<std::mutex> lk(g_panel_cache[dev].mu);
+    for (const auto& q : g_panel_cache[dev].idle) idle.push_back(q.first);
+    g_panel_cache[dev].idle.clear();
+  }
+  for (void* q : idle) (void)hipFreeAsync(q, s);
+  const hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(HMAT_EDEVICE, std::string("release memory: ") + hipGetErrorString(e));
+  }
+  mem_trim(dev, s);  // cached blocks, then the pool
+  return HMAT_OK;
+}
+
 hmat_status hmat_free(hmat_t h) {
   if (!h) return HMAT_OK;
   const hipStream_t s = h->last_stream;

@@ -2,15 +2,16 @@
 
 The library keeps released device buffers and lends them to later
 allocations on any stream (ordered by an event recorded at the release), and
-keeps one first-pass ACA panel buffer per device that one build at a time
-borrows. Checked here:
+keeps a pool of first-pass ACA panel buffers per device that concurrent
+builds borrow. Checked here:
   * two threads, each on its own stream, build and multiply a sequence of
     meshes of different sizes and free each handle right away (so buffers
     pass between the threads' streams); every product equals the one from a
     single-threaded run bit for bit, and so do the ranks;
   * products issued right after the build on a side stream, and handles
     freed while the other thread's kernels run, leave the results unchanged
-    over three rounds.
+    over three rounds;
+  * hmat_release_memory returns the kept memory to the device.
 """
 import threading
 
@@ -73,3 +74,26 @@ def test_threads_and_streams_share_buffers():
         # thread b ran the meshes in reverse order with reversed eps: compare per mesh
         for (yb, rb), (yr, rr) in zip(out["b"], ref["b"][::-1]):
             assert rb == rr and np.array_equal(yb, yr)
+
+
+def test_release_memory_returns_cached_memory():
+    """hmat_release_memory hands the cached buffers back to the device (free
+    device memory rises by at least half of a freed handle's bytes) and later
+    builds give the same products bit for bit."""
+    H = _H()
+    V, T = W.icosphere(4)
+    N = 3 * len(T)
+    x = torch.from_numpy(W.random_x(N, 2, seed=5)).cuda()
+    g = H.HMatrix(V, T, 1.0, 0.3, 2.0, 32, 1e-6)
+    held = g.info()["device_bytes"]
+    y0 = g.matvec(x).cpu()
+    g.close()
+    torch.cuda.synchronize()
+    free_before, _ = torch.cuda.mem_get_info()
+    H.release_memory()
+    free_after, _ = torch.cuda.mem_get_info()
+    assert free_after - free_before >= held // 2, (free_before, free_after, held)
+    g = H.HMatrix(V, T, 1.0, 0.3, 2.0, 32, 1e-6)
+    y1 = g.matvec(x).cpu()
+    g.close()
+    assert torch.equal(y0, y1)
