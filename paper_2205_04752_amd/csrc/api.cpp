@@ -25,7 +25,8 @@ namespace hm {
 hipError_t launch_self(const DevGeo&, const SelfTask*, double*, hipStream_t);
 hipError_t launch_near_only(const DevGeo&, const NearTask*, int, double*, hipStream_t);
 hipError_t launch_entries(const DevGeo&, int64_t, const int64_t*, const int64_t*, double*, hipStream_t);
-hipError_t launch_aca(const DevGeo&, const AcaTask*, int, int, size_t, int32_t*, int32_t*, double*, hipStream_t);
+hipError_t launch_aca(const DevGeo&, const AcaTask*, int, int, size_t, size_t, int32_t*, int32_t*, double*,
+                      hipStream_t);
 hipError_t launch_compact(const CopyTask*, int, hipStream_t);
 hipError_t launch_to_stream(const StreamTask*, int, double*, hipStream_t);
 hipError_t launch_from_stream(const StreamTask*, int, const double*, hipStream_t);
@@ -991,16 +992,18 @@ void run_aca_pass(hmat* h, const std::vector<int32_t>& fidx, CapFn cap, PanelFn 
   };
   const int n_big = (int)(std::stable_partition(ord.begin(), ord.end(), big) - ord.begin());
   int64_t panel_total = 0, piv_total = 0;
-  size_t shmem = 0;
-  for (int32_t f : ord) {
-    const int32_t b = h->far_blocks[f];
+  size_t shmem[2] = {0, 0};  // 256-thread part, one-wave part
+  for (size_t q = 0; q < ord.size(); q++) {
+    const int32_t b = h->far_blocks[ord[q]];
     const int64_t m = block_m(h, b), n = block_n(h, b);
-    const int32_t kc = cap(f);
+    const int32_t kc = cap(ord[q]);
     panel_total += (m + n) * kc;
     piv_total += 2 * (int64_t)kc;
-    shmem = std::max(shmem, (size_t)kc * 8 + (size_t)((m + 31) / 32) * 4);
+    size_t& sh = shmem[(int)q < n_big ? 0 : 1];
+    sh = std::max(sh, aca_shmem(kc, m, n));
   }
-  if (shmem > 160 * 1024) throw HipError{HMAT_ENOTSUP, "ACA panel row exceeds LDS capacity"};
+  if (std::max(shmem[0], shmem[1]) > 160 * 1024)
+    throw HipError{HMAT_ENOTSUP, "ACA panel row exceeds LDS capacity"};
   double* const panels = get_panels(sizeof(double) * std::max<int64_t>(panel_total, 1));
   piv.alloc(sizeof(int32_t) * piv_total, "ACA pivots");
   std::vector<AcaTask> tasks;
@@ -1032,8 +1035,8 @@ void run_aca_pass(hmat* h, const std::vector<int32_t>& fidx, CapFn cap, PanelFn 
   upload(d_tasks, tasks, s, "ACA tasks");
   EventPair ev;
   check(hipEventRecord(ev.a, s), "event");
-  check(launch_aca(h->G, d_tasks.as<AcaTask>(), (int)tasks.size(), n_big, shmem, d_rank.as<int32_t>(),
-                   d_stop.as<int32_t>(), d_ratio.as<double>(), s),
+  check(launch_aca(h->G, d_tasks.as<AcaTask>(), (int)tasks.size(), n_big, shmem[0], shmem[1],
+                   d_rank.as<int32_t>(), d_stop.as<int32_t>(), d_ratio.as<double>(), s),
         "ACA launch");
   check(hipEventRecord(ev.b, s), "event");
   check(hipStreamSynchronize(s), "ACA");
@@ -1734,10 +1737,13 @@ hmat_status amvm_impl(const hmat_mesh* mesh, double E, double nu, double eta, in
         t.zbits = zbits.as<uint32_t>() + zoff[f];
       }
     }
-    size_t shmem = 0;
-    for (size_t f = 0; f < nf; f++)
-      shmem = std::max(shmem, (size_t)kcap[f] * 8 + (size_t)((M[f] + 31) / 32) * 4);
-    if (shmem > 160 * 1024) throw HipError{HMAT_ENOTSUP, "ACA panel row exceeds LDS capacity"};
+    size_t shmem[2] = {0, 0};  // 256-thread blocks, one-wave blocks
+    for (size_t f = 0; f < nf; f++) {
+      const bool small = std::max(base[f].t_len, base[f].s_len) <= ACA_SMALL_TRI;
+      shmem[small ? 1 : 0] = std::max(shmem[small ? 1 : 0], aca_shmem(kcap[f], M[f], Nn[f]));
+    }
+    if (std::max(shmem[0], shmem[1]) > 160 * 1024)
+      throw HipError{HMAT_ENOTSUP, "ACA panel row exceeds LDS capacity"};
     // rows -> admissible blocks containing them (canonical order)
     std::vector<int64_t> rptr(N + 1, 0);
     for (size_t f = 0; f < nf; f++)
@@ -1782,7 +1788,8 @@ hmat_status amvm_impl(const hmat_mesh* mesh, double E, double nu, double eta, in
                                 }) - tasks.begin());
         DevBuf d_tasks;
         upload(d_tasks, tasks, s, "amvm ACA");
-        check(launch_aca(h->G, d_tasks.as<AcaTask>(), (int)tasks.size(), n_big, shmem, d_rank.as<int32_t>(),
+        check(launch_aca(h->G, d_tasks.as<AcaTask>(), (int)tasks.size(), n_big, shmem[0], shmem[1],
+                         d_rank.as<int32_t>(),
                          d_stop.as<int32_t>(), d_ratio.as<double>(), s), "amvm ACA");
         std::vector<int32_t> rk(nf), sp(nf);
         check(hipMemcpyAsync(rk.data(), d_rank.p, sizeof(int32_t) * nf, hipMemcpyDeviceToHost, s), "amvm ACA");

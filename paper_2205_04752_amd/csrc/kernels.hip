@@ -348,7 +348,9 @@ __device__ __forceinline__ double lane_dot(const double* x, const double* y, int
 //   panel capacity reached (4: the host re-runs the block with a larger capacity),
 //   no finite pivot (5: non-finite entries; reported as an error).
 // Panels live in global memory (column-major U m x kcap, V n x kcap); the
-// coefficient row U[i, 0:k] / V[j, 0:k] and the set Z are staged in LDS.
+// coefficient row U[i, 0:k] / V[j, 0:k] and the set Z are staged in LDS, and
+// for m + n <= ACA_STAGE_MAX also the newest row v_k and column u_k (written
+// to both; the step's later reads of them use the LDS copy).
 template <int TPB>
 __global__ __launch_bounds__(TPB) void k_aca(DevGeo g0, const AcaTask* __restrict__ tasks,
                                                int32_t* __restrict__ rank_out,
@@ -367,6 +369,9 @@ __global__ __launch_bounds__(TPB) void k_aca(DevGeo g0, const AcaTask* __restric
   double* coef = sh;
   uint32_t* Z = reinterpret_cast<uint32_t*>(sh + kcap);
   const int zw = (m + 31) >> 5;
+  const bool stage = m + n <= ACA_STAGE_MAX;
+  double* const vs = sh + kcap + ((zw + 1) >> 1);  // staged v_k (n), then u_k (m)
+  double* const us = vs + n;
   const int nt = g.nt;
   int ph = 0, k = 0, nZ = 0, i = 0, stop = 0, visited = 0, pending = 0;
   double S2 = 0.0, ratio = 0.0;
@@ -392,6 +397,7 @@ __global__ __launch_bounds__(TPB) void k_aca(DevGeo g0, const AcaTask* __restric
     __syncthreads();
     // row i of the remainder into V[:, k]
     double* __restrict__ vk = V + (size_t)k * n;
+    double* const vr = stage ? vs : vk;  // where this step reads v_k
     const int pi = T.t_off + i / 3, ai = i % 3;
     const double x0 = g.cen[pi], x1 = g.cen[nt + pi], x2 = g.cen[2 * nt + pi];
     double mx = 0.0;
@@ -402,6 +408,11 @@ __global__ __launch_bounds__(TPB) void k_aca(DevGeo g0, const AcaTask* __restric
       vk[3 * q] = e0;
       vk[3 * q + 1] = e1;
       vk[3 * q + 2] = e2;
+      if (stage) {
+        vs[3 * q] = e0;
+        vs[3 * q + 1] = e1;
+        vs[3 * q + 2] = e2;
+      }
       mx = fmax(mx, fmax(fabs(e0), fmax(fabs(e1), fabs(e2))));
     }
     mx = blk_max(mx, R, ph);
@@ -441,7 +452,7 @@ __global__ __launch_bounds__(TPB) void k_aca(DevGeo g0, const AcaTask* __restric
     const double thr = (1.0 - 1e-10) * mx;
     int cand = INT_MAX;
     for (int c = tid; c < n; c += TPB)
-      if (fabs(vk[c]) >= thr) {
+      if (fabs(vr[c]) >= thr) {
         cand = c;
         break;
       }
@@ -450,18 +461,20 @@ __global__ __launch_bounds__(TPB) void k_aca(DevGeo g0, const AcaTask* __restric
       stop = 5;
       break;
     }
-    const double piv = vk[j];
+    const double piv = vr[j];
     __syncthreads();  // every thread holds piv before vk is normalised in place
     double vv = 0.0;
     for (int c = tid; c < n; c += TPB) {
-      const double v = vk[c] / piv;
+      const double v = vr[c] / piv;
       vk[c] = v;
+      if (stage) vs[c] = v;
       vv += v * v;
     }
     for (int l = tid; l < k; l += TPB) coef[l] = V[j + (size_t)l * n];
     __syncthreads();
     // column j of the remainder into U[:, k] (S is symmetric: A[3p+a, 3q+b] = S_ba)
     double* __restrict__ uk = U + (size_t)k * m;
+    double* const ur = stage ? us : uk;  // where this step reads u_k
     const int qj = T.s_off + j / 3, bj = j % 3;
     double uu = 0.0;
     for (int p = tid; p < T.t_len; p += TPB) {
@@ -472,6 +485,11 @@ __global__ __launch_bounds__(TPB) void k_aca(DevGeo g0, const AcaTask* __restric
       uk[3 * p] = e0;
       uk[3 * p + 1] = e1;
       uk[3 * p + 2] = e2;
+      if (stage) {
+        us[3 * p] = e0;
+        us[3 * p + 1] = e1;
+        us[3 * p + 2] = e2;
+      }
       uu += e0 * e0 + e1 * e1 + e2 * e2;
     }
     blk_sum2(uu, vv, R, ph);
@@ -480,7 +498,7 @@ __global__ __launch_bounds__(TPB) void k_aca(DevGeo g0, const AcaTask* __restric
     for (int l = wv; l < k; l += NWV) {
       const double* ul = U + (size_t)l * m;
       const double* vl = V + (size_t)l * n;
-      const double a = lane_dot(ul, uk, m, lane), b = lane_dot(vl, vk, n, lane);
+      const double a = lane_dot(ul, ur, m, lane), b = lane_dot(vl, vr, n, lane);
       cr += wave_sum(a) * wave_sum(b);
     }
     double cross = (lane == 0) ? cr : 0.0, dummy = 0.0;
@@ -507,7 +525,7 @@ __global__ __launch_bounds__(TPB) void k_aca(DevGeo g0, const AcaTask* __restric
       i = class_probe<TPB>(Z, m, visited, R, ph);
       if (i < 0) { stop = 1; break; }
     } else {
-      i = argmax_free<TPB>(uk, m, Z, R, ph);
+      i = argmax_free<TPB>(ur, m, Z, R, ph);
       if (i >= m) {
         stop = 5;
         break;
@@ -805,22 +823,25 @@ hipError_t launch_entries(const DevGeo& g, int64_t n, const int64_t* rows, const
 // tasks[0, n_big): 256-thread workgroups; tasks[n_big, ntasks): blocks with
 // at most ACA_SMALL_TRI triangles per side, one wave each. A one-wave block
 // has no cross-wave barriers, and four times as many blocks fit on a CU.
-hipError_t launch_aca(const DevGeo& g, const AcaTask* tasks, int ntasks, int n_big, size_t shmem,
-                      int32_t* rank, int32_t* stop, double* ratio, hipStream_t s) {
-  if (shmem > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_aca<ACA_T>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-    if (e == hipSuccess)
-      e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_aca<ACA_SMALL_T>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+// shmem_big / shmem_small: the largest aca_shmem of each part's tasks.
+hipError_t launch_aca(const DevGeo& g, const AcaTask* tasks, int ntasks, int n_big, size_t shmem_big,
+                      size_t shmem_small, int32_t* rank, int32_t* stop, double* ratio, hipStream_t s) {
+  if (shmem_big > 64 * 1024) {
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_aca<ACA_T>),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem_big);
+    if (e != hipSuccess) return e;
+  }
+  if (shmem_small > 64 * 1024) {
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_aca<ACA_SMALL_T>),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem_small);
     if (e != hipSuccess) return e;
   }
   if (n_big > 0)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_aca<ACA_T>), dim3(n_big), dim3(ACA_T), shmem, s, g, tasks,
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_aca<ACA_T>), dim3(n_big), dim3(ACA_T), shmem_big, s, g, tasks,
                        rank, stop, ratio);
   if (ntasks > n_big)
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_aca<ACA_SMALL_T>), dim3(ntasks - n_big), dim3(ACA_SMALL_T),
-                       shmem, s, g, tasks + n_big, rank, stop, ratio);
+                       shmem_small, s, g, tasks + n_big, rank, stop, ratio);
   return hipGetLastError();
 }
 
