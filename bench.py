@@ -158,6 +158,88 @@ def measured_traffic(kernel_tag: str):
     return None
 
 
+def bench_precision(args):
+    """Precision workload: the 10 x 1 x 1 box (108864 triangles, 326592 DOF),
+    Dirichlet problem only (single-layer operator; the traction rows would need
+    the adjoint double-layer operator). FP64 build at eps = 1e-7; GMRES(50) to
+    relative residual 1e-8 with FP64 entries, against FP32 copies of the entries
+    with FP64 iterative refinement to the same FP64 residual. Value: solves/s of
+    the refinement form."""
+    import numpy as np
+    import torch
+    import workloads as W
+    import paper_2205_04752_amd as H
+
+    wl = W.workload_c3()
+    V, T = wl["vertices"], wl["triangles"]
+    N = 3 * len(T)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    n_solves = max(1, args.solves // 2)
+    G = [torch.from_numpy(W.smooth_rhs(V, T, seed=1 + i)).to(dev) for i in range(n_solves)]
+    X = torch.from_numpy(W.random_x(N, 1, seed=0)).to(dev)
+    Y = torch.empty_like(X)
+    print("precision-box: build", file=sys.stderr, flush=True)
+    h = H.HMatrix(V, T, wl["E"], wl["nu"], wl["eta"], wl["leaf"], wl["eps"])
+    st = h.info()
+
+    def product_ms(prec, reps=10):
+        for _ in range(2):
+            h.matvec(X, Y, precision=prec)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            h.matvec(X, Y, precision=prec)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    stored = st["far_u_scalars"] + st["far_v_scalars"] + st["near_scalars"]
+    mv64 = product_ms(0)
+    print("precision-box: FP64 solves", file=sys.stderr, flush=True)
+    sol64, s64 = [], []
+    for g in G:
+        x, info = h.solve(g, tol=1e-8, restart=50, maxit=20000)
+        sol64.append(x.clone())
+        s64.append(info)
+    h.set_precision(1)
+    mv32 = product_ms(1)
+    print("precision-box: refinement solves", file=sys.stderr, flush=True)
+    s32, diff = [], []
+    for g, x64 in zip(G, sol64):
+        x, info = h.solve_ir(g, tol=1e-8, restart=50, maxit=20000, inner_precision=1, inner_tol=1e-6)
+        s32.append(info)
+        diff.append(float(torch.linalg.norm(x - x64) / torch.linalg.norm(x64)))
+    h.close()
+
+    def rate(infos):
+        return round(1e3 / float(np.mean([i["time_ms"] for i in infos])), 4)
+
+    out = {
+        "metric": "precision: GMRES(50) solves/s at relative residual 1e-8, FP32 storage + FP64 "
+                  "refinement vs FP64",
+        "value": rate(s32), "unit": "solves/s", "n_gpus": 1, "higher_is_better": True,
+        "dtype": "f32 storage, f64 arithmetic and refinement", "data": "synthetic",
+        "config": {"workload": wl["name"], "n_triangles": len(T), "n_dof": N, "eps": wl["eps"],
+                   "nu": wl["nu"], "eta": wl["eta"], "leaf": wl["leaf"], "problem": "Dirichlet only",
+                   "solves": n_solves},
+        "vs_fp64": round(rate(s32) / rate(s64), 3),
+        "fp64": {"solves_per_s": rate(s64), "iterations": [i["iterations"] for i in s64],
+                 "relres": [i["relres"] for i in s64], "matvec_ms": round(mv64, 4),
+                 "matvec_gbs": round((8 * stored + 16 * N) / (mv64 * 1e-3) / 1e9, 2)},
+        "fp32_refinement": {"solves_per_s": rate(s32), "inner_iterations": [i["iterations"] for i in s32],
+                            "refinements": [i["refinements"] for i in s32],
+                            "relres_fp64": [i["relres"] for i in s32], "matvec_ms": round(mv32, 4),
+                            "rel_diff_to_fp64_solution": diff},
+        "build_ms": round(st["t_build_ms"], 1), "build_aca_kernel_ms": round(st["t_aca_kernel_ms"], 1),
+        "hmatrix": {"n_blocks": st["n_blocks"], "rank_mean": round(st["rank_mean"], 2),
+                    "rank_max": st["rank_max"], "stored_scalars": stored,
+                    "compression": round(st["compression"], 5), "device_bytes": st["device_bytes"]},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def bench_batch(args):
     """Batched workload: 96 independent bodies (ellipsoids and tori, 2k-40k
     triangles), eps 1e-5, one handle. Step = batched build + 8-vector products
@@ -416,7 +498,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["icosphere-L5", "icosphere-L3", "batch96", "serve",
+    ap.add_argument("--workload", choices=["icosphere-L5", "icosphere-L3", "batch96", "serve", "precision-box",
                                            "amvm-ellipsoid"],
                     default="icosphere-L5")
     ap.add_argument("--requests", type=int, default=120, help="serve: requests per run")
@@ -440,6 +522,9 @@ def main():
 
     if args.workload == "batch96":
         bench_batch(args)
+        return
+    if args.workload == "precision-box":
+        bench_precision(args)
         return
     if args.workload == "serve":
         bench_serve(args)

@@ -1243,11 +1243,12 @@ hmat_status build_impl(const std::vector<BodyIn>& in, double eta, int32_t leaf, 
       const double e = h->bodies[h->pos_body[h->plan.cl[h->plan.blk[b].t].off]].eps;
       return (int32_t)std::min<int64_t>(std::min(block_m(h, b), block_n(h, b)), kcap_first(e));
     };
-    auto cap2 = [&](int32_t f) {
-      const int32_t b = h->far_blocks[f];
-      return (int32_t)std::min(block_m(h, b), block_n(h, b));
-    };
     std::vector<int32_t> capv(nf, 0);
+    // later passes: four times the previous capacity, at most min(m, n)
+    auto cap_next = [&](int32_t f) {
+      const int32_t b = h->far_blocks[f];
+      return (int32_t)std::min<int64_t>(std::min(block_m(h, b), block_n(h, b)), 4 * (int64_t)capv[f]);
+    };
     std::vector<const double*> panel_ptr(nf, nullptr), u_ptr(nf, nullptr), v_ptr(nf, nullptr);
     std::deque<DevBuf> ustage, vstage;
     int64_t staged_u = 0, staged_v = 0;  // bytes
@@ -1269,7 +1270,7 @@ hmat_status build_impl(const std::vector<BodyIn>& in, double eta, int32_t leaf, 
       std::vector<int32_t> grp(f1 - f0);
       std::iota(grp.begin(), grp.end(), (int32_t)f0);
       for (int32_t f : grp) capv[f] = cap1(f);
-      DevBuf panels2;
+      std::deque<DevBuf> panels_more;  // panels of the later passes (read by the compaction)
       h->piv_bufs.emplace_back();
       run_aca_pass(h, grp, cap1, [&](size_t b) { return panels1.get(b); }, h->piv_bufs.back(), d_rank,
                    d_stop, d_ratio, panel_ptr, s);
@@ -1282,19 +1283,25 @@ hmat_status build_impl(const std::vector<BodyIn>& in, double eta, int32_t leaf, 
         check(hipStreamSynchronize(s), "ranks");
       };
       fetch();
-      std::vector<int32_t> again;
-      for (int32_t f : grp)
-        if (h->stop[f] == 4) again.push_back(f);
-      if (!again.empty()) {
-        for (int32_t f : again) capv[f] = cap2(f);
+      // blocks that filled their panels run again from the start with a
+      // larger capacity (ACA is deterministic, so the factors are those of an
+      // uninterrupted run), until none does
+      for (int pass = 2;; pass++) {
+        std::vector<int32_t> again;
+        for (int32_t f : grp)
+          if (h->stop[f] == 4) again.push_back(f);
+        if (again.empty()) break;
+        for (int32_t f : again) capv[f] = cap_next(f);
+        panels_more.emplace_back();
+        DevBuf& pb = panels_more.back();
         h->piv_bufs.emplace_back();
-        run_aca_pass(h, again, cap2,
+        run_aca_pass(h, again, [&](int32_t f) { return capv[f]; },
                      [&](size_t b) {
-                       if (panels2.bytes < b) panels2.alloc(b, "ACA panels");
-                       return panels2.as<double>();
+                       if (pb.bytes < b) pb.alloc(b, "ACA panels");
+                       return pb.as<double>();
                      },
                      h->piv_bufs.back(), d_rank, d_stop, d_ratio, panel_ptr, s);
-        h->aca_passes = 2;
+        h->aca_passes = std::max(h->aca_passes, pass);
         fetch();
       }
       // U and V staged in separate buffers: the V staging is freed as soon as

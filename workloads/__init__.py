@@ -294,6 +294,16 @@ def workload_c1():
                 leaf=32, eps=1e-6, nrhs=16)
 
 
+def workload_c3():
+    """Box [0,10]x[0,1]x[0,1], structured surface with h = 1/36: 108864 triangles,
+    326592 DOF; nu = 0.3, E = 1; reference FP64 build at eps = 1e-7. Only the
+    Dirichlet (single-layer) problem: the traction part needs the adjoint
+    double-layer operator, which is not part of this library."""
+    V, T = box_surface(10.0, 1.0, 1.0, 360, 36, 36)
+    return dict(name="precision-box", vertices=V, triangles=T, E=1.0, nu=0.3, eta=2.0,
+                leaf=32, eps=1e-7)
+
+
 def batch_bodies(n_bodies: int = 96, n_lo: int = 2000, n_hi: int = 40000, seed: int = 2,
                  eps: float = 1e-5):
     """Independent bodies for one batched build: ellipsoids and tori.
