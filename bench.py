@@ -341,7 +341,7 @@ def bench_serve(args):
     Compared: the plain form -- one request at a time, FP64 -- and the serving
     form -- `slots` requests in flight, FP32 storage with FP64 refinement for
     solves. Each is run with every request arriving at once (capacity) and
-    with Poisson arrivals at 0.5x and 1.0x the plain form's capacity (latency)."""
+    with Poisson arrivals at 0.5x, 1.0x and 1.2x the plain form's capacity (latency)."""
     import threading
 
     import numpy as np
@@ -409,7 +409,7 @@ def bench_serve(args):
     serve_cap = run(args.slots, 1, None, f"serving, {args.slots} slots, mixed precision, all at once")
     cap = plain_cap["requests_per_s"]
     loads = {}
-    for f in (0.5, 1.0):
+    for f in (0.5, 1.0, 1.2):
         loads[f"{f}x"] = {"plain": run(1, 0, f * cap, f"plain FP64 at {f}x capacity"),
                           "serving": run(args.slots, 1, f * cap, f"serving at {f}x capacity")}
     out = {
