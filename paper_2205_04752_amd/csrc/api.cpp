@@ -199,6 +199,8 @@ void trim_pool_after(int64_t freed_bytes, hipStream_t s) {
   (void)hipGetLastError();
 }
 
+void drop_idle_panels(int dev, hipStream_t s);  // idle ACA panel buffers (below)
+
 // At least b bytes for use on stream s; *cls and *dev receive what mem_free needs.
 void* mem_alloc(size_t b, hipStream_t s, size_t* cls, int* dev, const char* what) {
   const size_t cl = size_class(b);
@@ -234,8 +236,9 @@ void* mem_alloc(size_t b, hipStream_t s, size_t* cls, int* dev, const char* what
   }
   void* p = nullptr;
   hipError_t e = hipMallocAsync(&p, cl, s);
-  if (e == hipErrorOutOfMemory) {
+  if (e == hipErrorOutOfMemory) {  // hand everything kept back, then try again
     (void)hipGetLastError();
+    drop_idle_panels(d, s);
     mem_trim(d, s);
     e = hipMallocAsync(&p, cl, s);
   }
@@ -351,6 +354,18 @@ struct PanelCache {
   size_t keep_max = 0;                         // largest buffer kept (0: not known yet)
 };
 PanelCache g_panel_cache[MAX_DEVICES];
+
+// Frees the idle ACA panel buffers of device dev, ordered on stream s.
+void drop_idle_panels(int dev, hipStream_t s) {
+  if (dev < 0) return;
+  std::vector<void*> idle;
+  {
+    std::lock_guard<std::mutex> lk(g_panel_cache[dev].mu);
+    for (const auto& q : g_panel_cache[dev].idle) idle.push_back(q.first);
+    g_panel_cache[dev].idle.clear();
+  }
+  for (void* q : idle) (void)hipFreeAsync(q, s);
+}
 
 class PanelLease {
  public:
@@ -2319,13 +2334,7 @@ hmat_status hmat_release_memory(void* hip_stream) {
   StreamScope scope(s);
   const int dev = current_device();
   if (dev < 0) return fail(HMAT_EDEVICE, "no HIP device");
-  std::vector<void*> idle;
-  {
-    std::lock_guard<std::mutex> lk(g_panel_cache[dev].mu);
-    for (const auto& q : g_panel_cache[dev].idle) idle.push_back(q.first);
-    g_panel_cache[dev].idle.clear();
-  }
-  for (void* q : idle) (void)hipFreeAsync(q, s);
+  drop_idle_panels(dev, s);
   const hipError_t e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
     (void)hipGetLastError();
