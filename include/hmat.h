@@ -39,6 +39,17 @@
  *     memory (4 GiB; 64 GiB while a request server runs). Allocating and
  *     releasing buffers of that size per build stalled builds, the more so
  *     with several at once. hmat_release_memory hands all of it back.
+ *   - Environment (read at build time of a handle; for tuning and tracing):
+ *       HMAT_ACA_BUDGET_MB  bytes of first-pass ACA panels one ACA group may
+ *                           hold (default: a quarter of the free device
+ *                           memory, at least 1 GiB); smaller budgets run ACA
+ *                           in more groups, with the same results;
+ *       HMAT_MV_CHUNK_KB    product chunk size for one vector (default 16);
+ *       HMAT_MV_UNROLL      columns per batch of the one-vector product
+ *                           kernels, 8 or 16 (default 16); hmat_tune sets
+ *                           both per handle;
+ *       HMAT_TRACE_BUILD    if set, print the build's phase times to stderr
+ *                           (synchronises the stream at every phase).
  */
 #ifndef HMAT_H
 #define HMAT_H
