@@ -1236,8 +1236,6 @@ hmat_status build_impl(const std::vector<BodyIn>& in, double eta, int32_t leaf, 
     std::vector<int64_t> near_off;
     EventPair evn;
     setup_dense(h, in, eta, leaf, s, t0, near_stage, near_off, evn);
-    const Plan& P = h->plan;
-    const int32_t nt = P.nt;
     // K2: ACA in groups of far blocks (canonical order) whose first-pass
     // panels fit the budget; each group's factors are compacted into a plain
     // column-major staging buffer (U m x k, then V n x k) and its panels freed.
@@ -1438,7 +1436,7 @@ void matvec_impl(hmat* h, int prec, int32_t nrhs, const double* x, int64_t ldx, 
     if (h->prof) {
       if (h->prof_pending.size() >= 4096) prof_collect(h);
       std::array<hipEvent_t, 5> e{};
-      for (auto& x : e) check(hipEventCreate(&x), "profile");
+      for (auto& q : e) check(hipEventCreate(&q), "profile");
       h->prof_pending.push_back(e);
       ev = h->prof_pending.back().data();
       check(hipEventRecord(ev[0], s), "profile");

@@ -653,7 +653,7 @@ __global__ __launch_bounds__(256) void k_dots_part(const double* __restrict__ Q,
     if (lane == 0) red[wv][c] = t;
   }
   __syncthreads();
-  if (threadIdx.x < nc) {
+  if ((int)threadIdx.x < nc) {
     double t = 0.0;
     for (int k = 0; k < NW; k++) t += red[k][threadIdx.x];
     part[(size_t)blockIdx.x * ncols + c0 + threadIdx.x] = t;
