@@ -46,6 +46,8 @@ hipError_t launch_fill(double*, int64_t, double, hipStream_t);
 hipError_t launch_axpy(double, const double*, int64_t, double*, hipStream_t);
 hipError_t launch_dense_mv(const DenseMvTask*, int, const double*, const double*, double*, hipStream_t);
 hipError_t launch_lowrank_delta(const DeltaTask*, int, const double*, double*, hipStream_t);
+hipError_t launch_amvm_rowsum(const int64_t*, const int32_t*, const char*, const int64_t*, const int64_t*,
+                              const double*, int64_t, double*, hipStream_t);
 }  // namespace hm
 
 using namespace hm;
@@ -1776,14 +1778,23 @@ hmat_status amvm_impl(const hmat_mesh* mesh, double E, double nu, double eta, in
         for (int64_t r = 0; r < M[f]; r++) rblk[fill[R0[f] + r]++] = (int32_t)f;
     }
     std::vector<char> adv(nf, 1);  // blocks whose look-ahead must be computed
-    // the look-ahead contributions come back every round: pinned host memory
+    // the row errors are summed on the device (rows -> blocks as above)
+    DevBuf d_rptr, d_rblk, d_doff, d_r0, d_has, d_e;
+    upload(d_rptr, rptr, s, "amvm rows");
+    upload(d_rblk, rblk, s, "amvm rows");
+    upload(d_doff, doff, s, "amvm rows");
+    upload(d_r0, R0, s, "amvm rows");
+    d_e.alloc(sizeof(double) * std::max<int64_t>(N, 1), "amvm rows");
+    // the look-ahead contributions and row errors come back every round:
+    // pinned host memory
     struct Pinned {
       double* p = nullptr;
       ~Pinned() {
         if (p) (void)hipHostFree(p);
       }
-    } d_host;
+    } d_host, e_host;
     check(hipHostMalloc((void**)&d_host.p, sizeof(double) * std::max<int64_t>(dtot, 1)), "amvm host buffer");
+    check(hipHostMalloc((void**)&e_host.p, sizeof(double) * std::max<int64_t>(N, 1)), "amvm host buffer");
     double* const d = d_host.p;
     std::vector<double> e(N), rest(N);
     std::vector<int64_t> rows(N);
@@ -1834,19 +1845,24 @@ hmat_status amvm_impl(const hmat_mesh* mesh, double E, double nu, double eta, in
         dts.push_back(DeltaTask{pan, pan + M[f] * kcap[f], doff[f], (int32_t)M[f], (int32_t)Nn[f], r_use[f], r1,
                                 3 * P.cl[P.blk[h->far_blocks[f]].s].off, 0});
       }
+      // (c) the estimator: row errors summed on the device in canonical block
+      // order (the same additions, in the same order, as a loop over blocks)
       if (!dts.empty()) {
         DevBuf d_t;
         upload(d_t, dts, s, "amvm deltas");
+        upload(d_has, has_d, s, "amvm deltas");
         check(launch_lowrank_delta(d_t.as<DeltaTask>(), (int)dts.size(), xp.as<double>(), d_d.as<double>(), s),
               "amvm deltas");
+        check(launch_amvm_rowsum(d_rptr.as<int64_t>(), d_rblk.as<int32_t>(), d_has.as<char>(),
+                                 d_doff.as<int64_t>(), d_r0.as<int64_t>(), d_d.as<double>(), N, d_e.as<double>(), s),
+              "amvm rows");
+        check(hipMemcpyAsync(e_host.p, d_e.p, sizeof(double) * N, hipMemcpyDeviceToHost, s), "amvm rows");
         check(hipMemcpyAsync(d, d_d.p, sizeof(double) * dtot, hipMemcpyDeviceToHost, s), "amvm deltas");
         check(hipStreamSynchronize(s), "amvm deltas");
+        std::memcpy(e.data(), e_host.p, sizeof(double) * N);
+      } else {
+        std::fill(e.begin(), e.end(), 0.0);
       }
-      // (c) the estimator
-      std::fill(e.begin(), e.end(), 0.0);
-      for (size_t f = 0; f < nf; f++)
-        if (has_d[f])
-          for (int64_t r = 0; r < M[f]; r++) e[R0[f] + r] += d[doff[f] + r];
       double g2 = 0.0, bh2 = 0.0;
       for (int64_t i = 0; i < N; i++) {
         g2 += e[i] * e[i];

@@ -4,7 +4,7 @@
 //   K2  k_aca             ACA with partial pivoting on every admissible block
 //                         (Sec. 2.2, Algorithm 1), one workgroup per block
 //   --  k_compact         final low-rank arena (first k columns of the panels)
-//   --  k_dense_mv, k_lowrank_delta   the adaptive multiplication (Algorithm 2)
+//   --  k_dense_mv, k_lowrank_delta, k_amvm_rowsum   the adaptive multiplication (Algorithm 2)
 //   --  GMRES helpers     dots, column updates, norms
 // (K3, the product, is in product.hip.)
 //
@@ -606,6 +606,35 @@ __global__ __launch_bounds__(256) void k_lowrank_delta(const DeltaTask* __restri
 hipError_t launch_dense_mv(const DenseMvTask* tasks, int n, const double* D, const double* xp,
                            double* out, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_dense_mv, dim3(n), dim3(256), 0, s, tasks, D, xp, out);
+  return hipGetLastError();
+}
+
+// The estimator's row errors: e[i] = sum over the admissible blocks containing
+// row i (rblk[rptr[i] .. rptr[i+1]), canonical order) of their look-ahead
+// contribution to that row, d[doff[f] + i - r0[f]]; blocks without a
+// look-ahead window (has_d[f] == 0) add nothing.
+__global__ __launch_bounds__(256) void k_amvm_rowsum(const int64_t* __restrict__ rptr,
+                                                     const int32_t* __restrict__ rblk,
+                                                     const char* __restrict__ has_d,
+                                                     const int64_t* __restrict__ doff,
+                                                     const int64_t* __restrict__ r0,
+                                                     const double* __restrict__ d, int64_t n,
+                                                     double* __restrict__ e) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double sum = 0.0;
+  for (int64_t q = rptr[i]; q < rptr[i + 1]; q++) {
+    const int32_t f = rblk[q];
+    if (has_d[f]) sum += d[doff[f] + (i - r0[f])];
+  }
+  e[i] = sum;
+}
+
+hipError_t launch_amvm_rowsum(const int64_t* rptr, const int32_t* rblk, const char* has_d, const int64_t* doff,
+                              const int64_t* r0, const double* d, int64_t n, double* e, hipStream_t s) {
+  if (n > 0)
+    hipLaunchKernelGGL(k_amvm_rowsum, dim3(blocks_for(n, 256)), dim3(256), 0, s, rptr, rblk, has_d, doff, r0, d,
+                       n, e);
   return hipGetLastError();
 }
 
