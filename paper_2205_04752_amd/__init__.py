@@ -92,6 +92,10 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                            "or python paper_2205_04752_amd/build.py")
+    # torch first: the library then binds to the HIP runtime torch has loaded
+    # (same soname), so torch's streams and device pointers are valid in it.
+    # Loaded on its own, it binds to the system runtime instead.
+    import torch  # noqa: F401
     L = C.CDLL(LIB_PATH)
     vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
     L.hmat_build.argtypes = [C.POINTER(_Mesh), dbl, dbl, dbl, i32, dbl, vp, C.POINTER(vp)]
