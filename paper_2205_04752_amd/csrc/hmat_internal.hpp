@@ -49,11 +49,11 @@ constexpr int ACA_SMALL_TRI = 64;
 // the normalisation and the norm update of a step read them from LDS.
 constexpr int ACA_STAGE_MAX = 7936;
 // Dynamic LDS (bytes) of the ACA kernel for one block: the coefficient row
-// (kcap doubles), the row set Z (m bits, in 32-bit words, padded to a
+// and the cross-term weights (kcap doubles each), the row set Z (m bits, in 32-bit words, padded to a
 // double) and, if staged, the newest row and column (n + m doubles).
 inline size_t aca_shmem(int kcap, int64_t m, int64_t n) {
   const size_t zw = (size_t)((m + 31) / 32);
-  return 8 * (size_t)kcap + 8 * ((zw + 1) / 2) + (m + n <= ACA_STAGE_MAX ? 8 * (size_t)(m + n) : 0);
+  return 16 * (size_t)kcap + 8 * ((zw + 1) / 2) + (m + n <= ACA_STAGE_MAX ? 8 * (size_t)(m + n) : 0);
 }
 
 // Dense (non-admissible) block at d_off in the near arena (m = 3 t_len rows).

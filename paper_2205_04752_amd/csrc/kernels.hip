@@ -199,7 +199,7 @@ constexpr int NW = 256 / WAVE;  // waves of a 256-thread workgroup
 
 template <int NWV>
 struct RedT {
-  double d[2][2][NWV];
+  double d[2][3][NWV];
   int i[2][NWV];
 };
 
@@ -227,20 +227,24 @@ __device__ __forceinline__ int blk_min(int v, RedT<NWV>& R, int& ph) {
   return r;
 }
 template <int NWV>
-__device__ __forceinline__ void blk_sum2(double& a, double& b, RedT<NWV>& R, int& ph) {
+__device__ __forceinline__ void blk_sum3(double& a, double& b, double& c, RedT<NWV>& R, int& ph) {
   a = wave_sum(a);
   b = wave_sum(b);
+  c = wave_sum(c);
   if ((threadIdx.x & (WAVE - 1)) == 0) {
     R.d[ph][0][threadIdx.x / WAVE] = a;
     R.d[ph][1][threadIdx.x / WAVE] = b;
+    R.d[ph][2][threadIdx.x / WAVE] = c;
   }
   __syncthreads();
   a = R.d[ph][0][0];
   b = R.d[ph][1][0];
+  c = R.d[ph][2][0];
 #pragma unroll
   for (int w = 1; w < NWV; w++) {
     a += R.d[ph][0][w];
     b += R.d[ph][1][w];
+    c += R.d[ph][2][w];
   }
   ph ^= 1;
 }
@@ -322,6 +326,65 @@ __device__ __forceinline__ void sub_panel3(const double* __restrict__ coef, cons
   e2 -= (a2 + b2) + (c2 + d2);
 }
 
+// As sub_panel3 (same loads, same partial sums for e_b), and also
+// t_b = sum_{l<k} w[l] * P[l*ld + b] from the same loads.
+__device__ __forceinline__ void sub_panel3w(const double* __restrict__ coef,
+                                            const double* __restrict__ w, const double* P, int k,
+                                            int ld, double& e0, double& e1, double& e2, double& t0,
+                                            double& t1, double& t2) {
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, b0 = 0.0, b1 = 0.0, b2 = 0.0;
+  double c0 = 0.0, c1 = 0.0, c2 = 0.0, d0 = 0.0, d1 = 0.0, d2 = 0.0;
+  double f0 = 0.0, f1 = 0.0, f2 = 0.0, h0 = 0.0, h1 = 0.0, h2 = 0.0;
+  int l = 0;
+  for (; l + 3 < k; l += 4) {
+    const double* p0 = P + (size_t)l * ld;
+    const double* p1 = p0 + ld;
+    const double* p2 = p1 + ld;
+    const double* p3 = p2 + ld;
+    const double x00 = p0[0], x01 = p0[1], x02 = p0[2];
+    const double x10 = p1[0], x11 = p1[1], x12 = p1[2];
+    const double x20 = p2[0], x21 = p2[1], x22 = p2[2];
+    const double x30 = p3[0], x31 = p3[1], x32 = p3[2];
+    const double w0 = coef[l], w1 = coef[l + 1], w2 = coef[l + 2], w3 = coef[l + 3];
+    const double z0 = w[l], z1 = w[l + 1], z2 = w[l + 2], z3 = w[l + 3];
+    a0 += w0 * x00;
+    a1 += w0 * x01;
+    a2 += w0 * x02;
+    b0 += w1 * x10;
+    b1 += w1 * x11;
+    b2 += w1 * x12;
+    c0 += w2 * x20;
+    c1 += w2 * x21;
+    c2 += w2 * x22;
+    d0 += w3 * x30;
+    d1 += w3 * x31;
+    d2 += w3 * x32;
+    f0 += z0 * x00 + z2 * x20;
+    f1 += z0 * x01 + z2 * x21;
+    f2 += z0 * x02 + z2 * x22;
+    h0 += z1 * x10 + z3 * x30;
+    h1 += z1 * x11 + z3 * x31;
+    h2 += z1 * x12 + z3 * x32;
+  }
+  for (; l < k; l++) {
+    const double* p0 = P + (size_t)l * ld;
+    const double w0 = coef[l], z0 = w[l];
+    const double x00 = p0[0], x01 = p0[1], x02 = p0[2];
+    a0 += w0 * x00;
+    a1 += w0 * x01;
+    a2 += w0 * x02;
+    f0 += z0 * x00;
+    f1 += z0 * x01;
+    f2 += z0 * x02;
+  }
+  e0 -= (a0 + b0) + (c0 + d0);
+  e1 -= (a1 + b1) + (c1 + d1);
+  e2 -= (a2 + b2) + (c2 + d2);
+  t0 = f0 + h0;
+  t1 = f1 + h1;
+  t2 = f2 + h2;
+}
+
 // sum_r x[r] y[r] over r = lane, lane + 64, ... < n; four partial sums.
 __device__ __forceinline__ double lane_dot(const double* x, const double* y, int n, int lane) {
   double a = 0.0, b = 0.0, c = 0.0, d = 0.0;
@@ -348,9 +411,12 @@ __device__ __forceinline__ double lane_dot(const double* x, const double* y, int
 //   panel capacity reached (4: the host re-runs the block with a larger capacity),
 //   no finite pivot (5: non-finite entries; reported as an error).
 // Panels live in global memory (column-major U m x kcap, V n x kcap); the
-// coefficient row U[i, 0:k] / V[j, 0:k] and the set Z are staged in LDS, and
-// for m + n <= ACA_STAGE_MAX also the newest row v_k and column u_k (written
-// to both; the step's later reads of them use the LDS copy).
+// coefficient row U[i, 0:k] / V[j, 0:k], w = V[:, 0:k]^T v_k and the set Z
+// are staged in LDS, and for m + n <= ACA_STAGE_MAX also the newest row v_k
+// and column u_k (written to both; the step's later reads of them use the
+// LDS copy). The cross term is evaluated as u_k^T (U[:, 0:k] w): the column
+// pass forms U[:, 0:k] w from the same loads that subtract U[:, 0:k] V[j, 0:k]^T,
+// so a step reads the U panel once and the V panel twice.
 template <int TPB>
 __global__ __launch_bounds__(TPB) void k_aca(DevGeo g0, const AcaTask* __restrict__ tasks,
                                                int32_t* __restrict__ rank_out,
@@ -367,10 +433,11 @@ __global__ __launch_bounds__(TPB) void k_aca(DevGeo g0, const AcaTask* __restric
   double* __restrict__ U = T.panel;
   double* __restrict__ V = T.panel + (size_t)m * kcap;
   double* coef = sh;
-  uint32_t* Z = reinterpret_cast<uint32_t*>(sh + kcap);
+  double* const wl = sh + kcap;  // w_l = v_l . v_k
+  uint32_t* Z = reinterpret_cast<uint32_t*>(sh + 2 * kcap);
   const int zw = (m + 31) >> 5;
   const bool stage = m + n <= ACA_STAGE_MAX;
-  double* const vs = sh + kcap + ((zw + 1) >> 1);  // staged v_k (n), then u_k (m)
+  double* const vs = sh + 2 * kcap + ((zw + 1) >> 1);  // staged v_k (n), then u_k (m)
   double* const us = vs + n;
   const int nt = g.nt;
   int ph = 0, k = 0, nZ = 0, i = 0, stop = 0, visited = 0, pending = 0;
@@ -472,16 +539,24 @@ __global__ __launch_bounds__(TPB) void k_aca(DevGeo g0, const AcaTask* __restric
     }
     for (int l = tid; l < k; l += TPB) coef[l] = V[j + (size_t)l * n];
     __syncthreads();
-    // column j of the remainder into U[:, k] (S is symmetric: A[3p+a, 3q+b] = S_ba)
+    // w = V[:, 0:k]^T v_k: wave w takes l = w, w + NWV, ...
+    for (int l = wv; l < k; l += NWV) {
+      const double b = wave_sum(lane_dot(V + (size_t)l * n, vr, n, lane));
+      if (lane == 0) wl[l] = b;
+    }
+    __syncthreads();
+    // column j of the remainder into U[:, k] (S is symmetric: A[3p+a, 3q+b] = S_ba),
+    // and the cross term sum_{l<k} (u_l . u_k)(v_l . v_k) = u_k . (U[:, 0:k] w)
     double* __restrict__ uk = U + (size_t)k * m;
     double* const ur = stage ? us : uk;  // where this step reads u_k
     const int qj = T.s_off + j / 3, bj = j % 3;
-    double uu = 0.0;
+    double uu = 0.0, cross = 0.0;
     for (int p = tid; p < T.t_len; p += TPB) {
       const int ip = T.t_off + p;
-      double e0, e1, e2;
+      double e0, e1, e2, t0, t1, t2;
       row3(g, g.cen[ip], g.cen[nt + ip], g.cen[2 * nt + ip], bj, qj, e0, e1, e2);
-      sub_panel3(coef, U + 3 * p, k, m, e0, e1, e2);
+      sub_panel3w(coef, wl, U + 3 * p, k, m, e0, e1, e2, t0, t1, t2);
+      cross += e0 * t0 + e1 * t1 + e2 * t2;
       uk[3 * p] = e0;
       uk[3 * p + 1] = e1;
       uk[3 * p + 2] = e2;
@@ -492,17 +567,7 @@ __global__ __launch_bounds__(TPB) void k_aca(DevGeo g0, const AcaTask* __restric
       }
       uu += e0 * e0 + e1 * e1 + e2 * e2;
     }
-    blk_sum2(uu, vv, R, ph);
-    // sum_{l<k} (u_l . u_k)(v_l . v_k): wave w takes l = w, w + NWV, ...
-    double cr = 0.0;
-    for (int l = wv; l < k; l += NWV) {
-      const double* ul = U + (size_t)l * m;
-      const double* vl = V + (size_t)l * n;
-      const double a = lane_dot(ul, ur, m, lane), b = lane_dot(vl, vr, n, lane);
-      cr += wave_sum(a) * wave_sum(b);
-    }
-    double cross = (lane == 0) ? cr : 0.0, dummy = 0.0;
-    blk_sum2(cross, dummy, R, ph);
+    blk_sum3(uu, vv, cross, R, ph);
     if (tid == 0) {
       T.piv[k] = i;
       T.piv[kcap + k] = j;
