@@ -25,8 +25,8 @@ namespace hm {
 hipError_t launch_self(const DevGeo&, const SelfTask*, double*, hipStream_t);
 hipError_t launch_near_only(const DevGeo&, const NearTask*, int, double*, hipStream_t);
 hipError_t launch_entries(const DevGeo&, int64_t, const int64_t*, const int64_t*, double*, hipStream_t);
-hipError_t launch_aca(const DevGeo&, const AcaTask*, int, int, size_t, size_t, int32_t*, int32_t*, double*,
-                      hipStream_t);
+hipError_t launch_aca(const DevGeo&, const AcaTask*, int, int, size_t, size_t, bool, int32_t*, int32_t*,
+                      double*, hipStream_t);
 hipError_t launch_compact(const CopyTask*, int, hipStream_t);
 hipError_t launch_to_stream(const StreamTask*, int, double*, hipStream_t);
 hipError_t launch_from_stream(const StreamTask*, int, const double*, hipStream_t);
@@ -987,11 +987,12 @@ struct EventPair {
 };
 
 // One ACA pass over the far blocks listed in `fidx` (largest first) with
-// per-block capacity cap(f); panels in `panels`, pivots in `piv`.
+// per-block capacity cap(f); panels in `panels`, pivots in `piv`. `wide`:
+// 512-thread workgroups for the large blocks (later passes, which hold few).
 template <class CapFn, class PanelFn>
 void run_aca_pass(hmat* h, const std::vector<int32_t>& fidx, CapFn cap, PanelFn get_panels, DevBuf& piv,
                   DevBuf& d_rank, DevBuf& d_stop, DevBuf& d_ratio,
-                  std::vector<const double*>& panel_ptr, hipStream_t s) {
+                  std::vector<const double*>& panel_ptr, bool wide, hipStream_t s) {
   const Plan& P = h->plan;
   // largest blocks first (|t| + |s|), equal sizes in the given order
   std::vector<uint64_t> size(fidx.size());
@@ -1052,7 +1053,7 @@ void run_aca_pass(hmat* h, const std::vector<int32_t>& fidx, CapFn cap, PanelFn 
   upload(d_tasks, tasks, s, "ACA tasks");
   EventPair ev;
   check(hipEventRecord(ev.a, s), "event");
-  check(launch_aca(h->G, d_tasks.as<AcaTask>(), (int)tasks.size(), n_big, shmem[0], shmem[1],
+  check(launch_aca(h->G, d_tasks.as<AcaTask>(), (int)tasks.size(), n_big, shmem[0], shmem[1], wide,
                    d_rank.as<int32_t>(), d_stop.as<int32_t>(), d_ratio.as<double>(), s),
         "ACA launch");
   check(hipEventRecord(ev.b, s), "event");
@@ -1288,7 +1289,7 @@ hmat_status build_impl(const std::vector<BodyIn>& in, double eta, int32_t leaf, 
       std::deque<DevBuf> panels_more;  // panels of the later passes (read by the compaction)
       h->piv_bufs.emplace_back();
       run_aca_pass(h, grp, cap1, [&](size_t b) { return panels1.get(b); }, h->piv_bufs.back(), d_rank,
-                   d_stop, d_ratio, panel_ptr, s);
+                   d_stop, d_ratio, panel_ptr, false, s);
       h->aca_passes = std::max(h->aca_passes, 1);
       auto fetch = [&]() {
         check(hipMemcpyAsync(h->rank.data() + f0, d_rank.as<int32_t>() + f0, sizeof(int32_t) * (f1 - f0),
@@ -1315,7 +1316,7 @@ hmat_status build_impl(const std::vector<BodyIn>& in, double eta, int32_t leaf, 
                        if (pb.bytes < b) pb.alloc(b, "ACA panels");
                        return pb.as<double>();
                      },
-                     h->piv_bufs.back(), d_rank, d_stop, d_ratio, panel_ptr, s);
+                     h->piv_bufs.back(), d_rank, d_stop, d_ratio, panel_ptr, true, s);
         h->aca_passes = std::max(h->aca_passes, pass);
         fetch();
       }
@@ -1819,7 +1820,7 @@ hmat_status amvm_impl(const hmat_mesh* mesh, double E, double nu, double eta, in
                                 }) - tasks.begin());
         DevBuf d_tasks;
         upload(d_tasks, tasks, s, "amvm ACA");
-        check(launch_aca(h->G, d_tasks.as<AcaTask>(), (int)tasks.size(), n_big, shmem[0], shmem[1],
+        check(launch_aca(h->G, d_tasks.as<AcaTask>(), (int)tasks.size(), n_big, shmem[0], shmem[1], true,
                          d_rank.as<int32_t>(),
                          d_stop.as<int32_t>(), d_ratio.as<double>(), s), "amvm ACA");
         std::vector<int32_t> rk(nf), sp(nf);

@@ -194,6 +194,7 @@ __global__ void k_entries(DevGeo g0, int64_t n, const int64_t* __restrict__ rows
 // barrier of the following reduction, so one barrier per reduction suffices.
 
 constexpr int ACA_T = 256;      // workgroup of the ACA kernel (large blocks)
+constexpr int ACA_WIDE_T = 512; // the same for launches of few blocks (one per CU)
 constexpr int ACA_SMALL_T = WAVE;  // one wave per small block
 constexpr int NW = 256 / WAVE;  // waves of a 256-thread workgroup
 
@@ -914,15 +915,21 @@ hipError_t launch_entries(const DevGeo& g, int64_t n, const int64_t* rows, const
   return hipGetLastError();
 }
 
-// tasks[0, n_big): 256-thread workgroups; tasks[n_big, ntasks): blocks with
-// at most ACA_SMALL_TRI triangles per side, one wave each. A one-wave block
-// has no cross-wave barriers, and four times as many blocks fit on a CU.
-// shmem_big / shmem_small: the largest aca_shmem of each part's tasks.
+// tasks[0, n_big): 256-thread workgroups (512 if `wide`); tasks[n_big,
+// ntasks): blocks with at most ACA_SMALL_TRI triangles per side, one wave
+// each. A one-wave block has no cross-wave barriers, and four times as many
+// blocks fit on a CU. A launch of few large blocks (later capacity passes,
+// the rounds of the adaptive multiplication) leaves most CUs idle; there a
+// block's step is bound by the loads its own workgroup keeps in flight, and
+// 512 threads keep twice as many. shmem_big / shmem_small: the largest
+// aca_shmem of each part's tasks.
 hipError_t launch_aca(const DevGeo& g, const AcaTask* tasks, int ntasks, int n_big, size_t shmem_big,
-                      size_t shmem_small, int32_t* rank, int32_t* stop, double* ratio, hipStream_t s) {
+                      size_t shmem_small, bool wide, int32_t* rank, int32_t* stop, double* ratio,
+                      hipStream_t s) {
   if (shmem_big > 64 * 1024) {
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_aca<ACA_T>),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem_big);
+    const void* f = wide ? reinterpret_cast<const void*>(&k_aca<ACA_WIDE_T>)
+                         : reinterpret_cast<const void*>(&k_aca<ACA_T>);
+    const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem_big);
     if (e != hipSuccess) return e;
   }
   if (shmem_small > 64 * 1024) {
@@ -930,7 +937,10 @@ hipError_t launch_aca(const DevGeo& g, const AcaTask* tasks, int ntasks, int n_b
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem_small);
     if (e != hipSuccess) return e;
   }
-  if (n_big > 0)
+  if (n_big > 0 && wide)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_aca<ACA_WIDE_T>), dim3(n_big), dim3(ACA_WIDE_T), shmem_big, s, g,
+                       tasks, rank, stop, ratio);
+  else if (n_big > 0)
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_aca<ACA_T>), dim3(n_big), dim3(ACA_T), shmem_big, s, g, tasks,
                        rank, stop, ratio);
   if (ntasks > n_big)
