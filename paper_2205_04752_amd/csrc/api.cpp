@@ -28,6 +28,7 @@ hipError_t launch_entries(const DevGeo&, int64_t, const int64_t*, const int64_t*
 hipError_t launch_aca(const DevGeo&, const AcaTask*, int, int, size_t, size_t, bool, int32_t*, int32_t*,
                       double*, hipStream_t);
 hipError_t launch_compact(const CopyTask*, int, hipStream_t);
+hipError_t launch_copy_spans(const SpanCopy*, int, hipStream_t);
 hipError_t launch_to_stream(const StreamTask*, int, double*, hipStream_t);
 hipError_t launch_from_stream(const StreamTask*, int, const double*, hipStream_t);
 hipError_t launch_gather(int, const double*, int64_t, const int32_t*, int64_t, double*, int64_t, hipStream_t);
@@ -987,12 +988,16 @@ struct EventPair {
 };
 
 // One ACA pass over the far blocks listed in `fidx` (largest first) with
-// per-block capacity cap(f); panels in `panels`, pivots in `piv`. `wide`:
-// 512-thread workgroups for the large blocks (later passes, which hold few).
-template <class CapFn, class PanelFn>
+// per-block capacity cap(f); panels in `panels`, pivots in `piv`. Each block
+// resumes from and saves to states[f] and its row set at zbits + zoff[f]
+// (zeroed state: a fresh start). prep(tasks) enqueues what must precede the
+// launch. `wide`: 512-thread workgroups for the large blocks (later passes,
+// which hold few).
+template <class CapFn, class PanelFn, class PrepFn>
 void run_aca_pass(hmat* h, const std::vector<int32_t>& fidx, CapFn cap, PanelFn get_panels, DevBuf& piv,
                   DevBuf& d_rank, DevBuf& d_stop, DevBuf& d_ratio,
-                  std::vector<const double*>& panel_ptr, bool wide, hipStream_t s) {
+                  std::vector<const double*>& panel_ptr, AcaState* states, uint32_t* zbits,
+                  const std::vector<int64_t>& zoff, PrepFn prep, bool wide, hipStream_t s) {
   const Plan& P = h->plan;
   // largest blocks first (|t| + |s|), equal sizes in the given order
   std::vector<uint64_t> size(fidx.size());
@@ -1042,6 +1047,8 @@ void run_aca_pass(hmat* h, const std::vector<int32_t>& fidx, CapFn cap, PanelFn 
     t.kcap = kc;
     t.blk = f;
     t.eps = h->bodies[h->pos_body[t.t_off]].eps;
+    t.st = states + f;
+    t.zbits = zbits + zoff[f];
     tasks.push_back(t);
     h->piv_ptr[f] = t.piv;
     h->piv_cap[f] = kc;
@@ -1051,6 +1058,7 @@ void run_aca_pass(hmat* h, const std::vector<int32_t>& fidx, CapFn cap, PanelFn 
   }
   DevBuf d_tasks;
   upload(d_tasks, tasks, s, "ACA tasks");
+  prep(tasks);
   EventPair ev;
   check(hipEventRecord(ev.a, s), "event");
   check(launch_aca(h->G, d_tasks.as<AcaTask>(), (int)tasks.size(), n_big, shmem[0], shmem[1], wide,
@@ -1266,6 +1274,21 @@ hmat_status build_impl(const std::vector<BodyIn>& in, double eta, int32_t leaf, 
       return (int32_t)std::min<int64_t>(std::min(block_m(h, b), block_n(h, b)), 4 * (int64_t)capv[f]);
     };
     std::vector<const double*> panel_ptr(nf, nullptr), u_ptr(nf, nullptr), v_ptr(nf, nullptr);
+    // ACA state of every far block (a block that fills its panels is
+    // resumed from it in the next pass), zeroed: the first pass starts fresh
+    std::vector<int64_t> zoff(nf, 0);
+    int64_t ztot = 0;
+    for (size_t f = 0; f < nf; f++) {
+      zoff[f] = ztot;
+      ztot += (block_m(h, h->far_blocks[f]) + 31) / 32;
+    }
+    DevBuf d_states, d_zbits, d_spans;
+    d_states.alloc(sizeof(AcaState) * std::max<size_t>(nf, 1), "ACA state");
+    d_zbits.alloc(sizeof(uint32_t) * std::max<int64_t>(ztot, 1), "ACA state");
+    check(hipMemsetAsync(d_states.p, 0, d_states.bytes, s), "ACA state");
+    check(hipMemsetAsync(d_zbits.p, 0, d_zbits.bytes, s), "ACA state");
+    AcaState* const states = d_states.as<AcaState>();
+    uint32_t* const zbits = d_zbits.as<uint32_t>();
     std::deque<DevBuf> ustage, vstage;
     int64_t staged_u = 0, staged_v = 0;  // bytes
     const int64_t budget = aca_budget();
@@ -1289,7 +1312,8 @@ hmat_status build_impl(const std::vector<BodyIn>& in, double eta, int32_t leaf, 
       std::deque<DevBuf> panels_more;  // panels of the later passes (read by the compaction)
       h->piv_bufs.emplace_back();
       run_aca_pass(h, grp, cap1, [&](size_t b) { return panels1.get(b); }, h->piv_bufs.back(), d_rank,
-                   d_stop, d_ratio, panel_ptr, false, s);
+                   d_stop, d_ratio, panel_ptr, states, zbits, zoff, [](const std::vector<AcaTask>&) {},
+                   false, s);
       h->aca_passes = std::max(h->aca_passes, 1);
       auto fetch = [&]() {
         check(hipMemcpyAsync(h->rank.data() + f0, d_rank.as<int32_t>() + f0, sizeof(int32_t) * (f1 - f0),
@@ -1299,15 +1323,41 @@ hmat_status build_impl(const std::vector<BodyIn>& in, double eta, int32_t leaf, 
         check(hipStreamSynchronize(s), "ranks");
       };
       fetch();
-      // blocks that filled their panels run again from the start with a
-      // larger capacity (ACA is deterministic, so the factors are those of an
-      // uninterrupted run), until none does
+      // blocks that filled their panels continue from their saved state with
+      // a larger capacity (their panel columns and pivots so far are copied
+      // over first; ACA is sequential, so the factors are those of an
+      // uninterrupted run), until none fills its panels
       for (int pass = 2;; pass++) {
         std::vector<int32_t> again;
         for (int32_t f : grp)
           if (h->stop[f] == 4) again.push_back(f);
         if (again.empty()) break;
-        for (int32_t f : again) capv[f] = cap_next(f);
+        std::vector<const double*> old_panel(nf, nullptr);
+        std::vector<const int32_t*> old_piv(nf, nullptr);
+        std::vector<int32_t> old_cap(nf, 0);
+        for (int32_t f : again) {
+          old_panel[f] = panel_ptr[f];
+          old_piv[f] = h->piv_ptr[f];
+          old_cap[f] = capv[f];
+          capv[f] = cap_next(f);
+        }
+        auto carry = [&](const std::vector<AcaTask>& tasks) {
+          std::vector<SpanCopy> sp;
+          sp.reserve(4 * tasks.size());
+          auto span = [&](const void* src, void* dst, int64_t words) {
+            sp.push_back(SpanCopy{static_cast<const uint32_t*>(src), static_cast<uint32_t*>(dst), words});
+          };
+          for (const AcaTask& t : tasks) {
+            const int32_t f = t.blk, kc = old_cap[f];  // stop 4: k == kc columns so far
+            const int64_t m = 3 * (int64_t)t.t_len, n = 3 * (int64_t)t.s_len;
+            span(old_panel[f], t.panel, 2 * m * kc);                               // U
+            span(old_panel[f] + m * kc, t.panel + m * t.kcap, 2 * n * kc);         // V
+            span(old_piv[f], t.piv, kc);                                           // pivot rows
+            span(old_piv[f] + kc, t.piv + t.kcap, kc);                             // pivot columns
+          }
+          upload(d_spans, sp, s, "ACA carry");
+          check(launch_copy_spans(d_spans.as<SpanCopy>(), (int)sp.size(), s), "ACA carry");
+        };
         panels_more.emplace_back();
         DevBuf& pb = panels_more.back();
         h->piv_bufs.emplace_back();
@@ -1316,7 +1366,8 @@ hmat_status build_impl(const std::vector<BodyIn>& in, double eta, int32_t leaf, 
                        if (pb.bytes < b) pb.alloc(b, "ACA panels");
                        return pb.as<double>();
                      },
-                     h->piv_bufs.back(), d_rank, d_stop, d_ratio, panel_ptr, true, s);
+                     h->piv_bufs.back(), d_rank, d_stop, d_ratio, panel_ptr, states, zbits, zoff, carry, true,
+                     s);
         h->aca_passes = std::max(h->aca_passes, pass);
         fetch();
       }

@@ -110,6 +110,14 @@ struct DeltaTask {
   int32_t m, n, r0, r1, col0, pad;
 };
 
+// One contiguous copy of `words` 32-bit words (the panels and pivots of a
+// block carried into the next, larger ACA pass).
+struct SpanCopy {
+  const uint32_t* src;
+  uint32_t* dst;
+  int64_t words;
+};
+
 // Compaction of the V factors: copy the first k columns of a scratch panel
 // (n x kcap, leading dimension n) into the panel layout above.
 struct CopyTask {

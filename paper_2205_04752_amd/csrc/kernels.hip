@@ -409,7 +409,8 @@ __device__ __forceinline__ double lane_dot(const double* x, const double* y, int
 //   (row mod 3) are in Z; before that, the next row is the lowest unused row
 //   of the first unvisited component, and a vanishing remainder there passes;
 //   stop: |u_k||v_k| <= eps ||S_k|| (1), k = min(m,n) (2), Z full (3),
-//   panel capacity reached (4: the host re-runs the block with a larger capacity),
+//   panel capacity reached (4: the host resumes the block from its saved
+//   state with a larger capacity; the step's next row is chosen first),
 //   no finite pivot (5: non-finite entries; reported as an error).
 // Panels live in global memory (column-major U m x kcap, V n x kcap); the
 // coefficient row U[i, 0:k] / V[j, 0:k], w = V[:, 0:k]^T v_k and the set Z
@@ -586,7 +587,6 @@ __global__ __launch_bounds__(TPB) void k_aca(DevGeo g0, const AcaTask* __restric
     }
     if (k == kmax) { stop = 2; break; }
     if (nZ == m) { stop = 3; break; }
-    if (k == kcap) { stop = 4; break; }
     if (pending) {
       i = class_probe<TPB>(Z, m, visited, R, ph);
       if (i < 0) { stop = 1; break; }
@@ -597,6 +597,9 @@ __global__ __launch_bounds__(TPB) void k_aca(DevGeo g0, const AcaTask* __restric
         break;
       }
     }
+    // panels full: the saved state holds the next row, and the host resumes
+    // the block there with a larger capacity
+    if (k == kcap) { stop = 4; break; }
     if (T.k_stop > 0 && k >= T.k_stop) {  // paused: the next step starts at row i
       stop = 6;
       break;
@@ -946,6 +949,16 @@ hipError_t launch_aca(const DevGeo& g, const AcaTask* tasks, int ntasks, int n_b
   if (ntasks > n_big)
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_aca<ACA_SMALL_T>), dim3(ntasks - n_big), dim3(ACA_SMALL_T),
                        shmem_small, s, g, tasks + n_big, rank, stop, ratio);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_copy_spans(const SpanCopy* __restrict__ t) {
+  const SpanCopy c = t[blockIdx.x];
+  for (int64_t w = threadIdx.x; w < c.words; w += 256) c.dst[w] = c.src[w];
+}
+
+hipError_t launch_copy_spans(const SpanCopy* t, int n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_copy_spans, dim3(n), dim3(256), 0, s, t);
   return hipGetLastError();
 }
 
