@@ -44,6 +44,10 @@
  *                           hold (default: a quarter of the free device
  *                           memory, at least 1 GiB); smaller budgets run ACA
  *                           in more groups, with the same results;
+ *       HMAT_ACA_KCAP_FIRST first-pass ACA capacity (columns, >= 2; default
+ *                           from eps as stated with aca_passes); blocks that
+ *                           fill it continue in later passes, with the same
+ *                           results;
  *       HMAT_MV_CHUNK_KB    product chunk size for one vector (default 16);
  *       HMAT_MV_UNROLL      columns per batch of the one-vector product
  *                           kernels, 8 or 16 (default 16); hmat_tune sets

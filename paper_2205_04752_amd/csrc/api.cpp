@@ -334,9 +334,11 @@ constexpr int KCAP_FIRST = 128;  // largest first-pass panel capacity (columns) 
 // First-pass capacity for accuracy eps: about twice the largest rank that
 // ACA reaches at that accuracy on the surface meshes here (ranks grow by
 // about six per decade of eps), in multiples of 16, at most KCAP_FIRST. A
-// block that reaches it is run again with capacity min(m, n), so the factors
-// do not depend on this choice; only the panel memory and the reruns do.
+// block that reaches it continues in a later pass with a larger capacity, so
+// the factors do not depend on this choice; only the panel memory and the
+// number of passes do. HMAT_ACA_KCAP_FIRST (>= 2) overrides it.
 int32_t kcap_first(double eps) {
+  if (const char* e = std::getenv("HMAT_ACA_KCAP_FIRST")) return std::max(2, std::atoi(e));
   const double d = -std::log10(eps);
   const int32_t c = 16 * (int32_t)std::ceil((24.0 + 12.0 * d) / 16.0);
   return std::min<int32_t>(KCAP_FIRST, std::max<int32_t>(32, c));

@@ -332,3 +332,35 @@ def test_capacity_passes(name, mesh, eps):
     for r in range(2):
         assert np.linalg.norm(y[r] - yo[r]) <= 1e-10 * np.linalg.norm(yo[r])
     c.g.close()
+
+
+def test_resumed_passes(c0, monkeypatch):
+    """A first-pass capacity of 4 columns (HMAT_ACA_KCAP_FIRST) makes every
+    admissible block of the icosphere L3 case (ranks 9 to 28) continue in a
+    later pass and those above rank 16 in a third (4, 16, 64 columns), each resuming from the state and panel columns the
+    previous one left. The factors must be those of one uninterrupted run:
+    the oracle's pivots and ranks in every admissible block, factors and
+    product within 1e-10."""
+    H = _H()
+    monkeypatch.setenv("HMAT_ACA_KCAP_FIRST", "4")
+    print("case resumed passes: icosphere level 3, eps 1e-4, first capacity 4", flush=True)
+    g = H.HMatrix(c0.V, c0.T, 1.0, 0.3, 2.0, 32, c0.eps)
+    monkeypatch.delenv("HMAT_ACA_KCAP_FIRST")
+    assert g.info()["aca_passes"] >= 3, g.info()["aca_passes"]
+    far = np.nonzero(c0.ob[:, 4] == 1)[0]
+    diverged = []
+    for b in far:
+        gb = g.block(int(b))
+        Uo, Vo, pr, pc = c0.o.factors(int(b))
+        if gb["rank"] != Uo.shape[1] or not (np.array_equal(gb["rows"], pr) and np.array_equal(gb["cols"], pc)):
+            diverged.append(int(b))
+            continue
+        Ao = Uo @ Vo.T
+        assert np.linalg.norm(gb["U"] @ gb["V"].T - Ao) <= 1e-10 * np.linalg.norm(Ao)
+    assert not diverged, f"blocks with divergent pivots: {diverged[:20]} ({len(diverged)} total)"
+    x = W.random_x(c0.N, 2, seed=3)
+    y = g.matvec(_dev(x)).cpu().numpy()
+    yo = c0.o.matvec(x)
+    for r in range(2):
+        assert np.linalg.norm(y[r] - yo[r]) <= 1e-10 * np.linalg.norm(yo[r])
+    g.close()
