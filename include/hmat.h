@@ -53,7 +53,9 @@
  *                           kernels, 8 or 16 (default 16); hmat_tune sets
  *                           both per handle;
  *       HMAT_TRACE_BUILD    if set, print the build's phase times to stderr
- *                           (synchronises the stream at every phase).
+ *                           (synchronises the stream at every phase), and
+ *                           any allocation that found the device full and
+ *                           had to release the kept memory first.
  */
 #ifndef HMAT_H
 #define HMAT_H

@@ -241,9 +241,13 @@ void* mem_alloc(size_t b, hipStream_t s, size_t* cls, int* dev, const char* what
   hipError_t e = hipMallocAsync(&p, cl, s);
   if (e == hipErrorOutOfMemory) {  // hand everything kept back, then try again
     (void)hipGetLastError();
+    const auto t0 = std::chrono::steady_clock::now();
     drop_idle_panels(d, s);
     mem_trim(d, s);
     e = hipMallocAsync(&p, cl, s);
+    if (std::getenv("HMAT_TRACE_BUILD"))
+      std::fprintf(stderr, "hmat memory: %s (%zu bytes) found the device full; releasing kept memory and retrying took %.1f ms\n",
+                   what, cl, std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
   }
   check(e, what);
   *cls = cl;
@@ -1074,10 +1078,12 @@ void run_aca_pass(hmat* h, const std::vector<int32_t>& fidx, CapFn cap, PanelFn 
 // Fill the stream arena from plain column-major sources of the dense blocks
 // (near_src + near_off[i]) and of the U factors (u_ptr[f], leading dimension m).
 void fill_stream(hmat* h, const double* near_src, const std::vector<int64_t>& near_off,
-                 const std::vector<const double*>& u_ptr, hipStream_t s) {
+                 const std::vector<const double*>& u_ptr, hipStream_t s, BuildTrace* tr = nullptr) {
   h->stream.alloc(sizeof(double) * h->stream_n, "product stream");
+  if (tr) tr->mark("  stream: allocation", s);
   // the gaps that align segment starts are never read; keep them zero anyway
   check(hipMemsetAsync(h->stream.p, 0, h->stream.bytes, s), "product stream");
+  if (tr) tr->mark("  stream: zero fill", s);
   auto tasks = stream_tasks(
       h, [&](int32_t b) { return !h->plan.blk[b].far || h->rank[h->kind_index[b]] > 0; },
       [&](int32_t b) -> double* {
@@ -1086,8 +1092,10 @@ void fill_stream(hmat* h, const double* near_src, const std::vector<int64_t>& ne
       });
   DevBuf d_t;
   upload(d_t, tasks, s, "stream tasks");
+  if (tr) tr->mark("  stream: tasks", s);
   check(launch_to_stream(d_t.as<StreamTask>(), (int)tasks.size(), h->stream.as<double>(), s), "stream fill");
   check(hipStreamSynchronize(s), "stream fill");
+  if (tr) tr->mark("  stream: copies", s);
 }
 
 // One body of a build: mesh (HOST, borrowed) and its material and accuracy.
@@ -1445,7 +1453,7 @@ hmat_status build_impl(const std::vector<BodyIn>& in, double eta, int32_t leaf, 
     // product plan, then U factors and dense blocks into the stream arena
     build_product_plan(h, s);
     tr.mark("product plan", s);
-    fill_stream(h, near_stage.as<double>(), near_off, u_ptr, s);
+    fill_stream(h, near_stage.as<double>(), near_off, u_ptr, s, &tr);
     tr.mark("stream fill", s);
     check(hipEventRecord(eva.b, s), "event");
     check(hipStreamSynchronize(s), "build");
