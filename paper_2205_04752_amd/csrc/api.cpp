@@ -1272,10 +1272,12 @@ hmat_status build_impl(const std::vector<BodyIn>& in, double eta, int32_t leaf, 
     d_ratio.alloc(sizeof(double) * std::max<size_t>(nf, 1), "ACA ranks");
     EventPair eva;
     check(hipEventRecord(eva.a, s), "event");
+    std::vector<int32_t> kfirst(h->bodies.size());  // first-pass capacity of each body's blocks
+    for (size_t q = 0; q < h->bodies.size(); q++) kfirst[q] = kcap_first(h->bodies[q].eps);
     auto cap1 = [&](int32_t f) {
       const int32_t b = h->far_blocks[f];
-      const double e = h->bodies[h->pos_body[h->plan.cl[h->plan.blk[b].t].off]].eps;
-      return (int32_t)std::min<int64_t>(std::min(block_m(h, b), block_n(h, b)), kcap_first(e));
+      const int32_t kf = kfirst[h->pos_body[h->plan.cl[h->plan.blk[b].t].off]];
+      return (int32_t)std::min<int64_t>(std::min(block_m(h, b), block_n(h, b)), kf);
     };
     std::vector<int32_t> capv(nf, 0);
     // later passes: four times the previous capacity, at most min(m, n)
