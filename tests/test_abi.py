@@ -30,6 +30,22 @@ def test_exports_every_declared_symbol():
         assert hasattr(L, n), n
 
 
+def test_environment_variables_documented():
+    """Every environment variable the library reads is documented in the
+    header's conventions, and the header documents none it does not read."""
+    csrc = os.path.join(ROOT, "paper_2205_04752_amd", "csrc")
+    read = set()
+    for f in os.listdir(csrc):
+        if f.endswith((".cpp", ".hip", ".hpp")):
+            read |= set(re.findall(r'getenv\("(HMAT_[A-Z0-9_]+)"', open(os.path.join(csrc, f)).read()))
+    hdr = open(os.path.join(ROOT, "include", "hmat.h")).read()
+    env = hdr[hdr.index("Environment"):]
+    env = env[:env.index("*/")]
+    documented = set(re.findall(r"\n \*\s+(HMAT_[A-Z0-9_]+)\s", env))
+    assert read, "no environment variables found"
+    assert read == documented, (sorted(read), sorted(documented))
+
+
 def _mesh_struct(V, T):
     m, keep = H._mesh(V, T)
     return m, keep
