@@ -541,7 +541,7 @@ __global__ __launch_bounds__(TPB) void k_aca(DevGeo g0, const AcaTask* __restric
     }
     for (int l = tid; l < k; l += TPB) coef[l] = V[j + (size_t)l * n];
     __syncthreads();
-    // w = V[:, 0:k]^T v_k: wave w takes l = w, w + NWV, ...
+    // w = V[:, 0:k]^T v_k: wave wv takes l = wv, wv + NWV, ...
     for (int l = wv; l < k; l += NWV) {
       const double b = wave_sum(lane_dot(V + (size_t)l * n, vr, n, lane));
       if (lane == 0) wl[l] = b;
