@@ -142,3 +142,31 @@ def test_flat_geometry_all_components(eps):
     assert np.linalg.norm(y - A @ x) <= 10 * eps * np.linalg.norm(A @ x)
     ob = h.blocks()
     assert int(ob[:, 4].sum()) > 50  # many admissible (coplanar) blocks
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_norm_recurrence_equals_frobenius_norm(seed):
+    """The stopping test compares |u_k||v_k| with eps ||S_k||_F, where ||S_k||_F^2
+    is updated by the recurrence of Sec. 2.2 (previous value, twice the cross
+    terms (u_l.u_k)(v_l.v_k) over l < k, and |u_k|^2 |v_k|^2). The ratio the
+    oracle reports must equal the one computed from the Frobenius norm of
+    U V^T itself. The matrix has a decaying spectrum and non-orthogonal
+    factors, so the cross terms matter: without them (or with the factor 2
+    dropped) the norm would differ by far more than the tolerance."""
+    rng = np.random.default_rng(seed)
+    m, n, r = 60, 45, 30
+    X = rng.standard_normal((m, r)) + 0.8 * rng.standard_normal((m, 1))
+    Y = rng.standard_normal((n, r)) + 0.8 * rng.standard_normal((n, 1))
+    A = (X * 10.0 ** (-0.3 * np.arange(r))) @ Y.T
+    eps = 1e-6
+    res = O.aca_dense(A, eps)
+    assert res["stop"] == 1
+    U, V = res["U"], res["V"]
+    k = U.shape[1]
+    S = U @ V.T
+    lhs = np.linalg.norm(U[:, -1]) * np.linalg.norm(V[:, -1])
+    direct = lhs / (eps * np.linalg.norm(S))
+    assert abs(res["ratio"] - direct) <= 1e-10 * direct
+    # sensitivity: the sum of the rank-one norms alone is far from ||S||_F^2
+    no_cross = sum(np.linalg.norm(U[:, l]) ** 2 * np.linalg.norm(V[:, l]) ** 2 for l in range(k))
+    assert abs(no_cross - np.linalg.norm(S) ** 2) > 1e-6 * np.linalg.norm(S) ** 2
