@@ -108,7 +108,8 @@ typedef struct {
   int32_t n_near_threshold; /* blocks whose final |u||v| / (eps ||S||) lies in [1-1e-9, 1] */
   int32_t aca_passes;     /* ACA passes: 1, or more if some blocks outgrew the rank capacity of
                              the first pass, min(128, max(32, 16 ceil((24 + 12 log10(1/eps)) / 16)))
-                             steps; each later pass has 4x the capacity, at most min(m,n) */
+                             steps; each later pass continues those blocks from where they
+                             stopped with 4x the capacity, at most min(m,n) */
   int32_t reserved;
   double t_plan_ms;       /* host: geometry, tree, partition, device lists */
   double t_near_ms;       /* device: dense blocks (K1) */
