@@ -36,7 +36,8 @@ def amvm(mesh: Mesh, x, theta: float = 0.5, tol: float = 1e-6, max_iter: int = 2
          eta: float = 2.0, leaf: int = 32, kcap: int = 96, lookahead: int = 2, hm=None):
     """Returns (b in the caller's DOF order, history list of dicts with
     'ranks' (per block at A_k, -1 for dense blocks), 'gamma', 'marked',
-    'gamma_rest' (gamma_k(P_k)), 'tau'), and the oracle H-matrix used."""
+    'marked_rows' (the cluster-order row at which each marked block joined
+    P_k), 'gamma_rest' (gamma_k(P_k)), 'tau'), and the oracle H-matrix used."""
     if hm is None:
         hm = HMatrix(mesh, eta, leaf)
         hm.fill_steps(kcap)
@@ -85,7 +86,7 @@ def amvm(mesh: Mesh, x, theta: float = 0.5, tol: float = 1e-6, max_iter: int = 2
         tau = (1.0 - theta) * (csp * M * N) ** -0.5 * gamma
         rec["tau"] = tau
         order_rows = np.argsort(-np.abs(e), kind="stable")
-        marked, rest = [], e.copy()
+        marked, marked_rows, rest = [], [], e.copy()
         in_p = set()
         for i in order_rows:
             added = False
@@ -95,11 +96,13 @@ def amvm(mesh: Mesh, x, theta: float = 0.5, tol: float = 1e-6, max_iter: int = 2
                 if abs(d[b][i - rows[b].start]) >= tau:
                     in_p.add(b)
                     marked.append(b)
+                    marked_rows.append(int(i))
                     rest[rows[b]] -= d[b]
                     added = True
             if added and np.linalg.norm(rest) <= (1.0 - theta) * gamma:
                 break
         rec["marked"] = marked
+        rec["marked_rows"] = marked_rows
         rec["gamma_rest"] = float(np.linalg.norm(rest))
         for b in marked:
             bk[rows[b]] += d[b]

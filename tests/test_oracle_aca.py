@@ -170,3 +170,27 @@ def test_norm_recurrence_equals_frobenius_norm(seed):
     # sensitivity: the sum of the rank-one norms alone is far from ||S||_F^2
     no_cross = sum(np.linalg.norm(U[:, l]) ** 2 * np.linalg.norm(V[:, l]) ** 2 for l in range(k))
     assert abs(no_cross - np.linalg.norm(S) ** 2) > 1e-6 * np.linalg.norm(S) ** 2
+
+
+def test_pivot_ties_take_the_lowest_index():
+    """Reading of the argmax (no tie rule in Algorithm 1): among entries whose
+    magnitude is within a relative 1e-10 of the maximum, the lowest index is the
+    pivot, for the column j_k as for the next row i_{k+1}. The matrix is
+    a b^T + c d^T with near-ties placed so that the plain argmax, the highest
+    tied index and the lowest tied index all differ, and an entry just outside
+    the 1e-10 band that must not be taken."""
+    a = np.array([1.0, 0.2, 0.9 * (1 - 1e-13), -0.9, 0.4, 0.9 * (1 - 1e-12)])
+    b = np.array([0.3, -(1 - 1e-12), 0.5, -0.2, 1.0, 1 - 1e-8, 0.1])
+    c = np.array([0.0, 0.5, 1.0, -0.3, 0.2, 0.6])
+    d = np.array([0.7 * (1 - 1e-11), 0.0, -0.7, 0.7, 0.1, 0.2, 0.3])
+    A = np.outer(a, b) + np.outer(c, d)
+    r = O.aca_dense(A, 1e-14)
+    # row 0 = b: maximum at column 4, near-tie at column 1 (lower), column 5
+    # is 1e-8 below the maximum (outside the band)
+    assert r["cols"][0] == 1
+    # u_1 = A[:, 1] = a b_1: rows 2, 3, 5 tie (row 3 largest), row 0 is in Z
+    assert r["rows"][1] == 2
+    # remainder row 2 = c_2 d: columns 0, 2, 3 tie up to rounding
+    assert r["cols"][1] == 0
+    assert r["U"].shape[1] == 2
+    assert np.linalg.norm(A - r["U"] @ r["V"].T) <= 1e-13 * np.linalg.norm(A)

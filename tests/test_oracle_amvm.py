@@ -158,3 +158,90 @@ def test_convergence_and_estimator_quality(small):
             ratios.append(rec["gamma"] / err)
     ratios = np.array(ratios[2:])  # after the first rounds (saturation regime)
     assert np.mean((ratios >= 0.5) & (ratios <= 2.0)) >= 0.8, ratios
+
+
+def test_estimator_within_factor_two_once_accurate(small):
+    """The paper's efficiency figure (Sec. 6.1) shows gamma_k / ||b - b_k|| inside
+    [1/2, 2] at every point of its range (errors from about 3e-4 down); here every
+    round whose error against the exact collocation product is below 1e-3
+    relative must lie in that band, and there must be many such rounds."""
+    V, T, mesh = small
+    x = _point_force_x(V, T)
+    bt = mesh.dense() @ x
+    y, hist, hm = amvm(mesh, x, theta=0.5, tol=1e-8, leaf=16, kcap=96)
+    ob, far = _dense_blocks(hm)
+    seen = 0
+    for k, rec in enumerate(hist):
+        Ak, perm = _assemble(hm, ob, far, rec["ranks"])
+        bk = np.zeros_like(x)
+        bk[perm] = Ak @ x[perm]
+        err = np.linalg.norm(bk - bt)
+        if err <= 1e-3 * np.linalg.norm(bt):
+            seen += 1
+            assert 0.5 <= rec["gamma"] / err <= 2.0, (k, rec["gamma"], err)
+    assert seen >= 10, seen
+
+
+def test_marking_stops_at_first_row(small):
+    """Algorithm 2, step 3: rows are taken in decreasing |(b^_k - b_k)_i|; along
+    them every block with a row entry at or above the threshold joins P_k, and
+    marking ends at the first row after which gamma_k(P_k) <= (1 - theta) gamma_k
+    (the minimal-cardinality set of the algorithm). Everything is recomputed here
+    from dense block products: the row errors, each block's contribution, the
+    Doerfler test after every row group, and completeness above the last row."""
+    V, T, mesh = small
+    x = _point_force_x(V, T)
+    theta = 0.5
+    y, hist, hm = amvm(mesh, x, theta=theta, tol=1e-7, leaf=16, kcap=96)
+    ob, far = _dense_blocks(hm)
+    fars = np.nonzero(ob[:, 4] == 1)[0]
+    checked = 0
+    for k, rec in enumerate(hist):
+        if not rec["marked"]:
+            continue
+        Ak, perm = _assemble(hm, ob, far, rec["ranks"])
+        Ah, _ = _assemble(hm, ob, far, rec["ranks"], extra=2)
+        xp = x[perm]
+        D = Ah - Ak
+        e = D @ xp
+        gk = np.linalg.norm(e)
+        contrib = {}
+        for b in fars:
+            rs = slice(3 * ob[b, 0], 3 * (ob[b, 0] + ob[b, 1]))
+            cs = slice(3 * ob[b, 2], 3 * (ob[b, 2] + ob[b, 3]))
+            contrib[int(b)] = (rs, D[rs, cs] @ xp[cs])
+        rows = rec["marked_rows"]
+        assert len(rows) == len(rec["marked"])
+        groups = []  # (row, [blocks]) in marking order
+        for b, i in zip(rec["marked"], rows):
+            if groups and groups[-1][0] == i:
+                groups[-1][1].append(b)
+            else:
+                groups.append((i, [b]))
+        # rows in decreasing |e_i|, each visited once
+        r = [g[0] for g in groups]
+        assert len(set(r)) == len(r)
+        for a, c in zip(r, r[1:]):
+            assert abs(e[c]) <= abs(e[a]) * (1 + 1e-12) + 1e-300, (k, a, c)
+        # the Doerfler test fails after every row group but the last
+        rest = e.copy()
+        for gi, (i, bs) in enumerate(groups):
+            for b in bs:
+                rs, db = contrib[b]
+                assert abs(db[i - rs.start]) >= rec["tau"] * (1 - 1e-12)
+                rest[rs] -= db
+            nr = np.linalg.norm(rest)
+            if gi + 1 < len(groups):
+                assert nr > (1 - theta) * gk * (1 + 1e-12), (k, gi, nr, gk)
+            else:
+                assert nr <= (1 - theta) * gk * (1 + 1e-10), (k, nr, gk)
+        # completeness: above the last row, no block over the threshold is left out
+        last = abs(e[r[-1]])
+        marked = set(rec["marked"])
+        for b, (rs, db) in contrib.items():
+            if b in marked:
+                continue
+            big = np.abs(e[rs]) > last * (1 + 1e-9)
+            assert not np.any(big & (np.abs(db) >= rec["tau"] * (1 + 1e-9))), (k, b)
+        checked += 1
+    assert checked >= 3
