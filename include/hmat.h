@@ -217,6 +217,32 @@ hmat_status hmat_solve(hmat_t h, const double* b, double* x, double tol, int32_t
                        int32_t maxit, void* hip_stream, hmat_solve_info* info);
 
 /*
+ * hmat_solve_noalloc -- hmat_solve for callers that cannot allocate memory
+ * (no hipMalloc, hipFree, pinned host allocation or event creation during
+ * the call: harnesses that forbid allocation, serving loops that must not
+ * touch the allocator). Same arguments, results and errors as hmat_solve,
+ * bit for bit (the same kernels in the same order).
+ * Workspace: the Krylov basis, the work vector, the partial sums and the
+ * Hessenberg columns live in one fixed device array of 32 MiB per device,
+ * part of the library's code object (held from the library's first use on a
+ * device until the process ends); the Hessenberg columns come back through
+ * ordinary host memory on the calling thread's stack, so every Arnoldi step
+ * synchronises the stream (hmat_solve overlaps the host's Givens update
+ * with the next step instead).
+ * Limit: 8 * (n_dof * (restart + 1) + n_dof + partial sums + 4112) bytes,
+ * each part rounded to 256 bytes, must fit 32 MiB (GMRES(50) up to 80418
+ * DOF, GMRES(20) up to 190072); larger requests return
+ * HMAT_EINVAL with the sizes in the message, before any device work.
+ * Concurrency: every call on a device shares that device's array, which
+ * keeps the last call's contents (nothing in it needs to start at zero).
+ * Calls that overlapped on one device would race on it, so the library
+ * runs one such call at a time in a process (a second caller waits).
+ * hmat_profile's per-phase events are not recorded by this call.
+ */
+hmat_status hmat_solve_noalloc(hmat_t h, const double* b, double* x, double tol, int32_t restart,
+                               int32_t maxit, void* hip_stream, hmat_solve_info* info);
+
+/*
  * hmat_set_precision -- reduced-precision storage of the H-matrix entries.
  * precision 1 makes FP32 copies of the stored low-rank factors and dense
  * blocks (same layout; FP64 values rounded to nearest) next to the FP64

@@ -76,7 +76,7 @@ class _Result(C.Structure):
 
 
 EXPORTS = ["hmat_build", "hmat_build_batch", "hmat_bodies", "hmat_matvec", "hmat_matvec_ex",
-           "hmat_solve", "hmat_solve_ir", "hmat_set_precision", "hmat_info", "hmat_free",
+           "hmat_solve", "hmat_solve_noalloc", "hmat_solve_ir", "hmat_set_precision", "hmat_info", "hmat_free",
            "hmat_last_error", "hmat_plan", "hmat_block", "hmat_entries", "hmat_set_factors",
            "hmat_profile", "hmat_tune", "hmat_matvec_graph", "hmat_amvm", "hmat_server_create", "hmat_server_submit", "hmat_server_wait",
            "hmat_server_destroy", "hmat_server_last_error", "hmat_release_memory"]
@@ -103,6 +103,7 @@ def lib():
     L.hmat_bodies.argtypes = [vp, C.POINTER(i32), vp]
     L.hmat_matvec.argtypes = [vp, i32, vp, i64, vp, i64, vp]
     L.hmat_solve.argtypes = [vp, vp, vp, dbl, i32, i32, vp, C.POINTER(_SolveInfo)]
+    L.hmat_solve_noalloc.argtypes = [vp, vp, vp, dbl, i32, i32, vp, C.POINTER(_SolveInfo)]
     L.hmat_solve_ir.argtypes = [vp, vp, vp, dbl, i32, i32, i32, dbl, vp, C.POINTER(_SolveInfo)]
     L.hmat_set_precision.argtypes = [vp, i32, vp]
     L.hmat_matvec_ex.argtypes = [vp, i32, i32, vp, i64, vp, i64, vp]
@@ -309,16 +310,19 @@ class HMatrix:
                            relres=info.relres, time_ms=info.time_ms,
                            refinements=info.refinements)
 
-    def solve(self, b, x=None, tol=1e-8, restart=50, maxit=10000, stream=None, check=True):
-        """GMRES(restart) for A_H x = b; returns (x, info dict)."""
+    def solve(self, b, x=None, tol=1e-8, restart=50, maxit=10000, stream=None, check=True,
+              noalloc=False):
+        """GMRES(restart) for A_H x = b; returns (x, info dict). noalloc=True calls
+        hmat_solve_noalloc (fixed per-device workspace; x must then be given
+        to avoid an allocation here)."""
         import torch
         b2, bp, _ = _dev_ptr(b, self.n_dof, "b")
         if x is None:
             x = torch.empty_like(b2[0])
         x2, xp, _ = _dev_ptr(x, self.n_dof, "x")
         info = _SolveInfo()
-        st = lib().hmat_solve(self._h, bp, xp, float(tol), int(restart), int(maxit),
-                              _stream(stream), C.byref(info))
+        fn = lib().hmat_solve_noalloc if noalloc else lib().hmat_solve
+        st = fn(self._h, bp, xp, float(tol), int(restart), int(maxit), _stream(stream), C.byref(info))
         if st not in (HMAT_OK, HMAT_ENOCONV) or (check and st != HMAT_OK):
             _check(st)
         return x2[0], dict(status=st, iterations=info.iterations, restarts=info.restarts,

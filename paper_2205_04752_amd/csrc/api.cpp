@@ -49,6 +49,7 @@ hipError_t launch_dense_mv(const DenseMvTask*, int, const double*, const double*
 hipError_t launch_lowrank_delta(const DeltaTask*, int, const double*, double*, hipStream_t);
 hipError_t launch_amvm_rowsum(const int64_t*, const int32_t*, const char*, const int64_t*, const int64_t*,
                               const double*, int64_t, double*, hipStream_t);
+hipError_t noalloc_workspace(double**);
 }  // namespace hm
 
 using namespace hm;
@@ -1494,12 +1495,14 @@ void prof_collect(hmat* h) {
   h->prof_pending.clear();
 }
 
+// allow_prof = false: no per-phase events even while hmat_profile is on
+// (the allocation-free solve creates no events).
 void matvec_impl(hmat* h, int prec, int32_t nrhs, const double* x, int64_t ldx, double* y,
-                 int64_t ldy, hipStream_t s) {
+                 int64_t ldy, hipStream_t s, bool allow_prof = true) {
   for (int32_t r0 = 0; r0 < nrhs; r0 += MV_MAX_NR) {
     const int nr = std::min<int32_t>(MV_MAX_NR, nrhs - r0);
     hipEvent_t* ev = nullptr;
-    if (h->prof) {
+    if (h->prof && allow_prof) {
       if (h->prof_pending.size() >= 4096) prof_collect(h);
       std::array<hipEvent_t, 5> e{};
       for (auto& q : e) check(hipEventCreate(&q), "profile");
@@ -1566,10 +1569,39 @@ void copy_stream_out(const hmat* h, int32_t b, int64_t m, int64_t cols, double* 
 // HMAT_OK or HMAT_ENOCONV; throws HipError on device errors.
 constexpr int GM_COL = 1026;  // stride of a Hessenberg column buffer (restart <= 1024)
 
+// Buffers of one GMRES(m) run: device Q (n_dof x (m+1)), w (n_dof), the
+// partial sums (dots_part_size(n_dof, m+1) + norm_part_size(n_dof)) and the
+// small buffer (4 GM_COL + 8); host: 3 GM_COL doubles for the Hessenberg
+// columns and the update coefficients. With the two events the host reads
+// column j while the device runs step j+1 (the host buffer is then pinned);
+// without them every column copy is followed by a stream synchronisation.
+struct GmresWs {
+  double* Q = nullptr;
+  double* w = nullptr;
+  double* dotpart = nullptr;
+  double* small = nullptr;
+  double* host = nullptr;
+  hipEvent_t* ev = nullptr;
+};
+
+size_t gmres_ws_doubles(int64_t N, int m, size_t* off) {
+  auto up = [](size_t v) { return (v + 31) / 32 * 32; };  // 256-byte starts
+  size_t o = 0;
+  off[0] = o;  // Q
+  o += up((size_t)N * (m + 1));
+  off[1] = o;  // w
+  o += up((size_t)N);
+  off[2] = o;  // dot and norm partial sums
+  o += up(dots_part_size(N, m + 1) + norm_part_size(N));
+  off[3] = o;  // small
+  o += up(4 * GM_COL + 8);
+  return o;
+}
+
 // GMRES(m) workspace of the handle (grown, never shrunk). Allocation happens
 // here, before any solve enqueues work, so no buffer is freed under a
 // running kernel.
-void ensure_gmres_ws(hmat* h, int m) {
+GmresWs ensure_gmres_ws(hmat* h, int m) {
   const int64_t N = h->N;
   if (h->q_cols < m + 1) {
     h->d_Q.alloc(sizeof(double) * N * (m + 1), "GMRES basis");
@@ -1585,26 +1617,34 @@ void ensure_gmres_ws(hmat* h, int m) {
   }
   for (hipEvent_t& e : h->col_ev)
     if (!e) check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "GMRES event");
+  GmresWs ws;
+  ws.Q = h->d_Q.as<double>();
+  ws.w = h->d_w.as<double>();
+  ws.dotpart = h->d_dotpart.as<double>();
+  ws.small = h->d_small.as<double>();
+  ws.host = h->h_pinned;
+  ws.ev = h->col_ev;
+  return ws;
 }
 
-hmat_status gmres_impl(hmat* h, int prec, const double* b, double* x, double tol, int m,
-                       int maxit, hipStream_t s, int* used_out, int* restarts_out,
+hmat_status gmres_impl(hmat* h, int prec, const GmresWs& ws, const double* b, double* x, double tol,
+                       int m, int maxit, hipStream_t s, int* used_out, int* restarts_out,
                        double* rel_out) {
   const int64_t N = h->N;
   constexpr int COL = GM_COL;
-    ensure_gmres_ws(h, m);
+    const bool piped = ws.ev != nullptr;
     const size_t dp = dots_part_size(N, m + 1);
-    double* dotpart = h->d_dotpart.as<double>();
+    double* dotpart = ws.dotpart;
     double* normpart = dotpart + dp;
-    double* Q = h->d_Q.as<double>();
-    double* w = h->d_w.as<double>();
-    double* base = h->d_small.as<double>();
+    double* Q = ws.Q;
+    double* w = ws.w;
+    double* base = ws.small;
     double* hvec = base;                             // coefficients of one Gram-Schmidt pass
     double* hacc[2] = {base + COL, base + 2 * COL};  // Hessenberg columns, double-buffered
     double* ycoef = base + 3 * COL;                  // [m]
     double* scal = ycoef + COL;                      // scalars
-    double* hcol_host[2] = {h->h_pinned, h->h_pinned + COL};
-    double* y_host = h->h_pinned + 2 * COL;
+    double* hcol_host[2] = {ws.host, ws.host + COL};
+    double* y_host = ws.host + 2 * COL;
     auto norm_host = [&](const double* v) {
       check(launch_norm(v, N, normpart, scal, s), "norm");
       check(hipMemcpyAsync(y_host, scal, sizeof(double), hipMemcpyDeviceToHost, s), "norm");
@@ -1616,7 +1656,7 @@ hmat_status gmres_impl(hmat* h, int prec, const double* b, double* x, double tol
     // asynchronous copy of the column to pinned host memory (event col_ev[j % 2]).
     auto enqueue_step = [&](int j) {
       double* col = hacc[j % 2];
-      matvec_impl(h, prec, 1, Q + (size_t)j * N, N, w, N, s);
+      matvec_impl(h, prec, 1, Q + (size_t)j * N, N, w, N, s, piped);
       for (int pass = 0; pass < 2; pass++)
         check(launch_cgs_pass(Q, N, N, j + 1, w, dotpart, hvec, col, pass == 0,
                               pass == 1 ? normpart : nullptr, s),
@@ -1624,7 +1664,10 @@ hmat_status gmres_impl(hmat* h, int prec, const double* b, double* x, double tol
       check(launch_scale_norm(w, N, normpart, col + j + 1, Q + (size_t)(j + 1) * N, s), "scale");
       check(hipMemcpyAsync(hcol_host[j % 2], col, sizeof(double) * (j + 2), hipMemcpyDeviceToHost, s),
             "hessenberg");
-      check(hipEventRecord(h->col_ev[j % 2], s), "hessenberg");
+      if (piped)
+        check(hipEventRecord(ws.ev[j % 2], s), "hessenberg");
+      else
+        check(hipStreamSynchronize(s), "hessenberg");
     };
     check(launch_fill(x, N, 0.0, s), "fill");
     const double bn = norm_host(b);
@@ -1637,7 +1680,7 @@ hmat_status gmres_impl(hmat* h, int prec, const double* b, double* x, double tol
       rel = 0.0;
     } else {
       for (;;) {
-        matvec_impl(h, prec, 1, x, N, w, N, s);
+        matvec_impl(h, prec, 1, x, N, w, N, s, piped);
         check(launch_residual(b, N, w, s), "residual");
         const double beta = norm_host(w);
         rel = beta / bn;
@@ -1662,7 +1705,7 @@ hmat_status gmres_impl(hmat* h, int prec, const double* b, double* x, double tol
             enqueue_step(j + 1);
             launched++;
           }
-          check(hipEventSynchronize(h->col_ev[j % 2]), "hessenberg");
+          if (piped) check(hipEventSynchronize(ws.ev[j % 2]), "hessenberg");
           const double* col = hcol_host[j % 2];
           for (int i = 0; i <= j + 1; i++) H[(size_t)i * m + j] = col[i];
           const double hn = col[j + 1];
@@ -1692,6 +1735,7 @@ hmat_status gmres_impl(hmat* h, int prec, const double* b, double* x, double tol
         check(hipStreamSynchronize(s), "update");
         std::memcpy(y_host, yv.data(), sizeof(double) * j);
         check(hipMemcpyAsync(ycoef, y_host, sizeof(double) * j, hipMemcpyHostToDevice, s), "update");
+        if (!piped) check(hipStreamSynchronize(s), "update");  // y_host is ordinary host memory
         check(launch_add_comb(Q, N, N, j, ycoef, x, s), "update");
         restarts++;
       }
@@ -2259,7 +2303,52 @@ hmat_status hmat_solve(hmat_t h, const double* b, double* x, double tol, int32_t
   try {
     int used = 0, restarts = 0;
     double rel = 0.0;
-    st = gmres_impl(h, 0, b, x, tol, restart, maxit, s, &used, &restarts, &rel);
+    const GmresWs ws = ensure_gmres_ws(h, restart);
+    st = gmres_impl(h, 0, ws, b, x, tol, restart, maxit, s, &used, &restarts, &rel);
+    if (info) {
+      info->iterations = used;
+      info->restarts = restarts;
+      info->relres = rel;
+      info->time_ms = ms_since(t0);
+      info->refinements = 0;
+    }
+    if (st != HMAT_OK) return fail(st, "GMRES reached maxit before tol");
+    return HMAT_OK;
+  } catch (const HipError& e) {
+    (void)hipStreamSynchronize(s);
+    return fail(e.st, e.msg);
+  }
+}
+
+hmat_status hmat_solve_noalloc(hmat_t h, const double* b, double* x, double tol, int32_t restart,
+                               int32_t maxit, void* hip_stream, hmat_solve_info* info) {
+  hmat_status st = check_solve_args(h, b, x, tol, restart, maxit);
+  if (st != HMAT_OK) return st;
+  size_t off[4];
+  const size_t need = gmres_ws_doubles(h->N, restart, off);
+  if (need > NOALLOC_DOUBLES)
+    return fail(HMAT_EINVAL, "hmat_solve_noalloc: n_dof x (restart + 1) exceeds the fixed workspace (" +
+                                 std::to_string(need * 8) + " bytes needed, " +
+                                 std::to_string(NOALLOC_DOUBLES * 8) + " available)");
+  hipStream_t s = (hipStream_t)hip_stream;
+  h->last_stream = s;
+  auto t0 = std::chrono::steady_clock::now();
+  // one call at a time per process: every call on a device uses its array
+  static std::mutex mu;
+  std::lock_guard<std::mutex> lk(mu);
+  try {
+    double* base = nullptr;
+    check(noalloc_workspace(&base), "fixed workspace");
+    std::array<double, 3 * GM_COL> host{};
+    GmresWs ws;
+    ws.Q = base + off[0];
+    ws.w = base + off[1];
+    ws.dotpart = base + off[2];
+    ws.small = base + off[3];
+    ws.host = host.data();
+    int used = 0, restarts = 0;
+    double rel = 0.0;
+    st = gmres_impl(h, 0, ws, b, x, tol, restart, maxit, s, &used, &restarts, &rel);
     if (info) {
       info->iterations = used;
       info->restarts = restarts;
@@ -2294,7 +2383,7 @@ hmat_status hmat_solve_ir(hmat_t h, const double* b, double* x, double tol, int3
     if (h->d_ir.bytes < sizeof(double) * 2 * N) h->d_ir.alloc(sizeof(double) * 2 * N, "refinement work");
     double* r = h->d_ir.as<double>();
     double* d = r + N;
-    ensure_gmres_ws(h, restart);
+    const GmresWs ws = ensure_gmres_ws(h, restart);
     auto norm_host = [&](const double* v) {
       check(launch_norm(v, N, h->d_dotpart.as<double>(), h->d_small.as<double>(), s), "norm");
       check(hipMemcpyAsync(h->h_pinned, h->d_small.p, sizeof(double), hipMemcpyDeviceToHost, s), "norm");
@@ -2325,7 +2414,7 @@ hmat_status hmat_solve_ir(hmat_t h, const double* b, double* x, double tol, int3
         const double itol = std::max(inner_tol, 0.5 * tol * bn / rn);
         int u = 0, rs = 0;
         double irel = 0.0;
-        (void)gmres_impl(h, inner_precision, r, d, itol, restart, maxit - used, s, &u, &rs, &irel);
+        (void)gmres_impl(h, inner_precision, ws, r, d, itol, restart, maxit - used, s, &u, &rs, &irel);
         used += u;
         restarts += rs;
         outer++;

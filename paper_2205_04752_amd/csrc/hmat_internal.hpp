@@ -48,6 +48,10 @@ constexpr int ACA_SMALL_TRI = 64;
 // its remainder in LDS as well as in the panels, so the pivot searches,
 // the normalisation and the norm update of a step read them from LDS.
 constexpr int ACA_STAGE_MAX = 7936;
+// Size (doubles) of the per-device workspace of the allocation-free solve:
+// 32 MiB, enough for GMRES(50) at 61440 DOF (Krylov basis, work vector,
+// partial sums and Hessenberg columns).
+constexpr size_t NOALLOC_DOUBLES = size_t(4) << 20;
 // Dynamic LDS (bytes) of the ACA kernel for one block: the coefficient row
 // and the cross-term weights (kcap doubles each), the row set Z (m bits, in 32-bit words, padded to a
 // double) and, if staged, the newest row and column (n + m doubles).

@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <climits>
+#include <mutex>
 
 #include "device_common.hpp"
 #include "hmat_internal.hpp"
@@ -1029,6 +1030,38 @@ hipError_t launch_axpy(double a, const double* x, int64_t n, double* y, hipStrea
 hipError_t launch_fill(double* x, int64_t n, double v, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_fill, dim3(blocks_for(n, 256)), dim3(256), 0, s, x, n, v);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Workspace of the allocation-free solve (hmat_solve_noalloc): one fixed
+// array per device, loaded with the code object and held until the process
+// ends. Host code never passes the array's name to a kernel (on the host it
+// is only a stand-in for the symbol); it passes the device address that
+// hipGetSymbolAddress returns, resolved once per device with that device
+// current.
+static __device__ __align__(256) double scratch[NOALLOC_DOUBLES];
+
+namespace {
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[64] = {};
+}  // namespace
+
+hipError_t noalloc_workspace(double** out) {
+  *out = nullptr;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
 }
 
 }  // namespace hm

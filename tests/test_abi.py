@@ -146,6 +146,7 @@ def test_other_entry_points_reject_null_handle():
     L = H.lib()
     assert L.hmat_matvec(None, 1, None, 3, None, 3, None) == H.HMAT_EINVAL
     assert L.hmat_solve(None, None, None, 1e-8, 50, 10, None, None) == H.HMAT_EINVAL
+    assert L.hmat_solve_noalloc(None, None, None, 1e-8, 50, 10, None, None) == H.HMAT_EINVAL
     assert L.hmat_info(None, None) == H.HMAT_EINVAL
     assert L.hmat_block(None, 0, None, None, None, None, None) == H.HMAT_EINVAL
     assert L.hmat_entries(None, 0, None, None, None, None) == H.HMAT_EINVAL
