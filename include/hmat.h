@@ -400,7 +400,14 @@ hmat_status hmat_tune(hmat_t h, int32_t nrhs, int32_t reps, void* hip_stream, hm
  * sequence A_k shares the tree and partition of hmat_build (eta, leaf); its
  * dense blocks are exact, and every admissible block starts at rank 0. The
  * look-ahead A^_k takes two more ACA steps on every admissible block; ACA is
- * resumed from saved state, with no accuracy test of its own. Each round:
+ * resumed from saved state, with no accuracy test of its own, and its pivot
+ * rows cycle through the three displacement components: after a step at row
+ * i the next row comes from the next component (i+1, i+2, i mod 3) with
+ * unused rows, as the largest |u_l| there of the latest cross u_l that has
+ * entries above 1e-12 of its maximum on those rows, else their lowest row.
+ * (On coplanar clusters the in-plane and normal components decouple; plain
+ * partial pivoting would never sample the normal one, and the estimator
+ * would miss its error.) Each round:
  *   - d_b = (A^_k - A_k)_b x_s for every admissible block;
  *   - gamma_k = ||b_k - b^_k||_2 = ||sum_b d_b||;
  *   - rows are visited in decreasing |(b^_k - b_k)_i|, and a block containing

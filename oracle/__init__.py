@@ -46,6 +46,9 @@ def lib():
     L.or_aca_dense.restype = C.c_int
     L.or_aca_dense.argtypes = [C.c_int, C.c_int, _dp, C.c_double, _dp, _dp, _ip, _ip,
                                C.POINTER(C.c_int), C.POINTER(C.c_double)]
+    L.or_aca_dense_steps.restype = C.c_int
+    L.or_aca_dense_steps.argtypes = [C.c_int, C.c_int, _dp, C.c_int, C.c_int, _dp, _dp, _ip, _ip,
+                                     C.POINTER(C.c_int)]
     L.or_h_plan.restype = vp
     L.or_h_plan.argtypes = [vp, C.c_double, C.c_int]
     L.or_h_fill.restype = C.c_int
@@ -122,6 +125,23 @@ def aca_dense(A: np.ndarray, eps: float):
     k = lib().or_aca_dense(m, n, A, float(eps), U, V, pr, pc, C.byref(st), C.byref(ra))
     return dict(U=U[: m * k].reshape(k, m).T.copy(), V=V[: n * k].reshape(k, n).T.copy(),
                 rows=pr[:k].copy(), cols=pc[:k].copy(), stop=st.value, ratio=ra.value)
+
+
+def aca_dense_steps(A: np.ndarray, kcap: int, ncls: int = 3):
+    """Step-limited ACA (no accuracy test, class-cycling rows; the adaptive
+    multiplication's look-ahead) on a dense matrix whose row i is in class
+    i mod ncls. Returns dict(U, V, rows, cols, stop)."""
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    m, n = A.shape
+    kmax = min(m, n, kcap)
+    U = np.zeros(m * kmax)
+    V = np.zeros(n * kmax)
+    pr = np.zeros(kmax, dtype=np.int32)
+    pc = np.zeros(kmax, dtype=np.int32)
+    st = C.c_int(0)
+    k = lib().or_aca_dense_steps(m, n, A, int(kcap), int(ncls), U, V, pr, pc, C.byref(st))
+    return dict(U=U[: m * k].reshape(k, m).T.copy(), V=V[: n * k].reshape(k, n).T.copy(),
+                rows=pr[:k].copy(), cols=pc[:k].copy(), stop=st.value)
 
 
 class Mesh:

@@ -21,7 +21,11 @@ ordinary build; only the ranks of the admissible blocks change.
   * Stop when gamma_k <= tol ||b^_k||_2 (reading: the tolerance is relative)
     or after max_iter rounds; the result is b_k.
 ACA crosses come from ``HMatrix.fill_steps(kcap)``: ACA without the accuracy
-test, so the first r crosses of a block are those of r resumed steps. A block
+test, so the first r crosses of a block are those of r resumed steps. Its
+pivot rows cycle through the three displacement components (the oracle's
+cycle_next rule): with no accuracy test, nothing else would send ACA to the
+normal component of a coplanar block, whose error the estimator would then
+never see. A block
 that is exhausted (full rank, every row used, or kcap reached) has no further
 crosses and contributes nothing more.
 """

@@ -366,6 +366,8 @@ void or_brute_matvec_rows(const or_ctx* c, int nrows, const int* tri_rows, int n
  *     passed. (On coplanar clusters the Kelvin tensor decouples into
  *     in-plane and normal parts, and pivoting that never visits one class
  *     would miss its part of the block.)
+ *   - cycle = 1 (step-limited runs only, eps = 0): the row rule of
+ *     cycle_next below replaces partial pivoting and the class probes.
  * U is m x k and V is n x k, both column-major, returned through *pU / *pV
  * (malloc'd, grown as needed). Pivots are recorded in prow/pcol (capacity
  * min(m,n)). stop: 1 = threshold, 2 = rank = min(m,n), 3 = Z full. */
@@ -393,8 +395,44 @@ static int class_probe(const unsigned char* Z, int m, int ncls, int visited) {
   return -1;
 }
 
+/* Row rule of the step-limited runs (cycle = 1; the adaptive
+ * multiplication's look-ahead, which has no accuracy test that could send ACA
+ * to an unvisited class): the rows cycle through the classes. After a step at
+ * row i -- a new cross, or a row whose remainder vanished -- the next row
+ * comes from the first class c among i+1, i+2, i (mod ncls) that still has
+ * rows outside Z: the fuzzy argmax over those rows of |u_l|, where u_l is the
+ * latest cross whose largest magnitude on those rows exceeds 1e-12 times its
+ * largest magnitude over all rows; if no cross qualifies, the lowest of
+ * those rows. Returns -1 when Z holds every row. On coplanar clusters the
+ * classes of the in-plane and normal components are decoupled, and each
+ * gets its share of the steps; on coupled blocks u_l is the latest cross, as
+ * in plain partial pivoting, restricted to the class. */
+static int cycle_next(const double* U, int k, int m, const unsigned char* Z, int ncls, int i) {
+  for (int dc = 1; dc <= ncls; dc++) {
+    const int c = (i % ncls + dc) % ncls;
+    int lowest = -1;
+    for (int r = c; r < m; r += ncls)
+      if (!Z[r]) { lowest = r; break; }
+    if (lowest < 0) continue;
+    for (int l = k - 1; l >= 0; l--) {
+      const double* u = U + (size_t)l * m;
+      double all = 0.0, cls = 0.0;
+      for (int r = 0; r < m; r++)
+        if (fabs(u[r]) > all) all = fabs(u[r]);
+      for (int r = c; r < m; r += ncls)
+        if (!Z[r] && fabs(u[r]) > cls) cls = fabs(u[r]);
+      if (!(cls > 1e-12 * all)) continue;
+      const double thr = (1.0 - 1e-10) * cls;
+      for (int r = c; r < m; r += ncls)
+        if (!Z[r] && fabs(u[r]) >= thr) return r;
+    }
+    return lowest;
+  }
+  return -1;
+}
+
 static int aca_core(int m, int n, or_rowfn rowf, or_colfn colf, void* user, double eps,
-                    int kcap, int ncls, double** pU, double** pV, int* prow, int* pcol,
+                    int kcap, int ncls, int cycle, double** pU, double** pV, int* prow, int* pcol,
                     int* stop, double* ratio) {
   int kmax = m < n ? m : n;
   const int allcls = (1 << ncls) - 1;
@@ -424,7 +462,9 @@ static int aca_core(int m, int n, or_rowfn rowf, or_colfn colf, void* user, doub
     if (vanished) {
       if (nZ == m) { *stop = 3; break; }
       if (pending && visited == allcls) { *stop = 1; break; }
-      if (pending) {
+      if (cycle) {
+        i = cycle_next(U, k, m, Z, ncls, i);
+      } else if (pending) {
         i = class_probe(Z, m, ncls, visited);
         if (i < 0) { *stop = 1; break; }
       } else if (k == 0) {
@@ -474,7 +514,9 @@ static int aca_core(int m, int n, or_rowfn rowf, or_colfn colf, void* user, doub
     if (k == kmax) { *stop = 2; break; }
     if (nZ == m) { *stop = 3; break; }
     if (kcap > 0 && k == kcap) { *stop = 4; break; }
-    if (pending) {
+    if (cycle) {
+      i = cycle_next(U, k, m, Z, ncls, i);
+    } else if (pending) {
       i = class_probe(Z, m, ncls, visited);
       if (i < 0) { *stop = 1; break; }
     } else {
@@ -502,7 +544,23 @@ int or_aca_dense(int m, int n, const double* A, double eps, double* U, double* V
                  int* pcol, int* stop, double* ratio) {
   dense_src s = {m, n, A};
   double *Ui, *Vi;
-  int k = aca_core(m, n, dense_row, dense_col, &s, eps, 0, 1, &Ui, &Vi, prow, pcol, stop, ratio);
+  int k = aca_core(m, n, dense_row, dense_col, &s, eps, 0, 1, 0, &Ui, &Vi, prow, pcol, stop, ratio);
+  memcpy(U, Ui, sizeof(double) * (size_t)m * k);
+  memcpy(V, Vi, sizeof(double) * (size_t)n * k);
+  free(Ui); free(Vi);
+  return k;
+}
+
+/* The step-limited run (no accuracy test, class-cycling rows) on a dense
+ * row-major m x n matrix whose rows fall into ncls classes: at most kcap
+ * crosses. U, V must hold m*min(m,n,kcap) and n*min(m,n,kcap) doubles;
+ * returns the rank (stop: 2 = min(m,n), 3 = Z full, 4 = kcap). */
+int or_aca_dense_steps(int m, int n, const double* A, int kcap, int ncls, double* U, double* V,
+                       int* prow, int* pcol, int* stop) {
+  dense_src s = {m, n, A};
+  double *Ui, *Vi, ratio;
+  int k = aca_core(m, n, dense_row, dense_col, &s, 0.0, kcap, ncls, 1, &Ui, &Vi, prow, pcol, stop,
+                   &ratio);
   memcpy(U, Ui, sizeof(double) * (size_t)m * k);
   memcpy(V, Vi, sizeof(double) * (size_t)n * k);
   free(Ui); free(Vi);
@@ -774,10 +832,11 @@ int or_h_fill(or_hmat* h, double eps) {
 }
 
 /* The same with ACA run for a fixed number of steps: no accuracy test
- * (eps = 0), stopping at k = kcap (stop code 4) unless a block is exhausted
- * first (k = min(m,n), or every row used). ACA is sequential, so the first
- * r crosses of such a run are those of any run that takes r steps: the
- * adaptive multiplication (Algorithm 2) uses prefixes of these crosses. */
+ * (eps = 0) and the class-cycling row rule (cycle_next), stopping at k = kcap
+ * (stop code 4) unless a block is exhausted first (k = min(m,n), or every
+ * row used). ACA is sequential, so the first r crosses of such a run are
+ * those of any run that takes r steps: the adaptive multiplication
+ * (Algorithm 2) uses prefixes of these crosses. */
 int or_h_fill_steps(or_hmat* h, int kcap) {
   if (kcap < 1) return 1;
   return h_fill(h, 0.0, kcap);
@@ -829,7 +888,7 @@ static int h_fill(or_hmat* h, double eps, int kcap) {
     blk_src src = {h, B->t, B->s};
     h->prow[b] = (int*)malloc(sizeof(int) * kmax);
     h->pcol[b] = (int*)malloc(sizeof(int) * kmax);
-    h->rank[b] = aca_core(m, n, blk_row, blk_col, &src, eps, kcap, 3, &h->U[b], &h->Vf[b], h->prow[b],
+    h->rank[b] = aca_core(m, n, blk_row, blk_col, &src, eps, kcap, 3, eps == 0.0, &h->U[b], &h->Vf[b], h->prow[b],
                           h->pcol[b], &h->stop[b], &h->ratio[b]);
   }
   free(idx);

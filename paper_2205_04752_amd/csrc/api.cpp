@@ -1863,6 +1863,7 @@ hmat_status amvm_impl(const hmat_mesh* mesh, double E, double nu, double eta, in
         t.kcap = kcap[f];
         t.blk = (int32_t)f;
         t.eps = 0.0;  // no accuracy test: steps are steered by the estimator
+        t.cycle = 1;  // rows cycle through the components (coplanar clusters decouple them)
         t.st = states.as<AcaState>() + f;
         t.zbits = zbits.as<uint32_t>() + zoff[f];
       }

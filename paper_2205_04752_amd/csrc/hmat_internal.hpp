@@ -94,7 +94,7 @@ struct AcaTask {
   AcaState* st;   // null: start from scratch; else resume from and save to *st
   uint32_t* zbits;  // with st: the block's set Z of used rows, (m + 31) / 32 words
   int32_t k_stop;   // > 0: pause (stop code 6) once k reaches k_stop
-  int32_t pad;
+  int32_t cycle;    // 1: class-cycling rows (step-limited runs of the adaptive multiplication)
 };
 
 // Adaptive multiplication: out[out + r] = (D x)_r for a dense block (D plain

@@ -289,6 +289,54 @@ __device__ int class_probe(const uint32_t* Z, int m, int visited, RedT<TPB / WAV
   return -1;
 }
 
+// Row rule of the step-limited runs of the adaptive multiplication (no
+// accuracy test that could send ACA to an unvisited component): the rows
+// cycle through the three classes. After a step at row i, the next row comes
+// from the first class c among i+1, i+2, i (mod 3) with rows outside Z: the
+// fuzzy argmax over them of |u_l|, u_l the latest of the k crosses whose
+// largest magnitude on them exceeds 1e-12 times its largest magnitude over
+// all rows; the lowest of them if no cross qualifies. u_{k-1} is read from
+// `ulast` (its LDS copy, or the panel), older crosses from the panel U.
+// Returns -1 when Z holds every row.
+template <int TPB>
+__device__ int cycle_next(const double* U, const double* ulast, int k, int m, const uint32_t* Z,
+                          int i, RedT<TPB / WAVE>& R, int& ph) {
+  const int tid = threadIdx.x;
+  for (int dc = 1; dc <= 3; dc++) {
+    const int c = (i % 3 + dc) % 3;
+    int cand = INT_MAX;
+    for (int r = c + 3 * tid; r < m; r += 3 * TPB)
+      if (!in_z(Z, r)) {
+        cand = r;
+        break;
+      }
+    const int lowest = blk_min(cand, R, ph);
+    if (lowest >= m) continue;
+    for (int l = k - 1; l >= 0; l--) {
+      const double* __restrict__ u = (l == k - 1) ? ulast : U + (size_t)l * m;
+      double all = 0.0, cls = 0.0;
+      for (int r = tid; r < m; r += TPB) {
+        const double a = fabs(u[r]);
+        all = fmax(all, a);
+        if (r % 3 == c && !in_z(Z, r)) cls = fmax(cls, a);
+      }
+      all = blk_max(all, R, ph);
+      cls = blk_max(cls, R, ph);
+      if (!(cls > 1e-12 * all)) continue;
+      const double thr = (1.0 - 1e-10) * cls;
+      cand = INT_MAX;
+      for (int r = c + 3 * tid; r < m; r += 3 * TPB)
+        if (!in_z(Z, r) && fabs(u[r]) >= thr) {
+          cand = r;
+          break;
+        }
+      return blk_min(cand, R, ph);
+    }
+    return lowest;
+  }
+  return -1;
+}
+
 // e_b -= sum_{l<k} coef[l] * P[l*ld + b] for b = 0..2 (one triangle's three
 // rows or columns of a panel); four columns per step with separate sums, so
 // twelve loads are in flight.
@@ -412,7 +460,9 @@ __device__ __forceinline__ double lane_dot(const double* x, const double* y, int
 //   stop: |u_k||v_k| <= eps ||S_k|| (1), k = min(m,n) (2), Z full (3),
 //   panel capacity reached (4: the host resumes the block from its saved
 //   state with a larger capacity; the step's next row is chosen first),
-//   no finite pivot (5: non-finite entries; reported as an error).
+//   no finite pivot (5: non-finite entries; reported as an error);
+//   with T.cycle (the adaptive multiplication's step-limited runs, eps = 0)
+//   the rows follow cycle_next instead of partial pivoting and the probes.
 // Panels live in global memory (column-major U m x kcap, V n x kcap); the
 // coefficient row U[i, 0:k] / V[j, 0:k], w = V[:, 0:k]^T v_k and the set Z
 // are staged in LDS, and for m + n <= ACA_STAGE_MAX also the newest row v_k
@@ -496,7 +546,10 @@ __global__ __launch_bounds__(TPB) void k_aca(DevGeo g0, const AcaTask* __restric
         stop = 1;
         break;
       }
-      if (pending) {
+      if (T.cycle) {
+        i = cycle_next<TPB>(U, U + (size_t)(k > 0 ? k - 1 : 0) * m, k, m, Z, i, R, ph);
+        if (i < 0) i = m;  // unreachable: Z is not full here
+      } else if (pending) {
         i = class_probe<TPB>(Z, m, visited, R, ph);
         if (i < 0) {
           stop = 1;
@@ -588,7 +641,10 @@ __global__ __launch_bounds__(TPB) void k_aca(DevGeo g0, const AcaTask* __restric
     }
     if (k == kmax) { stop = 2; break; }
     if (nZ == m) { stop = 3; break; }
-    if (pending) {
+    if (T.cycle) {
+      i = cycle_next<TPB>(U, ur, k, m, Z, i, R, ph);
+      if (i < 0) { stop = 3; break; }  // unreachable: Z is not full here
+    } else if (pending) {
       i = class_probe<TPB>(Z, m, visited, R, ph);
       if (i < 0) { stop = 1; break; }
     } else {

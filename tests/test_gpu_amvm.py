@@ -32,6 +32,9 @@ CASES = {
     "ico2-leaf16-pointforce": (lambda: W.icosphere(2), 16, "point", 0.5, 1e-7),
     "ico3-pointforce": (lambda: W.icosphere(3), 32, "point", 0.5, 1e-6),
     "torus-random": (lambda: W.torus(1.0, 0.3, 36, 12), 32, "random", 0.7, 1e-5),
+    # coplanar clusters: the in-plane and normal components decouple
+    "plate20-pointforce": (lambda: W.plate(20), 32, "point", 0.5, 1e-6),
+    "cube12-leaf16-pointforce": (lambda: W.cube_surface(12), 16, "point", 0.5, 1e-6),
 }
 
 
