@@ -1030,7 +1030,7 @@ void run_aca_pass(hmat* h, const std::vector<int32_t>& fidx, CapFn cap, PanelFn 
     panel_total += (m + n) * kc;
     piv_total += 2 * (int64_t)kc;
     size_t& sh = shmem[(int)q < n_big ? 0 : 1];
-    sh = std::max(sh, aca_shmem(kc, m, n));
+    sh = std::max(sh, aca_shmem(kc, m, n, (int)q < n_big ? (wide ? ACA_WIDE_NWV : ACA_NWV) : 1));
   }
   if (std::max(shmem[0], shmem[1]) > 160 * 1024)
     throw HipError{HMAT_ENOTSUP, "ACA panel row exceeds LDS capacity"};
@@ -1871,7 +1871,8 @@ hmat_status amvm_impl(const hmat_mesh* mesh, double E, double nu, double eta, in
     size_t shmem[2] = {0, 0};  // 256-thread blocks, one-wave blocks
     for (size_t f = 0; f < nf; f++) {
       const bool small = std::max(base[f].t_len, base[f].s_len) <= ACA_SMALL_TRI;
-      shmem[small ? 1 : 0] = std::max(shmem[small ? 1 : 0], aca_shmem(kcap[f], M[f], Nn[f]));
+      shmem[small ? 1 : 0] =
+          std::max(shmem[small ? 1 : 0], aca_shmem(kcap[f], M[f], Nn[f], small ? 1 : ACA_WIDE_NWV));
     }
     if (std::max(shmem[0], shmem[1]) > 160 * 1024)
       throw HipError{HMAT_ENOTSUP, "ACA panel row exceeds LDS capacity"};

@@ -44,6 +44,8 @@ constexpr int SEG_START_ALIGN = 16;  // doubles (128 bytes)
 // blocks with at most ACA_SMALL_TRI triangles on either side (the launch
 // takes the large blocks first, then the small ones).
 constexpr int ACA_SMALL_TRI = 64;
+constexpr int ACA_NWV = 4;       // waves of the ACA workgroup for large blocks
+constexpr int ACA_WIDE_NWV = 8;  // the same in launches of few blocks (one per CU)
 // A block with m + n <= ACA_STAGE_MAX keeps the newest row and column of
 // its remainder in LDS as well as in the panels, so the pivot searches,
 // the normalisation and the norm update of a step read them from LDS.
@@ -52,12 +54,15 @@ constexpr int ACA_STAGE_MAX = 7936;
 // 32 MiB, enough for GMRES(50) at 61440 DOF (Krylov basis, work vector,
 // partial sums and Hessenberg columns).
 constexpr size_t NOALLOC_DOUBLES = size_t(4) << 20;
-// Dynamic LDS (bytes) of the ACA kernel for one block: the coefficient row
-// and the cross-term weights (kcap doubles each), the row set Z (m bits, in 32-bit words, padded to a
-// double) and, if staged, the newest row and column (n + m doubles).
-inline size_t aca_shmem(int kcap, int64_t m, int64_t n) {
+// Dynamic LDS (bytes) of the ACA kernel for one block and a workgroup of
+// nwv waves: the coefficient row and the cross-term weights (kcap doubles
+// each), the per-wave partial sums of V^T v~ (kcap * nwv doubles), the row
+// set Z (m bits, in 32-bit words, padded to a double) and, if staged, the
+// newest row and column (n + m doubles).
+inline size_t aca_shmem(int kcap, int64_t m, int64_t n, int nwv) {
   const size_t zw = (size_t)((m + 31) / 32);
-  return 16 * (size_t)kcap + 8 * ((zw + 1) / 2) + (m + n <= ACA_STAGE_MAX ? 8 * (size_t)(m + n) : 0);
+  return 8 * (size_t)kcap * (2 + nwv) + 8 * ((zw + 1) / 2) +
+         (m + n <= ACA_STAGE_MAX ? 8 * (size_t)(m + n) : 0);
 }
 
 // Dense (non-admissible) block at d_off in the near arena (m = 3 t_len rows).

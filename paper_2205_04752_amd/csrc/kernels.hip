@@ -17,6 +17,7 @@
 // 16-point rule in s integrates it exactly and only the 16 points in t remain.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
 #include <mutex>
 
@@ -194,8 +195,8 @@ __global__ void k_entries(DevGeo g0, int64_t n, const int64_t* __restrict__ rows
 // sets: a slot set is rewritten only after every thread has passed the
 // barrier of the following reduction, so one barrier per reduction suffices.
 
-constexpr int ACA_T = 256;      // workgroup of the ACA kernel (large blocks)
-constexpr int ACA_WIDE_T = 512; // the same for launches of few blocks (one per CU)
+constexpr int ACA_T = ACA_NWV * WAVE;            // workgroup of the ACA kernel (large blocks)
+constexpr int ACA_WIDE_T = ACA_WIDE_NWV * WAVE;  // the same for launches of few blocks (one per CU)
 constexpr int ACA_SMALL_T = WAVE;  // one wave per small block
 constexpr int NW = 256 / WAVE;  // waves of a 256-thread workgroup
 
@@ -435,18 +436,43 @@ __device__ __forceinline__ void sub_panel3w(const double* __restrict__ coef,
   t2 = f2 + h2;
 }
 
-// sum_r x[r] y[r] over r = lane, lane + 64, ... < n; four partial sums.
-__device__ __forceinline__ double lane_dot(const double* x, const double* y, int n, int lane) {
-  double a = 0.0, b = 0.0, c = 0.0, d = 0.0;
-  int r = lane;
-  for (; r + 3 * WAVE < n; r += 4 * WAVE) {
-    a += x[r] * y[r];
-    b += x[r + WAVE] * y[r + WAVE];
-    c += x[r + 2 * WAVE] * y[r + 2 * WAVE];
-    d += x[r + 3 * WAVE] * y[r + 3 * WAVE];
+// Dot products of the panel columns 0..k-1 with the lane's three entries
+// e_0..e_2 (rows 3q..3q+2 of the panel), summed over the wave:
+// pw[l * NWV] += sum over lanes of sum_b P[l*ld + b] e_b (pw: the wave's slot,
+// NWV slots per column). The lane re-reads the rows sub_panel3 has just read,
+// so the loads hit the caches. Four columns per step; their four sums are
+// reduced together (a reduce-scatter over lane bits 5 and 4, then a
+// butterfly within 16 lanes): 7 exchanges instead of 4 x 6. Every lane of
+// the wave calls it; an inactive lane passes zero entries and a valid P.
+// Columns past k are masked (their addresses clamped to k - 1).
+template <int NWV>
+__device__ __forceinline__ void panel3_dot(const double* P, int k, int ld, double e0, double e1,
+                                           double e2, double* pw, int lane) {
+  const bool hi32 = lane & 32, hi16 = lane & 16;
+  const int mine = 2 * (lane >> 5) + ((lane >> 4) & 1);  // column (of the four) this lane's sum ends in
+  for (int l = 0; l < k; l += 4) {
+    const bool h1 = l + 1 < k, h2 = l + 2 < k, h3 = l + 3 < k;
+    const double* p0 = P + (size_t)l * ld;
+    const double* p1 = P + (size_t)min(l + 1, k - 1) * ld;
+    const double* p2 = P + (size_t)min(l + 2, k - 1) * ld;
+    const double* p3 = P + (size_t)min(l + 3, k - 1) * ld;
+    const double s0 = p0[0] * e0 + p0[1] * e1 + p0[2] * e2;
+    const double s1 = h1 ? p1[0] * e0 + p1[1] * e1 + p1[2] * e2 : 0.0;
+    const double s2 = h2 ? p2[0] * e0 + p2[1] * e1 + p2[2] * e2 : 0.0;
+    const double s3 = h3 ? p3[0] * e0 + p3[1] * e1 + p3[2] * e2 : 0.0;
+    // lanes 0-31 keep columns 0, 1 and lanes 32-63 columns 2, 3
+    double ka = hi32 ? s2 : s0, kb = hi32 ? s3 : s1;
+    ka += __shfl_xor(hi32 ? s0 : s2, 32, WAVE);
+    kb += __shfl_xor(hi32 ? s1 : s3, 32, WAVE);
+    // then lanes with bit 4 clear keep the first of their two, the others the second
+    double t = hi16 ? kb : ka;
+    t += __shfl_xor(hi16 ? ka : kb, 16, WAVE);
+    t += __shfl_xor(t, 8, WAVE);
+    t += __shfl_xor(t, 4, WAVE);
+    t += __shfl_xor(t, 2, WAVE);
+    t += __shfl_xor(t, 1, WAVE);
+    if ((lane & 15) == 0 && l + mine < k) pw[(l + mine) * NWV] += t;
   }
-  for (; r < n; r += WAVE) a += x[r] * y[r];
-  return (a + b) + (c + d);
 }
 
 // K2: ACA (Algorithm 1) on the DOF block of task blockIdx.x.
@@ -464,12 +490,14 @@ __device__ __forceinline__ double lane_dot(const double* x, const double* y, int
 //   with T.cycle (the adaptive multiplication's step-limited runs, eps = 0)
 //   the rows follow cycle_next instead of partial pivoting and the probes.
 // Panels live in global memory (column-major U m x kcap, V n x kcap); the
-// coefficient row U[i, 0:k] / V[j, 0:k], w = V[:, 0:k]^T v_k and the set Z
-// are staged in LDS, and for m + n <= ACA_STAGE_MAX also the newest row v_k
-// and column u_k (written to both; the step's later reads of them use the
-// LDS copy). The cross term is evaluated as u_k^T (U[:, 0:k] w): the column
-// pass forms U[:, 0:k] w from the same loads that subtract U[:, 0:k] V[j, 0:k]^T,
-// so a step reads the U panel once and the V panel twice.
+// coefficient row U[i, 0:k] / V[j, 0:k], w = V[:, 0:k]^T v_k, the per-wave
+// partial sums of V^T v~_k and the set Z are staged in LDS, and for
+// m + n <= ACA_STAGE_MAX also the newest row v_k and column u_k (written to
+// both; the step's later reads of them use the LDS copy). The cross term is
+// evaluated as u_k^T (U[:, 0:k] w): the column pass forms U[:, 0:k] w from the
+// same loads that subtract U[:, 0:k] V[j, 0:k]^T. w comes from the row pass:
+// each lane, right after subtracting V[c, 0:k] from its entries of the row,
+// reads those panel rows again (from the caches) for V[c, 0:k] v~_k(c).
 template <int TPB>
 __global__ __launch_bounds__(TPB) void k_aca(DevGeo g0, const AcaTask* __restrict__ tasks,
                                                int32_t* __restrict__ rank_out,
@@ -486,11 +514,12 @@ __global__ __launch_bounds__(TPB) void k_aca(DevGeo g0, const AcaTask* __restric
   double* __restrict__ U = T.panel;
   double* __restrict__ V = T.panel + (size_t)m * kcap;
   double* coef = sh;
-  double* const wl = sh + kcap;  // w_l = v_l . v_k
-  uint32_t* Z = reinterpret_cast<uint32_t*>(sh + 2 * kcap);
+  double* const wl = sh + kcap;      // w_l = v_l . v_k
+  double* const pw = sh + 2 * kcap;  // per wave: partial sums of V[:, l] . v~_k
+  uint32_t* Z = reinterpret_cast<uint32_t*>(sh + (2 + NWV) * kcap);
   const int zw = (m + 31) >> 5;
   const bool stage = m + n <= ACA_STAGE_MAX;
-  double* const vs = sh + 2 * kcap + ((zw + 1) >> 1);  // staged v_k (n), then u_k (m)
+  double* const vs = sh + (2 + NWV) * kcap + ((zw + 1) >> 1);  // staged v_k (n), then u_k (m)
   double* const us = vs + n;
   const int nt = g.nt;
   int ph = 0, k = 0, nZ = 0, i = 0, stop = 0, visited = 0, pending = 0;
@@ -511,6 +540,7 @@ __global__ __launch_bounds__(TPB) void k_aca(DevGeo g0, const AcaTask* __restric
   __syncthreads();
   for (;;) {
     for (int l = tid; l < k; l += TPB) coef[l] = U[i + (size_t)l * m];
+    for (int l = tid; l < k * NWV; l += TPB) pw[l] = 0.0;
     if (tid == 0) Z[i >> 5] |= (1u << (i & 31));
     nZ++;
     visited |= 1 << (i % 3);
@@ -521,19 +551,26 @@ __global__ __launch_bounds__(TPB) void k_aca(DevGeo g0, const AcaTask* __restric
     const int pi = T.t_off + i / 3, ai = i % 3;
     const double x0 = g.cen[pi], x1 = g.cen[nt + pi], x2 = g.cen[2 * nt + pi];
     double mx = 0.0;
-    for (int q = tid; q < T.s_len; q += TPB) {
-      double e0, e1, e2;
-      row3(g, x0, x1, x2, ai, T.s_off + q, e0, e1, e2);
-      sub_panel3(coef, V + 3 * q, k, n, e0, e1, e2);
-      vk[3 * q] = e0;
-      vk[3 * q + 1] = e1;
-      vk[3 * q + 2] = e2;
-      if (stage) {
-        vs[3 * q] = e0;
-        vs[3 * q + 1] = e1;
-        vs[3 * q + 2] = e2;
+    // wave-uniform trip count: the dot products V[:, l] . v~_k are summed over the wave
+    for (int q0 = wv * WAVE; q0 < T.s_len; q0 += TPB) {
+      const int q = q0 + lane;
+      const bool act = q < T.s_len;
+      const double* Vq = V + 3 * (act ? q : 0);
+      double e0 = 0.0, e1 = 0.0, e2 = 0.0;
+      if (act) {
+        row3(g, x0, x1, x2, ai, T.s_off + q, e0, e1, e2);
+        sub_panel3(coef, Vq, k, n, e0, e1, e2);
+        vk[3 * q] = e0;
+        vk[3 * q + 1] = e1;
+        vk[3 * q + 2] = e2;
+        if (stage) {
+          vs[3 * q] = e0;
+          vs[3 * q + 1] = e1;
+          vs[3 * q + 2] = e2;
+        }
+        mx = fmax(mx, fmax(fabs(e0), fmax(fabs(e1), fabs(e2))));
       }
-      mx = fmax(mx, fmax(fabs(e0), fmax(fabs(e1), fabs(e2))));
+      panel3_dot<NWV>(Vq, k, n, e0, e1, e2, pw + wv, lane);
     }
     mx = blk_max(mx, R, ph);
     const bool vanished = (k == 0) ? (mx == 0.0) : (mx <= 1e-14 * sqrt(S2));
@@ -593,12 +630,12 @@ __global__ __launch_bounds__(TPB) void k_aca(DevGeo g0, const AcaTask* __restric
       if (stage) vs[c] = v;
       vv += v * v;
     }
-    for (int l = tid; l < k; l += TPB) coef[l] = V[j + (size_t)l * n];
-    __syncthreads();
-    // w = V[:, 0:k]^T v_k: wave wv takes l = wv, wv + NWV, ...
-    for (int l = wv; l < k; l += NWV) {
-      const double b = wave_sum(lane_dot(V + (size_t)l * n, vr, n, lane));
-      if (lane == 0) wl[l] = b;
+    // w = V[:, 0:k]^T v_k = (V[:, 0:k]^T v~_k) / piv from the row pass's sums
+    for (int l = tid; l < k; l += TPB) {
+      double p = 0.0;
+      for (int q = 0; q < NWV; q++) p += pw[l * NWV + q];
+      wl[l] = p / piv;
+      coef[l] = V[j + (size_t)l * n];
     }
     __syncthreads();
     // column j of the remainder into U[:, k] (S is symmetric: A[3p+a, 3q+b] = S_ba),
@@ -983,18 +1020,45 @@ hipError_t launch_entries(const DevGeo& g, int64_t n, const int64_t* rows, const
 // block's step is bound by the loads its own workgroup keeps in flight, and
 // 512 threads keep twice as many. shmem_big / shmem_small: the largest
 // aca_shmem of each part's tasks.
+namespace {
+// Dynamic LDS beyond 64 KiB must be allowed per kernel. Each ACA kernel is
+// allowed the device's whole per-workgroup LDS (less its static part) once
+// per device, so concurrent builds never lower the limit under one another.
+std::mutex g_lds_mu;
+uint32_t g_lds_set[64] = {};
+hipError_t allow_full_lds(const void* f, int bit) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_lds_mu);
+  if (g_lds_set[dev] & (1u << bit)) return hipSuccess;
+  int a = 0, b = 0;
+  if ((e = hipDeviceGetAttribute(&a, hipDeviceAttributeMaxSharedMemoryPerBlock, dev)) != hipSuccess) return e;
+  if (hipDeviceGetAttribute(&b, hipDeviceAttributeSharedMemPerBlockOptin, dev) != hipSuccess) {
+    (void)hipGetLastError();
+    b = 0;
+  }
+  hipFuncAttributes fa{};
+  if ((e = hipFuncGetAttributes(&fa, f)) != hipSuccess) return e;
+  const int limit = std::min(std::max(a, b), 160 * 1024) - (int)fa.sharedSizeBytes;
+  if ((e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, limit)) != hipSuccess) return e;
+  g_lds_set[dev] |= 1u << bit;
+  return hipSuccess;
+}
+}  // namespace
+
 hipError_t launch_aca(const DevGeo& g, const AcaTask* tasks, int ntasks, int n_big, size_t shmem_big,
                       size_t shmem_small, bool wide, int32_t* rank, int32_t* stop, double* ratio,
                       hipStream_t s) {
   if (shmem_big > 64 * 1024) {
     const void* f = wide ? reinterpret_cast<const void*>(&k_aca<ACA_WIDE_T>)
                          : reinterpret_cast<const void*>(&k_aca<ACA_T>);
-    const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem_big);
+    const hipError_t e = allow_full_lds(f, wide ? 1 : 0);
     if (e != hipSuccess) return e;
   }
   if (shmem_small > 64 * 1024) {
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_aca<ACA_SMALL_T>),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem_small);
+    const hipError_t e = allow_full_lds(reinterpret_cast<const void*>(&k_aca<ACA_SMALL_T>), 2);
     if (e != hipSuccess) return e;
   }
   if (n_big > 0 && wide)
