@@ -56,7 +56,7 @@ constexpr int ACA_STAGE_MAX = 7936;
 constexpr size_t NOALLOC_DOUBLES = size_t(4) << 20;
 // Dynamic LDS (bytes) of the ACA kernel for one block and a workgroup of
 // nwv waves: the coefficient row and the cross-term weights (kcap doubles
-// each), the per-wave partial sums of V^T v~ (kcap * nwv doubles), the row
+// each), the per-wave partial sums of V^T v_c (kcap * nwv doubles), the row
 // set Z (m bits, in 32-bit words, padded to a double) and, if staged, the
 // newest row and column (n + m doubles).
 inline size_t aca_shmem(int kcap, int64_t m, int64_t n, int nwv) {
@@ -86,7 +86,8 @@ struct SelfTask {
 // was unvisited, ||S_k||_F^2, last stop ratio.
 struct AcaState {
   int32_t k, i, nZ, stop, visited, pending;
-  double S2, ratio;
+  int32_t pc, pad;  // pc = 1: the test of cross k - 1 is not settled (its |u|^2, |v|^2 in puu, pvv)
+  double S2, ratio, puu, pvv;
 };
 
 struct AcaTask {

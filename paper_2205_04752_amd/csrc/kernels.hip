@@ -436,30 +436,74 @@ __device__ __forceinline__ void sub_panel3w(const double* __restrict__ coef,
   t2 = f2 + h2;
 }
 
-// Dot products of the panel columns 0..k-1 with the lane's three entries
-// e_0..e_2 (rows 3q..3q+2 of the panel), summed over the wave:
-// pw[l * NWV] += sum over lanes of sum_b P[l*ld + b] e_b (pw: the wave's slot,
-// NWV slots per column). The lane re-reads the rows sub_panel3 has just read,
-// so the loads hit the caches. Four columns per step; their four sums are
-// reduced together (a reduce-scatter over lane bits 5 and 4, then a
+// As sub_panel3 (e_b -= sum_{l<k} coef[l] P[l*ld + b]), and from the same
+// loads the dot products of panel columns l < c = k - 1 with column c (the
+// cross whose norm-update term is pending), summed over the wave:
+// pw[l * NWV] += sum over lanes of sum_b P[l*ld + b] P[c*ld + b] (pw: the
+// wave's slot, NWV slots per column). Four columns per step; their four sums
+// are reduced together (a reduce-scatter over lane bits 5 and 4, then a
 // butterfly within 16 lanes): 7 exchanges instead of 4 x 6. Every lane of
-// the wave calls it; an inactive lane passes zero entries and a valid P.
-// Columns past k are masked (their addresses clamped to k - 1).
+// the wave calls it; an inactive lane (act = false) passes a valid P and
+// contributes nothing. Columns past k are masked (addresses clamped).
 template <int NWV>
-__device__ __forceinline__ void panel3_dot(const double* P, int k, int ld, double e0, double e1,
-                                           double e2, double* pw, int lane) {
+__device__ __forceinline__ void sub_panel3_pend(const double* __restrict__ coef, const double* P, int k,
+                                                int ld, bool act, double& e0, double& e1, double& e2,
+                                                double* pw, int lane) {
+  const int c = k - 1;
+  const double* pc = P + (size_t)c * ld;
+  const double y0 = act ? pc[0] : 0.0, y1 = act ? pc[1] : 0.0, y2 = act ? pc[2] : 0.0;
+  // the subtraction keeps sub_panel3's partial sums (four columns in four
+  // sums, the tail column by column into the first), so v~ has its bits
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, b0 = 0.0, b1 = 0.0, b2 = 0.0;
+  double c0 = 0.0, c1 = 0.0, c2 = 0.0, d0 = 0.0, d1 = 0.0, d2 = 0.0;
   const bool hi32 = lane & 32, hi16 = lane & 16;
   const int mine = 2 * (lane >> 5) + ((lane >> 4) & 1);  // column (of the four) this lane's sum ends in
   for (int l = 0; l < k; l += 4) {
     const bool h1 = l + 1 < k, h2 = l + 2 < k, h3 = l + 3 < k;
     const double* p0 = P + (size_t)l * ld;
-    const double* p1 = P + (size_t)min(l + 1, k - 1) * ld;
-    const double* p2 = P + (size_t)min(l + 2, k - 1) * ld;
-    const double* p3 = P + (size_t)min(l + 3, k - 1) * ld;
-    const double s0 = p0[0] * e0 + p0[1] * e1 + p0[2] * e2;
-    const double s1 = h1 ? p1[0] * e0 + p1[1] * e1 + p1[2] * e2 : 0.0;
-    const double s2 = h2 ? p2[0] * e0 + p2[1] * e1 + p2[2] * e2 : 0.0;
-    const double s3 = h3 ? p3[0] * e0 + p3[1] * e1 + p3[2] * e2 : 0.0;
+    const double* p1 = P + (size_t)min(l + 1, c) * ld;
+    const double* p2 = P + (size_t)min(l + 2, c) * ld;
+    const double* p3 = P + (size_t)min(l + 3, c) * ld;
+    const double x00 = p0[0], x01 = p0[1], x02 = p0[2];
+    const double x10 = h1 ? p1[0] : 0.0, x11 = h1 ? p1[1] : 0.0, x12 = h1 ? p1[2] : 0.0;
+    const double x20 = h2 ? p2[0] : 0.0, x21 = h2 ? p2[1] : 0.0, x22 = h2 ? p2[2] : 0.0;
+    const double x30 = h3 ? p3[0] : 0.0, x31 = h3 ? p3[1] : 0.0, x32 = h3 ? p3[2] : 0.0;
+    if (h3) {
+      const double w0 = coef[l], w1 = coef[l + 1], w2 = coef[l + 2], w3 = coef[l + 3];
+      a0 += w0 * x00;
+      a1 += w0 * x01;
+      a2 += w0 * x02;
+      b0 += w1 * x10;
+      b1 += w1 * x11;
+      b2 += w1 * x12;
+      c0 += w2 * x20;
+      c1 += w2 * x21;
+      c2 += w2 * x22;
+      d0 += w3 * x30;
+      d1 += w3 * x31;
+      d2 += w3 * x32;
+    } else {  // the last one to three columns, one after another into the first sums
+      const double w0 = coef[l];
+      a0 += w0 * x00;
+      a1 += w0 * x01;
+      a2 += w0 * x02;
+      if (h1) {
+        const double w1 = coef[l + 1];
+        a0 += w1 * x10;
+        a1 += w1 * x11;
+        a2 += w1 * x12;
+      }
+      if (h2) {
+        const double w2 = coef[l + 2];
+        a0 += w2 * x20;
+        a1 += w2 * x21;
+        a2 += w2 * x22;
+      }
+    }
+    const double s0 = l < c ? x00 * y0 + x01 * y1 + x02 * y2 : 0.0;
+    const double s1 = l + 1 < c ? x10 * y0 + x11 * y1 + x12 * y2 : 0.0;
+    const double s2 = l + 2 < c ? x20 * y0 + x21 * y1 + x22 * y2 : 0.0;
+    const double s3 = l + 3 < c ? x30 * y0 + x31 * y1 + x32 * y2 : 0.0;
     // lanes 0-31 keep columns 0, 1 and lanes 32-63 columns 2, 3
     double ka = hi32 ? s2 : s0, kb = hi32 ? s3 : s1;
     ka += __shfl_xor(hi32 ? s0 : s2, 32, WAVE);
@@ -471,8 +515,38 @@ __device__ __forceinline__ void panel3_dot(const double* P, int k, int ld, doubl
     t += __shfl_xor(t, 4, WAVE);
     t += __shfl_xor(t, 2, WAVE);
     t += __shfl_xor(t, 1, WAVE);
-    if ((lane & 15) == 0 && l + mine < k) pw[(l + mine) * NWV] += t;
+    if ((lane & 15) == 0 && l + mine < c) pw[(l + mine) * NWV] += t;
   }
+  e0 -= (a0 + b0) + (c0 + d0);
+  e1 -= (a1 + b1) + (c1 + d1);
+  e2 -= (a2 + b2) + (c2 + d2);
+}
+
+// The pending cross term on its own, where no next step carries it (the
+// block ends, or the next row is exactly zero): w_l = V[:, l] . V[:, c] for
+// l < c (one wave per column, into wl), then sum_r U[r, c] (U[r, 0:c] w).
+template <int TPB>
+__device__ double pending_cross(const double* U, const double* V, int m, int n, int c, double* wl,
+                                RedT<TPB / WAVE>& R, int& ph) {
+  constexpr int NWV = TPB / WAVE;
+  const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
+  const double* vc = V + (size_t)c * n;
+  for (int l = wv; l < c; l += NWV) {
+    const double* vl = V + (size_t)l * n;
+    double a = 0.0;
+    for (int r = lane; r < n; r += WAVE) a += vl[r] * vc[r];
+    a = wave_sum(a);
+    if (lane == 0) wl[l] = a;
+  }
+  __syncthreads();
+  double x = 0.0, d1 = 0.0, d2 = 0.0;
+  for (int r = tid; r < m; r += TPB) {
+    double t = 0.0;
+    for (int l = 0; l < c; l++) t += U[r + (size_t)l * m] * wl[l];
+    x += U[r + (size_t)c * m] * t;
+  }
+  blk_sum3(x, d1, d2, R, ph);
+  return x;
 }
 
 // K2: ACA (Algorithm 1) on the DOF block of task blockIdx.x.
@@ -490,14 +564,24 @@ __device__ __forceinline__ void panel3_dot(const double* P, int k, int ld, doubl
 //   with T.cycle (the adaptive multiplication's step-limited runs, eps = 0)
 //   the rows follow cycle_next instead of partial pivoting and the probes.
 // Panels live in global memory (column-major U m x kcap, V n x kcap); the
-// coefficient row U[i, 0:k] / V[j, 0:k], w = V[:, 0:k]^T v_k, the per-wave
-// partial sums of V^T v~_k and the set Z are staged in LDS, and for
-// m + n <= ACA_STAGE_MAX also the newest row v_k and column u_k (written to
-// both; the step's later reads of them use the LDS copy). The cross term is
-// evaluated as u_k^T (U[:, 0:k] w): the column pass forms U[:, 0:k] w from the
-// same loads that subtract U[:, 0:k] V[j, 0:k]^T. w comes from the row pass:
-// each lane, right after subtracting V[c, 0:k] from its entries of the row,
-// reads those panel rows again (from the caches) for V[c, 0:k] v~_k(c).
+// coefficient row U[i, 0:k] / V[j, 0:k], the weights w, the per-wave partial
+// sums and the set Z are staged in LDS, and for m + n <= ACA_STAGE_MAX also
+// the newest row v_k and column u_k (written to both; the step's later reads
+// of them use the LDS copy).
+// Each panel is read once per step. The cross term of cross c,
+// sum_{l<c} (u_l . u_c)(v_l . v_c) = u_c . (U[:, 0:c] w) with w = V[:, 0:c]^T v_c,
+// is formed during the next step: its row pass, which reads V[:, 0:c+1] for
+// the subtraction, also forms w (v_c is a panel column by then), and its
+// column pass, which reads U[:, 0:c+1], forms U[:, 0:c] w and the dot with
+// u_c. The test of cross c is therefore settled one step late, with the
+// next row chosen as if it failed (argmax |u_c|). When it passes, the step
+// is dropped: ACA stops at rank c + 1, or (components not all visited) the
+// speculative row leaves Z again and the step reruns at the probe row. The
+// row's vanishing test waits for the settled norm the same way. Where no
+// step follows (the block ends: k = min(m,n) or Z full) or the next row is
+// exactly zero, the term is computed on its own (pending_cross). The
+// decisions and crosses are those of the plain order; only the rounding of
+// ||S_k|| differs.
 template <int TPB>
 __global__ __launch_bounds__(TPB) void k_aca(DevGeo g0, const AcaTask* __restrict__ tasks,
                                                int32_t* __restrict__ rank_out,
@@ -514,8 +598,8 @@ __global__ __launch_bounds__(TPB) void k_aca(DevGeo g0, const AcaTask* __restric
   double* __restrict__ U = T.panel;
   double* __restrict__ V = T.panel + (size_t)m * kcap;
   double* coef = sh;
-  double* const wl = sh + kcap;      // w_l = v_l . v_k
-  double* const pw = sh + 2 * kcap;  // per wave: partial sums of V[:, l] . v~_k
+  double* const wl = sh + kcap;      // weights w_l of the pending cross term
+  double* const pw = sh + 2 * kcap;  // per wave: partial sums of V[:, l] . V[:, c]
   uint32_t* Z = reinterpret_cast<uint32_t*>(sh + (2 + NWV) * kcap);
   const int zw = (m + 31) >> 5;
   const bool stage = m + n <= ACA_STAGE_MAX;
@@ -523,6 +607,8 @@ __global__ __launch_bounds__(TPB) void k_aca(DevGeo g0, const AcaTask* __restric
   double* const us = vs + n;
   const int nt = g.nt;
   int ph = 0, k = 0, nZ = 0, i = 0, stop = 0, visited = 0, pending = 0;
+  int pc = 0;                 // 1: the test of cross k - 1 is not settled yet
+  double puu = 0.0, pvv = 0.0;  // |u|^2, |v|^2 of that cross
   double S2 = 0.0, ratio = 0.0;
   if (T.st) {  // resume
     const AcaState s0 = *T.st;
@@ -531,18 +617,31 @@ __global__ __launch_bounds__(TPB) void k_aca(DevGeo g0, const AcaTask* __restric
     nZ = s0.nZ;
     visited = s0.visited;
     pending = s0.pending;
+    pc = s0.pc;
     S2 = s0.S2;
     ratio = s0.ratio;
+    puu = s0.puu;
+    pvv = s0.pvv;
     for (int w = tid; w < zw; w += TPB) Z[w] = T.zbits[w];
   } else {
     for (int w = tid; w < zw; w += TPB) Z[w] = 0u;
   }
+  // settle the pending cross's test: S2 gets its terms; true if the test passes
+  auto settle = [&](double cross) {
+    S2 = S2 + 2.0 * cross + puu * pvv;
+    const double lhs = sqrt(puu) * sqrt(pvv), rhs = eps * sqrt(S2);
+    ratio = rhs > 0.0 ? lhs / rhs : INFINITY;
+    pc = 0;
+    return lhs <= rhs;
+  };
   __syncthreads();
   for (;;) {
     for (int l = tid; l < k; l += TPB) coef[l] = U[i + (size_t)l * m];
-    for (int l = tid; l < k * NWV; l += TPB) pw[l] = 0.0;
+    if (pc)
+      for (int l = tid; l < k * NWV; l += TPB) pw[l] = 0.0;
     if (tid == 0) Z[i >> 5] |= (1u << (i & 31));
     nZ++;
+    const int vis_before = visited;
     visited |= 1 << (i % 3);
     __syncthreads();
     // row i of the remainder into V[:, k]
@@ -551,15 +650,31 @@ __global__ __launch_bounds__(TPB) void k_aca(DevGeo g0, const AcaTask* __restric
     const int pi = T.t_off + i / 3, ai = i % 3;
     const double x0 = g.cen[pi], x1 = g.cen[nt + pi], x2 = g.cen[2 * nt + pi];
     double mx = 0.0;
-    // wave-uniform trip count: the dot products V[:, l] . v~_k are summed over the wave
-    for (int q0 = wv * WAVE; q0 < T.s_len; q0 += TPB) {
-      const int q = q0 + lane;
-      const bool act = q < T.s_len;
-      const double* Vq = V + 3 * (act ? q : 0);
-      double e0 = 0.0, e1 = 0.0, e2 = 0.0;
-      if (act) {
+    if (pc) {
+      // wave-uniform trip count: the dot products are summed over the wave
+      for (int q0 = wv * WAVE; q0 < T.s_len; q0 += TPB) {
+        const int q = q0 + lane;
+        const bool act = q < T.s_len;
+        double e0 = 0.0, e1 = 0.0, e2 = 0.0;
+        if (act) row3(g, x0, x1, x2, ai, T.s_off + q, e0, e1, e2);
+        sub_panel3_pend<NWV>(coef, V + 3 * (act ? q : 0), k, n, act, e0, e1, e2, pw + wv, lane);
+        if (act) {
+          vk[3 * q] = e0;
+          vk[3 * q + 1] = e1;
+          vk[3 * q + 2] = e2;
+          if (stage) {
+            vs[3 * q] = e0;
+            vs[3 * q + 1] = e1;
+            vs[3 * q + 2] = e2;
+          }
+          mx = fmax(mx, fmax(fabs(e0), fmax(fabs(e1), fabs(e2))));
+        }
+      }
+    } else {
+      for (int q = tid; q < T.s_len; q += TPB) {
+        double e0, e1, e2;
         row3(g, x0, x1, x2, ai, T.s_off + q, e0, e1, e2);
-        sub_panel3(coef, Vq, k, n, e0, e1, e2);
+        sub_panel3(coef, V + 3 * q, k, n, e0, e1, e2);
         vk[3 * q] = e0;
         vk[3 * q + 1] = e1;
         vk[3 * q + 2] = e2;
@@ -570,44 +685,60 @@ __global__ __launch_bounds__(TPB) void k_aca(DevGeo g0, const AcaTask* __restric
         }
         mx = fmax(mx, fmax(fabs(e0), fmax(fabs(e1), fabs(e2))));
       }
-      panel3_dot<NWV>(Vq, k, n, e0, e1, e2, pw + wv, lane);
     }
     mx = blk_max(mx, R, ph);
-    const bool vanished = (k == 0) ? (mx == 0.0) : (mx <= 1e-14 * sqrt(S2));
-    if (vanished) {
-      if (nZ == m) {
-        stop = 3;
-        break;
-      }
-      if (pending && visited == 7) {  // the probe row of the last class is captured
-        stop = 1;
-        break;
-      }
-      if (T.cycle) {
-        i = cycle_next<TPB>(U, U + (size_t)(k > 0 ? k - 1 : 0) * m, k, m, Z, i, R, ph);
-        if (i < 0) i = m;  // unreachable: Z is not full here
-      } else if (pending) {
+    if (pc && !(mx > 0.0)) {
+      // no pivot to normalise by: settle the pending cross on its own
+      if (settle(pending_cross<TPB>(U, V, m, n, k - 1, wl, R, ph))) {
+        if (vis_before == 7) { stop = 1; break; }
+        // probe the first unvisited component instead of row i
+        if (tid == 0) Z[i >> 5] &= ~(1u << (i & 31));
+        __syncthreads();
+        nZ--;
+        visited = vis_before;
+        pending = 1;
         i = class_probe<TPB>(Z, m, visited, R, ph);
-        if (i < 0) {
+        if (i < 0) { stop = 1; break; }
+        continue;
+      }
+    }
+    if (!pc) {
+      const bool vanished = (k == 0) ? (mx == 0.0) : (mx <= 1e-14 * sqrt(S2));
+      if (vanished) {
+        if (nZ == m) {
+          stop = 3;
+          break;
+        }
+        if (pending && visited == 7) {  // the probe row of the last class is captured
           stop = 1;
           break;
         }
-      } else if (k == 0) {
-        int cand = INT_MAX;
-        for (int r = tid; r < m; r += TPB)
-          if (!in_z(Z, r)) {
-            cand = r;
+        if (T.cycle) {
+          i = cycle_next<TPB>(U, U + (size_t)(k > 0 ? k - 1 : 0) * m, k, m, Z, i, R, ph);
+          if (i < 0) i = m;  // unreachable: Z is not full here
+        } else if (pending) {
+          i = class_probe<TPB>(Z, m, visited, R, ph);
+          if (i < 0) {
+            stop = 1;
             break;
           }
-        i = blk_min(cand, R, ph);
-      } else {
-        i = argmax_free<TPB>(U + (size_t)(k - 1) * m, m, Z, R, ph);
+        } else if (k == 0) {
+          int cand = INT_MAX;
+          for (int r = tid; r < m; r += TPB)
+            if (!in_z(Z, r)) {
+              cand = r;
+              break;
+            }
+          i = blk_min(cand, R, ph);
+        } else {
+          i = argmax_free<TPB>(U + (size_t)(k - 1) * m, m, Z, R, ph);
+        }
+        if (i >= m) {
+          stop = 5;
+          break;
+        }
+        continue;
       }
-      if (i >= m) {
-        stop = 5;
-        break;
-      }
-      continue;
     }
     const double thr = (1.0 - 1e-10) * mx;
     int cand = INT_MAX;
@@ -630,26 +761,33 @@ __global__ __launch_bounds__(TPB) void k_aca(DevGeo g0, const AcaTask* __restric
       if (stage) vs[c] = v;
       vv += v * v;
     }
-    // w = V[:, 0:k]^T v_k = (V[:, 0:k]^T v~_k) / piv from the row pass's sums
+    const int pend = pc;  // this step also forms the pending cross term
     for (int l = tid; l < k; l += TPB) {
       double p = 0.0;
-      for (int q = 0; q < NWV; q++) p += pw[l * NWV + q];
-      wl[l] = p / piv;
+      if (pend && l < k - 1)
+        for (int q = 0; q < NWV; q++) p += pw[l * NWV + q];
+      wl[l] = p;
       coef[l] = V[j + (size_t)l * n];
     }
     __syncthreads();
     // column j of the remainder into U[:, k] (S is symmetric: A[3p+a, 3q+b] = S_ba),
-    // and the cross term sum_{l<k} (u_l . u_k)(v_l . v_k) = u_k . (U[:, 0:k] w)
+    // and the pending cross term u_c . (U[:, 0:c] w), c = k - 1
     double* __restrict__ uk = U + (size_t)k * m;
     double* const ur = stage ? us : uk;  // where this step reads u_k
     const int qj = T.s_off + j / 3, bj = j % 3;
     double uu = 0.0, cross = 0.0;
     for (int p = tid; p < T.t_len; p += TPB) {
       const int ip = T.t_off + p;
-      double e0, e1, e2, t0, t1, t2;
+      double e0, e1, e2;
       row3(g, g.cen[ip], g.cen[nt + ip], g.cen[2 * nt + ip], bj, qj, e0, e1, e2);
-      sub_panel3w(coef, wl, U + 3 * p, k, m, e0, e1, e2, t0, t1, t2);
-      cross += e0 * t0 + e1 * t1 + e2 * t2;
+      if (pend) {
+        double t0, t1, t2;
+        sub_panel3w(coef, wl, U + 3 * p, k, m, e0, e1, e2, t0, t1, t2);
+        const double* uc = U + (size_t)(k - 1) * m + 3 * p;
+        cross += uc[0] * t0 + uc[1] * t1 + uc[2] * t2;
+      } else {
+        sub_panel3(coef, U + 3 * p, k, m, e0, e1, e2);
+      }
       uk[3 * p] = e0;
       uk[3 * p + 1] = e1;
       uk[3 * p + 2] = e2;
@@ -661,23 +799,59 @@ __global__ __launch_bounds__(TPB) void k_aca(DevGeo g0, const AcaTask* __restric
       uu += e0 * e0 + e1 * e1 + e2 * e2;
     }
     blk_sum3(uu, vv, cross, R, ph);
+    if (pend) {
+      if (settle(cross)) {
+        if (vis_before == 7) { stop = 1; break; }  // rank k: this step is dropped
+        // the accuracy test sends ACA to the first unvisited component: the
+        // step reruns there, and row i leaves Z again
+        if (tid == 0) Z[i >> 5] &= ~(1u << (i & 31));
+        __syncthreads();
+        nZ--;
+        visited = vis_before;
+        pending = 1;
+        i = class_probe<TPB>(Z, m, visited, R, ph);
+        if (i < 0) { stop = 1; break; }
+        continue;
+      }
+      if (mx <= 1e-14 * sqrt(S2)) {  // row i vanishes: it stays in Z, no cross
+        if (nZ == m) { stop = 3; break; }
+        if (T.cycle)
+          i = cycle_next<TPB>(U, U + (size_t)(k - 1) * m, k, m, Z, i, R, ph);
+        else
+          i = argmax_free<TPB>(U + (size_t)(k - 1) * m, m, Z, R, ph);
+        if (i < 0 || i >= m) { stop = 5; break; }
+        continue;
+      }
+    }
     if (tid == 0) {
       T.piv[k] = i;
       T.piv[kcap + k] = j;
     }
     k++;
-    S2 = S2 + 2.0 * cross + uu * vv;
-    const double lhs = sqrt(uu) * sqrt(vv), rhs = eps * sqrt(S2);
-    ratio = rhs > 0.0 ? lhs / rhs : INFINITY;
-    // the accuracy test stops ACA only once every row class (component) has
-    // had a row in Z; otherwise the next row probes the first unvisited class
     pending = 0;
-    if (lhs <= rhs) {
-      if (visited == 7) { stop = 1; break; }
-      pending = 1;
+    if (k == 1) {  // no earlier crosses: the test is settled at once
+      puu = uu;
+      pvv = vv;
+      if (settle(0.0)) {
+        if (visited == 7) { stop = 1; break; }
+        pending = 1;
+      }
+    } else {
+      puu = uu;
+      pvv = vv;
+      pc = 1;
+      if (k == kmax || nZ == m) {  // no step follows to carry the cross term
+        __syncthreads();
+        if (settle(pending_cross<TPB>(U, V, m, n, k - 1, wl, R, ph))) {
+          if (visited == 7) { stop = 1; break; }
+          pending = 1;
+        }
+      }
     }
     if (k == kmax) { stop = 2; break; }
     if (nZ == m) { stop = 3; break; }
+    // the next row (while the test of the new cross is pending: the row it
+    // would take if the test fails)
     if (T.cycle) {
       i = cycle_next<TPB>(U, ur, k, m, Z, i, R, ph);
       if (i < 0) { stop = 3; break; }  // unreachable: Z is not full here
@@ -691,8 +865,8 @@ __global__ __launch_bounds__(TPB) void k_aca(DevGeo g0, const AcaTask* __restric
         break;
       }
     }
-    // panels full: the saved state holds the next row, and the host resumes
-    // the block there with a larger capacity
+    // panels full: the saved state holds the next row (and a pending test),
+    // and the host resumes the block there with a larger capacity
     if (k == kcap) { stop = 4; break; }
     if (T.k_stop > 0 && k >= T.k_stop) {  // paused: the next step starts at row i
       stop = 6;
@@ -707,7 +881,7 @@ __global__ __launch_bounds__(TPB) void k_aca(DevGeo g0, const AcaTask* __restric
   if (T.st) {
     __syncthreads();
     for (int w = tid; w < zw; w += TPB) T.zbits[w] = Z[w];
-    if (tid == 0) *T.st = AcaState{k, i, nZ, stop, visited, pending, S2, ratio};
+    if (tid == 0) *T.st = AcaState{k, i, nZ, stop, visited, pending, pc, 0, S2, ratio, puu, pvv};
   }
 }
 
