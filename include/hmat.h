@@ -292,6 +292,27 @@ hmat_status hmat_free(hmat_t h);
  * kept). Errors: none beyond device errors (HMAT_EDEVICE). */
 hmat_status hmat_release_memory(void* hip_stream);
 
+/*
+ * hmat_set_mem_budget -- cap on the device memory the library holds on each
+ * device: live buffers of handles, builds, products and solves, plus the
+ * memory it keeps for reuse (cached blocks, idle ACA panel buffers). 0 (the
+ * default) means no cap; bytes < 0 is HMAT_EINVAL. An allocation that would
+ * pass the cap is treated as a full device: the kept memory is handed back
+ * and the allocation retried, and if it still does not fit the call fails
+ * with HMAT_ENOMEM ("... device memory budget ... exceeded"), leaving no
+ * half-built handle. For failure injection and for sharing a device with
+ * other users; the request server's per-request vectors are not counted.
+ * Process-wide; takes effect at the next allocation.
+ */
+hmat_status hmat_set_mem_budget(int64_t bytes);
+
+/* hmat_mem_held -- the bytes of device memory the library holds on the
+ * current device (what hmat_set_mem_budget caps) and, if peak is not NULL,
+ * the most it held right after any of its allocations since the previous
+ * hmat_mem_held call (0 if it allocated nothing; each call starts a new
+ * interval). HOST outputs; held must not be NULL. */
+hmat_status hmat_mem_held(int64_t* held, int64_t* peak);
+
 /* Thread-local description of the last failure on the calling thread. */
 const char* hmat_last_error(void);
 

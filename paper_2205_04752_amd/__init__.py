@@ -79,7 +79,8 @@ EXPORTS = ["hmat_build", "hmat_build_batch", "hmat_bodies", "hmat_matvec", "hmat
            "hmat_solve", "hmat_solve_noalloc", "hmat_solve_ir", "hmat_set_precision", "hmat_info", "hmat_free",
            "hmat_last_error", "hmat_plan", "hmat_block", "hmat_entries", "hmat_set_factors",
            "hmat_profile", "hmat_tune", "hmat_matvec_graph", "hmat_amvm", "hmat_server_create", "hmat_server_submit", "hmat_server_wait",
-           "hmat_server_destroy", "hmat_server_last_error", "hmat_release_memory"]
+           "hmat_server_destroy", "hmat_server_last_error", "hmat_release_memory",
+           "hmat_set_mem_budget", "hmat_mem_held"]
 
 _lib = None
 
@@ -110,6 +111,8 @@ def lib():
     L.hmat_info.argtypes = [vp, C.POINTER(_Stats)]
     L.hmat_free.argtypes = [vp]
     L.hmat_release_memory.argtypes = [vp]
+    L.hmat_set_mem_budget.argtypes = [i64]
+    L.hmat_mem_held.argtypes = [C.POINTER(i64), C.POINTER(i64)]
     L.hmat_last_error.restype = C.c_char_p
     L.hmat_plan.argtypes = [C.POINTER(_Mesh), dbl, i32, vp, C.POINTER(i32), vp]
     L.hmat_block.argtypes = [vp, i32, vp, vp, vp, vp, vp]
@@ -168,6 +171,19 @@ def release_memory(stream=None) -> None:
     """Hand the device memory the library keeps for reuse back to the device
     (hmat_release_memory); live handles keep theirs."""
     _check(lib().hmat_release_memory(_stream(stream)))
+
+
+def set_mem_budget(nbytes: int) -> None:
+    """Cap on the device memory the library holds (0: none); see hmat_set_mem_budget."""
+    _check(lib().hmat_set_mem_budget(int(nbytes)))
+
+
+def mem_held() -> tuple[int, int]:
+    """(bytes of device memory the library holds on the current device, the
+    most it held since the previous call)."""
+    v, pk = C.c_int64(0), C.c_int64(0)
+    _check(lib().hmat_mem_held(C.byref(v), C.byref(pk)))
+    return v.value, pk.value
 
 
 def plan(vertices, triangles, eta: float = 2.0, leaf: int = 32):

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <atomic>
 #include <array>
 #include <chrono>
 #include <cmath>
@@ -162,6 +163,43 @@ int current_device() {
   return dev < MAX_DEVICES ? dev : -1;
 }
 
+// Device memory the library holds per device: live buffers, cached blocks
+// and kept ACA panel buffers (what it has allocated and not handed back), and
+// the cap hmat_set_mem_budget sets on it (0: none). An allocation that would
+// pass the cap fails as if the device were full, so the release-and-retry
+// path runs first and HMAT_ENOMEM follows if that does not make room.
+std::atomic<int64_t> g_held[MAX_DEVICES];
+std::atomic<int64_t> g_peak[MAX_DEVICES];  // largest g_held after an allocation since hmat_mem_held
+std::atomic<int64_t> g_budget{0};
+
+bool over_budget(int dev, size_t bytes) {
+  const int64_t b = g_budget.load();
+  return b > 0 && dev >= 0 && g_held[dev].load() + (int64_t)bytes > b;
+}
+hipError_t dev_malloc(void** p, size_t bytes, hipStream_t s, int dev) {
+  if (over_budget(dev, bytes)) return hipErrorOutOfMemory;
+  const hipError_t e = hipMallocAsync(p, bytes, s);
+  if (e == hipSuccess && dev >= 0) {
+    const int64_t now = g_held[dev] += (int64_t)bytes;
+    int64_t pk = g_peak[dev].load();
+    while (now > pk && !g_peak[dev].compare_exchange_weak(pk, now)) {
+    }
+  }
+  return e;
+}
+void dev_free(void* p, size_t bytes, hipStream_t s, int dev) {
+  (void)hipFreeAsync(p, s);
+  if (dev >= 0) g_held[dev] -= (int64_t)bytes;
+}
+// The error of an allocation that still failed after the retry.
+void check_alloc(hipError_t e, int dev, size_t bytes, const char* what) {
+  if (e == hipErrorOutOfMemory && over_budget(dev, bytes)) {
+    (void)hipGetLastError();
+    throw HipError{HMAT_ENOMEM, std::string(what) + ": the device memory budget (hmat_set_mem_budget) is exceeded"};
+  }
+  check(e, what);
+}
+
 // Frees every cached block of device dev, ordered on stream s, and hands the
 // default pool's unused memory back to the device.
 void mem_trim(int dev, hipStream_t s) {
@@ -176,7 +214,7 @@ void mem_trim(int dev, hipStream_t s) {
   }
   for (const CachedBlock& b : all) {
     (void)hipStreamWaitEvent(s, b.ev, 0);
-    (void)hipFreeAsync(b.p, s);
+    dev_free(b.p, b.bytes, s, dev);
     (void)hipEventDestroy(b.ev);
   }
   (void)hipStreamSynchronize(s);
@@ -232,6 +270,7 @@ void* mem_alloc(size_t b, hipStream_t s, size_t* cls, int* dev, const char* what
         (void)hipGetLastError();
         (void)hipStreamSynchronize(s);
         (void)hipFree(blk.p);
+        g_held[d] -= (int64_t)blk.bytes;
       } else {
         *cls = blk.bytes;
         return blk.p;
@@ -239,18 +278,18 @@ void* mem_alloc(size_t b, hipStream_t s, size_t* cls, int* dev, const char* what
     }
   }
   void* p = nullptr;
-  hipError_t e = hipMallocAsync(&p, cl, s);
+  hipError_t e = dev_malloc(&p, cl, s, d);
   if (e == hipErrorOutOfMemory) {  // hand everything kept back, then try again
     (void)hipGetLastError();
     const auto t0 = std::chrono::steady_clock::now();
     drop_idle_panels(d, s);
     mem_trim(d, s);
-    e = hipMallocAsync(&p, cl, s);
+    e = dev_malloc(&p, cl, s, d);
     if (std::getenv("HMAT_TRACE_BUILD"))
       std::fprintf(stderr, "hmat memory: %s (%zu bytes) found the device full; releasing kept memory and retrying took %.1f ms\n",
                    what, cl, std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
   }
-  check(e, what);
+  check_alloc(e, d, cl, what);
   *cls = cl;
   return p;
 }
@@ -259,7 +298,7 @@ void* mem_alloc(size_t b, hipStream_t s, size_t* cls, int* dev, const char* what
 // is on stream s.
 void mem_free(void* p, size_t cls, int dev, hipStream_t s) {
   if (dev < 0 || dev != current_device()) {
-    (void)hipFreeAsync(p, s);
+    dev_free(p, cls, s, dev);
     return;
   }
   MemCache& c = g_mem[dev];
@@ -280,7 +319,7 @@ void mem_free(void* p, size_t cls, int dev, hipStream_t s) {
       hipEventRecord(ev, s) != hipSuccess) {
     (void)hipGetLastError();
     if (ev) (void)hipEventDestroy(ev);
-    (void)hipFreeAsync(p, s);
+    dev_free(p, cls, s, dev);
     return;
   }
   std::vector<CachedBlock> evict;
@@ -297,7 +336,7 @@ void mem_free(void* p, size_t cls, int dev, hipStream_t s) {
   }
   for (const CachedBlock& b : evict) {
     (void)hipStreamWaitEvent(s, b.ev, 0);
-    (void)hipFreeAsync(b.p, s);
+    dev_free(b.p, b.bytes, s, dev);
     std::lock_guard<std::mutex> lk(c.mu);
     c.spare.push_back(b.ev);
   }
@@ -368,18 +407,17 @@ PanelCache g_panel_cache[MAX_DEVICES];
 // Frees the idle ACA panel buffers of device dev, ordered on stream s.
 void drop_idle_panels(int dev, hipStream_t s) {
   if (dev < 0) return;
-  std::vector<void*> idle;
+  std::vector<std::pair<void*, size_t>> idle;
   {
     std::lock_guard<std::mutex> lk(g_panel_cache[dev].mu);
-    for (const auto& q : g_panel_cache[dev].idle) idle.push_back(q.first);
-    g_panel_cache[dev].idle.clear();
+    idle.swap(g_panel_cache[dev].idle);
   }
-  for (void* q : idle) (void)hipFreeAsync(q, s);
+  for (const auto& q : idle) dev_free(q.first, q.second, s, dev);
 }
 
 class PanelLease {
  public:
-  PanelLease(int dev, hipStream_t s) : s_(s) {
+  PanelLease(int dev, hipStream_t s) : s_(s), dev_(dev < MAX_DEVICES ? dev : -1) {
     if (dev < 0 || dev >= MAX_DEVICES) return;
     PanelCache& c = g_panel_cache[dev];
     std::lock_guard<std::mutex> lk(c.mu);
@@ -422,15 +460,15 @@ class PanelLease {
       }
     }
     if (!p_) {
-      hipError_t e = hipMallocAsync(&p_, need, s_);
+      hipError_t e = dev_malloc(&p_, need, s_, dev_);
       if (e == hipErrorOutOfMemory) {
         (void)hipGetLastError();
         drop_idle(0);
-        mem_trim(current_device(), s_);
-        e = hipMallocAsync(&p_, need, s_);
+        mem_trim(dev_, s_);
+        e = dev_malloc(&p_, need, s_, dev_);
       }
       if (e != hipSuccess) p_ = nullptr;
-      check(e, "ACA panels");
+      check_alloc(e, dev_, need, "ACA panels");
       bytes_ = need;
     }
     return static_cast<double*>(p_);
@@ -455,7 +493,7 @@ class PanelLease {
  private:
   // Frees idle buffers, smallest first, until at most `keep` bytes are idle.
   void drop_idle(size_t keep) {
-    std::vector<void*> drop;
+    std::vector<std::pair<void*, size_t>> drop;
     {
       std::lock_guard<std::mutex> lk(cache_->mu);
       size_t total = 0;
@@ -466,14 +504,15 @@ class PanelLease {
                                      return x.second < y.second;
                                    });
         total -= it->second;
-        drop.push_back(it->first);
+        drop.push_back(*it);
         cache_->idle.erase(it);
       }
     }
-    for (void* q : drop) (void)hipFreeAsync(q, s_);
+    for (const auto& q : drop) dev_free(q.first, q.second, s_, dev_);
   }
 
   hipStream_t s_;
+  int dev_ = -1;
   PanelCache* cache_ = nullptr;
   void* p_ = nullptr;
   size_t bytes_ = 0;
@@ -2510,6 +2549,22 @@ hmat_status hmat_release_memory(void* hip_stream) {
     return fail(HMAT_EDEVICE, std::string("release memory: ") + hipGetErrorString(e));
   }
   mem_trim(dev, s);  // cached blocks, then the pool
+  return HMAT_OK;
+}
+
+hmat_status hmat_set_mem_budget(int64_t bytes) {
+  if (bytes < 0) return fail(HMAT_EINVAL, "budget must be >= 0 (0: none)");
+  g_budget.store(bytes);
+  return HMAT_OK;
+}
+
+hmat_status hmat_mem_held(int64_t* held, int64_t* peak) {
+  if (!held) return fail(HMAT_EINVAL, "held is NULL");
+  const int dev = current_device();
+  if (dev < 0) return fail(HMAT_EDEVICE, "no HIP device");
+  *held = g_held[dev].load();
+  const int64_t pk = g_peak[dev].exchange(0);
+  if (peak) *peak = pk;
   return HMAT_OK;
 }
 

@@ -155,6 +155,10 @@ def test_other_entry_points_reject_null_handle():
     assert L.hmat_matvec_ex(None, 1, 1, None, 3, None, 3, None) == H.HMAT_EINVAL
     assert L.hmat_solve_ir(None, None, None, 1e-8, 50, 10, 1, 1e-6, None, None) == H.HMAT_EINVAL
     assert L.hmat_free(None) == H.HMAT_OK
+    assert L.hmat_set_mem_budget(-1) == H.HMAT_EINVAL
+    assert "budget" in L.hmat_last_error().decode()
+    assert L.hmat_set_mem_budget(0) == H.HMAT_OK
+    assert L.hmat_mem_held(None, None) == H.HMAT_EINVAL
     srv = C.c_void_p(5)
     assert L.hmat_server_create(0, 0, 2.0, 32, C.byref(srv)) == H.HMAT_EINVAL and srv.value is None
     assert L.hmat_server_create(2, -1, 2.0, 32, C.byref(srv)) == H.HMAT_EINVAL
