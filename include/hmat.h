@@ -74,7 +74,8 @@ typedef enum {
   HMAT_ENOMEM = 2,  /* device or host allocation failed (budget included) */
   HMAT_EDEVICE = 3, /* a HIP call failed */
   HMAT_ENOCONV = 4, /* iteration limit reached; outputs still written */
-  HMAT_ENOTSUP = 5  /* valid but unsupported request */
+  HMAT_ENOTSUP = 5, /* valid but unsupported request */
+  HMAT_ECANCELED = 6 /* request server: the request was cancelled */
 } hmat_status;
 
 /* Surface triangulation (Sec. 4.2: admissible triangulation into flat
@@ -516,10 +517,25 @@ hmat_status hmat_server_submit(hmat_server_t s, const hmat_mesh* mesh, const hma
 
 /* hmat_server_wait -- block until request `id` completes; out (HOST,
  * nvec x n_dof or n_dof; may be NULL) receives A_H x or the solution, res
- * (may be NULL) its timings and counts. A request is collected once.
- * Returns the request's status (its error message via
- * hmat_server_last_error); HMAT_EINVAL for an unknown id. */
+ * (may be NULL) its timings and counts. A request is collected once: the
+ * first wait takes it, and a second wait on the same id (also one made
+ * while the first still waits) returns HMAT_EINVAL. Returns the request's
+ * status (its error message via hmat_server_last_error): HMAT_ECANCELED for
+ * a cancelled request; HMAT_EINVAL for an unknown id. */
 hmat_status hmat_server_wait(hmat_server_t s, int64_t id, double* out, hmat_result* res);
+
+/* hmat_server_cancel -- stop request `id` if it has not finished. A queued
+ * request leaves the queue at once (it never holds a reservation); a running
+ * one stops at its next phase boundary (before its build, after its build,
+ * before its products or solve), frees its handle and gives its memory
+ * reservation back, so queued requests can be admitted. Its wait then
+ * returns HMAT_ECANCELED. A request that has already finished keeps its
+ * result. Returns HMAT_OK, or HMAT_EINVAL for an unknown or collected id. */
+hmat_status hmat_server_cancel(hmat_server_t s, int64_t id);
+
+/* hmat_server_status -- HOST snapshot: bytes reserved by running requests
+ * (in_use), queued and running requests; any pointer may be NULL. */
+hmat_status hmat_server_status(hmat_server_t s, int64_t* in_use, int32_t* queued, int32_t* running);
 
 /* hmat_server_destroy -- finish every queued request, stop the workers and
  * free the server (NULL is a no-op). */

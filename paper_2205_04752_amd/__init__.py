@@ -17,8 +17,8 @@ __all__ = ["lib", "HMatrix", "Server", "plan", "amvm", "release_memory", "HmatEr
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhmat.so")
 
-HMAT_OK, HMAT_EINVAL, HMAT_ENOMEM, HMAT_EDEVICE, HMAT_ENOCONV, HMAT_ENOTSUP = range(6)
-_STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ENOCONV", 5: "ENOTSUP"}
+HMAT_OK, HMAT_EINVAL, HMAT_ENOMEM, HMAT_EDEVICE, HMAT_ENOCONV, HMAT_ENOTSUP, HMAT_ECANCELED = range(7)
+_STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ENOCONV", 5: "ENOTSUP", 6: "ECANCELED"}
 
 
 class HmatError(RuntimeError):
@@ -78,7 +78,7 @@ class _Result(C.Structure):
 EXPORTS = ["hmat_build", "hmat_build_batch", "hmat_bodies", "hmat_matvec", "hmat_matvec_ex",
            "hmat_solve", "hmat_solve_noalloc", "hmat_solve_ir", "hmat_set_precision", "hmat_info", "hmat_free",
            "hmat_last_error", "hmat_plan", "hmat_block", "hmat_entries", "hmat_set_factors",
-           "hmat_profile", "hmat_tune", "hmat_matvec_graph", "hmat_amvm", "hmat_server_create", "hmat_server_submit", "hmat_server_wait",
+           "hmat_profile", "hmat_tune", "hmat_matvec_graph", "hmat_amvm", "hmat_server_create", "hmat_server_submit", "hmat_server_wait", "hmat_server_cancel", "hmat_server_status",
            "hmat_server_destroy", "hmat_server_last_error", "hmat_release_memory",
            "hmat_set_mem_budget", "hmat_mem_held"]
 
@@ -126,6 +126,8 @@ def lib():
     L.hmat_server_create.argtypes = [i32, i64, dbl, i32, C.POINTER(vp)]
     L.hmat_server_submit.argtypes = [vp, C.POINTER(_Mesh), C.POINTER(_Request), vp, C.POINTER(i64)]
     L.hmat_server_wait.argtypes = [vp, i64, vp, C.POINTER(_Result)]
+    L.hmat_server_cancel.argtypes = [vp, i64]
+    L.hmat_server_status.argtypes = [vp, C.POINTER(i64), C.POINTER(i32), C.POINTER(i32)]
     L.hmat_server_destroy.argtypes = [vp]
     L.hmat_server_last_error.restype = C.c_char_p
     for name in EXPORTS:
@@ -442,6 +444,20 @@ class Server:
                 raise HmatError(st, lib().hmat_server_last_error().decode())
             return None, info
         return out, info
+
+    def cancel(self, rid: int) -> None:
+        """Stop request rid if it has not finished (its wait then reports ECANCELED)."""
+        st = lib().hmat_server_cancel(self._s, int(rid))
+        if st != HMAT_OK:
+            raise HmatError(st, lib().hmat_server_last_error().decode())
+
+    def status(self) -> dict:
+        """Bytes reserved by running requests, queued and running counts."""
+        u, q, r = C.c_int64(0), C.c_int32(0), C.c_int32(0)
+        st = lib().hmat_server_status(self._s, C.byref(u), C.byref(q), C.byref(r))
+        if st != HMAT_OK:
+            raise HmatError(st, lib().hmat_server_last_error().decode())
+        return dict(in_use=u.value, queued=q.value, running=r.value)
 
     def close(self):
         if getattr(self, "_s", None):

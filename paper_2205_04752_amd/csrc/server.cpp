@@ -12,6 +12,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
@@ -43,6 +44,7 @@ struct Request {
   std::string err;
   int64_t reserved = 0;
   bool done = false;
+  std::atomic<bool> cancel{false};  // set by hmat_server_cancel; checked between phases
 };
 
 // Device bytes a request is assumed to need before it is built: the stored
@@ -71,9 +73,10 @@ struct hmat_server {
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   std::deque<std::shared_ptr<Request>> pending;
-  std::map<int64_t, std::shared_ptr<Request>> all;
+  std::map<int64_t, std::shared_ptr<Request>> all;  // submitted, not collected
   int64_t next_id = 1;
   int64_t in_use = 0;
+  int32_t running = 0;
   bool stop = false;
   std::vector<std::thread> workers;
 
@@ -119,8 +122,17 @@ void hmat_server::execute(Request& r, hipStream_t s) {
     r.err = hmat_last_error();
     if (h) hmat_free(h);
   };
+  auto cancelled = [&]() {
+    if (!r.cancel.load()) return false;
+    r.res.status = HMAT_ECANCELED;
+    r.err = "request cancelled";
+    if (h) hmat_free(h);
+    return true;
+  };
+  if (cancelled()) return;
   hmat_status st = hmat_build(&mesh, r.q.E, r.q.nu, eta, leaf, r.q.eps, s, &h);
   if (st != HMAT_OK) return fail_req(st);
+  if (cancelled()) return;
   hmat_stats hs{};
   hmat_info(h, &hs);
   r.res.build_ms = hs.t_build_ms;
@@ -138,6 +150,7 @@ void hmat_server::execute(Request& r, hipStream_t s) {
     r.res.device_bytes = hs.device_bytes;
   }
   cv_work.notify_all();
+  if (cancelled()) return;
   const int nv = r.q.kind == HMAT_REQ_SOLVE ? 1 : r.q.nvec;
   DevVec dx, dy;
   if (!dx.alloc(sizeof(double) * N * nv, s) || !dy.alloc(sizeof(double) * N * nv, s)) {
@@ -206,11 +219,13 @@ void hmat_server::run_worker() {
       pending.pop_front();
       r->reserved = estimate_bytes(*r, aca_cap);
       in_use += r->reserved;
+      running++;
       r->res.t_admit_ms = now_ms();
     }
     execute(*r, s);
     {
       std::lock_guard<std::mutex> lk(mu);
+      running--;
       in_use -= r->reserved;
       r->reserved = 0;
       r->res.t_done_ms = now_ms();
@@ -317,12 +332,44 @@ hmat_status hmat_server_wait(hmat_server_t S, int64_t id, double* out, hmat_resu
     auto it = S->all.find(id);
     if (it == S->all.end()) return srv_fail(HMAT_EINVAL, "unknown request id (or already collected)");
     r = it->second;
+    S->all.erase(it);  // collected by this wait: another wait on id finds nothing
     S->cv_done.wait(lk, [&] { return r->done; });
-    S->all.erase(it);
   }
   if (res) *res = r->res;
   if (r->res.status != HMAT_OK) return srv_fail((hmat_status)r->res.status, r->err);
   if (out) std::memcpy(out, r->out.data(), sizeof(double) * r->out.size());
+  return HMAT_OK;
+}
+
+hmat_status hmat_server_cancel(hmat_server_t S, int64_t id) {
+  if (!S) return srv_fail(HMAT_EINVAL, "server is NULL");
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->all.find(id);
+    if (it == S->all.end()) return srv_fail(HMAT_EINVAL, "unknown request id (or already collected)");
+    const std::shared_ptr<Request>& r = it->second;
+    if (r->done) return HMAT_OK;
+    r->cancel.store(true);
+    auto q = std::find(S->pending.begin(), S->pending.end(), r);
+    if (q != S->pending.end()) {  // still queued: finish it here, never admitted
+      S->pending.erase(q);
+      r->res.status = HMAT_ECANCELED;
+      r->err = "request cancelled";
+      r->res.t_done_ms = S->now_ms();
+      r->done = true;
+    }
+  }
+  S->cv_done.notify_all();
+  S->cv_work.notify_all();
+  return HMAT_OK;
+}
+
+hmat_status hmat_server_status(hmat_server_t S, int64_t* in_use, int32_t* queued, int32_t* running) {
+  if (!S) return srv_fail(HMAT_EINVAL, "server is NULL");
+  std::lock_guard<std::mutex> lk(S->mu);
+  if (in_use) *in_use = S->in_use;
+  if (queued) *queued = (int32_t)S->pending.size();
+  if (running) *running = S->running;
   return HMAT_OK;
 }
 

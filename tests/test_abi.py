@@ -166,6 +166,8 @@ def test_other_entry_points_reject_null_handle():
     assert L.hmat_server_last_error().decode()
     assert L.hmat_server_submit(None, None, None, None, None) == H.HMAT_EINVAL
     assert L.hmat_server_wait(None, 1, None, None) == H.HMAT_EINVAL
+    assert L.hmat_server_cancel(None, 1) == H.HMAT_EINVAL
+    assert L.hmat_server_status(None, None, None, None) == H.HMAT_EINVAL
     assert L.hmat_server_destroy(None) == H.HMAT_OK
 
 

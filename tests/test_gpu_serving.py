@@ -131,3 +131,59 @@ def test_submit_errors():
     with pytest.raises(H.HmatError):
         srv.submit(V, T, np.zeros(3 * len(T)), kind=H.REQ_SOLVE, tol=0.0)
     srv.close()
+
+
+def test_cancel_frees_reservation():
+    """A cancelled queued request leaves the queue without ever being admitted;
+    a cancelled running request stops at its next phase boundary and gives its
+    memory reservation back, so the next queued request is admitted and
+    completes; afterwards nothing is reserved, queued or running."""
+    H = _H()
+    Vb, Tb = W.icosphere(5)
+    Vs, Ts = W.icosphere(2)
+    print("case serving: cancellation", flush=True)
+    srv = H.Server(slots=1, hbm_budget=1)  # below any request: one at a time
+    a = srv.submit(Vb, Tb, W.smooth_rhs(Vb, Tb, seed=1), kind=H.REQ_SOLVE, eps=1e-7, tol=1e-10)
+    b = srv.submit(Vs, Ts, W.random_x(3 * len(Ts), 2, seed=2), kind=H.REQ_MATVEC, eps=1e-6)
+    c = srv.submit(Vs, Ts, W.random_x(3 * len(Ts), 1, seed=3), kind=H.REQ_MATVEC, eps=1e-6)
+    srv.cancel(b)
+    out, ib = srv.wait(b, check=False)
+    assert out is None and ib["status"] == H.HMAT_ECANCELED and ib["t_admit_ms"] == 0.0
+    srv.cancel(a)
+    out, ia = srv.wait(a, check=False)
+    assert out is None and ia["status"] == H.HMAT_ECANCELED, ia
+    yc, ic = srv.wait(c)
+    assert ic["status"] == H.HMAT_OK
+    g = H.HMatrix(Vs, Ts, 1.0, 0.3, 2.0, 32, 1e-6)
+    y = g.matvec(torch.from_numpy(W.random_x(3 * len(Ts), 1, seed=3)).cuda()).cpu().numpy()
+    g.close()
+    assert np.array_equal(yc.reshape(y.shape), y)
+    assert srv.status() == dict(in_use=0, queued=0, running=0)
+    with pytest.raises(H.HmatError):
+        srv.cancel(c)  # collected
+    srv.close()
+
+
+def test_second_wait_on_an_id_is_rejected():
+    """Two threads wait on one request: exactly one gets the result, the other
+    HMAT_EINVAL (a request is collected once)."""
+    import ctypes as C
+    import threading
+    H = _H()
+    V, T = W.icosphere(3)
+    srv = H.Server(slots=1)
+    rid = srv.submit(V, T, W.random_x(3 * len(T), 1, seed=4), kind=H.REQ_MATVEC, eps=1e-6)
+    codes = []
+
+    def waiter():
+        res = H._Result()
+        codes.append(H.lib().hmat_server_wait(srv._s, rid, None, C.byref(res)))
+
+    ts = [threading.Thread(target=waiter) for _ in range(2)]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    assert sorted(codes) == [H.HMAT_OK, H.HMAT_EINVAL], codes
+    srv._n.pop(rid, None)
+    srv.close()
