@@ -111,7 +111,9 @@ typedef struct {
                              the first pass, min(128, max(32, 16 ceil((24 + 12 log10(1/eps)) / 16)))
                              steps; each later pass continues those blocks from where they
                              stopped with 4x the capacity, at most min(m,n) */
-  int32_t reserved;
+  int32_t n_exact;        /* admissible blocks whose ACA reached full rank, stored exactly:
+                             U = B, V = I (n <= m) or U = I, V = B^T (a cross approximation
+                             is kept only as a compression, Sec. 2) */
   double t_plan_ms;       /* host: geometry, tree, partition, device lists */
   double t_near_ms;       /* device: dense blocks (K1) */
   double t_aca_ms;        /* device: ACA (K2) incl. compaction */

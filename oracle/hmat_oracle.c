@@ -890,6 +890,29 @@ static int h_fill(or_hmat* h, double eps, int kcap) {
     h->pcol[b] = (int*)malloc(sizeof(int) * kmax);
     h->rank[b] = aca_core(m, n, blk_row, blk_col, &src, eps, kcap, 3, eps == 0.0, &h->U[b], &h->Vf[b], h->prow[b],
                           h->pcol[b], &h->stop[b], &h->ratio[b]);
+    /* A block whose accuracy-controlled ACA reaches full rank is stored
+     * exactly: a cross approximation is kept only as a compression (Sec. 2
+     * stores a block low-rank only if k(M+N) < MN, which full rank never
+     * meets), and a full-rank run can end inexact when a remainder at
+     * rounding level is taken as a cross. U = B, V = I for n <= m, else
+     * U = I, V = B^T; the rank stays min(m, n). */
+    if (eps > 0.0 && h->rank[b] == kmax) {
+      double* U = h->U[b];
+      double* V = h->Vf[b];
+      memset(U, 0, sizeof(double) * (size_t)m * kmax);
+      memset(V, 0, sizeof(double) * (size_t)n * kmax);
+      if (n <= m) {
+        for (int c = 0; c < n; c++) {
+          blk_col(&src, c, U + (size_t)c * m);
+          V[(size_t)c * n + c] = 1.0;
+        }
+      } else {
+        for (int r = 0; r < m; r++) {
+          blk_row(&src, r, V + (size_t)r * n);
+          U[(size_t)r * m + r] = 1.0;
+        }
+      }
+    }
   }
   free(idx);
   h->t_near = t1 - t0;

@@ -39,7 +39,7 @@ class _Stats(C.Structure):
                 ("rank_max", C.c_int32), ("rank_mean", C.c_double), ("far_scalars", C.c_int64),
                 ("near_scalars", C.c_int64), ("compression", C.c_double),
                 ("n_rank_full", C.c_int32), ("n_near_threshold", C.c_int32),
-                ("aca_passes", C.c_int32), ("reserved", C.c_int32), ("t_plan_ms", C.c_double),
+                ("aca_passes", C.c_int32), ("n_exact", C.c_int32), ("t_plan_ms", C.c_double),
                 ("t_near_ms", C.c_double), ("t_aca_ms", C.c_double), ("t_build_ms", C.c_double),
                 ("device_bytes", C.c_int64), ("far_u_scalars", C.c_int64),
                 ("far_v_scalars", C.c_int64), ("t_aca_kernel_ms", C.c_double),

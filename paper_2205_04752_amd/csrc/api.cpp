@@ -29,6 +29,7 @@ hipError_t launch_entries(const DevGeo&, int64_t, const int64_t*, const int64_t*
 hipError_t launch_aca(const DevGeo&, const AcaTask*, int, int, size_t, size_t, bool, int32_t*, int32_t*,
                       double*, hipStream_t);
 hipError_t launch_compact(const CopyTask*, int, hipStream_t);
+hipError_t launch_exact(const DevGeo&, const ExactTask*, int, hipStream_t);
 hipError_t launch_copy_spans(const SpanCopy*, int, hipStream_t);
 hipError_t launch_to_stream(const StreamTask*, int, double*, hipStream_t);
 hipError_t launch_from_stream(const StreamTask*, int, const double*, hipStream_t);
@@ -619,6 +620,7 @@ struct hmat {
   std::vector<const int32_t*> piv_ptr;  // per far block: device [2][cap]
   std::vector<int32_t> piv_cap;
   int aca_passes = 0;
+  int32_t n_exact = 0;  // admissible blocks stored exactly (ACA reached full rank)
   // product plan
   DevBuf d_seg;
   // Work lists: [0] for single right-hand sides (8-column phase-A items,
@@ -1003,6 +1005,7 @@ void fill_stats(hmat* h) {
   for (const hmat::Body& B : h->bodies) dense += 9.0 * (double)B.nt * (double)B.nt;
   st.compression = (double)(st.far_scalars + st.near_scalars) / dense;
   st.aca_passes = h->aca_passes;
+  st.n_exact = h->n_exact;
   st.n_bodies = (int32_t)h->bodies.size();
   size_t piv_bytes = 0;
   for (const DevBuf& d : h->piv_bufs) piv_bytes += d.bytes;
@@ -1362,6 +1365,7 @@ hmat_status build_impl(const std::vector<BodyIn>& in, double eta, int32_t leaf, 
       std::iota(grp.begin(), grp.end(), (int32_t)f0);
       for (int32_t f : grp) capv[f] = cap1(f);
       std::deque<DevBuf> panels_more;  // panels of the later passes (read by the compaction)
+      int64_t later_bytes = 0;         // their bytes
       h->piv_bufs.emplace_back();
       run_aca_pass(h, grp, cap1, [&](size_t b) { return panels1.get(b); }, h->piv_bufs.back(), d_rank,
                    d_stop, d_ratio, panel_ptr, states, zbits, zoff, [](const std::vector<AcaTask>&) {},
@@ -1410,18 +1414,54 @@ hmat_status build_impl(const std::vector<BodyIn>& in, double eta, int32_t leaf, 
           upload(d_spans, sp, s, "ACA carry");
           check(launch_copy_spans(d_spans.as<SpanCopy>(), (int)sp.size(), s), "ACA carry");
         };
-        panels_more.emplace_back();
-        DevBuf& pb = panels_more.back();
-        h->piv_bufs.emplace_back();
-        run_aca_pass(h, again, [&](int32_t f) { return capv[f]; },
-                     [&](size_t b) {
-                       if (pb.bytes < b) pb.alloc(b, "ACA panels");
-                       return pb.as<double>();
-                     },
-                     h->piv_bufs.back(), d_rank, d_stop, d_ratio, panel_ptr, states, zbits, zoff, carry, true,
-                     s);
+        // in sub-groups whose panels fit what is left of the ACA budget beside
+        // the later-pass panels this group already holds (one block at least)
+        for (size_t a0 = 0; a0 < again.size();) {
+          size_t a1 = a0;
+          int64_t bytes = 0;
+          const int64_t avail = std::max<int64_t>(budget - later_bytes, 0);
+          while (a1 < again.size()) {
+            const int32_t b = h->far_blocks[again[a1]];
+            const int64_t bb = 8 * ((block_m(h, b) + block_n(h, b)) * (int64_t)capv[again[a1]]);
+            if (a1 > a0 && bytes + bb > avail) break;
+            bytes += bb;
+            a1++;
+          }
+          const std::vector<int32_t> sub(again.begin() + a0, again.begin() + a1);
+          panels_more.emplace_back();
+          DevBuf& pb = panels_more.back();
+          h->piv_bufs.emplace_back();
+          run_aca_pass(h, sub, [&](int32_t f) { return capv[f]; },
+                       [&](size_t b) {
+                         if (pb.bytes < b) pb.alloc(b, "ACA panels");
+                         return pb.as<double>();
+                       },
+                       h->piv_bufs.back(), d_rank, d_stop, d_ratio, panel_ptr, states, zbits, zoff, carry,
+                       true, s);
+          later_bytes += (int64_t)pb.bytes;
+          a0 = a1;
+        }
         h->aca_passes = std::max(h->aca_passes, pass);
         fetch();
+      }
+      // blocks whose ACA reached full rank are stored exactly (U = B, V = I or
+      // U = I, V = B^T) in their panels before the compaction
+      {
+        std::vector<ExactTask> ex;
+        for (int32_t f : grp) {
+          const int32_t b = h->far_blocks[f];
+          const BlockRec& B = h->plan.blk[b];
+          const auto& CL = h->plan.cl;
+          if (h->rank[f] == std::min(block_m(h, b), block_n(h, b)))
+            ex.push_back(ExactTask{CL[B.t].off, CL[B.t].len, CL[B.s].off, CL[B.s].len,
+                                   const_cast<double*>(panel_ptr[f]), capv[f], 0});
+        }
+        if (!ex.empty()) {
+          DevBuf d_ex;
+          upload(d_ex, ex, s, "exact factors");
+          check(launch_exact(h->G, d_ex.as<ExactTask>(), (int)ex.size(), s), "exact factors");
+          h->n_exact += (int32_t)ex.size();
+        }
       }
       // U and V staged in separate buffers: the V staging is freed as soon as
       // the V arena is filled, before the stream arena is allocated

@@ -128,6 +128,14 @@ struct SpanCopy {
   int64_t words;
 };
 
+// A block whose ACA reached full rank, stored exactly in its panels (U m x
+// kcap, V n x kcap): U = B, V = I for n <= m, else U = I, V = B^T.
+struct ExactTask {
+  int32_t t_off, t_len, s_off, s_len;
+  double* panel;
+  int32_t kcap, pad;
+};
+
 // Compaction of the V factors: copy the first k columns of a scratch panel
 // (n x kcap, leading dimension n) into the panel layout above.
 struct CopyTask {

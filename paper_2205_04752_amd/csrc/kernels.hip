@@ -1257,6 +1257,47 @@ hipError_t launch_copy_spans(const SpanCopy* t, int n, hipStream_t s) {
   return hipGetLastError();
 }
 
+// A block whose accuracy-controlled ACA reached full rank is stored exactly
+// (a cross approximation is kept only as a compression, Sec. 2, and a
+// full-rank run can end inexact when a remainder at rounding level is taken
+// as a cross): U = B, V = I for n <= m, else U = I, V = B^T, entries as in the
+// ACA passes (S symmetric: A[3p+a, 3q+b] = S_ba). One workgroup per block.
+__global__ __launch_bounds__(256) void k_exact(DevGeo g0, const ExactTask* __restrict__ tasks) {
+  const ExactTask T = tasks[blockIdx.x];
+  const DevGeo g = body_geo(g0, T.t_off);
+  const int m = 3 * T.t_len, n = 3 * T.s_len, nt = g.nt;
+  double* __restrict__ U = T.panel;
+  double* __restrict__ V = T.panel + (size_t)m * T.kcap;
+  if (n <= m) {
+    for (int e = threadIdx.x; e < T.t_len * n; e += blockDim.x) {
+      const int p = e % T.t_len, c = e / T.t_len, ip = T.t_off + p;
+      double e0, e1, e2;
+      row3(g, g.cen[ip], g.cen[nt + ip], g.cen[2 * nt + ip], c % 3, T.s_off + c / 3, e0, e1, e2);
+      double* col = U + (size_t)c * m + 3 * p;
+      col[0] = e0;
+      col[1] = e1;
+      col[2] = e2;
+    }
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) V[(size_t)(e / n) * n + e % n] = (e / n == e % n) ? 1.0 : 0.0;
+  } else {
+    for (int e = threadIdx.x; e < m * T.s_len; e += blockDim.x) {
+      const int q = e % T.s_len, r = e / T.s_len, ip = T.t_off + r / 3;
+      double e0, e1, e2;
+      row3(g, g.cen[ip], g.cen[nt + ip], g.cen[2 * nt + ip], r % 3, T.s_off + q, e0, e1, e2);
+      double* col = V + (size_t)r * n + 3 * q;
+      col[0] = e0;
+      col[1] = e1;
+      col[2] = e2;
+    }
+    for (int e = threadIdx.x; e < m * m; e += blockDim.x) U[(size_t)(e / m) * m + e % m] = (e / m == e % m) ? 1.0 : 0.0;
+  }
+}
+
+hipError_t launch_exact(const DevGeo& g, const ExactTask* tasks, int ntasks, hipStream_t s) {
+  if (ntasks > 0) hipLaunchKernelGGL(k_exact, dim3(ntasks), dim3(256), 0, s, g, tasks);
+  return hipGetLastError();
+}
+
 hipError_t launch_compact(const CopyTask* tasks, int ntasks, hipStream_t s) {
   if (ntasks > 0) hipLaunchKernelGGL(k_compact, dim3(ntasks), dim3(256), 0, s, tasks);
   return hipGetLastError();

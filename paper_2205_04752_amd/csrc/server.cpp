@@ -50,14 +50,15 @@ struct Request {
 // Device bytes a request is assumed to need before it is built: the stored
 // matrix at 25% of dense FP64 (a bound above what the admissibility and
 // accuracy settings of this library produce at these sizes; 9-11% measured
-// at 61k DOF, eps 1e-5 .. 1e-6), an FP32 copy if asked for, the capped ACA
-// panels, and vectors.
+// at 61k DOF, eps 1e-5 .. 1e-6), an FP32 copy if asked for, the ACA panels
+// (the first pass's and the later passes', each capped by the worker's ACA
+// budget), and vectors.
 int64_t estimate_bytes(const Request& r, int64_t aca_cap) {
   const double N = (double)r.T.size();  // 3 DOF per triangle
   const double stored = 0.25 * N * N;
   const double mat = 8.0 * stored * (r.q.precision == 1 ? 1.5 : 1.0);
   const double vec = 8.0 * N * (60.0 + 2.0 * std::max(1, r.q.nvec));
-  return (int64_t)(mat + vec) + aca_cap;
+  return (int64_t)(mat + vec) + 2 * aca_cap;
 }
 
 }  // namespace

@@ -194,3 +194,34 @@ def test_pivot_ties_take_the_lowest_index():
     assert r["cols"][1] == 0
     assert r["U"].shape[1] == 2
     assert np.linalg.norm(A - r["U"] @ r["V"].T) <= 1e-13 * np.linalg.norm(A)
+
+
+def test_full_rank_blocks_stored_exactly():
+    """An admissible block whose accuracy-controlled ACA reaches full rank is
+    stored exactly (U = B, V = I, or U = I, V = B^T; Sec. 2 keeps a cross
+    approximation only as a compression): on a flat plate with leaf 8 (small
+    blocks of a regular grid, many at full rank) every such block reproduces
+    its dense block, recomputed here entry by entry, to rounding, and every
+    other block stays within the accuracy the ACA pins allow."""
+    V, T = W.plate(20)
+    mesh = O.Mesh(V, T, 1.0, 0.3)
+    eps = 1e-6
+    h = O.HMatrix(mesh, 2.0, 8, eps=eps)
+    ob = h.blocks()
+    A = mesh.dense()
+    order = h.order
+    n_full = 0
+    for b in np.nonzero(ob[:, 4] == 1)[0]:
+        rt = (3 * order[ob[b, 0]:ob[b, 0] + ob[b, 1], None] + np.arange(3)).ravel()
+        cs = (3 * order[ob[b, 2]:ob[b, 2] + ob[b, 3], None] + np.arange(3)).ravel()
+        B = A[np.ix_(rt, cs)]
+        U, Vv, _, _ = h.factors(int(b))
+        err = np.linalg.norm(B - U @ Vv.T) / np.linalg.norm(B)
+        if U.shape[1] == min(B.shape):
+            n_full += 1
+            assert err <= 1e-15, (b, err)
+            I = np.eye(min(B.shape))
+            assert np.array_equal(Vv, I) if B.shape[1] <= B.shape[0] else np.array_equal(U, I)
+        else:
+            assert err <= 200 * eps, (b, err)
+    assert n_full > 10, n_full
