@@ -125,6 +125,8 @@ typedef struct {
   double t_layout_ms;     /* host + device: compaction, product plan, stream fill */
   int32_t aca_groups;     /* groups of admissible blocks ACA ran in (memory budget) */
   int32_t n_bodies;       /* bodies in the handle (hmat_build_batch) */
+  int32_t precision;      /* stored entries: 0 FP64, 1 FP32 only (hmat_build_ex) */
+  int32_t aca_fp32;       /* 1 if ACA ran in FP32 */
 } hmat_stats;
 
 typedef struct {
@@ -162,6 +164,34 @@ typedef struct {
  */
 hmat_status hmat_build(const hmat_mesh* mesh, double E, double nu, double eta, int32_t leaf,
                        double eps, void* hip_stream, hmat_t* out);
+
+/*
+ * hmat_build_ex -- hmat_build with options (opts may be NULL: the defaults).
+ *   precision        0 (default): entries, ACA and storage in FP64.
+ *                    1: the handle stores its entries in FP32 only (half the
+ *                    device memory; products and solves read them in FP64
+ *                    arithmetic, and hmat_solve_ir's residual uses them too,
+ *                    so its relative residual refers to the FP32-stored
+ *                    operator). ACA runs in FP32 (panels, entries and
+ *                    remainders; the ||S_k|| update in FP64) for eps >= 1e-5,
+ *                    where FP32 arithmetic resolves the remainders; for
+ *                    smaller eps it runs in FP64 and the factors are rounded.
+ *                    Dense blocks are computed in FP64 and rounded.
+ *                    hmat_set_precision(h, 0) and FP64-precision calls then
+ *                    return HMAT_ENOTSUP; hmat_set_factors too.
+ *   aca_stop_factor  the constant c of the ACA stop test |u_k||v_k| <= c eps ||S_k||_F
+ *                    (Algorithm 1 prints eps(1-beta)/(1+eps); default 1.0).
+ * Errors: as hmat_build; HMAT_EINVAL for precision not 0 or 1, or
+ * aca_stop_factor <= 0 or aca_stop_factor * eps >= 1.
+ */
+typedef struct {
+  int32_t precision;
+  int32_t reserved; /* 0 */
+  double aca_stop_factor;
+} hmat_opts;
+
+hmat_status hmat_build_ex(const hmat_mesh* mesh, double E, double nu, double eta, int32_t leaf,
+                          double eps, const hmat_opts* opts, void* hip_stream, hmat_t* out);
 
 /*
  * hmat_build_batch -- hmat_build for n_bodies independent bodies in one

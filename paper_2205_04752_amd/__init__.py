@@ -43,7 +43,8 @@ class _Stats(C.Structure):
                 ("t_near_ms", C.c_double), ("t_aca_ms", C.c_double), ("t_build_ms", C.c_double),
                 ("device_bytes", C.c_int64), ("far_u_scalars", C.c_int64),
                 ("far_v_scalars", C.c_int64), ("t_aca_kernel_ms", C.c_double),
-                ("t_layout_ms", C.c_double), ("aca_groups", C.c_int32), ("n_bodies", C.c_int32)]
+                ("t_layout_ms", C.c_double), ("aca_groups", C.c_int32), ("n_bodies", C.c_int32),
+                ("precision", C.c_int32), ("aca_fp32", C.c_int32)]
 
 
 class _SolveInfo(C.Structure):
@@ -62,6 +63,10 @@ class _AmvmInfo(C.Structure):
                 ("marked_total", C.c_int64), ("gamma", C.c_double), ("time_ms", C.c_double)]
 
 
+class _Opts(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("reserved", C.c_int32), ("aca_stop_factor", C.c_double)]
+
+
 class _Request(C.Structure):
     _fields_ = [("kind", C.c_int32), ("nvec", C.c_int32), ("precision", C.c_int32),
                 ("restart", C.c_int32), ("E", C.c_double), ("nu", C.c_double), ("eps", C.c_double),
@@ -75,7 +80,7 @@ class _Result(C.Structure):
                 ("device_bytes", C.c_int64)]
 
 
-EXPORTS = ["hmat_build", "hmat_build_batch", "hmat_bodies", "hmat_matvec", "hmat_matvec_ex",
+EXPORTS = ["hmat_build", "hmat_build_ex", "hmat_build_batch", "hmat_bodies", "hmat_matvec", "hmat_matvec_ex",
            "hmat_solve", "hmat_solve_noalloc", "hmat_solve_ir", "hmat_set_precision", "hmat_info", "hmat_free",
            "hmat_last_error", "hmat_plan", "hmat_block", "hmat_entries", "hmat_set_factors",
            "hmat_profile", "hmat_tune", "hmat_matvec_graph", "hmat_amvm", "hmat_server_create", "hmat_server_submit", "hmat_server_wait", "hmat_server_cancel", "hmat_server_status",
@@ -100,6 +105,7 @@ def lib():
     L = C.CDLL(LIB_PATH)
     vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
     L.hmat_build.argtypes = [C.POINTER(_Mesh), dbl, dbl, dbl, i32, dbl, vp, C.POINTER(vp)]
+    L.hmat_build_ex.argtypes = [C.POINTER(_Mesh), dbl, dbl, dbl, i32, dbl, C.POINTER(_Opts), vp, C.POINTER(vp)]
     L.hmat_build_batch.argtypes = [i32, vp, vp, vp, vp, dbl, i32, vp, C.POINTER(vp)]
     L.hmat_bodies.argtypes = [vp, C.POINTER(i32), vp]
     L.hmat_matvec.argtypes = [vp, i32, vp, i64, vp, i64, vp]
@@ -222,11 +228,18 @@ class HMatrix:
     """Device-resident H-matrix of the Kelvin single-layer collocation matrix."""
 
     def __init__(self, vertices, triangles, E=1.0, nu=0.3, eta=2.0, leaf=32, eps=1e-4,
-                 stream=None):
+                 stream=None, precision: int = 0, aca_stop_factor: float = 1.0):
+        """precision 1 stores the entries in FP32 only (hmat_build_ex);
+        aca_stop_factor is the constant of the ACA stop test."""
         m, keep = _mesh(vertices, triangles)
         h = C.c_void_p()
-        _check(lib().hmat_build(C.byref(m), float(E), float(nu), float(eta), int(leaf),
-                                float(eps), _stream(stream), C.byref(h)))
+        if precision == 0 and aca_stop_factor == 1.0:
+            _check(lib().hmat_build(C.byref(m), float(E), float(nu), float(eta), int(leaf),
+                                    float(eps), _stream(stream), C.byref(h)))
+        else:
+            o = _Opts(int(precision), 0, float(aca_stop_factor))
+            _check(lib().hmat_build_ex(C.byref(m), float(E), float(nu), float(eta), int(leaf),
+                                       float(eps), C.byref(o), _stream(stream), C.byref(h)))
         self._h = h
         self.n_triangles = m.n_triangles
         self.n_dof = 3 * m.n_triangles

@@ -26,13 +26,15 @@ namespace hm {
 hipError_t launch_self(const DevGeo&, const SelfTask*, double*, hipStream_t);
 hipError_t launch_near_only(const DevGeo&, const NearTask*, int, double*, hipStream_t);
 hipError_t launch_entries(const DevGeo&, int64_t, const int64_t*, const int64_t*, double*, hipStream_t);
-hipError_t launch_aca(const DevGeo&, const AcaTask*, int, int, size_t, size_t, bool, int32_t*, int32_t*,
+hipError_t launch_aca(const DevGeo&, const AcaTask*, int, int, size_t, size_t, bool, bool, int32_t*, int32_t*,
                       double*, hipStream_t);
 hipError_t launch_compact(const CopyTask*, int, hipStream_t);
-hipError_t launch_exact(const DevGeo&, const ExactTask*, int, hipStream_t);
+hipError_t launch_exact(const DevGeo&, const ExactTask*, int, bool, hipStream_t);
+hipError_t launch_compact32(const CopyTask32*, int, hipStream_t);
 hipError_t launch_copy_spans(const SpanCopy*, int, hipStream_t);
 hipError_t launch_to_stream(const StreamTask*, int, double*, hipStream_t);
 hipError_t launch_from_stream(const StreamTask*, int, const double*, hipStream_t);
+hipError_t launch_from_stream32(const StreamTask*, int, const float*, hipStream_t);
 hipError_t launch_gather(int, const double*, int64_t, const int32_t*, int64_t, double*, int64_t, hipStream_t);
 hipError_t launch_matvec_group(const ProductPlanDev&, int, int, const double*, int64_t, double*, int64_t,
                                double*, double*, int64_t, hipStream_t, hipEvent_t*, int);
@@ -604,6 +606,7 @@ struct hmat {
   std::vector<Body> bodies;
   std::vector<int32_t> pos_body;  // cluster position -> body
   DevBuf d_cen, d_q, d_vtx, d_gl, d_order, d_kc;
+  DevBuf d_cen32, d_q32;  // FP32 copies of d_cen, d_q (FP32 ACA only)
   DevGeo G{};
   std::vector<int32_t> inv_order;  // caller's triangle -> cluster position
   // block bookkeeping (canonical order)
@@ -621,6 +624,9 @@ struct hmat {
   std::vector<int32_t> piv_cap;
   int aca_passes = 0;
   int32_t n_exact = 0;  // admissible blocks stored exactly (ACA reached full rank)
+  bool fp32_only = false;    // entries stored in FP32 only (hmat_build_ex precision 1)
+  bool fp32_aca = false;     // ACA in FP32 (FP32 builds with eps >= 1e-5)
+  double stop_factor = 1.0;  // ACA stop test |u||v| <= stop_factor eps ||S||
   // product plan
   DevBuf d_seg;
   // Work lists: [0] for single right-hand sides (8-column phase-A items,
@@ -1006,6 +1012,8 @@ void fill_stats(hmat* h) {
   st.compression = (double)(st.far_scalars + st.near_scalars) / dense;
   st.aca_passes = h->aca_passes;
   st.n_exact = h->n_exact;
+  st.precision = h->fp32_only ? 1 : 0;
+  st.aca_fp32 = h->fp32_aca ? 1 : 0;
   st.n_bodies = (int32_t)h->bodies.size();
   size_t piv_bytes = 0;
   for (const DevBuf& d : h->piv_bufs) piv_bytes += d.bytes;
@@ -1045,7 +1053,7 @@ struct EventPair {
 template <class CapFn, class PanelFn, class PrepFn>
 void run_aca_pass(hmat* h, const std::vector<int32_t>& fidx, CapFn cap, PanelFn get_panels, DevBuf& piv,
                   DevBuf& d_rank, DevBuf& d_stop, DevBuf& d_ratio,
-                  std::vector<const double*>& panel_ptr, AcaState* states, uint32_t* zbits,
+                  std::vector<const void*>& panel_ptr, AcaState* states, uint32_t* zbits,
                   const std::vector<int64_t>& zoff, PrepFn prep, bool wide, hipStream_t s) {
   const Plan& P = h->plan;
   // largest blocks first (|t| + |s|), equal sizes in the given order
@@ -1063,6 +1071,7 @@ void run_aca_pass(hmat* h, const std::vector<int32_t>& fidx, CapFn cap, PanelFn 
     return std::max(P.cl[B.t].len, P.cl[B.s].len) > ACA_SMALL_TRI;
   };
   const int n_big = (int)(std::stable_partition(ord.begin(), ord.end(), big) - ord.begin());
+  const int esize = h->fp32_aca ? 4 : 8;  // bytes per panel entry
   int64_t panel_total = 0, piv_total = 0;
   size_t shmem[2] = {0, 0};  // 256-thread part, one-wave part
   for (size_t q = 0; q < ord.size(); q++) {
@@ -1072,11 +1081,11 @@ void run_aca_pass(hmat* h, const std::vector<int32_t>& fidx, CapFn cap, PanelFn 
     panel_total += (m + n) * kc;
     piv_total += 2 * (int64_t)kc;
     size_t& sh = shmem[(int)q < n_big ? 0 : 1];
-    sh = std::max(sh, aca_shmem(kc, m, n, (int)q < n_big ? (wide ? ACA_WIDE_NWV : ACA_NWV) : 1));
+    sh = std::max(sh, aca_shmem(kc, m, n, (int)q < n_big ? (wide ? ACA_WIDE_NWV : ACA_NWV) : 1, esize));
   }
   if (std::max(shmem[0], shmem[1]) > 160 * 1024)
     throw HipError{HMAT_ENOTSUP, "ACA panel row exceeds LDS capacity"};
-  double* const panels = get_panels(sizeof(double) * std::max<int64_t>(panel_total, 1));
+  char* const panels = static_cast<char*>(get_panels((size_t)esize * std::max<int64_t>(panel_total, 1)));
   piv.alloc(sizeof(int32_t) * piv_total, "ACA pivots");
   std::vector<AcaTask> tasks;
   tasks.reserve(ord.size());
@@ -1091,11 +1100,11 @@ void run_aca_pass(hmat* h, const std::vector<int32_t>& fidx, CapFn cap, PanelFn 
     t.t_len = P.cl[B.t].len;
     t.s_off = P.cl[B.s].off;
     t.s_len = P.cl[B.s].len;
-    t.panel = panels + po;
+    t.panel = panels + (size_t)esize * po;
     t.piv = piv.as<int32_t>() + vo;
     t.kcap = kc;
     t.blk = f;
-    t.eps = h->bodies[h->pos_body[t.t_off]].eps;
+    t.eps = h->bodies[h->pos_body[t.t_off]].eps * h->stop_factor;
     t.st = states + f;
     t.zbits = zbits + zoff[f];
     tasks.push_back(t);
@@ -1110,7 +1119,7 @@ void run_aca_pass(hmat* h, const std::vector<int32_t>& fidx, CapFn cap, PanelFn 
   prep(tasks);
   EventPair ev;
   check(hipEventRecord(ev.a, s), "event");
-  check(launch_aca(h->G, d_tasks.as<AcaTask>(), (int)tasks.size(), n_big, shmem[0], shmem[1], wide,
+  check(launch_aca(h->G, d_tasks.as<AcaTask>(), (int)tasks.size(), n_big, shmem[0], shmem[1], wide, h->fp32_aca,
                    d_rank.as<int32_t>(), d_stop.as<int32_t>(), d_ratio.as<double>(), s),
         "ACA launch");
   check(hipEventRecord(ev.b, s), "event");
@@ -1235,8 +1244,13 @@ void setup_dense(hmat* h, const std::vector<BodyIn>& in, double eta, int32_t lea
     kc[nt + p] = cK;
   }
   upload(h->d_kc, kc, s, "geometry");
+  if (h->fp32_aca) {  // FP32 copies of the centroids and quadrature nodes for the FP32 ACA
+    upload(h->d_cen32, std::vector<float>(hg.cen.begin(), hg.cen.end()), s, "geometry");
+    upload(h->d_q32, std::vector<float>(hg.q.begin(), hg.q.end()), s, "geometry");
+  }
   h->G = DevGeo{h->d_cen.as<double>(), h->d_q.as<double>(), h->d_vtx.as<double>(),
-                h->d_gl.as<double>(), h->d_kc.as<double>(), nt, 0, 0.0, 0.0};
+                h->d_gl.as<double>(), h->d_kc.as<double>(), h->d_cen32.as<float>(), h->d_q32.as<float>(),
+                nt, 0, 0.0, 0.0};
   h->kind_index.assign(P.blk.size(), -1);
   for (size_t b = 0; b < P.blk.size(); b++) {
     if (P.blk[b].far) {
@@ -1282,8 +1296,13 @@ void setup_dense(hmat* h, const std::vector<BodyIn>& in, double eta, int32_t lea
   check(hipEventRecord(evn.b, s), "event");
 }
 
+struct BuildOpts {
+  int precision = 0;         // 1: store the entries in FP32 only
+  double stop_factor = 1.0;  // constant of the ACA stop test
+};
+
 hmat_status build_impl(const std::vector<BodyIn>& in, double eta, int32_t leaf, hipStream_t s,
-                       hmat** out) {
+                       hmat** out, const BuildOpts& opt = BuildOpts{}) {
   auto t0 = std::chrono::steady_clock::now();
   StreamScope scope(s);
   init_pool();
@@ -1296,6 +1315,12 @@ hmat_status build_impl(const std::vector<BodyIn>& in, double eta, int32_t leaf, 
     if (const char* e = std::getenv("HMAT_MV_UNROLL")) h->mv_unroll = std::atoi(e);
     h->eta = eta;
     h->leaf = leaf;
+    h->fp32_only = opt.precision == 1;
+    h->stop_factor = opt.stop_factor;
+    // FP32 arithmetic resolves ACA remainders down to about 1e-6 of a block
+    double eps_min = 1.0;
+    for (const BodyIn& b : in) eps_min = std::min(eps_min, b.eps * opt.stop_factor);
+    h->fp32_aca = h->fp32_only && eps_min >= 1e-5;
     DevBuf near_stage;
     std::vector<int64_t> near_off;
     EventPair evn;
@@ -1328,7 +1353,9 @@ hmat_status build_impl(const std::vector<BodyIn>& in, double eta, int32_t leaf, 
       const int32_t b = h->far_blocks[f];
       return (int32_t)std::min<int64_t>(std::min(block_m(h, b), block_n(h, b)), 4 * (int64_t)capv[f]);
     };
-    std::vector<const double*> panel_ptr(nf, nullptr), u_ptr(nf, nullptr), v_ptr(nf, nullptr);
+    std::vector<const void*> panel_ptr(nf, nullptr);  // in the ACA precision
+    std::vector<const double*> u_ptr(nf, nullptr), v_ptr(nf, nullptr);
+    const int esize = h->fp32_aca ? 4 : 8;  // bytes per panel entry
     // ACA state of every far block (a block that fills its panels is
     // resumed from it in the next pass), zeroed: the first pass starts fresh
     std::vector<int64_t> zoff(nf, 0);
@@ -1356,7 +1383,7 @@ hmat_status build_impl(const std::vector<BodyIn>& in, double eta, int32_t leaf, 
       int64_t bytes = 0;
       while (f1 < nf) {
         const int32_t b = h->far_blocks[f1];
-        const int64_t bb = 8 * (block_m(h, b) + block_n(h, b)) * cap1((int32_t)f1);
+        const int64_t bb = esize * (block_m(h, b) + block_n(h, b)) * cap1((int32_t)f1);
         if (f1 > f0 && bytes + bb > budget) break;
         bytes += bb;
         f1++;
@@ -1367,7 +1394,7 @@ hmat_status build_impl(const std::vector<BodyIn>& in, double eta, int32_t leaf, 
       std::deque<DevBuf> panels_more;  // panels of the later passes (read by the compaction)
       int64_t later_bytes = 0;         // their bytes
       h->piv_bufs.emplace_back();
-      run_aca_pass(h, grp, cap1, [&](size_t b) { return panels1.get(b); }, h->piv_bufs.back(), d_rank,
+      run_aca_pass(h, grp, cap1, [&](size_t b) { return static_cast<void*>(panels1.get(b)); }, h->piv_bufs.back(), d_rank,
                    d_stop, d_ratio, panel_ptr, states, zbits, zoff, [](const std::vector<AcaTask>&) {},
                    false, s);
       h->aca_passes = std::max(h->aca_passes, 1);
@@ -1388,11 +1415,11 @@ hmat_status build_impl(const std::vector<BodyIn>& in, double eta, int32_t leaf, 
         for (int32_t f : grp)
           if (h->stop[f] == 4) again.push_back(f);
         if (again.empty()) break;
-        std::vector<const double*> old_panel(nf, nullptr);
+        std::vector<const char*> old_panel(nf, nullptr);
         std::vector<const int32_t*> old_piv(nf, nullptr);
         std::vector<int32_t> old_cap(nf, 0);
         for (int32_t f : again) {
-          old_panel[f] = panel_ptr[f];
+          old_panel[f] = static_cast<const char*>(panel_ptr[f]);
           old_piv[f] = h->piv_ptr[f];
           old_cap[f] = capv[f];
           capv[f] = cap_next(f);
@@ -1405,9 +1432,10 @@ hmat_status build_impl(const std::vector<BodyIn>& in, double eta, int32_t leaf, 
           };
           for (const AcaTask& t : tasks) {
             const int32_t f = t.blk, kc = old_cap[f];  // stop 4: k == kc columns so far
-            const int64_t m = 3 * (int64_t)t.t_len, n = 3 * (int64_t)t.s_len;
-            span(old_panel[f], t.panel, 2 * m * kc);                               // U
-            span(old_panel[f] + m * kc, t.panel + m * t.kcap, 2 * n * kc);         // V
+            const int64_t m = 3 * (int64_t)t.t_len, n = 3 * (int64_t)t.s_len, w = esize / 4;
+            char* dst = static_cast<char*>(t.panel);
+            span(old_panel[f], dst, w * m * kc);                                            // U
+            span(old_panel[f] + esize * m * kc, dst + esize * m * t.kcap, w * n * kc);      // V
             span(old_piv[f], t.piv, kc);                                           // pivot rows
             span(old_piv[f] + kc, t.piv + t.kcap, kc);                             // pivot columns
           }
@@ -1422,7 +1450,7 @@ hmat_status build_impl(const std::vector<BodyIn>& in, double eta, int32_t leaf, 
           const int64_t avail = std::max<int64_t>(budget - later_bytes, 0);
           while (a1 < again.size()) {
             const int32_t b = h->far_blocks[again[a1]];
-            const int64_t bb = 8 * ((block_m(h, b) + block_n(h, b)) * (int64_t)capv[again[a1]]);
+            const int64_t bb = esize * ((block_m(h, b) + block_n(h, b)) * (int64_t)capv[again[a1]]);
             if (a1 > a0 && bytes + bb > avail) break;
             bytes += bb;
             a1++;
@@ -1434,7 +1462,7 @@ hmat_status build_impl(const std::vector<BodyIn>& in, double eta, int32_t leaf, 
           run_aca_pass(h, sub, [&](int32_t f) { return capv[f]; },
                        [&](size_t b) {
                          if (pb.bytes < b) pb.alloc(b, "ACA panels");
-                         return pb.as<double>();
+                         return pb.p;
                        },
                        h->piv_bufs.back(), d_rank, d_stop, d_ratio, panel_ptr, states, zbits, zoff, carry,
                        true, s);
@@ -1454,12 +1482,12 @@ hmat_status build_impl(const std::vector<BodyIn>& in, double eta, int32_t leaf, 
           const auto& CL = h->plan.cl;
           if (h->rank[f] == std::min(block_m(h, b), block_n(h, b)))
             ex.push_back(ExactTask{CL[B.t].off, CL[B.t].len, CL[B.s].off, CL[B.s].len,
-                                   const_cast<double*>(panel_ptr[f]), capv[f], 0});
+                                   const_cast<void*>(panel_ptr[f]), capv[f], 0});
         }
         if (!ex.empty()) {
           DevBuf d_ex;
           upload(d_ex, ex, s, "exact factors");
-          check(launch_exact(h->G, d_ex.as<ExactTask>(), (int)ex.size(), s), "exact factors");
+          check(launch_exact(h->G, d_ex.as<ExactTask>(), (int)ex.size(), h->fp32_aca, s), "exact factors");
           h->n_exact += (int32_t)ex.size();
         }
       }
@@ -1481,22 +1509,30 @@ hmat_status build_impl(const std::vector<BodyIn>& in, double eta, int32_t leaf, 
       staged_u += (int64_t)us.bytes;
       staged_v += (int64_t)vs.bytes;
       std::vector<CopyTask> ct;
+      std::vector<CopyTask32> ct32;  // FP32 panels, widened to the FP64 staging
       int64_t ou = 0, ov = 0;
       for (int32_t f : grp) {
         const int32_t b = h->far_blocks[f];
         const int32_t m = (int32_t)block_m(h, b), n = (int32_t)block_n(h, b), k = h->rank[f];
         u_ptr[f] = us.as<double>() + ou;
         v_ptr[f] = vs.as<double>() + ov;
-        if (k > 0) {
-          ct.push_back(CopyTask{panel_ptr[f], us.as<double>() + ou, m, k, m, 0});
-          ct.push_back(CopyTask{panel_ptr[f] + (int64_t)m * capv[f], vs.as<double>() + ov, n, k, n, 0});
+        if (k > 0 && h->fp32_aca) {
+          const float* pf = static_cast<const float*>(panel_ptr[f]);
+          ct32.push_back(CopyTask32{pf, us.as<double>() + ou, m, k, m, 0});
+          ct32.push_back(CopyTask32{pf + (int64_t)m * capv[f], vs.as<double>() + ov, n, k, n, 0});
+        } else if (k > 0) {
+          const double* pd = static_cast<const double*>(panel_ptr[f]);
+          ct.push_back(CopyTask{pd, us.as<double>() + ou, m, k, m, 0});
+          ct.push_back(CopyTask{pd + (int64_t)m * capv[f], vs.as<double>() + ov, n, k, n, 0});
         }
         ou += (int64_t)m * k;
         ov += (int64_t)n * k;
       }
-      DevBuf d_ct;
+      DevBuf d_ct, d_ct32;
       upload(d_ct, ct, s, "compaction tasks");
+      upload(d_ct32, ct32, s, "compaction tasks");
       check(launch_compact(d_ct.as<CopyTask>(), (int)ct.size(), s), "compaction launch");
+      check(launch_compact32(d_ct32.as<CopyTask32>(), (int)ct32.size(), s), "compaction launch");
       check(hipStreamSynchronize(s), "compaction");
       h->st.aca_groups++;
       f0 = f1;
@@ -1542,6 +1578,17 @@ hmat_status build_impl(const std::vector<BodyIn>& in, double eta, int32_t leaf, 
     h->st.t_layout_ms = ms_since(t_layout);
     ustage.clear();
     trim_pool_after(staged_u, s);
+    if (h->fp32_only) {  // the FP32 arenas replace the FP64 ones (same layout)
+      const int64_t nfar = (int64_t)(h->far_arena.bytes / sizeof(double));
+      const int64_t nst = (int64_t)(h->stream.bytes / sizeof(double));
+      h->far32.alloc(sizeof(float) * std::max<int64_t>(nfar, 2), "FP32 arenas");
+      h->stream32.alloc(sizeof(float) * std::max<int64_t>(nst, 2), "FP32 arenas");
+      check(launch_to_f32(h->far_arena.as<double>(), h->far32.as<float>(), nfar, s), "FP32 arenas");
+      check(launch_to_f32(h->stream.as<double>(), h->stream32.as<float>(), nst, s), "FP32 arenas");
+      h->far_arena.release();
+      h->stream.release();
+      check(hipStreamSynchronize(s), "FP32 arenas");
+    }
     h->st.t_near_ms = evn.ms();
     h->st.t_aca_ms = eva.ms();
     fill_stats(h);
@@ -1623,9 +1670,17 @@ void copy_v_out(const hmat* h, int32_t f, int64_t n, int64_t k, double* out) {
   if (k == 0) return;
   const PanelShape sh = h->far_vshape[f];
   std::vector<double> tmp((size_t)sh.ld * k);
-  check(hipMemcpy(tmp.data(), h->far_arena.as<double>() + h->far_voff[f], sizeof(double) * tmp.size(),
-                  hipMemcpyDeviceToHost),
-        "block copy");
+  if (h->fp32_only) {
+    std::vector<float> t32(tmp.size());
+    check(hipMemcpy(t32.data(), h->far32.as<float>() + h->far_voff[f], sizeof(float) * t32.size(),
+                    hipMemcpyDeviceToHost),
+          "block copy");
+    std::copy(t32.begin(), t32.end(), tmp.begin());
+  } else {
+    check(hipMemcpy(tmp.data(), h->far_arena.as<double>() + h->far_voff[f], sizeof(double) * tmp.size(),
+                    hipMemcpyDeviceToHost),
+          "block copy");
+  }
   for (int64_t c = 0; c < k; c++) std::memcpy(out + c * n, tmp.data() + c * sh.ld + sh.fp, sizeof(double) * n);
 }
 
@@ -1637,7 +1692,10 @@ void copy_stream_out(const hmat* h, int32_t b, int64_t m, int64_t cols, double* 
   auto tasks = stream_tasks(h, [&](int32_t bb) { return bb == b; }, [&](int32_t) { return tmp.as<double>(); });
   DevBuf d_t;
   upload(d_t, tasks, s, "block copy");
-  check(launch_from_stream(d_t.as<StreamTask>(), (int)tasks.size(), h->stream.as<double>(), s), "block copy");
+  if (h->fp32_only)
+    check(launch_from_stream32(d_t.as<StreamTask>(), (int)tasks.size(), h->stream32.as<float>(), s), "block copy");
+  else
+    check(launch_from_stream(d_t.as<StreamTask>(), (int)tasks.size(), h->stream.as<double>(), s), "block copy");
   check(hipMemcpyAsync(out, tmp.p, sizeof(double) * m * cols, hipMemcpyDeviceToHost, s), "block copy");
   check(hipStreamSynchronize(s), "block copy");
 }
@@ -1826,6 +1884,9 @@ hmat_status gmres_impl(hmat* h, int prec, const GmresWs& ws, const double* b, do
   return status;
 }
 
+// Precision of the stored entries a call uses: FP64 unless only FP32 is stored.
+inline int stored_prec(const hmat* h) { return h->fp32_only ? 1 : 0; }
+
 hmat_status check_solve_args(hmat_t h, const double* b, const double* x, double tol,
                              int32_t restart, int32_t maxit) {
   if (!h) return fail(HMAT_EINVAL, "handle is NULL");
@@ -2008,7 +2069,7 @@ hmat_status amvm_impl(const hmat_mesh* mesh, double E, double nu, double eta, in
                                 }) - tasks.begin());
         DevBuf d_tasks;
         upload(d_tasks, tasks, s, "amvm ACA");
-        check(launch_aca(h->G, d_tasks.as<AcaTask>(), (int)tasks.size(), n_big, shmem[0], shmem[1], true,
+        check(launch_aca(h->G, d_tasks.as<AcaTask>(), (int)tasks.size(), n_big, shmem[0], shmem[1], true, false,
                          d_rank.as<int32_t>(),
                          d_stop.as<int32_t>(), d_ratio.as<double>(), s), "amvm ACA");
         std::vector<int32_t> rk(nf), sp(nf);
@@ -2174,6 +2235,27 @@ hmat_status hmat_build(const hmat_mesh* mesh, double E, double nu, double eta, i
   return build_impl({BodyIn{mesh, E, nu, eps}}, eta, leaf, (hipStream_t)hip_stream, out);
 }
 
+hmat_status hmat_build_ex(const hmat_mesh* mesh, double E, double nu, double eta, int32_t leaf,
+                          double eps, const hmat_opts* opts, void* hip_stream, hmat_t* out) {
+  if (!out) return fail(HMAT_EINVAL, "out is NULL");
+  *out = nullptr;
+  BuildOpts o;
+  if (opts) {
+    if (opts->precision != 0 && opts->precision != 1) return fail(HMAT_EINVAL, "precision must be 0 (FP64) or 1 (FP32)");
+    if (!(opts->aca_stop_factor > 0.0) || !(opts->aca_stop_factor * eps < 1.0))
+      return fail(HMAT_EINVAL, "aca_stop_factor must be > 0 with aca_stop_factor * eps < 1");
+    o.precision = opts->precision;
+    o.stop_factor = opts->aca_stop_factor;
+  }
+  std::string err;
+  hmat_status st = validate_params(E, nu, eta, leaf, eps, err);
+  if (st != HMAT_OK) return fail(st, err);
+  st = validate_mesh(mesh, err);
+  if (st != HMAT_OK) return fail(st, err);
+  g_err.clear();
+  return build_impl({BodyIn{mesh, E, nu, eps}}, eta, leaf, (hipStream_t)hip_stream, out, o);
+}
+
 hmat_status hmat_build_batch(int32_t n_bodies, const hmat_mesh* meshes, const double* E,
                              const double* nu, const double* eps, double eta, int32_t leaf,
                              void* hip_stream, hmat_t* out) {
@@ -2221,6 +2303,7 @@ hmat_status hmat_matvec_graph(hmat_t h, int32_t precision, int32_t nrhs, const d
   if (precision != 0 && precision != 1) return fail(HMAT_EINVAL, "precision must be 0 (FP64) or 1 (FP32)");
   if (precision == 1 && !h->far32.p && !h->stream32.p)
     return fail(HMAT_EINVAL, "no FP32 copy: call hmat_set_precision(h, 1, ...) first");
+  if (precision == 0 && h->fp32_only) return fail(HMAT_ENOTSUP, "the handle stores FP32 entries only");
   if (!x || !y) return fail(HMAT_EINVAL, "x or y is NULL");
   if (nrhs < 1 || nrhs > 64) return fail(HMAT_EINVAL, "nrhs must lie in [1, 64]");
   if (ldx < h->N || ldy < h->N) return fail(HMAT_EINVAL, "ldx and ldy must be >= n_dof");
@@ -2305,10 +2388,10 @@ hmat_status hmat_tune(hmat_t h, int32_t nrhs, int32_t reps, void* hip_stream, hm
     for (size_t c = 0; c < cand.size(); c++) {
       set_chunk_list(h, l, (int64_t)cand[c].first * 1024, s);
       h->mv_unroll = cand[c].second;
-      matvec_impl(h, 0, nrhs, dx.as<double>(), h->N, dy.as<double>(), h->N, s);  // warm-up
+      matvec_impl(h, stored_prec(h), nrhs, dx.as<double>(), h->N, dy.as<double>(), h->N, s);  // warm-up
       check(hipEventRecord(ev.a, s), "tune");
       for (int r = 0; r < reps; r++)
-        matvec_impl(h, 0, nrhs, dx.as<double>(), h->N, dy.as<double>(), h->N, s);
+        matvec_impl(h, stored_prec(h), nrhs, dx.as<double>(), h->N, dy.as<double>(), h->N, s);
       check(hipEventRecord(ev.b, s), "tune");
       check(hipEventSynchronize(ev.b), "tune");
       ms[c] = ev.ms() / reps;
@@ -2366,7 +2449,7 @@ hmat_status hmat_matvec(hmat_t h, int32_t nrhs, const double* x, int64_t ldx, do
   StreamScope scope((hipStream_t)hip_stream);
   h->last_stream = (hipStream_t)hip_stream;
   try {
-    matvec_impl(h, 0, nrhs, x, ldx, y, ldy, (hipStream_t)hip_stream);
+    matvec_impl(h, stored_prec(h), nrhs, x, ldx, y, ldy, (hipStream_t)hip_stream);
   } catch (const HipError& e) {
     return fail(e.st, e.msg);
   }
@@ -2385,7 +2468,7 @@ hmat_status hmat_solve(hmat_t h, const double* b, double* x, double tol, int32_t
     int used = 0, restarts = 0;
     double rel = 0.0;
     const GmresWs ws = ensure_gmres_ws(h, restart);
-    st = gmres_impl(h, 0, ws, b, x, tol, restart, maxit, s, &used, &restarts, &rel);
+    st = gmres_impl(h, stored_prec(h), ws, b, x, tol, restart, maxit, s, &used, &restarts, &rel);
     if (info) {
       info->iterations = used;
       info->restarts = restarts;
@@ -2429,7 +2512,7 @@ hmat_status hmat_solve_noalloc(hmat_t h, const double* b, double* x, double tol,
     ws.host = host.data();
     int used = 0, restarts = 0;
     double rel = 0.0;
-    st = gmres_impl(h, 0, ws, b, x, tol, restart, maxit, s, &used, &restarts, &rel);
+    st = gmres_impl(h, stored_prec(h), ws, b, x, tol, restart, maxit, s, &used, &restarts, &rel);
     if (info) {
       info->iterations = used;
       info->restarts = restarts;
@@ -2453,6 +2536,7 @@ hmat_status hmat_solve_ir(hmat_t h, const double* b, double* x, double tol, int3
   if (inner_precision != 0 && inner_precision != 1) return fail(HMAT_EINVAL, "inner_precision must be 0 or 1");
   if (inner_precision == 1 && !h->far32.p && !h->stream32.p)
     return fail(HMAT_EINVAL, "no FP32 copy: call hmat_set_precision(h, 1, ...) first");
+  if (inner_precision == 0 && h->fp32_only) return fail(HMAT_ENOTSUP, "the handle stores FP32 entries only");
   if (!(inner_tol > 0.0 && inner_tol < 1.0)) return fail(HMAT_EINVAL, "inner_tol must lie in (0, 1)");
   hipStream_t s = (hipStream_t)hip_stream;
   StreamScope scope(s);
@@ -2483,7 +2567,7 @@ hmat_status hmat_solve_ir(hmat_t h, const double* b, double* x, double tol, int3
       // relative residual max(inner_tol, tol ||b|| / (2 ||r_k||)); the
       // residual r_k = b - A x_k uses the FP64 matrix.
       for (;;) {
-        matvec_impl(h, 0, 1, x, N, r, N, s);
+        matvec_impl(h, stored_prec(h), 1, x, N, r, N, s);
         check(launch_residual(b, N, r, s), "residual");
         const double rn = norm_host(r);
         rel = rn / bn;
@@ -2521,6 +2605,10 @@ hmat_status hmat_solve_ir(hmat_t h, const double* b, double* x, double tol, int3
 hmat_status hmat_set_precision(hmat_t h, int32_t precision, void* hip_stream) {
   if (!h) return fail(HMAT_EINVAL, "handle is NULL");
   if (precision != 0 && precision != 1) return fail(HMAT_EINVAL, "precision must be 0 (FP64) or 1 (FP32)");
+  if (h->fp32_only) {
+    if (precision == 1) return HMAT_OK;  // already so
+    return fail(HMAT_ENOTSUP, "the handle stores FP32 entries only");
+  }
   hipStream_t s = (hipStream_t)hip_stream;
   StreamScope scope(s);
   h->last_stream = s;
@@ -2552,6 +2640,7 @@ hmat_status hmat_matvec_ex(hmat_t h, int32_t precision, int32_t nrhs, const doub
   if (precision != 0 && precision != 1) return fail(HMAT_EINVAL, "precision must be 0 (FP64) or 1 (FP32)");
   if (precision == 1 && !h->far32.p && !h->stream32.p)
     return fail(HMAT_EINVAL, "no FP32 copy: call hmat_set_precision(h, 1, ...) first");
+  if (precision == 0 && h->fp32_only) return fail(HMAT_ENOTSUP, "the handle stores FP32 entries only");
   if (!x || !y) return fail(HMAT_EINVAL, "x or y is NULL");
   if (nrhs < 1 || nrhs > 64) return fail(HMAT_EINVAL, "nrhs must lie in [1, 64]");
   if (ldx < h->N || ldy < h->N) return fail(HMAT_EINVAL, "ldx and ldy must be >= n_dof");
@@ -2720,6 +2809,7 @@ hmat_status hmat_entries(hmat_t h, int64_t n, const int64_t* rows, const int64_t
 hmat_status hmat_set_factors(hmat_t h, const int32_t* ranks, const double* U, const double* V,
                              void* hip_stream) {
   if (!h || !ranks) return fail(HMAT_EINVAL, "handle or ranks is NULL");
+  if (h->fp32_only) return fail(HMAT_ENOTSUP, "the handle stores FP32 entries only");
   hipStream_t s = (hipStream_t)hip_stream;
   StreamScope scope(s);
   h->last_stream = s;

@@ -24,6 +24,8 @@ struct DevGeo {
   const double* vtx;  // [9][nt]: p0x p0y p0z p1x ... p2z
   const double* gl;   // [2][16] Gauss-Legendre nodes and weights on [0,1]
   const double* kc;   // [2][nt]: c1, c2 of the triangle's body
+  const float* cen32; // FP32 copies of cen and q (FP32 ACA only; else null)
+  const float* q32;
   int32_t nt;
   int32_t pad;
   double c1, c2;
@@ -55,14 +57,15 @@ constexpr int ACA_STAGE_MAX = 7936;
 // partial sums and Hessenberg columns).
 constexpr size_t NOALLOC_DOUBLES = size_t(4) << 20;
 // Dynamic LDS (bytes) of the ACA kernel for one block and a workgroup of
-// nwv waves: the coefficient row and the cross-term weights (kcap doubles
-// each), the per-wave partial sums of V^T v_c (kcap * nwv doubles), the row
-// set Z (m bits, in 32-bit words, padded to a double) and, if staged, the
-// newest row and column (n + m doubles).
-inline size_t aca_shmem(int kcap, int64_t m, int64_t n, int nwv) {
+// nwv waves, panel entries of esize bytes: the cross-term weights (kcap
+// doubles), the per-wave partial sums of V^T v_c (kcap * nwv doubles), the
+// coefficient row (kcap entries, padded to a double), the row set Z (m bits,
+// in 32-bit words, padded to a double) and, if staged, the newest row and
+// column (n + m entries).
+inline size_t aca_shmem(int kcap, int64_t m, int64_t n, int nwv, int esize = 8) {
   const size_t zw = (size_t)((m + 31) / 32);
-  return 8 * (size_t)kcap * (2 + nwv) + 8 * ((zw + 1) / 2) +
-         (m + n <= ACA_STAGE_MAX ? 8 * (size_t)(m + n) : 0);
+  return 8 * (size_t)kcap * (1 + nwv) + 8 * (((size_t)kcap * esize + 7) / 8) + 8 * ((zw + 1) / 2) +
+         (m + n <= ACA_STAGE_MAX ? (size_t)esize * (size_t)(m + n) : 0);
 }
 
 // Dense (non-admissible) block at d_off in the near arena (m = 3 t_len rows).
@@ -92,7 +95,7 @@ struct AcaState {
 
 struct AcaTask {
   int32_t t_off, t_len, s_off, s_len;
-  double* panel;
+  void* panel;    // U (m x kcap) then V (n x kcap), column-major, in the ACA precision
   int32_t* piv;   // [2][kcap]: pivot rows, pivot columns
   int32_t kcap;
   int32_t blk;    // index into the far-block result arrays
@@ -132,7 +135,7 @@ struct SpanCopy {
 // kcap, V n x kcap): U = B, V = I for n <= m, else U = I, V = B^T.
 struct ExactTask {
   int32_t t_off, t_len, s_off, s_len;
-  double* panel;
+  void* panel;
   int32_t kcap, pad;
 };
 
@@ -141,6 +144,13 @@ struct ExactTask {
 struct CopyTask {
   const double* srcV;
   double* dstV;  // column c, row i at dstV[c*ldv + fpv + i]
+  int32_t n, k, ldv, fpv;
+};
+
+// The same from an FP32 panel into an FP64 staging buffer (FP32 ACA).
+struct CopyTask32 {
+  const float* srcV;
+  double* dstV;
   int32_t n, k, ldv, fpv;
 };
 

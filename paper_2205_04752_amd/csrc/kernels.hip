@@ -254,18 +254,33 @@ __device__ __forceinline__ void blk_sum3(double& a, double& b, double& c, RedT<N
 
 __device__ __forceinline__ bool in_z(const uint32_t* Z, int r) { return (Z[r >> 5] >> (r & 31)) & 1u; }
 
-// Fuzzy argmax over rows not in Z: lowest r with |u_r| >= (1 - 1e-10) max.
-template <int TPB>
-__device__ int argmax_free(const double* __restrict__ u, int m, const uint32_t* Z,
+// ACA in the precision P of its panels, entries and remainders (FP64, or
+// FP32 for FP32 builds); the norm update is FP64 either way. FUZZ: the
+// relative width of an argmax tie (well above P's rounding); VANISH: a row
+// remainder vanishes at max|v~| <= VANISH ||S_k||_F.
+template <typename P>
+struct AcaPrec;
+template <>
+struct AcaPrec<double> {
+  static constexpr double FUZZ = 1e-10, VANISH = 1e-14;
+};
+template <>
+struct AcaPrec<float> {
+  static constexpr double FUZZ = 1e-6, VANISH = 1e-9;
+};
+
+// Fuzzy argmax over rows not in Z: lowest r with |u_r| >= (1 - FUZZ) max.
+template <int TPB, typename P>
+__device__ int argmax_free(const P* __restrict__ u, int m, const uint32_t* Z,
                            RedT<TPB / WAVE>& R, int& ph) {
   double mx = -1.0;
   for (int r = threadIdx.x; r < m; r += TPB)
-    if (!in_z(Z, r)) mx = fmax(mx, fabs(u[r]));
+    if (!in_z(Z, r)) mx = fmax(mx, (double)fabs(u[r]));
   mx = blk_max(mx, R, ph);
-  const double thr = (1.0 - 1e-10) * mx;
+  const double thr = (1.0 - AcaPrec<P>::FUZZ) * mx;
   int cand = INT_MAX;
   for (int r = threadIdx.x; r < m; r += TPB)
-    if (!in_z(Z, r) && fabs(u[r]) >= thr) {
+    if (!in_z(Z, r) && (double)fabs(u[r]) >= thr) {
       cand = r;
       break;
     }
@@ -299,8 +314,8 @@ __device__ int class_probe(const uint32_t* Z, int m, int visited, RedT<TPB / WAV
 // all rows; the lowest of them if no cross qualifies. u_{k-1} is read from
 // `ulast` (its LDS copy, or the panel), older crosses from the panel U.
 // Returns -1 when Z holds every row.
-template <int TPB>
-__device__ int cycle_next(const double* U, const double* ulast, int k, int m, const uint32_t* Z,
+template <int TPB, typename P>
+__device__ int cycle_next(const P* U, const P* ulast, int k, int m, const uint32_t* Z,
                           int i, RedT<TPB / WAVE>& R, int& ph) {
   const int tid = threadIdx.x;
   for (int dc = 1; dc <= 3; dc++) {
@@ -314,20 +329,20 @@ __device__ int cycle_next(const double* U, const double* ulast, int k, int m, co
     const int lowest = blk_min(cand, R, ph);
     if (lowest >= m) continue;
     for (int l = k - 1; l >= 0; l--) {
-      const double* __restrict__ u = (l == k - 1) ? ulast : U + (size_t)l * m;
+      const P* __restrict__ u = (l == k - 1) ? ulast : U + (size_t)l * m;
       double all = 0.0, cls = 0.0;
       for (int r = tid; r < m; r += TPB) {
-        const double a = fabs(u[r]);
+        const double a = fabs((double)u[r]);
         all = fmax(all, a);
         if (r % 3 == c && !in_z(Z, r)) cls = fmax(cls, a);
       }
       all = blk_max(all, R, ph);
       cls = blk_max(cls, R, ph);
       if (!(cls > 1e-12 * all)) continue;
-      const double thr = (1.0 - 1e-10) * cls;
+      const double thr = (1.0 - AcaPrec<P>::FUZZ) * cls;
       cand = INT_MAX;
       for (int r = c + 3 * tid; r < m; r += 3 * TPB)
-        if (!in_z(Z, r) && fabs(u[r]) >= thr) {
+        if (!in_z(Z, r) && fabs((double)u[r]) >= thr) {
           cand = r;
           break;
         }
@@ -341,17 +356,18 @@ __device__ int cycle_next(const double* U, const double* ulast, int k, int m, co
 // e_b -= sum_{l<k} coef[l] * P[l*ld + b] for b = 0..2 (one triangle's three
 // rows or columns of a panel); four columns per step with separate sums, so
 // twelve loads are in flight.
-__device__ __forceinline__ void sub_panel3(const double* __restrict__ coef, const double* P,
-                                           int k, int ld, double& e0, double& e1, double& e2) {
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0, b0 = 0.0, b1 = 0.0, b2 = 0.0;
-  double c0 = 0.0, c1 = 0.0, c2 = 0.0, d0 = 0.0, d1 = 0.0, d2 = 0.0;
+template <typename E>
+__device__ __forceinline__ void sub_panel3(const E* __restrict__ coef, const E* P,
+                                           int k, int ld, E& e0, E& e1, E& e2) {
+  E a0 = 0, a1 = 0, a2 = 0, b0 = 0, b1 = 0, b2 = 0;
+  E c0 = 0, c1 = 0, c2 = 0, d0 = 0, d1 = 0, d2 = 0;
   int l = 0;
   for (; l + 3 < k; l += 4) {
-    const double* p0 = P + (size_t)l * ld;
-    const double* p1 = p0 + ld;
-    const double* p2 = p1 + ld;
-    const double* p3 = p2 + ld;
-    const double w0 = coef[l], w1 = coef[l + 1], w2 = coef[l + 2], w3 = coef[l + 3];
+    const E* p0 = P + (size_t)l * ld;
+    const E* p1 = p0 + ld;
+    const E* p2 = p1 + ld;
+    const E* p3 = p2 + ld;
+    const E w0 = coef[l], w1 = coef[l + 1], w2 = coef[l + 2], w3 = coef[l + 3];
     a0 += w0 * p0[0];
     a1 += w0 * p0[1];
     a2 += w0 * p0[2];
@@ -366,8 +382,8 @@ __device__ __forceinline__ void sub_panel3(const double* __restrict__ coef, cons
     d2 += w3 * p3[2];
   }
   for (; l < k; l++) {
-    const double* p0 = P + (size_t)l * ld;
-    const double w0 = coef[l];
+    const E* p0 = P + (size_t)l * ld;
+    const E w0 = coef[l];
     a0 += w0 * p0[0];
     a1 += w0 * p0[1];
     a2 += w0 * p0[2];
@@ -378,25 +394,26 @@ __device__ __forceinline__ void sub_panel3(const double* __restrict__ coef, cons
 }
 
 // As sub_panel3 (same loads, same partial sums for e_b), and also
-// t_b = sum_{l<k} w[l] * P[l*ld + b] from the same loads.
-__device__ __forceinline__ void sub_panel3w(const double* __restrict__ coef,
-                                            const double* __restrict__ w, const double* P, int k,
-                                            int ld, double& e0, double& e1, double& e2, double& t0,
+// t_b = sum_{l<k} w[l] * P[l*ld + b] from the same loads (in FP64).
+template <typename E>
+__device__ __forceinline__ void sub_panel3w(const E* __restrict__ coef,
+                                            const double* __restrict__ w, const E* P, int k,
+                                            int ld, E& e0, E& e1, E& e2, double& t0,
                                             double& t1, double& t2) {
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0, b0 = 0.0, b1 = 0.0, b2 = 0.0;
-  double c0 = 0.0, c1 = 0.0, c2 = 0.0, d0 = 0.0, d1 = 0.0, d2 = 0.0;
+  E a0 = 0, a1 = 0, a2 = 0, b0 = 0, b1 = 0, b2 = 0;
+  E c0 = 0, c1 = 0, c2 = 0, d0 = 0, d1 = 0, d2 = 0;
   double f0 = 0.0, f1 = 0.0, f2 = 0.0, h0 = 0.0, h1 = 0.0, h2 = 0.0;
   int l = 0;
   for (; l + 3 < k; l += 4) {
-    const double* p0 = P + (size_t)l * ld;
-    const double* p1 = p0 + ld;
-    const double* p2 = p1 + ld;
-    const double* p3 = p2 + ld;
-    const double x00 = p0[0], x01 = p0[1], x02 = p0[2];
-    const double x10 = p1[0], x11 = p1[1], x12 = p1[2];
-    const double x20 = p2[0], x21 = p2[1], x22 = p2[2];
-    const double x30 = p3[0], x31 = p3[1], x32 = p3[2];
-    const double w0 = coef[l], w1 = coef[l + 1], w2 = coef[l + 2], w3 = coef[l + 3];
+    const E* p0 = P + (size_t)l * ld;
+    const E* p1 = p0 + ld;
+    const E* p2 = p1 + ld;
+    const E* p3 = p2 + ld;
+    const E x00 = p0[0], x01 = p0[1], x02 = p0[2];
+    const E x10 = p1[0], x11 = p1[1], x12 = p1[2];
+    const E x20 = p2[0], x21 = p2[1], x22 = p2[2];
+    const E x30 = p3[0], x31 = p3[1], x32 = p3[2];
+    const E w0 = coef[l], w1 = coef[l + 1], w2 = coef[l + 2], w3 = coef[l + 3];
     const double z0 = w[l], z1 = w[l + 1], z2 = w[l + 2], z3 = w[l + 3];
     a0 += w0 * x00;
     a1 += w0 * x01;
@@ -410,23 +427,24 @@ __device__ __forceinline__ void sub_panel3w(const double* __restrict__ coef,
     d0 += w3 * x30;
     d1 += w3 * x31;
     d2 += w3 * x32;
-    f0 += z0 * x00 + z2 * x20;
-    f1 += z0 * x01 + z2 * x21;
-    f2 += z0 * x02 + z2 * x22;
-    h0 += z1 * x10 + z3 * x30;
-    h1 += z1 * x11 + z3 * x31;
-    h2 += z1 * x12 + z3 * x32;
+    f0 += z0 * (double)x00 + z2 * (double)x20;
+    f1 += z0 * (double)x01 + z2 * (double)x21;
+    f2 += z0 * (double)x02 + z2 * (double)x22;
+    h0 += z1 * (double)x10 + z3 * (double)x30;
+    h1 += z1 * (double)x11 + z3 * (double)x31;
+    h2 += z1 * (double)x12 + z3 * (double)x32;
   }
   for (; l < k; l++) {
-    const double* p0 = P + (size_t)l * ld;
-    const double w0 = coef[l], z0 = w[l];
-    const double x00 = p0[0], x01 = p0[1], x02 = p0[2];
+    const E* p0 = P + (size_t)l * ld;
+    const E w0 = coef[l];
+    const double z0 = w[l];
+    const E x00 = p0[0], x01 = p0[1], x02 = p0[2];
     a0 += w0 * x00;
     a1 += w0 * x01;
     a2 += w0 * x02;
-    f0 += z0 * x00;
-    f1 += z0 * x01;
-    f2 += z0 * x02;
+    f0 += z0 * (double)x00;
+    f1 += z0 * (double)x01;
+    f2 += z0 * (double)x02;
   }
   e0 -= (a0 + b0) + (c0 + d0);
   e1 -= (a1 + b1) + (c1 + d1);
@@ -445,31 +463,32 @@ __device__ __forceinline__ void sub_panel3w(const double* __restrict__ coef,
 // butterfly within 16 lanes): 7 exchanges instead of 4 x 6. Every lane of
 // the wave calls it; an inactive lane (act = false) passes a valid P and
 // contributes nothing. Columns past k are masked (addresses clamped).
-template <int NWV>
-__device__ __forceinline__ void sub_panel3_pend(const double* __restrict__ coef, const double* P, int k,
-                                                int ld, bool act, double& e0, double& e1, double& e2,
+template <int NWV, typename E>
+__device__ __forceinline__ void sub_panel3_pend(const E* __restrict__ coef, const E* P, int k,
+                                                int ld, bool act, E& e0, E& e1, E& e2,
                                                 double* pw, int lane) {
   const int c = k - 1;
-  const double* pc = P + (size_t)c * ld;
-  const double y0 = act ? pc[0] : 0.0, y1 = act ? pc[1] : 0.0, y2 = act ? pc[2] : 0.0;
+  const E* pc = P + (size_t)c * ld;
+  const double y0 = act ? (double)pc[0] : 0.0, y1 = act ? (double)pc[1] : 0.0,
+               y2 = act ? (double)pc[2] : 0.0;
   // the subtraction keeps sub_panel3's partial sums (four columns in four
   // sums, the tail column by column into the first), so v~ has its bits
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0, b0 = 0.0, b1 = 0.0, b2 = 0.0;
-  double c0 = 0.0, c1 = 0.0, c2 = 0.0, d0 = 0.0, d1 = 0.0, d2 = 0.0;
+  E a0 = 0, a1 = 0, a2 = 0, b0 = 0, b1 = 0, b2 = 0;
+  E c0 = 0, c1 = 0, c2 = 0, d0 = 0, d1 = 0, d2 = 0;
   const bool hi32 = lane & 32, hi16 = lane & 16;
   const int mine = 2 * (lane >> 5) + ((lane >> 4) & 1);  // column (of the four) this lane's sum ends in
   for (int l = 0; l < k; l += 4) {
     const bool h1 = l + 1 < k, h2 = l + 2 < k, h3 = l + 3 < k;
-    const double* p0 = P + (size_t)l * ld;
-    const double* p1 = P + (size_t)min(l + 1, c) * ld;
-    const double* p2 = P + (size_t)min(l + 2, c) * ld;
-    const double* p3 = P + (size_t)min(l + 3, c) * ld;
-    const double x00 = p0[0], x01 = p0[1], x02 = p0[2];
-    const double x10 = h1 ? p1[0] : 0.0, x11 = h1 ? p1[1] : 0.0, x12 = h1 ? p1[2] : 0.0;
-    const double x20 = h2 ? p2[0] : 0.0, x21 = h2 ? p2[1] : 0.0, x22 = h2 ? p2[2] : 0.0;
-    const double x30 = h3 ? p3[0] : 0.0, x31 = h3 ? p3[1] : 0.0, x32 = h3 ? p3[2] : 0.0;
+    const E* p0 = P + (size_t)l * ld;
+    const E* p1 = P + (size_t)min(l + 1, c) * ld;
+    const E* p2 = P + (size_t)min(l + 2, c) * ld;
+    const E* p3 = P + (size_t)min(l + 3, c) * ld;
+    const E x00 = p0[0], x01 = p0[1], x02 = p0[2];
+    const E x10 = h1 ? p1[0] : E(0), x11 = h1 ? p1[1] : E(0), x12 = h1 ? p1[2] : E(0);
+    const E x20 = h2 ? p2[0] : E(0), x21 = h2 ? p2[1] : E(0), x22 = h2 ? p2[2] : E(0);
+    const E x30 = h3 ? p3[0] : E(0), x31 = h3 ? p3[1] : E(0), x32 = h3 ? p3[2] : E(0);
     if (h3) {
-      const double w0 = coef[l], w1 = coef[l + 1], w2 = coef[l + 2], w3 = coef[l + 3];
+      const E w0 = coef[l], w1 = coef[l + 1], w2 = coef[l + 2], w3 = coef[l + 3];
       a0 += w0 * x00;
       a1 += w0 * x01;
       a2 += w0 * x02;
@@ -483,27 +502,27 @@ __device__ __forceinline__ void sub_panel3_pend(const double* __restrict__ coef,
       d1 += w3 * x31;
       d2 += w3 * x32;
     } else {  // the last one to three columns, one after another into the first sums
-      const double w0 = coef[l];
+      const E w0 = coef[l];
       a0 += w0 * x00;
       a1 += w0 * x01;
       a2 += w0 * x02;
       if (h1) {
-        const double w1 = coef[l + 1];
+        const E w1 = coef[l + 1];
         a0 += w1 * x10;
         a1 += w1 * x11;
         a2 += w1 * x12;
       }
       if (h2) {
-        const double w2 = coef[l + 2];
+        const E w2 = coef[l + 2];
         a0 += w2 * x20;
         a1 += w2 * x21;
         a2 += w2 * x22;
       }
     }
-    const double s0 = l < c ? x00 * y0 + x01 * y1 + x02 * y2 : 0.0;
-    const double s1 = l + 1 < c ? x10 * y0 + x11 * y1 + x12 * y2 : 0.0;
-    const double s2 = l + 2 < c ? x20 * y0 + x21 * y1 + x22 * y2 : 0.0;
-    const double s3 = l + 3 < c ? x30 * y0 + x31 * y1 + x32 * y2 : 0.0;
+    const double s0 = l < c ? (double)x00 * y0 + (double)x01 * y1 + (double)x02 * y2 : 0.0;
+    const double s1 = l + 1 < c ? (double)x10 * y0 + (double)x11 * y1 + (double)x12 * y2 : 0.0;
+    const double s2 = l + 2 < c ? (double)x20 * y0 + (double)x21 * y1 + (double)x22 * y2 : 0.0;
+    const double s3 = l + 3 < c ? (double)x30 * y0 + (double)x31 * y1 + (double)x32 * y2 : 0.0;
     // lanes 0-31 keep columns 0, 1 and lanes 32-63 columns 2, 3
     double ka = hi32 ? s2 : s0, kb = hi32 ? s3 : s1;
     ka += __shfl_xor(hi32 ? s0 : s2, 32, WAVE);
@@ -525,16 +544,16 @@ __device__ __forceinline__ void sub_panel3_pend(const double* __restrict__ coef,
 // The pending cross term on its own, where no next step carries it (the
 // block ends, or the next row is exactly zero): w_l = V[:, l] . V[:, c] for
 // l < c (one wave per column, into wl), then sum_r U[r, c] (U[r, 0:c] w).
-template <int TPB>
-__device__ double pending_cross(const double* U, const double* V, int m, int n, int c, double* wl,
+template <int TPB, typename E>
+__device__ double pending_cross(const E* U, const E* V, int m, int n, int c, double* wl,
                                 RedT<TPB / WAVE>& R, int& ph) {
   constexpr int NWV = TPB / WAVE;
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
-  const double* vc = V + (size_t)c * n;
+  const E* vc = V + (size_t)c * n;
   for (int l = wv; l < c; l += NWV) {
-    const double* vl = V + (size_t)l * n;
+    const E* vl = V + (size_t)l * n;
     double a = 0.0;
-    for (int r = lane; r < n; r += WAVE) a += vl[r] * vc[r];
+    for (int r = lane; r < n; r += WAVE) a += (double)vl[r] * (double)vc[r];
     a = wave_sum(a);
     if (lane == 0) wl[l] = a;
   }
@@ -542,12 +561,62 @@ __device__ double pending_cross(const double* U, const double* V, int m, int n, 
   double x = 0.0, d1 = 0.0, d2 = 0.0;
   for (int r = tid; r < m; r += TPB) {
     double t = 0.0;
-    for (int l = 0; l < c; l++) t += U[r + (size_t)l * m] * wl[l];
-    x += U[r + (size_t)c * m] * t;
+    for (int l = 0; l < c; l++) t += (double)U[r + (size_t)l * m] * wl[l];
+    x += (double)U[r + (size_t)c * m] * t;
   }
   blk_sum3(x, d1, d2, R, ph);
   return x;
 }
+
+// The FP32 form of row3 (FP32 geometry copies, FP32 arithmetic): entries of
+// admissible blocks in FP32 builds, where |r| >= dist(X_t, X_s) > 0.
+__device__ __forceinline__ void row3f(const DevGeo& g, float x0, float x1, float x2, int a, int q,
+                                      float& e0, float& e1, float& e2) {
+  const int nt = g.nt;
+  e0 = e1 = e2 = 0.0f;
+  float diag = 0.0f;
+#pragma unroll
+  for (int k = 0; k < 7; k++) {
+    const float r0 = x0 - g.q32[(0 * 7 + k) * (size_t)nt + q];
+    const float r1 = x1 - g.q32[(1 * 7 + k) * (size_t)nt + q];
+    const float r2 = x2 - g.q32[(2 * 7 + k) * (size_t)nt + q];
+    const float w = g.q32[(3 * 7 + k) * (size_t)nt + q];
+    const float inv = 1.0f / sqrtf(r0 * r0 + r1 * r1 + r2 * r2);
+    const float ra = (a == 0) ? r0 : ((a == 1) ? r1 : r2);
+    const float t = w * inv * inv * inv * ra;
+    e0 += t * r0;
+    e1 += t * r1;
+    e2 += t * r2;
+    diag += w * inv;
+  }
+  const float c2 = (float)g.c2;
+  e0 *= c2;
+  e1 *= c2;
+  e2 *= c2;
+  const float dd = (float)g.c1 * diag;
+  if (a == 0) e0 += dd; else if (a == 1) e1 += dd; else e2 += dd;
+}
+
+// Three entries of row 3p+a, columns 3q..3q+2 (p, q cluster positions), in
+// the ACA precision P.
+template <typename P>
+struct Ent;
+template <>
+struct Ent<double> {
+  static __device__ __forceinline__ void row(const DevGeo& g, int p, int a, int q, double& e0, double& e1,
+                                             double& e2) {
+    const int nt = g.nt;
+    row3(g, g.cen[p], g.cen[nt + p], g.cen[2 * nt + p], a, q, e0, e1, e2);
+  }
+};
+template <>
+struct Ent<float> {
+  static __device__ __forceinline__ void row(const DevGeo& g, int p, int a, int q, float& e0, float& e1,
+                                             float& e2) {
+    const int nt = g.nt;
+    row3f(g, g.cen32[p], g.cen32[nt + p], g.cen32[2 * nt + p], a, q, e0, e1, e2);
+  }
+};
 
 // K2: ACA (Algorithm 1) on the DOF block of task blockIdx.x.
 //   rows i_{k+1}: fuzzy argmax over rows not in Z of |u_k| (i_1 = 0);
@@ -582,7 +651,7 @@ __device__ double pending_cross(const double* U, const double* V, int m, int n, 
 // exactly zero, the term is computed on its own (pending_cross). The
 // decisions and crosses are those of the plain order; only the rounding of
 // ||S_k|| differs.
-template <int TPB>
+template <int TPB, typename P>
 __global__ __launch_bounds__(TPB) void k_aca(DevGeo g0, const AcaTask* __restrict__ tasks,
                                                int32_t* __restrict__ rank_out,
                                                int32_t* __restrict__ stop_out,
@@ -595,16 +664,17 @@ __global__ __launch_bounds__(TPB) void k_aca(DevGeo g0, const AcaTask* __restric
   const double eps = T.eps;
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
   const int m = 3 * T.t_len, n = 3 * T.s_len, kmax = min(m, n), kcap = T.kcap;
-  double* __restrict__ U = T.panel;
-  double* __restrict__ V = T.panel + (size_t)m * kcap;
-  double* coef = sh;
-  double* const wl = sh + kcap;      // weights w_l of the pending cross term
-  double* const pw = sh + 2 * kcap;  // per wave: partial sums of V[:, l] . V[:, c]
-  uint32_t* Z = reinterpret_cast<uint32_t*>(sh + (2 + NWV) * kcap);
+  P* __restrict__ U = static_cast<P*>(T.panel);
+  P* __restrict__ V = U + (size_t)m * kcap;
+  double* const wl = sh;             // weights w_l of the pending cross term
+  double* const pw = sh + kcap;      // per wave: partial sums of V[:, l] . V[:, c]
+  P* const coef = reinterpret_cast<P*>(sh + (1 + NWV) * kcap);
+  const int cw = (kcap * (int)sizeof(P) + 7) / 8;  // coef in doubles
+  uint32_t* Z = reinterpret_cast<uint32_t*>(sh + (1 + NWV) * kcap + cw);
   const int zw = (m + 31) >> 5;
   const bool stage = m + n <= ACA_STAGE_MAX;
-  double* const vs = sh + (2 + NWV) * kcap + ((zw + 1) >> 1);  // staged v_k (n), then u_k (m)
-  double* const us = vs + n;
+  P* const vs = reinterpret_cast<P*>(sh + (1 + NWV) * kcap + cw + ((zw + 1) >> 1));  // staged v_k (n), then u_k (m)
+  P* const us = vs + n;
   const int nt = g.nt;
   int ph = 0, k = 0, nZ = 0, i = 0, stop = 0, visited = 0, pending = 0;
   int pc = 0;                 // 1: the test of cross k - 1 is not settled yet
@@ -645,18 +715,17 @@ __global__ __launch_bounds__(TPB) void k_aca(DevGeo g0, const AcaTask* __restric
     visited |= 1 << (i % 3);
     __syncthreads();
     // row i of the remainder into V[:, k]
-    double* __restrict__ vk = V + (size_t)k * n;
-    double* const vr = stage ? vs : vk;  // where this step reads v_k
+    P* __restrict__ vk = V + (size_t)k * n;
+    P* const vr = stage ? vs : vk;  // where this step reads v_k
     const int pi = T.t_off + i / 3, ai = i % 3;
-    const double x0 = g.cen[pi], x1 = g.cen[nt + pi], x2 = g.cen[2 * nt + pi];
     double mx = 0.0;
     if (pc) {
       // wave-uniform trip count: the dot products are summed over the wave
       for (int q0 = wv * WAVE; q0 < T.s_len; q0 += TPB) {
         const int q = q0 + lane;
         const bool act = q < T.s_len;
-        double e0 = 0.0, e1 = 0.0, e2 = 0.0;
-        if (act) row3(g, x0, x1, x2, ai, T.s_off + q, e0, e1, e2);
+        P e0 = 0, e1 = 0, e2 = 0;
+        if (act) Ent<P>::row(g, pi, ai, T.s_off + q, e0, e1, e2);
         sub_panel3_pend<NWV>(coef, V + 3 * (act ? q : 0), k, n, act, e0, e1, e2, pw + wv, lane);
         if (act) {
           vk[3 * q] = e0;
@@ -667,13 +736,13 @@ __global__ __launch_bounds__(TPB) void k_aca(DevGeo g0, const AcaTask* __restric
             vs[3 * q + 1] = e1;
             vs[3 * q + 2] = e2;
           }
-          mx = fmax(mx, fmax(fabs(e0), fmax(fabs(e1), fabs(e2))));
+          mx = fmax(mx, (double)fmax(fabs(e0), fmax(fabs(e1), fabs(e2))));
         }
       }
     } else {
       for (int q = tid; q < T.s_len; q += TPB) {
-        double e0, e1, e2;
-        row3(g, x0, x1, x2, ai, T.s_off + q, e0, e1, e2);
+        P e0, e1, e2;
+        Ent<P>::row(g, pi, ai, T.s_off + q, e0, e1, e2);
         sub_panel3(coef, V + 3 * q, k, n, e0, e1, e2);
         vk[3 * q] = e0;
         vk[3 * q + 1] = e1;
@@ -683,7 +752,7 @@ __global__ __launch_bounds__(TPB) void k_aca(DevGeo g0, const AcaTask* __restric
           vs[3 * q + 1] = e1;
           vs[3 * q + 2] = e2;
         }
-        mx = fmax(mx, fmax(fabs(e0), fmax(fabs(e1), fabs(e2))));
+        mx = fmax(mx, (double)fmax(fabs(e0), fmax(fabs(e1), fabs(e2))));
       }
     }
     mx = blk_max(mx, R, ph);
@@ -703,7 +772,7 @@ __global__ __launch_bounds__(TPB) void k_aca(DevGeo g0, const AcaTask* __restric
       }
     }
     if (!pc) {
-      const bool vanished = (k == 0) ? (mx == 0.0) : (mx <= 1e-14 * sqrt(S2));
+      const bool vanished = (k == 0) ? (mx == 0.0) : (mx <= AcaPrec<P>::VANISH * sqrt(S2));
       if (vanished) {
         if (nZ == m) {
           stop = 3;
@@ -740,10 +809,10 @@ __global__ __launch_bounds__(TPB) void k_aca(DevGeo g0, const AcaTask* __restric
         continue;
       }
     }
-    const double thr = (1.0 - 1e-10) * mx;
+    const double thr = (1.0 - AcaPrec<P>::FUZZ) * mx;
     int cand = INT_MAX;
     for (int c = tid; c < n; c += TPB)
-      if (fabs(vr[c]) >= thr) {
+      if ((double)fabs(vr[c]) >= thr) {
         cand = c;
         break;
       }
@@ -752,14 +821,14 @@ __global__ __launch_bounds__(TPB) void k_aca(DevGeo g0, const AcaTask* __restric
       stop = 5;
       break;
     }
-    const double piv = vr[j];
+    const P piv = vr[j];
     __syncthreads();  // every thread holds piv before vk is normalised in place
     double vv = 0.0;
     for (int c = tid; c < n; c += TPB) {
-      const double v = vr[c] / piv;
+      const P v = vr[c] / piv;
       vk[c] = v;
       if (stage) vs[c] = v;
-      vv += v * v;
+      vv += (double)v * (double)v;
     }
     const int pend = pc;  // this step also forms the pending cross term
     for (int l = tid; l < k; l += TPB) {
@@ -772,19 +841,19 @@ __global__ __launch_bounds__(TPB) void k_aca(DevGeo g0, const AcaTask* __restric
     __syncthreads();
     // column j of the remainder into U[:, k] (S is symmetric: A[3p+a, 3q+b] = S_ba),
     // and the pending cross term u_c . (U[:, 0:c] w), c = k - 1
-    double* __restrict__ uk = U + (size_t)k * m;
-    double* const ur = stage ? us : uk;  // where this step reads u_k
+    P* __restrict__ uk = U + (size_t)k * m;
+    P* const ur = stage ? us : uk;  // where this step reads u_k
     const int qj = T.s_off + j / 3, bj = j % 3;
     double uu = 0.0, cross = 0.0;
     for (int p = tid; p < T.t_len; p += TPB) {
       const int ip = T.t_off + p;
-      double e0, e1, e2;
-      row3(g, g.cen[ip], g.cen[nt + ip], g.cen[2 * nt + ip], bj, qj, e0, e1, e2);
+      P e0, e1, e2;
+      Ent<P>::row(g, ip, bj, qj, e0, e1, e2);
       if (pend) {
         double t0, t1, t2;
         sub_panel3w(coef, wl, U + 3 * p, k, m, e0, e1, e2, t0, t1, t2);
-        const double* uc = U + (size_t)(k - 1) * m + 3 * p;
-        cross += uc[0] * t0 + uc[1] * t1 + uc[2] * t2;
+        const P* uc = U + (size_t)(k - 1) * m + 3 * p;
+        cross += (double)uc[0] * t0 + (double)uc[1] * t1 + (double)uc[2] * t2;
       } else {
         sub_panel3(coef, U + 3 * p, k, m, e0, e1, e2);
       }
@@ -796,7 +865,7 @@ __global__ __launch_bounds__(TPB) void k_aca(DevGeo g0, const AcaTask* __restric
         us[3 * p + 1] = e1;
         us[3 * p + 2] = e2;
       }
-      uu += e0 * e0 + e1 * e1 + e2 * e2;
+      uu += (double)e0 * (double)e0 + (double)e1 * (double)e1 + (double)e2 * (double)e2;
     }
     blk_sum3(uu, vv, cross, R, ph);
     if (pend) {
@@ -813,7 +882,7 @@ __global__ __launch_bounds__(TPB) void k_aca(DevGeo g0, const AcaTask* __restric
         if (i < 0) { stop = 1; break; }
         continue;
       }
-      if (mx <= 1e-14 * sqrt(S2)) {  // row i vanishes: it stays in Z, no cross
+      if (mx <= AcaPrec<P>::VANISH * sqrt(S2)) {  // row i vanishes: it stays in Z, no cross
         if (nZ == m) { stop = 3; break; }
         if (T.cycle)
           i = cycle_next<TPB>(U, U + (size_t)(k - 1) * m, k, m, Z, i, R, ph);
@@ -1222,29 +1291,39 @@ hipError_t allow_full_lds(const void* f, int bit) {
 }
 }  // namespace
 
-hipError_t launch_aca(const DevGeo& g, const AcaTask* tasks, int ntasks, int n_big, size_t shmem_big,
-                      size_t shmem_small, bool wide, int32_t* rank, int32_t* stop, double* ratio,
-                      hipStream_t s) {
+template <typename P>
+hipError_t launch_aca_t(const DevGeo& g, const AcaTask* tasks, int ntasks, int n_big, size_t shmem_big,
+                        size_t shmem_small, bool wide, int32_t* rank, int32_t* stop, double* ratio,
+                        hipStream_t s) {
+  const int bits = sizeof(P) == 8 ? 0 : 3;
   if (shmem_big > 64 * 1024) {
-    const void* f = wide ? reinterpret_cast<const void*>(&k_aca<ACA_WIDE_T>)
-                         : reinterpret_cast<const void*>(&k_aca<ACA_T>);
-    const hipError_t e = allow_full_lds(f, wide ? 1 : 0);
+    const void* f = wide ? reinterpret_cast<const void*>(&k_aca<ACA_WIDE_T, P>)
+                         : reinterpret_cast<const void*>(&k_aca<ACA_T, P>);
+    const hipError_t e = allow_full_lds(f, bits + (wide ? 1 : 0));
     if (e != hipSuccess) return e;
   }
   if (shmem_small > 64 * 1024) {
-    const hipError_t e = allow_full_lds(reinterpret_cast<const void*>(&k_aca<ACA_SMALL_T>), 2);
+    const hipError_t e = allow_full_lds(reinterpret_cast<const void*>(&k_aca<ACA_SMALL_T, P>), bits + 2);
     if (e != hipSuccess) return e;
   }
   if (n_big > 0 && wide)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_aca<ACA_WIDE_T>), dim3(n_big), dim3(ACA_WIDE_T), shmem_big, s, g,
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_aca<ACA_WIDE_T, P>), dim3(n_big), dim3(ACA_WIDE_T), shmem_big, s, g,
                        tasks, rank, stop, ratio);
   else if (n_big > 0)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_aca<ACA_T>), dim3(n_big), dim3(ACA_T), shmem_big, s, g, tasks,
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_aca<ACA_T, P>), dim3(n_big), dim3(ACA_T), shmem_big, s, g, tasks,
                        rank, stop, ratio);
   if (ntasks > n_big)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_aca<ACA_SMALL_T>), dim3(ntasks - n_big), dim3(ACA_SMALL_T),
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_aca<ACA_SMALL_T, P>), dim3(ntasks - n_big), dim3(ACA_SMALL_T),
                        shmem_small, s, g, tasks + n_big, rank, stop, ratio);
   return hipGetLastError();
+}
+
+// fp32: panels, entries and remainders in FP32 (FP32 builds); else FP64.
+hipError_t launch_aca(const DevGeo& g, const AcaTask* tasks, int ntasks, int n_big, size_t shmem_big,
+                      size_t shmem_small, bool wide, bool fp32, int32_t* rank, int32_t* stop, double* ratio,
+                      hipStream_t s) {
+  return fp32 ? launch_aca_t<float>(g, tasks, ntasks, n_big, shmem_big, shmem_small, wide, rank, stop, ratio, s)
+              : launch_aca_t<double>(g, tasks, ntasks, n_big, shmem_big, shmem_small, wide, rank, stop, ratio, s);
 }
 
 __global__ __launch_bounds__(256) void k_copy_spans(const SpanCopy* __restrict__ t) {
@@ -1262,39 +1341,55 @@ hipError_t launch_copy_spans(const SpanCopy* t, int n, hipStream_t s) {
 // full-rank run can end inexact when a remainder at rounding level is taken
 // as a cross): U = B, V = I for n <= m, else U = I, V = B^T, entries as in the
 // ACA passes (S symmetric: A[3p+a, 3q+b] = S_ba). One workgroup per block.
+template <typename P>
 __global__ __launch_bounds__(256) void k_exact(DevGeo g0, const ExactTask* __restrict__ tasks) {
   const ExactTask T = tasks[blockIdx.x];
   const DevGeo g = body_geo(g0, T.t_off);
   const int m = 3 * T.t_len, n = 3 * T.s_len, nt = g.nt;
-  double* __restrict__ U = T.panel;
-  double* __restrict__ V = T.panel + (size_t)m * T.kcap;
+  P* __restrict__ U = static_cast<P*>(T.panel);
+  P* __restrict__ V = U + (size_t)m * T.kcap;
   if (n <= m) {
     for (int e = threadIdx.x; e < T.t_len * n; e += blockDim.x) {
       const int p = e % T.t_len, c = e / T.t_len, ip = T.t_off + p;
       double e0, e1, e2;
       row3(g, g.cen[ip], g.cen[nt + ip], g.cen[2 * nt + ip], c % 3, T.s_off + c / 3, e0, e1, e2);
-      double* col = U + (size_t)c * m + 3 * p;
-      col[0] = e0;
-      col[1] = e1;
-      col[2] = e2;
+      P* col = U + (size_t)c * m + 3 * p;
+      col[0] = (P)e0;
+      col[1] = (P)e1;
+      col[2] = (P)e2;
     }
-    for (int e = threadIdx.x; e < n * n; e += blockDim.x) V[(size_t)(e / n) * n + e % n] = (e / n == e % n) ? 1.0 : 0.0;
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) V[(size_t)(e / n) * n + e % n] = (e / n == e % n) ? P(1) : P(0);
   } else {
     for (int e = threadIdx.x; e < m * T.s_len; e += blockDim.x) {
       const int q = e % T.s_len, r = e / T.s_len, ip = T.t_off + r / 3;
       double e0, e1, e2;
       row3(g, g.cen[ip], g.cen[nt + ip], g.cen[2 * nt + ip], r % 3, T.s_off + q, e0, e1, e2);
-      double* col = V + (size_t)r * n + 3 * q;
-      col[0] = e0;
-      col[1] = e1;
-      col[2] = e2;
+      P* col = V + (size_t)r * n + 3 * q;
+      col[0] = (P)e0;
+      col[1] = (P)e1;
+      col[2] = (P)e2;
     }
-    for (int e = threadIdx.x; e < m * m; e += blockDim.x) U[(size_t)(e / m) * m + e % m] = (e / m == e % m) ? 1.0 : 0.0;
+    for (int e = threadIdx.x; e < m * m; e += blockDim.x) U[(size_t)(e / m) * m + e % m] = (e / m == e % m) ? P(1) : P(0);
   }
 }
 
-hipError_t launch_exact(const DevGeo& g, const ExactTask* tasks, int ntasks, hipStream_t s) {
-  if (ntasks > 0) hipLaunchKernelGGL(k_exact, dim3(ntasks), dim3(256), 0, s, g, tasks);
+hipError_t launch_exact(const DevGeo& g, const ExactTask* tasks, int ntasks, bool fp32, hipStream_t s) {
+  if (ntasks > 0 && fp32) hipLaunchKernelGGL(HIP_KERNEL_NAME(k_exact<float>), dim3(ntasks), dim3(256), 0, s, g, tasks);
+  if (ntasks > 0 && !fp32) hipLaunchKernelGGL(HIP_KERNEL_NAME(k_exact<double>), dim3(ntasks), dim3(256), 0, s, g, tasks);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_compact32(const CopyTask32* __restrict__ tasks) {
+  const CopyTask32 T = tasks[blockIdx.x];
+  const int64_t nv = (int64_t)T.n * T.k;
+  for (int64_t e = threadIdx.x; e < nv; e += blockDim.x) {
+    const int64_t c = e / T.n, i = e - c * T.n;
+    T.dstV[c * T.ldv + T.fpv + i] = (double)T.srcV[e];
+  }
+}
+
+hipError_t launch_compact32(const CopyTask32* tasks, int ntasks, hipStream_t s) {
+  if (ntasks > 0) hipLaunchKernelGGL(k_compact32, dim3(ntasks), dim3(256), 0, s, tasks);
   return hipGetLastError();
 }
 

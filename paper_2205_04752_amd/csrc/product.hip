@@ -511,15 +511,16 @@ __global__ __launch_bounds__(256) void k_to_stream(const StreamTask* __restrict_
 }
 
 // Stream segment -> plain column-major block matrix (rows outside [0, m) skipped).
+template <typename E>
 __global__ __launch_bounds__(256) void k_from_stream(const StreamTask* __restrict__ tasks,
-                                                     const double* __restrict__ stream) {
+                                                     const E* __restrict__ stream) {
   const StreamTask T = tasks[blockIdx.x];
   const int len = T.row_hi - T.row_lo;
   const int64_t total = (int64_t)len * (T.c1 - T.c0);
   for (int64_t e = threadIdx.x; e < total; e += blockDim.x) {
     const int64_t c = T.c0 + e / len;
     const int i = T.r0 + T.row_lo + (int)(e % len);
-    if (i >= 0 && i < T.ld) T.dst[c * T.ld + i] = stream[T.so + e];
+    if (i >= 0 && i < T.ld) T.dst[c * T.ld + i] = (double)stream[T.so + e];
   }
 }
 
@@ -663,7 +664,11 @@ hipError_t launch_to_stream(const StreamTask* tasks, int ntasks, double* stream,
 }
 
 hipError_t launch_from_stream(const StreamTask* tasks, int ntasks, const double* stream, hipStream_t s) {
-  if (ntasks > 0) hipLaunchKernelGGL(k_from_stream, dim3(ntasks), dim3(256), 0, s, tasks, stream);
+  if (ntasks > 0) hipLaunchKernelGGL(HIP_KERNEL_NAME(k_from_stream<double>), dim3(ntasks), dim3(256), 0, s, tasks, stream);
+  return hipGetLastError();
+}
+hipError_t launch_from_stream32(const StreamTask* tasks, int ntasks, const float* stream, hipStream_t s) {
+  if (ntasks > 0) hipLaunchKernelGGL(HIP_KERNEL_NAME(k_from_stream<float>), dim3(ntasks), dim3(256), 0, s, tasks, stream);
   return hipGetLastError();
 }
 

@@ -82,6 +82,16 @@ def test_build_validation_before_device_work():
     m4, keep4 = _mesh_struct(V4, T)
     assert L.hmat_build(C.byref(m4), 1.0, 0.3, 2.0, 32, 1e-4, None, C.byref(h)) == H.HMAT_EINVAL
     assert L.hmat_build(None, 1.0, 0.3, 2.0, 32, 1e-4, None, C.byref(h)) == H.HMAT_EINVAL
+    # options of hmat_build_ex
+    for prec, fac, eps in ((2, 1.0, 1e-4), (-1, 1.0, 1e-4), (0, 0.0, 1e-4), (0, -1.0, 1e-4),
+                           (1, float("nan"), 1e-4), (0, 2e4, 1e-4)):
+        o = H._Opts(prec, 0, fac)
+        h = C.c_void_p(123)
+        assert L.hmat_build_ex(C.byref(m), 1.0, 0.3, 2.0, 32, eps, C.byref(o), None,
+                               C.byref(h)) == H.HMAT_EINVAL, (prec, fac)
+        assert h.value is None and L.hmat_last_error().decode()
+    o = H._Opts(0, 0, 1.0)
+    assert L.hmat_build_ex(C.byref(m), 1.0, 0.5, 2.0, 32, 1e-4, C.byref(o), None, C.byref(h)) == H.HMAT_EINVAL
     assert L.hmat_build(C.byref(m), 1.0, 0.3, 2.0, 32, 1e-4, None, None) == H.HMAT_EINVAL
 
 
@@ -147,6 +157,7 @@ def test_other_entry_points_reject_null_handle():
     assert L.hmat_matvec(None, 1, None, 3, None, 3, None) == H.HMAT_EINVAL
     assert L.hmat_solve(None, None, None, 1e-8, 50, 10, None, None) == H.HMAT_EINVAL
     assert L.hmat_solve_noalloc(None, None, None, 1e-8, 50, 10, None, None) == H.HMAT_EINVAL
+    assert L.hmat_build_ex(None, 1.0, 0.3, 2.0, 32, 1e-4, None, None, None) == H.HMAT_EINVAL
     assert L.hmat_info(None, None) == H.HMAT_EINVAL
     assert L.hmat_block(None, 0, None, None, None, None, None) == H.HMAT_EINVAL
     assert L.hmat_entries(None, 0, None, None, None, None) == H.HMAT_EINVAL

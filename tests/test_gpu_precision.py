@@ -114,3 +114,100 @@ def test_precision_switch_and_errors(c0):
     with pytest.raises(H.HmatError):
         g.set_precision(2)
     g.close()
+
+
+@pytest.fixture(scope="module")
+def f32():
+    """FP32 builds (hmat_build_ex precision 1) of icosphere level 3: eps 1e-5
+    (ACA in FP32) and 1e-7 (ACA in FP64, factors rounded), beside FP64 builds."""
+    H = _H()
+    V, T = W.icosphere(3)
+    mesh = O.Mesh(V, T, 1.0, 0.3)
+    out = {}
+    for eps in (1e-5, 1e-7):
+        print(f"case precision: FP32 build, icosphere level 3, eps {eps}", flush=True)
+        out[eps] = (H.HMatrix(V, T, 1.0, 0.3, 2.0, 32, eps, precision=1),
+                    H.HMatrix(V, T, 1.0, 0.3, 2.0, 32, eps))
+    return dict(V=V, T=T, mesh=mesh, A=mesh.dense(), out=out, N=3 * len(T))
+
+
+def test_fp32_build_accuracy_and_memory(f32):
+    """The FP32 build's product is within the requested accuracy of the exact
+    collocation product (the bound the FP64 build meets, 10 eps, plus FP32
+    rounding), within that of the FP64 build's, and the handle holds about
+    half the device memory."""
+    x = W.random_x(f32["N"], 4, seed=21)
+    bt = x @ f32["A"].T
+    for eps, (g32, g64) in f32["out"].items():
+        st32, st64 = g32.info(), g64.info()
+        assert st32["precision"] == 1 and st64["precision"] == 0
+        assert st32["aca_fp32"] == (1 if eps >= 1e-5 else 0)
+        assert st32["device_bytes"] < 0.62 * st64["device_bytes"], (st32["device_bytes"], st64["device_bytes"])
+        xd = torch.from_numpy(x).cuda()
+        y32 = g32.matvec(xd).cpu().numpy()
+        y64 = g64.matvec(xd).cpu().numpy()
+        tol = 10 * max(eps, 1e-7)
+        for r in range(4):
+            e32 = np.linalg.norm(y32[r] - bt[r]) / np.linalg.norm(bt[r])
+            e64 = np.linalg.norm(y64[r] - bt[r]) / np.linalg.norm(bt[r])
+            assert e32 <= tol, (eps, r, e32, e64)
+            assert np.linalg.norm(y32[r] - y64[r]) <= tol * np.linalg.norm(y64[r])
+        print(f"fp32 build eps {eps}: ranks mean {st32['rank_mean']:.1f} (fp64 {st64['rank_mean']:.1f}), "
+              f"bytes {st32['device_bytes']} (fp64 {st64['device_bytes']}), product error {e32:.2e} "
+              f"(fp64 {e64:.2e})", flush=True)
+
+
+def test_fp32_build_refinement(f32):
+    """Iterative refinement on an FP32 build: the residual uses the stored FP32
+    operator in FP64 arithmetic, so the relative residual 1e-8 refers to it;
+    the solution differs from the FP64 build's by what the operators' eps
+    allows."""
+    V, T = f32["V"], f32["T"]
+    b = torch.from_numpy(W.smooth_rhs(V, T, seed=5)).cuda()
+    for eps, (g32, g64) in f32["out"].items():
+        x, info = g32.solve_ir(b, tol=1e-8, restart=50, inner_precision=1, inner_tol=1e-6)
+        assert info["status"] == 0
+        rel = float(torch.linalg.norm(b - g32.matvec(x)) / torch.linalg.norm(b))
+        assert rel <= 1e-8
+        x64, _ = g64.solve(b, tol=1e-8, restart=50)
+        d = float(torch.linalg.norm(x - x64) / torch.linalg.norm(x64))
+        assert d <= 1e3 * max(eps, 1e-7), (eps, d)
+        print(f"fp32 build eps {eps}: refinement {info['refinements']} steps, "
+              f"{info['iterations']} inner iterations, relres {rel:.2e}, vs FP64 solution {d:.2e}", flush=True)
+        xs, _ = g32.solve(b, tol=1e-8, restart=50)  # plain GMRES on the FP32 entries
+        assert float(torch.linalg.norm(b - g32.matvec(xs)) / torch.linalg.norm(b)) <= 1e-8
+
+
+def test_fp32_build_refuses_fp64(f32):
+    H = _H()
+    g32 = f32["out"][1e-5][0]
+    x = torch.from_numpy(W.random_x(f32["N"], 1, seed=2)[0]).cuda()
+    with pytest.raises(H.HmatError) as ei:
+        g32.set_precision(0)
+    assert ei.value.status == H.HMAT_ENOTSUP
+    g32.set_precision(1)  # already so
+    with pytest.raises(H.HmatError):
+        g32.solve_ir(x, inner_precision=0)
+    y1 = g32.matvec(x, precision=1)
+    y = g32.matvec(x)
+    assert torch.equal(y, y1)
+
+
+def test_aca_stop_factor():
+    """hmat_build_ex's stop constant c: ACA stops at |u||v| <= c eps ||S||, so
+    (eps, c = 0.5) is the build at eps / 2, bit for bit, and the oracle's
+    ranks and pivots at eps / 2."""
+    H = _H()
+    V, T = W.icosphere(3)
+    ga = H.HMatrix(V, T, 1.0, 0.3, 2.0, 32, 1e-4, aca_stop_factor=0.5)
+    gb = H.HMatrix(V, T, 1.0, 0.3, 2.0, 32, 5e-5)
+    o = O.HMatrix(O.Mesh(V, T, 1.0, 0.3), 2.0, 32, eps=5e-5)
+    ob = o.blocks()
+    for b in np.nonzero(ob[:, 4] == 1)[0]:
+        ba, bb = ga.block(int(b)), gb.block(int(b))
+        assert ba["rank"] == bb["rank"] == ob[b, 5]
+        assert np.array_equal(ba["U"], bb["U"]) and np.array_equal(ba["V"], bb["V"])
+        _, _, pr, pc = o.factors(int(b))
+        assert np.array_equal(ba["rows"], pr) and np.array_equal(ba["cols"], pc)
+    ga.close()
+    gb.close()
