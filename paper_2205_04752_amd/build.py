@@ -26,6 +26,7 @@ SOURCES = [
     # (file, extra flags)
     ("kernels.hip", ["-x", "hip", f"--offload-arch={ARCH}", *NO_PK, "-munsafe-fp-atomics"]),
     ("product.hip", ["-x", "hip", f"--offload-arch={ARCH}", *NO_PK]),
+    ("amvm.hip", ["-x", "hip", f"--offload-arch={ARCH}", *NO_PK]),
     # the planner's geometry and admissibility tests must not be contracted
     ("planner.cpp", ["-ffp-contract=off"]),
     ("api.cpp", []),

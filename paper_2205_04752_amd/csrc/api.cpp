@@ -50,9 +50,15 @@ hipError_t launch_residual(const double*, int64_t, double*, hipStream_t);
 hipError_t launch_fill(double*, int64_t, double, hipStream_t);
 hipError_t launch_axpy(double, const double*, int64_t, double*, hipStream_t);
 hipError_t launch_dense_mv(const DenseMvTask*, int, const double*, const double*, double*, hipStream_t);
-hipError_t launch_lowrank_delta(const DeltaTask*, int, const double*, double*, hipStream_t);
-hipError_t launch_amvm_rowsum(const int64_t*, const int32_t*, const char*, const int64_t*, const int64_t*,
-                              const double*, int64_t, double*, hipStream_t);
+hipError_t launch_lowrank_delta(const DeltaTask*, const int2*, int, const int32_t*, int, const double*, double*,
+                                char*, hipStream_t);
+hipError_t launch_amvm_aca_tasks(const AcaTask*, const int2*, int, AcaTask*, hipStream_t);
+size_t amvm_sort_bytes(int64_t, int);
+size_t amvm_leaf_shmem(int);
+hipError_t launch_amvm_estimate(const AmvmDev&, double, double, hipStream_t);
+hipError_t launch_amvm_stop(const AmvmDev&, double, int32_t, hipStream_t);
+hipError_t launch_amvm_update(const AmvmDev&, int32_t, hipStream_t);
+hipError_t launch_amvm_out(const double*, const int32_t*, int64_t, double*, hipStream_t);
 hipError_t noalloc_workspace(double**);
 }  // namespace hm
 
@@ -2016,168 +2022,231 @@ hmat_status amvm_impl(const hmat_mesh* mesh, double E, double nu, double eta, in
     }
     if (std::max(shmem[0], shmem[1]) > 160 * 1024)
       throw HipError{HMAT_ENOTSUP, "ACA panel row exceeds LDS capacity"};
-    // rows -> admissible blocks containing them (canonical order)
-    std::vector<int64_t> rptr(N + 1, 0);
-    for (size_t f = 0; f < nf; f++)
-      for (int64_t r = 0; r < M[f]; r++) rptr[R0[f] + r + 1]++;
-    for (int64_t i = 0; i < N; i++) rptr[i + 1] += rptr[i];
-    std::vector<int32_t> rblk(rptr[N]);
-    {
-      std::vector<int64_t> fill(rptr.begin(), rptr.end() - 1);
-      for (size_t f = 0; f < nf; f++)
-        for (int64_t r = 0; r < M[f]; r++) rblk[fill[R0[f] + r]++] = (int32_t)f;
+    // Leaf clusters: the rows of a leaf all lie in the same admissible blocks
+    // (those whose row cluster contains the leaf), listed in canonical order.
+    std::vector<AmvmLeaf> leaves;
+    for (const Cluster& c : P.cl)
+      if (c.son0 < 0) leaves.push_back(AmvmLeaf{3 * (int64_t)c.off, 0, 3 * c.len, 0});
+    std::sort(leaves.begin(), leaves.end(), [](const AmvmLeaf& u, const AmvmLeaf& v) { return u.r0 < v.r0; });
+    const int nl = (int)leaves.size();
+    // leaves inside a block's row cluster: a contiguous range of `leaves`
+    const auto leaf_range = [&](size_t f) {
+      const auto lo = std::lower_bound(leaves.begin(), leaves.end(), R0[f],
+                                       [](const AmvmLeaf& u, int64_t r) { return u.r0 < r; });
+      const auto hi = std::lower_bound(lo, leaves.end(), R0[f] + M[f],
+                                       [](const AmvmLeaf& u, int64_t r) { return u.r0 < r; });
+      return std::make_pair(lo - leaves.begin(), hi - leaves.begin());
+    };
+    for (size_t f = 0; f < nf; f++) {
+      const auto lr = leaf_range(f);
+      for (auto l = lr.first; l < lr.second; l++) leaves[l].nb++;
     }
-    std::vector<char> adv(nf, 1);  // blocks whose look-ahead must be computed
-    // the row errors are summed on the device (rows -> blocks as above)
-    DevBuf d_rptr, d_rblk, d_doff, d_r0, d_has, d_e;
-    upload(d_rptr, rptr, s, "amvm rows");
-    upload(d_rblk, rblk, s, "amvm rows");
-    upload(d_doff, doff, s, "amvm rows");
-    upload(d_r0, R0, s, "amvm rows");
-    d_e.alloc(sizeof(double) * std::max<int64_t>(N, 1), "amvm rows");
-    // the look-ahead contributions and row errors come back every round:
-    // pinned host memory
+    int64_t ltot = 0;
+    int nbmax = 0;
+    for (AmvmLeaf& L : leaves) {
+      L.b0 = ltot;
+      ltot += L.nb;
+      nbmax = std::max(nbmax, L.nb);
+    }
+    std::vector<int32_t> lblk(std::max<int64_t>(ltot, 1));
+    {
+      std::vector<int64_t> fill(nl);
+      for (int l = 0; l < nl; l++) fill[l] = leaves[l].b0;
+      for (size_t f = 0; f < nf; f++) {
+        const auto lr = leaf_range(f);
+        for (auto l = lr.first; l < lr.second; l++) lblk[fill[l]++] = (int32_t)f;
+      }
+    }
+    if (amvm_leaf_shmem(nbmax) > 64 * 1024)
+      throw HipError{HMAT_ENOTSUP, "adaptive multiplication: too many admissible blocks over one leaf cluster"};
+    std::vector<int64_t> dbase(nf);
+    std::vector<int32_t> mrow(nf);
+    for (size_t f = 0; f < nf; f++) {
+      dbase[f] = doff[f] - R0[f];
+      mrow[f] = (int32_t)M[f];
+    }
+    DevBuf d_leaves, d_lblk, d_lsorted, d_lcount, d_has, d_dbase, d_doff, d_r0, d_mrow, d_dsq, d_restv, d_b, d_e,
+        d_rkey, d_rval, d_rrank, d_part, d_bkey, d_sf, d_pos, d_ds, d_ctl, d_sort;
+    upload(d_leaves, leaves, s, "amvm leaves");
+    upload(d_lblk, lblk, s, "amvm leaves");
+    upload(d_dbase, dbase, s, "amvm blocks");
+    upload(d_doff, doff, s, "amvm blocks");
+    upload(d_r0, R0, s, "amvm blocks");
+    upload(d_mrow, mrow, s, "amvm blocks");
+    upload(d_b, b, s, "amvm vectors");
+    const auto nz = [](int64_t v) { return (size_t)std::max<int64_t>(v, 1); };
+    d_lsorted.alloc(sizeof(int32_t) * nz(ltot), "amvm leaves");
+    d_lcount.alloc(sizeof(int32_t) * nz(nl), "amvm leaves");
+    d_has.alloc(nz(nf), "amvm blocks");
+    d_dsq.alloc(sizeof(double) * nz(dtot), "amvm deltas");
+    d_restv.alloc(sizeof(double) * nz(dtot), "amvm deltas");
+    d_e.alloc(sizeof(double) * nz(N), "amvm vectors");
+    d_rkey.alloc(sizeof(uint64_t) * 2 * nz(N), "amvm sort");
+    d_rval.alloc(sizeof(int32_t) * 2 * nz(N), "amvm sort");
+    d_rrank.alloc(sizeof(int32_t) * nz(N), "amvm sort");
+    d_part.alloc(sizeof(double) * 2 * nz(nl), "amvm sort");
+    d_bkey.alloc(sizeof(uint64_t) * 2 * nz(nf), "amvm sort");
+    d_sf.alloc(sizeof(int32_t) * nz(nf), "amvm sort");
+    d_pos.alloc(sizeof(int32_t) * nz(nf), "amvm sort");
+    d_ds.alloc(sizeof(double) * nz(nf), "amvm sort");
+    d_ctl.alloc(sizeof(AmvmCtl), "amvm sort");
+    const size_t sort_bytes = amvm_sort_bytes(N, (int)nf);
+    d_sort.alloc(sort_bytes, "amvm sort");
+    AmvmDev A{};
+    A.leaves = d_leaves.as<AmvmLeaf>();
+    A.n_leaves = nl;
+    A.nbmax = nbmax;
+    A.nf = (int)nf;
+    A.n = N;
+    A.lblk = d_lblk.as<int32_t>();
+    A.has_d = d_has.as<char>();
+    A.dbase = d_dbase.as<int64_t>();
+    A.doff = d_doff.as<int64_t>();
+    A.r0 = d_r0.as<int64_t>();
+    A.mrow = d_mrow.as<int32_t>();
+    A.d = d_d.as<double>();
+    A.b = d_b.as<double>();
+    A.e = d_e.as<double>();
+    A.part = d_part.as<double>();
+    A.dsq = d_dsq.as<double>();
+    A.restv = d_restv.as<double>();
+    A.ds = d_ds.as<double>();
+    A.rkey = d_rkey.as<uint64_t>();
+    A.bkey = d_bkey.as<uint64_t>();
+    A.rval = d_rval.as<int32_t>();
+    A.rank = d_rrank.as<int32_t>();
+    A.sf = d_sf.as<int32_t>();
+    A.pos = d_pos.as<int32_t>();
+    A.lsorted = d_lsorted.as<int32_t>();
+    A.lcount = d_lcount.as<int32_t>();
+    A.ctl = d_ctl.as<AmvmCtl>();
+    A.sort_tmp = d_sort.p;
+    A.sort_bytes = sort_bytes;
+    // per-block templates of the round's tasks, on the device
+    std::vector<DeltaTask> tmpl(nf);
+    for (size_t f = 0; f < nf; f++) {
+      const double* pan = panels.as<double>() + poff[f];
+      tmpl[f] = DeltaTask{pan, pan + M[f] * kcap[f], doff[f], (int32_t)M[f], (int32_t)Nn[f], 0, 0,
+                          3 * P.cl[P.blk[h->far_blocks[f]].s].off, 0};
+    }
+    DevBuf d_base, d_tmpl, d_lists, d_tasks;
+    upload(d_base, base, s, "amvm ACA");
+    upload(d_tmpl, tmpl, s, "amvm deltas");
+    d_lists.alloc(sizeof(int2) * 2 * nz(nf), "amvm ACA");
+    d_tasks.alloc(sizeof(AcaTask) * nz(nf), "amvm ACA");
+    check(hipMemsetAsync(d_has.p, 0, d_has.bytes, s), "amvm deltas");
+    // pinned host buffers: the round's lists (ACA: block, pause; deltas:
+    // block, first column) and what a round reads back (scalars, order of
+    // the candidate blocks, ACA ranks and stop codes)
     struct Pinned {
-      double* p = nullptr;
+      void* p = nullptr;
       ~Pinned() {
         if (p) (void)hipHostFree(p);
       }
-    } d_host, e_host;
-    check(hipHostMalloc((void**)&d_host.p, sizeof(double) * std::max<int64_t>(dtot, 1)), "amvm host buffer");
-    check(hipHostMalloc((void**)&e_host.p, sizeof(double) * std::max<int64_t>(N, 1)), "amvm host buffer");
-    double* const d = d_host.p;
-    std::vector<double> e(N), rest(N);
-    std::vector<int64_t> rows(N);
-    std::vector<char> marked(nf, 0), has_d(nf, 0);
+    } up, back;
+    check(hipHostMalloc(&up.p, sizeof(int2) * 2 * nz(nf)), "amvm host buffer");
+    check(hipHostMalloc(&back.p, sizeof(AmvmCtl) + 3 * sizeof(int32_t) * nz(nf)), "amvm host buffer");
+    int2* const aca_list = (int2*)up.p;
+    int2* const dl_list = aca_list + nz(nf);
+    AmvmCtl* const ctl = (AmvmCtl*)back.p;
+    int32_t* const sf = (int32_t*)(ctl + 1);
+    int32_t* const rk = sf + nz(nf);
+    int32_t* const sp = rk + nz(nf);
+    // the one-wave ACA launch runs beside the wide one, on a second stream
+    struct Side {
+      hipStream_t s2 = nullptr;
+      hipEvent_t fork = nullptr, join = nullptr;
+      ~Side() {
+        if (fork) (void)hipEventDestroy(fork);
+        if (join) (void)hipEventDestroy(join);
+        if (s2) (void)hipStreamDestroy(s2);
+      }
+    } side;
+    check(hipStreamCreateWithFlags(&side.s2, hipStreamNonBlocking), "amvm stream");
+    check(hipEventCreateWithFlags(&side.fork, hipEventDisableTiming), "amvm stream");
+    check(hipEventCreateWithFlags(&side.join, hipEventDisableTiming), "amvm stream");
+    const double den = std::sqrt((double)P.csp * (double)N * (double)N);
+    std::vector<char> adv(nf, 1);  // blocks marked in the last round (all at first)
+    std::vector<char> big(nf);
+    for (size_t f = 0; f < nf; f++) big[f] = std::max(base[f].t_len, base[f].s_len) > ACA_SMALL_TRI;
     int rounds = 0;
     int64_t marked_total = 0;
     double gamma = 0.0;
     for (;;) {
-      // (a) resume ACA up to r_use + LOOK on the blocks that need it
-      std::vector<AcaTask> tasks;
-      for (size_t f = 0; f < nf; f++) {
-        if (!adv[f] || done[f]) continue;
-        const int32_t target = std::min(r_use[f] + LOOK, kcap[f]);
-        if (k_avail[f] >= target) continue;
-        AcaTask t = base[f];
-        t.k_stop = target;
-        tasks.push_back(t);
-      }
-      if (!tasks.empty()) {
-        const int n_big = (int)(std::stable_partition(tasks.begin(), tasks.end(), [](const AcaTask& t) {
-                                  return std::max(t.t_len, t.s_len) > ACA_SMALL_TRI;
-                                }) - tasks.begin());
-        DevBuf d_tasks;
-        upload(d_tasks, tasks, s, "amvm ACA");
-        check(launch_aca(h->G, d_tasks.as<AcaTask>(), (int)tasks.size(), n_big, shmem[0], shmem[1], true, false,
-                         d_rank.as<int32_t>(),
-                         d_stop.as<int32_t>(), d_ratio.as<double>(), s), "amvm ACA");
-        std::vector<int32_t> rk(nf), sp(nf);
-        check(hipMemcpyAsync(rk.data(), d_rank.p, sizeof(int32_t) * nf, hipMemcpyDeviceToHost, s), "amvm ACA");
-        check(hipMemcpyAsync(sp.data(), d_stop.p, sizeof(int32_t) * nf, hipMemcpyDeviceToHost, s), "amvm ACA");
-        check(hipStreamSynchronize(s), "amvm ACA");
-        for (const AcaTask& t : tasks) {
-          const int32_t f = t.blk;
-          if (sp[f] == 5) throw HipError{HMAT_EINVAL, "non-finite matrix entries (overlapping or duplicate triangles?)"};
-          k_avail[f] = rk[f];
-          done[f] = sp[f] != 6;
+      // (a) resume ACA up to r_use + LOOK on the marked blocks that need it
+      // (wide launch first in the list), and (b) recompute d_b for the marked
+      // blocks: the windows of the others have not moved
+      int na = 0, nd = 0;
+      for (int pass = 0; pass < 2; pass++)
+        for (size_t f = 0; f < nf; f++) {
+          if (!adv[f] || done[f] || big[f] != (pass == 0)) continue;
+          const int32_t target = std::min(r_use[f] + LOOK, kcap[f]);
+          if (k_avail[f] < target) aca_list[na++] = int2{(int)f, target};
         }
+      int n_big = 0;
+      while (n_big < na && big[aca_list[n_big].x]) n_big++;
+      for (size_t f = 0; f < nf; f++)
+        if (adv[f]) dl_list[nd++] = int2{(int)f, r_use[f]};
+      int2* const d_aca_list = d_lists.as<int2>();
+      int2* const d_dl_list = d_aca_list + nz(nf);
+      if (na > 0) {
+        check(hipMemcpyAsync(d_aca_list, aca_list, sizeof(int2) * na, hipMemcpyHostToDevice, s), "amvm ACA");
+        check(launch_amvm_aca_tasks(d_base.as<AcaTask>(), d_aca_list, na, d_tasks.as<AcaTask>(), s), "amvm ACA");
+        check(hipEventRecord(side.fork, s), "amvm stream");
+        check(hipStreamWaitEvent(side.s2, side.fork, 0), "amvm stream");
+        check(launch_aca(h->G, d_tasks.as<AcaTask>(), n_big, n_big, shmem[0], shmem[1], true, false,
+                         d_rank.as<int32_t>(), d_stop.as<int32_t>(), d_ratio.as<double>(), s), "amvm ACA");
+        check(launch_aca(h->G, d_tasks.as<AcaTask>() + n_big, na - n_big, 0, shmem[0], shmem[1], true, false,
+                         d_rank.as<int32_t>(), d_stop.as<int32_t>(), d_ratio.as<double>(), side.s2), "amvm ACA");
+        check(hipEventRecord(side.join, side.s2), "amvm stream");
+        check(hipStreamWaitEvent(s, side.join, 0), "amvm stream");
+      }
+      if (nd > 0) {
+        check(hipMemcpyAsync(d_dl_list, dl_list, sizeof(int2) * nd, hipMemcpyHostToDevice, s), "amvm deltas");
+        check(launch_lowrank_delta(d_tmpl.as<DeltaTask>(), d_dl_list, nd, d_rank.as<int32_t>(), LOOK,
+                                   xp.as<double>(), d_d.as<double>(), d_has.as<char>(), s), "amvm deltas");
+      }
+      // (c) the estimator and a candidate P_k, on the device
+      check(launch_amvm_estimate(A, theta, den, s), "amvm estimator");
+      check(launch_amvm_stop(A, theta, 0, s), "amvm marking");
+      check(hipMemcpyAsync(ctl, d_ctl.p, sizeof(AmvmCtl), hipMemcpyDeviceToHost, s), "amvm marking");
+      check(hipMemcpyAsync(sf, d_sf.p, sizeof(int32_t) * nf, hipMemcpyDeviceToHost, s), "amvm marking");
+      if (na > 0) {
+        check(hipMemcpyAsync(rk, d_rank.p, sizeof(int32_t) * nf, hipMemcpyDeviceToHost, s), "amvm ACA");
+        check(hipMemcpyAsync(sp, d_stop.p, sizeof(int32_t) * nf, hipMemcpyDeviceToHost, s), "amvm ACA");
+      }
+      check(hipStreamSynchronize(s), "amvm marking");
+      for (int q = 0; q < na; q++) {
+        const int32_t f = aca_list[q].x;
+        if (sp[f] == 5) throw HipError{HMAT_EINVAL, "non-finite matrix entries (overlapping or duplicate triangles?)"};
+        k_avail[f] = rk[f];
+        done[f] = sp[f] != 6;
       }
       std::fill(adv.begin(), adv.end(), 0);
-      // (b) look-ahead contributions d_b of every block with a window
-      std::vector<DeltaTask> dts;
-      std::fill(has_d.begin(), has_d.end(), 0);
-      for (size_t f = 0; f < nf; f++) {
-        const int32_t r1 = std::min(r_use[f] + LOOK, k_avail[f]);
-        if (r1 <= r_use[f]) continue;
-        has_d[f] = 1;
-        const double* pan = panels.as<double>() + poff[f];
-        dts.push_back(DeltaTask{pan, pan + M[f] * kcap[f], doff[f], (int32_t)M[f], (int32_t)Nn[f], r_use[f], r1,
-                                3 * P.cl[P.blk[h->far_blocks[f]].s].off, 0});
-      }
-      // (c) the estimator: row errors summed on the device in canonical block
-      // order (the same additions, in the same order, as a loop over blocks)
-      if (!dts.empty()) {
-        DevBuf d_t;
-        upload(d_t, dts, s, "amvm deltas");
-        upload(d_has, has_d, s, "amvm deltas");
-        check(launch_lowrank_delta(d_t.as<DeltaTask>(), (int)dts.size(), xp.as<double>(), d_d.as<double>(), s),
-              "amvm deltas");
-        check(launch_amvm_rowsum(d_rptr.as<int64_t>(), d_rblk.as<int32_t>(), d_has.as<char>(),
-                                 d_doff.as<int64_t>(), d_r0.as<int64_t>(), d_d.as<double>(), N, d_e.as<double>(), s),
-              "amvm rows");
-        check(hipMemcpyAsync(e_host.p, d_e.p, sizeof(double) * N, hipMemcpyDeviceToHost, s), "amvm rows");
-        check(hipMemcpyAsync(d, d_d.p, sizeof(double) * dtot, hipMemcpyDeviceToHost, s), "amvm deltas");
-        check(hipStreamSynchronize(s), "amvm deltas");
-        std::memcpy(e.data(), e_host.p, sizeof(double) * N);
-      } else {
-        std::fill(e.begin(), e.end(), 0.0);
-      }
-      double g2 = 0.0, bh2 = 0.0;
-      for (int64_t i = 0; i < N; i++) {
-        g2 += e[i] * e[i];
-        bh2 += (b[i] + e[i]) * (b[i] + e[i]);
-      }
-      gamma = std::sqrt(g2);
-      if (dts.empty() || gamma <= tol * std::sqrt(bh2) || rounds >= max_rounds) break;
-      // (d) marking along rows of decreasing error
-      const double tau = (1.0 - theta) * gamma / std::sqrt((double)P.csp * (double)N * (double)N);
-      // rows come off a max-heap keyed by (|e_i| descending, i ascending): the
-      // order of a stable sort by |e_i|, but marking usually stops after a
-      // small share of the rows, so only those are ordered
-      const auto lower = [&](int64_t a, int64_t c) {
-        const double fa = std::fabs(e[a]), fc = std::fabs(e[c]);
-        return fa < fc || (fa == fc && a > c);
-      };
-      std::iota(rows.begin(), rows.end(), (int64_t)0);
-      std::make_heap(rows.begin(), rows.end(), lower);
-      auto heap_end = rows.end();
-      rest = e;
-      double rn2 = g2;
-      std::fill(marked.begin(), marked.end(), 0);
-      std::vector<int32_t> Pk;
+      // no block with a window (all exhausted) gives gamma = 0 and stops here
+      gamma = std::sqrt(ctl->g2);
+      if (gamma <= tol * std::sqrt(ctl->bh2) || rounds >= max_rounds) break;
+      // (d) the first candidate whose exact rest norm reaches the goal
       const double goal = (1.0 - theta) * gamma;
-      while (heap_end != rows.begin()) {
-        std::pop_heap(rows.begin(), heap_end, lower);
-        --heap_end;
-        const int64_t i = *heap_end;
-        bool added = false;
-        for (int64_t q = rptr[i]; q < rptr[i + 1]; q++) {
-          const int32_t f = rblk[q];
-          if (marked[f] || !has_d[f]) continue;
-          if (std::fabs(d[doff[f] + (i - R0[f])]) < tau) continue;
-          marked[f] = 1;
-          Pk.push_back(f);
-          for (int64_t r = 0; r < M[f]; r++) {
-            double& v = rest[R0[f] + r];
-            rn2 -= v * v;
-            v -= d[doff[f] + r];
-            rn2 += v * v;
-          }
-          added = true;
-        }
-        if (added && rn2 <= goal * goal * (1.0 + 1e-6)) {
-          double ex = 0.0;  // confirm with the exact norm
-          for (int64_t j = 0; j < N; j++) ex += rest[j] * rest[j];
-          rn2 = ex;
-          if (std::sqrt(ex) <= goal) break;
-        }
+      while (ctl->p_cand < ctl->ncand && !(std::sqrt(ctl->exact2) <= goal)) {
+        check(launch_amvm_stop(A, theta, ctl->p_cand, s), "amvm marking");
+        check(hipMemcpyAsync(ctl, d_ctl.p, sizeof(AmvmCtl), hipMemcpyDeviceToHost, s), "amvm marking");
+        check(hipStreamSynchronize(s), "amvm marking");
       }
-      if (Pk.empty()) break;
+      const int32_t pk = ctl->p_cand;
+      if (pk == 0) break;
       // (e) A_{k+1} = A^_k on the marked blocks
-      for (int32_t f : Pk) {
-        for (int64_t r = 0; r < M[f]; r++) b[R0[f] + r] += d[doff[f] + r];
+      check(launch_amvm_update(A, pk, s), "amvm update");
+      for (int32_t j = 0; j < pk; j++) {
+        const int32_t f = sf[j];
         r_use[f] = std::min(r_use[f] + LOOK, k_avail[f]);
         adv[f] = 1;
       }
-      marked_total += (int64_t)Pk.size();
+      marked_total += pk;
       rounds++;
     }
     // result in the caller's order
-    std::vector<double> yh(N);
-    for (int32_t p = 0; p < P.nt; p++)
-      for (int a = 0; a < 3; a++) yh[3 * (int64_t)P.order[p] + a] = b[3 * (int64_t)p + a];
-    check(hipMemcpyAsync(y, yh.data(), sizeof(double) * N, hipMemcpyHostToDevice, s), "amvm result");
+    check(launch_amvm_out(d_b.as<double>(), h->d_order.as<int32_t>(), N, y, s), "amvm result");
     check(hipStreamSynchronize(s), "amvm result");
     if (ranks_out) {
       for (size_t q = 0; q < P.blk.size(); q++) ranks_out[q] = -1;

@@ -123,6 +123,42 @@ struct DeltaTask {
   int32_t m, n, r0, r1, col0, pad;
 };
 
+// Adaptive multiplication, marking on the device: a leaf cluster's rows
+// [r0, r0 + nr) all lie in the same admissible blocks, listed (canonical
+// order) at lblk[b0 .. b0 + nb).
+struct AmvmLeaf {
+  int64_t r0, b0;
+  int32_t nr, nb;
+};
+
+// Scalars of one round, kept on the device.
+struct AmvmCtl {
+  double g2;      // gamma_k^2 = ||b^_k - b_k||^2
+  double bh2;     // ||b^_k||^2
+  double exact2;  // ||rest||^2 after the first p_cand candidate blocks
+  int32_t ncand;  // blocks that would join P_k if marking ran through every row
+  int32_t p_cand; // candidate size of P_k
+};
+
+// Device arrays of the marking (see amvm.hip). n rows, nf admissible blocks;
+// rkey/rval and bkey hold the sort input followed by its output.
+struct AmvmDev {
+  const AmvmLeaf* leaves;
+  int n_leaves, nbmax, nf, pad;
+  int64_t n;
+  const int32_t* lblk;
+  const char* has_d;
+  const int64_t *dbase, *doff, *r0;  // dbase = doff - r0: entry of row i at dbase + i
+  const int32_t* mrow;
+  const double* d;
+  double *b, *e, *part, *dsq, *restv, *ds;
+  uint64_t *rkey, *bkey;
+  int32_t *rval, *rank, *sf, *pos, *lsorted, *lcount;
+  AmvmCtl* ctl;
+  void* sort_tmp;
+  size_t sort_bytes;
+};
+
 // One contiguous copy of `words` 32-bit words (the panels and pivots of a
 // block carried into the next, larger ACA pass).
 struct SpanCopy {

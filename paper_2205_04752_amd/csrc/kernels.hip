@@ -4,9 +4,9 @@
 //   K2  k_aca             ACA with partial pivoting on every admissible block
 //                         (Sec. 2.2, Algorithm 1), one workgroup per block
 //   --  k_compact         final low-rank arena (first k columns of the panels)
-//   --  k_dense_mv, k_lowrank_delta, k_amvm_rowsum   the adaptive multiplication (Algorithm 2)
 //   --  GMRES helpers     dots, column updates, norms
-// (K3, the product, is in product.hip.)
+// (K3, the product, is in product.hip; the adaptive multiplication's kernels
+// are in amvm.hip.)
 //
 // Entries: A[3i+a, 3j+b] = int_{tau_j} S_ab(c_i - y) ds_y with Kelvin's tensor
 // S = c1 delta/|r| + c2 r r^T/|r|^3 (Sec. 4.1), collocation at the centroid c_i
@@ -963,91 +963,6 @@ __global__ __launch_bounds__(256) void k_compact(const CopyTask* __restrict__ ta
     const int64_t c = e / T.n, i = e - c * T.n;
     T.dstV[c * T.ldv + T.fpv + i] = T.srcV[e];
   }
-}
-
-// Adaptive multiplication (Algorithm 2): dense-block products and the
-// rank-two look-ahead contributions (A^_k - A_k)_b x_s, one workgroup per block.
-__global__ __launch_bounds__(256) void k_dense_mv(const DenseMvTask* __restrict__ tasks,
-                                                  const double* __restrict__ D,
-                                                  const double* __restrict__ xp,
-                                                  double* __restrict__ out) {
-  const DenseMvTask T = tasks[blockIdx.x];
-  const double* __restrict__ Db = D + T.d_off;
-  const double* __restrict__ xs = xp + T.col0;
-  for (int r = threadIdx.x; r < T.m; r += blockDim.x) {
-    double acc = 0.0;
-    for (int c = 0; c < T.n; c++) acc += Db[(size_t)c * T.m + r] * xs[c];
-    out[T.out + r] = acc;
-  }
-}
-
-__global__ __launch_bounds__(256) void k_lowrank_delta(const DeltaTask* __restrict__ tasks,
-                                                       const double* __restrict__ xp,
-                                                       double* __restrict__ out) {
-  __shared__ double red[2][256 / WAVE];
-  const DeltaTask T = tasks[blockIdx.x];
-  const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
-  const int nl = T.r1 - T.r0;  // 1 or 2
-  double w[2] = {0.0, 0.0};
-  for (int l = 0; l < nl; l++) {
-    const double* __restrict__ v = T.V + (size_t)(T.r0 + l) * T.n;
-    double a = 0.0;
-    for (int c = tid; c < T.n; c += blockDim.x) a += v[c] * xp[T.col0 + c];
-    a = wave_sum(a);
-    if (lane == 0) red[l][wv] = a;
-  }
-  __syncthreads();
-  for (int l = 0; l < nl; l++) {
-    double t = 0.0;
-    for (int q = 0; q < 256 / WAVE; q++) t += red[l][q];
-    w[l] = t;
-  }
-  for (int r = tid; r < T.m; r += blockDim.x) {
-    double acc = 0.0;
-    for (int l = 0; l < nl; l++) acc += T.U[(size_t)(T.r0 + l) * T.m + r] * w[l];
-    out[T.out + r] = acc;
-  }
-}
-
-hipError_t launch_dense_mv(const DenseMvTask* tasks, int n, const double* D, const double* xp,
-                           double* out, hipStream_t s) {
-  if (n > 0) hipLaunchKernelGGL(k_dense_mv, dim3(n), dim3(256), 0, s, tasks, D, xp, out);
-  return hipGetLastError();
-}
-
-// The estimator's row errors: e[i] = sum over the admissible blocks containing
-// row i (rblk[rptr[i] .. rptr[i+1]), canonical order) of their look-ahead
-// contribution to that row, d[doff[f] + i - r0[f]]; blocks without a
-// look-ahead window (has_d[f] == 0) add nothing.
-__global__ __launch_bounds__(256) void k_amvm_rowsum(const int64_t* __restrict__ rptr,
-                                                     const int32_t* __restrict__ rblk,
-                                                     const char* __restrict__ has_d,
-                                                     const int64_t* __restrict__ doff,
-                                                     const int64_t* __restrict__ r0,
-                                                     const double* __restrict__ d, int64_t n,
-                                                     double* __restrict__ e) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  double sum = 0.0;
-  for (int64_t q = rptr[i]; q < rptr[i + 1]; q++) {
-    const int32_t f = rblk[q];
-    if (has_d[f]) sum += d[doff[f] + (i - r0[f])];
-  }
-  e[i] = sum;
-}
-
-hipError_t launch_amvm_rowsum(const int64_t* rptr, const int32_t* rblk, const char* has_d, const int64_t* doff,
-                              const int64_t* r0, const double* d, int64_t n, double* e, hipStream_t s) {
-  if (n > 0)
-    hipLaunchKernelGGL(k_amvm_rowsum, dim3(blocks_for(n, 256)), dim3(256), 0, s, rptr, rblk, has_d, doff, r0, d,
-                       n, e);
-  return hipGetLastError();
-}
-
-hipError_t launch_lowrank_delta(const DeltaTask* tasks, int n, const double* xp, double* out,
-                                hipStream_t s) {
-  if (n > 0) hipLaunchKernelGGL(k_lowrank_delta, dim3(n), dim3(256), 0, s, tasks, xp, out);
-  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
