@@ -339,9 +339,10 @@ def bench_serve(args):
     torus meshes of 1k-80k DOF, eps in {1e-3, 1e-5, 1e-7}, half of them one
     GMRES(50) solve to FP64 relative residual 1e-8, half 1-32 products; seed 4).
     Compared: the plain form -- one request at a time, FP64 -- and the serving
-    form -- `slots` requests in flight, FP32 storage with FP64 refinement for
-    solves. Each is run with every request arriving at once (capacity) and
-    with Poisson arrivals at 0.5x, 1.0x and 1.2x the plain form's capacity (latency)."""
+    form -- `slots` requests in flight, FP32-only builds for products, FP32
+    copies with FP64 refinement for solves. Each is run with every request
+    arriving at once (capacity) and, unless --serve-capacity-only, with
+    Poisson arrivals at 0.5x, 1.0x and 1.2x the plain form's capacity (latency)."""
     import threading
 
     import numpy as np
@@ -352,11 +353,13 @@ def bench_serve(args):
     reqs = W.serving_requests(args.requests, seed=4)
     print(f"serve: generating {len(reqs)} meshes", file=sys.stderr, flush=True)
     data = []
-    for r in reqs:
+    for k, r in enumerate(reqs):
         V, T = W.mesh_of(r)
         N = 3 * len(T)
         x = W.smooth_rhs(V, T, seed=r["vseed"]) if r["solve"] else W.random_x(N, r["m"], seed=r["vseed"])
         data.append((V, T, x))
+        if (k + 1) % 250 == 0:
+            print(f"serve:   {k + 1} meshes", file=sys.stderr, flush=True)
     n_solves = sum(r["solve"] for r in reqs)
     dof = [3 * len(d[1]) for d in data]
 
@@ -389,6 +392,8 @@ def bench_serve(args):
             while ids[k] is None:
                 time.sleep(0.0005)
             infos.append(srv.wait(ids[k])[1])
+            if (k + 1) % 250 == 0:
+                print(f"serve:   {k + 1} done", file=sys.stderr, flush=True)
         th.join()
         srv.close()
         lat = np.array([i["t_done_ms"] - i["t_submit_ms"] for i in infos])
@@ -409,7 +414,7 @@ def bench_serve(args):
     serve_cap = run(args.slots, 1, None, f"serving, {args.slots} slots, mixed precision, all at once")
     cap = plain_cap["requests_per_s"]
     loads = {}
-    for f in (0.5, 1.0, 1.2):
+    for f in (() if args.serve_capacity_only else (0.5, 1.0, 1.2)):
         loads[f"{f}x"] = {"plain": run(1, 0, f * cap, f"plain FP64 at {f}x capacity"),
                           "serving": run(args.slots, 1, f * cap, f"serving at {f}x capacity")}
     out = {
@@ -503,6 +508,8 @@ def main():
                     default="icosphere-L5")
     ap.add_argument("--requests", type=int, default=120, help="serve: requests per run")
     ap.add_argument("--slots", type=int, default=4, help="serve: concurrent requests")
+    ap.add_argument("--serve-capacity-only", action="store_true",
+                    help="serve: only the all-at-once runs (no Poisson arrivals)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=5.0)
     ap.add_argument("--solves", type=int, default=4, help="GMRES solves per step")

@@ -511,9 +511,11 @@ enum { HMAT_REQ_MATVEC = 0, HMAT_REQ_SOLVE = 1 };
 typedef struct {
   int32_t kind;       /* HMAT_REQ_MATVEC: nvec products; HMAT_REQ_SOLVE: one solve */
   int32_t nvec;       /* products: 1..64 vectors (ignored for a solve) */
-  int32_t precision;  /* 0: FP64 throughout; 1: FP32 copies of the entries (products
-                         read them; solves refine FP32 inner GMRES with FP64 residuals,
-                         hmat_solve_ir with inner_tol 1e-6) */
+  int32_t precision;  /* 0: FP64 throughout; 1: reduced precision. Products build an
+                         FP32-only handle (hmat_build_ex precision 1: FP32 ACA at
+                         eps >= 1e-5) and read it. Solves build in FP64, add FP32
+                         copies and refine FP32 inner GMRES with FP64 residuals of
+                         the FP64 operator (hmat_solve_ir, inner_tol 1e-6) */
   int32_t restart;    /* solve: GMRES restart length (1..1024) */
   double E, nu, eps;  /* material (Sec. 1) and ACA accuracy, as for hmat_build */
   double tol;         /* solve: FP64 relative residual to reach */

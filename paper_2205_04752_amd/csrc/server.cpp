@@ -50,7 +50,8 @@ struct Request {
 // Device bytes a request is assumed to need before it is built: the stored
 // matrix at 25% of dense FP64 (a bound above what the admissibility and
 // accuracy settings of this library produce at these sizes; 9-11% measured
-// at 61k DOF, eps 1e-5 .. 1e-6), an FP32 copy if asked for, the ACA panels
+// at 61k DOF, eps 1e-5 .. 1e-6), FP32 entries if asked for (copies beside the
+// FP64 ones, or the conversion peak of an FP32-only build), the ACA panels
 // (the first pass's and the later passes', each capped by the worker's ACA
 // budget), and vectors.
 int64_t estimate_bytes(const Request& r, int64_t aca_cap) {
@@ -131,13 +132,24 @@ void hmat_server::execute(Request& r, hipStream_t s) {
     return true;
   };
   if (cancelled()) return;
-  hmat_status st = hmat_build(&mesh, r.q.E, r.q.nu, eta, leaf, r.q.eps, s, &h);
+  // reduced-precision products need only the FP32 entries; a solve keeps the
+  // FP64 operator for the refinement residual
+  const bool f32_only = r.q.precision == 1 && r.q.kind != HMAT_REQ_SOLVE;
+  hmat_status st;
+  if (f32_only) {
+    hmat_opts o{};
+    o.precision = 1;
+    o.aca_stop_factor = 1.0;
+    st = hmat_build_ex(&mesh, r.q.E, r.q.nu, eta, leaf, r.q.eps, &o, s, &h);
+  } else {
+    st = hmat_build(&mesh, r.q.E, r.q.nu, eta, leaf, r.q.eps, s, &h);
+  }
   if (st != HMAT_OK) return fail_req(st);
   if (cancelled()) return;
   hmat_stats hs{};
   hmat_info(h, &hs);
   r.res.build_ms = hs.t_build_ms;
-  if (r.q.precision == 1) {
+  if (r.q.precision == 1 && !f32_only) {
     st = hmat_set_precision(h, 1, s);
     if (st != HMAT_OK) return fail_req(st);
     hmat_info(h, &hs);
