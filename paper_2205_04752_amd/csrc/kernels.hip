@@ -575,7 +575,11 @@ __device__ __forceinline__ void row3f(const DevGeo& g, float x0, float x1, float
   const int nt = g.nt;
   e0 = e1 = e2 = 0.0f;
   float diag = 0.0f;
-#pragma unroll
+  // not unrolled: the FP32 ACA kernels then fit three waves per SIMD (about
+  // 164 VGPRs against 210; 9.4 -> 8.1 ms of ACA at icosphere L5, eps 1e-5).
+  // The FP64 form stays unrolled: there the rolled loop saves too few
+  // registers for a third wave and loses the overlap of the seven divisions.
+#pragma unroll 1
   for (int k = 0; k < 7; k++) {
     const float r0 = x0 - g.q32[(0 * 7 + k) * (size_t)nt + q];
     const float r1 = x1 - g.q32[(1 * 7 + k) * (size_t)nt + q];
