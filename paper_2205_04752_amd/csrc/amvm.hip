@@ -52,19 +52,21 @@ __global__ __launch_bounds__(256) void k_dense_mv(const DenseMvTask* __restrict_
   }
 }
 
-// d_b for the listed blocks (list[j] = {block, r0}): the window [r0, r1) with
-// r1 = min(r0 + look, crosses available); a block without one gets
-// has_d = 0. tmpl[f] holds the block's panels, output offset, sizes and
-// column offset (its r0, r1 are unused).
+// d_b for the listed blocks, list[j] = {block, r0, r1, source}: the window
+// [r0, r1) with r1 = min(r0 + look, crosses available), the count read from
+// avail (source 0) or avail2 (source 1), or r1 as given (source 2); a block
+// without a window gets has_d = 0. tmpl[f] holds the block's panels, output
+// offset, sizes and column offset (its r0, r1 are unused).
 __global__ __launch_bounds__(256) void k_lowrank_delta(const DeltaTask* __restrict__ tmpl,
-                                                       const int2* __restrict__ list,
-                                                       const int32_t* __restrict__ avail, int look,
+                                                       const int4* __restrict__ list,
+                                                       const int32_t* __restrict__ avail,
+                                                       const int32_t* __restrict__ avail2, int look,
                                                        const double* __restrict__ xp,
                                                        double* __restrict__ out, char* __restrict__ has_d) {
   __shared__ double red[2][256 / WAVE];
-  const int2 L = list[blockIdx.x];
+  const int4 L = list[blockIdx.x];
   const DeltaTask T = tmpl[L.x];
-  const int r0 = L.y, r1 = min(r0 + look, avail[L.x]);
+  const int r0 = L.y, r1 = L.w == 2 ? L.z : min(r0 + look, (L.w == 1 ? avail2 : avail)[L.x]);
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
   if (tid == 0) has_d[L.x] = r1 > r0 ? 1 : 0;
   if (r1 <= r0) return;
@@ -204,32 +206,39 @@ __global__ void k_amvm_rowrank(const int32_t* __restrict__ sorted_rows, int64_t 
   if (j < n) rank[sorted_rows[j]] = (int32_t)j;
 }
 
-// Block keys, one wave per admissible block: (first qualifying row rank) << 32
-// | block, or (N << 32) | block when no row qualifies or the block has no window.
-// tau = (1 - theta) gamma_k / den with den = sqrt(c_sp M N).
-__global__ __launch_bounds__(1024) void k_amvm_keys(const AmvmCtl* __restrict__ ctl, double theta, double den,
-                                                    const char* __restrict__ has_d,
-                                                    const int64_t* __restrict__ doff,
-                                                    const int64_t* __restrict__ r0,
-                                                    const int32_t* __restrict__ mrow,
-                                                    const double* __restrict__ d,
-                                                    const int32_t* __restrict__ rank, int nf, int64_t n,
-                                                    uint64_t* __restrict__ key) {
-  const int lane = threadIdx.x & (WAVE - 1);
-  const int nw = gridDim.x * (blockDim.x / WAVE);
-  const double tau = (1.0 - theta) * sqrt(ctl->g2) / den;
-  for (int f = blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE; f < nf; f += nw) {
-    int best = INT_MAX;
-    if (has_d[f]) {
-      const double* __restrict__ df = d + doff[f];
-      const int32_t* __restrict__ rk = rank + r0[f];
-      const int m = mrow[f];
-      for (int r = lane; r < m; r += WAVE)
-        if (fabs(df[r]) >= tau) best = min(best, rk[r]);
-      best = wave_min(best);
+// Block keys, one workgroup per admissible block: (first qualifying row rank)
+// << 32 | block, or (N << 32) | block when no row qualifies or the block has
+// no window. tau = (1 - theta) gamma_k / den with den = sqrt(c_sp M N). (A
+// workgroup, not a wave: the largest blocks have thousands of rows.)
+__global__ __launch_bounds__(256) void k_amvm_keys(const AmvmCtl* __restrict__ ctl, double theta, double den,
+                                                   const char* __restrict__ has_d,
+                                                   const int64_t* __restrict__ doff,
+                                                   const int64_t* __restrict__ r0,
+                                                   const int32_t* __restrict__ mrow,
+                                                   const double* __restrict__ d,
+                                                   const int32_t* __restrict__ rank, int64_t n,
+                                                   uint64_t* __restrict__ key) {
+  __shared__ int red[256 / WAVE];
+  const int f = blockIdx.x;
+  int best = INT_MAX;
+  if (has_d[f]) {
+    const double tau = (1.0 - theta) * sqrt(ctl->g2) / den;
+    const double* __restrict__ df = d + doff[f];
+    const int32_t* __restrict__ rk = rank + r0[f];
+    const int m = mrow[f];
+#pragma unroll 4
+    for (int r = threadIdx.x; r < m; r += 256) {
+      const double v = df[r];
+      const int q = rk[r];
+      if (fabs(v) >= tau) best = min(best, q);
     }
-    if (lane == 0) key[f] = ((uint64_t)(best == INT_MAX ? n : best) << 32) | (uint32_t)f;
+    best = wave_min(best);
+    if ((threadIdx.x & (WAVE - 1)) == 0) red[threadIdx.x / WAVE] = best;
+    __syncthreads();
+    if (threadIdx.x == 0)
+      for (int w = 1; w < 256 / WAVE; w++) best = min(best, red[w]);
   }
+  if (threadIdx.x == 0) key[f] = ((uint64_t)(best == INT_MAX ? n : best) << 32) | (uint32_t)f;
 }
 
 // Sorted keys -> order of the candidate blocks (sf), join positions (pos,
@@ -305,26 +314,25 @@ __global__ __launch_bounds__(LEAF_T) void k_amvm_rest(const AmvmLeaf* __restrict
   }
 }
 
-// ds[j] = sum over the rows of the j-th candidate block of its dsq (one wave
-// per candidate, fixed order).
-__global__ __launch_bounds__(1024) void k_amvm_blockdelta(const AmvmCtl* __restrict__ ctl,
-                                                          const int32_t* __restrict__ sf,
-                                                          const int64_t* __restrict__ doff,
-                                                          const int32_t* __restrict__ mrow,
-                                                          const double* __restrict__ dsq, int nf,
-                                                          double* __restrict__ ds) {
-  const int lane = threadIdx.x & (WAVE - 1);
-  const int nw = gridDim.x * (blockDim.x / WAVE);
-  const int nc = min(nf, ctl->ncand);
-  for (int j = blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE; j < nc; j += nw) {
-    const int32_t f = sf[j];
-    const double* __restrict__ v = dsq + doff[f];
-    const int m = mrow[f];
-    double s = 0.0;
-    for (int r = lane; r < m; r += WAVE) s += v[r];
-    s = wave_sum(s);
-    if (lane == 0) ds[j] = s;
-  }
+// ds[j] = sum over the rows of the j-th candidate block of its dsq (one
+// workgroup per candidate, fixed order).
+__global__ __launch_bounds__(256) void k_amvm_blockdelta(const AmvmCtl* __restrict__ ctl,
+                                                         const int32_t* __restrict__ sf,
+                                                         const int64_t* __restrict__ doff,
+                                                         const int32_t* __restrict__ mrow,
+                                                         const double* __restrict__ dsq,
+                                                         double* __restrict__ ds) {
+  __shared__ double red[256 / WAVE];
+  const int j = blockIdx.x;
+  if (j >= ctl->ncand) return;
+  const int32_t f = sf[j];
+  const double* __restrict__ v = dsq + doff[f];
+  const int m = mrow[f];
+  double s = 0.0;
+#pragma unroll 4
+  for (int r = threadIdx.x; r < m; r += 256) s += v[r];
+  s = block_sum<256>(s, red);
+  if (threadIdx.x == 0) ds[j] = s;
 }
 
 // First row boundary p > from (p = number of blocks in P_k, a boundary when
@@ -459,9 +467,11 @@ hipError_t launch_dense_mv(const DenseMvTask* tasks, int n, const double* D, con
   return hipGetLastError();
 }
 
-hipError_t launch_lowrank_delta(const DeltaTask* tmpl, const int2* list, int n, const int32_t* avail, int look,
-                                const double* xp, double* out, char* has_d, hipStream_t s) {
-  if (n > 0) hipLaunchKernelGGL(k_lowrank_delta, dim3(n), dim3(256), 0, s, tmpl, list, avail, look, xp, out, has_d);
+hipError_t launch_lowrank_delta(const DeltaTask* tmpl, const int4* list, int n, const int32_t* avail,
+                                const int32_t* avail2, int look, const double* xp, double* out, char* has_d,
+                                hipStream_t s) {
+  if (n > 0)
+    hipLaunchKernelGGL(k_lowrank_delta, dim3(n), dim3(256), 0, s, tmpl, list, avail, avail2, look, xp, out, has_d);
   return hipGetLastError();
 }
 
@@ -490,9 +500,9 @@ hipError_t launch_amvm_estimate(const AmvmDev& A, double theta, double den, hipS
                                                       (int)A.n, 0, 64, s);
   if (err != hipSuccess) return err;
   hipLaunchKernelGGL(k_amvm_rowrank, dim3(blocks_for(A.n, 256)), dim3(256), 0, s, A.rval + A.n, A.n, A.rank);
-  const unsigned gw = std::min(blocks_for(A.nf, 1024 / WAVE), 1024u);
-  hipLaunchKernelGGL(k_amvm_keys, dim3(gw), dim3(1024), 0, s, A.ctl, theta, den, A.has_d,
-                     A.doff, A.r0, A.mrow, A.d, A.rank, A.nf, A.n, A.bkey);
+  if (A.nf == 0) return hipGetLastError();  // no admissible blocks: nothing to mark
+  hipLaunchKernelGGL(k_amvm_keys, dim3(A.nf), dim3(256), 0, s, A.ctl, theta, den, A.has_d, A.doff, A.r0, A.mrow,
+                     A.d, A.rank, A.n, A.bkey);
   int bits = 32;
   while (bits < 64 && ((int64_t)1 << (bits - 32)) <= A.n) bits++;
   tb = A.sort_bytes;
@@ -502,12 +512,12 @@ hipError_t launch_amvm_estimate(const AmvmDev& A, double theta, double den, hipS
   hipLaunchKernelGGL(k_amvm_pos, dim3(blocks_for(A.nf, 256)), dim3(256), 0, s, skey, A.nf, A.n, A.sf, A.pos, A.ctl);
   hipLaunchKernelGGL(k_amvm_rest, dim3(nl), dim3(LEAF_T), amvm_leaf_shmem(A.nbmax), s, A.leaves, A.lblk, A.pos,
                      A.dbase, A.d, A.e, A.lsorted, A.lcount, A.dsq, A.restv);
-  hipLaunchKernelGGL(k_amvm_blockdelta, dim3(gw), dim3(1024), 0, s, A.ctl, A.sf, A.doff,
-                     A.mrow, A.dsq, A.nf, A.ds);
+  hipLaunchKernelGGL(k_amvm_blockdelta, dim3(A.nf), dim3(256), 0, s, A.ctl, A.sf, A.doff, A.mrow, A.dsq, A.ds);
   return hipGetLastError();
 }
 
 hipError_t launch_amvm_stop(const AmvmDev& A, double theta, int32_t from, hipStream_t s) {
+  if (A.nf == 0) return hipGetLastError();  // ncand = p_cand = 0 from k_amvm_norms
   hipLaunchKernelGGL(k_amvm_scan, dim3(1), dim3(SCAN_T), 0, s, A.ctl, A.ds, A.bkey + A.nf, theta, from);
   hipLaunchKernelGGL(k_amvm_exact, dim3(A.n_leaves), dim3(LEAF_T), 8 * (size_t)std::max(A.nbmax, 1), s, A.ctl,
                      A.leaves, A.lsorted, A.lcount, A.pos, A.dbase, A.e, A.restv, A.part);

@@ -50,8 +50,8 @@ hipError_t launch_residual(const double*, int64_t, double*, hipStream_t);
 hipError_t launch_fill(double*, int64_t, double, hipStream_t);
 hipError_t launch_axpy(double, const double*, int64_t, double*, hipStream_t);
 hipError_t launch_dense_mv(const DenseMvTask*, int, const double*, const double*, double*, hipStream_t);
-hipError_t launch_lowrank_delta(const DeltaTask*, const int2*, int, const int32_t*, int, const double*, double*,
-                                char*, hipStream_t);
+hipError_t launch_lowrank_delta(const DeltaTask*, const int4*, int, const int32_t*, const int32_t*, int,
+                                const double*, double*, char*, hipStream_t);
 hipError_t launch_amvm_aca_tasks(const AcaTask*, const int2*, int, AcaTask*, hipStream_t);
 size_t amvm_sort_bytes(int64_t, int);
 size_t amvm_leaf_shmem(int);
@@ -2129,69 +2129,134 @@ hmat_status amvm_impl(const hmat_mesh* mesh, double E, double nu, double eta, in
       tmpl[f] = DeltaTask{pan, pan + M[f] * kcap[f], doff[f], (int32_t)M[f], (int32_t)Nn[f], 0, 0,
                           3 * P.cl[P.blk[h->far_blocks[f]].s].off, 0};
     }
-    DevBuf d_base, d_tmpl, d_lists, d_tasks;
+    DevBuf d_base, d_tmpl, d_aca_list, d_dl_list, d_pf_list, d_tasks, d_pf_tasks, d_rank_pf, d_stop_pf, d_ratio_pf;
     upload(d_base, base, s, "amvm ACA");
     upload(d_tmpl, tmpl, s, "amvm deltas");
-    d_lists.alloc(sizeof(int2) * 2 * nz(nf), "amvm ACA");
+    d_aca_list.alloc(sizeof(int2) * nz(nf), "amvm ACA");
+    d_pf_list.alloc(sizeof(int2) * nz(nf), "amvm ACA");
+    d_dl_list.alloc(sizeof(int4) * nz(nf), "amvm deltas");
     d_tasks.alloc(sizeof(AcaTask) * nz(nf), "amvm ACA");
+    d_pf_tasks.alloc(sizeof(AcaTask) * nz(nf), "amvm ACA");
+    d_rank_pf.alloc(sizeof(int32_t) * nz(nf), "amvm ACA");
+    d_stop_pf.alloc(sizeof(int32_t) * nz(nf), "amvm ACA");
+    d_ratio_pf.alloc(sizeof(double) * nz(nf), "amvm ACA");
     check(hipMemsetAsync(d_has.p, 0, d_has.bytes, s), "amvm deltas");
+    check(hipMemsetAsync(d_lcount.p, 0, d_lcount.bytes, s), "amvm leaves");
     // pinned host buffers: the round's lists (ACA: block, pause; deltas:
-    // block, first column) and what a round reads back (scalars, order of
-    // the candidate blocks, ACA ranks and stop codes)
+    // block, first column, last column, its source), what a round reads back
+    // (scalars, order of the candidate blocks, ACA ranks and stop codes), and
+    // the run-ahead launch's list and results
     struct Pinned {
       void* p = nullptr;
       ~Pinned() {
         if (p) (void)hipHostFree(p);
       }
-    } up, back;
-    check(hipHostMalloc(&up.p, sizeof(int2) * 2 * nz(nf)), "amvm host buffer");
+    } up, back, pf_up, pf_back;
+    check(hipHostMalloc(&up.p, (sizeof(int2) + sizeof(int4)) * nz(nf)), "amvm host buffer");
     check(hipHostMalloc(&back.p, sizeof(AmvmCtl) + 3 * sizeof(int32_t) * nz(nf)), "amvm host buffer");
+    check(hipHostMalloc(&pf_up.p, sizeof(int2) * nz(nf)), "amvm host buffer");
+    check(hipHostMalloc(&pf_back.p, 2 * sizeof(int32_t) * nz(nf)), "amvm host buffer");
     int2* const aca_list = (int2*)up.p;
-    int2* const dl_list = aca_list + nz(nf);
+    int4* const dl_list = (int4*)(aca_list + nz(nf));
     AmvmCtl* const ctl = (AmvmCtl*)back.p;
     int32_t* const sf = (int32_t*)(ctl + 1);
     int32_t* const rk = sf + nz(nf);
     int32_t* const sp = rk + nz(nf);
-    // the one-wave ACA launch runs beside the wide one, on a second stream
+    int2* const pf_list = (int2*)pf_up.p;
+    int32_t* const rk_pf = (int32_t*)pf_back.p;
+    int32_t* const sp_pf = rk_pf + nz(nf);
+    // The one-wave ACA launch runs beside the wide one on a second stream.
+    // The largest blocks, whose two steps would outlast the rest of a round,
+    // run ahead on a third: each round takes them to two windows past their
+    // used rank (r_use + 4), so the window a round uses was computed during
+    // the round before. The crosses are the same; only when they are computed
+    // differs (a block's last run-ahead window may stay unused).
     struct Side {
-      hipStream_t s2 = nullptr;
-      hipEvent_t fork = nullptr, join = nullptr;
+      hipStream_t s2 = nullptr, s3 = nullptr;
+      hipEvent_t fork = nullptr, join = nullptr, pf_done = nullptr;
       ~Side() {
+        if (s3) (void)hipStreamSynchronize(s3);
+        if (s2) (void)hipStreamSynchronize(s2);
         if (fork) (void)hipEventDestroy(fork);
         if (join) (void)hipEventDestroy(join);
+        if (pf_done) (void)hipEventDestroy(pf_done);
         if (s2) (void)hipStreamDestroy(s2);
+        if (s3) (void)hipStreamDestroy(s3);
       }
     } side;
     check(hipStreamCreateWithFlags(&side.s2, hipStreamNonBlocking), "amvm stream");
+    check(hipStreamCreateWithFlags(&side.s3, hipStreamNonBlocking), "amvm stream");
     check(hipEventCreateWithFlags(&side.fork, hipEventDisableTiming), "amvm stream");
     check(hipEventCreateWithFlags(&side.join, hipEventDisableTiming), "amvm stream");
+    check(hipEventCreateWithFlags(&side.pf_done, hipEventDisableTiming), "amvm stream");
     const double den = std::sqrt((double)P.csp * (double)N * (double)N);
     std::vector<char> adv(nf, 1);  // blocks marked in the last round (all at first)
-    std::vector<char> big(nf);
-    for (size_t f = 0; f < nf; f++) big[f] = std::max(base[f].t_len, base[f].s_len) > ACA_SMALL_TRI;
+    std::vector<char> big(nf), ahead(nf);
+    for (size_t f = 0; f < nf; f++) {
+      big[f] = std::max(base[f].t_len, base[f].s_len) > ACA_SMALL_TRI;
+      ahead[f] = big[f] && M[f] + Nn[f] >= AMVM_AHEAD_ROWS;
+    }
+    int n_pf = 0;
+    bool pf_pending = false;
+    const auto collect_ahead = [&]() {  // results of the last run-ahead launch
+      if (!pf_pending) return;
+      check(hipEventSynchronize(side.pf_done), "amvm stream");
+      for (int q = 0; q < n_pf; q++) {
+        const int32_t f = pf_list[q].x;
+        if (sp_pf[f] == 5) throw HipError{HMAT_EINVAL, "non-finite matrix entries (overlapping or duplicate triangles?)"};
+        k_avail[f] = rk_pf[f];
+        done[f] = sp_pf[f] != 6;
+      }
+      pf_pending = false;
+    };
     int rounds = 0;
     int64_t marked_total = 0;
     double gamma = 0.0;
     for (;;) {
+      collect_ahead();
       // (a) resume ACA up to r_use + LOOK on the marked blocks that need it
-      // (wide launch first in the list), and (b) recompute d_b for the marked
-      // blocks: the windows of the others have not moved
+      // (wide launch first in the list), the run-ahead blocks up to
+      // r_use + 2 LOOK, and (b) recompute d_b for the marked blocks: the
+      // windows of the others have not moved
       int na = 0, nd = 0;
       for (int pass = 0; pass < 2; pass++)
         for (size_t f = 0; f < nf; f++) {
-          if (!adv[f] || done[f] || big[f] != (pass == 0)) continue;
+          if (!adv[f] || done[f] || ahead[f] || big[f] != (pass == 0)) continue;
           const int32_t target = std::min(r_use[f] + LOOK, kcap[f]);
           if (k_avail[f] < target) aca_list[na++] = int2{(int)f, target};
         }
       int n_big = 0;
       while (n_big < na && big[aca_list[n_big].x]) n_big++;
-      for (size_t f = 0; f < nf; f++)
-        if (adv[f]) dl_list[nd++] = int2{(int)f, r_use[f]};
-      int2* const d_aca_list = d_lists.as<int2>();
-      int2* const d_dl_list = d_aca_list + nz(nf);
+      n_pf = 0;
+      for (size_t f = 0; f < nf; f++) {
+        if (!ahead[f] || done[f]) continue;
+        const int32_t target = std::min(r_use[f] + 2 * LOOK, kcap[f]);
+        if (k_avail[f] < target) pf_list[n_pf++] = int2{(int)f, target};
+      }
+      const bool first = rounds == 0 && !pf_pending;  // the first window of a run-ahead block is computed now
+      for (size_t f = 0; f < nf; f++) {
+        if (!adv[f]) continue;
+        if (ahead[f] && !first)  // its window is known: computed during the last round
+          dl_list[nd++] = int4{(int)f, r_use[f], std::min(r_use[f] + LOOK, k_avail[f]), 2};
+        else
+          dl_list[nd++] = int4{(int)f, r_use[f], 0, ahead[f] ? 1 : 0};
+      }
+      if (n_pf > 0) {
+        check(hipMemcpyAsync(d_pf_list.p, pf_list, sizeof(int2) * n_pf, hipMemcpyHostToDevice, side.s3), "amvm ACA");
+        check(launch_amvm_aca_tasks(d_base.as<AcaTask>(), d_pf_list.as<int2>(), n_pf, d_pf_tasks.as<AcaTask>(),
+                                    side.s3), "amvm ACA");
+        check(launch_aca(h->G, d_pf_tasks.as<AcaTask>(), n_pf, n_pf, shmem[0], shmem[1], true, false,
+                         d_rank_pf.as<int32_t>(), d_stop_pf.as<int32_t>(), d_ratio_pf.as<double>(), side.s3),
+              "amvm ACA");
+        check(hipMemcpyAsync(rk_pf, d_rank_pf.p, sizeof(int32_t) * nf, hipMemcpyDeviceToHost, side.s3), "amvm ACA");
+        check(hipMemcpyAsync(sp_pf, d_stop_pf.p, sizeof(int32_t) * nf, hipMemcpyDeviceToHost, side.s3), "amvm ACA");
+        check(hipEventRecord(side.pf_done, side.s3), "amvm stream");
+        pf_pending = true;
+      }
       if (na > 0) {
-        check(hipMemcpyAsync(d_aca_list, aca_list, sizeof(int2) * na, hipMemcpyHostToDevice, s), "amvm ACA");
-        check(launch_amvm_aca_tasks(d_base.as<AcaTask>(), d_aca_list, na, d_tasks.as<AcaTask>(), s), "amvm ACA");
+        check(hipMemcpyAsync(d_aca_list.p, aca_list, sizeof(int2) * na, hipMemcpyHostToDevice, s), "amvm ACA");
+        check(launch_amvm_aca_tasks(d_base.as<AcaTask>(), d_aca_list.as<int2>(), na, d_tasks.as<AcaTask>(), s),
+              "amvm ACA");
         check(hipEventRecord(side.fork, s), "amvm stream");
         check(hipStreamWaitEvent(side.s2, side.fork, 0), "amvm stream");
         check(launch_aca(h->G, d_tasks.as<AcaTask>(), n_big, n_big, shmem[0], shmem[1], true, false,
@@ -2201,10 +2266,12 @@ hmat_status amvm_impl(const hmat_mesh* mesh, double E, double nu, double eta, in
         check(hipEventRecord(side.join, side.s2), "amvm stream");
         check(hipStreamWaitEvent(s, side.join, 0), "amvm stream");
       }
+      if (first && n_pf > 0) check(hipStreamWaitEvent(s, side.pf_done, 0), "amvm stream");
       if (nd > 0) {
-        check(hipMemcpyAsync(d_dl_list, dl_list, sizeof(int2) * nd, hipMemcpyHostToDevice, s), "amvm deltas");
-        check(launch_lowrank_delta(d_tmpl.as<DeltaTask>(), d_dl_list, nd, d_rank.as<int32_t>(), LOOK,
-                                   xp.as<double>(), d_d.as<double>(), d_has.as<char>(), s), "amvm deltas");
+        check(hipMemcpyAsync(d_dl_list.p, dl_list, sizeof(int4) * nd, hipMemcpyHostToDevice, s), "amvm deltas");
+        check(launch_lowrank_delta(d_tmpl.as<DeltaTask>(), d_dl_list.as<int4>(), nd, d_rank.as<int32_t>(),
+                                   d_rank_pf.as<int32_t>(), LOOK, xp.as<double>(), d_d.as<double>(), d_has.as<char>(),
+                                   s), "amvm deltas");
       }
       // (c) the estimator and a candidate P_k, on the device
       check(launch_amvm_estimate(A, theta, den, s), "amvm estimator");
@@ -2222,6 +2289,7 @@ hmat_status amvm_impl(const hmat_mesh* mesh, double E, double nu, double eta, in
         k_avail[f] = rk[f];
         done[f] = sp[f] != 6;
       }
+      if (first) collect_ahead();  // the run-ahead blocks' first windows were waited for
       std::fill(adv.begin(), adv.end(), 0);
       // no block with a window (all exhausted) gives gamma = 0 and stops here
       gamma = std::sqrt(ctl->g2);
@@ -2245,6 +2313,7 @@ hmat_status amvm_impl(const hmat_mesh* mesh, double E, double nu, double eta, in
       marked_total += pk;
       rounds++;
     }
+    collect_ahead();
     // result in the caller's order
     check(launch_amvm_out(d_b.as<double>(), h->d_order.as<int32_t>(), N, y, s), "amvm result");
     check(hipStreamSynchronize(s), "amvm result");

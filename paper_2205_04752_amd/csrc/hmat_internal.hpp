@@ -48,6 +48,9 @@ constexpr int SEG_START_ALIGN = 16;  // doubles (128 bytes)
 constexpr int ACA_SMALL_TRI = 64;
 constexpr int ACA_NWV = 4;       // waves of the ACA workgroup for large blocks
 constexpr int ACA_WIDE_NWV = 8;  // the same in launches of few blocks (one per CU)
+// Adaptive multiplication: admissible blocks with m + n >= AMVM_AHEAD_ROWS run
+// their look-ahead ACA steps one round ahead, on a stream of their own.
+constexpr int64_t AMVM_AHEAD_ROWS = 2048;
 // A block with m + n <= ACA_STAGE_MAX keeps the newest row and column of
 // its remainder in LDS as well as in the panels, so the pivot searches,
 // the normalisation and the norm update of a step read them from LDS.

@@ -70,3 +70,15 @@ def test_amvm_zero_vector():
                             leaf=16)
     assert float(torch.abs(y).max()) == 0.0 and info["rounds"] == 0
     assert np.all(ranks[ranks >= 0] == 0)
+
+
+def test_amvm_without_admissible_blocks():
+    """A mesh whose partition has no admissible block (one leaf cluster): the
+    adaptive product is the dense product after zero rounds."""
+    H = _H()
+    V, T = W.icosahedron()
+    x = W.random_x(3 * len(T), 1, seed=2)[0]
+    y, info, ranks = H.amvm(V, T, torch.from_numpy(x).cuda(), leaf=32)
+    assert info["rounds"] == 0 and info["gamma"] == 0.0 and np.all(ranks == -1)
+    bt = O.Mesh(V, T, 1.0, 0.3).brute_matvec(x[None, :])[0]
+    assert np.linalg.norm(y.cpu().numpy() - bt) <= 1e-13 * np.linalg.norm(bt)
