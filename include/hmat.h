@@ -477,13 +477,17 @@ hmat_status hmat_tune(hmat_t h, int32_t nrhs, int32_t reps, void* hip_stream, hm
  *            it, or full rank, is exhausted and contributes no further.
  *   ranks    HOST, n_blocks entries or NULL: final rank of each admissible
  *            block in canonical block order (-1 for dense blocks).
- * Synchronises the stream. Errors: as hmat_build; HMAT_EINVAL for theta,
- * tol, kmax, max_rounds or NULL/aliased vectors.
+ * Marking runs on the device; a round reads back a few scalars and the join
+ * order. Work runs on the given stream and on two internal ones (created and
+ * destroyed by the call). Synchronises the stream. Errors: as hmat_build;
+ * HMAT_EINVAL for theta, tol, kmax, max_rounds or NULL/aliased vectors.
  */
 typedef struct {
   int32_t rounds;          /* rounds of Algorithm 2 that marked blocks */
   int32_t exhausted;       /* admissible blocks out of ACA steps (rank min(m,n), rows used, or kmax) */
-  int64_t aca_steps;       /* sum over admissible blocks of the ACA steps taken (incl. look-ahead) */
+  int64_t aca_steps;       /* sum over admissible blocks of the ACA steps taken (incl. look-ahead;
+                              the largest blocks, m + n >= 2048, compute their look-ahead one
+                              round early, so up to two of their steps may stay unused) */
   int64_t marked_total;    /* sum over rounds of |P_k| */
   double gamma;            /* final estimator gamma_k */
   double time_ms;

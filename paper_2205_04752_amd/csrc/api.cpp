@@ -1981,16 +1981,23 @@ hmat_status amvm_impl(const hmat_mesh* mesh, double E, double nu, double eta, in
       doff[f] = dtot;
       dtot += M[f];
     }
-    DevBuf panels, pivs, states, zbits, d_rank, d_stop, d_ratio, d_d;
+    DevBuf panels, pivs, states, zbits, d_back, d_ratio, d_d;
     panels.alloc(sizeof(double) * std::max<int64_t>(ptot, 1), "amvm panels");
     pivs.alloc(sizeof(int32_t) * std::max<int64_t>(vtot, 1), "amvm panels");
     states.alloc(sizeof(AcaState) * std::max<size_t>(nf, 1), "amvm state");
     zbits.alloc(sizeof(uint32_t) * std::max<int64_t>(ztot, 1), "amvm state");
     check(hipMemsetAsync(states.p, 0, states.bytes, s), "amvm state");
     check(hipMemsetAsync(zbits.p, 0, zbits.bytes, s), "amvm state");
-    d_rank.alloc(sizeof(int32_t) * std::max<size_t>(nf, 1), "amvm state");
-    d_stop.alloc(sizeof(int32_t) * std::max<size_t>(nf, 1), "amvm state");
-    d_ratio.alloc(sizeof(double) * std::max<size_t>(nf, 1), "amvm state");
+    // what a round reads back, in one piece: the round's scalars, the order
+    // of the candidate blocks, and the ACA ranks and stop codes
+    const size_t nf1 = std::max<size_t>(nf, 1);
+    const size_t back_bytes = sizeof(AmvmCtl) + 3 * sizeof(int32_t) * nf1;
+    d_back.alloc(back_bytes, "amvm state");
+    AmvmCtl* const dv_ctl = d_back.as<AmvmCtl>();
+    int32_t* const dv_sf = reinterpret_cast<int32_t*>(dv_ctl + 1);
+    int32_t* const dv_rank = dv_sf + nf1;
+    int32_t* const dv_stop = dv_rank + nf1;
+    d_ratio.alloc(sizeof(double) * nf1, "amvm state");
     d_d.alloc(sizeof(double) * std::max<int64_t>(dtot, 1), "amvm deltas");
     std::vector<AcaTask> base(nf);
     {
@@ -2066,7 +2073,7 @@ hmat_status amvm_impl(const hmat_mesh* mesh, double E, double nu, double eta, in
       mrow[f] = (int32_t)M[f];
     }
     DevBuf d_leaves, d_lblk, d_lsorted, d_lcount, d_has, d_dbase, d_doff, d_r0, d_mrow, d_dsq, d_restv, d_b, d_e,
-        d_rkey, d_rval, d_rrank, d_part, d_bkey, d_sf, d_pos, d_ds, d_ctl, d_sort;
+        d_rkey, d_rval, d_rrank, d_part, d_bkey, d_pos, d_ds, d_sort;
     upload(d_leaves, leaves, s, "amvm leaves");
     upload(d_lblk, lblk, s, "amvm leaves");
     upload(d_dbase, dbase, s, "amvm blocks");
@@ -2086,10 +2093,8 @@ hmat_status amvm_impl(const hmat_mesh* mesh, double E, double nu, double eta, in
     d_rrank.alloc(sizeof(int32_t) * nz(N), "amvm sort");
     d_part.alloc(sizeof(double) * 2 * nz(nl), "amvm sort");
     d_bkey.alloc(sizeof(uint64_t) * 2 * nz(nf), "amvm sort");
-    d_sf.alloc(sizeof(int32_t) * nz(nf), "amvm sort");
     d_pos.alloc(sizeof(int32_t) * nz(nf), "amvm sort");
     d_ds.alloc(sizeof(double) * nz(nf), "amvm sort");
-    d_ctl.alloc(sizeof(AmvmCtl), "amvm sort");
     const size_t sort_bytes = amvm_sort_bytes(N, (int)nf);
     d_sort.alloc(sort_bytes, "amvm sort");
     AmvmDev A{};
@@ -2115,11 +2120,11 @@ hmat_status amvm_impl(const hmat_mesh* mesh, double E, double nu, double eta, in
     A.bkey = d_bkey.as<uint64_t>();
     A.rval = d_rval.as<int32_t>();
     A.rank = d_rrank.as<int32_t>();
-    A.sf = d_sf.as<int32_t>();
+    A.sf = dv_sf;
     A.pos = d_pos.as<int32_t>();
     A.lsorted = d_lsorted.as<int32_t>();
     A.lcount = d_lcount.as<int32_t>();
-    A.ctl = d_ctl.as<AmvmCtl>();
+    A.ctl = dv_ctl;
     A.sort_tmp = d_sort.p;
     A.sort_bytes = sort_bytes;
     // per-block templates of the round's tasks, on the device
@@ -2153,7 +2158,7 @@ hmat_status amvm_impl(const hmat_mesh* mesh, double E, double nu, double eta, in
       }
     } up, back, pf_up, pf_back;
     check(hipHostMalloc(&up.p, (sizeof(int2) + sizeof(int4)) * nz(nf)), "amvm host buffer");
-    check(hipHostMalloc(&back.p, sizeof(AmvmCtl) + 3 * sizeof(int32_t) * nz(nf)), "amvm host buffer");
+    check(hipHostMalloc(&back.p, back_bytes), "amvm host buffer");
     check(hipHostMalloc(&pf_up.p, sizeof(int2) * nz(nf)), "amvm host buffer");
     check(hipHostMalloc(&pf_back.p, 2 * sizeof(int32_t) * nz(nf)), "amvm host buffer");
     int2* const aca_list = (int2*)up.p;
@@ -2260,28 +2265,23 @@ hmat_status amvm_impl(const hmat_mesh* mesh, double E, double nu, double eta, in
         check(hipEventRecord(side.fork, s), "amvm stream");
         check(hipStreamWaitEvent(side.s2, side.fork, 0), "amvm stream");
         check(launch_aca(h->G, d_tasks.as<AcaTask>(), n_big, n_big, shmem[0], shmem[1], true, false,
-                         d_rank.as<int32_t>(), d_stop.as<int32_t>(), d_ratio.as<double>(), s), "amvm ACA");
+                         dv_rank, dv_stop, d_ratio.as<double>(), s), "amvm ACA");
         check(launch_aca(h->G, d_tasks.as<AcaTask>() + n_big, na - n_big, 0, shmem[0], shmem[1], true, false,
-                         d_rank.as<int32_t>(), d_stop.as<int32_t>(), d_ratio.as<double>(), side.s2), "amvm ACA");
+                         dv_rank, dv_stop, d_ratio.as<double>(), side.s2), "amvm ACA");
         check(hipEventRecord(side.join, side.s2), "amvm stream");
         check(hipStreamWaitEvent(s, side.join, 0), "amvm stream");
       }
       if (first && n_pf > 0) check(hipStreamWaitEvent(s, side.pf_done, 0), "amvm stream");
       if (nd > 0) {
         check(hipMemcpyAsync(d_dl_list.p, dl_list, sizeof(int4) * nd, hipMemcpyHostToDevice, s), "amvm deltas");
-        check(launch_lowrank_delta(d_tmpl.as<DeltaTask>(), d_dl_list.as<int4>(), nd, d_rank.as<int32_t>(),
+        check(launch_lowrank_delta(d_tmpl.as<DeltaTask>(), d_dl_list.as<int4>(), nd, dv_rank,
                                    d_rank_pf.as<int32_t>(), LOOK, xp.as<double>(), d_d.as<double>(), d_has.as<char>(),
                                    s), "amvm deltas");
       }
       // (c) the estimator and a candidate P_k, on the device
       check(launch_amvm_estimate(A, theta, den, s), "amvm estimator");
       check(launch_amvm_stop(A, theta, 0, s), "amvm marking");
-      check(hipMemcpyAsync(ctl, d_ctl.p, sizeof(AmvmCtl), hipMemcpyDeviceToHost, s), "amvm marking");
-      check(hipMemcpyAsync(sf, d_sf.p, sizeof(int32_t) * nf, hipMemcpyDeviceToHost, s), "amvm marking");
-      if (na > 0) {
-        check(hipMemcpyAsync(rk, d_rank.p, sizeof(int32_t) * nf, hipMemcpyDeviceToHost, s), "amvm ACA");
-        check(hipMemcpyAsync(sp, d_stop.p, sizeof(int32_t) * nf, hipMemcpyDeviceToHost, s), "amvm ACA");
-      }
+      check(hipMemcpyAsync(back.p, d_back.p, back_bytes, hipMemcpyDeviceToHost, s), "amvm marking");
       check(hipStreamSynchronize(s), "amvm marking");
       for (int q = 0; q < na; q++) {
         const int32_t f = aca_list[q].x;
@@ -2298,7 +2298,7 @@ hmat_status amvm_impl(const hmat_mesh* mesh, double E, double nu, double eta, in
       const double goal = (1.0 - theta) * gamma;
       while (ctl->p_cand < ctl->ncand && !(std::sqrt(ctl->exact2) <= goal)) {
         check(launch_amvm_stop(A, theta, ctl->p_cand, s), "amvm marking");
-        check(hipMemcpyAsync(ctl, d_ctl.p, sizeof(AmvmCtl), hipMemcpyDeviceToHost, s), "amvm marking");
+        check(hipMemcpyAsync(ctl, dv_ctl, sizeof(AmvmCtl), hipMemcpyDeviceToHost, s), "amvm marking");
         check(hipStreamSynchronize(s), "amvm marking");
       }
       const int32_t pk = ctl->p_cand;
