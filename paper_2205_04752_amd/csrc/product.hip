@@ -70,7 +70,39 @@ __device__ __forceinline__ double2 ld2_nt(const T* p) {
 // Phase A item: z = V_b^T x_s for a group of <= 8 columns; one wave. Lanes
 // cover the aligned row window of V two rows at a time (16-byte loads of V and
 // of the gathered x; pad rows of V are zero); NR right-hand sides at once,
-// columns in sub-batches of CB.
+// columns in sub-batches of CB. mv_a_cols does NC columns [l0, l0 + NC), NC
+// known at compile time, so an item's last, partial sub-batch loads only its
+// own columns (0.637 -> 0.631 ms per product at icosphere L5).
+template <int NR, int NC, typename T>
+__device__ __forceinline__ void mv_a_cols(const MvA& I, int l0, const T* __restrict__ V,
+                                          const double* __restrict__ X, int64_t ldxp, int nr,
+                                          double* __restrict__ z, int64_t ldz, int lane) {
+  double acc[NC][NR];
+#pragma unroll
+  for (int c = 0; c < NC; c++)
+#pragma unroll
+    for (int r = 0; r < NR; r++) acc[c][r] = 0.0;
+  for (int i = 2 * lane; i < I.ld; i += TILE) {
+    double2 xv[NR], v[NC];
+#pragma unroll
+    for (int c = 0; c < NC; c++) v[c] = ld2_nt(V + (size_t)(l0 + c) * I.ld + i);
+#pragma unroll
+    for (int r = 0; r < NR; r++)
+      xv[r] = (r < nr) ? *reinterpret_cast<const double2*>(X + r * ldxp + i) : make_double2(0.0, 0.0);
+#pragma unroll
+    for (int c = 0; c < NC; c++)
+#pragma unroll
+      for (int r = 0; r < NR; r++) acc[c][r] += v[c].x * xv[r].x + v[c].y * xv[r].y;
+  }
+#pragma unroll
+  for (int c = 0; c < NC; c++)
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+      const double sum = wave_sum(acc[c][r]);
+      if (lane == 0 && r < nr) z[r * ldz + I.zoff + (l0 - I.l0) + c] = sum;
+    }
+}
+
 template <int NR, typename T>
 __device__ __forceinline__ void mv_a_item(const MvA& I, const T* __restrict__ far,
                                           const double* __restrict__ xp, int64_t ldxp, int nr,
@@ -81,34 +113,16 @@ __device__ __forceinline__ void mv_a_item(const MvA& I, const T* __restrict__ fa
   const double* __restrict__ X = xp + I.a0;
   for (int l0 = I.l0; l0 < I.l1; l0 += CB) {
     const int nc = min(CB, I.l1 - l0);
-    double acc[CB][NR];
-#pragma unroll
-    for (int c = 0; c < CB; c++)
-#pragma unroll
-      for (int r = 0; r < NR; r++) acc[c][r] = 0.0;
-    for (int i = 2 * lane; i < I.ld; i += TILE) {
-      double2 xv[NR], v[CB];
-#pragma unroll
-      for (int c = 0; c < CB; c++)  // columns past l1 re-read the last one (not accumulated)
-        v[c] = ld2_nt(V + (size_t)(l0 + min(c, nc - 1)) * I.ld + i);
-#pragma unroll
-      for (int r = 0; r < NR; r++)
-        xv[r] = (r < nr) ? *reinterpret_cast<const double2*>(X + r * ldxp + i) : make_double2(0.0, 0.0);
-#pragma unroll
-      for (int c = 0; c < CB; c++) {
-        if (c < nc) {
-#pragma unroll
-          for (int r = 0; r < NR; r++) acc[c][r] += v[c].x * xv[r].x + v[c].y * xv[r].y;
-        }
-      }
+    switch (nc) {  // wave-uniform
+      case 1: mv_a_cols<NR, 1, T>(I, l0, V, X, ldxp, nr, z, ldz, lane); break;
+      case 2: mv_a_cols<NR, (CB >= 2 ? 2 : 1), T>(I, l0, V, X, ldxp, nr, z, ldz, lane); break;
+      case 3: mv_a_cols<NR, (CB >= 3 ? 3 : 1), T>(I, l0, V, X, ldxp, nr, z, ldz, lane); break;
+      case 4: mv_a_cols<NR, (CB >= 4 ? 4 : 1), T>(I, l0, V, X, ldxp, nr, z, ldz, lane); break;
+      case 5: mv_a_cols<NR, (CB >= 5 ? 5 : 1), T>(I, l0, V, X, ldxp, nr, z, ldz, lane); break;
+      case 6: mv_a_cols<NR, (CB >= 6 ? 6 : 1), T>(I, l0, V, X, ldxp, nr, z, ldz, lane); break;
+      case 7: mv_a_cols<NR, (CB >= 7 ? 7 : 1), T>(I, l0, V, X, ldxp, nr, z, ldz, lane); break;
+      default: mv_a_cols<NR, CB, T>(I, l0, V, X, ldxp, nr, z, ldz, lane); break;
     }
-#pragma unroll
-    for (int c = 0; c < CB; c++)
-#pragma unroll
-      for (int r = 0; r < NR; r++) {
-        const double sum = wave_sum(acc[c][r]);
-        if (lane == 0 && c < nc && r < nr) z[r * ldz + I.zoff + (l0 - I.l0) + c] = sum;
-      }
   }
 }
 
@@ -120,9 +134,11 @@ __device__ __forceinline__ void mv_a_item(const MvA& I, const T* __restrict__ fa
 // shorter one (single right-hand side) puts p = 64 / (len/2) columns side by
 // side, so each load instruction covers p*len consecutive doubles; the p
 // column groups are then summed with a lane tree and moved to the owning
-// lanes. A segment's last partial batch re-reads in-segment data without
-// accumulating it, so every batch issues its UNR loads back to back (skipping
-// those loads instead saves 0.5% in FP64 and costs 70% with FP32 entries).
+// lanes. A tall segment's last partial batch issues its loads back to back
+// too, rounded up to 4, 8 or 12 columns (the extra loads re-read the last
+// column and are not added; a batch size fixed at compile time for each case
+// cut 0.6% in FP64 and 1% in FP32 against re-reading up to 15 columns, and
+// skipping the loads at run time cost 70% in FP32).
 // Writes part[chunk][r][128].
 // One short segment (len <= 64 rows, single right-hand side) of a phase-B
 // chunk: g = len/2 lanes per column, p = 64/g >= 2 columns per load. Lane l
@@ -179,6 +195,38 @@ __device__ __forceinline__ void mv_b_grouped(const MvSeg& S, const T* __restrict
   }
 }
 
+// One batch of B columns c .. c + B - 1 of a tall segment (B known at compile
+// time); columns at or past c + nc re-read column c1 - 1 and are not added.
+template <int NR, int B, typename T>
+__device__ __forceinline__ void mv_b_batch(const T* __restrict__ A, int len, int c, int nc, int c1,
+                                           const double* __restrict__ src, int64_t ld, int nr, bool act,
+                                           double (&acc0)[NR], double (&acc1)[NR]) {
+  typename Pair<T>::type a[B];
+#pragma unroll
+  for (int u = 0; u < B; u++) {
+    const int cu = (u < nc) ? c + u : c1 - 1;
+    a[u] = ldp_nt(A + (int64_t)cu * len);
+  }
+#pragma unroll
+  for (int u = 0; u < B; u++) {
+    a[u].x = act ? a[u].x : (T)0;
+    a[u].y = act ? a[u].y : (T)0;
+  }
+#pragma unroll
+  for (int r = 0; r < NR; r++) {
+    if (r < nr) {
+      const double* sr = src + r * ld + c;
+#pragma unroll
+      for (int u = 0; u < B; u++) {
+        if (u < nc) {
+          acc0[r] += (double)a[u].x * sr[u];
+          acc1[r] += (double)a[u].y * sr[u];
+        }
+      }
+    }
+  }
+}
+
 template <int NR, int UNR, typename T>
 __device__ __forceinline__ void mv_b_chunk(const MvChunk& C, int chunk,
                                            const MvSeg* __restrict__ segs,
@@ -204,46 +252,15 @@ __device__ __forceinline__ void mv_b_chunk(const MvChunk& C, int chunk,
     const T* __restrict__ A = stream + S.so + (Lc - S.row_lo) - (int64_t)S.c0 * len;
     const double* __restrict__ src = (S.far ? z : xp) + S.soff;
     const int64_t ld = S.far ? ldz : ldxp;
-    for (int c = S.c0; c < S.c1; c += UNR) {
-      const int nc = min(UNR, S.c1 - c);
-      typename Pair<T>::type a[UNR];
-#pragma unroll
-      for (int u = 0; u < UNR; u++) {
-        const int cu = (u < nc) ? c + u : S.c1 - 1;
-        a[u] = ldp_nt(A + (int64_t)cu * len);
-      }
-#pragma unroll
-      for (int u = 0; u < UNR; u++) {
-        a[u].x = act ? a[u].x : (T)0;
-        a[u].y = act ? a[u].y : (T)0;
-      }
-      if (nc == UNR) {
-#pragma unroll
-        for (int r = 0; r < NR; r++) {
-          if (r < nr) {
-            const double* sr = src + r * ld + c;
-#pragma unroll
-            for (int u = 0; u < UNR; u++) {
-              acc0[r] += (double)a[u].x * sr[u];
-              acc1[r] += (double)a[u].y * sr[u];
-            }
-          }
-        }
-      } else {
-#pragma unroll
-        for (int r = 0; r < NR; r++) {
-          if (r < nr) {
-            const double* sr = src + r * ld + c;
-#pragma unroll
-            for (int u = 0; u < UNR; u++) {
-              if (u < nc) {
-                acc0[r] += (double)a[u].x * sr[u];
-                acc1[r] += (double)a[u].y * sr[u];
-              }
-            }
-          }
-        }
-      }
+    int c = S.c0;
+    for (; c + UNR <= S.c1; c += UNR) mv_b_batch<NR, UNR, T>(A, len, c, UNR, S.c1, src, ld, nr, act, acc0, acc1);
+    const int nc = S.c1 - c;  // last, partial batch (nc < UNR): loads rounded up to four columns
+    if (nc > 0) {
+      static_assert(UNR == 8 || UNR == 16, "partial batches assume 8 or 16 columns per batch");
+      if (nc <= 4) mv_b_batch<NR, 4, T>(A, len, c, nc, S.c1, src, ld, nr, act, acc0, acc1);
+      else if (nc <= 8) mv_b_batch<NR, 8, T>(A, len, c, nc, S.c1, src, ld, nr, act, acc0, acc1);
+      else if (nc <= 12) mv_b_batch<NR, 12, T>(A, len, c, nc, S.c1, src, ld, nr, act, acc0, acc1);
+      else mv_b_batch<NR, 16, T>(A, len, c, nc, S.c1, src, ld, nr, act, acc0, acc1);
     }
   }
 #pragma unroll
