@@ -164,7 +164,8 @@ def bench_precision(args):
     the adjoint double-layer operator). FP64 build at eps = 1e-7; GMRES(50) to
     relative residual 1e-8 with FP64 entries, against FP32 copies of the entries
     with FP64 iterative refinement to the same FP64 residual. Value: solves/s of
-    the refinement form."""
+    the refinement form. Also an FP32-only build (half the memory), refined
+    against its own stored operator, with its FP64 residual reported."""
     import numpy as np
     import torch
     import workloads as W
@@ -211,6 +212,28 @@ def bench_precision(args):
         x, info = h.solve_ir(g, tol=1e-8, restart=50, maxit=20000, inner_precision=1, inner_tol=1e-6)
         s32.append(info)
         diff.append(float(torch.linalg.norm(x - x64) / torch.linalg.norm(x64)))
+    # FP32-only build (entries stored in FP32 only; ACA stays FP64 at this eps):
+    # refinement against the stored operator, FP64 residual checked with h
+    print("precision-box: FP32-only build", file=sys.stderr, flush=True)
+    h.set_precision(0)
+    h32 = H.HMatrix(V, T, wl["E"], wl["nu"], wl["eta"], wl["leaf"], wl["eps"], precision=1)
+    st32 = h32.info()
+    for _ in range(2):
+        h32.matvec(X, Y, precision=1)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(10):
+        h32.matvec(X, Y, precision=1)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    mv32o = e0.elapsed_time(e1) / 10
+    s32o, res64o, diffo = [], [], []
+    for g, x64 in zip(G, sol64):
+        x, info = h32.solve_ir(g, tol=1e-8, restart=50, maxit=20000, inner_precision=1, inner_tol=1e-6)
+        s32o.append(info)
+        res64o.append(float(torch.linalg.norm(g - h.matvec(x)) / torch.linalg.norm(g)))
+        diffo.append(float(torch.linalg.norm(x - x64) / torch.linalg.norm(x64)))
+    h32.close()
     h.close()
 
     def rate(infos):
@@ -232,6 +255,10 @@ def bench_precision(args):
                             "refinements": [i["refinements"] for i in s32],
                             "relres_fp64": [i["relres"] for i in s32], "matvec_ms": round(mv32, 4),
                             "rel_diff_to_fp64_solution": diff},
+        "fp32_only_build": {"build_ms": round(st32["t_build_ms"], 1), "device_bytes": st32["device_bytes"],
+                            "matvec_ms": round(mv32o, 4), "solves_per_s": rate(s32o),
+                            "relres_stored_operator": [i["relres"] for i in s32o],
+                            "relres_fp64_operator": res64o, "rel_diff_to_fp64_solution": diffo},
         "build_ms": round(st["t_build_ms"], 1), "build_aca_kernel_ms": round(st["t_aca_kernel_ms"], 1),
         "hmatrix": {"n_blocks": st["n_blocks"], "rank_mean": round(st["rank_mean"], 2),
                     "rank_max": st["rank_max"], "stored_scalars": stored,
