@@ -181,17 +181,56 @@ hmat_status hmat_build(const hmat_mesh* mesh, double E, double nu, double eta, i
  *                    return HMAT_ENOTSUP; hmat_set_factors too.
  *   aca_stop_factor  the constant c of the ACA stop test |u_k||v_k| <= c eps ||S_k||_F
  *                    (Algorithm 1 prints eps(1-beta)/(1+eps); default 1.0).
- * Errors: as hmat_build; HMAT_EINVAL for precision not 0 or 1, or
- * aca_stop_factor <= 0 or aca_stop_factor * eps >= 1.
+ *   aca_small_tri    ACA schedule: blocks with at most this many triangles on
+ *                    both sides run one wave each, larger ones a workgroup
+ *                    (0: the default, 64; else 1..1024).
+ *   aca_wide         ACA schedule: 1 runs the first pass's larger blocks in
+ *                    512-thread workgroups instead of 256 (0: default).
+ *                    The schedule changes only how the work is launched: the
+ *                    factors are the same unless a stop test lies within
+ *                    rounding of its threshold (||S_k|| is summed in another
+ *                    order). hmat_tune_aca times the candidates on a mesh.
+ * Errors: as hmat_build; HMAT_EINVAL for precision not 0 or 1,
+ * aca_stop_factor <= 0 or aca_stop_factor * eps >= 1, aca_small_tri outside
+ * 0..1024, or aca_wide not 0 or 1.
  */
 typedef struct {
   int32_t precision;
-  int32_t reserved; /* 0 */
+  int32_t aca_small_tri;
   double aca_stop_factor;
+  int32_t aca_wide;
+  int32_t reserved; /* 0 */
 } hmat_opts;
 
 hmat_status hmat_build_ex(const hmat_mesh* mesh, double E, double nu, double eta, int32_t leaf,
                           double eps, const hmat_opts* opts, void* hip_stream, hmat_t* out);
+
+/*
+ * hmat_tune_aca -- autotuner of the ACA launch schedule for one mesh and
+ * accuracy (the rank-bucket split of NEXT-1: which blocks run one wave each,
+ * and the workgroup size of the others). Builds the H-matrix `reps` times
+ * with each candidate schedule (aca_small_tri in {32, 64, 128} x aca_wide in
+ * {0, 1}), keeps the least ACA kernel time of each, and reports them; pass
+ * the best schedule to hmat_build_ex through hmat_opts. `opts` (may be NULL)
+ * supplies precision and aca_stop_factor; its schedule fields are ignored.
+ * The best schedule depends on the block sizes and ranks: at icosphere level
+ * 5, eps 1e-6, small_tri 128 cuts ACA 12%; on the 10 x 1 x 1 box at eps 1e-7
+ * the 512-thread first pass cuts it 24%.
+ * Synchronises the stream. Errors: as hmat_build_ex; HMAT_EINVAL for reps < 1
+ * or info NULL.
+ */
+typedef struct {
+  int32_t n_candidates;
+  int32_t best;             /* index of the fastest candidate */
+  int32_t small_tri[8];     /* candidate aca_small_tri */
+  int32_t wide[8];          /* candidate aca_wide */
+  double aca_ms[8];         /* least ACA kernel time over reps (ms) */
+  double best_ms;
+} hmat_aca_tune_info;
+
+hmat_status hmat_tune_aca(const hmat_mesh* mesh, double E, double nu, double eta, int32_t leaf,
+                          double eps, const hmat_opts* opts, int32_t reps, void* hip_stream,
+                          hmat_aca_tune_info* info);
 
 /*
  * hmat_build_batch -- hmat_build for n_bodies independent bodies in one

@@ -64,7 +64,13 @@ class _AmvmInfo(C.Structure):
 
 
 class _Opts(C.Structure):
-    _fields_ = [("precision", C.c_int32), ("reserved", C.c_int32), ("aca_stop_factor", C.c_double)]
+    _fields_ = [("precision", C.c_int32), ("aca_small_tri", C.c_int32), ("aca_stop_factor", C.c_double),
+                ("aca_wide", C.c_int32), ("reserved", C.c_int32)]
+
+
+class _AcaTuneInfo(C.Structure):
+    _fields_ = [("n_candidates", C.c_int32), ("best", C.c_int32), ("small_tri", C.c_int32 * 8),
+                ("wide", C.c_int32 * 8), ("aca_ms", C.c_double * 8), ("best_ms", C.c_double)]
 
 
 class _Request(C.Structure):
@@ -80,7 +86,7 @@ class _Result(C.Structure):
                 ("device_bytes", C.c_int64)]
 
 
-EXPORTS = ["hmat_build", "hmat_build_ex", "hmat_build_batch", "hmat_bodies", "hmat_matvec", "hmat_matvec_ex",
+EXPORTS = ["hmat_build", "hmat_build_ex", "hmat_tune_aca", "hmat_build_batch", "hmat_bodies", "hmat_matvec", "hmat_matvec_ex",
            "hmat_solve", "hmat_solve_noalloc", "hmat_solve_ir", "hmat_set_precision", "hmat_info", "hmat_free",
            "hmat_last_error", "hmat_plan", "hmat_block", "hmat_entries", "hmat_set_factors",
            "hmat_profile", "hmat_tune", "hmat_matvec_graph", "hmat_amvm", "hmat_server_create", "hmat_server_submit", "hmat_server_wait", "hmat_server_cancel", "hmat_server_status",
@@ -106,6 +112,8 @@ def lib():
     vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
     L.hmat_build.argtypes = [C.POINTER(_Mesh), dbl, dbl, dbl, i32, dbl, vp, C.POINTER(vp)]
     L.hmat_build_ex.argtypes = [C.POINTER(_Mesh), dbl, dbl, dbl, i32, dbl, C.POINTER(_Opts), vp, C.POINTER(vp)]
+    L.hmat_tune_aca.argtypes = [C.POINTER(_Mesh), dbl, dbl, dbl, i32, dbl, C.POINTER(_Opts), i32, vp,
+                                C.POINTER(_AcaTuneInfo)]
     L.hmat_build_batch.argtypes = [i32, vp, vp, vp, vp, dbl, i32, vp, C.POINTER(vp)]
     L.hmat_bodies.argtypes = [vp, C.POINTER(i32), vp]
     L.hmat_matvec.argtypes = [vp, i32, vp, i64, vp, i64, vp]
@@ -205,6 +213,21 @@ def plan(vertices, triangles, eta: float = 2.0, leaf: int = 32):
     return order, blocks
 
 
+def tune_aca(vertices, triangles, E=1.0, nu=0.3, eta=2.0, leaf=32, eps=1e-4, reps=2, precision=0,
+             aca_stop_factor=1.0, stream=None) -> dict:
+    """Time the ACA launch schedules on this mesh (hmat_tune_aca); returns the
+    candidates and the best as an aca_schedule for HMatrix."""
+    m, keep = _mesh(vertices, triangles)
+    o = _Opts(int(precision), 0, float(aca_stop_factor), 0, 0)
+    t = _AcaTuneInfo()
+    _check(lib().hmat_tune_aca(C.byref(m), float(E), float(nu), float(eta), int(leaf), float(eps), C.byref(o),
+                               int(reps), _stream(stream), C.byref(t)))
+    n = t.n_candidates
+    cands = [(t.small_tri[c], t.wide[c], t.aca_ms[c]) for c in range(n)]
+    return dict(candidates=cands, best=t.best, best_ms=t.best_ms,
+                aca_schedule=(t.small_tri[t.best], t.wide[t.best]))
+
+
 def amvm(vertices, triangles, x, E=1.0, nu=0.3, eta=2.0, leaf=32, theta=0.5, tol=1e-6,
          max_rounds=1000, kmax=128, stream=None):
     """Adaptive matrix-vector multiplication (hmat_amvm): returns (y, info, ranks)
@@ -228,16 +251,18 @@ class HMatrix:
     """Device-resident H-matrix of the Kelvin single-layer collocation matrix."""
 
     def __init__(self, vertices, triangles, E=1.0, nu=0.3, eta=2.0, leaf=32, eps=1e-4,
-                 stream=None, precision: int = 0, aca_stop_factor: float = 1.0):
+                 stream=None, precision: int = 0, aca_stop_factor: float = 1.0, aca_schedule=None):
         """precision 1 stores the entries in FP32 only (hmat_build_ex);
-        aca_stop_factor is the constant of the ACA stop test."""
+        aca_stop_factor is the constant of the ACA stop test; aca_schedule is
+        (aca_small_tri, aca_wide), e.g. from tune_aca."""
         m, keep = _mesh(vertices, triangles)
         h = C.c_void_p()
-        if precision == 0 and aca_stop_factor == 1.0:
+        small, wide = aca_schedule if aca_schedule is not None else (0, 0)
+        if precision == 0 and aca_stop_factor == 1.0 and aca_schedule is None:
             _check(lib().hmat_build(C.byref(m), float(E), float(nu), float(eta), int(leaf),
                                     float(eps), _stream(stream), C.byref(h)))
         else:
-            o = _Opts(int(precision), 0, float(aca_stop_factor))
+            o = _Opts(int(precision), int(small), float(aca_stop_factor), int(wide), 0)
             _check(lib().hmat_build_ex(C.byref(m), float(E), float(nu), float(eta), int(leaf),
                                        float(eps), C.byref(o), _stream(stream), C.byref(h)))
         self._h = h

@@ -633,6 +633,8 @@ struct hmat {
   bool fp32_only = false;    // entries stored in FP32 only (hmat_build_ex precision 1)
   bool fp32_aca = false;     // ACA in FP32 (FP32 builds with eps >= 1e-5)
   double stop_factor = 1.0;  // ACA stop test |u||v| <= stop_factor eps ||S||
+  int32_t aca_small_tri = ACA_SMALL_TRI;  // ACA schedule: one wave per block up to this size
+  bool aca_wide = false;                  // ACA schedule: 512-thread first pass
   // product plan
   DevBuf d_seg;
   // Work lists: [0] for single right-hand sides (8-column phase-A items,
@@ -1102,7 +1104,7 @@ void run_aca_pass(hmat* h, const std::vector<int32_t>& fidx, CapFn cap, PanelFn 
   // blocks for the 256-thread kernel first, then the one-wave ones
   auto big = [&](int32_t f) {
     const BlockRec& B = P.blk[h->far_blocks[f]];
-    return std::max(P.cl[B.t].len, P.cl[B.s].len) > ACA_SMALL_TRI;
+    return std::max(P.cl[B.t].len, P.cl[B.s].len) > h->aca_small_tri;
   };
   const int n_big = (int)(std::stable_partition(ord.begin(), ord.end(), big) - ord.begin());
   const int esize = h->fp32_aca ? 4 : 8;  // bytes per panel entry
@@ -1333,7 +1335,34 @@ void setup_dense(hmat* h, const std::vector<BodyIn>& in, double eta, int32_t lea
 struct BuildOpts {
   int precision = 0;         // 1: store the entries in FP32 only
   double stop_factor = 1.0;  // constant of the ACA stop test
+  int32_t small_tri = ACA_SMALL_TRI;  // ACA schedule (see hmat_opts)
+  bool wide = false;
 };
+
+hmat_status parse_opts(const hmat_opts* opts, double eps, BuildOpts& o, std::string& err) {
+  if (!opts) return HMAT_OK;
+  if (opts->precision != 0 && opts->precision != 1) {
+    err = "precision must be 0 (FP64) or 1 (FP32)";
+    return HMAT_EINVAL;
+  }
+  if (!(opts->aca_stop_factor > 0.0) || !(opts->aca_stop_factor * eps < 1.0)) {
+    err = "aca_stop_factor must be > 0 with aca_stop_factor * eps < 1";
+    return HMAT_EINVAL;
+  }
+  if (opts->aca_small_tri < 0 || opts->aca_small_tri > 1024) {
+    err = "aca_small_tri must lie in 0..1024";
+    return HMAT_EINVAL;
+  }
+  if (opts->aca_wide != 0 && opts->aca_wide != 1) {
+    err = "aca_wide must be 0 or 1";
+    return HMAT_EINVAL;
+  }
+  o.precision = opts->precision;
+  o.stop_factor = opts->aca_stop_factor;
+  o.small_tri = opts->aca_small_tri > 0 ? opts->aca_small_tri : ACA_SMALL_TRI;
+  o.wide = opts->aca_wide == 1;
+  return HMAT_OK;
+}
 
 hmat_status build_impl(const std::vector<BodyIn>& in, double eta, int32_t leaf, hipStream_t s,
                        hmat** out, const BuildOpts& opt = BuildOpts{}) {
@@ -1351,6 +1380,8 @@ hmat_status build_impl(const std::vector<BodyIn>& in, double eta, int32_t leaf, 
     h->leaf = leaf;
     h->fp32_only = opt.precision == 1;
     h->stop_factor = opt.stop_factor;
+    h->aca_small_tri = opt.small_tri;
+    h->aca_wide = opt.wide;
     // FP32 arithmetic resolves ACA remainders down to about 1e-6 of a block
     double eps_min = 1.0;
     for (const BodyIn& b : in) eps_min = std::min(eps_min, b.eps * opt.stop_factor);
@@ -1430,7 +1461,7 @@ hmat_status build_impl(const std::vector<BodyIn>& in, double eta, int32_t leaf, 
       h->piv_bufs.emplace_back();
       run_aca_pass(h, grp, cap1, [&](size_t b) { return static_cast<void*>(panels1.get(b)); }, h->piv_bufs.back(), d_rank,
                    d_stop, d_ratio, panel_ptr, states, zbits, zoff, [](const std::vector<AcaTask>&) {},
-                   false, s);
+                   h->aca_wide, s);
       h->aca_passes = std::max(h->aca_passes, 1);
       auto fetch = [&]() {
         check(hipMemcpyAsync(h->rank.data() + f0, d_rank.as<int32_t>() + f0, sizeof(int32_t) * (f1 - f0),
@@ -2406,20 +2437,59 @@ hmat_status hmat_build_ex(const hmat_mesh* mesh, double E, double nu, double eta
   if (!out) return fail(HMAT_EINVAL, "out is NULL");
   *out = nullptr;
   BuildOpts o;
-  if (opts) {
-    if (opts->precision != 0 && opts->precision != 1) return fail(HMAT_EINVAL, "precision must be 0 (FP64) or 1 (FP32)");
-    if (!(opts->aca_stop_factor > 0.0) || !(opts->aca_stop_factor * eps < 1.0))
-      return fail(HMAT_EINVAL, "aca_stop_factor must be > 0 with aca_stop_factor * eps < 1");
-    o.precision = opts->precision;
-    o.stop_factor = opts->aca_stop_factor;
-  }
   std::string err;
+  if (parse_opts(opts, eps, o, err) != HMAT_OK) return fail(HMAT_EINVAL, err);
   hmat_status st = validate_params(E, nu, eta, leaf, eps, err);
   if (st != HMAT_OK) return fail(st, err);
   st = validate_mesh(mesh, err);
   if (st != HMAT_OK) return fail(st, err);
   g_err.clear();
   return build_impl({BodyIn{mesh, E, nu, eps}}, eta, leaf, (hipStream_t)hip_stream, out, o);
+}
+
+hmat_status hmat_tune_aca(const hmat_mesh* mesh, double E, double nu, double eta, int32_t leaf, double eps,
+                          const hmat_opts* opts, int32_t reps, void* hip_stream, hmat_aca_tune_info* info) {
+  if (!info) return fail(HMAT_EINVAL, "info is NULL");
+  if (reps < 1) return fail(HMAT_EINVAL, "reps must be >= 1");
+  BuildOpts base;
+  std::string err;
+  if (opts) {
+    hmat_opts o = *opts;
+    o.aca_small_tri = 0;
+    o.aca_wide = 0;
+    if (parse_opts(&o, eps, base, err) != HMAT_OK) return fail(HMAT_EINVAL, err);
+  }
+  hmat_status st = validate_params(E, nu, eta, leaf, eps, err);
+  if (st != HMAT_OK) return fail(st, err);
+  st = validate_mesh(mesh, err);
+  if (st != HMAT_OK) return fail(st, err);
+  g_err.clear();
+  *info = hmat_aca_tune_info{};
+  int n = 0;
+  for (int32_t small : {32, 64, 128})
+    for (int32_t wide : {0, 1}) {
+      BuildOpts o = base;
+      o.small_tri = small;
+      o.wide = wide == 1;
+      double best = INFINITY;
+      for (int r = 0; r < reps; r++) {
+        hmat* h = nullptr;
+        st = build_impl({BodyIn{mesh, E, nu, eps}}, eta, leaf, (hipStream_t)hip_stream, &h, o);
+        if (st != HMAT_OK) return st;
+        best = std::min(best, h->st.t_aca_kernel_ms);
+        hmat_free(h);
+      }
+      info->small_tri[n] = small;
+      info->wide[n] = wide;
+      info->aca_ms[n] = best;
+      if (n == 0 || best < info->best_ms) {
+        info->best = n;
+        info->best_ms = best;
+      }
+      n++;
+    }
+  info->n_candidates = n;
+  return HMAT_OK;
 }
 
 hmat_status hmat_build_batch(int32_t n_bodies, const hmat_mesh* meshes, const double* E,

@@ -92,6 +92,20 @@ def test_build_validation_before_device_work():
         assert h.value is None and L.hmat_last_error().decode()
     o = H._Opts(0, 0, 1.0)
     assert L.hmat_build_ex(C.byref(m), 1.0, 0.5, 2.0, 32, 1e-4, C.byref(o), None, C.byref(h)) == H.HMAT_EINVAL
+    # ACA schedule fields
+    for small, wide in ((-1, 0), (1025, 0), (64, 2), (64, -1)):
+        o = H._Opts(0, small, 1.0, wide, 0)
+        assert L.hmat_build_ex(C.byref(m), 1.0, 0.3, 2.0, 32, 1e-4, C.byref(o), None,
+                               C.byref(h)) == H.HMAT_EINVAL, (small, wide)
+        assert "aca_" in L.hmat_last_error().decode()
+    # the schedule autotuner validates before building anything
+    t = H._AcaTuneInfo()
+    assert L.hmat_tune_aca(C.byref(m), 1.0, 0.3, 2.0, 32, 1e-4, None, 0, None, C.byref(t)) == H.HMAT_EINVAL
+    assert L.hmat_tune_aca(C.byref(m), 1.0, 0.3, 2.0, 32, 1e-4, None, 1, None, None) == H.HMAT_EINVAL
+    assert L.hmat_tune_aca(None, 1.0, 0.3, 2.0, 32, 1e-4, None, 1, None, C.byref(t)) == H.HMAT_EINVAL
+    assert L.hmat_tune_aca(C.byref(m), 1.0, 0.6, 2.0, 32, 1e-4, None, 1, None, C.byref(t)) == H.HMAT_EINVAL
+    o = H._Opts(3, 0, 1.0, 0, 0)
+    assert L.hmat_tune_aca(C.byref(m), 1.0, 0.3, 2.0, 32, 1e-4, C.byref(o), 1, None, C.byref(t)) == H.HMAT_EINVAL
     assert L.hmat_build(C.byref(m), 1.0, 0.3, 2.0, 32, 1e-4, None, None) == H.HMAT_EINVAL
 
 
