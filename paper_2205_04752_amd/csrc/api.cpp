@@ -1966,7 +1966,7 @@ hmat_status check_solve_args(hmat_t h, const double* b, const double* x, double 
 // Adaptive matrix-vector multiplication (Algorithm 2, Sec. 3) on the device:
 // resumable ACA (k_aca with saved state, paused at a step count), the
 // rank-two look-ahead contributions d_b = (A^_k - A_k)_b x_s per admissible
-// block, and the marking on the host. A_0: dense blocks exact, admissible
+// block, and the marking (amvm.hip). A_0: dense blocks exact, admissible
 // blocks of rank 0; the look-ahead adds two ACA steps per block; rows are
 // visited in decreasing |(b^_k - b_k)_i| (ties: lower row first), blocks of a
 // row in canonical order; a block joins P_k when its entry in that row
