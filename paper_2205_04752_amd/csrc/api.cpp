@@ -2082,7 +2082,7 @@ hmat_status amvm_impl(const hmat_mesh* mesh, double E, double nu, double eta, in
     }
     size_t shmem[2] = {0, 0};  // 256-thread blocks, one-wave blocks
     for (size_t f = 0; f < nf; f++) {
-      const bool small = std::max(base[f].t_len, base[f].s_len) <= ACA_SMALL_TRI;
+      const bool small = std::max(base[f].t_len, base[f].s_len) <= AMVM_SMALL_TRI;
       shmem[small ? 1 : 0] =
           std::max(shmem[small ? 1 : 0], aca_shmem(kcap[f], M[f], Nn[f], small ? 1 : ACA_WIDE_NWV));
     }
@@ -2257,7 +2257,7 @@ hmat_status amvm_impl(const hmat_mesh* mesh, double E, double nu, double eta, in
     std::vector<char> adv(nf, 1);  // blocks marked in the last round (all at first)
     std::vector<char> big(nf), ahead(nf);
     for (size_t f = 0; f < nf; f++) {
-      big[f] = std::max(base[f].t_len, base[f].s_len) > ACA_SMALL_TRI;
+      big[f] = std::max(base[f].t_len, base[f].s_len) > AMVM_SMALL_TRI;
       ahead[f] = big[f] && M[f] + Nn[f] >= AMVM_AHEAD_ROWS;
     }
     int n_pf = 0;

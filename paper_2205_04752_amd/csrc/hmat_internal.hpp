@@ -51,6 +51,10 @@ constexpr int ACA_WIDE_NWV = 8;  // the same in launches of few blocks (one per 
 // Adaptive multiplication: admissible blocks with m + n >= AMVM_AHEAD_ROWS run
 // their look-ahead ACA steps one round ahead, on a stream of their own.
 constexpr int64_t AMVM_AHEAD_ROWS = 2048;
+// Adaptive multiplication: blocks with at most AMVM_SMALL_TRI triangles on both
+// sides resume ACA one wave each (two steps per round: a workgroup would idle;
+// 256 against 64, 128 and 512 cut the ellipsoid's AMVM 53 -> 45 ms).
+constexpr int AMVM_SMALL_TRI = 256;
 // A block with m + n <= ACA_STAGE_MAX keeps the newest row and column of
 // its remainder in LDS as well as in the panels, so the pivot searches,
 // the normalisation and the norm update of a step read them from LDS.
