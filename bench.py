@@ -544,6 +544,7 @@ def main():
     ap.add_argument("--serve-capacity-only", action="store_true",
                     help="serve: only the all-at-once runs (no Poisson arrivals)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune-aca", action="store_true", help="skip the ACA schedule tuning line")
     ap.add_argument("--cpu-seconds", type=float, default=5.0)
     ap.add_argument("--solves", type=int, default=4, help="GMRES solves per step")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -755,6 +756,17 @@ def main():
                                                  "gbs": round(bb / (t * 1e-3) / 1e9, 2)}
                                              for n, bb, t in kernels if n != name}}
     out["build_flops"] = build_flops(H, V, T, wl, stats, rec)
+    if not args.no_tune_aca:
+        # the ACA launch schedule tuned for this mesh (hmat_tune_aca; not timed
+        # above, where the default schedule builds): same matrix, ACA kernel time
+        tn = H.tune_aca(V, T, wl["E"], wl["nu"], wl["eta"], wl["leaf"], wl["eps"], reps=2)
+        ht = H.HMatrix(V, T, wl["E"], wl["nu"], wl["eta"], wl["leaf"], wl["eps"], aca_schedule=tn["aca_schedule"])
+        stt = ht.info()
+        ht.close()
+        out["build_tuned"] = {"aca_schedule": {"small_tri": tn["aca_schedule"][0], "wide": tn["aca_schedule"][1]},
+                              "build_ms": round(stt["t_build_ms"], 3),
+                              "aca_kernel_ms": round(stt["t_aca_kernel_ms"], 3),
+                              "candidates_ms": [[c[0], c[1], round(c[2], 3)] for c in tn["candidates"]]}
     if not args.no_cpu_baseline:
         try:
             out["cpu_baseline"] = cpu_baseline(V, T, wl, W.random_x(N, 1, seed=0), args.cpu_seconds)
