@@ -43,7 +43,8 @@ size_t dots_part_size(int64_t, int);
 size_t norm_part_size(int64_t);
 hipError_t launch_cgs_pass(const double*, int64_t, int64_t, int, double*, double*, double*, double*, int, double*, hipStream_t);
 hipError_t launch_norm(const double*, int64_t, double*, double*, hipStream_t);
-hipError_t launch_scale_norm(const double*, int64_t, const double*, double*, double*, hipStream_t);
+hipError_t launch_scale_norm(const double*, int64_t, const double*, double*, double*, const int32_t*, double*,
+                             const double*, int, double*, hipStream_t);
 hipError_t launch_scale(const double*, int64_t, const double*, double*, hipStream_t);
 hipError_t launch_add_comb(const double*, int64_t, int64_t, int, const double*, double*, hipStream_t);
 hipError_t launch_residual(const double*, int64_t, double*, hipStream_t);
@@ -554,6 +555,7 @@ double ms_since(std::chrono::steady_clock::time_point t0) {
 namespace {
 // Pinned host buffers for GMRES's Hessenberg columns (3 x 1026 doubles),
 // recycled across handles: allocating pinned memory synchronises the device.
+// Coherent, since a kernel writes the columns into them directly.
 std::mutex g_pin_mu;
 std::vector<double*> g_pin_free;
 constexpr size_t PIN_DOUBLES = 3 * 1026;
@@ -567,7 +569,7 @@ double* pinned_acquire() {
     }
   }
   double* p = nullptr;
-  if (hipHostMalloc((void**)&p, sizeof(double) * PIN_DOUBLES) != hipSuccess) {
+  if (hipHostMalloc((void**)&p, sizeof(double) * PIN_DOUBLES, hipHostMallocCoherent) != hipSuccess) {
     (void)hipGetLastError();
     return nullptr;
   }
@@ -1687,9 +1689,10 @@ void prof_collect(hmat* h) {
 }
 
 // allow_prof = false: no per-phase events even while hmat_profile is on
-// (the allocation-free solve creates no events).
+// (the allocation-free solve creates no events). gathered = true (nrhs 1
+// only): h->d_xp already holds x in cluster order, so the gather is skipped.
 void matvec_impl(hmat* h, int prec, int32_t nrhs, const double* x, int64_t ldx, double* y,
-                 int64_t ldy, hipStream_t s, bool allow_prof = true) {
+                 int64_t ldy, hipStream_t s, bool allow_prof = true, bool gathered = false) {
   for (int32_t r0 = 0; r0 < nrhs; r0 += MV_MAX_NR) {
     const int nr = std::min<int32_t>(MV_MAX_NR, nrhs - r0);
     hipEvent_t* ev = nullptr;
@@ -1701,9 +1704,10 @@ void matvec_impl(hmat* h, int prec, int32_t nrhs, const double* x, int64_t ldx, 
       ev = h->prof_pending.back().data();
       check(hipEventRecord(ev[0], s), "profile");
     }
-    check(launch_gather(nr, x + r0 * ldx, ldx, h->d_order.as<int32_t>(), h->N, h->d_xp.as<double>(),
-                        h->ldxp, s),
-          "gather");
+    if (!(gathered && nrhs == 1))
+      check(launch_gather(nr, x + r0 * ldx, ldx, h->d_order.as<int32_t>(), h->N,
+                          h->d_xp.as<double>(), h->ldxp, s),
+            "gather");
     if (ev) check(hipEventRecord(ev[1], s), "profile");
     ProductPlanDev P{};
 
@@ -1854,22 +1858,31 @@ hmat_status gmres_impl(hmat* h, int prec, const GmresWs& ws, const double* b, do
       return y_host[0];
     };
     // One Arnoldi step j: w = A q_j, two classical Gram-Schmidt passes against
-    // q_0..q_j (Hessenberg column in hacc[j % 2]), q_{j+1} = w / ||w||, and an
-    // asynchronous copy of the column to pinned host memory (event col_ev[j % 2]).
+    // q_0..q_j (Hessenberg column in hacc[j % 2]), q_{j+1} = w / ||w||, and the
+    // column in host memory: written by the normalisation kernel into pinned
+    // memory (event col_ev[j % 2]), or copied into ordinary host memory
+    // (allocation-free solve). The normalisation also writes q_{j+1} in
+    // cluster order into the product's input buffer, so step j+1's product
+    // skips its gather; step 0 gathers (the residual's product uses that
+    // buffer in between).
     auto enqueue_step = [&](int j) {
       double* col = hacc[j % 2];
-      matvec_impl(h, prec, 1, Q + (size_t)j * N, N, w, N, s, piped);
+      matvec_impl(h, prec, 1, Q + (size_t)j * N, N, w, N, s, piped, j > 0);
       for (int pass = 0; pass < 2; pass++)
         check(launch_cgs_pass(Q, N, N, j + 1, w, dotpart, hvec, col, pass == 0,
                               pass == 1 ? normpart : nullptr, s),
               "project");
-      check(launch_scale_norm(w, N, normpart, col + j + 1, Q + (size_t)(j + 1) * N, s), "scale");
-      check(hipMemcpyAsync(hcol_host[j % 2], col, sizeof(double) * (j + 2), hipMemcpyDeviceToHost, s),
-            "hessenberg");
-      if (piped)
+      check(launch_scale_norm(w, N, normpart, col + j + 1, Q + (size_t)(j + 1) * N,
+                              h->d_order.as<int32_t>(), h->d_xp.as<double>(), col, j + 1,
+                              piped ? hcol_host[j % 2] : nullptr, s),
+            "scale");
+      if (piped) {
         check(hipEventRecord(ws.ev[j % 2], s), "hessenberg");
-      else
+      } else {
+        check(hipMemcpyAsync(hcol_host[j % 2], col, sizeof(double) * (j + 2), hipMemcpyDeviceToHost, s),
+              "hessenberg");
         check(hipStreamSynchronize(s), "hessenberg");
+      }
     };
     check(launch_fill(x, N, 0.0, s), "fill");
     const double bn = norm_host(b);

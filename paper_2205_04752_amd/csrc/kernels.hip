@@ -1063,7 +1063,11 @@ __global__ __launch_bounds__(256) void k_proj(const double* __restrict__ Q, int6
 __global__ __launch_bounds__(256) void k_scale_norm(const double* __restrict__ w, int64_t n,
                                                     const double* __restrict__ normpart, int nblk,
                                                     double* __restrict__ nrm,
-                                                    double* __restrict__ out) {
+                                                    double* __restrict__ out,
+                                                    const int32_t* __restrict__ order,
+                                                    double* __restrict__ xp,
+                                                    const double* __restrict__ col, int ncol,
+                                                    double* __restrict__ col_host) {
   __shared__ double red[NW];
   __shared__ double dsh;
   double t = 0.0;
@@ -1079,8 +1083,17 @@ __global__ __launch_bounds__(256) void k_scale_norm(const double* __restrict__ w
   }
   __syncthreads();
   const double d = dsh;
+  // col_host (host memory the device can write): col[0:ncol] and the norm
+  if (col_host && blockIdx.x == 0) {
+    for (int c = threadIdx.x; c < ncol; c += blockDim.x) col_host[c] = col[c];
+    if (threadIdx.x == 0) col_host[ncol] = d;
+  }
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < n && d != 0.0) out[i] = w[i] / d;
+  if (i < n && d != 0.0) {
+    out[i] = w[i] / d;
+    // also the product's input in cluster order, xp[i] = out[3 order[i/3] + i%3]
+    if (xp) xp[i] = w[3 * (int64_t)order[i / 3] + i % 3] / d;
+  }
 }
 
 // Partial sums of squares: part[b] = sum over the rows of block b of w[i]^2.
@@ -1339,11 +1352,15 @@ hipError_t launch_cgs_pass(const double* Q, int64_t ldq, int64_t n, int ncols, d
 size_t norm_part_size(int64_t n) { return (size_t)((n + 255) / 256); }
 
 // out = w / ||w|| from the partial sums of squares written by the last pass;
-// *nrm = ||w||.
+// *nrm = ||w||. With xp != nullptr, also xp[i] = out[3 order[i/3] + i%3]
+// (out in cluster order; n a multiple of 3, order a permutation of n/3).
+// With col_host != nullptr (pinned host memory), also col_host[0:ncol] =
+// col[0:ncol] and col_host[ncol] = ||w||, written by the kernel itself.
 hipError_t launch_scale_norm(const double* w, int64_t n, const double* normpart, double* nrm,
-                             double* out, hipStream_t s) {
+                             double* out, const int32_t* order, double* xp, const double* col,
+                             int ncol, double* col_host, hipStream_t s) {
   hipLaunchKernelGGL(k_scale_norm, dim3(blocks_for(n, 256)), dim3(256), 0, s, w, n, normpart,
-                     (int)blocks_for(n, 256), nrm, out);
+                     (int)blocks_for(n, 256), nrm, out, order, xp, col, ncol, col_host);
   return hipGetLastError();
 }
 
