@@ -397,6 +397,117 @@ __device__ __forceinline__ void mv_a_mfma(const MvA& I, const T* __restrict__ fa
 // c + l/16 in each 64-row half the segment touches, and entry c + l/16 of
 // vector l%16. Product t of a half accumulates tile rows 64h + 4m + t.
 // Writes part[chunk][16][128].
+//
+// The work is a sequence of steps (segment, batch of 16 columns). The loads
+// of step i+1 are issued before the products of step i, so a wave keeps a
+// batch of loads in flight while its products run (software pipelining; two
+// register sets in turn). Every step issues the same loads, also for a half
+// the segment does not touch (clamped to the column's first row, a cache
+// hit), so the compiler can wait for exactly one step's loads; after the last
+// step the next batch repeats it. The products and their order are those of
+// the plain loop over segments and batches.
+template <typename T>
+struct MfmaSeg {  // one segment as this lane sees it (no flags: derived where used)
+  const T* __restrict__ base;     // the segment's column block in the stream
+  const double* __restrict__ Bp;  // its vector (z or xp) at the segment's columns
+  int c0, c1, lo, hi;             // columns, tile rows [lo, hi)
+};
+
+template <typename T>
+__device__ __forceinline__ MfmaSeg<T> mfma_seg(const MvSeg& S, const T* __restrict__ stream,
+                                               const double* __restrict__ z, int64_t ldz,
+                                               const double* __restrict__ xp, int64_t ldxp,
+                                               int nr, int m16) {
+  MfmaSeg<T> G;
+  G.base = stream + S.so;
+  G.Bp = (S.far ? z + (int64_t)min(m16, nr - 1) * ldz : xp + (int64_t)min(m16, nr - 1) * ldxp) + S.soff;
+  G.c0 = S.c0;
+  G.c1 = S.c1;
+  G.lo = S.row_lo;
+  G.hi = S.row_hi;
+  return G;
+}
+
+template <typename T>
+struct MfmaStep {  // one step's loads, as loaded (FP32 entries widen at use)
+  double bv[4];
+  typename Pair<T>::type av[4][2][2];
+};
+
+// Row offsets of this lane in the segment: half 0 rows 4 m16 + {0,1} and +{2,3}
+// (index 0, 1), half 1 the same + 64 (index 2, 3); inside = within the
+// segment (pairs are whole: segment bounds are even).
+__device__ __forceinline__ int mfma_row(int lo, int m16, int k) {
+  return 64 * (k >> 1) + 4 * m16 + 2 * (k & 1) - lo;
+}
+
+template <typename T>
+__device__ __forceinline__ void mfma_load(MfmaStep<T>& B, const MfmaSeg<T>& G, int c, int kq,
+                                          int m16) {
+  const int len = G.hi - G.lo;
+  int off[4];
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    const int r = mfma_row(G.lo, m16, k);
+    off[k] = (r >= 0 && r < len) ? r : 0;
+  }
+#pragma unroll
+  for (int g = 0; g < 4; g++) {
+    const int cc = min(c + 4 * g + kq, G.c1 - 1);
+    const T* __restrict__ col = G.base + (int64_t)(cc - G.c0) * len;
+    B.bv[g] = G.Bp[cc];
+    B.av[g][0][0] = ldp(col + off[0]);
+    B.av[g][0][1] = ldp(col + off[1]);
+    B.av[g][1][0] = ldp(col + off[2]);
+    B.av[g][1][1] = ldp(col + off[3]);
+  }
+}
+
+// s_waitcnt immediate (gfx9 encoding) that waits until at most n vector-memory
+// loads are outstanding (expcnt and lgkmcnt left at their maxima).
+constexpr int vmcnt_imm(int n) { return (n & 15) | ((n >> 4) << 14) | (7 << 4) | (15 << 8); }
+constexpr int MFMA_STEP_LOADS = 20;  // per step: 4 vector entries + 16 matrix pairs
+
+template <typename T>
+__device__ __forceinline__ void mfma_step(v4d (&acc)[2][4], const MfmaStep<T>& B,
+                                          const MfmaSeg<T>& G, int c, int kq, int m16, bool rv) {
+  // This step's loads are done once at most the next step's are in flight.
+  // Waiting here, before the branches over the halves, tells the compiler so
+  // on every path (else it waits for all loads before reusing registers).
+  __builtin_amdgcn_s_waitcnt(vmcnt_imm(MFMA_STEP_LOADS));
+  const int len = G.hi - G.lo;
+  bool q[4];
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    const int r = mfma_row(G.lo, m16, k);
+    q[k] = r >= 0 && r < len;
+  }
+  const bool h0 = G.lo < 64, h1 = G.hi > 64;  // halves the segment touches
+#pragma unroll
+  for (int g = 0; g < 4; g++) {
+    const double b = (rv && c + 4 * g + kq < G.c1) ? B.bv[g] : 0.0;
+    if (h0) {
+      acc[0][0] = mfma4(q[0] ? (double)B.av[g][0][0].x : 0.0, b, acc[0][0]);
+      acc[0][1] = mfma4(q[0] ? (double)B.av[g][0][0].y : 0.0, b, acc[0][1]);
+      acc[0][2] = mfma4(q[1] ? (double)B.av[g][0][1].x : 0.0, b, acc[0][2]);
+      acc[0][3] = mfma4(q[1] ? (double)B.av[g][0][1].y : 0.0, b, acc[0][3]);
+    }
+    if (h1) {
+      acc[1][0] = mfma4(q[2] ? (double)B.av[g][1][0].x : 0.0, b, acc[1][0]);
+      acc[1][1] = mfma4(q[2] ? (double)B.av[g][1][0].y : 0.0, b, acc[1][1]);
+      acc[1][2] = mfma4(q[3] ? (double)B.av[g][1][1].x : 0.0, b, acc[1][2]);
+      acc[1][3] = mfma4(q[3] ? (double)B.av[g][1][1].y : 0.0, b, acc[1][3]);
+    }
+  }
+}
+
+// First segment at or after t (< seg_hi) with columns, or seg_hi.
+__device__ __forceinline__ int mfma_seg_from(int t, int seg_hi, const MvSeg* __restrict__ segs) {
+  for (; t < seg_hi; t++)
+    if (segs[t].c1 > segs[t].c0) break;
+  return t;
+}
+
 template <typename T>
 __device__ __forceinline__ void mv_b_mfma(const MvChunk& C, int chunk,
                                           const MvSeg* __restrict__ segs,
@@ -412,51 +523,43 @@ __device__ __forceinline__ void mv_b_mfma(const MvChunk& C, int chunk,
   for (int h = 0; h < 2; h++)
 #pragma unroll
     for (int t = 0; t < 4; t++) acc[h][t] = v4d{0.0, 0.0, 0.0, 0.0};
-  for (int s = C.seg_lo; s < C.seg_hi; s++) {
-    const MvSeg S = segs[s];
-    const int len = S.row_hi - S.row_lo;
-    const double* __restrict__ Bp =
-        (S.far ? z + (int64_t)min(m16, nr - 1) * ldz : xp + (int64_t)min(m16, nr - 1) * ldxp) + S.soff;
-    const bool h0 = S.row_lo < 64, h1 = S.row_hi > 64;  // halves the segment touches
-    // this lane's rows in each half, relative to the segment (pairs are whole: bounds are even)
-    const int R0 = 4 * m16 - S.row_lo, R1 = 64 + 4 * m16 - S.row_lo;
-    const bool q00 = R0 >= 0 && R0 < len, q01 = R0 + 2 >= 0 && R0 + 2 < len;
-    const bool q10 = R1 >= 0 && R1 < len, q11 = R1 + 2 >= 0 && R1 + 2 < len;
-    // batches of 16 columns (four groups of four): all loads first
-    for (int c = S.c0; c < S.c1; c += 16) {
-      double bv[4];
-      double2 av[4][2][2];
-#pragma unroll
-      for (int g = 0; g < 4; g++) {
-        const int cc = c + 4 * g + kq;
-        const bool cok = cc < S.c1;
-        const int ccl = cok ? cc : S.c1 - 1;
-        const T* __restrict__ col = stream + S.so + (int64_t)(ccl - S.c0) * len;
-        bv[g] = Bp[ccl];
-        bv[g] = (cok && rv) ? bv[g] : 0.0;
-        if (h0) {
-          av[g][0][0] = ld2(col + (q00 ? R0 : 0));
-          av[g][0][1] = ld2(col + (q01 ? R0 + 2 : 0));
-        }
-        if (h1) {
-          av[g][1][0] = ld2(col + (q10 ? R1 : 0));
-          av[g][1][1] = ld2(col + (q11 ? R1 + 2 : 0));
-        }
+  int s = mfma_seg_from(C.seg_lo, C.seg_hi, segs);
+  if (s < C.seg_hi) {
+    // (Ga, ca) and (Gb, cb): the steps whose loads are in A and B
+    MfmaSeg<T> Ga = mfma_seg<T>(segs[s], stream, z, ldz, xp, ldxp, nr, m16), Gb;
+    int ca = Ga.c0, cb;
+    MfmaStep<T> A, B;
+    mfma_load(A, Ga, ca, kq, m16);
+    // advance (G, c) from segment s to the next step; false at the chunk's
+    // end, where (Gn, cn) = (G, c + 16): a batch past the segment's columns,
+    // whose loads (all clamped to its last column) are issued and unused, so
+    // that every step waits for exactly one step's loads
+    auto next = [&](const MfmaSeg<T>& G, int c, MfmaSeg<T>& Gn, int& cn) -> bool {
+      if (c + 16 < G.c1 || (s = mfma_seg_from(s + 1, C.seg_hi, segs)) >= C.seg_hi) {
+        Gn = G;
+        cn = c + 16;
+        return cn < G.c1;
       }
-#pragma unroll
-      for (int g = 0; g < 4; g++) {
-        if (h0) {
-          acc[0][0] = mfma4(q00 ? av[g][0][0].x : 0.0, bv[g], acc[0][0]);
-          acc[0][1] = mfma4(q00 ? av[g][0][0].y : 0.0, bv[g], acc[0][1]);
-          acc[0][2] = mfma4(q01 ? av[g][0][1].x : 0.0, bv[g], acc[0][2]);
-          acc[0][3] = mfma4(q01 ? av[g][0][1].y : 0.0, bv[g], acc[0][3]);
-        }
-        if (h1) {
-          acc[1][0] = mfma4(q10 ? av[g][1][0].x : 0.0, bv[g], acc[1][0]);
-          acc[1][1] = mfma4(q10 ? av[g][1][0].y : 0.0, bv[g], acc[1][1]);
-          acc[1][2] = mfma4(q11 ? av[g][1][1].x : 0.0, bv[g], acc[1][2]);
-          acc[1][3] = mfma4(q11 ? av[g][1][1].y : 0.0, bv[g], acc[1][3]);
-        }
+      Gn = mfma_seg<T>(segs[s], stream, z, ldz, xp, ldxp, nr, m16);
+      cn = Gn.c0;
+      return true;
+    };
+    // (the exits wait for the unused loads, so that no path into the loop's
+    // latch leaves loads in flight into registers the next step reuses)
+    for (;;) {
+      bool more = next(Ga, ca, Gb, cb);
+      mfma_load(B, Gb, cb, kq, m16);
+      mfma_step(acc, A, Ga, ca, kq, m16, rv);
+      if (!more) {
+        __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+        break;
+      }
+      more = next(Gb, cb, Ga, ca);
+      mfma_load(A, Ga, ca, kq, m16);
+      mfma_step(acc, B, Gb, cb, kq, m16, rv);
+      if (!more) {
+        __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+        break;
       }
     }
   }
