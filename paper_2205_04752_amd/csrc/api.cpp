@@ -533,7 +533,6 @@ constexpr int MV_TILE = 128;     // rows per product tile (one wave, two rows pe
 constexpr int MV_SEG_COLS = 128; // columns per product segment
 constexpr int64_t MV_CHUNK_BYTES = 16 * 1024;         // nrhs = 1; HMAT_MV_CHUNK_KB overrides
 constexpr int64_t MV_CHUNK_BYTES_MULTI = 128 * 1024;  // nrhs > 1
-constexpr int MV_MAX_NR = 16;    // right-hand sides per pass over the matrix
 
 inline int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 
@@ -974,9 +973,10 @@ void build_product_plan(hmat* h, hipStream_t s) {
     set_chunk_list(h, l, l == 0 ? h->mv_chunk_bytes : h->mv_chunk_bytes_multi, s);
   }
 
-  if (h->d_xp.bytes < sizeof(double) * MV_MAX_NR * h->ldxp) {
-    h->d_xp.alloc(sizeof(double) * MV_MAX_NR * h->ldxp, "product workspace");
-    // rows [N, ldxp) stay zero: they meet only zero pad rows of V panels
+  if (h->d_xp.bytes < sizeof(double) * (MV_MAX_NR + 1) * h->ldxp) {
+    // one vector at [0, ldxp), several side by side at [ldxp, (MV_MAX_NR + 1) ldxp);
+    // rows [N, ldxp) of either stay zero: they meet only zero pad rows of V panels
+    h->d_xp.alloc(sizeof(double) * (MV_MAX_NR + 1) * h->ldxp, "product workspace");
     check(hipMemsetAsync(h->d_xp.p, 0, h->d_xp.bytes, s), "product workspace");
   }
   h->d_z.alloc(sizeof(double) * MV_MAX_NR * h->Ztot, "product workspace");

@@ -24,6 +24,18 @@ __global__ void k_gather(int nr, const double* __restrict__ x, int64_t ldx,
   xp[r * ldxp + d] = x[r * ldx + 3 * (int64_t)order[d / 3] + d % 3];
 }
 
+// Several vectors: xi[d][r] = x[r][3 order[d/3] + d%3], MV_MAX_NR entries per
+// row (r < nr written), so that the vectors' entries of a row share cache
+// lines and pages.
+__global__ void k_gather_il(int nr, const double* __restrict__ x, int64_t ldx,
+                            const int32_t* __restrict__ order, int64_t N, double* __restrict__ xi) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= N * MV_MAX_NR) return;
+  const int64_t d = e / MV_MAX_NR;
+  const int r = (int)(e - d * MV_MAX_NR);
+  if (r < nr) xi[e] = x[r * ldx + 3 * (int64_t)order[d / 3] + d % 3];
+}
+
 constexpr int TILE = 2 * WAVE;  // rows per product tile: two rows per lane
 
 // Stored matrix entries are FP64 or FP32 (T); the product computes in FP64.
@@ -327,9 +339,10 @@ __device__ __forceinline__ v4d mfma4(double a, double b, v4d c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// Phase A, several vectors: z[:, zoff + c] = V[:, l0 + c]^T X for c < l1 - l0
+// Phase A, several vectors: z[zoff + c][:] = V[:, l0 + c]^T X for c < l1 - l0
 // (<= 64 columns: four 16-column tiles). Per 16-row step lane l reads rows
 // 4(l/16) .. +3 of column l%16 of each tile and the same rows of vector l%16.
+// X and z hold a row's vectors side by side (MV_MAX_NR entries per row).
 template <typename T>
 __device__ __forceinline__ void mv_a_mfma(const MvA& I, const T* __restrict__ far,
                                           const double* __restrict__ xp, int64_t ldxp, int nr,
@@ -339,7 +352,7 @@ __device__ __forceinline__ void mv_a_mfma(const MvA& I, const T* __restrict__ fa
   const int ncols = I.l1 - I.l0;
   const int ntile = (ncols + 15) >> 4;
   const bool rv = cl < nr;
-  const double* __restrict__ X = xp + (int64_t)min(cl, nr - 1) * ldxp + I.a0;
+  const double* __restrict__ X = xp + (int64_t)I.a0 * MV_MAX_NR + cl;
   const T* Vc[4];
   bool cv[4];
 #pragma unroll
@@ -354,8 +367,10 @@ __device__ __forceinline__ void mv_a_mfma(const MvA& I, const T* __restrict__ fa
   for (int i0 = 0; i0 < I.ld; i0 += 16) {
     const int r0 = i0 + 4 * kq;
     const bool p0 = r0 < I.ld, p1 = r0 + 2 < I.ld;  // ld and r0 even: pairs are whole
-    double2 x0 = *reinterpret_cast<const double2*>(X + (p0 ? r0 : 0));
-    double2 x1 = *reinterpret_cast<const double2*>(X + (p1 ? r0 + 2 : 0));
+    const double* X0 = X + (int64_t)(p0 ? r0 : 0) * MV_MAX_NR;
+    const double* X1 = X + (int64_t)(p1 ? r0 + 2 : 0) * MV_MAX_NR;
+    double2 x0 = make_double2(X0[0], X0[MV_MAX_NR]);
+    double2 x1 = make_double2(X1[0], X1[MV_MAX_NR]);
     const bool b0 = rv && p0, b1 = rv && p1;
     x0.x = b0 ? x0.x : 0.0;
     x0.y = b0 ? x0.y : 0.0;
@@ -386,17 +401,20 @@ __device__ __forceinline__ void mv_a_mfma(const MvA& I, const T* __restrict__ fa
 #pragma unroll
       for (int v = 0; v < 4; v++) {
         const int col = q * 16 + 4 * v + kq;
-        if (col < ncols && rv) z[(int64_t)cl * ldz + I.zoff + col] = acc[q][v];
+        if (col < ncols && rv) z[(int64_t)(I.zoff + col) * MV_MAX_NR + cl] = acc[q][v];
       }
     }
   }
 }
 
 // Phase B, several vectors: one chunk (segments of one 128-row tile). Per
-// group of four columns c..c+3, lane l reads rows 4(l%16) .. +3 of column
-// c + l/16 in each 64-row half the segment touches, and entry c + l/16 of
-// vector l%16. Product t of a half accumulates tile rows 64h + 4m + t.
-// Writes part[chunk][16][128].
+// group of four columns c..c+3, lane l reads, of column c + l/16, the row
+// pairs 64h + 2(l%16) and 64h + 32 + 2(l%16) in each 64-row half h the
+// segment touches (so the 16 lanes of a column read 256 contiguous bytes per
+// load), and entry c + l/16 of vector l%16. The four products of a half take
+// the rows 64h + 2m, 64h + 2m + 1, 64h + 32 + 2m, 64h + 32 + 2m + 1 in place
+// of row m of the 16-row operand; the stores undo it. Writes
+// part[chunk][16][128].
 //
 // The work is a sequence of steps (segment, batch of 16 columns). The loads
 // of step i+1 are issued before the products of step i, so a wave keeps a
@@ -404,8 +422,8 @@ __device__ __forceinline__ void mv_a_mfma(const MvA& I, const T* __restrict__ fa
 // register sets in turn). Every step issues the same loads, also for a half
 // the segment does not touch (clamped to the column's first row, a cache
 // hit), so the compiler can wait for exactly one step's loads; after the last
-// step the next batch repeats it. The products and their order are those of
-// the plain loop over segments and batches.
+// step one more, unused, batch is issued. The products and their order are
+// those of the plain loop over segments and batches.
 template <typename T>
 struct MfmaSeg {  // one segment as this lane sees it (no flags: derived where used)
   const T* __restrict__ base;     // the segment's column block in the stream
@@ -420,7 +438,7 @@ __device__ __forceinline__ MfmaSeg<T> mfma_seg(const MvSeg& S, const T* __restri
                                                int nr, int m16) {
   MfmaSeg<T> G;
   G.base = stream + S.so;
-  G.Bp = (S.far ? z + (int64_t)min(m16, nr - 1) * ldz : xp + (int64_t)min(m16, nr - 1) * ldxp) + S.soff;
+  G.Bp = (S.far ? z : xp) + (int64_t)S.soff * MV_MAX_NR + m16;
   G.c0 = S.c0;
   G.c1 = S.c1;
   G.lo = S.row_lo;
@@ -434,11 +452,11 @@ struct MfmaStep {  // one step's loads, as loaded (FP32 entries widen at use)
   typename Pair<T>::type av[4][2][2];
 };
 
-// Row offsets of this lane in the segment: half 0 rows 4 m16 + {0,1} and +{2,3}
-// (index 0, 1), half 1 the same + 64 (index 2, 3); inside = within the
-// segment (pairs are whole: segment bounds are even).
+// Row offset in the segment of this lane's k-th row pair (k = 0..3: half
+// k/2, upper 32 rows of the half if k is odd); inside the segment iff in
+// [0, len) (pairs are whole: segment bounds are even).
 __device__ __forceinline__ int mfma_row(int lo, int m16, int k) {
-  return 64 * (k >> 1) + 4 * m16 + 2 * (k & 1) - lo;
+  return 64 * (k >> 1) + 32 * (k & 1) + 2 * m16 - lo;
 }
 
 template <typename T>
@@ -455,7 +473,7 @@ __device__ __forceinline__ void mfma_load(MfmaStep<T>& B, const MfmaSeg<T>& G, i
   for (int g = 0; g < 4; g++) {
     const int cc = min(c + 4 * g + kq, G.c1 - 1);
     const T* __restrict__ col = G.base + (int64_t)(cc - G.c0) * len;
-    B.bv[g] = G.Bp[cc];
+    B.bv[g] = G.Bp[(int64_t)cc * MV_MAX_NR];
     B.av[g][0][0] = ldp(col + off[0]);
     B.av[g][0][1] = ldp(col + off[1]);
     B.av[g][1][0] = ldp(col + off[2]);
@@ -563,16 +581,17 @@ __device__ __forceinline__ void mv_b_mfma(const MvChunk& C, int chunk,
       }
     }
   }
-  // lane holds vector m16, tile rows 64h + 16v + 4kq + t in acc[h][t][v]
+  // lane holds vector m16 and, for operand row i = 4v + kq, tile rows
+  // 64h + 2i + t (t = 0, 1) in acc[h][t][v] and 64h + 32 + 2i + t - 2 (t = 2, 3)
   if (rv) {
     double* __restrict__ out = part + ((size_t)chunk * 16 + m16) * TILE;
 #pragma unroll
     for (int h = 0; h < 2; h++)
 #pragma unroll
       for (int v = 0; v < 4; v++) {
-        const int row = 64 * h + 16 * v + 4 * kq;
+        const int row = 64 * h + 8 * v + 2 * kq;
         *reinterpret_cast<double2*>(out + row) = make_double2(acc[h][0][v], acc[h][1][v]);
-        *reinterpret_cast<double2*>(out + row + 2) = make_double2(acc[h][2][v], acc[h][3][v]);
+        *reinterpret_cast<double2*>(out + row + 32) = make_double2(acc[h][2][v], acc[h][3][v]);
       }
   }
 }
@@ -706,8 +725,12 @@ hipError_t launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t s
 
 hipError_t launch_gather(int nr, const double* x, int64_t ldx, const int32_t* order, int64_t N,
                          double* xp, int64_t ldxp, hipStream_t s) {
-  hipLaunchKernelGGL(k_gather, dim3(blocks_for(N * nr, 256)), dim3(256), 0, s, nr, x, ldx, order,
-                     N, xp, ldxp);
+  if (nr > 1)  // several vectors: side by side, after the single-vector area
+    hipLaunchKernelGGL(k_gather_il, dim3(blocks_for(N * MV_MAX_NR, 256)), dim3(256), 0, s, nr, x,
+                       ldx, order, N, xp + ldxp);
+  else
+    hipLaunchKernelGGL(k_gather, dim3(blocks_for(N * nr, 256)), dim3(256), 0, s, nr, x, ldx, order,
+                       N, xp, ldxp);
   return hipGetLastError();
 }
 
@@ -763,7 +786,7 @@ hipError_t launch_matvec_group(const ProductPlanDev& P, int prec, int nr, const 
       else
         mv_group<1, 8, float>(P, P.far32, P.stream32, xp, ldxp, nr, z, ldz, part, y, ldy, s, ev);
     } else {
-      mv_group_mfma<float>(P, P.far32, P.stream32, xp, ldxp, nr, z, ldz, part, y, ldy, s, ev);
+      mv_group_mfma<float>(P, P.far32, P.stream32, xp + ldxp, ldxp, nr, z, ldz, part, y, ldy, s, ev);
     }
   } else {
     if (nr <= 1) {
@@ -772,7 +795,7 @@ hipError_t launch_matvec_group(const ProductPlanDev& P, int prec, int nr, const 
       else
         mv_group<1, 8, double>(P, P.far, P.stream, xp, ldxp, nr, z, ldz, part, y, ldy, s, ev);
     } else {
-      mv_group_mfma<double>(P, P.far, P.stream, xp, ldxp, nr, z, ldz, part, y, ldy, s, ev);
+      mv_group_mfma<double>(P, P.far, P.stream, xp + ldxp, ldxp, nr, z, ldz, part, y, ldy, s, ev);
     }
   }
   return hipGetLastError();
