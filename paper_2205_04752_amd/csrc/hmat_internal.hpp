@@ -199,9 +199,9 @@ struct CopyTask32 {
 
 // Product, phase A: z[zoff + l - l0] = V[:, l] . xp[window] for l in [l0, l1).
 // The window is the aligned row range [a0, a0 + ld) of V (global DOFs).
-// Right-hand sides per pass over the matrix. With several, the product's
-// gathered input and its Vᵀx results hold a row's MV_MAX_NR vector entries
-// side by side (entry (row, r) at row * MV_MAX_NR + r).
+// Right-hand sides per pass over the matrix. With nr > 1 of them, the
+// product's gathered input and its Vᵀx results hold a row's nr vector entries
+// side by side (entry (row, r) at row * nr + r).
 constexpr int MV_MAX_NR = 16;
 
 struct MvA {

@@ -24,16 +24,17 @@ __global__ void k_gather(int nr, const double* __restrict__ x, int64_t ldx,
   xp[r * ldxp + d] = x[r * ldx + 3 * (int64_t)order[d / 3] + d % 3];
 }
 
-// Several vectors: xi[d][r] = x[r][3 order[d/3] + d%3], MV_MAX_NR entries per
-// row (r < nr written), so that the vectors' entries of a row share cache
-// lines and pages.
+// Several vectors: xi[d * nr + r] = x[r][3 order[d/3] + d%3] for rows d < N,
+// zero for the pad rows [N, ldxp), so that the nr vectors' entries of a row
+// share cache lines and pages.
 __global__ void k_gather_il(int nr, const double* __restrict__ x, int64_t ldx,
-                            const int32_t* __restrict__ order, int64_t N, double* __restrict__ xi) {
+                            const int32_t* __restrict__ order, int64_t N, int64_t ldxp,
+                            double* __restrict__ xi) {
   const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (e >= N * MV_MAX_NR) return;
-  const int64_t d = e / MV_MAX_NR;
-  const int r = (int)(e - d * MV_MAX_NR);
-  if (r < nr) xi[e] = x[r * ldx + 3 * (int64_t)order[d / 3] + d % 3];
+  if (e >= ldxp * nr) return;
+  const int64_t d = e / nr;
+  const int r = (int)(e - d * nr);
+  xi[e] = d < N ? x[r * ldx + 3 * (int64_t)order[d / 3] + d % 3] : 0.0;
 }
 
 constexpr int TILE = 2 * WAVE;  // rows per product tile: two rows per lane
@@ -342,7 +343,8 @@ __device__ __forceinline__ v4d mfma4(double a, double b, v4d c) {
 // Phase A, several vectors: z[zoff + c][:] = V[:, l0 + c]^T X for c < l1 - l0
 // (<= 64 columns: four 16-column tiles). Per 16-row step lane l reads rows
 // 4(l/16) .. +3 of column l%16 of each tile and the same rows of vector l%16.
-// X and z hold a row's vectors side by side (MV_MAX_NR entries per row).
+// X and z hold a row's nr vector entries side by side; lanes of vectors past
+// nr read the next row's (unused).
 template <typename T>
 __device__ __forceinline__ void mv_a_mfma(const MvA& I, const T* __restrict__ far,
                                           const double* __restrict__ xp, int64_t ldxp, int nr,
@@ -352,7 +354,7 @@ __device__ __forceinline__ void mv_a_mfma(const MvA& I, const T* __restrict__ fa
   const int ncols = I.l1 - I.l0;
   const int ntile = (ncols + 15) >> 4;
   const bool rv = cl < nr;
-  const double* __restrict__ X = xp + (int64_t)I.a0 * MV_MAX_NR + cl;
+  const double* __restrict__ X = xp + (int64_t)I.a0 * nr + cl;
   const T* Vc[4];
   bool cv[4];
 #pragma unroll
@@ -367,10 +369,10 @@ __device__ __forceinline__ void mv_a_mfma(const MvA& I, const T* __restrict__ fa
   for (int i0 = 0; i0 < I.ld; i0 += 16) {
     const int r0 = i0 + 4 * kq;
     const bool p0 = r0 < I.ld, p1 = r0 + 2 < I.ld;  // ld and r0 even: pairs are whole
-    const double* X0 = X + (int64_t)(p0 ? r0 : 0) * MV_MAX_NR;
-    const double* X1 = X + (int64_t)(p1 ? r0 + 2 : 0) * MV_MAX_NR;
-    double2 x0 = make_double2(X0[0], X0[MV_MAX_NR]);
-    double2 x1 = make_double2(X1[0], X1[MV_MAX_NR]);
+    const double* X0 = X + (int64_t)(p0 ? r0 : 0) * nr;
+    const double* X1 = X + (int64_t)(p1 ? r0 + 2 : 0) * nr;
+    double2 x0 = make_double2(X0[0], X0[nr]);
+    double2 x1 = make_double2(X1[0], X1[nr]);
     const bool b0 = rv && p0, b1 = rv && p1;
     x0.x = b0 ? x0.x : 0.0;
     x0.y = b0 ? x0.y : 0.0;
@@ -401,7 +403,7 @@ __device__ __forceinline__ void mv_a_mfma(const MvA& I, const T* __restrict__ fa
 #pragma unroll
       for (int v = 0; v < 4; v++) {
         const int col = q * 16 + 4 * v + kq;
-        if (col < ncols && rv) z[(int64_t)(I.zoff + col) * MV_MAX_NR + cl] = acc[q][v];
+        if (col < ncols && rv) z[(int64_t)(I.zoff + col) * nr + cl] = acc[q][v];
       }
     }
   }
@@ -427,8 +429,9 @@ __device__ __forceinline__ void mv_a_mfma(const MvA& I, const T* __restrict__ fa
 template <typename T>
 struct MfmaSeg {  // one segment as this lane sees it (no flags: derived where used)
   const T* __restrict__ base;     // the segment's column block in the stream
-  const double* __restrict__ Bp;  // its vector (z or xp) at the segment's columns
+  const double* __restrict__ Bp;  // its vectors (z or xp) at the segment's first column
   int c0, c1, lo, hi;             // columns, tile rows [lo, hi)
+  int vs;                         // entries per column in Bp (the number of vectors)
 };
 
 template <typename T>
@@ -438,7 +441,8 @@ __device__ __forceinline__ MfmaSeg<T> mfma_seg(const MvSeg& S, const T* __restri
                                                int nr, int m16) {
   MfmaSeg<T> G;
   G.base = stream + S.so;
-  G.Bp = (S.far ? z : xp) + (int64_t)S.soff * MV_MAX_NR + m16;
+  G.Bp = (S.far ? z : xp) + (int64_t)S.soff * nr + m16;
+  G.vs = nr;
   G.c0 = S.c0;
   G.c1 = S.c1;
   G.lo = S.row_lo;
@@ -473,7 +477,7 @@ __device__ __forceinline__ void mfma_load(MfmaStep<T>& B, const MfmaSeg<T>& G, i
   for (int g = 0; g < 4; g++) {
     const int cc = min(c + 4 * g + kq, G.c1 - 1);
     const T* __restrict__ col = G.base + (int64_t)(cc - G.c0) * len;
-    B.bv[g] = G.Bp[(int64_t)cc * MV_MAX_NR];
+    B.bv[g] = G.Bp[(int64_t)cc * G.vs];
     B.av[g][0][0] = ldp(col + off[0]);
     B.av[g][0][1] = ldp(col + off[1]);
     B.av[g][1][0] = ldp(col + off[2]);
@@ -726,8 +730,8 @@ hipError_t launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t s
 hipError_t launch_gather(int nr, const double* x, int64_t ldx, const int32_t* order, int64_t N,
                          double* xp, int64_t ldxp, hipStream_t s) {
   if (nr > 1)  // several vectors: side by side, after the single-vector area
-    hipLaunchKernelGGL(k_gather_il, dim3(blocks_for(N * MV_MAX_NR, 256)), dim3(256), 0, s, nr, x,
-                       ldx, order, N, xp + ldxp);
+    hipLaunchKernelGGL(k_gather_il, dim3(blocks_for(ldxp * nr, 256)), dim3(256), 0, s, nr, x,
+                       ldx, order, N, ldxp, xp + ldxp);
   else
     hipLaunchKernelGGL(k_gather, dim3(blocks_for(N * nr, 256)), dim3(256), 0, s, nr, x, ldx, order,
                        N, xp, ldxp);
