@@ -175,6 +175,29 @@ def test_matvec_strided_and_deterministic(c0):
         assert np.array_equal(again, ref)
 
 
+def test_vector_counts_share_buffers(c0):
+    """Products with different numbers of vectors on one handle share the input
+    and V^T x buffers (one vector; or nr entries of a row side by side, lanes
+    past nr reading and discarding their neighbours'). A product with an
+    infinite and a NaN entry changes only its own two vectors, and the products
+    after it, with other vector counts, equal the ones before it bit for bit."""
+    x = W.random_x(c0.N, 16, seed=11)
+
+    def run(a):
+        return c0.g.matvec(_dev(a if a.shape[0] > 1 else a[0])).cpu().numpy()
+
+    ref = {nr: run(x[:nr]) for nr in (1, 3, 8, 16)}
+    bad = x.copy()
+    bad[5, 17] = np.inf
+    bad[9, 100] = np.nan
+    yb = run(bad)
+    keep = [r for r in range(16) if r not in (5, 9)]
+    assert np.array_equal(yb[keep], ref[16][keep])
+    assert not np.all(np.isfinite(yb[5])) and not np.all(np.isfinite(yb[9]))
+    for nr in (8, 1, 3, 16):
+        assert np.array_equal(run(x[:nr]), ref[nr])
+
+
 def test_matvec_argument_errors(c0):
     H = _H()
     x = torch.zeros(c0.N, dtype=torch.float64, device="cuda")
