@@ -532,7 +532,12 @@ class PanelLease {
 constexpr int MV_TILE = 128;     // rows per product tile (one wave, two rows per lane)
 constexpr int MV_SEG_COLS = 128; // columns per product segment
 constexpr int64_t MV_CHUNK_BYTES = 16 * 1024;         // nrhs = 1; HMAT_MV_CHUNK_KB overrides
-constexpr int64_t MV_CHUNK_BYTES_MULTI = 128 * 1024;  // nrhs > 1
+// nrhs > 1: 64 KB while the stream holds under 32768 such chunks of 128 KB
+// (so there are several rounds of waves and no long tail), else 128 KB (the
+// partial sums, 16 KB per chunk, stay an eighth of the stream)
+constexpr int64_t MV_CHUNK_BYTES_MULTI = 128 * 1024;
+constexpr int64_t MV_CHUNK_BYTES_MULTI_SMALL = 64 * 1024;
+constexpr int64_t MV_CHUNK_MULTI_SMALL_BELOW = 32768 * MV_CHUNK_BYTES_MULTI;  // stream bytes
 
 inline int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 
@@ -659,7 +664,7 @@ struct hmat {
   };
   std::vector<std::vector<Piece>> block_pieces;  // canonical block -> its pieces
   int64_t mv_chunk_bytes = MV_CHUNK_BYTES;       // product tuning (HMAT_MV_CHUNK_KB)
-  int64_t mv_chunk_bytes_multi = MV_CHUNK_BYTES_MULTI;
+  int64_t mv_chunk_bytes_multi = 0;  // 0: by stream size (multi_chunk_bytes)
   int mv_unroll = 16;                            // columns per batch in phase B (HMAT_MV_UNROLL)
   DevBuf d_xp, d_z, d_part, d_dotpart;
   DevBuf d_ir;  // iterative refinement: residual and correction
@@ -783,6 +788,13 @@ void set_chunk_list(hmat* h, int l, int64_t target, hipStream_t s) {
   const size_t need = sizeof(double) * MV_TILE *
                       std::max<int64_t>(std::max(1, h->cl[0].n), (int64_t)MV_MAX_NR * std::max(1, h->cl[1].n));
   if (h->d_part.bytes < need) h->d_part.alloc(need, "product workspace");
+}
+
+// Chunk size of the several-vector product: the tuned one, else by stream size.
+int64_t multi_chunk_bytes(const hmat* h) {
+  if (h->mv_chunk_bytes_multi > 0) return h->mv_chunk_bytes_multi;
+  return (int64_t)sizeof(double) * h->stream_n < MV_CHUNK_MULTI_SMALL_BELOW ? MV_CHUNK_BYTES_MULTI_SMALL
+                                                                           : MV_CHUNK_BYTES_MULTI;
 }
 
 void build_product_plan(hmat* h, hipStream_t s) {
@@ -970,7 +982,7 @@ void build_product_plan(hmat* h, hipStream_t s) {
   for (int l = 0; l < 2; l++) {
     upload(h->cl[l].d_items, items_l[l], s, "product plan");
     h->cl[l].nA = (int)items_l[l].size();
-    set_chunk_list(h, l, l == 0 ? h->mv_chunk_bytes : h->mv_chunk_bytes_multi, s);
+    set_chunk_list(h, l, l == 0 ? h->mv_chunk_bytes : multi_chunk_bytes(h), s);
   }
 
   if (h->d_xp.bytes < sizeof(double) * (MV_MAX_NR + 1) * h->ldxp) {
