@@ -429,16 +429,15 @@ __device__ __forceinline__ void mv_a_mfma(const MvA& I, const T* __restrict__ fa
 template <typename T>
 struct MfmaSeg {  // one segment as this lane sees it (no flags: derived where used)
   const T* __restrict__ base;     // the segment's column block in the stream
-  const double* __restrict__ Bp;  // its vectors (z or xp) at the segment's first column
+  const double* __restrict__ Bp;  // its vectors (z or xp): column c's entry of this lane's at Bp[c * vs]
   int c0, c1, lo, hi;             // columns, tile rows [lo, hi)
   int vs;                         // entries per column in Bp (the number of vectors)
 };
 
 template <typename T>
 __device__ __forceinline__ MfmaSeg<T> mfma_seg(const MvSeg& S, const T* __restrict__ stream,
-                                               const double* __restrict__ z, int64_t ldz,
-                                               const double* __restrict__ xp, int64_t ldxp,
-                                               int nr, int m16) {
+                                               const double* __restrict__ z,
+                                               const double* __restrict__ xp, int nr, int m16) {
   MfmaSeg<T> G;
   G.base = stream + S.so;
   G.Bp = (S.far ? z : xp) + (int64_t)S.soff * nr + m16;
@@ -548,7 +547,7 @@ __device__ __forceinline__ void mv_b_mfma(const MvChunk& C, int chunk,
   int s = mfma_seg_from(C.seg_lo, C.seg_hi, segs);
   if (s < C.seg_hi) {
     // (Ga, ca) and (Gb, cb): the steps whose loads are in A and B
-    MfmaSeg<T> Ga = mfma_seg<T>(segs[s], stream, z, ldz, xp, ldxp, nr, m16), Gb;
+    MfmaSeg<T> Ga = mfma_seg<T>(segs[s], stream, z, xp, nr, m16), Gb;
     int ca = Ga.c0, cb;
     MfmaStep<T> A, B;
     mfma_load(A, Ga, ca, kq, m16);
@@ -562,7 +561,7 @@ __device__ __forceinline__ void mv_b_mfma(const MvChunk& C, int chunk,
         cn = c + 16;
         return cn < G.c1;
       }
-      Gn = mfma_seg<T>(segs[s], stream, z, ldz, xp, ldxp, nr, m16);
+      Gn = mfma_seg<T>(segs[s], stream, z, xp, nr, m16);
       cn = Gn.c0;
       return true;
     };
