@@ -281,7 +281,9 @@ hmat_status hmat_matvec(hmat_t h, int32_t nrhs, const double* x, int64_t ldx, do
  *   restart  Krylov dimension per cycle, 1..1024.
  *   maxit    maximum number of Arnoldi steps in total (>= 1).
  *   info     HOST, may be NULL.
- * Synchronises the stream (the Hessenberg column is read back each step).
+ * Synchronises the stream. Each Arnoldi step's Hessenberg column reaches the
+ * host through pinned memory that the normalisation kernel writes; the host's
+ * Givens update of step j overlaps the device's step j + 1.
  * Returns HMAT_ENOCONV if maxit is reached first; x and info are written in
  * that case too.
  */
