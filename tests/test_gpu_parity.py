@@ -225,6 +225,24 @@ def test_gmres_c0(c0):
     assert info2["status"] == 4 and info2["iterations"] == 5 and 0 < info2["relres"] < 1
 
 
+@pytest.mark.parametrize("restart", [1, 4])
+def test_gmres_short_restarts(c0, restart):
+    """Short cycles: every Arnoldi step but a cycle's first takes its product's
+    input as the previous step's normalisation wrote it (in cluster order),
+    and each restart's residual product gathers its own; restart 1 runs only
+    first steps. Same solution as the oracle's GMRES with the same restart,
+    and the explicit residual meets the tolerance."""
+    b = W.smooth_rhs(c0.V, c0.T, seed=2)
+    bt = _dev(b)
+    x, info = c0.g.solve(bt, tol=1e-8, restart=restart, maxit=20000)
+    assert info["status"] == 0 and info["restarts"] >= 2
+    r = bt - c0.g.matvec(x)
+    assert float(torch.linalg.norm(r) / torch.linalg.norm(bt)) <= 1e-8
+    xo, io = c0.o.gmres(b, tol=1e-8, restart=restart, maxit=20000)
+    assert np.linalg.norm(x.cpu().numpy() - xo) <= 1e-5 * np.linalg.norm(xo)
+    print(f"gmres restart {restart}: gpu iters", info["iterations"], "oracle iters", io["iters"], flush=True)
+
+
 EDGE = {
     "one-triangle": lambda: (np.array([[0.0, 0, 0], [1, 0, 0], [0, 1, 0.2]]), np.array([[0, 1, 2]], dtype=np.int32)),
     "ico1-leaf4": lambda: W.icosphere(1),
