@@ -1906,8 +1906,13 @@ hmat_status gmres_impl(hmat* h, int prec, const GmresWs& ws, const double* b, do
       status = HMAT_OK;
       rel = 0.0;
     } else {
+      bool x_zero = true;  // x0 = 0: the first residual is b, no product needed
       for (;;) {
-        matvec_impl(h, prec, 1, x, N, w, N, s, piped);
+        if (x_zero)
+          check(launch_fill(w, N, 0.0, s), "fill");
+        else
+          matvec_impl(h, prec, 1, x, N, w, N, s, piped);
+        x_zero = false;
         check(launch_residual(b, N, w, s), "residual");
         const double beta = norm_host(w);
         rel = beta / bn;
@@ -2827,8 +2832,13 @@ hmat_status hmat_solve_ir(hmat_t h, const double* b, double* x, double tol, int3
       // x_{k+1} = x_k + d_k with A_p d_k = b - A x_k solved by GMRES to a
       // relative residual max(inner_tol, tol ||b|| / (2 ||r_k||)); the
       // residual r_k = b - A x_k uses the FP64 matrix.
+      bool x_zero = true;  // x0 = 0: the first residual is b, no product needed
       for (;;) {
-        matvec_impl(h, stored_prec(h), 1, x, N, r, N, s);
+        if (x_zero)
+          check(launch_fill(r, N, 0.0, s), "fill");
+        else
+          matvec_impl(h, stored_prec(h), 1, x, N, r, N, s);
+        x_zero = false;
         check(launch_residual(b, N, r, s), "residual");
         const double rn = norm_host(r);
         rel = rn / bn;
