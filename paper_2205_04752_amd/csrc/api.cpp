@@ -1906,15 +1906,17 @@ hmat_status gmres_impl(hmat* h, int prec, const GmresWs& ws, const double* b, do
       status = HMAT_OK;
       rel = 0.0;
     } else {
-      bool x_zero = true;  // x0 = 0: the first residual is b, no product needed
+      // x0 = 0: the first residual is b (b - 0, bit for bit), so neither a
+      // product nor its norm is needed (scal[0] still holds ||b||)
+      bool x_zero = true;
       for (;;) {
         if (x_zero)
           check(launch_fill(w, N, 0.0, s), "fill");
         else
           matvec_impl(h, prec, 1, x, N, w, N, s, piped);
-        x_zero = false;
         check(launch_residual(b, N, w, s), "residual");
-        const double beta = norm_host(w);
+        const double beta = x_zero ? bn : norm_host(w);
+        x_zero = false;
         rel = beta / bn;
         if (beta <= tol * bn) {
           status = HMAT_OK;
@@ -2832,15 +2834,17 @@ hmat_status hmat_solve_ir(hmat_t h, const double* b, double* x, double tol, int3
       // x_{k+1} = x_k + d_k with A_p d_k = b - A x_k solved by GMRES to a
       // relative residual max(inner_tol, tol ||b|| / (2 ||r_k||)); the
       // residual r_k = b - A x_k uses the FP64 matrix.
-      bool x_zero = true;  // x0 = 0: the first residual is b, no product needed
+      // x0 = 0: the first residual is b (b - 0, bit for bit), so neither a
+      // product nor its norm is needed
+      bool x_zero = true;
       for (;;) {
         if (x_zero)
           check(launch_fill(r, N, 0.0, s), "fill");
         else
           matvec_impl(h, stored_prec(h), 1, x, N, r, N, s);
-        x_zero = false;
         check(launch_residual(b, N, r, s), "residual");
-        const double rn = norm_host(r);
+        const double rn = x_zero ? bn : norm_host(r);
+        x_zero = false;
         rel = rn / bn;
         if (rn <= tol * bn) {
           st = HMAT_OK;
