@@ -1929,15 +1929,21 @@ hmat_status gmres_impl(hmat* h, int prec, const GmresWs& ws, const double* b, do
         // Pipelined Arnoldi: step j+1 is enqueued before the host waits for
         // column j (it needs only device data), so the host's Givens update
         // overlaps the device's next product. A step enqueued past convergence
-        // is discarded.
+        // is discarded (a whole product); so when the residual estimate,
+        // shrinking at twice its last rate, would meet the tolerance after
+        // column j, step j+1 waits until column j has been checked (a held-back
+        // step costs one host round trip, far less than a discarded one).
         enqueue_step(0);
         launched++;
-        int j = 0;
+        int j = 0, queued = 1;  // steps 0 .. queued - 1 of this cycle are enqueued
+        double res = beta, res_prev = 0.0;  // residual estimates after j and j - 1 steps
         for (;;) {
-          const bool more = (j + 1 < m) && (launched < maxit);
-          if (more) {
+          bool near = false;
+          if (res_prev > 0.0) near = res * std::min(1.0, 0.5 * res / res_prev) <= tol * bn;
+          if (!near && queued == j + 1 && j + 1 < m && launched < maxit) {
             enqueue_step(j + 1);
             launched++;
+            queued++;
           }
           if (piped) check(hipEventSynchronize(ws.ev[j % 2]), "hessenberg");
           const double* col = hcol_host[j % 2];
@@ -1958,7 +1964,15 @@ hmat_status gmres_impl(hmat* h, int prec, const GmresWs& ws, const double* b, do
           g[j] = cs[j] * g[j];
           j++;
           used++;
-          if (std::fabs(g[j]) <= tol * bn || hn == 0.0 || !more) break;
+          res_prev = res;
+          res = std::fabs(g[j]);
+          if (res <= tol * bn || hn == 0.0) break;
+          if (queued == j) {  // step j was held back, or no step is left
+            if (j >= m || launched >= maxit) break;
+            enqueue_step(j);
+            launched++;
+            queued++;
+          }
         }
         for (int i = j - 1; i >= 0; i--) {
           double sum = g[i];
